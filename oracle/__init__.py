@@ -1,0 +1,207 @@
+"""CPU oracle for the winnowed-minimizer Jaccard seed filter and seed chaining.
+
+TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  The GPU library
+(``paper_1807_00205_amd``) never imports it, and the two share no code.
+
+``sdf_oracle.c`` holds the plain C definition (see its header); this module
+builds it with gcc and wraps it with ctypes.  ``brute.py`` holds an
+independent pure-Python restatement used on tiny inputs to pin the C code.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sdf_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+SEED_DTYPE = np.dtype([("query_id", "<u4"), ("i", "<u4"), ("j", "<u4"),
+                       ("strand", "<u4"), ("shared", "<u4"), ("sketch", "<u4")])
+CAND_DTYPE = np.dtype([("query_id", "<u4"), ("strand", "<u4"), ("q_seq", "<u4"),
+                       ("t_seq", "<u4"), ("q_begin", "<u8"), ("q_end", "<u8"),
+                       ("t_begin", "<u8"), ("t_end", "<u8"), ("n_seeds", "<u4"),
+                       ("max_shared", "<u4")])
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle (gcc, OpenMP) into ``oracle/liboracle.so``."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        vp, u32, u64, dbl = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
+        P = ctypes.POINTER
+        L.or_hash.restype = u32
+        L.or_hash.argtypes = [u32, u32]
+        L.or_encode.argtypes = [vp, u64, vp, vp]
+        L.or_hash_many.argtypes = [vp, u64, u32, vp]
+        L.or_kmer_table.argtypes = [vp, vp, u32, u32, vp, vp, vp, vp]
+        L.or_index_build.restype = vp
+        L.or_index_build.argtypes = [vp, vp, u32, u32, u32]
+        L.or_index_free.argtypes = [vp]
+        L.or_index_n_minimizers.restype = u64
+        L.or_index_n_minimizers.argtypes = [vp]
+        L.or_index_n_eligible.restype = u64
+        L.or_index_n_eligible.argtypes = [vp]
+        L.or_index_minimizers.argtypes = [vp, vp, vp, vp]
+        L.or_index_entries.argtypes = [vp, vp, vp, vp]
+        L.or_params.restype = ctypes.c_int
+        L.or_params.argtypes = [dbl, u32, u32, P(dbl), P(u32), P(u32)]
+        L.or_threshold.restype = u32
+        L.or_threshold.argtypes = [dbl, u32]
+        L.or_sketch_size.restype = u32
+        L.or_sketch_size.argtypes = [vp, u64, u32]
+        L.or_count.restype = u32
+        L.or_count.argtypes = [vp, u64, u64, u32, u32]
+        L.or_search.restype = vp
+        L.or_search.argtypes = [vp, vp, u32, dbl, u32, ctypes.c_int, P(ctypes.c_int)]
+        L.or_result_nseeds.restype = u64
+        L.or_result_nseeds.argtypes = [vp]
+        L.or_result_ncands.restype = u64
+        L.or_result_ncands.argtypes = [vp]
+        L.or_result_seeds.argtypes = [vp, vp]
+        L.or_result_cands.argtypes = [vp, vp]
+        L.or_result_free.argtypes = [vp]
+        L.or_seed_size.restype = ctypes.c_int
+        L.or_cand_size.restype = ctypes.c_int
+        assert L.or_seed_size() == SEED_DTYPE.itemsize
+        assert L.or_cand_size() == CAND_DTYPE.itemsize
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def kmer_hash(x: int, k: int) -> int:
+    return int(lib().or_hash(x, k))
+
+
+def hash_many(x: np.ndarray, k: int) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.uint32)
+    out = np.empty_like(x)
+    lib().or_hash_many(_ptr(x), len(x), k, _ptr(out))
+    return out
+
+
+def encode(seq: np.ndarray):
+    seq = np.ascontiguousarray(seq, dtype=np.uint8)
+    code = np.empty(len(seq), np.uint8)
+    lower = np.empty(len(seq), np.uint8)
+    lib().or_encode(_ptr(seq), len(seq), _ptr(code), _ptr(lower))
+    return code, lower
+
+
+def kmer_table(bytes_: np.ndarray, off: np.ndarray, k: int):
+    b = np.ascontiguousarray(bytes_, dtype=np.uint8)
+    off = np.ascontiguousarray(off, dtype=np.uint64)
+    n = len(b)
+    f = np.empty(n, np.uint32)
+    r = np.empty(n, np.uint32)
+    h = np.empty(n, np.uint32)
+    fl = np.empty(n, np.uint8)
+    lib().or_kmer_table(_ptr(b), _ptr(off), len(off) - 1, k, _ptr(f), _ptr(r), _ptr(h), _ptr(fl))
+    return f, r, h, fl
+
+
+def params(max_error: float, min_len: int, k: int):
+    tau = ctypes.c_double()
+    n = ctypes.c_uint32()
+    mo = ctypes.c_uint32()
+    rc = lib().or_params(max_error, min_len, k, ctypes.byref(tau), ctypes.byref(n),
+                         ctypes.byref(mo))
+    if rc != 0:
+        raise ValueError("invalid parameters")
+    return tau.value, n.value, mo.value
+
+
+def threshold(tau: float, s: int) -> int:
+    return int(lib().or_threshold(tau, s))
+
+
+class OracleIndex:
+    def __init__(self, bytes_: np.ndarray, off: np.ndarray, k: int = 12, w: int = 16):
+        self._b = np.ascontiguousarray(bytes_, dtype=np.uint8)
+        self._off = np.ascontiguousarray(off, dtype=np.uint64)
+        self.k, self.w = k, w
+        self._h = lib().or_index_build(_ptr(self._b), _ptr(self._off), len(self._off) - 1, k, w)
+        if not self._h:
+            raise ValueError("invalid index parameters")
+
+    def close(self):
+        if self._h:
+            lib().or_index_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def n_minimizers(self) -> int:
+        return int(lib().or_index_n_minimizers(self._h))
+
+    @property
+    def n_eligible(self) -> int:
+        return int(lib().or_index_n_eligible(self._h))
+
+    def minimizers(self):
+        n = self.n_minimizers
+        pos = np.empty(n, np.uint32)
+        h = np.empty(n, np.uint32)
+        fl = np.empty(n, np.uint8)
+        lib().or_index_minimizers(self._h, _ptr(pos), _ptr(h), _ptr(fl))
+        return pos, h, fl
+
+    def entries(self):
+        n = self.n_eligible
+        h = np.empty(n, np.uint32)
+        st = np.empty(n, np.uint8)
+        pos = np.empty(n, np.uint32)
+        lib().or_index_entries(self._h, _ptr(h), _ptr(st), _ptr(pos))
+        return h, st, pos
+
+    def sketch_size(self, i: int, n: int) -> int:
+        return int(lib().or_sketch_size(self._h, i, n))
+
+    def count(self, i: int, j: int, o: int, n: int) -> int:
+        return int(lib().or_count(self._h, i, j, o, n))
+
+    def search(self, spans, max_error: float = 0.25, min_len: int = 1000, threads: int = 0):
+        sp = np.ascontiguousarray(np.array(spans, dtype=np.uint64).reshape(-1, 3))
+        st = ctypes.c_int()
+        r = lib().or_search(self._h, _ptr(sp), len(sp), max_error, min_len, threads,
+                            ctypes.byref(st))
+        if st.value != 0:
+            raise ValueError("oracle search failed: status %d" % st.value)
+        try:
+            ns = int(lib().or_result_nseeds(r))
+            nc = int(lib().or_result_ncands(r))
+            seeds = np.empty(ns, SEED_DTYPE)
+            cands = np.empty(nc, CAND_DTYPE)
+            lib().or_result_seeds(r, _ptr(seeds))
+            lib().or_result_cands(r, _ptr(cands))
+        finally:
+            lib().or_result_free(r)
+        return seeds, cands

@@ -1,0 +1,266 @@
+"""Independent pure-Python restatement of the seed filter, for tiny inputs.
+
+TEST INFRASTRUCTURE (part of the oracle package).  It pins the C oracle: it
+shares no code with ``sdf_oracle.c`` and reaches the same results by a
+different route:
+
+* the winnow is computed with a streaming monotone queue (Section 2.2 notes
+  the winnow can be computed in linear time and O(w) space in a streaming
+  fashion) instead of per-window scans;
+* the shared count c_o(i, j) is computed for every integer window start j
+  by explicit set membership tests instead of the rolling update;
+* chaining uses explicit pairwise links and a depth-first search instead of
+  sorting and union-find.
+
+Everything here is O(n^2)-ish and meant for inputs of a few kbp.
+"""
+from __future__ import annotations
+
+import collections
+import math
+from typing import Dict, List, Tuple
+
+import numpy as np
+
+_CODE = {ord(c): i for i, c in enumerate("ACGT")}
+_CODE.update({ord(c): i for i, c in enumerate("acgt")})
+
+
+def bases(seq: np.ndarray):
+    """Per base: (code or None for N, lower-case flag)."""
+    out = []
+    for b in bytes(seq):
+        if b in _CODE:
+            out.append((_CODE[b], 97 <= b <= 122))
+        else:
+            out.append((None, False))
+    return out
+
+
+def hash_k(x: int, k: int) -> int:
+    m = 2 * k
+    mask = (1 << m) - 1
+    sh = (m + 1) // 2
+    x = (x * 0x6A09E667) & mask
+    x ^= x >> sh
+    x = (x * 0xBB67AE85) & mask
+    x ^= x >> sh
+    return x
+
+
+class Kmer:
+    __slots__ = ("pos", "f", "r", "canon", "strand", "pal", "eligible", "h")
+
+
+def kmers(seq_bytes: np.ndarray, off: np.ndarray, k: int) -> Dict[int, Kmer]:
+    """Valid k-mers by global start position."""
+    bb = bases(seq_bytes)
+    out = {}
+    for s in range(len(off) - 1):
+        b, e = int(off[s]), int(off[s + 1])
+        for p in range(b, e - k + 1):
+            win = bb[p:p + k]
+            if any(c is None for c, _ in win):
+                continue
+            f = 0
+            for c, _ in win:
+                f = 4 * f + c
+            r = 0
+            for c, _ in reversed(win):
+                r = 4 * r + (3 - c)
+            km = Kmer()
+            km.pos, km.f, km.r = p, f, r
+            km.canon = min(f, r)
+            km.strand = 1 if r < f else 0
+            km.pal = f == r
+            km.eligible = (not km.pal) and any(not low for _, low in win)
+            km.h = hash_k(km.canon, k)
+            out[p] = km
+    return out
+
+
+def winnow(seq_bytes, off, k: int, w: int, km=None) -> List[Kmer]:
+    """Streaming winnow with a monotone queue; rightmost minimum on ties."""
+    if km is None:
+        km = kmers(seq_bytes, off, k)
+    selected = set()
+    for s in range(len(off) - 1):
+        b, e = int(off[s]), int(off[s + 1])
+        K = e - b - k + 1
+        if K <= 0:
+            continue
+        width = min(w, K)
+        dq = collections.deque()  # positions with strictly increasing hash
+        for t in range(K):
+            p = b + t
+            if p in km:
+                # a later equal hash replaces earlier ones (rightmost wins)
+                while dq and km[dq[-1]].h >= km[p].h:
+                    dq.pop()
+                dq.append(p)
+            start = t - width + 1
+            while dq and dq[0] < b + start:
+                dq.popleft()
+            if start >= 0 and dq:
+                selected.add(dq[0])
+    return [km[p] for p in sorted(selected)]
+
+
+def params(max_error: float, min_len: int, k: int):
+    dM = min(0.15, max_error)
+    dG = max_error - dM
+    tau = ((1 - dG) / (1 + dG)) / (2 * math.exp(k * dM) - 1)
+    n = math.ceil(min_len * (1 - max_error))
+    return tau, n, math.floor(max_error * n)
+
+
+class Brute:
+    def __init__(self, seq_bytes: np.ndarray, off: np.ndarray, k: int, w: int):
+        self.seq = np.asarray(seq_bytes, dtype=np.uint8)
+        self.off = [int(x) for x in off]
+        self.k, self.w = k, w
+        self.km = kmers(self.seq, off, k)
+        self.M = winnow(self.seq, off, k, w, self.km)
+        self.total = self.off[-1]
+        isn = np.array([c is None for c, _ in bases(self.seq)], dtype=bool)
+        self.nprefix = np.concatenate([[0], np.cumsum(isn)])
+        self.elig = [m for m in self.M if m.eligible]
+        self.by_hash = collections.defaultdict(list)
+        for m in self.elig:
+            self.by_hash[m.h].append(m)
+
+    def seq_of(self, p: int) -> int:
+        for s in range(len(self.off) - 1):
+            if self.off[s] <= p < self.off[s + 1]:
+                return s
+        raise ValueError(p)
+
+    def window_ok(self, x: int, n: int) -> bool:
+        if x < 0 or x + n > self.total:
+            return False
+        s = self.seq_of(x)
+        if x + n > self.off[s + 1]:
+            return False
+        return self.nprefix[x + n] - self.nprefix[x] == 0
+
+    def window_minimizers(self, i: int, n: int):
+        return [m for m in self.M if i <= m.pos and m.pos + self.k <= i + n]
+
+    def sketch(self, i: int, n: int) -> int:
+        return len({m.h for m in self.window_minimizers(i, n)})
+
+    def counts_all_j(self, i: int, o: int, n: int) -> np.ndarray:
+        """c_o(i, j) for every integer j in [0, total - n]; set membership."""
+        J = np.arange(0, max(0, self.total - n + 1))
+        covered_by_h: Dict[int, np.ndarray] = {}
+        for q in self.window_minimizers(i, n):
+            if not q.eligible:
+                continue
+            targets = np.array(sorted(t.pos for t in self.by_hash[q.h]
+                                      if (t.strand ^ q.strand) == o and t.pos != q.pos),
+                               dtype=np.int64)
+            if targets.size == 0:
+                continue
+            idx = np.searchsorted(targets, J, side="left")
+            ok = idx < targets.size
+            ok[ok] = targets[idx[ok]] + self.k <= J[ok] + n
+            prev = covered_by_h.get(q.h)
+            covered_by_h[q.h] = ok if prev is None else (prev | ok)
+        c = np.zeros(J.size, dtype=np.int64)
+        for v in covered_by_h.values():
+            c += v
+        return c
+
+    def hit_positions(self, i: int, o: int, n: int):
+        out = set()
+        for q in self.window_minimizers(i, n):
+            if not q.eligible:
+                continue
+            for t in self.by_hash[q.h]:
+                if (t.strand ^ q.strand) == o and t.pos != q.pos:
+                    out.add(t.pos)
+        return sorted(out)
+
+    def search(self, spans, max_error=0.25, min_len=1000):
+        tau, n, mo = params(max_error, min_len, self.k)
+        seeds = []
+        for qid, (s, b, e) in enumerate(spans):
+            gb, ge = self.off[s] + b, self.off[s] + e
+            for m in self.elig:
+                i = m.pos
+                if not (gb <= i and i + n <= ge and self.window_ok(i, n)):
+                    continue
+                s_i = self.sketch(i, n)
+                T = math.ceil(tau * s_i)
+                qseq = self.seq_of(i)
+                for o in (0, 1):
+                    c = self.counts_all_j(i, o, n)
+                    Jl = [j for j in self.hit_positions(i, o, n) if self.window_ok(j, n)]
+                    run = []
+                    prev = None
+
+                    def flush():
+                        if run:
+                            best = max(run, key=lambda jc: (jc[1], -jc[0]))
+                            seeds.append((qid, i, best[0], o, best[1], s_i))
+
+                    for j in Jl:
+                        cj = int(c[j])
+                        tseq = self.seq_of(j)
+                        excl = tseq == qseq and abs(i - j) < n and n - abs(i - j) > mo
+                        ok = cj >= T and not excl
+                        cont = prev is not None and ok and tseq == prev[1] and j - prev[0] < n
+                        if run and not cont:
+                            flush()
+                            run = []
+                        if ok:
+                            run.append((j, cj))
+                        prev = (j, tseq)
+                    flush()
+        seeds.sort()
+        cands = self.chain(seeds, n, mo)
+        return seeds, cands
+
+    def chain(self, seeds, n, mo):
+        adj = collections.defaultdict(list)
+        for a in range(len(seeds)):
+            qa, ia, ja, oa, _, _ = seeds[a]
+            for b in range(a + 1, len(seeds)):
+                qb, ib, jb, ob, _, _ = seeds[b]
+                if qa != qb or oa != ob:
+                    continue
+                if self.seq_of(ja) != self.seq_of(jb):
+                    continue
+                di, dj = ib - ia, jb - ja
+                if abs(di) >= n or abs(dj) >= n:
+                    continue
+                dd = dj - di if oa == 0 else dj + di
+                if abs(dd) > mo:
+                    continue
+                adj[a].append(b)
+                adj[b].append(a)
+        seen = [False] * len(seeds)
+        cands = []
+        for a in range(len(seeds)):
+            if seen[a]:
+                continue
+            comp, stack = [], [a]
+            seen[a] = True
+            while stack:
+                x = stack.pop()
+                comp.append(x)
+                for y in adj[x]:
+                    if not seen[y]:
+                        seen[y] = True
+                        stack.append(y)
+            S = [seeds[x] for x in comp]
+            qs = self.seq_of(S[0][1])
+            ts = self.seq_of(S[0][2])
+            cands.append((S[0][0], S[0][3], qs, ts,
+                          min(x[1] for x in S) - self.off[qs],
+                          max(x[1] for x in S) + n - self.off[qs],
+                          min(x[2] for x in S) - self.off[ts],
+                          max(x[2] for x in S) + n - self.off[ts],
+                          len(S), max(x[4] for x in S)))
+        cands.sort()
+        return cands

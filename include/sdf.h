@@ -1,0 +1,192 @@
+/*
+ * sdf.h -- C ABI of the MI355X seed filter for segmental-duplication search.
+ *
+ * The library implements, on one AMD Instinct MI355X (gfx950), the seeding
+ * step of SEDEF (Numanagic et al., "Fast Characterization of Segmental
+ * Duplications in Genome Assemblies", Section 3.1) followed by a chaining of
+ * the surviving seeds into candidate duplication pairs on both strands:
+ *
+ *   sdf_index_build   index(G, k, w): winnow W(G), the position-sorted index
+ *                     I_G and the reverse index I_G^{-1} (Section 3.1).
+ *   sdf_search        search(query span, error bound, minimum length): for
+ *                     every window of the span, the windows elsewhere in G
+ *                     whose winnowed k-mer sets share at least tau * s
+ *                     minimizers (Section 2.2 filter lemma, tau from the
+ *                     Section 3.1 bound), reported as seeds and chained into
+ *                     candidates (the problem statement of Section 3).
+ *   sdf_search_batch  the same for many spans in one launch sequence.
+ *   sdf_result_*      candidates out.
+ *
+ * Every entry point returns an sdf_status: 0 on success, a negative code on
+ * failure, with a message available from sdf_last_error().  No C++ exception
+ * crosses this boundary and the library never terminates the process.
+ * Arguments are validated before any device work is queued; a failed search
+ * leaves its index valid.
+ *
+ * Threading: an index is immutable after sdf_index_build and may be searched
+ * from several host threads on different streams at once.  Results are
+ * owned by the caller until sdf_result_free.
+ *
+ * Coordinates are 0-based and half-open, per sequence (BEDPE style,
+ * Section 3.3).  The total length of all sequences must be below 2^32 - 2^20.
+ */
+#ifndef SDF_H
+#define SDF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sdf_status;
+
+enum {
+    SDF_OK = 0,
+    SDF_EINVAL = -1,    /* invalid argument (parameter out of range, NULL pointer) */
+    SDF_ENOMEM = -2,    /* device or host allocation failed; nothing was kept */
+    SDF_EDEVICE = -3,   /* a HIP call failed; the message names it */
+    SDF_ERANGE = -4,    /* a span lies outside its sequence */
+    SDF_EBUSY = -5,     /* reserved: resource in use */
+    SDF_EINTERNAL = -6  /* an internal capacity was exceeded; the message says which */
+};
+
+/* Message for the last failing call on this host thread; valid until the
+ * next call on the same thread.  Never NULL. */
+const char *sdf_last_error(void);
+
+typedef struct sdf_index_s *sdf_index;   /* device-resident, read-only after build */
+typedef struct sdf_result_s *sdf_result; /* device buffers + host copies of one search */
+
+/* k: k-mer length, 1 <= k <= 16 (Section 3.3 uses k = 12 for seeding).
+ * w: winnowing window in k-mers, 1 <= w <= 64 (Section 2.2). */
+typedef struct {
+    uint32_t k, w;
+} sdf_index_params;
+
+/* max_error: the error bound delta of Section 2, 0 < delta < 1 (the paper
+ * targets delta <= 0.25).  min_len: minimum duplication length L (Section 2:
+ * 1000 bp); the seed window length is n = ceil(L (1 - delta)) (Section 3).
+ * Requires n >= k + w - 1.  flags: SDF_TIMING records per-stage GPU times. */
+typedef struct {
+    double max_error;
+    uint32_t min_len;
+    uint32_t flags;
+} sdf_search_params;
+
+#define SDF_TIMING 1u
+
+/* A query span [begin, end) of sequence `seq`. */
+typedef struct {
+    uint32_t seq;
+    uint32_t _pad;
+    uint64_t begin, end;
+} sdf_span;
+
+/* One candidate duplication pair (56 bytes, fixed layout).  The query side
+ * lies in the span with index query_id; strand 0 pairs the two copies
+ * directly, strand 1 pairs one with the reverse complement of the other.
+ * n_seeds: seeds in the chain; max_shared: largest shared-minimizer count
+ * of those seeds. */
+typedef struct {
+    uint32_t query_id, strand, q_seq, t_seq;
+    uint64_t q_begin, q_end, t_begin, t_end;
+    uint32_t n_seeds, max_shared;
+} sdf_candidate;
+
+/* One seed (24 bytes): query window start i, target window start j (global
+ * coordinates over the concatenated sequences), strand, shared count c and
+ * sketch size s of the query window (Section 3.1). */
+typedef struct {
+    uint32_t query_id, i, j, strand, shared, sketch;
+} sdf_seed;
+
+/*
+ * Build the index of G (Section 3.1: "a sorted list of unique pairs (i, x)"
+ * and the reverse index "x -> positions").
+ *   seqs[t], lens[t]: the bytes of sequence t (host memory, borrowed for the
+ *     duration of the call).  A, C, G, T in either case are bases; lower
+ *     case marks soft-masked repeats (Section 3.2); any other byte is a gap
+ *     base (N) and no k-mer or window may contain it.
+ *   hip_stream: a hipStream_t passed as void* (NULL: the default stream).
+ *   *out: receives the index.  On failure *out is NULL and nothing leaks.
+ * Errors: SDF_EINVAL (bad k or w, NULL pointers, n_seqs == 0, total too
+ * long), SDF_ENOMEM, SDF_EDEVICE.
+ */
+sdf_status sdf_index_build(const char *const *seqs, const uint64_t *lens, uint32_t n_seqs,
+                           const sdf_index_params *p, void *hip_stream, sdf_index *out);
+
+/* Sizes of a built index.  Any out pointer may be NULL. */
+sdf_status sdf_index_info(sdf_index ix, uint64_t *n_minimizers, uint64_t *n_eligible,
+                          uint64_t *device_bytes);
+
+/* Copy the winnow W(G) (Section 2.2) to host memory in position order:
+ * pos (global), hash and flags (bit0: the reverse complement is the
+ * canonical k-mer; bit1: eligible for seeding, Section 3.2).  Any output
+ * pointer may be NULL.  Fails with SDF_EINVAL if cap < n_minimizers. */
+sdf_status sdf_index_minimizers(sdf_index ix, uint32_t *pos, uint32_t *hash, uint8_t *flags,
+                                uint64_t cap, uint64_t *written);
+
+/* Copy the reverse index I_G^{-1} (Section 3.1) to host memory as entries
+ * sorted by (hash, strand, position).  Fails with SDF_EINVAL if
+ * cap < n_eligible. */
+sdf_status sdf_index_entries(sdf_index ix, uint32_t *hash, uint8_t *strand, uint32_t *pos,
+                             uint64_t cap, uint64_t *written);
+
+/* Copy the 2-bit packed sequence (16 bases per word, base p at bits
+ * 2(p%16)), the soft-mask bits and the gap bits (32 bases per word, base p at
+ * bit p%32) to host memory.  Word counts: ceil(total/16) and ceil(total/32);
+ * any pointer may be NULL. */
+sdf_status sdf_index_packed(sdf_index ix, uint32_t *packed, uint32_t *mask, uint32_t *gaps);
+
+/* Release the index and its device memory.  NULL is ignored. */
+void sdf_index_free(sdf_index ix);
+
+/*
+ * Search one span against the whole index (self-search included).
+ * Every query window [i, i+n) of the span starts at an eligible minimizer,
+ * lies inside the span and holds no gap base; each is compared with every
+ * target window [j, j+n) of G that starts at one of its hits.  Seeds are the
+ * best target start of each run of consecutive passing targets; chains of
+ * seeds become candidates.
+ * Errors: SDF_EINVAL, SDF_ERANGE (span outside its sequence), SDF_ENOMEM,
+ * SDF_EDEVICE, SDF_EINTERNAL.  A span shorter than n succeeds with no
+ * candidates.  *out receives the result (NULL on failure).
+ */
+sdf_status sdf_search(sdf_index ix, const sdf_span *q, const sdf_search_params *p,
+                      void *hip_stream, sdf_result *out);
+
+/* Search n spans (host array) in one launch sequence; candidate query_id is
+ * the index of its span in qs.  Same errors as sdf_search. */
+sdf_status sdf_search_batch(sdf_index ix, const sdf_span *qs, uint32_t n,
+                            const sdf_search_params *p, void *hip_stream, sdf_result *out);
+
+/* Number of candidates (waits for the search to finish). */
+sdf_status sdf_result_count(sdf_result r, uint64_t *n);
+
+/* Copy up to cap candidates, sorted by (query_id, strand, q_seq, q_begin,
+ * q_end, t_seq, t_begin, t_end, n_seeds, max_shared), to host memory. */
+sdf_status sdf_result_copy(sdf_result r, sdf_candidate *dst, uint64_t cap, uint64_t *written);
+
+/* Number of seeds, and a copy of them sorted by (query_id, i, j, strand). */
+sdf_status sdf_result_seed_count(sdf_result r, uint64_t *n);
+sdf_status sdf_result_seeds(sdf_result r, sdf_seed *dst, uint64_t cap, uint64_t *written);
+
+/* GPU time in ms of each stage when the search ran with SDF_TIMING:
+ * [0] setup, [1] the tile search kernel alone (last launch),
+ * [2] chaining, [3] output sort, [4] whole search.  Also returns the number
+ * of tile-kernel launches measured in [1] (1 per search). */
+sdf_status sdf_result_timing(sdf_result r, float *ms, uint32_t n_ms);
+
+/* Work counters of the search: [0] query windows, [1] hits gathered
+ * (both passes count once), [2] hits kept by the prefilter, [3] tiles,
+ * [4] target partitions, [5] seeds. */
+sdf_status sdf_result_stats(sdf_result r, uint64_t *v, uint32_t n_v);
+
+void sdf_result_free(sdf_result r);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SDF_H */

@@ -1,0 +1,443 @@
+// C ABI of the library (include/sdf.h): argument checking, parameter
+// derivation on the host, launch sequences and result handling.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "sdf_impl.h"
+#include "search.h"
+
+namespace sdf {
+const char *last_error();
+}
+
+using namespace sdf;
+
+struct sdf_result_s {
+    int device = 0;
+    hipStream_t st = nullptr;
+    uint32_t n = 0;
+    uint64_t nseeds = 0;
+    DevBuf<uint32_t> seeds;
+    ChainOut chain;
+    std::vector<sdf_candidate> h_cands;
+    bool have_cands = false;
+    std::vector<uint32_t> h_seeds;
+    bool have_seeds = false;
+    float ms[5] = {0, 0, 0, 0, 0};
+    uint64_t stats[6] = {0, 0, 0, 0, 0, 0};
+};
+
+namespace {
+
+template <class F>
+sdf_status guarded(F &&f) {
+    try {
+        f();
+        return SDF_OK;
+    } catch (const Error &e) {
+        set_error(e.msg);
+        (void)hipGetLastError();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return SDF_ENOMEM;
+    } catch (...) {
+        set_error("unexpected internal error");
+        return SDF_EINTERNAL;
+    }
+}
+
+struct Params {
+    double tau;
+    uint32_t n, max_overlap;
+};
+
+// Section 2.1: delta_M = min(0.15, delta), delta_G = delta - delta_M.
+// Section 3.1 bound: tau = (1 - dG)/(1 + dG) / (2 e^{k dM} - 1).
+// Section 3: n = ceil(L (1 - delta)).  Section 2: overlap <= floor(delta n).
+Params derive(const sdf_search_params *p, uint32_t k, uint32_t w) {
+    if (!p) throw Error{SDF_EINVAL, "search params is NULL"};
+    const double d = p->max_error;
+    if (!(d > 0.0 && d < 1.0)) throw Error{SDF_EINVAL, "max_error must lie in (0, 1)"};
+    if (p->min_len < k + w - 1) throw Error{SDF_EINVAL, "min_len must be at least k + w - 1"};
+    Params r;
+    const double dM = d < 0.15 ? d : 0.15;
+    const double dG = d - dM;
+    r.tau = ((1.0 - dG) / (1.0 + dG)) / (2.0 * std::exp((double)k * dM) - 1.0);
+    const double nn = std::ceil((double)p->min_len * (1.0 - d));
+    if (nn < (double)(k + w - 1) || nn > 1e8)
+        throw Error{SDF_EINVAL, "seed window length n = ceil(min_len (1 - max_error)) must be at least k + w - 1"};
+    r.n = (uint32_t)nn;
+    r.max_overlap = (uint32_t)std::floor(d * (double)r.n);
+    return r;
+}
+
+uint32_t env_u32(const char *name, uint32_t def) {
+    const char *v = std::getenv(name);
+    if (!v || !*v) return def;
+    return (uint32_t)std::strtoul(v, nullptr, 10);
+}
+
+int cu_count(int dev) {
+    static int cached[64] = {0};
+    if (dev >= 0 && dev < 64 && cached[dev]) return cached[dev];
+    int c = 0;
+    SDF_HIP(hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev));
+    if (dev >= 0 && dev < 64) cached[dev] = c;
+    return c;
+}
+
+struct Timer {
+    bool on;
+    hipStream_t st;
+    hipEvent_t ev[6] = {};
+    int used = 0;
+    Timer(bool on_, hipStream_t s) : on(on_), st(s) {
+        if (on) {
+            for (auto &e : ev) SDF_HIP(hipEventCreate(&e));
+            SDF_HIP(hipEventCreate(&kb));
+            SDF_HIP(hipEventCreate(&ke));
+        }
+    }
+    hipEvent_t kb = nullptr, ke = nullptr;
+    void mark() {
+        if (on && used < 6) SDF_HIP(hipEventRecord(ev[used++], st));
+    }
+    void mark_kernel_begin() {
+        if (on) SDF_HIP(hipEventRecord(kb, st));
+    }
+    void mark_kernel_end() {
+        if (on) SDF_HIP(hipEventRecord(ke, st));
+    }
+    float kernel_ms() {
+        float ms = 0;
+        if (on) SDF_HIP(hipEventElapsedTime(&ms, kb, ke));
+        return ms;
+    }
+    ~Timer() {
+        if (on) {
+            for (auto &e : ev) (void)hipEventDestroy(e);
+            (void)hipEventDestroy(kb);
+            (void)hipEventDestroy(ke);
+        }
+    }
+    float between(int a, int b) {
+        float ms = 0;
+        if (on && b < used) SDF_HIP(hipEventElapsedTime(&ms, ev[a], ev[b]));
+        return ms;
+    }
+};
+
+void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_search_params *p,
+                hipStream_t st, sdf_result_s *res) {
+    const Params P = derive(p, ix->k, ix->w);
+    res->n = P.n;
+    for (uint32_t t = 0; t < nq; t++) {
+        const sdf_span &s = qs[t];
+        if (s.seq >= ix->nseq) throw Error{SDF_ERANGE, "span sequence index out of range"};
+        const uint64_t len = ix->h_off[s.seq + 1] - ix->h_off[s.seq];
+        if (s.begin > s.end || s.end > len) throw Error{SDF_ERANGE, "span outside its sequence"};
+    }
+    Timer tm((p->flags & SDF_TIMING) != 0, st);
+    tm.mark();
+    // thresholds T(s) = ceil(tau * s) for every sketch size a tile can see
+    const uint32_t smax = std::max<uint32_t>(P.n - ix->k + 2, 2048);
+    std::vector<uint16_t> T(smax + 1);
+    for (uint32_t s = 0; s <= smax; s++) {
+        double v = std::ceil(P.tau * (double)s);
+        T[s] = (uint16_t)std::min(v, 65535.0);
+    }
+    DevBuf<uint16_t> dT(T.size());
+    SDF_HIP(hipMemcpyAsync(dT.p, T.data(), T.size() * 2, hipMemcpyHostToDevice, st));
+    std::vector<SpanDesc> sd(nq);
+    uint64_t qbases = 0;
+    for (uint32_t t = 0; t < nq; t++) {
+        sd[t].gb = ix->h_off[qs[t].seq] + qs[t].begin;
+        sd[t].ge = ix->h_off[qs[t].seq] + qs[t].end;
+        sd[t].qid = t;
+        sd[t].qseq = qs[t].seq;
+        qbases += qs[t].end - qs[t].begin;
+    }
+    const uint32_t core = std::min(std::max<uint32_t>(env_u32("SDF_TILE_CORE", 512), 1),
+                                   tile_core_max());
+    const uint32_t hpart = std::max<uint32_t>(env_u32("SDF_HITS_PER_PART", 16384), 1024);
+    DevBuf<SpanDesc> dsd(nq);
+    DevBuf<uint32_t> ntiles(nq + 1), tile0(nq + 1);
+    uint32_t total_tiles = 0;
+    if (nq) {
+        SDF_HIP(hipMemcpyAsync(dsd.p, sd.data(), nq * sizeof(SpanDesc), hipMemcpyHostToDevice, st));
+        launch_span_setup(ix->view(), dsd.p, nq, P.n, core, ntiles.p, tile0.p, st);
+        SDF_HIP(hipMemcpyAsync(&total_tiles, tile0.p + nq, 4, hipMemcpyDeviceToHost, st));
+        SDF_HIP(hipStreamSynchronize(st));
+    }
+    tm.mark();
+    uint32_t sb = 0;
+    while ((1u << sb) < P.n) sb++;
+    uint64_t cap = qbases / 8 + 65536;
+    DevBuf<unsigned long long> counters(CNT_N);
+    DevBuf<uint32_t> work(2);
+    std::vector<unsigned long long> hc(CNT_N);
+    uint32_t herr = 0;
+    for (int attempt = 0; attempt < 3; attempt++) {
+        res->seeds.alloc(cap * 6);
+        SDF_HIP(hipMemsetAsync(counters.p, 0, CNT_N * 8, st));
+        SDF_HIP(hipMemsetAsync(work.p, 0, 8, st));
+        if (total_tiles) {
+            SearchArgs a;
+            a.ix = ix->view();
+            a.n = P.n;
+            a.max_overlap = P.max_overlap;
+            a.T = dT.p;
+            a.spans = dsd.p;
+            a.nspans = nq;
+            a.total_tiles = total_tiles;
+            a.work = work.p;
+            a.core = core;
+            a.hpart = hpart;
+            a.bin_shift = sb;
+            a.seeds = res->seeds.p;
+            a.seed_cap = cap;
+            a.counters = counters.p;
+            a.err = work.p + 1;
+            const uint32_t grid = std::min<uint32_t>(total_tiles, (uint32_t)cu_count(ix->device) *
+                                                                      env_u32("SDF_WG_PER_CU", 1));
+            tm.mark_kernel_begin();
+            launch_tile_search(a, std::max<uint32_t>(grid, 1), st);
+            tm.mark_kernel_end();
+        }
+        SDF_HIP(hipMemcpyAsync(hc.data(), counters.p, CNT_N * 8, hipMemcpyDeviceToHost, st));
+        SDF_HIP(hipMemcpyAsync(&herr, work.p + 1, 4, hipMemcpyDeviceToHost, st));
+        SDF_HIP(hipStreamSynchronize(st));
+        if (herr) break;
+        if (hc[CNT_SEEDS] <= cap) break;
+        cap = hc[CNT_SEEDS] + hc[CNT_SEEDS] / 8 + 1024;
+    }
+    tm.mark();
+    if (!herr && hc[CNT_SEEDS] > cap) throw Error{SDF_EINTERNAL, "seed buffer kept overflowing"};
+    if (herr) {
+        std::string m = "tile search capacity exceeded:";
+        if (herr & 1) m += " a window reaches more minimizers than a tile holds;";
+        if (herr & 2) m += " a dense target region keeps more hits than a tile holds;";
+        if (herr & 4) m += " a dense target region has more than 65535 hits;";
+        throw Error{SDF_EINTERNAL, m};
+    }
+    res->nseeds = hc[CNT_SEEDS];
+    res->stats[0] = hc[CNT_WINDOWS];
+    res->stats[1] = hc[CNT_HITS];
+    res->stats[2] = hc[CNT_KEPT];
+    res->stats[3] = total_tiles;
+    res->stats[4] = hc[CNT_PARTS];
+    res->stats[5] = hc[CNT_SEEDS];
+    chain_seeds(ix->view(), res->seeds.p, res->nseeds, P.n, P.max_overlap, res->chain, st);
+    tm.mark();
+    tm.mark();
+    SDF_HIP(hipStreamSynchronize(st));
+    res->ms[0] = tm.between(0, 1);
+    res->ms[1] = tm.kernel_ms();
+    res->ms[2] = tm.between(2, 3);
+    res->ms[3] = tm.between(3, 4);
+    res->ms[4] = tm.between(0, 4);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sdf_last_error(void) { return sdf::last_error(); }
+
+sdf_status sdf_index_build(const char *const *seqs, const uint64_t *lens, uint32_t n_seqs,
+                           const sdf_index_params *p, void *hip_stream, sdf_index *out) {
+    if (out) *out = nullptr;
+    sdf_index_s *ix = nullptr;
+    sdf_status rc = guarded([&] {
+        if (!out || !p || !seqs || !lens) throw Error{SDF_EINVAL, "NULL argument"};
+        if (n_seqs == 0) throw Error{SDF_EINVAL, "no sequences"};
+        if (p->k < 1 || p->k > 16) throw Error{SDF_EINVAL, "k must lie in [1, 16]"};
+        if (p->w < 1 || p->w > 64) throw Error{SDF_EINVAL, "w must lie in [1, 64]"};
+        uint64_t total = 0;
+        for (uint32_t s = 0; s < n_seqs; s++) {
+            if (!seqs[s] && lens[s]) throw Error{SDF_EINVAL, "NULL sequence"};
+            total += lens[s];
+        }
+        if (total == 0) throw Error{SDF_EINVAL, "empty input"};
+        if (total > MAX_TOTAL) throw Error{SDF_EINVAL, "total length too large for 32-bit positions"};
+        ix = new sdf_index_s();
+        SDF_HIP(hipGetDevice(&ix->device));
+        ix->k = p->k;
+        ix->w = p->w;
+        build_index(ix, seqs, lens, n_seqs, (hipStream_t)hip_stream);
+        *out = ix;
+    });
+    if (rc != SDF_OK) delete ix;
+    return rc;
+}
+
+sdf_status sdf_index_info(sdf_index ix, uint64_t *nm, uint64_t *ne, uint64_t *bytes) {
+    return guarded([&] {
+        if (!ix) throw Error{SDF_EINVAL, "NULL index"};
+        if (nm) *nm = ix->nm;
+        if (ne) *ne = ix->ne;
+        if (bytes) *bytes = ix->device_bytes;
+    });
+}
+
+sdf_status sdf_index_minimizers(sdf_index ix, uint32_t *pos, uint32_t *hash, uint8_t *flags,
+                                uint64_t cap, uint64_t *written) {
+    return guarded([&] {
+        if (!ix) throw Error{SDF_EINVAL, "NULL index"};
+        if (cap < ix->nm) throw Error{SDF_EINVAL, "capacity below the number of minimizers"};
+        SDF_HIP(hipSetDevice(ix->device));
+        if (pos) SDF_HIP(hipMemcpy(pos, ix->mpos.p, ix->nm * 4, hipMemcpyDeviceToHost));
+        if (hash) SDF_HIP(hipMemcpy(hash, ix->mhash.p, ix->nm * 4, hipMemcpyDeviceToHost));
+        if (flags) SDF_HIP(hipMemcpy(flags, ix->mflags.p, ix->nm, hipMemcpyDeviceToHost));
+        if (written) *written = ix->nm;
+    });
+}
+
+__global__ void k_expand_entries(const uint32_t *dir, uint64_t ndir, uint32_t shift,
+                                 const uint8_t *keylo, uint64_t *key) {
+    uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x + 1 >= ndir) return;
+    for (uint32_t e = dir[x]; e < dir[x + 1]; e++)
+        key[e] = (x << shift) | (shift ? keylo[e] : 0);
+}
+
+sdf_status sdf_index_entries(sdf_index ix, uint32_t *hash, uint8_t *strand, uint32_t *pos,
+                             uint64_t cap, uint64_t *written) {
+    return guarded([&] {
+        if (!ix) throw Error{SDF_EINVAL, "NULL index"};
+        if (cap < ix->ne) throw Error{SDF_EINVAL, "capacity below the number of entries"};
+        SDF_HIP(hipSetDevice(ix->device));
+        DevBuf<uint64_t> key(ix->ne + 1);
+        const uint64_t ndir = ix->dir.n;
+        k_expand_entries<<<(unsigned)((ndir + 255) / 256), 256>>>(ix->dir.p, ndir, ix->dir_shift,
+                                                                 ix->ekeylo.p, key.p);
+        SDF_HIP(hipGetLastError());
+        std::vector<uint64_t> hk(ix->ne);
+        SDF_HIP(hipMemcpy(hk.data(), key.p, ix->ne * 8, hipMemcpyDeviceToHost));
+        for (uint64_t e = 0; e < ix->ne; e++) {
+            if (hash) hash[e] = (uint32_t)(hk[e] >> 1);
+            if (strand) strand[e] = (uint8_t)(hk[e] & 1);
+        }
+        if (pos) SDF_HIP(hipMemcpy(pos, ix->epos.p, ix->ne * 4, hipMemcpyDeviceToHost));
+        if (written) *written = ix->ne;
+    });
+}
+
+sdf_status sdf_index_packed(sdf_index ix, uint32_t *packed, uint32_t *mask, uint32_t *gaps) {
+    return guarded([&] {
+        if (!ix) throw Error{SDF_EINVAL, "NULL index"};
+        SDF_HIP(hipSetDevice(ix->device));
+        const uint64_t w16 = (ix->total + 15) / 16, w32 = (ix->total + 31) / 32;
+        if (packed) SDF_HIP(hipMemcpy(packed, ix->packed.p, w16 * 4, hipMemcpyDeviceToHost));
+        if (mask) SDF_HIP(hipMemcpy(mask, ix->mask.p, w32 * 4, hipMemcpyDeviceToHost));
+        if (gaps) SDF_HIP(hipMemcpy(gaps, ix->gaps.p, w32 * 4, hipMemcpyDeviceToHost));
+    });
+}
+
+void sdf_index_free(sdf_index ix) {
+    if (!ix) return;
+    (void)hipSetDevice(ix->device);
+    (void)hipDeviceSynchronize();
+    delete ix;
+}
+
+sdf_status sdf_search_batch(sdf_index ix, const sdf_span *qs, uint32_t n,
+                            const sdf_search_params *p, void *hip_stream, sdf_result *out) {
+    if (out) *out = nullptr;
+    sdf_result_s *r = nullptr;
+    sdf_status rc = guarded([&] {
+        if (!ix || !out) throw Error{SDF_EINVAL, "NULL argument"};
+        if (n && !qs) throw Error{SDF_EINVAL, "NULL spans"};
+        SDF_HIP(hipSetDevice(ix->device));
+        r = new sdf_result_s();
+        r->device = ix->device;
+        r->st = (hipStream_t)hip_stream;
+        run_search(ix, qs, n, p, (hipStream_t)hip_stream, r);
+        *out = r;
+    });
+    if (rc != SDF_OK) delete r;
+    return rc;
+}
+
+sdf_status sdf_search(sdf_index ix, const sdf_span *q, const sdf_search_params *p,
+                      void *hip_stream, sdf_result *out) {
+    if (!q) {
+        set_error("NULL span");
+        if (out) *out = nullptr;
+        return SDF_EINVAL;
+    }
+    return sdf_search_batch(ix, q, 1, p, hip_stream, out);
+}
+
+sdf_status sdf_result_count(sdf_result r, uint64_t *n) {
+    return guarded([&] {
+        if (!r || !n) throw Error{SDF_EINVAL, "NULL argument"};
+        *n = r->chain.ncands;
+    });
+}
+
+sdf_status sdf_result_copy(sdf_result r, sdf_candidate *dst, uint64_t cap, uint64_t *written) {
+    return guarded([&] {
+        if (!r) throw Error{SDF_EINVAL, "NULL result"};
+        const uint64_t m = std::min<uint64_t>(cap, r->chain.ncands);
+        if (m && !dst) throw Error{SDF_EINVAL, "NULL destination"};
+        if (m) {
+            SDF_HIP(hipSetDevice(r->device));
+            SDF_HIP(hipMemcpy(dst, r->chain.cands.p, m * sizeof(sdf_candidate), hipMemcpyDeviceToHost));
+        }
+        if (written) *written = m;
+    });
+}
+
+sdf_status sdf_result_seed_count(sdf_result r, uint64_t *n) {
+    return guarded([&] {
+        if (!r || !n) throw Error{SDF_EINVAL, "NULL argument"};
+        *n = r->nseeds;
+    });
+}
+
+sdf_status sdf_result_seeds(sdf_result r, sdf_seed *dst, uint64_t cap, uint64_t *written) {
+    return guarded([&] {
+        if (!r) throw Error{SDF_EINVAL, "NULL result"};
+        const uint64_t m = std::min<uint64_t>(cap, r->nseeds);
+        if (m && !dst) throw Error{SDF_EINVAL, "NULL destination"};
+        if (r->nseeds) {
+            SDF_HIP(hipSetDevice(r->device));
+            if (!r->have_seeds) {
+                DevBuf<uint32_t> sorted(r->nseeds * 6);
+                sort_seeds(r->seeds.p, r->nseeds, sorted.p, r->st);
+                r->h_seeds.resize(r->nseeds * 6);
+                SDF_HIP(hipMemcpy(r->h_seeds.data(), sorted.p, r->nseeds * 24, hipMemcpyDeviceToHost));
+                r->have_seeds = true;
+            }
+            if (m) std::memcpy(dst, r->h_seeds.data(), m * sizeof(sdf_seed));
+        }
+        if (written) *written = m;
+    });
+}
+
+sdf_status sdf_result_timing(sdf_result r, float *ms, uint32_t n_ms) {
+    return guarded([&] {
+        if (!r || (n_ms && !ms)) throw Error{SDF_EINVAL, "NULL argument"};
+        for (uint32_t t = 0; t < n_ms && t < 5; t++) ms[t] = r->ms[t];
+    });
+}
+
+sdf_status sdf_result_stats(sdf_result r, uint64_t *v, uint32_t n_v) {
+    return guarded([&] {
+        if (!r || (n_v && !v)) throw Error{SDF_EINVAL, "NULL argument"};
+        for (uint32_t t = 0; t < n_v && t < 6; t++) v[t] = r->stats[t];
+    });
+}
+
+void sdf_result_free(sdf_result r) {
+    if (!r) return;
+    (void)hipSetDevice(r->device);
+    if (r->st) (void)hipStreamSynchronize(r->st);
+    delete r;
+}
+
+}  // extern "C"

@@ -1,0 +1,328 @@
+// Chaining of seeds into candidate duplication pairs.
+//
+// Two seeds of one query span and one strand are linked when they lie in the
+// same target sequence, their query starts and target starts each differ by
+// less than n, and their diagonals (j - i for '+', j + i for '-') differ by
+// at most floor(delta n) (the overlap bound of the SD conditions, Section 2).
+// Connected components become candidates [min i, max i + n) x
+// [min j, max j + n).  Seeds are sorted into cells of (query, strand,
+// diagonal / (floor(delta n) + 1), i); a seed only needs to look at its own
+// cell and the next one.  Components come from a lock-free union-find whose
+// result does not depend on the order of the unions.
+#include "sdf_impl.h"
+#include "search.h"
+
+namespace sdf {
+
+__device__ __forceinline__ uint32_t ld_relaxed(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ uint32_t uf_find(uint32_t *par, uint32_t x) {
+    for (;;) {
+        uint32_t p = ld_relaxed(par + x);
+        if (p == x) return x;
+        uint32_t gp = ld_relaxed(par + p);
+        if (gp != p) atomicCAS(par + x, p, gp);  // path halving; parents only move up
+        x = p;
+    }
+}
+
+__device__ void uf_union(uint32_t *par, uint32_t a, uint32_t b) {
+    for (;;) {
+        a = uf_find(par, a);
+        b = uf_find(par, b);
+        if (a == b) return;
+        if (a < b) {
+            uint32_t t = a;
+            a = b;
+            b = t;
+        }
+        // hook the larger root under the smaller one
+        if (atomicCAS(par + a, a, b) == a) return;
+    }
+}
+
+__device__ __forceinline__ uint32_t seq_of(const uint64_t *off, uint32_t nseq, uint64_t p) {
+    uint32_t lo = 0, hi = nseq;
+    while (hi - lo > 1) {
+        uint32_t m = (lo + hi) >> 1;
+        if (off[m] <= p) lo = m; else hi = m;
+    }
+    return lo;
+}
+
+// First sort key: i (u32).  Seed t: [qid, i, j, o, c, s].
+__global__ void k_key_i(const uint32_t *seeds, uint64_t ns, uint32_t *key, uint32_t *val) {
+    uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ns) return;
+    key[t] = seeds[t * 6 + 1];
+    val[t] = (uint32_t)t;
+}
+
+__device__ __forceinline__ int64_t diag_of(uint32_t o, uint32_t i, uint32_t j) {
+    return o == 0 ? (int64_t)j - (int64_t)i : (int64_t)j + (int64_t)i;
+}
+
+// Second key: (qid << 40) | (o << 39) | cell, in the order of the first sort.
+__global__ void k_key_cell(const uint32_t *seeds, const uint32_t *order, uint64_t ns,
+                           uint32_t cellw, uint64_t *key, uint32_t *val) {
+    uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ns) return;
+    const uint32_t s = order[t];
+    const uint32_t *r = seeds + (uint64_t)s * 6;
+    const int64_t d = diag_of(r[3], r[1], r[2]) + (1ll << 32);  // >= 0
+    const uint64_t cell = (uint64_t)d / cellw;                  // < 2^34
+    key[t] = ((uint64_t)r[0] << 40) | ((uint64_t)r[3] << 39) | cell;
+    val[t] = s;
+}
+
+struct Sorted {
+    uint64_t *g;   // group key
+    uint32_t *i, *j, *c, *ts;
+    int64_t *d;
+};
+
+__global__ void k_gather(const uint32_t *seeds, const uint64_t *gkey, const uint32_t *order,
+                         uint64_t ns, const uint64_t *off, uint32_t nseq, Sorted s) {
+    uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ns) return;
+    const uint32_t *r = seeds + (uint64_t)order[t] * 6;
+    s.g[t] = gkey[t];
+    s.i[t] = r[1];
+    s.j[t] = r[2];
+    s.c[t] = r[4];
+    s.ts[t] = seq_of(off, nseq, r[2]);
+    s.d[t] = diag_of(r[3], r[1], r[2]);
+}
+
+__device__ __forceinline__ bool linked(const Sorted &s, uint64_t a, uint64_t b, uint32_t n,
+                                       uint32_t mo) {
+    if (s.ts[a] != s.ts[b]) return false;
+    const int64_t dj = (int64_t)s.j[b] - (int64_t)s.j[a];
+    if (dj >= (int64_t)n || -dj >= (int64_t)n) return false;
+    const int64_t di = (int64_t)s.i[b] - (int64_t)s.i[a];
+    if (di >= (int64_t)n || -di >= (int64_t)n) return false;
+    const int64_t dd = s.d[b] - s.d[a];
+    return dd <= (int64_t)mo && -dd <= (int64_t)mo;
+}
+
+__global__ void k_link(Sorted s, uint64_t ns, uint32_t n, uint32_t mo, uint32_t *par) {
+    uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= ns) return;
+    const uint64_t g = s.g[a];
+    const uint64_t ia = s.i[a];
+    // same cell, larger or equal i
+    for (uint64_t b = a + 1; b < ns && s.g[b] == g && (uint64_t)s.i[b] < ia + n; b++)
+        if (linked(s, a, b, n, mo)) uf_union(par, (uint32_t)a, (uint32_t)b);
+    // next cell of the same query and strand: i within (ia - n, ia + n)
+    const uint64_t g2 = g + 1;
+    if ((g2 >> 39) != (g >> 39)) return;
+    uint64_t lo = a + 1, hi = ns;
+    while (lo < hi) {
+        uint64_t m = (lo + hi) >> 1;
+        if (s.g[m] < g2) lo = m + 1; else hi = m;
+    }
+    if (lo >= ns || s.g[lo] != g2) return;
+    uint64_t l2 = lo, h2 = ns;
+    const uint64_t lim = ia >= n ? ia - n + 1 : 0;  // first i not too small
+    while (l2 < h2) {
+        uint64_t m = (l2 + h2) >> 1;
+        if (s.g[m] == g2 && (uint64_t)s.i[m] < lim) l2 = m + 1; else h2 = m;
+    }
+    for (uint64_t b = l2; b < ns && s.g[b] == g2 && (uint64_t)s.i[b] < ia + n; b++)
+        if (linked(s, a, b, n, mo)) uf_union(par, (uint32_t)a, (uint32_t)b);
+}
+
+__global__ void k_flatten(uint32_t *par, uint64_t ns) {
+    uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < ns) par[a] = uf_find(par, (uint32_t)a);
+}
+
+struct Agg {
+    uint32_t *qmin, *qmax, *tmin, *tmax, *cnt, *cmax;
+};
+
+__global__ void k_agg_init(Agg g, uint64_t ns) {
+    uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= ns) return;
+    g.qmin[a] = 0xFFFFFFFFu;
+    g.tmin[a] = 0xFFFFFFFFu;
+    g.qmax[a] = 0;
+    g.tmax[a] = 0;
+    g.cnt[a] = 0;
+    g.cmax[a] = 0;
+}
+
+__global__ void k_agg(Sorted s, const uint32_t *par, uint64_t ns, Agg g) {
+    uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= ns) return;
+    const uint32_t r = par[a];
+    atomicMin(g.qmin + r, s.i[a]);
+    atomicMax(g.qmax + r, s.i[a]);
+    atomicMin(g.tmin + r, s.j[a]);
+    atomicMax(g.tmax + r, s.j[a]);
+    atomicAdd(g.cnt + r, 1u);
+    atomicMax(g.cmax + r, s.c[a]);
+}
+
+__global__ void k_root_flags(const uint32_t *par, uint64_t ns, uint32_t *flag) {
+    uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < ns) flag[a] = (par[a] == (uint32_t)a) ? 1u : 0u;
+}
+
+__global__ void k_emit_cands(Sorted s, const uint32_t *par, uint64_t ns, Agg g,
+                             const uint32_t *pre, const uint64_t *off, uint32_t nseq, uint32_t n,
+                             sdf_candidate *out) {
+    uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= ns || par[a] != (uint32_t)a) return;
+    sdf_candidate c;
+    const uint64_t gk = s.g[a];
+    c.query_id = (uint32_t)(gk >> 40);
+    c.strand = (uint32_t)((gk >> 39) & 1);
+    c.q_seq = seq_of(off, nseq, g.qmin[a]);
+    c.t_seq = s.ts[a];
+    c.q_begin = g.qmin[a] - off[c.q_seq];
+    c.q_end = (uint64_t)g.qmax[a] + n - off[c.q_seq];
+    c.t_begin = g.tmin[a] - off[c.t_seq];
+    c.t_end = (uint64_t)g.tmax[a] + n - off[c.t_seq];
+    c.n_seeds = g.cnt[a];
+    c.max_shared = g.cmax[a];
+    out[pre[a]] = c;
+}
+
+// ------------------------------------------------------------ record sort --
+__device__ __forceinline__ bool cand_less(const sdf_candidate &x, const sdf_candidate &y) {
+#define CMPF(f) if (x.f != y.f) return x.f < y.f;
+    CMPF(query_id) CMPF(strand) CMPF(q_seq) CMPF(q_begin) CMPF(q_end)
+    CMPF(t_seq) CMPF(t_begin) CMPF(t_end) CMPF(n_seeds) CMPF(max_shared)
+#undef CMPF
+    return false;
+}
+
+__global__ void k_pad_cands(sdf_candidate *c, uint64_t n, uint64_t n2) {
+    uint64_t t = n + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n2) return;
+    sdf_candidate z;
+    z.query_id = z.strand = z.q_seq = z.t_seq = 0xFFFFFFFFu;
+    z.q_begin = z.q_end = z.t_begin = z.t_end = ~0ull;
+    z.n_seeds = z.max_shared = 0xFFFFFFFFu;
+    c[t] = z;
+}
+
+__global__ void k_bitonic_cands(sdf_candidate *c, uint64_t n2, uint64_t k, uint64_t j) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n2) return;
+    uint64_t ixj = i ^ j;
+    if (ixj <= i) return;
+    const bool asc = (i & k) == 0;
+    sdf_candidate a = c[i], b = c[ixj];
+    const bool gt = cand_less(b, a);
+    if (gt == asc) {
+        c[i] = b;
+        c[ixj] = a;
+    }
+}
+
+static unsigned nb(uint64_t n, unsigned t = 256) { return (unsigned)((n + t - 1) / t); }
+
+void chain_seeds(const IndexView &ix, const uint32_t *seeds, uint64_t ns, uint32_t n,
+                 uint32_t mo, ChainOut &out, hipStream_t st) {
+    out.ncands = 0;
+    if (ns == 0) {
+        out.cands.alloc(1);
+        return;
+    }
+    DevBuf<uint32_t> k1(ns), order(ns);
+    k_key_i<<<nb(ns), 256, 0, st>>>(seeds, ns, k1.p, order.p);
+    SDF_HIP(hipGetLastError());
+    radix_sort_u32(k1.p, order.p, ns, 32, st);
+    DevBuf<uint64_t> gk(ns);
+    DevBuf<uint32_t> order2(ns);
+    k_key_cell<<<nb(ns), 256, 0, st>>>(seeds, order.p, ns, mo + 1, gk.p, order2.p);
+    SDF_HIP(hipGetLastError());
+    radix_sort_u64(gk.p, order2.p, ns, 64, st);
+    k1.reset();
+    order.reset();
+    DevBuf<uint64_t> sg(ns);
+    DevBuf<uint32_t> si(ns), sj(ns), sc(ns), sts(ns);
+    DevBuf<int64_t> sd(ns);
+    Sorted s{sg.p, si.p, sj.p, sc.p, sts.p, sd.p};
+    k_gather<<<nb(ns), 256, 0, st>>>(seeds, gk.p, order2.p, ns, ix.off, ix.nseq, s);
+    SDF_HIP(hipGetLastError());
+    DevBuf<uint32_t> par(ns);
+    iota_u32(par.p, ns, st);
+    k_link<<<nb(ns), 256, 0, st>>>(s, ns, n, mo, par.p);
+    SDF_HIP(hipGetLastError());
+    k_flatten<<<nb(ns), 256, 0, st>>>(par.p, ns);
+    SDF_HIP(hipGetLastError());
+    DevBuf<uint32_t> a1(ns), a2(ns), a3(ns), a4(ns), a5(ns), a6(ns);
+    Agg g{a1.p, a2.p, a3.p, a4.p, a5.p, a6.p};
+    k_agg_init<<<nb(ns), 256, 0, st>>>(g, ns);
+    k_agg<<<nb(ns), 256, 0, st>>>(s, par.p, ns, g);
+    SDF_HIP(hipGetLastError());
+    DevBuf<uint32_t> flag(ns + 1), pre(ns + 1);
+    k_root_flags<<<nb(ns), 256, 0, st>>>(par.p, ns, flag.p);
+    SDF_HIP(hipGetLastError());
+    scan_u32(flag.p, pre.p, ns, st);
+    uint32_t nc = 0;
+    SDF_HIP(hipMemcpyAsync(&nc, pre.p + ns, 4, hipMemcpyDeviceToHost, st));
+    SDF_HIP(hipStreamSynchronize(st));
+    uint64_t n2 = 1;
+    while (n2 < nc) n2 <<= 1;
+    out.cands.alloc(n2);
+    k_emit_cands<<<nb(ns), 256, 0, st>>>(s, par.p, ns, g, pre.p, ix.off, ix.nseq, n, out.cands.p);
+    SDF_HIP(hipGetLastError());
+    if (n2 > nc) {
+        k_pad_cands<<<nb(n2 - nc), 256, 0, st>>>(out.cands.p, nc, n2);
+        SDF_HIP(hipGetLastError());
+    }
+    for (uint64_t k = 2; k <= n2; k <<= 1)
+        for (uint64_t j = k >> 1; j > 0; j >>= 1) {
+            k_bitonic_cands<<<nb(n2), 256, 0, st>>>(out.cands.p, n2, k, j);
+            SDF_HIP(hipGetLastError());
+        }
+    out.ncands = nc;
+    SDF_HIP(hipStreamSynchronize(st));
+}
+
+// ------------------------------------------------------------- seed sort --
+__global__ void k_seed_key1(const uint32_t *seeds, uint64_t ns, uint64_t *key, uint32_t *val) {
+    uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ns) return;
+    const uint32_t *r = seeds + t * 6;
+    key[t] = ((uint64_t)r[2] << 1) | r[3];
+    val[t] = (uint32_t)t;
+}
+__global__ void k_seed_key2(const uint32_t *seeds, const uint32_t *order, uint64_t ns,
+                            uint64_t *key, uint32_t *val) {
+    uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ns) return;
+    const uint32_t *r = seeds + (uint64_t)order[t] * 6;
+    key[t] = ((uint64_t)r[0] << 32) | r[1];
+    val[t] = order[t];
+}
+__global__ void k_seed_permute(const uint32_t *seeds, const uint32_t *order, uint64_t ns,
+                               uint32_t *dst) {
+    uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ns) return;
+    const uint32_t *r = seeds + (uint64_t)order[t] * 6;
+    for (int f = 0; f < 6; f++) dst[t * 6 + f] = r[f];
+}
+
+void sort_seeds(const uint32_t *seeds, uint64_t ns, uint32_t *dst, hipStream_t st) {
+    if (!ns) return;
+    DevBuf<uint64_t> key(ns);
+    DevBuf<uint32_t> val(ns), val2(ns);
+    k_seed_key1<<<nb(ns), 256, 0, st>>>(seeds, ns, key.p, val.p);
+    SDF_HIP(hipGetLastError());
+    radix_sort_u64(key.p, val.p, ns, 33, st);
+    k_seed_key2<<<nb(ns), 256, 0, st>>>(seeds, val.p, ns, key.p, val2.p);
+    SDF_HIP(hipGetLastError());
+    radix_sort_u64(key.p, val2.p, ns, 64, st);
+    k_seed_permute<<<nb(ns), 256, 0, st>>>(seeds, val2.p, ns, dst);
+    SDF_HIP(hipGetLastError());
+    SDF_HIP(hipStreamSynchronize(st));
+}
+
+}  // namespace sdf

@@ -1,0 +1,340 @@
+// Device primitives: memory pool, prefix sums, stable LSD radix sort, fills.
+#include <map>
+#include <unordered_map>
+
+#include "sdf_impl.h"
+
+namespace sdf {
+
+// ---------------------------------------------------------------- errors --
+static thread_local std::string t_err = "no error";
+void set_error(const std::string &msg) { t_err = msg; }
+const char *last_error() { return t_err.c_str(); }
+
+// ------------------------------------------------------------------ pool --
+namespace {
+std::mutex g_mu;
+std::unordered_map<void *, std::pair<int, size_t>> g_live;  // ptr -> (device, class)
+std::map<std::pair<int, size_t>, std::vector<void *>> g_free;
+
+size_t size_class(size_t b) {
+    if (b <= 256) return 256;
+    if (b <= (64ull << 20)) {
+        size_t c = 256;
+        while (c < b) c <<= 1;
+        return c;
+    }
+    const size_t g = 64ull << 20;
+    return (b + g - 1) / g * g;
+}
+}  // namespace
+
+void pool_trim() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto &kv : g_free) {
+        (void)hipSetDevice(kv.first.first);
+        for (void *p : kv.second) (void)hipFree(p);
+        kv.second.clear();
+    }
+    (void)hipSetDevice(cur);
+}
+
+void *pool_alloc(size_t bytes) {
+    int dev = 0;
+    SDF_HIP(hipGetDevice(&dev));
+    size_t c = size_class(bytes);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_free.find({dev, c});
+        if (it != g_free.end() && !it->second.empty()) {
+            void *p = it->second.back();
+            it->second.pop_back();
+            g_live[p] = {dev, c};
+            return p;
+        }
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, c);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        pool_trim();
+        e = hipMalloc(&p, c);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error{SDF_ENOMEM, "device allocation of " + std::to_string(c) + " bytes failed"};
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_live[p] = {dev, c};
+    return p;
+}
+
+void pool_free(void *p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_live.find(p);
+    if (it == g_live.end()) return;
+    g_free[it->second].push_back(p);
+    g_live.erase(it);
+}
+
+// ---------------------------------------------------------------- fills --
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, uint64_t n) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+__global__ void k_iota_u32(uint32_t *p, uint64_t n) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = (uint32_t)i;
+}
+
+static unsigned grid_for(uint64_t n, unsigned threads, unsigned cap = 65536) {
+    uint64_t g = (n + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+void fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t st) {
+    if (!n) return;
+    k_fill_u32<<<grid_for(n, 256), 256, 0, st>>>(p, v, n);
+    SDF_HIP(hipGetLastError());
+}
+void iota_u32(uint32_t *p, uint64_t n, hipStream_t st) {
+    if (!n) return;
+    k_iota_u32<<<grid_for(n, 256), 256, 0, st>>>(p, n);
+    SDF_HIP(hipGetLastError());
+}
+
+// ----------------------------------------------------------------- scans --
+constexpr int SC_THREADS = 1024;
+constexpr int SC_ITEMS = 4;
+constexpr int SC_TILE = SC_THREADS * SC_ITEMS;
+
+// Block-wide exclusive scan of one value per thread; returns the exclusive
+// prefix and writes the block total to *total.
+__device__ inline uint64_t block_excl_scan(uint64_t v, uint64_t *lds /* >= 17 */,
+                                           uint64_t *total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint64_t x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint64_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) lds[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t s = 0;
+        int nw = (blockDim.x + 63) >> 6;
+        for (int w = 0; w < nw; w++) {
+            uint64_t t = lds[w];
+            lds[w] = s;
+            s += t;
+        }
+        lds[16] = s;
+    }
+    __syncthreads();
+    uint64_t r = lds[wave] + x - v;
+    *total = lds[16];
+    __syncthreads();
+    return r;
+}
+
+template <class T>
+__global__ void __launch_bounds__(SC_THREADS) k_scan_reduce(const T *in, uint64_t n, uint64_t *sums) {
+    __shared__ uint64_t lds[17];
+    uint64_t base = (uint64_t)blockIdx.x * SC_TILE + (uint64_t)threadIdx.x * SC_ITEMS;
+    uint64_t s = 0;
+#pragma unroll
+    for (int t = 0; t < SC_ITEMS; t++)
+        if (base + t < n) s += (uint64_t)in[base + t];
+    uint64_t tot;
+    block_excl_scan(s, lds, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+template <class T, class O>
+__global__ void __launch_bounds__(SC_THREADS) k_scan_down(const T *in, uint64_t n, const uint64_t *boff,
+                                                      O *out, int write_total) {
+    __shared__ uint64_t lds[17];
+    uint64_t base = (uint64_t)blockIdx.x * SC_TILE + (uint64_t)threadIdx.x * SC_ITEMS;
+    uint64_t v[SC_ITEMS];
+    uint64_t s = 0;
+#pragma unroll
+    for (int t = 0; t < SC_ITEMS; t++) {
+        v[t] = (base + t < n) ? (uint64_t)in[base + t] : 0;
+        s += v[t];
+    }
+    uint64_t tot;
+    uint64_t pre = block_excl_scan(s, lds, &tot) + (boff ? boff[blockIdx.x] : 0);
+#pragma unroll
+    for (int t = 0; t < SC_ITEMS; t++) {
+        if (base + t < n) out[base + t] = (O)pre;
+        pre += v[t];
+    }
+    if (write_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == blockDim.x - 1)
+        out[n] = (O)pre;
+}
+
+template <class T, class O>
+static void scan_impl(const T *in, O *out, uint64_t n, hipStream_t st) {
+    uint64_t nb = (n + SC_TILE - 1) / SC_TILE;
+    if (nb <= 1) {
+        k_scan_down<T, O><<<1, SC_THREADS, 0, st>>>(in, n, nullptr, out, 1);
+        SDF_HIP(hipGetLastError());
+        return;
+    }
+    DevBuf<uint64_t> sums(nb + 1);
+    k_scan_reduce<T><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, n, sums.p);
+    SDF_HIP(hipGetLastError());
+    DevBuf<uint64_t> off(nb + 1);
+    scan_impl<uint64_t, uint64_t>(sums.p, off.p, nb, st);
+    k_scan_down<T, O><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, n, off.p, out, 1);
+    SDF_HIP(hipGetLastError());
+    // temporaries are returned to the pool after the stream consumes them
+    SDF_HIP(hipStreamSynchronize(st));
+}
+
+void scan_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n, hipStream_t st) {
+    scan_impl<uint32_t, uint64_t>(in, out, n, st);
+}
+void scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, hipStream_t st) {
+    scan_impl<uint32_t, uint32_t>(in, out, n, st);
+}
+
+// ------------------------------------------------------------ radix sort --
+constexpr int RS_THREADS = 256;
+constexpr int RS_WAVES = RS_THREADS / 64;
+constexpr int RS_ITEMS = 16;
+constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
+constexpr int RS_BINS = 256;
+
+template <class K>
+__global__ void __launch_bounds__(RS_THREADS) k_rs_hist(const K *keys, uint64_t n, int shift,
+                                                     uint32_t *hist, uint32_t nblocks) {
+    __shared__ uint32_t h[RS_BINS];
+    for (int i = threadIdx.x; i < RS_BINS; i += RS_THREADS) h[i] = 0;
+    __syncthreads();
+    uint64_t base = (uint64_t)blockIdx.x * RS_TILE;
+#pragma unroll 4
+    for (int r = 0; r < RS_ITEMS; r++) {
+        uint64_t idx = base + (uint64_t)r * RS_THREADS + threadIdx.x;
+        if (idx < n) atomicAdd(&h[(uint32_t)(keys[idx] >> shift) & (RS_BINS - 1)], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < RS_BINS; i += RS_THREADS)
+        hist[(uint64_t)i * nblocks + blockIdx.x] = h[i];
+}
+
+// Stable scatter: elements keep their input order within a digit.  Wave w
+// of the block owns the w-th quarter of the tile and walks it 64 elements at
+// a time; lanes with equal digits are ranked with eight ballots.
+template <class K>
+__global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const K *kin, const uint32_t *vin, K *kout,
+                                                        uint32_t *vout, uint64_t n, int shift,
+                                                        const uint64_t *hoff, uint32_t nblocks) {
+    __shared__ uint32_t cnt[RS_WAVES][RS_BINS];
+    __shared__ uint64_t boff[RS_BINS];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < RS_BINS; i += RS_THREADS) {
+        boff[i] = hoff[(uint64_t)i * nblocks + blockIdx.x];
+#pragma unroll
+        for (int w = 0; w < RS_WAVES; w++) cnt[w][i] = 0;
+    }
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * RS_TILE + (uint64_t)wave * (RS_TILE / RS_WAVES);
+    K kk[RS_ITEMS];
+    uint32_t vv[RS_ITEMS];
+    uint32_t rk[RS_ITEMS];
+    uint32_t dg[RS_ITEMS];
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+    for (int r = 0; r < RS_ITEMS; r++) {
+        uint64_t idx = base + (uint64_t)r * 64 + lane;
+        bool valid = idx < n;
+        uint32_t d = 0;
+        if (valid) {
+            kk[r] = kin[idx];
+            vv[r] = vin[idx];
+            d = (uint32_t)(kk[r] >> shift) & (RS_BINS - 1);
+        }
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            bool bit = (d >> b) & 1;
+            uint64_t bb = __ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        dg[r] = d;
+        if (valid) {
+            rk[r] = cnt[wave][d] + (uint32_t)__popcll(m & lt);
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (valid && (m >> lane) == 1ull) cnt[wave][d] += (uint32_t)__popcll(m);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < RS_BINS; i += RS_THREADS) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int w = 0; w < RS_WAVES; w++) {
+            uint32_t t = cnt[w][i];
+            cnt[w][i] = s;
+            s += t;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RS_ITEMS; r++) {
+        uint64_t idx = base + (uint64_t)r * 64 + lane;
+        if (idx < n) {
+            uint64_t pos = boff[dg[r]] + cnt[wave][dg[r]] + rk[r];
+            kout[pos] = kk[r];
+            vout[pos] = vv[r];
+        }
+    }
+}
+
+template <class K>
+static void radix_impl(K *keys, uint32_t *vals, uint64_t n, int bits, hipStream_t st) {
+    if (n <= 1 || bits <= 0) return;
+    uint64_t nb64 = (n + RS_TILE - 1) / RS_TILE;
+    if (nb64 > 0xFFFFFFFFull) throw Error{SDF_EINVAL, "radix sort too large"};
+    uint32_t nb = (uint32_t)nb64;
+    DevBuf<K> k2(n);
+    DevBuf<uint32_t> v2(n);
+    DevBuf<uint32_t> hist((uint64_t)RS_BINS * nb);
+    DevBuf<uint64_t> hoff((uint64_t)RS_BINS * nb + 1);
+    K *ka = keys, *kb = k2.p;
+    uint32_t *va = vals, *vb = v2.p;
+    int passes = (bits + 7) / 8;
+    for (int p = 0; p < passes; p++) {
+        int shift = 8 * p;
+        k_rs_hist<K><<<nb, RS_THREADS, 0, st>>>(ka, n, shift, hist.p, nb);
+        SDF_HIP(hipGetLastError());
+        scan_u32_to_u64(hist.p, hoff.p, (uint64_t)RS_BINS * nb, st);
+        k_rs_scatter<K><<<nb, RS_THREADS, 0, st>>>(ka, va, kb, vb, n, shift, hoff.p, nb);
+        SDF_HIP(hipGetLastError());
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    if (ka != keys) {
+        SDF_HIP(hipMemcpyAsync(keys, ka, n * sizeof(K), hipMemcpyDeviceToDevice, st));
+        SDF_HIP(hipMemcpyAsync(vals, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+    }
+    SDF_HIP(hipStreamSynchronize(st));
+}
+
+void radix_sort_u32(uint32_t *keys, uint32_t *vals, uint64_t n, int bits, hipStream_t st) {
+    radix_impl<uint32_t>(keys, vals, n, bits, st);
+}
+void radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t n, int bits, hipStream_t st) {
+    radix_impl<uint64_t>(keys, vals, n, bits, st);
+}
+
+}  // namespace sdf

@@ -1,0 +1,120 @@
+// Internal declarations of the MI355X seed-filter library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/sdf.h"
+
+namespace sdf {
+
+constexpr uint32_t NONE32 = 0xFFFFFFFFu;
+constexpr uint64_t SENT64 = 0xFFFFFFFFFFFFFFFFull;
+constexpr uint64_t MAX_TOTAL = 0xFFFFFFFFull - (1ull << 20);
+
+// Error reporting -----------------------------------------------------------
+void set_error(const std::string &msg);
+struct Error {
+    sdf_status code;
+    std::string msg;
+};
+
+#define SDF_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            throw ::sdf::Error{SDF_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+// Device memory pool ----------------------------------------------------------
+// Size-class free lists per device; blocks are returned, not released, until
+// pool_trim() or process end.
+void *pool_alloc(size_t bytes);
+void pool_free(void *p);
+void pool_trim();
+
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t count) { alloc(count); }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        reset();
+        p = o.p; n = o.n; o.p = nullptr; o.n = 0;
+        return *this;
+    }
+    void alloc(size_t count) {
+        reset();
+        p = static_cast<T *>(pool_alloc((count ? count : 1) * sizeof(T)));
+        n = count;
+    }
+    void reset() {
+        if (p) pool_free(p);
+        p = nullptr;
+        n = 0;
+    }
+    ~DevBuf() { reset(); }
+};
+
+// Primitives (prims.hip) -----------------------------------------------------
+// Exclusive prefix sum of n u32 values into u64 outputs; out[n] = total.
+void scan_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n, hipStream_t st);
+// Exclusive prefix sum, u32 in, u32 out (caller guarantees no overflow); out[n] = total.
+void scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, hipStream_t st);
+// Stable LSD radix sort of (key, value) pairs on key bits [0, bits).
+void radix_sort_u32(uint32_t *keys, uint32_t *vals, uint64_t n, int bits, hipStream_t st);
+void radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t n, int bits, hipStream_t st);
+void fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t st);
+void iota_u32(uint32_t *p, uint64_t n, hipStream_t st);
+
+// Index --------------------------------------------------------------------
+struct IndexView {  // plain pointers for kernels
+    uint32_t k, w;
+    uint32_t nseq;
+    uint64_t total;
+    const uint64_t *off;
+    const uint32_t *packed, *mask, *gaps;
+    uint64_t nm;
+    const uint32_t *mpos, *mhash, *mprev;
+    const uint8_t *mflags;
+    uint64_t ne;
+    const uint32_t *dir;  // directory over the top dir_bits of key = hash<<1|strand
+    uint32_t dir_bits, dir_shift;
+    const uint32_t *epos;
+    const uint8_t *ekeylo;  // low key bits per entry when dir_shift > 0
+    uint64_t nseg;
+    const uint32_t *segb, *sege, *segseq;
+};
+
+}  // namespace sdf
+
+struct sdf_index_s {
+    int device = 0;
+    uint32_t k = 0, w = 0, nseq = 0;
+    uint64_t total = 0;
+    std::vector<uint64_t> h_off;
+    sdf::DevBuf<uint64_t> off;
+    sdf::DevBuf<uint32_t> packed, mask, gaps;
+    uint64_t nm = 0, ne = 0, nseg = 0;
+    sdf::DevBuf<uint32_t> mpos, mhash, mprev;
+    sdf::DevBuf<uint8_t> mflags;
+    sdf::DevBuf<uint32_t> dir, epos;
+    sdf::DevBuf<uint8_t> ekeylo;
+    uint32_t dir_bits = 0, dir_shift = 0;
+    sdf::DevBuf<uint32_t> segb, sege, segseq;
+    uint64_t device_bytes = 0;
+    sdf::IndexView view() const;
+};
+
+namespace sdf {
+void build_index(sdf_index_s *ix, const char *const *seqs, const uint64_t *lens,
+                 uint32_t n_seqs, hipStream_t st);
+}

@@ -1,0 +1,48 @@
+// Launch interface of the search kernels (internal).
+#pragma once
+#include "sdf_impl.h"
+
+namespace sdf {
+
+struct SpanDesc {
+    uint64_t gb, ge;        // global [begin, end) of the span
+    uint32_t qid, qseq;     // query id, sequence of the span
+    uint32_t m_lo, m_hi;    // minimizer indices of the span's window starts
+    uint32_t tile0, _pad;   // first tile of the span
+};
+
+enum { CNT_SEEDS = 0, CNT_WINDOWS, CNT_HITS, CNT_KEPT, CNT_PARTS, CNT_TILES, CNT_N };
+
+struct SearchArgs {
+    IndexView ix;
+    uint32_t n, max_overlap;
+    const uint16_t *T;       // T[s] = ceil(tau * s)
+    const SpanDesc *spans;
+    uint32_t nspans;
+    uint32_t total_tiles;
+    uint32_t *work;          // tile counter (starts at 0)
+    uint32_t core;           // window starts per tile
+    uint32_t hpart;          // target hits per partition
+    uint32_t bin_shift;      // target bins of 2^bin_shift >= n bases
+    uint32_t *seeds;         // 6 u32 per seed
+    uint64_t seed_cap;
+    unsigned long long *counters;  // CNT_N
+    uint32_t *err;
+};
+
+void launch_span_setup(const IndexView &ix, SpanDesc *spans, uint32_t nspans, uint32_t n,
+                       uint32_t core, uint32_t *ntiles, uint32_t *tile0, hipStream_t st);
+void launch_tile_search(const SearchArgs &a, uint32_t grid, hipStream_t st);
+uint32_t tile_core_max();
+
+// Chaining (chain.hip): seeds -> sorted candidates; returns the candidate count.
+struct ChainOut {
+    DevBuf<sdf_candidate> cands;
+    uint64_t ncands = 0;
+};
+void chain_seeds(const IndexView &ix, const uint32_t *seeds, uint64_t nseeds, uint32_t n,
+                 uint32_t max_overlap, ChainOut &out, hipStream_t st);
+// Seeds sorted by (query_id, i, j, strand) into dst (device, 6 u32 each).
+void sort_seeds(const uint32_t *seeds, uint64_t nseeds, uint32_t *dst, hipStream_t st);
+
+}  // namespace sdf

@@ -1,0 +1,247 @@
+"""ctypes binding of the C ABI declared in ``include/sdf.h``.
+
+Argument marshalling only: every step of indexing and search runs in the HIP
+kernels of ``libsdf.so``.  Loading fails loudly when the library has not been
+built; there is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsdf.so")
+
+SDF_OK, SDF_EINVAL, SDF_ENOMEM, SDF_EDEVICE, SDF_ERANGE, SDF_EBUSY, SDF_EINTERNAL = (
+    0, -1, -2, -3, -4, -5, -6)
+SDF_TIMING = 1
+
+CANDIDATE_DTYPE = np.dtype([("query_id", "<u4"), ("strand", "<u4"), ("q_seq", "<u4"),
+                            ("t_seq", "<u4"), ("q_begin", "<u8"), ("q_end", "<u8"),
+                            ("t_begin", "<u8"), ("t_end", "<u8"), ("n_seeds", "<u4"),
+                            ("max_shared", "<u4")])
+SEED_DTYPE = np.dtype([("query_id", "<u4"), ("i", "<u4"), ("j", "<u4"), ("strand", "<u4"),
+                       ("shared", "<u4"), ("sketch", "<u4")])
+EXPORTS = ["sdf_last_error", "sdf_index_build", "sdf_index_info", "sdf_index_minimizers",
+           "sdf_index_entries", "sdf_index_packed", "sdf_index_free", "sdf_search",
+           "sdf_search_batch", "sdf_result_count", "sdf_result_copy", "sdf_result_seed_count",
+           "sdf_result_seeds", "sdf_result_timing", "sdf_result_stats", "sdf_result_free"]
+
+
+class SdfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("sdf error %d: %s" % (code, msg))
+        self.code = code
+
+
+class _IndexParams(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_uint32), ("w", ctypes.c_uint32)]
+
+
+class _SearchParams(ctypes.Structure):
+    _fields_ = [("max_error", ctypes.c_double), ("min_len", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32)]
+
+
+class _Span(ctypes.Structure):
+    _fields_ = [("seq", ctypes.c_uint32), ("_pad", ctypes.c_uint32),
+                ("begin", ctypes.c_uint64), ("end", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libsdf.so is not built; run paper_1807_00205_amd/build.py "
+                              "(or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, u32, u64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
+        P = ctypes.POINTER
+        st = ctypes.c_int32
+        L.sdf_last_error.restype = ctypes.c_char_p
+        L.sdf_index_build.restype = st
+        L.sdf_index_build.argtypes = [vp, vp, u32, P(_IndexParams), vp, P(vp)]
+        L.sdf_index_info.restype = st
+        L.sdf_index_info.argtypes = [vp, P(u64), P(u64), P(u64)]
+        L.sdf_index_minimizers.restype = st
+        L.sdf_index_minimizers.argtypes = [vp, vp, vp, vp, u64, P(u64)]
+        L.sdf_index_entries.restype = st
+        L.sdf_index_entries.argtypes = [vp, vp, vp, vp, u64, P(u64)]
+        L.sdf_index_packed.restype = st
+        L.sdf_index_packed.argtypes = [vp, vp, vp, vp]
+        L.sdf_index_free.restype = None
+        L.sdf_index_free.argtypes = [vp]
+        L.sdf_search.restype = st
+        L.sdf_search.argtypes = [vp, P(_Span), P(_SearchParams), vp, P(vp)]
+        L.sdf_search_batch.restype = st
+        L.sdf_search_batch.argtypes = [vp, vp, u32, P(_SearchParams), vp, P(vp)]
+        L.sdf_result_count.restype = st
+        L.sdf_result_count.argtypes = [vp, P(u64)]
+        L.sdf_result_copy.restype = st
+        L.sdf_result_copy.argtypes = [vp, vp, u64, P(u64)]
+        L.sdf_result_seed_count.restype = st
+        L.sdf_result_seed_count.argtypes = [vp, P(u64)]
+        L.sdf_result_seeds.restype = st
+        L.sdf_result_seeds.argtypes = [vp, vp, u64, P(u64)]
+        L.sdf_result_timing.restype = st
+        L.sdf_result_timing.argtypes = [vp, P(ctypes.c_float), u32]
+        L.sdf_result_stats.restype = st
+        L.sdf_result_stats.argtypes = [vp, P(u64), u32]
+        L.sdf_result_free.restype = None
+        L.sdf_result_free.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != SDF_OK:
+        raise SdfError(rc, lib().sdf_last_error().decode())
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)  # torch.cuda.Stream
+
+
+class Result:
+    """Candidates (and seeds) of one search; owns the library result."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    def close(self):
+        if self._h:
+            lib().sdf_result_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def candidates(self) -> np.ndarray:
+        n = ctypes.c_uint64()
+        _check(lib().sdf_result_count(self._h, ctypes.byref(n)))
+        out = np.empty(n.value, CANDIDATE_DTYPE)
+        w = ctypes.c_uint64()
+        _check(lib().sdf_result_copy(self._h, out.ctypes.data_as(ctypes.c_void_p), n.value,
+                                     ctypes.byref(w)))
+        return out
+
+    def seeds(self) -> np.ndarray:
+        n = ctypes.c_uint64()
+        _check(lib().sdf_result_seed_count(self._h, ctypes.byref(n)))
+        out = np.empty(n.value, SEED_DTYPE)
+        w = ctypes.c_uint64()
+        _check(lib().sdf_result_seeds(self._h, out.ctypes.data_as(ctypes.c_void_p), n.value,
+                                      ctypes.byref(w)))
+        return out
+
+    def timing(self) -> np.ndarray:
+        ms = (ctypes.c_float * 5)()
+        _check(lib().sdf_result_timing(self._h, ms, 5))
+        return np.array(ms[:], dtype=np.float64)
+
+    def stats(self) -> dict:
+        v = (ctypes.c_uint64 * 6)()
+        _check(lib().sdf_result_stats(self._h, v, 6))
+        keys = ["windows", "hits", "kept", "tiles", "partitions", "seeds"]
+        return dict(zip(keys, [int(x) for x in v]))
+
+
+class Index:
+    """Device-resident index of a set of sequences (``sdf_index_build``)."""
+
+    def __init__(self, seqs: Sequence, k: int = 12, w: int = 16, stream=None):
+        bufs = [np.ascontiguousarray(np.frombuffer(s, dtype=np.uint8) if isinstance(s, bytes)
+                                     else s, dtype=np.uint8) for s in seqs]
+        self._keep = bufs
+        n = len(bufs)
+        ptrs = (ctypes.c_void_p * max(n, 1))(*[b.ctypes.data for b in bufs])
+        lens = (ctypes.c_uint64 * max(n, 1))(*[len(b) for b in bufs])
+        p = _IndexParams(k, w)
+        h = ctypes.c_void_p()
+        _check(lib().sdf_index_build(ctypes.cast(ptrs, ctypes.c_void_p),
+                                     ctypes.cast(lens, ctypes.c_void_p), n, ctypes.byref(p),
+                                     _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h.value
+        self._keep = None
+        self.k, self.w = k, w
+        self.lengths = [len(b) for b in bufs]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sdf_index_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> Tuple[int, int, int]:
+        a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().sdf_index_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def minimizers(self):
+        nm, _, _ = self.info()
+        pos = np.empty(nm, np.uint32)
+        h = np.empty(nm, np.uint32)
+        fl = np.empty(nm, np.uint8)
+        w = ctypes.c_uint64()
+        _check(lib().sdf_index_minimizers(self._h, pos.ctypes.data_as(ctypes.c_void_p),
+                                          h.ctypes.data_as(ctypes.c_void_p),
+                                          fl.ctypes.data_as(ctypes.c_void_p), nm, ctypes.byref(w)))
+        return pos, h, fl
+
+    def entries(self):
+        _, ne, _ = self.info()
+        h = np.empty(ne, np.uint32)
+        st = np.empty(ne, np.uint8)
+        pos = np.empty(ne, np.uint32)
+        w = ctypes.c_uint64()
+        _check(lib().sdf_index_entries(self._h, h.ctypes.data_as(ctypes.c_void_p),
+                                       st.ctypes.data_as(ctypes.c_void_p),
+                                       pos.ctypes.data_as(ctypes.c_void_p), ne, ctypes.byref(w)))
+        return h, st, pos
+
+    def packed(self):
+        total = sum(self.lengths)
+        pk = np.empty((total + 15) // 16, np.uint32)
+        mk = np.empty((total + 31) // 32, np.uint32)
+        gp = np.empty((total + 31) // 32, np.uint32)
+        _check(lib().sdf_index_packed(self._h, pk.ctypes.data_as(ctypes.c_void_p),
+                                      mk.ctypes.data_as(ctypes.c_void_p),
+                                      gp.ctypes.data_as(ctypes.c_void_p)))
+        return pk, mk, gp
+
+    def search(self, span: Tuple[int, int, int], max_error: float = 0.25, min_len: int = 1000,
+               timing: bool = False, stream=None) -> Result:
+        sp = _Span(span[0], 0, span[1], span[2])
+        p = _SearchParams(max_error, min_len, SDF_TIMING if timing else 0)
+        h = ctypes.c_void_p()
+        _check(lib().sdf_search(self._h, ctypes.byref(sp), ctypes.byref(p), _stream_ptr(stream),
+                                ctypes.byref(h)))
+        return Result(h.value)
+
+    def search_batch(self, spans: Iterable[Tuple[int, int, int]], max_error: float = 0.25,
+                     min_len: int = 1000, timing: bool = False, stream=None) -> Result:
+        spans = list(spans)
+        arr = (_Span * max(1, len(spans)))(*[_Span(s, 0, b, e) for (s, b, e) in spans])
+        p = _SearchParams(max_error, min_len, SDF_TIMING if timing else 0)
+        h = ctypes.c_void_p()
+        _check(lib().sdf_search_batch(self._h, ctypes.cast(arr, ctypes.c_void_p), len(spans),
+                                      ctypes.byref(p), _stream_ptr(stream), ctypes.byref(h)))
+        return Result(h.value)

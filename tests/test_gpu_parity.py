@@ -1,0 +1,236 @@
+"""Parity of the HIP library (through its C ABI) with the CPU oracle.
+
+Every comparison is exact: all outputs are integers.  Inputs come from the
+seeded generators in ``paper_1807_00205_amd.synth``.
+"""
+import numpy as np
+import pytest
+
+from paper_1807_00205_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_1807_00205_amd import sdf
+    sdf.lib()
+    return sdf
+
+
+def _same(a, b, fields, what=""):
+    assert len(a) == len(b), "%s: %d vs %d records" % (what, len(a), len(b))
+    for f in fields:
+        x, y = np.asarray(a[f]), np.asarray(b[f])
+        if not np.array_equal(x.astype(np.uint64), y.astype(np.uint64)):
+            bad = np.nonzero(x.astype(np.uint64) != y.astype(np.uint64))[0][:5]
+            raise AssertionError("%s: field %s differs at %s: gpu %s oracle %s" %
+                                 (what, f, bad, x[bad], y[bad]))
+
+
+SEED_F = ["query_id", "i", "j", "strand", "shared", "sketch"]
+CAND_F = ["query_id", "strand", "q_seq", "t_seq", "q_begin", "q_end", "t_begin", "t_end",
+          "n_seeds", "max_shared"]
+
+
+def _extra_seqs():
+    return [np.frombuffer(x, np.uint8).copy() for x in
+            (b"ACG", b"ACGTTGCAACGTAGG", b"ACGTTGCAACGTAGGCATTGACCAGTACAAAA",
+             b"NNNNNNNNNNNNNNNNNNNNN", b"acgtnacgtacgtgggtttacgtacg")]
+
+
+def _mixed_genome(seed, length=6000, n_seqs=3):
+    g = synth.small_case(seed, length=length, n_sd=3, sd_lo=400, sd_hi=900, n_seqs=n_seqs,
+                         lower_frac=0.25, n_gaps=2, gap_len=40, rate_hi=0.06)
+    g.seqs = g.seqs + _extra_seqs()
+    g.spans = [(i, 0, len(s)) for i, s in enumerate(g.seqs)]
+    return g
+
+
+def test_encode_bits(S, oracle_lib):
+    """a1: 2-bit codes, soft-mask bits and gap bits of every base."""
+    g = _mixed_genome(1)
+    b, off = g.concat()
+    code, lower = oracle_lib.encode(b)
+    ix = S.Index(g.seqs, 12, 16)
+    pk, mk, gp = ix.packed()
+    total = len(b)
+    c = np.where(code == 255, 0, code).astype(np.uint64)
+    pad16 = (-total) % 16
+    cw = np.concatenate([c, np.zeros(pad16, np.uint64)]).reshape(-1, 16)
+    exp_pk = (cw << (2 * np.arange(16, dtype=np.uint64))).sum(axis=1).astype(np.uint32)
+    assert np.array_equal(pk, exp_pk)
+    pad32 = (-total) % 32
+    lw = np.concatenate([lower.astype(np.uint64), np.zeros(pad32, np.uint64)]).reshape(-1, 32)
+    nw = np.concatenate([(code == 255).astype(np.uint64), np.ones(pad32, np.uint64)]).reshape(-1, 32)
+    sh = np.arange(32, dtype=np.uint64)
+    assert np.array_equal(mk, (lw << sh).sum(axis=1).astype(np.uint32))
+    assert np.array_equal(gp, (nw << sh).sum(axis=1).astype(np.uint32))
+
+
+@pytest.mark.parametrize("k,w", [(12, 16), (5, 1), (16, 64), (11, 7), (14, 20)])
+def test_winnow_and_reverse_index(S, oracle_lib, k, w):
+    """a2-a4: minimizer positions, hashes, strand and eligibility flags, and
+    the reverse index grouped by (hash, strand) with ascending positions."""
+    g = _mixed_genome(2 + k + w, length=20000)
+    b, off = g.concat()
+    orc = oracle_lib.OracleIndex(b, off, k, w)
+    ix = S.Index(g.seqs, k, w)
+    opos, oh, ofl = orc.minimizers()
+    gpos, gh, gfl = ix.minimizers()
+    assert np.array_equal(gpos, opos)
+    assert np.array_equal(gh, oh)
+    assert np.array_equal(gfl, ofl)
+    eh, es, ep = orc.entries()
+    gh2, gs2, gp2 = ix.entries()
+    assert np.array_equal(gh2, eh) and np.array_equal(gs2, es) and np.array_equal(gp2, ep)
+
+
+def test_winnow_large_uniform(S, oracle_lib):
+    """Minimizers of 1 Mbp (config 1) across many blocks of the winnow kernel."""
+    g = synth.config1()
+    b, off = g.concat()
+    orc = oracle_lib.OracleIndex(b, off, 12, 16)
+    ix = S.Index(g.seqs, 12, 16)
+    for x, y in zip(ix.minimizers(), orc.minimizers()):
+        assert np.array_equal(x, y)
+    for x, y in zip(ix.entries(), orc.entries()):
+        assert np.array_equal(x, y)
+
+
+SMALL = [
+    dict(seed=1, length=3000, n_sd=2, n_seqs=1, lower_frac=0.0, n_gaps=0),
+    dict(seed=2, length=2500, n_sd=2, n_seqs=2, lower_frac=0.25, n_gaps=1),
+    dict(seed=3, length=2000, n_sd=3, n_seqs=3, lower_frac=0.1, n_gaps=2),
+    dict(seed=4, length=4000, n_sd=2, n_seqs=1, lower_frac=0.4, n_gaps=1),
+]
+
+
+@pytest.mark.parametrize("case", SMALL, ids=lambda c: "seed%d" % c["seed"])
+@pytest.mark.parametrize("max_error,min_len,k,w", [(0.25, 200, 12, 16), (0.1, 300, 11, 8),
+                                                   (0.3, 120, 9, 5)])
+def test_search_small(S, oracle_lib, case, max_error, min_len, k, w):
+    """a5-a10 on small inputs (several sequences, masking, gaps, partial
+    spans): seeds and candidates equal the oracle's exactly."""
+    c = dict(case)
+    seed = c.pop("seed")
+    g = synth.small_case(60 + seed, sd_lo=300, sd_hi=600, gap_len=25, rate_hi=0.06, **c)
+    b, off = g.concat()
+    L0 = len(g.seqs[0])
+    spans = list(g.spans) + [(0, 100, L0 - 50), (0, L0 // 3, L0 // 3 + 700), (0, 10, 40)]
+    orc = oracle_lib.OracleIndex(b, off, k, w)
+    os_, oc = orc.search(spans, max_error, min_len)
+    ix = S.Index(g.seqs, k, w)
+    r = ix.search_batch(spans, max_error, min_len)
+    _same(r.seeds(), os_, SEED_F, "seeds")
+    _same(r.candidates(), oc, CAND_F, "candidates")
+
+
+def test_search_config1(S, oracle_lib):
+    """The 1 Mbp workload, self against self: exact seeds and candidates."""
+    g = synth.config1()
+    b, off = g.concat()
+    orc = oracle_lib.OracleIndex(b, off, 12, 16)
+    os_, oc = orc.search(g.spans, 0.25, 1000)
+    ix = S.Index(g.seqs, 12, 16)
+    r = ix.search(g.spans[0], 0.25, 1000)
+    _same(r.seeds(), os_, SEED_F, "seeds")
+    _same(r.candidates(), oc, CAND_F, "candidates")
+
+
+def test_search_config1_tile_shapes(S, oracle_lib, monkeypatch):
+    """Results do not depend on the tile size or the target partitioning."""
+    g = synth.config1()
+    b, off = g.concat()
+    orc = oracle_lib.OracleIndex(b, off, 12, 16)
+    os_, oc = orc.search(g.spans, 0.25, 1000)
+    ix = S.Index(g.seqs, 12, 16)
+    for core, hpart in ((64, 1024), (200, 3000), (512, 100000)):
+        monkeypatch.setenv("SDF_TILE_CORE", str(core))
+        monkeypatch.setenv("SDF_HITS_PER_PART", str(hpart))
+        r = ix.search(g.spans[0], 0.25, 1000)
+        _same(r.seeds(), os_, SEED_F, "seeds core=%d" % core)
+        _same(r.candidates(), oc, CAND_F, "candidates core=%d" % core)
+
+
+def test_edge_spans(S, oracle_lib):
+    """Empty spans, spans shorter than n, spans at sequence ends, sequences
+    shorter than k or made of gap bases, and several spans in one batch."""
+    g = _mixed_genome(9, length=5000)
+    b, off = g.concat()
+    lens = [len(s) for s in g.seqs]
+    spans = [(0, 0, 0), (0, 100, 100 + 300), (0, lens[0] - 760, lens[0]), (1, 0, lens[1]),
+             (3, 0, lens[3]), (6, 0, lens[6]), (0, 0, lens[0]), (2, 17, lens[2] - 3)]
+    orc = oracle_lib.OracleIndex(b, off, 12, 16)
+    os_, oc = orc.search(spans, 0.25, 1000)
+    ix = S.Index(g.seqs, 12, 16)
+    r = ix.search_batch(spans, 0.25, 1000)
+    _same(r.seeds(), os_, SEED_F, "seeds")
+    _same(r.candidates(), oc, CAND_F, "candidates")
+    r0 = ix.search((0, 5, 5))
+    assert len(r0.candidates()) == 0 and len(r0.seeds()) == 0
+
+
+def test_batch_equals_plain(S):
+    """A batch of spans gives, per span, what a plain search of that span
+    gives."""
+    g = synth.config1()
+    ix = S.Index(g.seqs, 12, 16)
+    rng = synth.rng_for(5)
+    spans = synth.draw_spans(rng, [len(g.seqs[0])], 24, 1000, 60000)
+    rb = ix.search_batch(spans).candidates()
+    for q, sp in enumerate(spans):
+        rp = ix.search(sp).candidates()
+        mine = rb[rb["query_id"] == q].copy()
+        mine["query_id"] = 0
+        _same(mine, rp, CAND_F, "span %d" % q)
+
+
+def test_deterministic(S):
+    g = synth.config1()
+    ix = S.Index(g.seqs, 12, 16)
+    a = ix.search(g.spans[0])
+    b = ix.search(g.spans[0])
+    assert a.candidates().tobytes() == b.candidates().tobytes()
+    assert a.seeds().tobytes() == b.seeds().tobytes()
+
+
+def test_errors(S):
+    g = synth.small_case(3, length=3000)
+    ix = S.Index(g.seqs, 12, 16)
+    with pytest.raises(S.SdfError) as e:
+        ix.search((0, 0, 3001))
+    assert e.value.code == S.SDF_ERANGE
+    with pytest.raises(S.SdfError) as e:
+        ix.search((1, 0, 10))
+    assert e.value.code == S.SDF_ERANGE
+    with pytest.raises(S.SdfError) as e:
+        ix.search((0, 0, 3000), 0.0, 1000)
+    assert e.value.code == S.SDF_EINVAL
+    with pytest.raises(S.SdfError) as e:
+        ix.search((0, 0, 3000), 0.25, 20)
+    assert e.value.code == S.SDF_EINVAL
+    with pytest.raises(S.SdfError) as e:
+        S.Index(g.seqs, 0, 16)
+    assert e.value.code == S.SDF_EINVAL
+    with pytest.raises(S.SdfError) as e:
+        S.Index(g.seqs, 12, 65)
+    assert e.value.code == S.SDF_EINVAL
+    # the index still works after failed searches
+    assert len(ix.search((0, 0, 3000)).candidates()) >= 0
+
+
+def test_search_config2(S, oracle_lib):
+    """The 50 Mbp chromosome-shaped workload (41% GC, 45% soft-masked
+    repeats, 2,000 duplications, 10 gap runs), whole sequence against the
+    index: exact candidates and seeds."""
+    g = synth.config2()
+    b, off = g.concat()
+    orc = oracle_lib.OracleIndex(b, off, 12, 16)
+    os_, oc = orc.search(g.spans, 0.25, 1000)
+    ix = S.Index(g.seqs, 12, 16)
+    for x, y in zip(ix.minimizers(), orc.minimizers()):
+        assert np.array_equal(x, y)
+    r = ix.search(g.spans[0], 0.25, 1000)
+    _same(r.candidates(), oc, CAND_F, "candidates")
+    _same(r.seeds(), os_, SEED_F, "seeds")

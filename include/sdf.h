@@ -67,7 +67,8 @@ typedef struct {
 /* max_error: the error bound delta of Section 2, 0 < delta < 1 (the paper
  * targets delta <= 0.25).  min_len: minimum duplication length L (Section 2:
  * 1000 bp); the seed window length is n = ceil(L (1 - delta)) (Section 3).
- * Requires n >= k + w - 1.  flags: SDF_TIMING records per-stage GPU times. */
+ * Requires k + w - 1 <= n <= 65536.  flags: SDF_TIMING records per-stage GPU
+ * times. */
 typedef struct {
     double max_error;
     uint32_t min_len;
@@ -180,7 +181,8 @@ sdf_status sdf_result_timing(sdf_result r, float *ms, uint32_t n_ms);
 
 /* Work counters of the search: [0] query windows, [1] hits gathered
  * (both passes count once), [2] hits kept by the prefilter, [3] tiles,
- * [4] target partitions, [5] seeds. */
+ * [4] target partitions, [5] seeds, [6] candidate target starts evaluated,
+ * [7] 64-hit words scanned by the per-window sweeps. */
 sdf_status sdf_result_stats(sdf_result r, uint64_t *v, uint32_t n_v);
 
 void sdf_result_free(sdf_result r);

@@ -2,6 +2,7 @@
 // derivation on the host, launch sequences and result handling.
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <new>
 
@@ -26,7 +27,7 @@ struct sdf_result_s {
     std::vector<uint32_t> h_seeds;
     bool have_seeds = false;
     float ms[5] = {0, 0, 0, 0, 0};
-    uint64_t stats[6] = {0, 0, 0, 0, 0, 0};
+    uint64_t stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -67,8 +68,8 @@ Params derive(const sdf_search_params *p, uint32_t k, uint32_t w) {
     const double dG = d - dM;
     r.tau = ((1.0 - dG) / (1.0 + dG)) / (2.0 * std::exp((double)k * dM) - 1.0);
     const double nn = std::ceil((double)p->min_len * (1.0 - d));
-    if (nn < (double)(k + w - 1) || nn > 1e8)
-        throw Error{SDF_EINVAL, "seed window length n = ceil(min_len (1 - max_error)) must be at least k + w - 1"};
+    if (nn < (double)(k + w - 1) || nn > 65536.0)
+        throw Error{SDF_EINVAL, "seed window length n = ceil(min_len (1 - max_error)) must lie in [k + w - 1, 65536]"};
     r.n = (uint32_t)nn;
     r.max_overlap = (uint32_t)std::floor(d * (double)r.n);
     return r;
@@ -177,6 +178,8 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
     while ((1u << sb) < P.n) sb++;
     uint64_t cap = qbases / 8 + 65536;
     DevBuf<unsigned long long> counters(CNT_N);
+    const bool phase_prof = env_u32("SDF_PHASE_PROF", 0) != 0;
+    DevBuf<unsigned long long> phase(PH_N);
     DevBuf<uint32_t> work(2);
     std::vector<unsigned long long> hc(CNT_N);
     uint32_t herr = 0;
@@ -184,6 +187,7 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
         res->seeds.alloc(cap * 6);
         SDF_HIP(hipMemsetAsync(counters.p, 0, CNT_N * 8, st));
         SDF_HIP(hipMemsetAsync(work.p, 0, 8, st));
+        SDF_HIP(hipMemsetAsync(phase.p, 0, PH_N * 8, st));
         if (total_tiles) {
             SearchArgs a;
             a.ix = ix->view();
@@ -201,6 +205,7 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
             a.seed_cap = cap;
             a.counters = counters.p;
             a.err = work.p + 1;
+            a.phase = phase_prof ? phase.p : nullptr;
             const uint32_t grid = std::min<uint32_t>(total_tiles, (uint32_t)cu_count(ix->device) *
                                                                       env_u32("SDF_WG_PER_CU", 1));
             tm.mark_kernel_begin();
@@ -223,6 +228,19 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
         if (herr & 4) m += " a dense target region has more than 65535 hits;";
         throw Error{SDF_EINTERNAL, m};
     }
+    if (phase_prof) {
+        // per-phase wall-clock ticks summed over workgroups (diagnostic)
+        std::vector<unsigned long long> ph(PH_N);
+        SDF_HIP(hipMemcpy(ph.data(), phase.p, PH_N * 8, hipMemcpyDeviceToHost));
+        int khz = 0;
+        SDF_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ix->device));
+        static const char *names[PH_N] = {"setup", "query", "lists", "plists", "pass1", "pass2",
+                                          "sort", "hot", "seginfo", "eval", "flush"};
+        fprintf(stderr, "[sdf phases, workgroup-ms summed]");
+        for (int t = 0; t < PH_N; t++)
+            fprintf(stderr, " %s=%.2f", names[t], khz ? (double)ph[t] / khz : 0.0);
+        fprintf(stderr, "\n");
+    }
     res->nseeds = hc[CNT_SEEDS];
     res->stats[0] = hc[CNT_WINDOWS];
     res->stats[1] = hc[CNT_HITS];
@@ -230,6 +248,8 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
     res->stats[3] = total_tiles;
     res->stats[4] = hc[CNT_PARTS];
     res->stats[5] = hc[CNT_SEEDS];
+    res->stats[6] = hc[CNT_EVALS];
+    res->stats[7] = hc[CNT_SCAN];
     chain_seeds(ix->view(), res->seeds.p, res->nseeds, P.n, P.max_overlap, res->chain, st);
     tm.mark();
     tm.mark();
@@ -429,7 +449,7 @@ sdf_status sdf_result_timing(sdf_result r, float *ms, uint32_t n_ms) {
 sdf_status sdf_result_stats(sdf_result r, uint64_t *v, uint32_t n_v) {
     return guarded([&] {
         if (!r || (n_v && !v)) throw Error{SDF_EINVAL, "NULL argument"};
-        for (uint32_t t = 0; t < n_v && t < 6; t++) v[t] = r->stats[t];
+        for (uint32_t t = 0; t < n_v && t < 8; t++) v[t] = r->stats[t];
     });
 }
 

@@ -462,6 +462,21 @@ __global__ void k_seg_count_ends(const uint32_t *gaps, const uint32_t *sb, uint6
     if (threadIdx.x == 0) cnt[blockIdx.x] = c;
 }
 
+// Gap-free extent of each minimizer: bases from its position to the end of
+// its segment (0 if it lies in none), so [p, p+n) is gap-free iff ext >= n.
+__global__ void k_min_extent(const uint32_t *mpos, uint64_t nm, const uint32_t *segb,
+                             const uint32_t *sege, uint64_t nseg, uint32_t *mext) {
+    uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nm) return;
+    const uint32_t p = mpos[t];
+    uint64_t lo = 0, hi = nseg;  // first segb > p
+    while (lo < hi) {
+        uint64_t m = (lo + hi) >> 1;
+        if (segb[m] <= p) lo = m + 1; else hi = m;
+    }
+    mext[t] = (lo > 0 && sege[lo - 1] > p) ? sege[lo - 1] - p : 0u;
+}
+
 // ------------------------------------------------------------------ build --
 static unsigned blocks_for(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
 
@@ -615,10 +630,16 @@ void build_index(sdf_index_s *ix, const char *const *seqs, const uint64_t *lens,
         k_seg_emit_ends<<<(unsigned)sbk, SG_THREADS, 0, st>>>(ix->gaps.p, sb.p, nw32, o2.p,
                                                               ix->sege.p);
         SDF_HIP(hipGetLastError());
+        ix->mext.alloc(nm + 1);
+        if (nm) {
+            k_min_extent<<<blocks_for(nm, 256), 256, 0, st>>>(ix->mpos.p, nm, ix->segb.p,
+                                                               ix->sege.p, ns, ix->mext.p);
+            SDF_HIP(hipGetLastError());
+        }
         SDF_HIP(hipStreamSynchronize(st));
     }
     ix->device_bytes = (ix->off.n * 8) + (ix->packed.n + ix->mask.n + ix->gaps.n) * 4 +
-                       (ix->mpos.n + ix->mhash.n + ix->mprev.n) * 4 + ix->mflags.n +
+                       (ix->mpos.n + ix->mhash.n + ix->mprev.n + ix->mext.n) * 4 + ix->mflags.n +
                        (ix->dir.n + ix->epos.n) * 4 + ix->ekeylo.n +
                        (ix->segb.n + ix->sege.n + ix->segseq.n) * 4;
 }
@@ -639,6 +660,7 @@ sdf::IndexView sdf_index_s::view() const {
     v.mpos = mpos.p;
     v.mhash = mhash.p;
     v.mprev = mprev.p;
+    v.mext = mext.p;
     v.mflags = mflags.p;
     v.ne = ne;
     v.dir = dir.p;

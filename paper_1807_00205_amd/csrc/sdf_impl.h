@@ -84,6 +84,7 @@ struct IndexView {  // plain pointers for kernels
     const uint32_t *packed, *mask, *gaps;
     uint64_t nm;
     const uint32_t *mpos, *mhash, *mprev;
+    const uint32_t *mext;  // gap-free bases from each minimizer to its segment end
     const uint8_t *mflags;
     uint64_t ne;
     const uint32_t *dir;  // directory over the top dir_bits of key = hash<<1|strand
@@ -104,7 +105,7 @@ struct sdf_index_s {
     sdf::DevBuf<uint64_t> off;
     sdf::DevBuf<uint32_t> packed, mask, gaps;
     uint64_t nm = 0, ne = 0, nseg = 0;
-    sdf::DevBuf<uint32_t> mpos, mhash, mprev;
+    sdf::DevBuf<uint32_t> mpos, mhash, mprev, mext;
     sdf::DevBuf<uint8_t> mflags;
     sdf::DevBuf<uint32_t> dir, epos;
     sdf::DevBuf<uint8_t> ekeylo;

@@ -11,7 +11,8 @@ struct SpanDesc {
     uint32_t tile0, _pad;   // first tile of the span
 };
 
-enum { CNT_SEEDS = 0, CNT_WINDOWS, CNT_HITS, CNT_KEPT, CNT_PARTS, CNT_TILES, CNT_N };
+enum { CNT_SEEDS = 0, CNT_WINDOWS, CNT_HITS, CNT_KEPT, CNT_PARTS, CNT_TILES, CNT_EVALS,
+       CNT_SCAN, CNT_N };
 
 struct SearchArgs {
     IndexView ix;
@@ -28,7 +29,12 @@ struct SearchArgs {
     uint64_t seed_cap;
     unsigned long long *counters;  // CNT_N
     uint32_t *err;
+    unsigned long long *phase;     // PH_N wall-clock ticks per phase, or null
 };
+
+// Phases of the tile kernel for the optional wall-clock breakdown.
+enum { PH_SETUP = 0, PH_QUERY, PH_LISTS, PH_PLISTS, PH_PASS1, PH_PASS2, PH_SORT, PH_HOT,
+       PH_SEGINFO, PH_EVAL, PH_FLUSH, PH_N };
 
 void launch_span_setup(const IndexView &ix, SpanDesc *spans, uint32_t nspans, uint32_t n,
                        uint32_t core, uint32_t *ntiles, uint32_t *tile0, hipStream_t st);

@@ -31,9 +31,10 @@ constexpr int NWAVES = TB / 64;
 constexpr int QCAP = 1280;      // query minimizers per tile (core + halo)
 constexpr int CMAX = 512;       // window starts per tile core
 constexpr int CB = 2048;        // kept hits per partition
-constexpr int TSLOTS = 32768;   // 16-bit counters in the bin table
+constexpr int TSLOTS = 16384;   // 16-bit counters in the bin table
 constexpr int TWORDS = TSLOTS / 2;
-constexpr int TSLOT_BITS = 15;
+constexpr int TSLOT_BITS = 14;
+constexpr int SBUF = 32;        // seeds buffered per wave before one global atomic
 constexpr uint32_t HMAX = 65535;  // hits per partition (16-bit counters cannot overflow)
 constexpr int STACK = 40;
 constexpr int QW = QCAP / 64;     // bitmask words per wave
@@ -53,7 +54,8 @@ struct RunState {
 };
 
 struct TileLds {
-    uint32_t qpos[QCAP];
+    uint32_t qpos[QCAP + 1];
+    uint32_t qhash[QCAP];
     int16_t qprev[QCAP];
     uint16_t qroot[QCAP];
     uint8_t qfl[QCAP];
@@ -63,25 +65,26 @@ struct TileLds {
     uint16_t win_qend[CMAX];
     uint16_t win_s[CMAX];
     RunState run[CMAX][2];
-    union {
+    union {  // bin table in the gather passes; scratch and seed buffers after
         uint32_t table[TWORDS];
         uint64_t scratch[TWORDS / 2];
     } u;
     uint64_t coll[CB];
+    uint32_t prevq[CB];
+    uint32_t eseq[CB];
     uint16_t rng_end[CB];
     uint8_t eflag[CB];
-    uint32_t eseq[CB];
     unsigned long long wbits[NWAVES][QW];
     uint32_t stackA[STACK], stackB[STACK];
     uint64_t wtmp[NWAVES + 1];
+    uint64_t ph[PH_N];
     // scalars
-    uint32_t tile, span, c0, c1, Q, C, qend_g, nwin, Tmin, ncoll, nrel;
+    uint32_t tile, c0, c1, Q, C, nwin, Tmin, ncoll, dup;
     uint32_t obeg[2], oend[2];
     uint32_t sp;
     uint32_t err;
     uint64_t gb, ge;
     uint32_t qid, qseq;
-    uint32_t H;
 };
 
 // ----------------------------------------------------------- block helpers --
@@ -128,15 +131,15 @@ __device__ uint32_t block_scan_u32(uint32_t *arr, int n, uint64_t *wtmp) {
 }
 
 // Inclusive max-scan over arr[0, n) (n <= 2 * TB).
-__device__ void block_maxscan_u64(uint64_t *arr, int n, uint64_t *wtmp) {
+__device__ void block_maxscan_u32(uint32_t *arr, int n, uint64_t *wtmp) {
     const int per = (n + TB - 1) / TB;
     const int b = threadIdx.x * per;
-    uint64_t m = 0;
+    uint32_t m = 0;
     for (int t = 0; t < per; t++)
         if (b + t < n) m = arr[b + t] > m ? arr[b + t] : m;
-    uint64_t x = m;
+    uint32_t x = m;
     for (int d = 1; d < 64; d <<= 1) {
-        uint64_t y = __shfl_up(x, d, 64);
+        uint32_t y = __shfl_up(x, d, 64);
         if (lane_id() >= d) x = y > x ? y : x;
     }
     if (lane_id() == 63) wtmp[wave_id()] = x;
@@ -150,9 +153,9 @@ __device__ void block_maxscan_u64(uint64_t *arr, int n, uint64_t *wtmp) {
         }
     }
     __syncthreads();
-    uint64_t pre = __shfl_up(x, 1, 64);
+    uint32_t pre = __shfl_up(x, 1, 64);
     if (lane_id() == 0) pre = 0;
-    pre = wtmp[wave_id()] > pre ? wtmp[wave_id()] : pre;
+    pre = (uint32_t)wtmp[wave_id()] > pre ? (uint32_t)wtmp[wave_id()] : pre;
     for (int t = 0; t < per; t++) {
         if (b + t < n) {
             pre = arr[b + t] > pre ? arr[b + t] : pre;
@@ -259,11 +262,42 @@ __device__ __forceinline__ uint32_t list_of(const uint32_t *hoff, uint32_t nl, u
     return lo;
 }
 
-__device__ void emit_seed(const SearchArgs &a, uint32_t qid, uint32_t i, uint32_t j, uint32_t o,
-                          uint32_t c, uint32_t s) {
-    unsigned long long idx = atomicAdd(&a.counters[CNT_SEEDS], 1ull);
-    if (idx < a.seed_cap) {
-        uint32_t *d = a.seeds + idx * 6;
+// ------------------------------------------------------------ tile kernel --
+// Optional phase breakdown: thread 0 reads the wall clock after the barrier
+// that ends each phase and accumulates the difference.
+#define PHASE(id)                                                       \
+    do {                                                                \
+        if (prof) {                                                     \
+            const uint64_t now_ = wall_clock64();                       \
+            L.ph[id] += now_ - ph_t;                                    \
+            ph_t = now_;                                                \
+        }                                                               \
+    } while (0)
+
+// Per-wave seed buffer (LDS) flushed with one global atomic per batch.
+struct SeedBuf {
+    uint32_t *buf;  // SBUF * 6 words of this wave
+    uint32_t n;     // wave-uniform
+};
+
+__device__ __forceinline__ void seeds_flush(const SearchArgs &a, SeedBuf &sb, int lane) {
+    if (sb.n == 0) return;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(&a.counters[CNT_SEEDS], (unsigned long long)sb.n);
+    base = __shfl(base, 0, 64);
+    for (uint32_t t = lane; t < sb.n * 6; t += 64) {
+        const unsigned long long idx = base + t / 6;
+        if (idx < a.seed_cap) a.seeds[base * 6 + t] = sb.buf[t];
+    }
+    __builtin_amdgcn_wave_barrier();
+    sb.n = 0;
+}
+
+__device__ __forceinline__ void seeds_push(const SearchArgs &a, SeedBuf &sb, int lane,
+                                           uint32_t qid, uint32_t i, uint32_t j, uint32_t o,
+                                           uint32_t c, uint32_t s) {
+    if (lane == 0) {
+        uint32_t *d = sb.buf + sb.n * 6;
         d[0] = qid;
         d[1] = i;
         d[2] = j;
@@ -271,31 +305,73 @@ __device__ void emit_seed(const SearchArgs &a, uint32_t qid, uint32_t i, uint32_
         d[4] = c;
         d[5] = s;
     }
+    __builtin_amdgcn_wave_barrier();
+    sb.n++;
+    if (sb.n == SBUF) seeds_flush(a, sb, lane);
 }
 
-// ------------------------------------------------------------ tile kernel --
+// Every lane with `mine` set pushes one seed; order within the buffer does
+// not matter (seeds are sorted afterwards).
+__device__ __forceinline__ void seeds_push_lanes(const SearchArgs &a, SeedBuf &sb, int lane,
+                                                 bool mine, uint32_t qid, uint32_t i, uint32_t j,
+                                                 uint32_t o, uint32_t c, uint32_t s) {
+    const uint64_t m = __ballot(mine);
+    const uint32_t cnt = (uint32_t)__popcll(m);
+    if (cnt == 0) return;
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const uint32_t rank = (uint32_t)__popcll(m & lt);
+    if (sb.n + cnt > SBUF) seeds_flush(a, sb, lane);
+    if (cnt > SBUF) {  // too many for the buffer: write directly
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(&a.counters[CNT_SEEDS], (unsigned long long)cnt);
+        base = __shfl(base, 0, 64);
+        if (mine && base + rank < a.seed_cap) {
+            uint32_t *d = a.seeds + (base + rank) * 6;
+            d[0] = qid; d[1] = i; d[2] = j; d[3] = o; d[4] = c; d[5] = s;
+        }
+        return;
+    }
+    if (mine) {
+        uint32_t *d = sb.buf + (sb.n + rank) * 6;
+        d[0] = qid; d[1] = i; d[2] = j; d[3] = o; d[4] = c; d[5] = s;
+    }
+    __builtin_amdgcn_wave_barrier();
+    sb.n += cnt;
+}
+
 __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
     __shared__ TileLds L;
     const IndexView &ix = a.ix;
     const uint32_t n = a.n, k = ix.k;
     const int lane = lane_id(), wave = wave_id();
+    const bool prof = a.phase != nullptr && threadIdx.x == 0;
+    if (threadIdx.x < PH_N) L.ph[threadIdx.x] = 0;
+    uint64_t ph_t = prof ? wall_clock64() : 0;
     // per-wave bitmasks start empty; each use clears the words it counted
     for (uint32_t t = threadIdx.x; t < NWAVES * QW; t += TB) (&L.wbits[0][0])[t] = 0;
+    uint32_t span_cache = 0;  // thread 0: span of the previous tile
     __syncthreads();
 
     for (;;) {
         if (threadIdx.x == 0) {
-            uint32_t t = atomicAdd(a.work, 1u);
+            const uint32_t t = atomicAdd(a.work, 1u);
             L.tile = t;
             if (t < a.total_tiles) {
-                // span of this tile: largest s with tile0[s] <= t
-                uint32_t lo = 0, hi = a.nspans;
-                while (hi - lo > 1) {
-                    uint32_t m = (lo + hi) >> 1;
-                    if (a.spans[m].tile0 <= t) lo = m; else hi = m;
+                // span of this tile: largest s with tile0[s] <= t (consecutive
+                // tiles mostly stay in one span)
+                uint32_t s = span_cache;
+                const bool hit = a.spans[s].tile0 <= t &&
+                                 (s + 1 == a.nspans || a.spans[s + 1].tile0 > t);
+                if (!hit) {
+                    uint32_t lo = 0, hi = a.nspans;
+                    while (hi - lo > 1) {
+                        uint32_t m = (lo + hi) >> 1;
+                        if (a.spans[m].tile0 <= t) lo = m; else hi = m;
+                    }
+                    s = lo;
                 }
-                const SpanDesc &sd = a.spans[lo];
-                L.span = lo;
+                span_cache = s;
+                const SpanDesc sd = a.spans[s];
                 L.c0 = sd.m_lo + (t - sd.tile0) * a.core;
                 L.c1 = min(L.c0 + a.core, sd.m_hi);
                 L.gb = sd.gb;
@@ -313,32 +389,38 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
         uint32_t c_begin = L.c0;
         __syncthreads();  // everyone has read the core bounds before they change
         while (c_begin < piece_end) {
+            // positions of the next QCAP + 1 minimizers (coalesced)
+            for (uint32_t q = threadIdx.x; q <= QCAP; q += TB) {
+                const uint64_t m = (uint64_t)c_begin + q;
+                L.qpos[q] = m < ix.nm ? ix.mpos[m] : 0xFFFFFFFFu;
+            }
+            __syncthreads();
             if (threadIdx.x == 0) {
                 uint32_t c1 = piece_end;
                 uint32_t qe = 0;
                 for (;;) {
                     // query range: up to the last minimizer inside the last window
-                    const uint64_t lim = (uint64_t)ix.mpos[c1 - 1] + n - k;
-                    uint32_t lo = c1, hi = (uint32_t)min<uint64_t>(ix.nm, (uint64_t)c_begin + QCAP + 1);
+                    const uint64_t lim = (uint64_t)L.qpos[c1 - 1 - c_begin] + n - k;
+                    uint32_t lo = c1 - c_begin, hi = QCAP + 1;
                     while (lo < hi) {
                         uint32_t m = (lo + hi) >> 1;
-                        if ((uint64_t)ix.mpos[m] <= lim) lo = m + 1; else hi = m;
+                        if ((uint64_t)L.qpos[m] <= lim) lo = m + 1; else hi = m;
                     }
                     qe = lo;
-                    if (qe - c_begin <= QCAP || c1 - c_begin == 1) break;
+                    if (qe <= QCAP || c1 - c_begin == 1) break;
                     c1 = c_begin + (c1 - c_begin) / 2;
                 }
                 L.c0 = c_begin;
                 L.c1 = c1;
-                L.qend_g = qe;
-                L.err = 0;
-                if (qe - c_begin > QCAP) L.err |= ERR_CORE;
-                L.Q = min<uint32_t>(qe - c_begin, QCAP);
+                L.err = (qe > QCAP) ? ERR_CORE : 0u;
+                L.Q = min<uint32_t>(qe, QCAP);
                 L.C = c1 - c_begin;
                 L.nwin = 0;
                 L.Tmin = 0xFFFFu;
+                L.dup = 0;
             }
             __syncthreads();
+            PHASE(PH_SETUP);
             const uint32_t c0 = L.c0, Q = L.Q, C = L.C;
             if (L.err) {
                 if (threadIdx.x == 0) atomicOr(a.err, L.err);
@@ -350,29 +432,36 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
             // ---- query minimizers of the tile ----
             for (uint32_t q = threadIdx.x; q < Q; q += TB) {
                 const uint32_t m = c0 + q;
-                L.qpos[q] = ix.mpos[m];
+                L.qhash[q] = ix.mhash[m];
                 L.qfl[q] = ix.mflags[m];
                 const uint32_t pg = ix.mprev[m];
                 L.qprev[q] = (pg != NONE32 && pg >= c0) ? (int16_t)(pg - c0) : (int16_t)-1;
+            }
+            // ---- windows of the core: eligible, inside the span, gap-free ----
+            for (uint32_t qc = threadIdx.x; qc < C; qc += TB) {
+                const uint32_t i = L.qpos[qc];
+                const bool w = (ix.mflags[c0 + qc] & 2) && (uint64_t)i + n <= L.ge &&
+                               ix.mext[c0 + qc] >= n;
+                L.win_T[qc] = w ? 1 : 0;  // finished below
             }
             __syncthreads();
             for (uint32_t q = threadIdx.x; q < Q; q += TB) {
                 int r = (int)q;
                 while (L.qprev[r] >= 0) r = L.qprev[r];
                 L.qroot[q] = (uint16_t)r;
+                if (r != (int)q && (L.qfl[q] & 2)) L.dup = 1;
             }
-            // ---- windows of the core ----
             for (uint32_t qc = threadIdx.x; qc < C; qc += TB) {
                 uint16_t T = 0, qend = 0, s = 0;
-                const uint32_t i = L.qpos[qc];
-                if ((L.qfl[qc] & 2) && (uint64_t)i + n <= L.ge && window_ok(ix, i, n, nullptr)) {
-                    const uint64_t lim = (uint64_t)i + n - k;
+                if (L.win_T[qc]) {
+                    const uint64_t lim = (uint64_t)L.qpos[qc] + n - k;
                     uint32_t lo = qc, hi = Q;
                     while (lo < hi) {
                         uint32_t m = (lo + hi) >> 1;
                         if ((uint64_t)L.qpos[m] <= lim) lo = m + 1; else hi = m;
                     }
                     qend = (uint16_t)lo;
+                    // s_i: distinct hashes among all minimizers of the window
                     uint32_t cnt = 0;
                     for (uint32_t q = qc; q < lo; q++) cnt += (L.qprev[q] < (int)qc) ? 1u : 0u;
                     s = (uint16_t)cnt;
@@ -387,6 +476,7 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                 L.run[qc][1] = RunState{NONE32, 0, 0, 0, 0};
             }
             __syncthreads();
+            PHASE(PH_QUERY);
             if (L.nwin == 0) {
                 c_begin = L.c1;
                 __syncthreads();
@@ -394,18 +484,20 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
             }
             if (threadIdx.x == 0) atomicAdd(&a.counters[CNT_WINDOWS], (unsigned long long)L.nwin);
             const uint32_t Tmin = L.Tmin;
+            const bool dup = L.dup != 0;
 
             // ---- full-range lists and partition count ----
             const uint32_t nl = 2 * Q;
             for (uint32_t l = threadIdx.x; l < nl; l += TB) {
                 const uint32_t q = l >> 1, b = l & 1;
                 uint32_t lo = 0, hi = 0;
-                if (L.qfl[q] & 2) lookup(ix, ix.mhash[c0 + q], b, lo, hi);
+                if (L.qfl[q] & 2) lookup(ix, L.qhash[q], b, lo, hi);
                 L.lst_lo[l] = lo;
                 L.hoff[l] = hi - lo;
             }
             __syncthreads();
             const uint32_t Hfull = block_scan_u32(L.hoff, (int)nl, L.wtmp);
+            PHASE(PH_LISTS);
             uint32_t P = (Hfull + a.hpart - 1) / a.hpart;
             if (P < 1) P = 1;
             bool lists_full = true;  // lst_lo/hoff hold the full lists
@@ -433,7 +525,7 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                         const uint32_t q = l >> 1, b = l & 1;
                         uint32_t lo = 0, hi = 0;
                         if (L.qfl[q] & 2) {
-                            lookup(ix, ix.mhash[c0 + q], b, lo, hi);
+                            lookup(ix, L.qhash[q], b, lo, hi);
                             if (!full) {
                                 uint32_t a0 = lower_pos(ix.epos, lo, hi, lo_pos);
                                 uint32_t b0 = lower_pos(ix.epos, a0, hi, hi_pos);
@@ -448,6 +540,7 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                     block_scan_u32(L.hoff, (int)nl, L.wtmp);
                     lists_full = full;
                 }
+                PHASE(PH_PLISTS);
                 const uint32_t H = L.hoff[nl];
                 if (H == 0) continue;
                 if (H > HMAX) {
@@ -483,6 +576,7 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                     atomicAdd(&L.u.table[slot >> 1], 1u << ((slot & 1) * 16));
                 }
                 __syncthreads();
+                PHASE(PH_PASS1);
                 // ---- pass 2: keep hits near bins that may be hot ----
                 for (uint32_t e = threadIdx.x; e < H; e += TB) {
                     const uint32_t l = list_of(L.hoff, nl, e);
@@ -501,6 +595,7 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                     }
                 }
                 __syncthreads();
+                PHASE(PH_PASS2);
                 const uint32_t ncoll = L.ncoll;
                 if (ncoll == 0) continue;
                 if (ncoll > CB) {
@@ -525,74 +620,100 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                     if (t >= (int)ncoll) L.coll[t] = ~0ull;
                 __syncthreads();
                 block_bitonic_u64(L.coll, n2);
+                PHASE(PH_SORT);
                 // ---- exact hot starts: >= Tmin hits in [x, x + n - k] ----
-                uint64_t *hot = L.u.scratch;
+                uint32_t *hot = reinterpret_cast<uint32_t *>(L.u.scratch);  // entry index + 1
+                uint8_t *relf = reinterpret_cast<uint8_t *>(hot + CB);
+                uint32_t *pref = hot + CB + CB / 4;
                 for (uint32_t e = threadIdx.x; e < ncoll; e += TB) {
                     const uint64_t key = L.coll[e];
-                    uint64_t hv = 0;
+                    uint32_t hv = 0;
                     const bool first = (e == 0) || ck_op(L.coll[e - 1]) != ck_op(key);
                     if (first && e + Tmin - 1 < ncoll) {
                         const uint64_t k2 = L.coll[e + Tmin - 1];
                         if (ck_o(k2) == ck_o(key) && (uint64_t)ck_p(k2) <= (uint64_t)ck_p(key) + n - k)
-                            hv = ((uint64_t)ck_o(key) << 33) | ((uint64_t)ck_p(key) + 1);
+                            hv = e + 1;
                     }
                     hot[e] = hv;
                 }
                 __syncthreads();
-                block_maxscan_u64(hot, (int)ncoll, L.wtmp);
+                block_maxscan_u32(hot, (int)ncoll, L.wtmp);
                 // ---- relevant: within [x, x + 2n - k) of the last hot x ----
-                uint32_t *relf = reinterpret_cast<uint32_t *>(L.u.scratch + CB);
                 for (uint32_t e = threadIdx.x; e < ncoll; e += TB) {
                     const uint64_t key = L.coll[e];
-                    const uint64_t lh = hot[e];
+                    const uint32_t lh = hot[e];
                     uint32_t f = 0;
-                    if (lh && (uint32_t)(lh >> 33) == ck_o(key)) {
-                        const uint64_t x = (lh & 0x1FFFFFFFFull) - 1;
+                    if (lh && ck_o(L.coll[lh - 1]) == ck_o(key)) {
+                        const uint64_t x = ck_p(L.coll[lh - 1]);
                         const uint64_t d = (uint64_t)ck_p(key) - x;
                         if (d < 2ull * n - k) f |= 4;   // relevant
                         if (d < n) f |= EF_CAND;
                     }
-                    relf[e] = f;
+                    relf[e] = (uint8_t)f;
+                    pref[e] = (f & 4) ? 1u : 0u;
                 }
                 __syncthreads();
-                // stable compaction of relevant entries into scratch, then back
-                uint32_t *pref = relf + CB;
-                for (uint32_t e = threadIdx.x; e < ncoll; e += TB) pref[e] = (relf[e] & 4) ? 1u : 0u;
-                __syncthreads();
                 const uint32_t nrel = block_scan_u32(pref, (int)ncoll, L.wtmp);
-                uint64_t *tmpk = L.u.scratch + 2 * CB + 1;  // after hot/relf/pref regions
-                uint8_t *tmpf = reinterpret_cast<uint8_t *>(tmpk + CB);
-                for (uint32_t e = threadIdx.x; e < ncoll; e += TB) {
-                    if (relf[e] & 4) {
-                        tmpk[pref[e]] = L.coll[e];
-                        tmpf[pref[e]] = (uint8_t)(relf[e] & EF_CAND);
+                // stable compaction in place: read everything first, then write
+                uint64_t keep_k[CB / TB];
+                uint32_t keep_at[CB / TB];
+                uint8_t keep_f[CB / TB];
+#pragma unroll
+                for (int r = 0; r < CB / TB; r++) {
+                    const uint32_t e = threadIdx.x + r * TB;
+                    keep_at[r] = NONE32;
+                    if (e < ncoll && (relf[e] & 4)) {
+                        keep_k[r] = L.coll[e];
+                        keep_f[r] = relf[e] & EF_CAND;
+                        keep_at[r] = pref[e];
                     }
                 }
                 __syncthreads();
+                PHASE(PH_HOT);
                 if (nrel == 0) continue;
-                for (uint32_t e = threadIdx.x; e < nrel; e += TB) {
-                    L.coll[e] = tmpk[e];
-                    L.eflag[e] = tmpf[e];
+#pragma unroll
+                for (int r = 0; r < CB / TB; r++) {
+                    if (keep_at[r] != NONE32) {
+                        L.coll[keep_at[r]] = keep_k[r];
+                        L.eflag[keep_at[r]] = keep_f[r];
+                    }
                 }
+                __syncthreads();
                 if (threadIdx.x == 0) {
+                    // orientation 1 starts at the first entry with o = 1
+                    uint32_t lo = 0, hi = nrel;
+                    while (lo < hi) {
+                        uint32_t m = (lo + hi) >> 1;
+                        if (ck_o(L.coll[m]) == 0) lo = m + 1; else hi = m;
+                    }
                     L.obeg[0] = 0;
+                    L.oend[0] = lo;
+                    L.obeg[1] = lo;
                     L.oend[1] = nrel;
                 }
                 __syncthreads();
                 for (uint32_t e = threadIdx.x; e < nrel; e += TB) {
                     const uint64_t key = L.coll[e];
-                    const uint32_t o = ck_o(key), p = ck_p(key);
-                    if (e + 1 == nrel || ck_o(L.coll[e + 1]) != o) L.oend[o] = e + 1;
-                    if (e == 0 || ck_o(L.coll[e - 1]) != o) L.obeg[o] = e;
+                    const uint32_t o = ck_o(key), p = ck_p(key), q = ck_q(key);
                     // end of the counting range [p, p + n - k]
-                    uint32_t lo = e, hi = nrel;
+                    uint32_t lo = e, hi = L.oend[o];
                     const uint64_t lim = (uint64_t)p + n - k;
                     while (lo < hi) {
                         uint32_t m = (lo + hi) >> 1;
-                        const uint64_t km = L.coll[m];
-                        if (ck_o(km) == o && (uint64_t)ck_p(km) <= lim) lo = m + 1; else hi = m;
+                        if ((uint64_t)ck_p(L.coll[m]) <= lim) lo = m + 1; else hi = m;
                     }
                     L.rng_end[e] = (uint16_t)lo;
+                    // nearest earlier hit of the same query minimizer within n - k
+                    uint32_t pv = 0;
+                    for (int f = (int)e - 1; f >= (int)L.obeg[o]; f--) {
+                        const uint64_t kf = L.coll[f];
+                        if ((uint64_t)ck_p(kf) + n - k < p) break;
+                        if (ck_q(kf) == q) {
+                            pv = ck_p(kf) + 1;
+                            break;
+                        }
+                    }
+                    L.prevq[e] = pv;
                     if ((L.eflag[e] & EF_CAND) && p >= A && p < B) {
                         uint32_t sq = 0;
                         if (window_ok(ix, p, n, &sq)) L.eflag[e] |= EF_VALID;
@@ -601,16 +722,28 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                         L.eflag[e] &= ~EF_CAND;  // not owned by this partition
                     }
                 }
-                // orientations absent from the kept set
-                if (threadIdx.x == 0) {
-                    if (ck_o(L.coll[0]) == 1) { L.obeg[0] = 0; L.oend[0] = 0; }
-                    if (ck_o(L.coll[nrel - 1]) == 0) { L.obeg[1] = nrel; L.oend[1] = nrel; }
-                }
                 __syncthreads();
+                PHASE(PH_SEGINFO);
 
                 // ---- exact counts, runs and seeds: one wave per window ----
+                // Per (window, orientation): bit e of `inw` says kept hit e
+                // comes from a query minimizer of the window, bit e of `dupw`
+                // that it also has an earlier hit of the same minimizer within
+                // n - k.  A candidate j's shared count is then the popcount of
+                // `inw` over its range [j, j+n-k], minus the hits whose earlier
+                // hit of the same minimizer also lies in the range.
+                // Candidates are gathered 64 at a time, counted one per lane,
+                // and the run logic walks each batch in target order.
+                SeedBuf sbuf{reinterpret_cast<uint32_t *>(L.u.scratch) + wave * SBUF * 6, 0};
+                uint32_t *cbuf = reinterpret_cast<uint32_t *>(L.u.scratch) + NWAVES * SBUF * 6 +
+                                 wave * 128;
+                uint64_t *inw = L.u.scratch + (NWAVES * SBUF * 6 + NWAVES * 128) / 2 +
+                                wave * (2 * (CB / 64));
+                uint64_t *dupw = inw + CB / 64;
                 unsigned long long *bits = L.wbits[wave];
                 const uint32_t nwords = (Q + 63) >> 6;
+                const uint64_t ltmask = lane ? (~0ull >> (64 - lane)) : 0ull;
+                uint32_t n_evals = 0, n_scan = 0;
                 for (uint32_t qc = wave; qc < C; qc += NWAVES) {
                     const uint32_t Ti = L.win_T[qc];
                     if (Ti == 0) continue;
@@ -619,74 +752,166 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                     for (uint32_t o = 0; o < 2; o++) {
                         const uint32_t ob = L.obeg[o], oe = L.oend[o];
                         if (ob >= oe) continue;
+                        const uint32_t wb = ob >> 6, we = (oe + 63) >> 6;
+                        n_scan += we - wb;
+                        // membership bitmasks over the orientation's kept hits
+                        for (uint32_t w = wb; w < we; w++) {
+                            const uint32_t e = w * 64 + lane;
+                            bool in = false, dp = false;
+                            if (e >= ob && e < oe) {
+                                const uint32_t q = ck_q(L.coll[e]);
+                                in = q >= qc && q < qe;
+                                dp = in && L.prevq[e] != 0;
+                            }
+                            const uint64_t mi = __ballot(in), md = __ballot(dp);
+                            if (lane == 0) {
+                                inw[w] = mi;
+                                dupw[w] = md;
+                            }
+                        }
+                        __builtin_amdgcn_wave_barrier();
                         RunState rs = L.run[qc][o];
-                        for (uint32_t base = ob; base < oe; base += 64) {
-                            const uint32_t e = base + lane;
+                        uint32_t nc = 0;
+                        for (uint32_t w = wb; w < we; w++) {
+                            const uint32_t e = w * 64 + lane;
+                            const uint64_t mi = inw[w];
                             bool cand = false;
-                            if (e < oe && (L.eflag[e] & (EF_CAND | EF_VALID)) == (EF_CAND | EF_VALID)) {
-                                const uint64_t key = L.coll[e];
-                                const uint32_t q = ck_q(key);
-                                if (q >= qc && q < qe) {
-                                    cand = true;
-                                    if (e > ob) {
-                                        const uint64_t kp = L.coll[e - 1];
-                                        if (ck_p(kp) == ck_p(key) && ck_q(kp) >= qc) cand = false;
-                                    }
+                            if (((mi >> lane) & 1) && (L.eflag[e] & (EF_CAND | EF_VALID)) == (EF_CAND | EF_VALID)) {
+                                cand = true;
+                                if (e > ob) {
+                                    const uint64_t kp = L.coll[e - 1], key = L.coll[e];
+                                    if (ck_p(kp) == ck_p(key) && ck_q(kp) >= qc) cand = false;
                                 }
                             }
-                            uint64_t cm = __ballot(cand);
-                            while (cm) {
-                                const int src = __ffsll((long long)cm) - 1;
-                                cm &= cm - 1;
-                                const uint32_t ec = base + src;
-                                const uint32_t j = ck_p(L.coll[ec]);
-                                const uint32_t re = L.rng_end[ec];
-                                // distinct roots of window hashes with a hit in [j, j+n-k]
-                                for (uint32_t f = ec + lane; f < re; f += 64) {
-                                    const uint32_t q = ck_q(L.coll[f]);
-                                    if (q >= qc && q < qe) {
-                                        const uint32_t r = L.qroot[q];
-                                        atomicOr(&bits[r >> 6], 1ull << (r & 63));
+                            const uint64_t cm = __ballot(cand);
+                            if (cand) cbuf[nc + (uint32_t)__popcll(cm & ltmask)] = e;
+                            nc += (uint32_t)__popcll(cm);
+                            __builtin_amdgcn_wave_barrier();
+                            const bool last = w + 1 >= we;
+                            while (nc >= 64 || (last && nc > 0)) {
+                                const uint32_t nb = nc < 64 ? nc : 64;
+                                n_evals += nb;
+                                uint32_t ec = 0, j = 0, cnt = 0, tseq = 0;
+                                if ((uint32_t)lane < nb) {
+                                    ec = cbuf[lane];
+                                    j = ck_p(L.coll[ec]);
+                                    tseq = L.eseq[ec];
+                                }
+                                if (!dup) {
+                                    if ((uint32_t)lane < nb) {
+                                        const uint32_t re = L.rng_end[ec];  // > ec
+                                        const uint32_t w0 = ec >> 6, w1 = (re - 1) >> 6;
+                                        for (uint32_t x = w0; x <= w1; x++) {
+                                            uint64_t m = inw[x], d = dupw[x];
+                                            uint64_t keep = ~0ull;
+                                            if (x == w0) keep &= ~0ull << (ec & 63);
+                                            if (x == w1 && (re & 63)) keep &= (1ull << (re & 63)) - 1;
+                                            cnt += (uint32_t)__popcll(m & keep);
+                                            d &= keep;
+                                            while (d) {
+                                                const uint32_t f = x * 64 + (__ffsll((long long)d) - 1);
+                                                d &= d - 1;
+                                                if (L.prevq[f] - 1 >= j) cnt--;  // earlier hit in range
+                                            }
+                                        }
+                                    }
+                                } else {
+                                    // repeated hashes in the tile: distinct roots via a bitmask
+                                    for (uint32_t t = 0; t < nb; t++) {
+                                        const uint32_t et = (uint32_t)__builtin_amdgcn_readlane((int)ec, (int)t);
+                                        const uint32_t rt = L.rng_end[et];
+                                        for (uint32_t f = et + lane; f < rt; f += 64) {
+                                            const uint32_t q = ck_q(L.coll[f]);
+                                            if (q >= qc && q < qe) {
+                                                const uint32_t r = L.qroot[q];
+                                                atomicOr(&bits[r >> 6], 1ull << (r & 63));
+                                            }
+                                        }
+                                        __builtin_amdgcn_wave_barrier();
+                                        uint32_t c = 0;
+                                        if ((uint32_t)lane < nwords) {
+                                            c = (uint32_t)__popcll(bits[lane]);
+                                            bits[lane] = 0;
+                                        }
+                                        for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
+                                        __builtin_amdgcn_wave_barrier();
+                                        if ((uint32_t)lane == t) cnt = c;
                                     }
                                 }
-                                __builtin_amdgcn_wave_barrier();
-                                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                                uint32_t cnt = 0;
-                                if ((uint32_t)lane < nwords) {
-                                    cnt = (uint32_t)__popcll(bits[lane]);
-                                    bits[lane] = 0;
-                                }
-                                for (int d = 32; d > 0; d >>= 1) cnt += __shfl_xor(cnt, d, 64);
-                                __builtin_amdgcn_wave_barrier();
-                                const uint32_t tseq = L.eseq[ec];
+                                // run logic over the batch (lane t = t-th candidate in
+                                // target order): a candidate continues the run of the
+                                // previous one when both pass, lie in one sequence and
+                                // less than n apart; each run's seed is its largest
+                                // count, smallest j on ties (segmented max-scan).
+                                const bool act = (uint32_t)lane < nb;
                                 bool excl = false;
-                                if (tseq == L.qseq) {
+                                if (act && tseq == L.qseq) {
                                     const uint32_t dd = j > i ? j - i : i - j;
                                     excl = dd < n && (n - dd) > a.max_overlap;
                                 }
-                                const bool pass = cnt >= Ti && !excl;
-                                if (rs.active && !(pass && tseq == rs.prev_seq && j - rs.prev_j < n)) {
-                                    if (lane == 0) emit_seed(a, L.qid, i, rs.best_j, o, rs.best_c, L.win_s[qc]);
-                                    rs.active = 0;
+                                const bool pass = act && cnt >= Ti && !excl;
+                                uint32_t pj = __shfl_up(j, 1, 64), ps = __shfl_up(tseq, 1, 64);
+                                bool ppass = __shfl_up((int)pass, 1, 64) != 0;
+                                if (lane == 0) {
+                                    pj = rs.prev_j;
+                                    ps = rs.prev_seq;
+                                    ppass = rs.active != 0;
                                 }
-                                if (pass) {
-                                    if (!rs.active) {
-                                        rs.active = 1;
-                                        rs.best_j = j;
-                                        rs.best_c = (uint16_t)cnt;
-                                    } else if (cnt > rs.best_c) {
-                                        rs.best_j = j;
-                                        rs.best_c = (uint16_t)cnt;
+                                const bool link = pass && ppass && tseq == ps && j - pj < n;
+                                uint64_t key = pass ? (((uint64_t)cnt << 32) | (uint32_t)~j) : 0ull;
+                                if (lane == 0 && link)
+                                    key = max(key, ((uint64_t)rs.best_c << 32) | (uint32_t)~rs.best_j);
+                                bool flag = !link;  // segment head (or not passing)
+                                for (int d = 1; d < 64; d <<= 1) {
+                                    const uint64_t y = __shfl_up(key, d, 64);
+                                    const bool fy = __shfl_up((int)flag, d, 64) != 0;
+                                    if (lane >= d && !flag) {
+                                        key = max(key, y);
+                                        flag = fy;
                                     }
                                 }
-                                rs.prev_j = j;
-                                rs.prev_seq = tseq;
+                                // the run open before this batch ends unless lane 0 links
+                                const bool link0 = __shfl((int)link, 0, 64) != 0;
+                                seeds_push_lanes(a, sbuf, lane, lane == 0 && rs.active && !link0,
+                                                 L.qid, i, rs.best_j, o, rs.best_c, L.win_s[qc]);
+                                // runs that end inside the batch
+                                const bool link_next = __shfl_down((int)link, 1, 64) != 0;
+                                const bool ends = pass && (uint32_t)lane + 1 < nb && !link_next;
+                                seeds_push_lanes(a, sbuf, lane, ends, L.qid, i, ~(uint32_t)key, o,
+                                                 (uint32_t)(key >> 32), L.win_s[qc]);
+                                // carry the state after the last candidate
+                                const uint32_t tl = nb - 1;
+                                const bool pl = __builtin_amdgcn_readlane((int)pass, (int)tl) != 0;
+                                const uint64_t kl = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(key >> 32), (int)tl) << 32) |
+                                                    (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)key, (int)tl);
+                                rs.prev_j = (uint32_t)__builtin_amdgcn_readlane((int)j, (int)tl);
+                                rs.prev_seq = (uint32_t)__builtin_amdgcn_readlane((int)tseq, (int)tl);
+                                rs.active = pl ? 1 : 0;
+                                if (pl) {
+                                    rs.best_c = (uint16_t)(kl >> 32);
+                                    rs.best_j = ~(uint32_t)kl;
+                                }
+                                // keep the candidates beyond this batch
+                                __builtin_amdgcn_wave_barrier();
+                                uint32_t rest = 0;
+                                if ((uint32_t)lane + nb < nc) rest = cbuf[lane + nb];
+                                __builtin_amdgcn_wave_barrier();
+                                if ((uint32_t)lane + nb < nc) cbuf[lane] = rest;
+                                __builtin_amdgcn_wave_barrier();
+                                nc -= nb;
                             }
                         }
                         if (lane == 0) L.run[qc][o] = rs;
+                        __builtin_amdgcn_wave_barrier();
                     }
                 }
+                seeds_flush(a, sbuf, lane);
+                if (lane == 0) {
+                    atomicAdd(&a.counters[CNT_EVALS], (unsigned long long)n_evals);
+                    atomicAdd(&a.counters[CNT_SCAN], (unsigned long long)n_scan);
+                }
                 __syncthreads();
+                PHASE(PH_EVAL);
             }  // stack of one partition
             __syncthreads();
             if (L.err) break;
@@ -695,19 +920,26 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                 if (threadIdx.x == 0) atomicOr(a.err, L.err);
             } else {
                 // close the runs still open after the last partition
-                for (uint32_t qc = threadIdx.x; qc < C; qc += TB) {
+                SeedBuf sbuf{reinterpret_cast<uint32_t *>(L.u.scratch) + wave * SBUF * 6, 0};
+                for (uint32_t qc = wave; qc < C; qc += NWAVES) {
                     if (L.win_T[qc] == 0) continue;
                     for (uint32_t o = 0; o < 2; o++) {
                         const RunState rs = L.run[qc][o];
-                        if (rs.active) emit_seed(a, L.qid, L.qpos[qc], rs.best_j, o, rs.best_c, L.win_s[qc]);
+                        if (rs.active)
+                            seeds_push(a, sbuf, lane, L.qid, L.qpos[qc], rs.best_j, o, rs.best_c,
+                                       L.win_s[qc]);
                     }
                 }
+                seeds_flush(a, sbuf, lane);
             }
             c_begin = L.c1;
             __syncthreads();
+            PHASE(PH_FLUSH);
         }
         __syncthreads();
     }
+    if (prof)
+        for (int t = 0; t < PH_N; t++) atomicAdd(&a.phase[t], (unsigned long long)L.ph[t]);
 }
 
 // Per span: minimizer range of its window starts and its tile count.

@@ -153,9 +153,10 @@ class Result:
         return np.array(ms[:], dtype=np.float64)
 
     def stats(self) -> dict:
-        v = (ctypes.c_uint64 * 6)()
-        _check(lib().sdf_result_stats(self._h, v, 6))
-        keys = ["windows", "hits", "kept", "tiles", "partitions", "seeds"]
+        v = (ctypes.c_uint64 * 8)()
+        _check(lib().sdf_result_stats(self._h, v, 8))
+        keys = ["windows", "hits", "kept", "tiles", "partitions", "seeds", "candidate_evals",
+                "scan_words"]
         return dict(zip(keys, [int(x) for x in v]))
 
 

@@ -250,7 +250,7 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
     res->stats[5] = hc[CNT_SEEDS];
     res->stats[6] = hc[CNT_EVALS];
     res->stats[7] = hc[CNT_SCAN];
-    chain_seeds(ix->view(), res->seeds.p, res->nseeds, P.n, P.max_overlap, res->chain, st);
+    chain_seeds(ix->view(), res->seeds.p, res->nseeds, P.n, P.max_overlap, nq, res->chain, st);
     tm.mark();
     tm.mark();
     SDF_HIP(hipStreamSynchronize(st));
@@ -283,6 +283,7 @@ sdf_status sdf_index_build(const char *const *seqs, const uint64_t *lens, uint32
         }
         if (total == 0) throw Error{SDF_EINVAL, "empty input"};
         if (total > MAX_TOTAL) throw Error{SDF_EINVAL, "total length too large for 32-bit positions"};
+        StreamScope scope((hipStream_t)hip_stream);
         ix = new sdf_index_s();
         SDF_HIP(hipGetDevice(&ix->device));
         ix->k = p->k;
@@ -330,6 +331,7 @@ sdf_status sdf_index_entries(sdf_index ix, uint32_t *hash, uint8_t *strand, uint
         if (!ix) throw Error{SDF_EINVAL, "NULL index"};
         if (cap < ix->ne) throw Error{SDF_EINVAL, "capacity below the number of entries"};
         SDF_HIP(hipSetDevice(ix->device));
+        StreamScope scope(nullptr);
         DevBuf<uint64_t> key(ix->ne + 1);
         const uint64_t ndir = ix->dir.n;
         k_expand_entries<<<(unsigned)((ndir + 255) / 256), 256>>>(ix->dir.p, ndir, ix->dir_shift,
@@ -372,13 +374,17 @@ sdf_status sdf_search_batch(sdf_index ix, const sdf_span *qs, uint32_t n,
         if (!ix || !out) throw Error{SDF_EINVAL, "NULL argument"};
         if (n && !qs) throw Error{SDF_EINVAL, "NULL spans"};
         SDF_HIP(hipSetDevice(ix->device));
+        StreamScope scope((hipStream_t)hip_stream);
         r = new sdf_result_s();
         r->device = ix->device;
         r->st = (hipStream_t)hip_stream;
         run_search(ix, qs, n, p, (hipStream_t)hip_stream, r);
         *out = r;
     });
-    if (rc != SDF_OK) delete r;
+    if (rc != SDF_OK && r) {
+        (void)hipStreamSynchronize((hipStream_t)hip_stream);  // queued work may use r's buffers
+        delete r;
+    }
     return rc;
 }
 
@@ -427,6 +433,7 @@ sdf_status sdf_result_seeds(sdf_result r, sdf_seed *dst, uint64_t cap, uint64_t 
         if (r->nseeds) {
             SDF_HIP(hipSetDevice(r->device));
             if (!r->have_seeds) {
+                StreamScope scope(r->st);
                 DevBuf<uint32_t> sorted(r->nseeds * 6);
                 sort_seeds(r->seeds.p, r->nseeds, sorted.p, r->st);
                 r->h_seeds.resize(r->nseeds * 6);
@@ -456,7 +463,8 @@ sdf_status sdf_result_stats(sdf_result r, uint64_t *v, uint32_t n_v) {
 void sdf_result_free(sdf_result r) {
     if (!r) return;
     (void)hipSetDevice(r->device);
-    if (r->st) (void)hipStreamSynchronize(r->st);
+    (void)hipStreamSynchronize(r->st);
+    StreamScope scope(r->st);
     delete r;
 }
 

@@ -64,16 +64,35 @@ __device__ __forceinline__ int64_t diag_of(uint32_t o, uint32_t i, uint32_t j) {
     return o == 0 ? (int64_t)j - (int64_t)i : (int64_t)j + (int64_t)i;
 }
 
-// Second key: (qid << 40) | (o << 39) | cell, in the order of the first sort.
-__global__ void k_key_cell(const uint32_t *seeds, const uint32_t *order, uint64_t ns,
-                           uint32_t cellw, uint64_t *key, uint32_t *val) {
+// Group key of a seed: (qid, strand, diagonal cell) packed as
+// ((qid << 1 | o) << cbits) | cell, cell = (diagonal + total) / cellw.
+struct CellKey {
+    uint64_t total;
+    uint32_t cellw, cbits, ibits;
+};
+__device__ __forceinline__ uint64_t group_of(const CellKey &ck, const uint32_t *r) {
+    const int64_t d = diag_of(r[3], r[1], r[2]) + (int64_t)ck.total;  // >= 0
+    const uint64_t cell = (uint64_t)d / ck.cellw;
+    return ((((uint64_t)r[0] << 1) | r[3]) << ck.cbits) | cell;
+}
+
+// One 64-bit key (group << ibits | i) when it fits.
+__global__ void k_key_combined(const uint32_t *seeds, uint64_t ns, CellKey ck, uint64_t *key,
+                               uint32_t *val) {
+    uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ns) return;
+    const uint32_t *r = seeds + t * 6;
+    key[t] = (group_of(ck, r) << ck.ibits) | r[1];
+    val[t] = (uint32_t)t;
+}
+
+// Otherwise: first sorted by i, then by the group key in that order.
+__global__ void k_key_cell(const uint32_t *seeds, const uint32_t *order, uint64_t ns, CellKey ck,
+                           uint64_t *key, uint32_t *val) {
     uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ns) return;
     const uint32_t s = order[t];
-    const uint32_t *r = seeds + (uint64_t)s * 6;
-    const int64_t d = diag_of(r[3], r[1], r[2]) + (1ll << 32);  // >= 0
-    const uint64_t cell = (uint64_t)d / cellw;                  // < 2^34
-    key[t] = ((uint64_t)r[0] << 40) | ((uint64_t)r[3] << 39) | cell;
+    key[t] = group_of(ck, seeds + (uint64_t)s * 6);
     val[t] = s;
 }
 
@@ -83,12 +102,13 @@ struct Sorted {
     int64_t *d;
 };
 
-__global__ void k_gather(const uint32_t *seeds, const uint64_t *gkey, const uint32_t *order,
-                         uint64_t ns, const uint64_t *off, uint32_t nseq, Sorted s) {
+__global__ void k_gather(const uint32_t *seeds, const uint64_t *gkey, uint32_t gshift,
+                         const uint32_t *order, uint64_t ns, const uint64_t *off, uint32_t nseq,
+                         Sorted s) {
     uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ns) return;
     const uint32_t *r = seeds + (uint64_t)order[t] * 6;
-    s.g[t] = gkey[t];
+    s.g[t] = gkey[t] >> gshift;
     s.i[t] = r[1];
     s.j[t] = r[2];
     s.c[t] = r[4];
@@ -107,7 +127,8 @@ __device__ __forceinline__ bool linked(const Sorted &s, uint64_t a, uint64_t b, 
     return dd <= (int64_t)mo && -dd <= (int64_t)mo;
 }
 
-__global__ void k_link(Sorted s, uint64_t ns, uint32_t n, uint32_t mo, uint32_t *par) {
+__global__ void k_link(Sorted s, uint64_t ns, uint32_t n, uint32_t mo, uint32_t cbits,
+                       uint32_t *par) {
     uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= ns) return;
     const uint64_t g = s.g[a];
@@ -117,7 +138,7 @@ __global__ void k_link(Sorted s, uint64_t ns, uint32_t n, uint32_t mo, uint32_t 
         if (linked(s, a, b, n, mo)) uf_union(par, (uint32_t)a, (uint32_t)b);
     // next cell of the same query and strand: i within (ia - n, ia + n)
     const uint64_t g2 = g + 1;
-    if ((g2 >> 39) != (g >> 39)) return;
+    if ((g2 >> cbits) != (g >> cbits)) return;  // the cell after the last of its strand
     uint64_t lo = a + 1, hi = ns;
     while (lo < hi) {
         uint64_t m = (lo + hi) >> 1;
@@ -154,16 +175,44 @@ __global__ void k_agg_init(Agg g, uint64_t ns) {
     g.cmax[a] = 0;
 }
 
+// Seeds of one component are mostly adjacent in the sorted order: each wave
+// reduces runs of equal roots first and only the last lane of a run issues
+// the atomics.
 __global__ void k_agg(Sorted s, const uint32_t *par, uint64_t ns, Agg g) {
-    uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= ns) return;
-    const uint32_t r = par[a];
-    atomicMin(g.qmin + r, s.i[a]);
-    atomicMax(g.qmax + r, s.i[a]);
-    atomicMin(g.tmin + r, s.j[a]);
-    atomicMax(g.tmax + r, s.j[a]);
-    atomicAdd(g.cnt + r, 1u);
-    atomicMax(g.cmax + r, s.c[a]);
+    const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const bool act = a < ns;
+    const uint32_t r = act ? par[a] : 0xFFFFFFFFu;
+    uint32_t qmin = act ? s.i[a] : 0xFFFFFFFFu, qmax = act ? s.i[a] : 0u;
+    uint32_t tmin = act ? s.j[a] : 0xFFFFFFFFu, tmax = act ? s.j[a] : 0u;
+    uint32_t cnt = act ? 1u : 0u, cmax = act ? s.c[a] : 0u;
+    const uint32_t rprev = __shfl_up(r, 1, 64);
+    bool head = lane == 0 || rprev != r;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y0 = __shfl_up(qmin, d, 64), y1 = __shfl_up(qmax, d, 64);
+        const uint32_t y2 = __shfl_up(tmin, d, 64), y3 = __shfl_up(tmax, d, 64);
+        const uint32_t y4 = __shfl_up(cnt, d, 64), y5 = __shfl_up(cmax, d, 64);
+        const bool hy = __shfl_up((int)head, d, 64) != 0;
+        if (lane >= d && !head) {
+            qmin = min(qmin, y0);
+            qmax = max(qmax, y1);
+            tmin = min(tmin, y2);
+            tmax = max(tmax, y3);
+            cnt += y4;
+            cmax = max(cmax, y5);
+            head = hy;
+        }
+    }
+    const uint32_t rnext = __shfl_down(r, 1, 64);
+    const bool tail = act && (lane == 63 || rnext != r || a + 1 >= ns);
+    if (tail) {
+        atomicMin(g.qmin + r, qmin);
+        atomicMax(g.qmax + r, qmax);
+        atomicMin(g.tmin + r, tmin);
+        atomicMax(g.tmax + r, tmax);
+        atomicAdd(g.cnt + r, cnt);
+        atomicMax(g.cmax + r, cmax);
+    }
 }
 
 __global__ void k_root_flags(const uint32_t *par, uint64_t ns, uint32_t *flag) {
@@ -171,15 +220,15 @@ __global__ void k_root_flags(const uint32_t *par, uint64_t ns, uint32_t *flag) {
     if (a < ns) flag[a] = (par[a] == (uint32_t)a) ? 1u : 0u;
 }
 
-__global__ void k_emit_cands(Sorted s, const uint32_t *par, uint64_t ns, Agg g,
+__global__ void k_emit_cands(Sorted s, const uint32_t *par, uint64_t ns, Agg g, uint32_t cbits,
                              const uint32_t *pre, const uint64_t *off, uint32_t nseq, uint32_t n,
                              sdf_candidate *out) {
     uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= ns || par[a] != (uint32_t)a) return;
     sdf_candidate c;
     const uint64_t gk = s.g[a];
-    c.query_id = (uint32_t)(gk >> 40);
-    c.strand = (uint32_t)((gk >> 39) & 1);
+    c.query_id = (uint32_t)(gk >> (cbits + 1));
+    c.strand = (uint32_t)((gk >> cbits) & 1);
     c.q_seq = seq_of(off, nseq, g.qmin[a]);
     c.t_seq = s.ts[a];
     c.q_begin = g.qmin[a] - off[c.q_seq];
@@ -224,35 +273,101 @@ __global__ void k_bitonic_cands(sdf_candidate *c, uint64_t n2, uint64_t k, uint6
     }
 }
 
+// Bitonic stages with j < BS run inside one block on LDS copies of the
+// records; stages with larger j use one launch each (k_bitonic_cands).
+constexpr int BS = 1024;
+__global__ void __launch_bounds__(BS / 2) k_bitonic_local(sdf_candidate *c, uint64_t n2,
+                                                          uint64_t k_first, uint64_t k_last) {
+    __shared__ sdf_candidate sh[BS];
+    const uint64_t base = (uint64_t)blockIdx.x * BS;
+    const uint32_t m = (uint32_t)min<uint64_t>(BS, n2);
+    for (uint32_t t = threadIdx.x; t < m; t += BS / 2) sh[t] = c[base + t];
+    __syncthreads();
+    for (uint64_t k = k_first; k <= k_last; k <<= 1) {
+        for (uint64_t j = min<uint64_t>(k >> 1, BS / 2); j > 0; j >>= 1) {
+            for (uint32_t t = threadIdx.x; t < m / 2; t += BS / 2) {
+                // t-th pair of this stage inside the block
+                const uint32_t lo = (uint32_t)(((t / j) * 2 * j) + (t % j));
+                const uint32_t hi = lo + (uint32_t)j;
+                const uint64_t gi = base + lo;
+                const bool asc = (gi & k) == 0;
+                const sdf_candidate x = sh[lo], y = sh[hi];
+                if (cand_less(y, x) == asc) {
+                    sh[lo] = y;
+                    sh[hi] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t t = threadIdx.x; t < m; t += BS / 2) c[base + t] = sh[t];
+}
+
 static unsigned nb(uint64_t n, unsigned t = 256) { return (unsigned)((n + t - 1) / t); }
 
+static void sort_candidates(sdf_candidate *c, uint64_t n2, hipStream_t st) {
+    if (n2 <= 1) return;
+    const unsigned blocks = (unsigned)((n2 + BS - 1) / BS);
+    // all stages with k <= BS inside blocks
+    k_bitonic_local<<<blocks, BS / 2, 0, st>>>(c, n2, 2, std::min<uint64_t>(n2, BS));
+    SDF_HIP(hipGetLastError());
+    for (uint64_t k = 2 * BS; k <= n2; k <<= 1) {
+        for (uint64_t j = k >> 1; j >= (uint64_t)BS; j >>= 1) {
+            k_bitonic_cands<<<nb(n2), 256, 0, st>>>(c, n2, k, j);
+            SDF_HIP(hipGetLastError());
+        }
+        // remaining stages j < BS of this k inside blocks
+        k_bitonic_local<<<blocks, BS / 2, 0, st>>>(c, n2, k, k);
+        SDF_HIP(hipGetLastError());
+    }
+}
+
+static uint32_t bitlen(uint64_t v) {
+    uint32_t b = 0;
+    while (b < 64 && (v >> b)) b++;
+    return b;
+}
+
 void chain_seeds(const IndexView &ix, const uint32_t *seeds, uint64_t ns, uint32_t n,
-                 uint32_t mo, ChainOut &out, hipStream_t st) {
+                 uint32_t mo, uint32_t nspans, ChainOut &out, hipStream_t st) {
     out.ncands = 0;
     if (ns == 0) {
         out.cands.alloc(1);
         return;
     }
-    DevBuf<uint32_t> k1(ns), order(ns);
-    k_key_i<<<nb(ns), 256, 0, st>>>(seeds, ns, k1.p, order.p);
-    SDF_HIP(hipGetLastError());
-    radix_sort_u32(k1.p, order.p, ns, 32, st);
+    CellKey ck;
+    ck.total = ix.total;
+    ck.cellw = mo + 1;
+    ck.cbits = bitlen((3 * ix.total) / ck.cellw + 1);
+    ck.ibits = bitlen(ix.total);
+    const uint32_t qbits = bitlen(nspans > 0 ? nspans - 1 : 0);
+    const uint32_t gbits = qbits + 1 + ck.cbits;
     DevBuf<uint64_t> gk(ns);
     DevBuf<uint32_t> order2(ns);
-    k_key_cell<<<nb(ns), 256, 0, st>>>(seeds, order.p, ns, mo + 1, gk.p, order2.p);
-    SDF_HIP(hipGetLastError());
-    radix_sort_u64(gk.p, order2.p, ns, 64, st);
-    k1.reset();
-    order.reset();
+    uint32_t gshift = 0;
+    if (gbits + ck.ibits <= 64) {
+        k_key_combined<<<nb(ns), 256, 0, st>>>(seeds, ns, ck, gk.p, order2.p);
+        SDF_HIP(hipGetLastError());
+        radix_sort_u64(gk.p, order2.p, ns, (int)(gbits + ck.ibits), st);
+        gshift = ck.ibits;
+    } else {
+        DevBuf<uint32_t> k1(ns), order(ns);
+        k_key_i<<<nb(ns), 256, 0, st>>>(seeds, ns, k1.p, order.p);
+        SDF_HIP(hipGetLastError());
+        radix_sort_u32(k1.p, order.p, ns, (int)ck.ibits, st);
+        k_key_cell<<<nb(ns), 256, 0, st>>>(seeds, order.p, ns, ck, gk.p, order2.p);
+        SDF_HIP(hipGetLastError());
+        radix_sort_u64(gk.p, order2.p, ns, (int)gbits, st);
+    }
     DevBuf<uint64_t> sg(ns);
     DevBuf<uint32_t> si(ns), sj(ns), sc(ns), sts(ns);
     DevBuf<int64_t> sd(ns);
     Sorted s{sg.p, si.p, sj.p, sc.p, sts.p, sd.p};
-    k_gather<<<nb(ns), 256, 0, st>>>(seeds, gk.p, order2.p, ns, ix.off, ix.nseq, s);
+    k_gather<<<nb(ns), 256, 0, st>>>(seeds, gk.p, gshift, order2.p, ns, ix.off, ix.nseq, s);
     SDF_HIP(hipGetLastError());
     DevBuf<uint32_t> par(ns);
     iota_u32(par.p, ns, st);
-    k_link<<<nb(ns), 256, 0, st>>>(s, ns, n, mo, par.p);
+    k_link<<<nb(ns), 256, 0, st>>>(s, ns, n, mo, ck.cbits, par.p);
     SDF_HIP(hipGetLastError());
     k_flatten<<<nb(ns), 256, 0, st>>>(par.p, ns);
     SDF_HIP(hipGetLastError());
@@ -271,19 +386,15 @@ void chain_seeds(const IndexView &ix, const uint32_t *seeds, uint64_t ns, uint32
     uint64_t n2 = 1;
     while (n2 < nc) n2 <<= 1;
     out.cands.alloc(n2);
-    k_emit_cands<<<nb(ns), 256, 0, st>>>(s, par.p, ns, g, pre.p, ix.off, ix.nseq, n, out.cands.p);
+    k_emit_cands<<<nb(ns), 256, 0, st>>>(s, par.p, ns, g, ck.cbits, pre.p, ix.off, ix.nseq, n,
+                                         out.cands.p);
     SDF_HIP(hipGetLastError());
     if (n2 > nc) {
         k_pad_cands<<<nb(n2 - nc), 256, 0, st>>>(out.cands.p, nc, n2);
         SDF_HIP(hipGetLastError());
     }
-    for (uint64_t k = 2; k <= n2; k <<= 1)
-        for (uint64_t j = k >> 1; j > 0; j >>= 1) {
-            k_bitonic_cands<<<nb(n2), 256, 0, st>>>(out.cands.p, n2, k, j);
-            SDF_HIP(hipGetLastError());
-        }
+    sort_candidates(out.cands.p, n2, st);
     out.ncands = nc;
-    SDF_HIP(hipStreamSynchronize(st));
 }
 
 // ------------------------------------------------------------- seed sort --
@@ -322,7 +433,6 @@ void sort_seeds(const uint32_t *seeds, uint64_t ns, uint32_t *dst, hipStream_t s
     radix_sort_u64(key.p, val2.p, ns, 64, st);
     k_seed_permute<<<nb(ns), 256, 0, st>>>(seeds, val2.p, ns, dst);
     SDF_HIP(hipGetLastError());
-    SDF_HIP(hipStreamSynchronize(st));
 }
 
 }  // namespace sdf

@@ -12,10 +12,25 @@ void set_error(const std::string &msg) { t_err = msg; }
 const char *last_error() { return t_err.c_str(); }
 
 // ------------------------------------------------------------------ pool --
+static thread_local hipStream_t t_stream = nullptr;
+hipStream_t current_stream() { return t_stream; }
+StreamScope::StreamScope(hipStream_t s) : prev(t_stream) { t_stream = s; }
+StreamScope::~StreamScope() { t_stream = prev; }
+
 namespace {
+struct PoolKey {
+    int dev;
+    size_t cls;
+    hipStream_t st;
+    bool operator<(const PoolKey &o) const {
+        if (dev != o.dev) return dev < o.dev;
+        if (cls != o.cls) return cls < o.cls;
+        return (uintptr_t)st < (uintptr_t)o.st;
+    }
+};
 std::mutex g_mu;
 std::unordered_map<void *, std::pair<int, size_t>> g_live;  // ptr -> (device, class)
-std::map<std::pair<int, size_t>, std::vector<void *>> g_free;
+std::map<PoolKey, std::vector<void *>> g_free;
 
 size_t size_class(size_t b) {
     if (b <= 256) return 256;
@@ -34,7 +49,7 @@ void pool_trim() {
     int cur = 0;
     (void)hipGetDevice(&cur);
     for (auto &kv : g_free) {
-        (void)hipSetDevice(kv.first.first);
+        (void)hipSetDevice(kv.first.dev);
         for (void *p : kv.second) (void)hipFree(p);
         kv.second.clear();
     }
@@ -47,7 +62,7 @@ void *pool_alloc(size_t bytes) {
     size_t c = size_class(bytes);
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        auto it = g_free.find({dev, c});
+        auto it = g_free.find(PoolKey{dev, c, t_stream});
         if (it != g_free.end() && !it->second.empty()) {
             void *p = it->second.back();
             it->second.pop_back();
@@ -76,7 +91,7 @@ void pool_free(void *p) {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_live.find(p);
     if (it == g_live.end()) return;
-    g_free[it->second].push_back(p);
+    g_free[PoolKey{it->second.first, it->second.second, t_stream}].push_back(p);
     g_live.erase(it);
 }
 
@@ -196,8 +211,6 @@ static void scan_impl(const T *in, O *out, uint64_t n, hipStream_t st) {
     scan_impl<uint64_t, uint64_t>(sums.p, off.p, nb, st);
     k_scan_down<T, O><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, n, off.p, out, 1);
     SDF_HIP(hipGetLastError());
-    // temporaries are returned to the pool after the stream consumes them
-    SDF_HIP(hipStreamSynchronize(st));
 }
 
 void scan_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n, hipStream_t st) {
@@ -327,7 +340,6 @@ static void radix_impl(K *keys, uint32_t *vals, uint64_t n, int bits, hipStream_
         SDF_HIP(hipMemcpyAsync(keys, ka, n * sizeof(K), hipMemcpyDeviceToDevice, st));
         SDF_HIP(hipMemcpyAsync(vals, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
     }
-    SDF_HIP(hipStreamSynchronize(st));
 }
 
 void radix_sort_u32(uint32_t *keys, uint32_t *vals, uint64_t n, int bits, hipStream_t st) {

@@ -31,11 +31,20 @@ struct Error {
     } while (0)
 
 // Device memory pool ----------------------------------------------------------
-// Size-class free lists per device; blocks are returned, not released, until
-// pool_trim() or process end.
+// Size-class free lists per (device, stream); blocks are returned, not
+// released, until pool_trim() or process end.  A block freed while a stream
+// is current is reused only by work on that same stream, so stream order
+// alone keeps a reused block from being overwritten while still in use and
+// no host synchronization is needed before a free.
 void *pool_alloc(size_t bytes);
 void pool_free(void *p);
 void pool_trim();
+hipStream_t current_stream();
+struct StreamScope {  // makes `s` the current stream of this host thread
+    hipStream_t prev;
+    explicit StreamScope(hipStream_t s);
+    ~StreamScope();
+};
 
 template <class T>
 struct DevBuf {

@@ -47,7 +47,7 @@ struct ChainOut {
     uint64_t ncands = 0;
 };
 void chain_seeds(const IndexView &ix, const uint32_t *seeds, uint64_t nseeds, uint32_t n,
-                 uint32_t max_overlap, ChainOut &out, hipStream_t st);
+                 uint32_t max_overlap, uint32_t nspans, ChainOut &out, hipStream_t st);
 // Seeds sorted by (query_id, i, j, strand) into dst (device, 6 u32 each).
 void sort_seeds(const uint32_t *seeds, uint64_t nseeds, uint32_t *dst, hipStream_t st);
 

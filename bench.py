@@ -54,6 +54,21 @@ def algorithmic_hits(ix):
     return int((c * c).sum() - c.sum())
 
 
+def measured_traffic(workload_name):
+    """HBM bytes per launch of the tile kernel from the committed rocprofv3
+    counter summary, or None if the kernel source changed since then."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_k_tile_search_%s.json" % workload_name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        tr = json.load(fh)
+    src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in tr["source_files"])
+    if hashlib.sha256(src).hexdigest() != tr["source_sha256"]:
+        return None
+    return int(tr["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(g, sample_mbp, max_error, min_len):
     import numpy as np
     import oracle
@@ -76,6 +91,73 @@ def cpu_baseline(g, sample_mbp, max_error, min_len):
             "seconds": round(dt, 3)}
 
 
+def batched_vs_plain(steps):
+    """4,096 spans of 1-100 kbp against the resident index of a 250 Mbp
+    sequence: one batched search against the same spans searched one by one."""
+    import numpy as np
+    import torch
+    from paper_1807_00205_amd import sdf, synth
+    g = synth.config3()
+    ix = sdf.Index(g.seqs, 12, 16)
+    spans = g.spans
+    qb = sum(e - b for _, b, e in spans)
+    r = ix.search_batch(spans, timing=True)
+    r.candidates()
+    r.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kms = []
+    for _ in range(steps):
+        r = ix.search_batch(spans, timing=True)
+        ncand = len(r.candidates())
+        kms.append(float(r.timing()[1]))
+        stats = r.stats()
+        r.close()
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / steps
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for sp in spans:
+        s0 = time.perf_counter()
+        r = ix.search(sp)
+        r.candidates()
+        r.close()
+        lat.append((time.perf_counter() - s0) * 1e3)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    return ix, g, {
+        "workload": "250 Mbp uniform sequence with 2,518 planted duplications (1-5 kbp, "
+                    "2-15%%); 4,096 query spans of 1-100 kbp (log-uniform), %.1f Mbp" % (qb / 1e6),
+        "batched_mbp_per_s": round(qb / tb / 1e6, 2), "batched_ms": round(tb * 1e3, 3),
+        "batched_tile_kernel_ms": round(float(np.mean(kms)), 4),
+        "plain_mbp_per_s": round(qb / tp / 1e6, 2), "plain_ms": round(tp * 1e3, 2),
+        "plain_latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                             "p99": round(float(np.percentile(lat, 99)), 4)},
+        "speedup": round(tp / tb, 2), "candidates": ncand, "stats": stats}
+
+
+def serving(ix, g, rates, seconds, workers):
+    """Open-loop Poisson arrivals of spans of 1 kbp - 5 Mbp (log-uniform) over
+    the resident 250 Mbp index: continuous batching vs one request at a time."""
+    from paper_1807_00205_amd import serve, synth
+    out = {"workload": "Poisson arrivals, spans 1 kbp - 5 Mbp (log-uniform) against the "
+                       "resident 250 Mbp index", "workers": workers, "rates": {}}
+    for rate in rates:
+        n = int(max(20, min(2000, rate * seconds)))
+        reqs = synth.poisson_requests(1000 + int(rate), rate, n, [len(g.seqs[0])])
+        served = serve.measure(ix, reqs, workers=workers, max_batch=4096)
+        plain = serve.measure(ix, reqs, workers=1, max_batch=1)
+        out["rates"][str(rate)] = {"requests": n,
+                                   "served": {k: round(v, 3) if isinstance(v, float) else v
+                                              for k, v in served.items()},
+                                   "plain_fifo": {k: round(v, 3) if isinstance(v, float) else v
+                                                  for k, v in plain.items()}}
+        log("  rate %s: served p50 %.2f p99 %.2f ms, plain p50 %.2f p99 %.2f ms" % (
+            rate, served["p50_ms"], served["p99_ms"], plain["p50_ms"], plain["p99_ms"]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +168,14 @@ def main():
     ap.add_argument("--min-len", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-mbp", type=float, default=12.0)
+    ap.add_argument("--no-batch", action="store_true", help="skip batched vs plain")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep")
+    ap.add_argument("--serve-rates", default="10,100,1000")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-workers", type=int, default=4)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first copy this many MiB device-to-device (a reference kernel "
+                         "of known traffic for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the search path is built and timed on a single "
@@ -97,6 +187,13 @@ def main():
     from paper_1807_00205_amd import sdf
 
     torch.cuda.init()
+    if args.calibrate_copy_mib:
+        nbytes = args.calibrate_copy_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     log("generating workload", args.workload)
     t = time.time()
     g, spans, desc = workload(args.workload)
@@ -156,7 +253,7 @@ def main():
                        "p99": round(float(np.percentile(lat, 99)), 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": None, "kernel": "k_tile_search",
+                     "traffic": measured_traffic(args.workload), "kernel": "k_tile_search",
                      "kernel_ms": round(mean_k, 4), "algorithmic_bytes": int(alg_bytes)},
         "detail": {"index_build_s": round(build_s, 3), "minimizers": nm, "eligible": ne,
                    "algorithmic_hits": alg_hits, "candidates": ncand, **stats},
@@ -164,6 +261,17 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_sample_mbp, args.max_error, args.min_len)
+    ix.close()
+    if not args.no_batch or not args.no_serve:
+        log("batched vs plain (250 Mbp, 4,096 spans)")
+        ix3, g3, bat = batched_vs_plain(max(1, args.steps // 2))
+        if not args.no_batch:
+            out["batched"] = bat
+        if not args.no_serve:
+            log("serving")
+            rates = [float(x) for x in args.serve_rates.split(",") if x]
+            out["serving"] = serving(ix3, g3, rates, args.serve_seconds, args.serve_workers)
+        ix3.close()
     print(json.dumps(out), flush=True)
 
 

@@ -231,7 +231,8 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
     if (phase_prof) {
         // per-phase wall-clock ticks summed over workgroups (diagnostic)
         std::vector<unsigned long long> ph(PH_N);
-        SDF_HIP(hipMemcpy(ph.data(), phase.p, PH_N * 8, hipMemcpyDeviceToHost));
+        SDF_HIP(hipMemcpyAsync(ph.data(), phase.p, PH_N * 8, hipMemcpyDeviceToHost, st));
+        SDF_HIP(hipStreamSynchronize(st));
         int khz = 0;
         SDF_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ix->device));
         static const char *names[PH_N] = {"setup", "query", "lists", "plists", "pass1", "pass2",
@@ -412,7 +413,9 @@ sdf_status sdf_result_copy(sdf_result r, sdf_candidate *dst, uint64_t cap, uint6
         if (m && !dst) throw Error{SDF_EINVAL, "NULL destination"};
         if (m) {
             SDF_HIP(hipSetDevice(r->device));
-            SDF_HIP(hipMemcpy(dst, r->chain.cands.p, m * sizeof(sdf_candidate), hipMemcpyDeviceToHost));
+            SDF_HIP(hipMemcpyAsync(dst, r->chain.cands.p, m * sizeof(sdf_candidate),
+                                   hipMemcpyDeviceToHost, r->st));
+            SDF_HIP(hipStreamSynchronize(r->st));
         }
         if (written) *written = m;
     });
@@ -437,7 +440,9 @@ sdf_status sdf_result_seeds(sdf_result r, sdf_seed *dst, uint64_t cap, uint64_t 
                 DevBuf<uint32_t> sorted(r->nseeds * 6);
                 sort_seeds(r->seeds.p, r->nseeds, sorted.p, r->st);
                 r->h_seeds.resize(r->nseeds * 6);
-                SDF_HIP(hipMemcpy(r->h_seeds.data(), sorted.p, r->nseeds * 24, hipMemcpyDeviceToHost));
+                SDF_HIP(hipMemcpyAsync(r->h_seeds.data(), sorted.p, r->nseeds * 24,
+                                       hipMemcpyDeviceToHost, r->st));
+                SDF_HIP(hipStreamSynchronize(r->st));
                 r->have_seeds = true;
             }
             if (m) std::memcpy(dst, r->h_seeds.data(), m * sizeof(sdf_seed));

@@ -54,12 +54,24 @@ class _Span(ctypes.Structure):
 _lib = None
 
 
+def _share_torch_runtime():
+    """PyTorch ships its own HIP runtime under the same soname.  Loading it
+    first makes libsdf.so bind to that one runtime, so streams and device
+    state are shared with torch instead of two runtimes competing for the
+    device."""
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        return
+
+
 def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError("libsdf.so is not built; run paper_1807_00205_amd/build.py "
                               "(or __graft_entry__.build())")
+        _share_torch_runtime()
         L = ctypes.CDLL(LIB_PATH)
         vp, u32, u64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
         P = ctypes.POINTER

@@ -1,0 +1,165 @@
+"""Continuous-batching search server over a resident index.
+
+Requests (query spans) arrive at any time.  Worker threads, each owning one
+HIP stream, repeatedly take every queued request that fits the free-HBM
+budget and run them as one batched search; requests that arrive while
+batches are on the GPU join the next batch of the first worker that frees
+up, so several batches overlap on the device.  Every request's result is
+the candidate set of its span alone (query ids are local to the request).
+
+The plain mode (``workers=1, max_batch=1``) is the one-request-at-a-time
+FIFO baseline.
+"""
+from __future__ import annotations
+
+import collections
+import threading
+import time
+from concurrent.futures import Future
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import sdf
+
+
+def request_bytes(span_len: int) -> int:
+    """Upper bound on the device memory one request adds to a batch: its seed
+    buffer (one seed per 8 query bases plus slack, 24 B each) and the
+    chaining scratch (about five times the seed buffer)."""
+    seeds = span_len // 8 + 65536
+    return seeds * 24 * 6
+
+
+class Request:
+    __slots__ = ("span", "arrival", "future", "bytes")
+
+    def __init__(self, span, arrival):
+        self.span = span
+        self.arrival = arrival
+        self.future = Future()
+        self.bytes = request_bytes(span[2] - span[1])
+
+
+class Server:
+    def __init__(self, index: sdf.Index, workers: int = 4, max_batch: int = 4096,
+                 hbm_budget: Optional[int] = None, max_error: float = 0.25,
+                 min_len: int = 1000):
+        import torch
+        self.index = index
+        self.max_batch = max_batch
+        self.max_error, self.min_len = max_error, min_len
+        if hbm_budget is None:
+            free, _ = torch.cuda.mem_get_info()
+            hbm_budget = int(free * 0.5)
+        self.budget = hbm_budget
+        self.in_flight = 0
+        self.queue: collections.deque = collections.deque()
+        self.cv = threading.Condition()
+        self.stop = False
+        self.batches = []  # (size, seconds) per batch
+        self.streams = [torch.cuda.Stream() for _ in range(workers)]
+        self.threads = [threading.Thread(target=self._work, args=(s,), daemon=True)
+                        for s in self.streams]
+        for t in self.threads:
+            t.start()
+
+    def submit(self, span: Tuple[int, int, int], arrival: Optional[float] = None) -> Future:
+        r = Request(span, time.perf_counter() if arrival is None else arrival)
+        if r.bytes > self.budget:
+            r.future.set_exception(MemoryError("request exceeds the HBM budget"))
+            return r.future
+        with self.cv:
+            self.queue.append(r)
+            self.cv.notify()
+        return r.future
+
+    def _take(self) -> List[Request]:
+        """Admit queued requests in arrival order while the budget allows."""
+        batch = []
+        while self.queue and len(batch) < self.max_batch:
+            r = self.queue[0]
+            if self.in_flight + r.bytes > self.budget:
+                break
+            self.queue.popleft()
+            self.in_flight += r.bytes
+            batch.append(r)
+        return batch
+
+    def _work(self, stream):
+        while True:
+            with self.cv:
+                while not self.stop and not (self.queue and
+                                             self.in_flight + self.queue[0].bytes <= self.budget):
+                    self.cv.wait()
+                if self.stop and not self.queue:
+                    return
+                batch = self._take()
+            if not batch:
+                continue
+            t0 = time.perf_counter()
+            try:
+                res = self.index.search_batch([r.span for r in batch], self.max_error,
+                                              self.min_len, stream=stream)
+                c = res.candidates()
+                res.close()
+                done = time.perf_counter()
+                order = np.argsort(c["query_id"], kind="stable")
+                c = c[order]
+                bounds = np.searchsorted(c["query_id"], np.arange(len(batch) + 1))
+                for q, r in enumerate(batch):
+                    mine = c[bounds[q]:bounds[q + 1]].copy()
+                    mine["query_id"] = 0
+                    r.future.set_result((mine, done))
+            except Exception as e:  # isolate failures per batch
+                for r in batch:
+                    if not r.future.done():
+                        r.future.set_exception(e)
+                done = time.perf_counter()
+            with self.cv:
+                self.in_flight -= sum(r.bytes for r in batch)
+                self.batches.append((len(batch), done - t0))
+                self.cv.notify_all()
+
+    def close(self):
+        with self.cv:
+            self.stop = True
+            self.cv.notify_all()
+        for t in self.threads:
+            t.join()
+
+
+def open_loop(server: Server, requests: Sequence[Tuple[float, Tuple[int, int, int]]]):
+    """Submit (arrival offset in s, span) pairs at their arrival times and
+    wait for all; returns per-request latencies (s), query bases and the
+    wall time from the first arrival to the last completion."""
+    t0 = time.perf_counter()
+    futs = []
+    for (ta, span) in requests:
+        now = time.perf_counter() - t0
+        if ta > now:
+            time.sleep(ta - now)
+        arr = time.perf_counter()
+        futs.append((arr, span, server.submit(span, arr)))
+    lat, bases, last = [], 0, t0
+    for arr, span, f in futs:
+        _, done = f.result()
+        lat.append(done - arr)
+        bases += span[2] - span[1]
+        last = max(last, done)
+    first = futs[0][0] if futs else t0
+    return np.array(lat), bases, last - first
+
+
+def measure(index: sdf.Index, requests, workers: int, max_batch: int, **kw):
+    srv = Server(index, workers=workers, max_batch=max_batch, **kw)
+    try:
+        lat, bases, wall = open_loop(srv, requests)
+    finally:
+        srv.close()
+    sizes = [b for b, _ in srv.batches]
+    return {"p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "mbp_per_s": bases / wall / 1e6 if wall > 0 else 0.0,
+            "requests": len(lat), "batches": len(sizes),
+            "mean_batch": float(np.mean(sizes)) if sizes else 0.0}

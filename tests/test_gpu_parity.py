@@ -234,3 +234,78 @@ def test_search_config2(S, oracle_lib):
     r = ix.search(g.spans[0], 0.25, 1000)
     _same(r.candidates(), oc, CAND_F, "candidates")
     _same(r.seeds(), os_, SEED_F, "seeds")
+
+
+@pytest.fixture(scope="module")
+def batch250(S):
+    g = synth.config3()
+    ix = S.Index(g.seqs, 12, 16)
+    return g, ix
+
+
+def test_batch_config3_sampled(S, oracle_lib, batch250):
+    """The 250 Mbp workload with 4,096 spans of 1-100 kbp searched in one batch:
+    the candidates and seeds of 48 sampled spans equal the oracle's, and a
+    plain search of a span equals its slice of the batch."""
+    g, ix = batch250
+    r = ix.search_batch(g.spans)
+    cands = r.candidates()
+    seeds = r.seeds()
+    rng = synth.rng_for(99)
+    pick = sorted(rng.choice(len(g.spans), size=48, replace=False).tolist())
+    b, off = g.concat()
+    orc = oracle_lib.OracleIndex(b, off, 12, 16)
+    os_, oc = orc.search([g.spans[q] for q in pick], 0.25, 1000)
+    remap = np.array(pick, dtype=np.uint32)
+    oc = oc.copy()
+    os_ = os_.copy()
+    oc["query_id"] = remap[oc["query_id"]]
+    os_["query_id"] = remap[os_["query_id"]]
+    sel = np.isin(cands["query_id"], remap)
+    _same(cands[sel], oc, CAND_F, "candidates")
+    sel = np.isin(seeds["query_id"], remap)
+    _same(seeds[sel], os_, SEED_F, "seeds")
+    for q in pick[:4]:
+        rp = ix.search(g.spans[q]).candidates()
+        mine = cands[cands["query_id"] == q].copy()
+        mine["query_id"] = 0
+        _same(mine, rp, CAND_F, "plain span %d" % q)
+
+
+def test_serving_mix_equals_alone(S, batch250):
+    """Requests served with continuous batching on several streams get the
+    same candidates as each span searched alone."""
+    from paper_1807_00205_amd import serve
+    g, ix = batch250
+    rng = synth.rng_for(4)
+    reqs = synth.draw_spans(rng, [len(g.seqs[0])], 40, 1000, 2_000_000)
+    srv = serve.Server(ix, workers=3, max_batch=16)
+    try:
+        futs = [srv.submit(sp) for sp in reqs]
+        got = [f.result(timeout=120)[0] for f in futs]
+    finally:
+        srv.close()
+    assert len(srv.batches) >= 1
+    for sp, mine in zip(reqs, got):
+        alone = ix.search(sp).candidates()
+        _same(mine, alone, CAND_F, "span %s" % (sp,))
+
+
+def test_serving_admission_budget(S, batch250):
+    """A budget that fits one request at a time still serves every request
+    (admission waits for memory to free up); an oversize request fails alone."""
+    from paper_1807_00205_amd import serve
+    g, ix = batch250
+    reqs = [(0, 1000 * t, 1000 * t + 50_000) for t in range(6)]
+    one = serve.request_bytes(50_000)
+    srv = serve.Server(ix, workers=2, max_batch=8, hbm_budget=one + one // 2)
+    try:
+        futs = [srv.submit(sp) for sp in reqs]
+        big = srv.submit((0, 0, 100_000_000))
+        for f in futs:
+            f.result(timeout=120)
+        with pytest.raises(MemoryError):
+            big.result(timeout=10)
+    finally:
+        srv.close()
+    assert max(b for b, _ in srv.batches) == 1

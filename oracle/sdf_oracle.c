@@ -250,25 +250,24 @@ void *or_index_build(const uint8_t *bytes, const uint64_t *off, uint32_t nseq,
         p = q;
     }
 
-    /* winnow each sequence */
-    uint64_t maxlen = 0;
-    for (uint32_t s = 0; s < nseq; s++)
-        if (off[s + 1] - off[s] > maxlen)
-            maxlen = off[s + 1] - off[s];
+    /* winnow each sequence (sequences are independent; OpenMP runs several
+     * at once, each with its own scratch arrays) */
     uint8_t *sel = (uint8_t *)calloc(ix->total ? ix->total : 1, 1);
-    uint32_t *h = (uint32_t *)malloc((maxlen ? maxlen : 1) * sizeof(uint32_t));
-    uint8_t *fl = (uint8_t *)malloc(maxlen ? maxlen : 1);
-    uint8_t *ok = (uint8_t *)malloc(maxlen ? maxlen : 1);
     uint64_t nm = 0;
-    for (uint32_t s = 0; s < nseq; s++) {
-        uint64_t b = off[s];
-        or_winnow_seq(ix, s, sel + b, h, fl, ok);
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : nm)
+    for (int64_t si = 0; si < (int64_t)nseq; si++) {
+        uint32_t s = (uint32_t)si;
+        uint64_t len = off[s + 1] - off[s];
+        uint32_t *h = (uint32_t *)malloc((len ? len : 1) * sizeof(uint32_t));
+        uint8_t *fl = (uint8_t *)malloc(len ? len : 1);
+        uint8_t *ok = (uint8_t *)malloc(len ? len : 1);
+        or_winnow_seq(ix, s, sel + off[s], h, fl, ok);
         for (uint64_t p = off[s]; p < off[s + 1]; p++)
             nm += sel[p];
+        free(h);
+        free(fl);
+        free(ok);
     }
-    free(h);
-    free(fl);
-    free(ok);
     ix->nm = nm;
     ix->m_pos = (uint32_t *)malloc((nm ? nm : 1) * sizeof(uint32_t));
     ix->m_hash = (uint32_t *)malloc((nm ? nm : 1) * sizeof(uint32_t));

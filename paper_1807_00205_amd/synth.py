@@ -42,9 +42,18 @@ def rng_for(seed: int) -> np.random.Generator:
 
 
 def random_bases(rng: np.random.Generator, n: int, gc: float = 0.5,
-                 chunk: int = 1 << 26) -> np.ndarray:
-    """Upper-case i.i.d. bases; P(C) = P(G) = gc/2, P(A) = P(T) = (1-gc)/2."""
+                 chunk: int = 1 << 26, byte_lut: bool = False) -> np.ndarray:
+    """Upper-case i.i.d. bases; P(C) = P(G) = gc/2, P(A) = P(T) = (1-gc)/2.
+    With ``byte_lut`` the probabilities are quantised to 1/256 (one random
+    byte per base), which is several times faster for genome-sized inputs."""
     out = np.empty(n, dtype=np.uint8)
+    if byte_lut:
+        c = int(round(gc / 2 * 256))
+        lut = np.repeat(_ACGT, [128 - c, c, c, 128 - c])
+        for s in range(0, n, chunk):
+            e = min(n, s + chunk)
+            out[s:e] = lut[np.frombuffer(rng.bytes(e - s), dtype=np.uint8)]
+        return out
     if gc == 0.5:
         for s in range(0, n, chunk):
             e = min(n, s + chunk)
@@ -70,6 +79,55 @@ def to_lower(seg: np.ndarray) -> np.ndarray:
     letters = _IDX[out] != 255
     out[letters] |= 0x20
     return out
+
+
+def mutate_many(rng: np.random.Generator, src: np.ndarray, seg_end: np.ndarray,
+                rates: np.ndarray) -> tuple:
+    """``mutate`` applied to many copies at once: ``src`` is their
+    concatenation, ``seg_end[p]`` the end of the copy holding position p and
+    ``rates[p]`` its rate.  Deletions stop at the end of their copy.  Returns
+    the mutated concatenation and the output offset of every input position
+    plus one past the end (so copy boundaries map through)."""
+    n = len(src)
+    epos = np.nonzero(rng.random(n, dtype=np.float32) < rates)[0]
+    kind = rng.random(epos.size, dtype=np.float32)
+    spos = epos[kind < 0.9]
+    ipos_all = epos[kind >= 0.9]
+    is_ins = rng.random(ipos_all.size, dtype=np.float32) < 0.5
+    lens = rng.geometric(0.5, size=ipos_all.size).astype(np.int64)
+    out = src.copy()
+    idx = _IDX[out[spos]]
+    ok = idx != 255
+    spos, idx = spos[ok], idx[ok]
+    if spos.size:
+        shift = rng.integers(1, 4, size=spos.size, dtype=np.uint8)
+        newb = _ACGT[(idx + shift) % 4]
+        lower = out[spos] >= 97
+        out[spos] = np.where(lower, newb | 0x20, newb)
+    dpos, dlen = ipos_all[~is_ins], lens[~is_ins]
+    removed = np.zeros(n, dtype=bool)
+    if dpos.size:
+        diff = np.zeros(n + 1, dtype=np.int32)
+        np.add.at(diff, dpos, 1)
+        np.add.at(diff, np.minimum(dpos + dlen, seg_end[dpos]), -1)
+        removed = np.cumsum(diff[:n], dtype=np.int32) > 0
+    ipos, ilen = ipos_all[is_ins], lens[is_ins]
+    alive = ~removed[ipos]
+    ipos, ilen = ipos[alive], ilen[alive]
+    counts = (~removed).astype(np.int32)
+    counts[ipos] += ilen.astype(np.int32)
+    offs = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=offs[1:])
+    src_of = np.repeat(np.arange(n, dtype=np.int64), counts)
+    res = out[src_of]
+    if ipos.size:
+        first_ins = offs[ipos] + 1  # inserted after the (kept) base itself
+        tot = int(ilen.sum())
+        slot = np.repeat(first_ins, ilen) + (np.arange(tot) - np.repeat(np.cumsum(ilen) - ilen, ilen))
+        nb = _ACGT[rng.integers(0, 4, size=slot.size, dtype=np.uint8)]
+        lower = res[slot] >= 97
+        res[slot] = np.where(lower, nb | 0x20, nb)
+    return res, offs
 
 
 def mutate(rng: np.random.Generator, src: np.ndarray, r: float) -> np.ndarray:
@@ -323,6 +381,48 @@ def _mask_repeats(rng, seqs, target_frac, gc, n_cons=20, lo=300, hi=6000,
     return n_lower / total
 
 
+def _mask_repeats_batched(rng, seqs, target_frac, gc, n_cons=20, lo=300, hi=6000,
+                          rate_lo=0.10, rate_hi=0.30, batch=8192):
+    """As _mask_repeats, with the copies of a batch mutated in one vectorized
+    call (each copy keeps its own rate; deletions stop at its end)."""
+    cons = [to_lower(random_bases(rng, _loguniform_int(rng, lo, hi), gc)) for _ in range(n_cons)]
+    cons_rc = [revcomp(c) for c in cons]
+    clen = np.array([len(c) for c in cons], dtype=np.int64)
+    total = sum(len(s) for s in seqs)
+    cum = np.cumsum([len(s) for s in seqs])
+    lower = [np.zeros(len(s), dtype=bool) for s in seqs]
+    n_lower = 0
+    target = int(math.ceil(target_frac * total))
+    while n_lower < target:
+        ids = rng.integers(0, n_cons, size=batch)
+        rc = rng.random(batch) < 0.5
+        rates = rng.uniform(rate_lo, rate_hi, size=batch)
+        parts = [cons_rc[i] if r else cons[i] for i, r in zip(ids.tolist(), rc.tolist())]
+        src = np.concatenate(parts)
+        L = clen[ids]
+        ends = np.cumsum(L)
+        seg_end = np.repeat(ends, L)
+        res, offs = mutate_many(rng, src, seg_end, np.repeat(rates, L))
+        starts_in = ends - L
+        ob = offs[starts_in]
+        oe = offs[ends]
+        gpos = rng.integers(0, total, size=batch)
+        seq_idx = np.searchsorted(cum, gpos, side="right")
+        for t in range(batch):
+            sidx = int(seq_idx[t])
+            b = int(gpos[t]) - (int(cum[sidx - 1]) if sidx > 0 else 0)
+            e = min(len(seqs[sidx]), b + int(oe[t] - ob[t]))
+            if e <= b:
+                continue
+            seqs[sidx][b:e] = res[ob[t]:ob[t] + (e - b)]
+            seg = lower[sidx][b:e]
+            n_lower += int(e - b - np.count_nonzero(seg))
+            seg[:] = True
+            if n_lower >= target:
+                break
+    return n_lower / total
+
+
 def _add_gaps(rng, seqs, n_per_seq, gap_len, avoid_sets, writes):
     """Write ``n_per_seq`` runs of N per sequence.  Each run avoids the first
     interval set in ``avoid_sets`` where it fits (then the next, looser one),
@@ -444,8 +544,8 @@ def config5(seed: int = 5, total: int = 3_100_000_000, n_seq: int = 24) -> Genom
     raw = rng.uniform(50e6, 250e6, size=n_seq)
     lens = np.floor(raw / raw.sum() * total).astype(np.int64)
     lens[-1] += total - int(lens.sum())
-    seqs = [random_bases(rng, int(x), gc=0.41) for x in lens]
-    _mask_repeats(rng, seqs, 0.50, 0.41, batch=4096)
+    seqs = [random_bases(rng, int(x), gc=0.41, byte_lut=True) for x in lens]
+    _mask_repeats_batched(rng, seqs, 0.50, 0.41)
     truth, writes, occ = [], [], _Disjoint(len(seqs))
     target = 0.05 * total
     _plant_sds(rng, seqs, None, lambda: _loguniform_int(rng, 1000, 300_000),

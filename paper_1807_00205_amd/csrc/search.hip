@@ -64,6 +64,9 @@ struct TileLds {
     uint16_t win_T[CMAX];
     uint16_t win_qend[CMAX];
     uint16_t win_s[CMAX];
+    uint16_t qT[QCAP];       // smallest threshold among the windows holding q (0xFFFF: none)
+    uint32_t Tblk[CMAX / 32];     // smallest threshold per 32 window starts
+    uint32_t ndup;
     RunState run[CMAX][2];
     union {  // bin table in the gather passes; scratch and seed buffers after
         uint32_t table[TWORDS];
@@ -252,6 +255,16 @@ __device__ __forceinline__ uint32_t ck_p(uint64_t k) { return (uint32_t)(k >> 11
 __device__ __forceinline__ uint32_t ck_q(uint64_t k) { return (uint32_t)(k & 2047); }
 __device__ __forceinline__ uint64_t ck_op(uint64_t k) { return k >> 11; }
 
+// Largest l in [lo, hi) with hoff[l] <= e (hoff[lo] <= e < hoff[hi]).
+__device__ __forceinline__ uint32_t list_of_from(const uint32_t *hoff, uint32_t lo, uint32_t hi,
+                                                 uint32_t e) {
+    while (hi - lo > 1) {
+        uint32_t m = (lo + hi) >> 1;
+        if (hoff[m] <= e) lo = m; else hi = m;
+    }
+    return lo;
+}
+
 // Find the list of hit e: largest l with hoff[l] <= e.
 __device__ __forceinline__ uint32_t list_of(const uint32_t *hoff, uint32_t nl, uint32_t e) {
     uint32_t lo = 0, hi = nl;  // invariant hoff[lo] <= e < hoff[hi]
@@ -260,6 +273,33 @@ __device__ __forceinline__ uint32_t list_of(const uint32_t *hoff, uint32_t nl, u
         if (hoff[m] <= e) lo = m; else hi = m;
     }
     return lo;
+}
+
+// Hits [cb, cb + 64 * HU) of the tile in lane-interleaved order: lv = list
+// (2q + strand) or NONE32 past the end, pv = target position.  The lists of
+// the block's first and last hit bound each lane's list search, and every
+// position load is issued before any is used.
+constexpr int HU = 8;
+__device__ __forceinline__ void gather_hits(const TileLds &L, const IndexView &ix, uint32_t nl,
+                                            uint32_t H, uint32_t cb, uint32_t lane,
+                                            uint32_t (&pv)[HU], uint32_t (&lv)[HU]) {
+#pragma unroll
+    for (int u = 0; u < HU; u++) {
+        pv[u] = 0;
+        lv[u] = NONE32;
+    }
+    if (cb >= H) return;
+    const uint32_t l0 = list_of(L.hoff, nl, cb);
+    const uint32_t l1 = list_of_from(L.hoff, l0, nl, min(cb + 64 * HU - 1, H - 1));
+#pragma unroll
+    for (int u = 0; u < HU; u++) {
+        const uint32_t e = cb + (uint32_t)u * 64 + lane;
+        if (e < H) {
+            const uint32_t l = (l1 > l0) ? list_of_from(L.hoff, l0, l1 + 1, e) : l0;
+            lv[u] = l;
+            pv[u] = ix.epos[L.lst_lo[l] + (e - L.hoff[l])];
+        }
+    }
 }
 
 // ------------------------------------------------------------ tile kernel --
@@ -445,35 +485,69 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                 L.win_T[qc] = w ? 1 : 0;  // finished below
             }
             __syncthreads();
+            // minimizers whose hash repeats earlier in the tile (usually few)
+            uint16_t *dups = reinterpret_cast<uint16_t *>(L.u.table);
+            if (threadIdx.x == 0) L.ndup = 0;
+            if (threadIdx.x < CMAX / 32) L.Tblk[threadIdx.x] = 0xFFFFu;
+            __syncthreads();
             for (uint32_t q = threadIdx.x; q < Q; q += TB) {
                 int r = (int)q;
                 while (L.qprev[r] >= 0) r = L.qprev[r];
                 L.qroot[q] = (uint16_t)r;
                 if (r != (int)q && (L.qfl[q] & 2)) L.dup = 1;
+                if (L.qprev[q] >= 0) dups[atomicAdd(&L.ndup, 1u)] = (uint16_t)q;
             }
+            __syncthreads();
+            const uint32_t ndup = L.ndup;
             for (uint32_t qc = threadIdx.x; qc < C; qc += TB) {
-                uint16_t T = 0, qend = 0, s = 0;
+                uint16_t T = 0, s = 0;
+                // last minimizer inside [pos, pos + n): for every core entry
+                const uint64_t lim = (uint64_t)L.qpos[qc] + n - k;
+                uint32_t lo = qc, hi = Q;
+                while (lo < hi) {
+                    uint32_t m = (lo + hi) >> 1;
+                    if ((uint64_t)L.qpos[m] <= lim) lo = m + 1; else hi = m;
+                }
                 if (L.win_T[qc]) {
-                    const uint64_t lim = (uint64_t)L.qpos[qc] + n - k;
-                    uint32_t lo = qc, hi = Q;
-                    while (lo < hi) {
-                        uint32_t m = (lo + hi) >> 1;
-                        if ((uint64_t)L.qpos[m] <= lim) lo = m + 1; else hi = m;
+                    // s_i: distinct hashes among all minimizers of the window =
+                    // all of them minus those repeating a hash already inside
+                    uint32_t cnt = lo - qc;
+                    if (ndup <= 256) {
+                        for (uint32_t d = 0; d < ndup; d++) {
+                            const uint32_t q = dups[d];
+                            if (q >= qc && q < lo && L.qprev[q] >= (int)qc) cnt--;
+                        }
+                    } else {
+                        cnt = 0;
+                        for (uint32_t q = qc; q < lo; q++) cnt += (L.qprev[q] < (int)qc) ? 1u : 0u;
                     }
-                    qend = (uint16_t)lo;
-                    // s_i: distinct hashes among all minimizers of the window
-                    uint32_t cnt = 0;
-                    for (uint32_t q = qc; q < lo; q++) cnt += (L.qprev[q] < (int)qc) ? 1u : 0u;
                     s = (uint16_t)cnt;
                     T = a.T[cnt];
                     atomicMin(&L.Tmin, (uint32_t)T);
                     atomicAdd(&L.nwin, 1u);
+                    atomicMin(&L.Tblk[qc >> 5], (uint32_t)T);
                 }
                 L.win_T[qc] = T;
-                L.win_qend[qc] = qend;
+                L.win_qend[qc] = (uint16_t)lo;
                 L.win_s[qc] = s;
                 L.run[qc][0] = RunState{NONE32, 0, 0, 0, 0};
                 L.run[qc][1] = RunState{NONE32, 0, 0, 0, 0};
+            }
+            __syncthreads();
+            // per query minimizer: the smallest threshold of the windows that
+            // hold it, bounded by the minima of the 32-entry blocks covering
+            // those windows (lossless: never above the true minimum)
+            for (uint32_t q = threadIdx.x; q < Q; q += TB) {
+                uint32_t lo = 0, hi = C;  // first core entry whose window reaches past q
+                while (lo < hi) {
+                    uint32_t m = (lo + hi) >> 1;
+                    if (L.win_qend[m] <= q) lo = m + 1; else hi = m;
+                }
+                const uint32_t last = q < C ? q : C - 1;
+                uint32_t t = 0xFFFFu;
+                if (lo <= last)
+                    for (uint32_t b = lo >> 5; b <= (last >> 5); b++) t = min(t, L.Tblk[b]);
+                L.qT[q] = (uint16_t)t;
             }
             __syncthreads();
             PHASE(PH_QUERY);
@@ -491,7 +565,7 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
             for (uint32_t l = threadIdx.x; l < nl; l += TB) {
                 const uint32_t q = l >> 1, b = l & 1;
                 uint32_t lo = 0, hi = 0;
-                if (L.qfl[q] & 2) lookup(ix, L.qhash[q], b, lo, hi);
+                if ((L.qfl[q] & 2) && L.qT[q] != 0xFFFFu) lookup(ix, L.qhash[q], b, lo, hi);
                 L.lst_lo[l] = lo;
                 L.hoff[l] = hi - lo;
             }
@@ -524,7 +598,7 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                     for (uint32_t l = threadIdx.x; l < nl; l += TB) {
                         const uint32_t q = l >> 1, b = l & 1;
                         uint32_t lo = 0, hi = 0;
-                        if (L.qfl[q] & 2) {
+                        if ((L.qfl[q] & 2) && L.qT[q] != 0xFFFFu) {
                             lookup(ix, L.qhash[q], b, lo, hi);
                             if (!full) {
                                 uint32_t a0 = lower_pos(ix.epos, lo, hi, lo_pos);
@@ -566,32 +640,51 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                 for (uint32_t t = threadIdx.x; t < TWORDS; t += TB) L.u.table[t] = 0;
                 __syncthreads();
                 const uint32_t SB = a.bin_shift;
-                for (uint32_t e = threadIdx.x; e < H; e += TB) {
-                    const uint32_t l = list_of(L.hoff, nl, e);
-                    const uint32_t q = l >> 1, b = l & 1;
-                    const uint32_t p = ix.epos[L.lst_lo[l] + (e - L.hoff[l])];
-                    if (p == L.qpos[q]) continue;
-                    const uint32_t o = b ^ (L.qfl[q] & 1);
-                    const uint32_t slot = slot_of(p >> SB, o);
-                    atomicAdd(&L.u.table[slot >> 1], 1u << ((slot & 1) * 16));
+                // Each wave takes HU * 64 consecutive hits per round and issues
+                // all their position loads before using any, so a thread waits
+                // for memory once per round instead of once per hit.  The
+                // first round's hits stay in registers for pass 2.
+                for (uint32_t r0 = 0; r0 < H; r0 += TB * HU) {
+                    const uint32_t cb = r0 + (uint32_t)wave * 64 * HU;
+                    uint32_t pv[HU], lv[HU];
+                    gather_hits(L, ix, nl, H, cb, lane, pv, lv);
+#pragma unroll
+                    for (int u = 0; u < HU; u++) {
+                        if (lv[u] == NONE32) continue;
+                        const uint32_t q = lv[u] >> 1, b = lv[u] & 1;
+                        if (pv[u] == L.qpos[q]) {  // an occurrence never pairs with itself
+                            lv[u] = NONE32;
+                            continue;
+                        }
+                        const uint32_t o = b ^ (L.qfl[q] & 1);
+                        const uint32_t slot = slot_of(pv[u] >> SB, o);
+                        atomicAdd(&L.u.table[slot >> 1], 1u << ((slot & 1) * 16));
+                    }
                 }
                 __syncthreads();
                 PHASE(PH_PASS1);
                 // ---- pass 2: keep hits near bins that may be hot ----
-                for (uint32_t e = threadIdx.x; e < H; e += TB) {
-                    const uint32_t l = list_of(L.hoff, nl, e);
-                    const uint32_t q = l >> 1, b = l & 1;
-                    const uint32_t p = ix.epos[L.lst_lo[l] + (e - L.hoff[l])];
-                    if (p == L.qpos[q]) continue;
-                    const uint32_t o = b ^ (L.qfl[q] & 1);
-                    const uint32_t c = p >> SB;
-                    const uint32_t m2 = slot_count(L.u.table, slot_of(c - 2, o));
-                    const uint32_t m1 = slot_count(L.u.table, slot_of(c - 1, o));
-                    const uint32_t z0 = slot_count(L.u.table, slot_of(c, o));
-                    const uint32_t p1 = slot_count(L.u.table, slot_of(c + 1, o));
-                    if (m2 + m1 >= Tmin || m1 + z0 >= Tmin || z0 + p1 >= Tmin) {
-                        uint32_t idx = atomicAdd(&L.ncoll, 1u);
-                        if (idx < CB) L.coll[idx] = ckey(o, p, q);
+                for (uint32_t r0 = 0; r0 < H; r0 += TB * HU) {
+                    const uint32_t cb = r0 + (uint32_t)wave * 64 * HU;
+                    uint32_t pv[HU], lv[HU];
+                    gather_hits(L, ix, nl, H, cb, lane, pv, lv);
+#pragma unroll
+                    for (int u = 0; u < HU; u++) {
+                        if (lv[u] == NONE32) continue;
+                        const uint32_t q = lv[u] >> 1, b = lv[u] & 1;
+                        const uint32_t p = pv[u];
+                        if (p == L.qpos[q]) continue;
+                        const uint32_t Tq = L.qT[q];
+                        const uint32_t o = b ^ (L.qfl[q] & 1);
+                        const uint32_t c = p >> SB;
+                        const uint32_t m2 = slot_count(L.u.table, slot_of(c - 2, o));
+                        const uint32_t m1 = slot_count(L.u.table, slot_of(c - 1, o));
+                        const uint32_t z0 = slot_count(L.u.table, slot_of(c, o));
+                        const uint32_t p1 = slot_count(L.u.table, slot_of(c + 1, o));
+                        if (m2 + m1 >= Tq || m1 + z0 >= Tq || z0 + p1 >= Tq) {
+                            uint32_t idx = atomicAdd(&L.ncoll, 1u);
+                            if (idx < CB) L.coll[idx] = ckey(o, p, q);
+                        }
                     }
                 }
                 __syncthreads();

@@ -151,8 +151,11 @@ void sdf_index_free(sdf_index ix);
  * best target start of each run of consecutive passing targets; chains of
  * seeds become candidates.
  * Errors: SDF_EINVAL, SDF_ERANGE (span outside its sequence), SDF_ENOMEM,
- * SDF_EDEVICE, SDF_EINTERNAL.  A span shorter than n succeeds with no
- * candidates.  *out receives the result (NULL on failure).
+ * SDF_EDEVICE, SDF_EINTERNAL (a single window would keep more than 2,048
+ * hits, or have more than 65,535, within 4n target bases: an unmasked
+ * satellite far denser than soft-masked assemblies contain).  A span
+ * shorter than n succeeds with no candidates.  *out receives the result
+ * (NULL on failure).
  */
 sdf_status sdf_search(sdf_index ix, const sdf_span *q, const sdf_search_params *p,
                       void *hip_stream, sdf_result *out);

@@ -226,6 +226,7 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
         if (herr & 1) m += " a window reaches more minimizers than a tile holds;";
         if (herr & 2) m += " a dense target region keeps more hits than a tile holds;";
         if (herr & 4) m += " a dense target region has more than 65535 hits;";
+        if (herr & 8) m += " partition splitting ran out of stack;";
         throw Error{SDF_EINTERNAL, m};
     }
     if (phase_prof) {
@@ -240,7 +241,7 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
         fprintf(stderr, "[sdf phases, workgroup-ms summed]");
         for (int t = 0; t < PH_N; t++)
             fprintf(stderr, " %s=%.2f", names[t], khz ? (double)ph[t] / khz : 0.0);
-        fprintf(stderr, "\n");
+        fprintf(stderr, " dup_tiles=%llu\n", (unsigned long long)hc[CNT_DUP_TILES]);
     }
     res->nseeds = hc[CNT_SEEDS];
     res->stats[0] = hc[CNT_WINDOWS];

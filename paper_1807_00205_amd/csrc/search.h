@@ -12,7 +12,7 @@ struct SpanDesc {
 };
 
 enum { CNT_SEEDS = 0, CNT_WINDOWS, CNT_HITS, CNT_KEPT, CNT_PARTS, CNT_TILES, CNT_EVALS,
-       CNT_SCAN, CNT_N };
+       CNT_SCAN, CNT_DUP_TILES, CNT_N };
 
 struct SearchArgs {
     IndexView ix;

@@ -37,14 +37,19 @@ constexpr int TSLOT_BITS = 14;
 constexpr int SBUF = 32;        // seeds buffered per wave before one global atomic
 constexpr uint32_t HMAX = 65535;  // hits per partition (16-bit counters cannot overflow)
 constexpr int STACK = 40;
-constexpr int QW = QCAP / 64;     // bitmask words per wave
+constexpr int QW = QCAP / 64;     // 64-bit words of a bitmask over the query minimizers
 
 enum : uint32_t { EF_CAND = 1, EF_VALID = 2 };
+// Minimizers of one window that share hash and strand have the same hits
+// except each one's own position, so their union is the full list: the
+// first one stands for all of them with its self-hit kept (QM_UNION), the
+// others are left out (QM_SKIP).
+enum : uint8_t { QM_NORMAL = 0, QM_SKIP = 1, QM_UNION = 2 };
 enum : uint32_t {
     ERR_CORE = 1,      // one window alone reaches more than QCAP minimizers
-    ERR_COLLECT = 2,   // a minimal partition keeps more than CB hits
-    ERR_HITS = 4,      // a minimal partition has more than HMAX hits
-    ERR_STACK = 8
+    ERR_COLLECT = 2,   // one window keeps more than CB hits in 4n target bases
+    ERR_HITS = 4,      // one window has more than HMAX hits in 4n target bases
+    ERR_STACK = 8      // partition splits nested deeper than the stack
 };
 
 struct RunState {
@@ -59,6 +64,7 @@ struct TileLds {
     int16_t qprev[QCAP];
     uint16_t qroot[QCAP];
     uint8_t qfl[QCAP];
+    uint8_t qmode[QCAP];  // QM_* while a partition covers a single window
     uint32_t lst_lo[2 * QCAP];
     uint32_t hoff[2 * QCAP + 4];
     uint16_t win_T[CMAX];
@@ -77,8 +83,9 @@ struct TileLds {
     uint32_t eseq[CB];
     uint16_t rng_end[CB];
     uint8_t eflag[CB];
-    unsigned long long wbits[NWAVES][QW];
-    uint32_t stackA[STACK], stackB[STACK];
+    uint16_t prevx[CB];  // index + 1 of the hit that prevq describes (0: none)
+    unsigned long long qhas[2][QW];  // q has a relevant kept hit in orientation o
+    uint32_t stackA[STACK], stackB[STACK], stackW[STACK];  // W: first window | end << 16
     uint64_t wtmp[NWAVES + 1];
     uint64_t ph[PH_N];
     // scalars
@@ -91,6 +98,24 @@ struct TileLds {
 };
 
 // ----------------------------------------------------------- block helpers --
+constexpr int DPP_ROW_SHR = 0x110;      // + n: lane reads lane - n of its row of 16
+constexpr int DPP_WAVE_SHR1 = 0x138;    // lane reads lane - 1 of the wave
+constexpr int DPP_ROW_BCAST15 = 0x142;  // last lane of each row feeds the next row
+constexpr int DPP_ROW_BCAST31 = 0x143;  // lane 31 feeds rows 2 and 3
+
+// Inclusive max-scan over the 64 lanes of a wave with DPP moves: prefix
+// within each row of 16, then row 0 into row 1 and row 2 into row 3, then
+// rows 0-1 into rows 2-3.  Lanes with no source keep 0, the identity.
+__device__ __forceinline__ uint32_t wave_max_scan(uint32_t x) {
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, DPP_ROW_SHR + 1, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, DPP_ROW_SHR + 2, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, DPP_ROW_SHR + 4, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, DPP_ROW_SHR + 8, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, DPP_ROW_BCAST15, 0xa, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, DPP_ROW_BCAST31, 0xc, 0xf, false));
+    return x;
+}
+
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 
@@ -302,6 +327,26 @@ __device__ __forceinline__ void gather_hits(const TileLds &L, const IndexView &i
     }
 }
 
+// Push the halves of an over-full partition [A, B) x windows [WA, WB): by
+// target while it spans more than 4n bases, else by window starts; the
+// lower half goes on top.  Sets `err` when neither split is possible.
+__device__ __forceinline__ void split_partition(TileLds &L, uint32_t A, uint32_t B, uint32_t WA,
+                                                uint32_t WB, uint32_t n, uint32_t err) {
+    if (L.sp + 2 > STACK) {
+        L.err |= ERR_STACK;
+    } else if ((uint64_t)B - A > 4ull * n) {
+        const uint32_t mid = A + (B - A) / 2, W = WA | (WB << 16);
+        L.stackA[L.sp] = mid; L.stackB[L.sp] = B; L.stackW[L.sp] = W; L.sp++;
+        L.stackA[L.sp] = A; L.stackB[L.sp] = mid; L.stackW[L.sp] = W; L.sp++;
+    } else if (WB - WA > 1) {
+        const uint32_t mid = WA + (WB - WA) / 2;
+        L.stackA[L.sp] = A; L.stackB[L.sp] = B; L.stackW[L.sp] = mid | (WB << 16); L.sp++;
+        L.stackA[L.sp] = A; L.stackB[L.sp] = B; L.stackW[L.sp] = WA | (mid << 16); L.sp++;
+    } else {
+        L.err |= err;
+    }
+}
+
 // ------------------------------------------------------------ tile kernel --
 // Optional phase breakdown: thread 0 reads the wall clock after the barrier
 // that ends each phase and accumulates the difference.
@@ -388,7 +433,6 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
     if (threadIdx.x < PH_N) L.ph[threadIdx.x] = 0;
     uint64_t ph_t = prof ? wall_clock64() : 0;
     // per-wave bitmasks start empty; each use clears the words it counted
-    for (uint32_t t = threadIdx.x; t < NWAVES * QW; t += TB) (&L.wbits[0][0])[t] = 0;
     uint32_t span_cache = 0;  // thread 0: span of the previous tile
     __syncthreads();
 
@@ -474,6 +518,7 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                 const uint32_t m = c0 + q;
                 L.qhash[q] = ix.mhash[m];
                 L.qfl[q] = ix.mflags[m];
+                L.qmode[q] = QM_NORMAL;
                 const uint32_t pg = ix.mprev[m];
                 L.qprev[q] = (pg != NONE32 && pg >= c0) ? (int16_t)(pg - c0) : (int16_t)-1;
             }
@@ -556,7 +601,10 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                 __syncthreads();
                 continue;
             }
-            if (threadIdx.x == 0) atomicAdd(&a.counters[CNT_WINDOWS], (unsigned long long)L.nwin);
+            if (threadIdx.x == 0) {
+                atomicAdd(&a.counters[CNT_WINDOWS], (unsigned long long)L.nwin);
+                if (L.dup) atomicAdd(&a.counters[CNT_DUP_TILES], 1ull);
+            }
             const uint32_t Tmin = L.Tmin;
             const bool dup = L.dup != 0;
 
@@ -575,30 +623,66 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
             uint32_t P = (Hfull + a.hpart - 1) / a.hpart;
             if (P < 1) P = 1;
             bool lists_full = true;  // lst_lo/hoff hold the full lists
+            bool modes_set = false;  // some qmode differs from QM_NORMAL
             // Target partitions in increasing order; a partition with too many
             // hits or kept hits is split in halves on a small stack (LIFO,
             // left half first, so candidates still arrive in target order).
+            // A partition already down to 4n bases is split over its window
+            // starts instead: each window keeps its own run state, so any
+            // grouping of windows sees its candidates in target order.
             for (uint32_t pt = 0; pt < P; pt++) {
             if (threadIdx.x == 0) {
                 L.sp = 1;
                 L.stackA[0] = (uint32_t)((ix.total * (uint64_t)pt) / P);
                 L.stackB[0] = (uint32_t)((ix.total * (uint64_t)(pt + 1)) / P);
+                L.stackW[0] = C << 16;
             }
             for (;;) {
                 __syncthreads();
                 if (L.sp == 0) break;
                 const uint32_t A = L.stackA[L.sp - 1], B = L.stackB[L.sp - 1];
+                const uint32_t WA = L.stackW[L.sp - 1] & 0xFFFFu, WB = L.stackW[L.sp - 1] >> 16;
                 __syncthreads();
                 if (threadIdx.x == 0) L.sp--;
                 const bool full = (A == 0 && (uint64_t)B >= ix.total);
+                const bool allw = (WA == 0 && WB == C);
+                const bool single_dup = dup && WB - WA == 1;
+                const uint32_t QE = L.win_qend[WB - 1];  // minimizers [WA, QE) of the windows
                 const uint64_t lo_pos = (A > n) ? (uint64_t)A - n : 0;
                 const uint64_t hi_pos = (uint64_t)B + 2ull * n;  // exclusive
-                // ---- lists restricted to [A - n, B + 2n) ----
-                if (!(full && lists_full)) {
+                // ---- lists restricted to [A - n, B + 2n) and the windows' minimizers ----
+                if (single_dup) {
+                    for (uint32_t q = threadIdx.x; q < Q; q += TB) {
+                        uint8_t m = QM_NORMAL;
+                        if (q >= WA && q < QE && (L.qfl[q] & 2))
+                            for (int r = L.qprev[q]; r >= (int)WA; r = L.qprev[r])
+                                if ((L.qfl[r] & 2) && ((L.qfl[r] ^ L.qfl[q]) & 1) == 0) {
+                                    m = QM_SKIP;
+                                    break;
+                                }
+                        L.qmode[q] = m;
+                    }
+                    __syncthreads();
+                    for (uint32_t q = threadIdx.x; q < Q; q += TB) {
+                        if (L.qmode[q] != QM_SKIP) continue;
+                        int first = -1;  // earliest member in the window
+                        for (int r = L.qprev[q]; r >= (int)WA; r = L.qprev[r])
+                            if ((L.qfl[r] & 2) && ((L.qfl[r] ^ L.qfl[q]) & 1) == 0) first = r;
+                        L.qmode[first] = QM_UNION;
+                    }
+                    __syncthreads();
+                    modes_set = true;
+                } else if (modes_set) {
+                    for (uint32_t q = threadIdx.x; q < Q; q += TB) L.qmode[q] = QM_NORMAL;
+                    __syncthreads();
+                    modes_set = false;
+                }
+                if (!(full && allw && lists_full && !single_dup)) {
                     for (uint32_t l = threadIdx.x; l < nl; l += TB) {
                         const uint32_t q = l >> 1, b = l & 1;
                         uint32_t lo = 0, hi = 0;
-                        if ((L.qfl[q] & 2) && L.qT[q] != 0xFFFFu) {
+                        if ((L.qfl[q] & 2) && L.qT[q] != 0xFFFFu && q >= WA && q < QE &&
+                            L.qmode[q] != QM_SKIP) {
                             lookup(ix, L.qhash[q], b, lo, hi);
                             if (!full) {
                                 uint32_t a0 = lower_pos(ix.epos, lo, hi, lo_pos);
@@ -612,21 +696,13 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                     }
                     __syncthreads();
                     block_scan_u32(L.hoff, (int)nl, L.wtmp);
-                    lists_full = full;
+                    lists_full = full && allw && !single_dup;
                 }
                 PHASE(PH_PLISTS);
                 const uint32_t H = L.hoff[nl];
                 if (H == 0) continue;
                 if (H > HMAX) {
-                    if (threadIdx.x == 0) {
-                        if ((uint64_t)B - A > 4ull * n && L.sp + 2 <= STACK) {
-                            uint32_t mid = A + (B - A) / 2;
-                            L.stackA[L.sp] = mid; L.stackB[L.sp] = B; L.sp++;
-                            L.stackA[L.sp] = A; L.stackB[L.sp] = mid; L.sp++;
-                        } else {
-                            L.err |= ERR_HITS;
-                        }
-                    }
+                    if (threadIdx.x == 0) split_partition(L, A, B, WA, WB, n, ERR_HITS);
                     __syncthreads();
                     if (L.err) break;
                     continue;
@@ -638,6 +714,7 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                 }
                 // ---- pass 1: bin counts ----
                 for (uint32_t t = threadIdx.x; t < TWORDS; t += TB) L.u.table[t] = 0;
+                if (threadIdx.x < 2 * QW) (&L.qhas[0][0])[threadIdx.x] = 0;
                 __syncthreads();
                 const uint32_t SB = a.bin_shift;
                 // Each wave takes HU * 64 consecutive hits per round and issues
@@ -652,7 +729,7 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                     for (int u = 0; u < HU; u++) {
                         if (lv[u] == NONE32) continue;
                         const uint32_t q = lv[u] >> 1, b = lv[u] & 1;
-                        if (pv[u] == L.qpos[q]) {  // an occurrence never pairs with itself
+                        if (pv[u] == L.qpos[q] && L.qmode[q] != QM_UNION) {  // never with itself
                             lv[u] = NONE32;
                             continue;
                         }
@@ -673,7 +750,7 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                         if (lv[u] == NONE32) continue;
                         const uint32_t q = lv[u] >> 1, b = lv[u] & 1;
                         const uint32_t p = pv[u];
-                        if (p == L.qpos[q]) continue;
+                        if (p == L.qpos[q] && L.qmode[q] != QM_UNION) continue;
                         const uint32_t Tq = L.qT[q];
                         const uint32_t o = b ^ (L.qfl[q] & 1);
                         const uint32_t c = p >> SB;
@@ -692,15 +769,7 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                 const uint32_t ncoll = L.ncoll;
                 if (ncoll == 0) continue;
                 if (ncoll > CB) {
-                    if (threadIdx.x == 0) {
-                        if ((uint64_t)B - A > 4ull * n && L.sp + 2 <= STACK) {
-                            uint32_t mid = A + (B - A) / 2;
-                            L.stackA[L.sp] = mid; L.stackB[L.sp] = B; L.sp++;
-                            L.stackA[L.sp] = A; L.stackB[L.sp] = mid; L.sp++;
-                        } else {
-                            L.err |= ERR_COLLECT;
-                        }
-                    }
+                    if (threadIdx.x == 0) split_partition(L, A, B, WA, WB, n, ERR_COLLECT);
                     __syncthreads();
                     if (L.err) break;
                     continue;
@@ -796,17 +865,24 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                         if ((uint64_t)ck_p(L.coll[m]) <= lim) lo = m + 1; else hi = m;
                     }
                     L.rng_end[e] = (uint16_t)lo;
-                    // nearest earlier hit of the same query minimizer within n - k
-                    uint32_t pv = 0;
+                    atomicOr(&L.qhas[o][q >> 6], 1ull << (q & 63));
+                    // nearest earlier hit within n - k of the same hash: of the
+                    // same query minimizer unless the tile repeats hashes, then
+                    // of any minimizer with the same root
+                    const uint32_t rq = dup ? L.qroot[q] : q;
+                    uint32_t pv = 0, px = 0;
                     for (int f = (int)e - 1; f >= (int)L.obeg[o]; f--) {
                         const uint64_t kf = L.coll[f];
                         if ((uint64_t)ck_p(kf) + n - k < p) break;
-                        if (ck_q(kf) == q) {
+                        const uint32_t qf = ck_q(kf);
+                        if ((dup ? L.qroot[qf] : qf) == rq) {
                             pv = ck_p(kf) + 1;
+                            px = (uint32_t)f + 1;
                             break;
                         }
                     }
                     L.prevq[e] = pv;
+                    L.prevx[e] = (uint16_t)px;
                     if ((L.eflag[e] & EF_CAND) && p >= A && p < B) {
                         uint32_t sq = 0;
                         if (window_ok(ix, p, n, &sq)) L.eflag[e] |= EF_VALID;
@@ -833,11 +909,9 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                 uint64_t *inw = L.u.scratch + (NWAVES * SBUF * 6 + NWAVES * 128) / 2 +
                                 wave * (2 * (CB / 64));
                 uint64_t *dupw = inw + CB / 64;
-                unsigned long long *bits = L.wbits[wave];
-                const uint32_t nwords = (Q + 63) >> 6;
                 const uint64_t ltmask = lane ? (~0ull >> (64 - lane)) : 0ull;
                 uint32_t n_evals = 0, n_scan = 0;
-                for (uint32_t qc = wave; qc < C; qc += NWAVES) {
+                for (uint32_t qc = WA + wave; qc < WB; qc += NWAVES) {
                     const uint32_t Ti = L.win_T[qc];
                     if (Ti == 0) continue;
                     const uint32_t i = L.qpos[qc];
@@ -845,6 +919,21 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                     for (uint32_t o = 0; o < 2; o++) {
                         const uint32_t ob = L.obeg[o], oe = L.oend[o];
                         if (ob >= oe) continue;
+                        RunState rs = L.run[qc][o];
+                        if (!rs.active) {
+                            // no candidate can pass when fewer minimizers of the
+                            // window have any kept hit than the threshold, and
+                            // with no open run nothing else changes
+                            const uint32_t w0 = qc >> 6, w1 = (qe - 1) >> 6;
+                            uint32_t nq = 0;
+                            for (uint32_t x = w0; x <= w1; x++) {
+                                uint64_t m = L.qhas[o][x];
+                                if (x == w0) m &= ~0ull << (qc & 63);
+                                if (x == w1 && (qe & 63)) m &= (1ull << (qe & 63)) - 1;
+                                nq += (uint32_t)__popcll(m);
+                            }
+                            if (nq < Ti) continue;
+                        }
                         const uint32_t wb = ob >> 6, we = (oe + 63) >> 6;
                         n_scan += we - wb;
                         // membership bitmasks over the orientation's kept hits
@@ -854,7 +943,25 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                             if (e >= ob && e < oe) {
                                 const uint32_t q = ck_q(L.coll[e]);
                                 in = q >= qc && q < qe;
-                                dp = in && L.prevq[e] != 0;
+                                if (in && L.prevx[e]) {
+                                    if (!dup) {
+                                        dp = true;  // same minimizer: in the window too
+                                    } else {
+                                        // walk earlier hits of the same hash for one
+                                        // of a minimizer inside the window
+                                        const uint32_t pe = ck_p(L.coll[e]);
+                                        for (uint32_t g = L.prevx[e]; g;) {
+                                            const uint64_t kg = L.coll[g - 1];
+                                            if ((uint64_t)ck_p(kg) + n - k < pe) break;
+                                            const uint32_t qg = ck_q(kg);
+                                            if (qg >= qc && qg < qe) {
+                                                dp = true;
+                                                break;
+                                            }
+                                            g = L.prevx[g - 1];
+                                        }
+                                    }
+                                }
                             }
                             const uint64_t mi = __ballot(in), md = __ballot(dp);
                             if (lane == 0) {
@@ -863,7 +970,6 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                             }
                         }
                         __builtin_amdgcn_wave_barrier();
-                        RunState rs = L.run[qc][o];
                         uint32_t nc = 0;
                         for (uint32_t w = wb; w < we; w++) {
                             const uint32_t e = w * 64 + lane;
@@ -890,45 +996,35 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                                     j = ck_p(L.coll[ec]);
                                     tseq = L.eseq[ec];
                                 }
-                                if (!dup) {
-                                    if ((uint32_t)lane < nb) {
-                                        const uint32_t re = L.rng_end[ec];  // > ec
-                                        const uint32_t w0 = ec >> 6, w1 = (re - 1) >> 6;
-                                        for (uint32_t x = w0; x <= w1; x++) {
-                                            uint64_t m = inw[x], d = dupw[x];
-                                            uint64_t keep = ~0ull;
-                                            if (x == w0) keep &= ~0ull << (ec & 63);
-                                            if (x == w1 && (re & 63)) keep &= (1ull << (re & 63)) - 1;
-                                            cnt += (uint32_t)__popcll(m & keep);
-                                            d &= keep;
-                                            while (d) {
-                                                const uint32_t f = x * 64 + (__ffsll((long long)d) - 1);
-                                                d &= d - 1;
+                                if ((uint32_t)lane < nb) {
+                                    const uint32_t re = L.rng_end[ec];  // > ec
+                                    const uint32_t w0 = ec >> 6, w1 = (re - 1) >> 6;
+                                    for (uint32_t x = w0; x <= w1; x++) {
+                                        uint64_t m = inw[x], d = dupw[x];
+                                        uint64_t keep = ~0ull;
+                                        if (x == w0) keep &= ~0ull << (ec & 63);
+                                        if (x == w1 && (re & 63)) keep &= (1ull << (re & 63)) - 1;
+                                        cnt += (uint32_t)__popcll(m & keep);
+                                        d &= keep;
+                                        while (d) {
+                                            const uint32_t f = x * 64 + (__ffsll((long long)d) - 1);
+                                            d &= d - 1;
+                                            if (!dup) {
                                                 if (L.prevq[f] - 1 >= j) cnt--;  // earlier hit in range
+                                            } else {
+                                                // nearest earlier same-hash hit of the window
+                                                for (uint32_t g = L.prevx[f]; g;) {
+                                                    const uint64_t kg = L.coll[g - 1];
+                                                    if (ck_p(kg) < j) break;
+                                                    const uint32_t qg = ck_q(kg);
+                                                    if (qg >= qc && qg < qe) {
+                                                        cnt--;
+                                                        break;
+                                                    }
+                                                    g = L.prevx[g - 1];
+                                                }
                                             }
                                         }
-                                    }
-                                } else {
-                                    // repeated hashes in the tile: distinct roots via a bitmask
-                                    for (uint32_t t = 0; t < nb; t++) {
-                                        const uint32_t et = (uint32_t)__builtin_amdgcn_readlane((int)ec, (int)t);
-                                        const uint32_t rt = L.rng_end[et];
-                                        for (uint32_t f = et + lane; f < rt; f += 64) {
-                                            const uint32_t q = ck_q(L.coll[f]);
-                                            if (q >= qc && q < qe) {
-                                                const uint32_t r = L.qroot[q];
-                                                atomicOr(&bits[r >> 6], 1ull << (r & 63));
-                                            }
-                                        }
-                                        __builtin_amdgcn_wave_barrier();
-                                        uint32_t c = 0;
-                                        if ((uint32_t)lane < nwords) {
-                                            c = (uint32_t)__popcll(bits[lane]);
-                                            bits[lane] = 0;
-                                        }
-                                        for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
-                                        __builtin_amdgcn_wave_barrier();
-                                        if ((uint32_t)lane == t) cnt = c;
                                     }
                                 }
                                 // run logic over the batch (lane t = t-th candidate in
@@ -943,46 +1039,52 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                                     excl = dd < n && (n - dd) > a.max_overlap;
                                 }
                                 const bool pass = act && cnt >= Ti && !excl;
-                                uint32_t pj = __shfl_up(j, 1, 64), ps = __shfl_up(tseq, 1, 64);
-                                bool ppass = __shfl_up((int)pass, 1, 64) != 0;
+                                // previous candidate: whole-wave shift right by one lane
+                                uint32_t pj = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)j, DPP_WAVE_SHR1, 0xf, 0xf, false);
+                                uint32_t ps = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)tseq, DPP_WAVE_SHR1, 0xf, 0xf, false);
+                                const uint64_t pb = __ballot(pass);
+                                bool ppass = lane ? ((pb >> (lane - 1)) & 1) != 0 : false;
                                 if (lane == 0) {
                                     pj = rs.prev_j;
                                     ps = rs.prev_seq;
                                     ppass = rs.active != 0;
                                 }
                                 const bool link = pass && ppass && tseq == ps && j - pj < n;
-                                uint64_t key = pass ? (((uint64_t)cnt << 32) | (uint32_t)~j) : 0ull;
-                                if (lane == 0 && link)
-                                    key = max(key, ((uint64_t)rs.best_c << 32) | (uint32_t)~rs.best_j);
-                                bool flag = !link;  // segment head (or not passing)
-                                for (int d = 1; d < 64; d <<= 1) {
-                                    const uint64_t y = __shfl_up(key, d, 64);
-                                    const bool fy = __shfl_up((int)flag, d, 64) != 0;
-                                    if (lane >= d && !flag) {
-                                        key = max(key, y);
-                                        flag = fy;
-                                    }
-                                }
+                                // One 32-bit key per lane: run number (runs start where
+                                // a candidate does not link), count, and 127 - slot with
+                                // slot 0 the open run carried in and lane t in slot t + 1,
+                                // so a plain max-scan gives each run's largest count,
+                                // earliest candidate on ties.
+                                const uint64_t lb = __ballot(link);
+                                const uint64_t heads = ~lb;
+                                const uint32_t run_no = (uint32_t)__popcll(heads & (ltmask | (1ull << lane)));
+                                uint32_t key = pass ? ((cnt << 7) | (126u - (uint32_t)lane)) : 0u;
+                                if (lane == 0 && link) key = max(key, ((uint32_t)rs.best_c << 7) | 127u);
+                                key = wave_max_scan((run_no << 18) | key);
+                                const uint32_t kslot = 127u - (key & 127u);
+                                const uint32_t kc = (key >> 7) & 2047u;
+                                const uint32_t kj = (uint32_t)__shfl((int)j, (int)((kslot - 1) & 63), 64);
+                                const uint32_t kbest_j = kslot ? kj : rs.best_j;
                                 // the run open before this batch ends unless lane 0 links
-                                const bool link0 = __shfl((int)link, 0, 64) != 0;
+                                const bool link0 = (lb & 1ull) != 0;
                                 seeds_push_lanes(a, sbuf, lane, lane == 0 && rs.active && !link0,
                                                  L.qid, i, rs.best_j, o, rs.best_c, L.win_s[qc]);
                                 // runs that end inside the batch
-                                const bool link_next = __shfl_down((int)link, 1, 64) != 0;
+                                const bool link_next = lane < 63 && ((lb >> (lane + 1)) & 1) != 0;
                                 const bool ends = pass && (uint32_t)lane + 1 < nb && !link_next;
-                                seeds_push_lanes(a, sbuf, lane, ends, L.qid, i, ~(uint32_t)key, o,
-                                                 (uint32_t)(key >> 32), L.win_s[qc]);
+                                seeds_push_lanes(a, sbuf, lane, ends, L.qid, i, kbest_j, o, kc,
+                                                 L.win_s[qc]);
                                 // carry the state after the last candidate
                                 const uint32_t tl = nb - 1;
-                                const bool pl = __builtin_amdgcn_readlane((int)pass, (int)tl) != 0;
-                                const uint64_t kl = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(key >> 32), (int)tl) << 32) |
-                                                    (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)key, (int)tl);
+                                const bool pl = ((pb >> tl) & 1) != 0;
+                                const uint32_t last_best_j = (uint32_t)__builtin_amdgcn_readlane((int)kbest_j, (int)tl);
+                                const uint32_t last_c = (uint32_t)__builtin_amdgcn_readlane((int)kc, (int)tl);
                                 rs.prev_j = (uint32_t)__builtin_amdgcn_readlane((int)j, (int)tl);
                                 rs.prev_seq = (uint32_t)__builtin_amdgcn_readlane((int)tseq, (int)tl);
                                 rs.active = pl ? 1 : 0;
                                 if (pl) {
-                                    rs.best_c = (uint16_t)(kl >> 32);
-                                    rs.best_j = ~(uint32_t)kl;
+                                    rs.best_c = (uint16_t)last_c;
+                                    rs.best_j = last_best_j;
                                 }
                                 // keep the candidates beyond this batch
                                 __builtin_amdgcn_wave_barrier();

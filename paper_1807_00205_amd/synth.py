@@ -585,3 +585,28 @@ def small_case(seed: int, length: int = 20_000, n_sd: int = 3, sd_lo: int = 1000
     _finish_intact(truth, writes)
     spans = [(i, 0, len(s)) for i, s in enumerate(seqs)]
     return Genome(seqs, truth, spans, f"small{seed}")
+
+
+def tandem_case(seed: int, length: int = 20_000, n_arrays: int = 12, unit_lo: int = 3,
+                unit_hi: int = 60, copies_lo: int = 4, copies_hi: int = 40,
+                rate: float = 0.03, n_sd: int = 2, n_seqs: int = 1,
+                lower_frac: float = 0.1) -> Genome:
+    """small_case plus tandem arrays (a unit of 3-60 bases repeated 4-40 times
+    with point mutations, every other array reverse-complemented, some copied
+    to a second place): windows full of repeated hashes."""
+    g = small_case(seed, length=length, n_sd=n_sd, sd_lo=300, sd_hi=800, n_seqs=n_seqs,
+                   lower_frac=lower_frac)
+    rng = rng_for(seed + 7919)
+    for a in range(n_arrays):
+        t = int(rng.integers(0, len(g.seqs)))
+        s = g.seqs[t]
+        unit = random_bases(rng, int(rng.integers(unit_lo, unit_hi + 1)))
+        arr = np.tile(unit, int(rng.integers(copies_lo, copies_hi + 1)))
+        arr = mutate(rng, arr, rate)[: max(1, len(s) // 4)]
+        if a % 2:
+            arr = revcomp(arr)
+        for _ in range(1 + (a % 3 == 0)):
+            b = int(rng.integers(0, max(1, len(s) - len(arr))))
+            s[b:b + len(arr)] = arr[: len(s) - b]
+    return Genome(g.seqs, g.truth, [(i, 0, len(x)) for i, x in enumerate(g.seqs)],
+                  "tandem%d" % seed)

@@ -126,6 +126,25 @@ def test_search_small(S, oracle_lib, case, max_error, min_len, k, w):
     _same(r.candidates(), oc, CAND_F, "candidates")
 
 
+@pytest.mark.parametrize("seed,length,n_seqs", [(1, 3000, 1), (2, 3000, 2), (3, 200_000, 3)])
+@pytest.mark.parametrize("max_error,min_len,k,w", [(0.25, 200, 12, 16), (0.3, 120, 9, 5),
+                                                   (0.25, 1000, 12, 16)])
+def test_search_tandem(S, oracle_lib, seed, length, n_seqs, max_error, min_len, k, w):
+    """Tiles whose windows repeat hashes (tandem arrays on both strands):
+    distinct-hash counts, seeds and candidates equal the oracle's."""
+    g = synth.tandem_case(90 + seed, length=length, n_arrays=5 if length < 10000 else 120,
+                          copies_hi=20 if length < 10000 else 60, n_seqs=n_seqs)
+    b, off = g.concat()
+    spans = list(g.spans) + [(0, 200, len(g.seqs[0]) - 300)]
+    orc = oracle_lib.OracleIndex(b, off, k, w)
+    os_, oc = orc.search(spans, max_error, min_len)
+    ix = S.Index(g.seqs, k, w)
+    r = ix.search_batch(spans, max_error, min_len)
+    assert len(os_) > 0
+    _same(r.seeds(), os_, SEED_F, "seeds")
+    _same(r.candidates(), oc, CAND_F, "candidates")
+
+
 def test_search_config1(S, oracle_lib):
     """The 1 Mbp workload, self against self: exact seeds and candidates."""
     g = synth.config1()

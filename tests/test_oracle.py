@@ -393,6 +393,25 @@ def test_search_matches_bruteforce(oracle_lib, case, max_error, min_len, k, w):
     assert [tuple(int(v) for v in x) for x in cands] == bc
 
 
+@pytest.mark.parametrize("seed", [1, 2])
+@pytest.mark.parametrize("max_error,min_len,k,w", [(0.25, 200, 12, 16), (0.3, 120, 9, 5)])
+def test_search_tandem_matches_bruteforce(oracle_lib, seed, max_error, min_len, k, w):
+    """P10 where windows hold many repeated hashes (tandem arrays on both
+    strands): shared counts are over distinct hashes on both sides, so the
+    oracle's seeds and candidates still equal the brute force's."""
+    from oracle import brute
+    g = synth.tandem_case(90 + seed, length=3000, n_arrays=5, copies_hi=20, n_seqs=seed)
+    b, off = g.concat()
+    spans = list(g.spans) + [(0, 200, 2600)]
+    ix = oracle_lib.OracleIndex(b, off, k, w)
+    seeds, cands = ix.search(spans, max_error, min_len)
+    br = brute.Brute(b, off, k, w)
+    bs, bc = br.search(spans, max_error, min_len)
+    assert len(bs) > 0
+    assert [tuple(int(v) for v in x) for x in seeds] == bs
+    assert [tuple(int(v) for v in x) for x in cands] == bc
+
+
 def test_search_rejects_bad_arguments(oracle_lib):
     g = synth.small_case(9, length=3000)
     b, off = g.concat()

@@ -7,7 +7,8 @@
 // Connected components become candidates [min i, max i + n) x
 // [min j, max j + n).  Seeds are sorted into cells of (query, strand,
 // diagonal / (floor(delta n) + 1), i); a seed only needs to look at its own
-// cell and the next one.  Components come from a lock-free union-find whose
+// cell and the next one.  Runs of consecutive linked seeds are joined by a
+// scan first; the lock-free union-find then starts from those runs, and its
 // result does not depend on the order of the unions.
 #include "sdf_impl.h"
 #include "search.h"
@@ -127,32 +128,92 @@ __device__ __forceinline__ bool linked(const Sorted &s, uint64_t a, uint64_t b, 
     return dd <= (int64_t)mo && -dd <= (int64_t)mo;
 }
 
+// Segments: maximal runs of the sorted order in which each seed links to
+// the one before it (same query and strand, linked()).  Along a
+// duplication, consecutive seeds of a diagonal cell link, so one segment
+// usually holds a whole cell's share of it.
+__global__ void k_seg_flags(Sorted s, uint64_t ns, uint32_t n, uint32_t mo, uint32_t cbits,
+                            uint32_t *flag) {
+    const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= ns) return;
+    bool head = true;
+    if (a > 0 && (s.g[a - 1] >> cbits) == (s.g[a] >> cbits) && linked(s, a - 1, a, n, mo))
+        head = false;
+    flag[a] = head ? 1u : 0u;
+}
+
+// sid = segment of each seed; head[sid] = its first seed, head[#segments] = ns.
+__global__ void k_seg_heads(const uint32_t *flag, const uint32_t *pre, uint64_t ns,
+                            uint32_t *sid, uint32_t *head) {
+    const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= ns) return;
+    const uint32_t id = pre[a] + flag[a] - 1;
+    sid[a] = id;
+    if (flag[a]) head[id] = (uint32_t)a;
+    if (a == ns - 1) head[pre[ns]] = (uint32_t)ns;
+}
+
+// Union-find starts from the segments: every seed points at its segment's
+// first seed (the smallest index, so roots stay the minima of components).
+__global__ void k_seg_par(const uint32_t *sid, const uint32_t *head, uint64_t ns, uint32_t *par) {
+    const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < ns) par[a] = head[sid[a]];
+}
+
+// First index in [lo, ns) whose value is not below x (sorted), found by
+// galloping from lo: the target is usually close.
+template <typename F>
+__device__ __forceinline__ uint64_t gallop(uint64_t lo, uint64_t ns, F below) {
+    uint64_t step = 1, hi = lo;
+    while (hi < ns && below(hi)) {
+        lo = hi + 1;
+        hi = lo + step;
+        step <<= 1;
+    }
+    if (hi > ns) hi = ns;
+    while (lo < hi) {
+        const uint64_t m = (lo + hi) >> 1;
+        if (below(m)) lo = m + 1; else hi = m;
+    }
+    return lo;
+}
+
+// Links of seed a to later seeds: in its own cell past its own segment, and
+// in the next diagonal cell with i in (ia - n, ia + n).  After a union the
+// rest of the other seed's segment is skipped (already connected).
 __global__ void k_link(Sorted s, uint64_t ns, uint32_t n, uint32_t mo, uint32_t cbits,
-                       uint32_t *par) {
-    uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                       const uint32_t *sid, const uint32_t *head, uint32_t *par) {
+    const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= ns) return;
     const uint64_t g = s.g[a];
     const uint64_t ia = s.i[a];
-    // same cell, larger or equal i
-    for (uint64_t b = a + 1; b < ns && s.g[b] == g && (uint64_t)s.i[b] < ia + n; b++)
-        if (linked(s, a, b, n, mo)) uf_union(par, (uint32_t)a, (uint32_t)b);
-    // next cell of the same query and strand: i within (ia - n, ia + n)
+    const uint32_t sa = sid[a];
+    uint64_t b = head[sa + 1];
+    while (b < ns && s.g[b] == g && (uint64_t)s.i[b] < ia + n) {
+        if (linked(s, a, b, n, mo)) {
+            uf_union(par, (uint32_t)a, (uint32_t)b);
+            b = head[sid[b] + 1];
+        } else {
+            b++;
+        }
+    }
     const uint64_t g2 = g + 1;
     if ((g2 >> cbits) != (g >> cbits)) return;  // the cell after the last of its strand
-    uint64_t lo = a + 1, hi = ns;
-    while (lo < hi) {
-        uint64_t m = (lo + hi) >> 1;
-        if (s.g[m] < g2) lo = m + 1; else hi = m;
-    }
-    if (lo >= ns || s.g[lo] != g2) return;
-    uint64_t l2 = lo, h2 = ns;
     const uint64_t lim = ia >= n ? ia - n + 1 : 0;  // first i not too small
-    while (l2 < h2) {
-        uint64_t m = (l2 + h2) >> 1;
-        if (s.g[m] == g2 && (uint64_t)s.i[m] < lim) l2 = m + 1; else h2 = m;
+    b = gallop(a + 1, ns, [&](uint64_t m) {
+        return s.g[m] < g2 || (s.g[m] == g2 && (uint64_t)s.i[m] < lim);
+    });
+    while (b < ns && s.g[b] == g2 && (uint64_t)s.i[b] < ia + n) {
+        const uint32_t sb = sid[b];
+        if (sb == sa) {
+            b = head[sa + 1];
+        } else if (linked(s, a, b, n, mo)) {
+            uf_union(par, (uint32_t)a, (uint32_t)b);
+            b = head[sb + 1];
+        } else {
+            b++;
+        }
     }
-    for (uint64_t b = l2; b < ns && s.g[b] == g2 && (uint64_t)s.i[b] < ia + n; b++)
-        if (linked(s, a, b, n, mo)) uf_union(par, (uint32_t)a, (uint32_t)b);
 }
 
 __global__ void k_flatten(uint32_t *par, uint64_t ns) {
@@ -366,9 +427,18 @@ void chain_seeds(const IndexView &ix, const uint32_t *seeds, uint64_t ns, uint32
     k_gather<<<nb(ns), 256, 0, st>>>(seeds, gk.p, gshift, order2.p, ns, ix.off, ix.nseq, s);
     SDF_HIP(hipGetLastError());
     DevBuf<uint32_t> par(ns);
-    iota_u32(par.p, ns, st);
-    k_link<<<nb(ns), 256, 0, st>>>(s, ns, n, mo, ck.cbits, par.p);
-    SDF_HIP(hipGetLastError());
+    {
+        DevBuf<uint32_t> sflag(ns + 1), spre(ns + 1), sid(ns), head(ns + 1);
+        k_seg_flags<<<nb(ns), 256, 0, st>>>(s, ns, n, mo, ck.cbits, sflag.p);
+        SDF_HIP(hipGetLastError());
+        scan_u32(sflag.p, spre.p, ns, st);
+        k_seg_heads<<<nb(ns), 256, 0, st>>>(sflag.p, spre.p, ns, sid.p, head.p);
+        SDF_HIP(hipGetLastError());
+        k_seg_par<<<nb(ns), 256, 0, st>>>(sid.p, head.p, ns, par.p);
+        SDF_HIP(hipGetLastError());
+        k_link<<<nb(ns), 256, 0, st>>>(s, ns, n, mo, ck.cbits, sid.p, head.p, par.p);
+        SDF_HIP(hipGetLastError());
+    }
     k_flatten<<<nb(ns), 256, 0, st>>>(par.p, ns);
     SDF_HIP(hipGetLastError());
     DevBuf<uint32_t> a1(ns), a2(ns), a3(ns), a4(ns), a5(ns), a6(ns);

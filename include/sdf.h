@@ -121,6 +121,14 @@ sdf_status sdf_index_build(const char *const *seqs, const uint64_t *lens, uint32
 sdf_status sdf_index_info(sdf_index ix, uint64_t *n_minimizers, uint64_t *n_eligible,
                           uint64_t *device_bytes);
 
+/* Hit density of a built index: the sum over canonical hashes of n_h^2
+ * divided by the sum of n_h, n_h = eligible occurrences of hash h on both
+ * strands (the index I_G^{-1} of Section 3.1).  It is the mean number of
+ * target occurrences a query minimizer's lookup returns, and it sets the
+ * default number of window starts per tile.  *hbar is 0 for an empty index.
+ * Errors: SDF_EINVAL (NULL pointer). */
+sdf_status sdf_index_hit_density(sdf_index ix, double *hbar);
+
 /* Copy the winnow W(G) (Section 2.2) to host memory in position order:
  * pos (global), hash and flags (bit0: the reverse complement is the
  * canonical k-mer; bit1: eligible for seeding, Section 3.2).  Any output

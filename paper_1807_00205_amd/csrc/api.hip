@@ -81,6 +81,17 @@ uint32_t env_u32(const char *name, uint32_t def) {
     return (uint32_t)std::strtoul(v, nullptr, 10);
 }
 
+// Window starts per tile: as many as keep a tile's hits within one target
+// partition (hits per window start run about 1.15 hbar, and splitting a tile
+// into partitions costs a search of every list per partition), at least 512
+// so fixed per-tile costs stay amortised.
+uint32_t auto_tile_core(double hbar, uint32_t hpart) {
+    const double per_win = 1.15 * (hbar > 1.0 ? hbar : 1.0);
+    double c = 0.95 * (double)hpart / per_win;
+    c = std::min(std::max(c, 512.0), (double)tile_core_max());
+    return ((uint32_t)c) & ~63u;
+}
+
 int cu_count(int dev) {
     static int cached[64] = {0};
     if (dev >= 0 && dev < 64 && cached[dev]) return cached[dev];
@@ -161,9 +172,10 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
         sd[t].qseq = qs[t].seq;
         qbases += qs[t].end - qs[t].begin;
     }
-    const uint32_t core = std::min(std::max<uint32_t>(env_u32("SDF_TILE_CORE", 512), 1),
-                                   tile_core_max());
     const uint32_t hpart = std::max<uint32_t>(env_u32("SDF_HITS_PER_PART", 16384), 1024);
+    const uint32_t core = std::min(std::max<uint32_t>(env_u32("SDF_TILE_CORE",
+                                                              auto_tile_core(ix->hbar, hpart)), 1),
+                                   tile_core_max());
     DevBuf<SpanDesc> dsd(nq);
     DevBuf<uint32_t> ntiles(nq + 1), tile0(nq + 1);
     uint32_t total_tiles = 0;
@@ -303,6 +315,13 @@ sdf_status sdf_index_info(sdf_index ix, uint64_t *nm, uint64_t *ne, uint64_t *by
         if (nm) *nm = ix->nm;
         if (ne) *ne = ix->ne;
         if (bytes) *bytes = ix->device_bytes;
+    });
+}
+
+sdf_status sdf_index_hit_density(sdf_index ix, double *hbar) {
+    return guarded([&] {
+        if (!ix || !hbar) throw Error{SDF_EINVAL, "NULL argument"};
+        *hbar = ix->hbar;
     });
 }
 

@@ -488,6 +488,40 @@ static uint64_t read_back(const T *d, hipStream_t st) {
     return (uint64_t)h;
 }
 
+// Sum over hashes of n_h^2 (n_h = eligible occurrences of canonical hash h,
+// both strands) from the (hash << 1 | strand)-sorted keys: each run start
+// finds its run end by galloping.  Divided by the entry count this is the
+// mean list length seen by a query minimizer (hits per minimizer).
+__global__ void k_hit_density(const uint64_t *key, uint64_t ne, unsigned long long *acc) {
+    __shared__ unsigned long long part[256 / 64];
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long v = 0;
+    if (e < ne && (e == 0 || (key[e - 1] >> 1) != (key[e] >> 1))) {
+        const uint64_t h = key[e] >> 1;
+        uint64_t lo = e + 1, hi = e + 1, step = 1;
+        while (hi < ne && (key[hi] >> 1) == h) {
+            lo = hi + 1;
+            hi = lo + step;
+            step <<= 1;
+        }
+        if (hi > ne) hi = ne;
+        while (lo < hi) {
+            const uint64_t m = (lo + hi) >> 1;
+            if ((key[m] >> 1) == h) lo = m + 1; else hi = m;
+        }
+        const unsigned long long len = lo - e;
+        v = len * len;
+    }
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < 256 / 64; w++) t += part[w];
+        if (t) atomicAdd(acc, t);
+    }
+}
+
 void build_index(sdf_index_s *ix, const char *const *seqs, const uint64_t *lens,
                  uint32_t n_seqs, hipStream_t st) {
     const uint32_t k = ix->k, w = ix->w;
@@ -595,6 +629,14 @@ void build_index(sdf_index_s *ix, const char *const *seqs, const uint64_t *lens,
                                                       eoff.p, key.p, ix->epos.p);
             SDF_HIP(hipGetLastError());
             radix_sort_u64(key.p, ix->epos.p, ne, (int)keybits, st);
+        }
+        ix->hbar = 0.0;
+        if (ne) {
+            DevBuf<unsigned long long> acc(1);
+            SDF_HIP(hipMemsetAsync(acc.p, 0, 8, st));
+            k_hit_density<<<blocks_for(ne, 256), 256, 0, st>>>(key.p, ne, acc.p);
+            SDF_HIP(hipGetLastError());
+            ix->hbar = (double)read_back(acc.p, st) / (double)ne;
         }
         k_directory<<<blocks_for(ndir, 256), 256, 0, st>>>(key.p, ne, ix->dir_shift, ix->dir.p, ndir);
         SDF_HIP(hipGetLastError());

@@ -29,7 +29,7 @@ namespace sdf {
 constexpr int TB = 1024;        // threads per tile workgroup
 constexpr int NWAVES = TB / 64;
 constexpr int QCAP = 1280;      // query minimizers per tile (core + halo)
-constexpr int CMAX = 512;       // window starts per tile core
+constexpr int CMAX = 1024;      // window starts per tile core
 constexpr int CB = 2048;        // kept hits per partition
 constexpr int TSLOTS = 16384;   // 16-bit counters in the bin table
 constexpr int TWORDS = TSLOTS / 2;
@@ -1114,16 +1114,19 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
             if (L.err) {
                 if (threadIdx.x == 0) atomicOr(a.err, L.err);
             } else {
-                // close the runs still open after the last partition
+                // close the runs still open after the last partition: one
+                // (window, orientation) per lane
                 SeedBuf sbuf{reinterpret_cast<uint32_t *>(L.u.scratch) + wave * SBUF * 6, 0};
-                for (uint32_t qc = wave; qc < C; qc += NWAVES) {
-                    if (L.win_T[qc] == 0) continue;
-                    for (uint32_t o = 0; o < 2; o++) {
-                        const RunState rs = L.run[qc][o];
-                        if (rs.active)
-                            seeds_push(a, sbuf, lane, L.qid, L.qpos[qc], rs.best_j, o, rs.best_c,
-                                       L.win_s[qc]);
+                for (uint32_t b0 = (uint32_t)wave * 64; b0 < 2 * C; b0 += TB) {
+                    const uint32_t x = b0 + lane, qc = x >> 1, o = x & 1;
+                    bool mine = false;
+                    RunState rs{0, 0, 0, 0, 0};
+                    if (x < 2 * C && L.win_T[qc]) {
+                        rs = L.run[qc][o];
+                        mine = rs.active != 0;
                     }
+                    seeds_push_lanes(a, sbuf, lane, mine, L.qid, mine ? L.qpos[qc] : 0, rs.best_j,
+                                     o, rs.best_c, mine ? L.win_s[qc] : 0);
                 }
                 seeds_flush(a, sbuf, lane);
             }

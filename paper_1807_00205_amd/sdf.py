@@ -25,7 +25,8 @@ CANDIDATE_DTYPE = np.dtype([("query_id", "<u4"), ("strand", "<u4"), ("q_seq", "<
                             ("max_shared", "<u4")])
 SEED_DTYPE = np.dtype([("query_id", "<u4"), ("i", "<u4"), ("j", "<u4"), ("strand", "<u4"),
                        ("shared", "<u4"), ("sketch", "<u4")])
-EXPORTS = ["sdf_last_error", "sdf_index_build", "sdf_index_info", "sdf_index_minimizers",
+EXPORTS = ["sdf_last_error", "sdf_index_build", "sdf_index_info", "sdf_index_hit_density",
+           "sdf_index_minimizers",
            "sdf_index_entries", "sdf_index_packed", "sdf_index_free", "sdf_search",
            "sdf_search_batch", "sdf_result_count", "sdf_result_copy", "sdf_result_seed_count",
            "sdf_result_seeds", "sdf_result_timing", "sdf_result_stats", "sdf_result_free"]
@@ -81,6 +82,8 @@ def lib() -> ctypes.CDLL:
         L.sdf_index_build.argtypes = [vp, vp, u32, P(_IndexParams), vp, P(vp)]
         L.sdf_index_info.restype = st
         L.sdf_index_info.argtypes = [vp, P(u64), P(u64), P(u64)]
+        L.sdf_index_hit_density.restype = st
+        L.sdf_index_hit_density.argtypes = [vp, P(ctypes.c_double)]
         L.sdf_index_minimizers.restype = st
         L.sdf_index_minimizers.argtypes = [vp, vp, vp, vp, u64, P(u64)]
         L.sdf_index_entries.restype = st
@@ -207,6 +210,12 @@ class Index:
         a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
         _check(lib().sdf_index_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
         return a.value, b.value, c.value
+
+    def hit_density(self) -> float:
+        """Mean number of target occurrences of a query minimizer's hash."""
+        v = ctypes.c_double()
+        _check(lib().sdf_index_hit_density(self._h, ctypes.byref(v)))
+        return v.value
 
     def minimizers(self):
         nm, _, _ = self.info()

@@ -86,6 +86,20 @@ def test_winnow_and_reverse_index(S, oracle_lib, k, w):
     assert np.array_equal(gh2, eh) and np.array_equal(gs2, es) and np.array_equal(gp2, ep)
 
 
+@pytest.mark.parametrize("k,w", [(12, 16), (9, 5), (15, 20)])
+def test_hit_density(S, oracle_lib, k, w):
+    """The index's hit density is sum n_h^2 / sum n_h over the oracle's
+    eligible entries (n_h = occurrences of hash h, both strands)."""
+    g = synth.tandem_case(77, length=60_000, n_arrays=30, n_seqs=2)
+    b, off = g.concat()
+    orc = oracle_lib.OracleIndex(b, off, k, w)
+    h, _, _ = orc.entries()
+    _, cnt = np.unique(h, return_counts=True)
+    want = float((cnt.astype(np.float64) ** 2).sum() / cnt.sum())
+    ix = S.Index(g.seqs, k, w)
+    assert ix.hit_density() == pytest.approx(want, rel=1e-12)
+
+
 def test_winnow_large_uniform(S, oracle_lib):
     """Minimizers of 1 Mbp (config 1) across many blocks of the winnow kernel."""
     g = synth.config1()
@@ -164,7 +178,7 @@ def test_search_config1_tile_shapes(S, oracle_lib, monkeypatch):
     orc = oracle_lib.OracleIndex(b, off, 12, 16)
     os_, oc = orc.search(g.spans, 0.25, 1000)
     ix = S.Index(g.seqs, 12, 16)
-    for core, hpart in ((64, 1024), (200, 3000), (512, 100000)):
+    for core, hpart in ((64, 1024), (200, 3000), (512, 100000), (1024, 16384), (1000, 4096)):
         monkeypatch.setenv("SDF_TILE_CORE", str(core))
         monkeypatch.setenv("SDF_HITS_PER_PART", str(hpart))
         r = ix.search(g.spans[0], 0.25, 1000)

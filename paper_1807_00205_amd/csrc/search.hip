@@ -39,7 +39,14 @@ constexpr uint32_t HMAX = 65535;  // hits per partition (16-bit counters cannot 
 constexpr int STACK = 40;
 constexpr int QW = QCAP / 64;     // 64-bit words of a bitmask over the query minimizers
 
-enum : uint32_t { EF_CAND = 1, EF_VALID = 2 };
+enum : uint32_t { EF_CAND = 1 };
+// Packed per kept hit after compaction: its query minimizer, whether it is a
+// candidate j owned by the partition with a valid target window, and whether
+// the kept hit before it has the same orientation and position.
+constexpr uint32_t EI_Q = 0x7FFu;        // bits 0-10
+constexpr uint32_t EI_CAND = 1u << 11;
+constexpr uint32_t EI_SAMEP = 1u << 12;
+static_assert(QCAP <= 2048, "EI_Q field width");
 // Minimizers of one window that share hash and strand have the same hits
 // except each one's own position, so their union is the full list: the
 // first one stands for all of them with its self-hit kept (QM_UNION), the
@@ -62,7 +69,6 @@ struct TileLds {
     uint32_t qpos[QCAP + 1];
     uint32_t qhash[QCAP];
     int16_t qprev[QCAP];
-    uint16_t qroot[QCAP];
     uint8_t qfl[QCAP];
     uint8_t qmode[QCAP];  // QM_* while a partition covers a single window
     uint32_t lst_lo[2 * QCAP];
@@ -79,12 +85,9 @@ struct TileLds {
         uint64_t scratch[TWORDS / 2];
     } u;
     uint64_t coll[CB];
-    uint32_t prevq[CB];
     uint32_t eseq[CB];
     uint16_t rng_end[CB];
-    uint8_t eflag[CB];
-    uint16_t prevx[CB];  // index + 1 of the hit that prevq describes (0: none)
-    unsigned long long qhas[2][QW];  // q has a relevant kept hit in orientation o
+    uint32_t einfo[CB];  // EI_* fields of each kept hit
     uint32_t stackA[STACK], stackB[STACK], stackW[STACK];  // W: first window | end << 16
     uint64_t wtmp[NWAVES + 1];
     uint64_t ph[PH_N];
@@ -536,11 +539,10 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
             if (threadIdx.x < CMAX / 32) L.Tblk[threadIdx.x] = 0xFFFFu;
             __syncthreads();
             for (uint32_t q = threadIdx.x; q < Q; q += TB) {
-                int r = (int)q;
-                while (L.qprev[r] >= 0) r = L.qprev[r];
-                L.qroot[q] = (uint16_t)r;
-                if (r != (int)q && (L.qfl[q] & 2)) L.dup = 1;
-                if (L.qprev[q] >= 0) dups[atomicAdd(&L.ndup, 1u)] = (uint16_t)q;
+                if (L.qprev[q] >= 0) {
+                    if (L.qfl[q] & 2) L.dup = 1;
+                    dups[atomicAdd(&L.ndup, 1u)] = (uint16_t)q;
+                }
             }
             __syncthreads();
             const uint32_t ndup = L.ndup;
@@ -714,7 +716,6 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                 }
                 // ---- pass 1: bin counts ----
                 for (uint32_t t = threadIdx.x; t < TWORDS; t += TB) L.u.table[t] = 0;
-                if (threadIdx.x < 2 * QW) (&L.qhas[0][0])[threadIdx.x] = 0;
                 __syncthreads();
                 const uint32_t SB = a.bin_shift;
                 // Each wave takes HU * 64 consecutive hits per round and issues
@@ -837,7 +838,7 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                 for (int r = 0; r < CB / TB; r++) {
                     if (keep_at[r] != NONE32) {
                         L.coll[keep_at[r]] = keep_k[r];
-                        L.eflag[keep_at[r]] = keep_f[r];
+                        L.einfo[keep_at[r]] = keep_f[r] ? EI_CAND : 0u;
                     }
                 }
                 __syncthreads();
@@ -865,239 +866,168 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                         if ((uint64_t)ck_p(L.coll[m]) <= lim) lo = m + 1; else hi = m;
                     }
                     L.rng_end[e] = (uint16_t)lo;
-                    atomicOr(&L.qhas[o][q >> 6], 1ull << (q & 63));
-                    // nearest earlier hit within n - k of the same hash: of the
-                    // same query minimizer unless the tile repeats hashes, then
-                    // of any minimizer with the same root
-                    const uint32_t rq = dup ? L.qroot[q] : q;
-                    uint32_t pv = 0, px = 0;
-                    for (int f = (int)e - 1; f >= (int)L.obeg[o]; f--) {
-                        const uint64_t kf = L.coll[f];
-                        if ((uint64_t)ck_p(kf) + n - k < p) break;
-                        const uint32_t qf = ck_q(kf);
-                        if ((dup ? L.qroot[qf] : qf) == rq) {
-                            pv = ck_p(kf) + 1;
-                            px = (uint32_t)f + 1;
-                            break;
-                        }
-                    }
-                    L.prevq[e] = pv;
-                    L.prevx[e] = (uint16_t)px;
-                    if ((L.eflag[e] & EF_CAND) && p >= A && p < B) {
+                    uint32_t info = q;
+                    if (e > L.obeg[o] && ck_p(L.coll[e - 1]) == p) info |= EI_SAMEP;
+                    if ((L.einfo[e] & EI_CAND) && p >= A && p < B) {  // owned by this partition
                         uint32_t sq = 0;
-                        if (window_ok(ix, p, n, &sq)) L.eflag[e] |= EF_VALID;
+                        if (window_ok(ix, p, n, &sq)) info |= EI_CAND;
                         L.eseq[e] = sq;
-                    } else {
-                        L.eflag[e] &= ~EF_CAND;  // not owned by this partition
                     }
+                    L.einfo[e] = info;
                 }
                 __syncthreads();
                 PHASE(PH_SEGINFO);
 
-                // ---- exact counts, runs and seeds: one wave per window ----
-                // Per (window, orientation): bit e of `inw` says kept hit e
-                // comes from a query minimizer of the window, bit e of `dupw`
-                // that it also has an earlier hit of the same minimizer within
-                // n - k.  A candidate j's shared count is then the popcount of
-                // `inw` over its range [j, j+n-k], minus the hits whose earlier
-                // hit of the same minimizer also lies in the range.
-                // Candidates are gathered 64 at a time, counted one per lane,
-                // and the run logic walks each batch in target order.
+                // ---- exact counts, runs and seeds: one lane per window ----
+                // A wave takes 64 consecutive windows, one per lane, and walks
+                // the kept hits of each orientation in target order.  At a kept
+                // hit that is a candidate j of some of its windows it marks, in
+                // a bitmask over the tile's query minimizers, those with a kept
+                // hit in [j, j+n-k]; a window's shared count is the popcount of
+                // the mask over its own minimizers (less the repeats of a hash
+                // when the tile has any), and every lane applies its window's
+                // run logic to its candidates in target order.
                 SeedBuf sbuf{reinterpret_cast<uint32_t *>(L.u.scratch) + wave * SBUF * 6, 0};
-                uint32_t *cbuf = reinterpret_cast<uint32_t *>(L.u.scratch) + NWAVES * SBUF * 6 +
-                                 wave * 128;
-                uint64_t *inw = L.u.scratch + (NWAVES * SBUF * 6 + NWAVES * 128) / 2 +
-                                wave * (2 * (CB / 64));
-                uint64_t *dupw = inw + CB / 64;
-                const uint64_t ltmask = lane ? (~0ull >> (64 - lane)) : 0ull;
+                uint64_t *sbits = L.u.scratch + (NWAVES * SBUF * 6) / 2 + wave * QW;
+                uint64_t *dbits = L.u.scratch + (NWAVES * SBUF * 6) / 2 + NWAVES * QW + wave * QW;
+                static_assert((NWAVES * SBUF * 6) / 2 + 2 * NWAVES * QW <= TWORDS / 2,
+                              "per-wave eval buffers exceed the scratch area");
+                if (lane < QW) {
+                    sbits[lane] = 0;
+                    dbits[lane] = 0;
+                }
+                __builtin_amdgcn_wave_barrier();
                 uint32_t n_evals = 0, n_scan = 0;
-                for (uint32_t qc = WA + wave; qc < WB; qc += NWAVES) {
-                    const uint32_t Ti = L.win_T[qc];
-                    if (Ti == 0) continue;
-                    const uint32_t i = L.qpos[qc];
-                    const uint32_t qe = L.win_qend[qc];
+                for (uint32_t b0 = WA + (uint32_t)wave * 64; b0 < WB; b0 += TB) {
+                    const uint32_t qc = b0 + lane;
+                    const uint32_t qlo = b0, qhi = L.win_qend[min(b0 + 63, WB - 1)];
+                    const uint32_t wlo = qlo >> 6, nwb = ((qhi - 1) >> 6) - wlo + 1;
+                    const uint32_t Ti = qc < WB ? L.win_T[qc] : 0u;
+                    const bool win = Ti != 0;
+                    const uint32_t qe = win ? L.win_qend[qc] : 0u;
+                    const uint32_t i = win ? L.qpos[qc] : 0u;
+                    const uint32_t si = win ? L.win_s[qc] : 0u;
                     for (uint32_t o = 0; o < 2; o++) {
                         const uint32_t ob = L.obeg[o], oe = L.oend[o];
                         if (ob >= oe) continue;
-                        RunState rs = L.run[qc][o];
-                        if (!rs.active) {
-                            // no candidate can pass when fewer minimizers of the
-                            // window have any kept hit than the threshold, and
-                            // with no open run nothing else changes
-                            const uint32_t w0 = qc >> 6, w1 = (qe - 1) >> 6;
-                            uint32_t nq = 0;
-                            for (uint32_t x = w0; x <= w1; x++) {
-                                uint64_t m = L.qhas[o][x];
-                                if (x == w0) m &= ~0ull << (qc & 63);
-                                if (x == w1 && (qe & 63)) m &= (1ull << (qe & 63)) - 1;
-                                nq += (uint32_t)__popcll(m);
-                            }
-                            if (nq < Ti) continue;
-                        }
-                        const uint32_t wb = ob >> 6, we = (oe + 63) >> 6;
-                        n_scan += we - wb;
-                        // membership bitmasks over the orientation's kept hits
-                        for (uint32_t w = wb; w < we; w++) {
-                            const uint32_t e = w * 64 + lane;
-                            bool in = false, dp = false;
-                            if (e >= ob && e < oe) {
-                                const uint32_t q = ck_q(L.coll[e]);
-                                in = q >= qc && q < qe;
-                                if (in && L.prevx[e]) {
-                                    if (!dup) {
-                                        dp = true;  // same minimizer: in the window too
-                                    } else {
-                                        // walk earlier hits of the same hash for one
-                                        // of a minimizer inside the window
-                                        const uint32_t pe = ck_p(L.coll[e]);
-                                        for (uint32_t g = L.prevx[e]; g;) {
-                                            const uint64_t kg = L.coll[g - 1];
-                                            if ((uint64_t)ck_p(kg) + n - k < pe) break;
-                                            const uint32_t qg = ck_q(kg);
-                                            if (qg >= qc && qg < qe) {
-                                                dp = true;
-                                                break;
-                                            }
-                                            g = L.prevx[g - 1];
-                                        }
+                        RunState rs{0, 0, 0, 0, 0};
+                        if (win) rs = L.run[qc][o];
+                        uint32_t carry_q = EI_Q;  // minimizer of the hit before the chunk
+                        for (uint32_t e0 = ob & ~63u; e0 < oe; e0 += 64) {
+                            n_scan++;
+                            const uint32_t ex = e0 + lane;
+                            const bool valid = ex >= ob && ex < oe;
+                            const uint32_t info = valid ? L.einfo[ex] : 0u;
+                            const uint32_t qx = info & EI_Q;
+                            // candidates whose minimizer lies in one of the block's windows
+                            uint64_t mm = __ballot(valid && (info & EI_CAND) && qx >= qlo && qx < qhi);
+                            const uint32_t chunk_last_q = (uint32_t)__builtin_amdgcn_readlane((int)qx, 63);
+                            while (mm) {
+                                const uint32_t bb = (uint32_t)__ffsll((long long)mm) - 1;
+                                mm &= mm - 1;
+                                const uint32_t e = e0 + bb;
+                                const uint32_t ie = (uint32_t)__builtin_amdgcn_readlane((int)info, (int)bb);
+                                const uint32_t q = ie & EI_Q;
+                                const uint32_t pq = bb ? ((uint32_t)__builtin_amdgcn_readlane((int)info, (int)bb - 1) & EI_Q)
+                                                       : carry_q;
+                                // the window's first hit at this position
+                                const bool mine = win && q >= qc && q < qe && !((ie & EI_SAMEP) && pq >= qc);
+                                const uint64_t mb = __ballot(mine);
+                                if (!mb) continue;
+                                n_evals += (uint32_t)__popcll(mb);
+                                const uint32_t j = ck_p(L.coll[e]);
+                                const uint32_t tseq = L.eseq[e];
+                                const uint32_t re = L.rng_end[e];  // > e
+                                // minimizers of the block with a kept hit in [j, j+n-k]
+                                for (uint32_t f0 = e; f0 < re; f0 += 64) {
+                                    const uint32_t f = f0 + lane;
+                                    if (f < re) {
+                                        const uint32_t qf = L.einfo[f] & EI_Q;
+                                        if (qf >= qlo && qf < qhi) atomicOr(&sbits[qf >> 6], 1ull << (qf & 63));
                                     }
                                 }
-                            }
-                            const uint64_t mi = __ballot(in), md = __ballot(dp);
-                            if (lane == 0) {
-                                inw[w] = mi;
-                                dupw[w] = md;
-                            }
-                        }
-                        __builtin_amdgcn_wave_barrier();
-                        uint32_t nc = 0;
-                        for (uint32_t w = wb; w < we; w++) {
-                            const uint32_t e = w * 64 + lane;
-                            const uint64_t mi = inw[w];
-                            bool cand = false;
-                            if (((mi >> lane) & 1) && (L.eflag[e] & (EF_CAND | EF_VALID)) == (EF_CAND | EF_VALID)) {
-                                cand = true;
-                                if (e > ob) {
-                                    const uint64_t kp = L.coll[e - 1], key = L.coll[e];
-                                    if (ck_p(kp) == ck_p(key) && ck_q(kp) >= qc) cand = false;
-                                }
-                            }
-                            const uint64_t cm = __ballot(cand);
-                            if (cand) cbuf[nc + (uint32_t)__popcll(cm & ltmask)] = e;
-                            nc += (uint32_t)__popcll(cm);
-                            __builtin_amdgcn_wave_barrier();
-                            const bool last = w + 1 >= we;
-                            while (nc >= 64 || (last && nc > 0)) {
-                                const uint32_t nb = nc < 64 ? nc : 64;
-                                n_evals += nb;
-                                uint32_t ec = 0, j = 0, cnt = 0, tseq = 0;
-                                if ((uint32_t)lane < nb) {
-                                    ec = cbuf[lane];
-                                    j = ck_p(L.coll[ec]);
-                                    tseq = L.eseq[ec];
-                                }
-                                if ((uint32_t)lane < nb) {
-                                    const uint32_t re = L.rng_end[ec];  // > ec
-                                    const uint32_t w0 = ec >> 6, w1 = (re - 1) >> 6;
+                                __builtin_amdgcn_wave_barrier();
+                                uint32_t cnt = 0;
+                                if (mine) {
+                                    const uint32_t w0 = qc >> 6, w1 = (qe - 1) >> 6;
                                     for (uint32_t x = w0; x <= w1; x++) {
-                                        uint64_t m = inw[x], d = dupw[x];
-                                        uint64_t keep = ~0ull;
-                                        if (x == w0) keep &= ~0ull << (ec & 63);
-                                        if (x == w1 && (re & 63)) keep &= (1ull << (re & 63)) - 1;
-                                        cnt += (uint32_t)__popcll(m & keep);
-                                        d &= keep;
-                                        while (d) {
-                                            const uint32_t f = x * 64 + (__ffsll((long long)d) - 1);
-                                            d &= d - 1;
-                                            if (!dup) {
-                                                if (L.prevq[f] - 1 >= j) cnt--;  // earlier hit in range
-                                            } else {
-                                                // nearest earlier same-hash hit of the window
-                                                for (uint32_t g = L.prevx[f]; g;) {
-                                                    const uint64_t kg = L.coll[g - 1];
-                                                    if (ck_p(kg) < j) break;
-                                                    const uint32_t qg = ck_q(kg);
-                                                    if (qg >= qc && qg < qe) {
-                                                        cnt--;
+                                        uint64_t m = sbits[x];
+                                        if (x == w0) m &= ~0ull << (qc & 63);
+                                        if (x == w1 && (qe & 63)) m &= (1ull << (qe & 63)) - 1;
+                                        cnt += (uint32_t)__popcll(m);
+                                    }
+                                }
+                                if (dup) {
+                                    // a marked minimizer repeats a hash when an earlier
+                                    // marked one has the same hash; it does not count
+                                    // in the windows holding that earlier one too
+                                    for (uint32_t f0 = e; f0 < re; f0 += 64) {
+                                        const uint32_t f = f0 + lane;
+                                        uint32_t qf = 0;
+                                        int ps = -1;
+                                        if (f < re) {
+                                            qf = L.einfo[f] & EI_Q;
+                                            if (qf >= qlo && qf < qhi)
+                                                for (int r = L.qprev[qf]; r >= (int)qlo; r = L.qprev[r])
+                                                    if ((sbits[r >> 6] >> (r & 63)) & 1) {
+                                                        ps = r;
                                                         break;
                                                     }
-                                                    g = L.prevx[g - 1];
-                                                }
-                                            }
+                                        }
+                                        bool own = false;
+                                        if (ps >= 0) {  // once per minimizer
+                                            const uint64_t old = atomicOr(&dbits[qf >> 6], 1ull << (qf & 63));
+                                            own = ((old >> (qf & 63)) & 1) == 0;
+                                        }
+                                        uint64_t om = __ballot(own);
+                                        while (om) {
+                                            const uint32_t t = (uint32_t)__ffsll((long long)om) - 1;
+                                            om &= om - 1;
+                                            const uint32_t dq = (uint32_t)__builtin_amdgcn_readlane((int)qf, (int)t);
+                                            const uint32_t dp = (uint32_t)__builtin_amdgcn_readlane(ps, (int)t);
+                                            if (mine && dq >= qc && dq < qe && dp >= qc) cnt--;
                                         }
                                     }
                                 }
-                                // run logic over the batch (lane t = t-th candidate in
-                                // target order): a candidate continues the run of the
-                                // previous one when both pass, lie in one sequence and
-                                // less than n apart; each run's seed is its largest
-                                // count, smallest j on ties (segmented max-scan).
-                                const bool act = (uint32_t)lane < nb;
+                                __builtin_amdgcn_wave_barrier();
+                                if ((uint32_t)lane < nwb) {
+                                    sbits[wlo + lane] = 0;
+                                    dbits[wlo + lane] = 0;
+                                }
+                                __builtin_amdgcn_wave_barrier();
+                                // run logic: a passing candidate continues the open run
+                                // when it lies in its sequence less than n after the
+                                // previous candidate; a run's seed is its largest count,
+                                // earliest j on ties
                                 bool excl = false;
-                                if (act && tseq == L.qseq) {
+                                if (tseq == L.qseq) {
                                     const uint32_t dd = j > i ? j - i : i - j;
                                     excl = dd < n && (n - dd) > a.max_overlap;
                                 }
-                                const bool pass = act && cnt >= Ti && !excl;
-                                // previous candidate: whole-wave shift right by one lane
-                                uint32_t pj = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)j, DPP_WAVE_SHR1, 0xf, 0xf, false);
-                                uint32_t ps = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)tseq, DPP_WAVE_SHR1, 0xf, 0xf, false);
-                                const uint64_t pb = __ballot(pass);
-                                bool ppass = lane ? ((pb >> (lane - 1)) & 1) != 0 : false;
-                                if (lane == 0) {
-                                    pj = rs.prev_j;
-                                    ps = rs.prev_seq;
-                                    ppass = rs.active != 0;
+                                const bool pass = mine && cnt >= Ti && !excl;
+                                const bool link = pass && rs.active && tseq == rs.prev_seq && j - rs.prev_j < n;
+                                seeds_push_lanes(a, sbuf, lane, mine && rs.active && !link, L.qid, i,
+                                                 rs.best_j, o, rs.best_c, si);
+                                if (mine) {
+                                    if (link) {
+                                        if (cnt > rs.best_c) {
+                                            rs.best_c = (uint16_t)cnt;
+                                            rs.best_j = j;
+                                        }
+                                    } else if (pass) {
+                                        rs.active = 1;
+                                        rs.best_c = (uint16_t)cnt;
+                                        rs.best_j = j;
+                                    } else {
+                                        rs.active = 0;
+                                    }
+                                    rs.prev_j = j;
+                                    rs.prev_seq = tseq;
                                 }
-                                const bool link = pass && ppass && tseq == ps && j - pj < n;
-                                // One 32-bit key per lane: run number (runs start where
-                                // a candidate does not link), count, and 127 - slot with
-                                // slot 0 the open run carried in and lane t in slot t + 1,
-                                // so a plain max-scan gives each run's largest count,
-                                // earliest candidate on ties.
-                                const uint64_t lb = __ballot(link);
-                                const uint64_t heads = ~lb;
-                                const uint32_t run_no = (uint32_t)__popcll(heads & (ltmask | (1ull << lane)));
-                                uint32_t key = pass ? ((cnt << 7) | (126u - (uint32_t)lane)) : 0u;
-                                if (lane == 0 && link) key = max(key, ((uint32_t)rs.best_c << 7) | 127u);
-                                key = wave_max_scan((run_no << 18) | key);
-                                const uint32_t kslot = 127u - (key & 127u);
-                                const uint32_t kc = (key >> 7) & 2047u;
-                                const uint32_t kj = (uint32_t)__shfl((int)j, (int)((kslot - 1) & 63), 64);
-                                const uint32_t kbest_j = kslot ? kj : rs.best_j;
-                                // the run open before this batch ends unless lane 0 links
-                                const bool link0 = (lb & 1ull) != 0;
-                                seeds_push_lanes(a, sbuf, lane, lane == 0 && rs.active && !link0,
-                                                 L.qid, i, rs.best_j, o, rs.best_c, L.win_s[qc]);
-                                // runs that end inside the batch
-                                const bool link_next = lane < 63 && ((lb >> (lane + 1)) & 1) != 0;
-                                const bool ends = pass && (uint32_t)lane + 1 < nb && !link_next;
-                                seeds_push_lanes(a, sbuf, lane, ends, L.qid, i, kbest_j, o, kc,
-                                                 L.win_s[qc]);
-                                // carry the state after the last candidate
-                                const uint32_t tl = nb - 1;
-                                const bool pl = ((pb >> tl) & 1) != 0;
-                                const uint32_t last_best_j = (uint32_t)__builtin_amdgcn_readlane((int)kbest_j, (int)tl);
-                                const uint32_t last_c = (uint32_t)__builtin_amdgcn_readlane((int)kc, (int)tl);
-                                rs.prev_j = (uint32_t)__builtin_amdgcn_readlane((int)j, (int)tl);
-                                rs.prev_seq = (uint32_t)__builtin_amdgcn_readlane((int)tseq, (int)tl);
-                                rs.active = pl ? 1 : 0;
-                                if (pl) {
-                                    rs.best_c = (uint16_t)last_c;
-                                    rs.best_j = last_best_j;
-                                }
-                                // keep the candidates beyond this batch
-                                __builtin_amdgcn_wave_barrier();
-                                uint32_t rest = 0;
-                                if ((uint32_t)lane + nb < nc) rest = cbuf[lane + nb];
-                                __builtin_amdgcn_wave_barrier();
-                                if ((uint32_t)lane + nb < nc) cbuf[lane] = rest;
-                                __builtin_amdgcn_wave_barrier();
-                                nc -= nb;
                             }
+                            carry_q = chunk_last_q;
                         }
-                        if (lane == 0) L.run[qc][o] = rs;
-                        __builtin_amdgcn_wave_barrier();
+                        if (win) L.run[qc][o] = rs;
                     }
                 }
                 seeds_flush(a, sbuf, lane);

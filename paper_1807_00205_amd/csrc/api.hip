@@ -178,12 +178,10 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
                                    tile_core_max());
     DevBuf<SpanDesc> dsd(nq);
     DevBuf<uint32_t> ntiles(nq + 1), tile0(nq + 1);
-    uint32_t total_tiles = 0;
+    uint32_t total_tiles = 0;  // read back with the counters; the kernel reads it on device
     if (nq) {
         SDF_HIP(hipMemcpyAsync(dsd.p, sd.data(), nq * sizeof(SpanDesc), hipMemcpyHostToDevice, st));
         launch_span_setup(ix->view(), dsd.p, nq, P.n, core, ntiles.p, tile0.p, st);
-        SDF_HIP(hipMemcpyAsync(&total_tiles, tile0.p + nq, 4, hipMemcpyDeviceToHost, st));
-        SDF_HIP(hipStreamSynchronize(st));
     }
     tm.mark();
     uint32_t sb = 0;
@@ -200,7 +198,7 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
         SDF_HIP(hipMemsetAsync(counters.p, 0, CNT_N * 8, st));
         SDF_HIP(hipMemsetAsync(work.p, 0, 8, st));
         SDF_HIP(hipMemsetAsync(phase.p, 0, PH_N * 8, st));
-        if (total_tiles) {
+        if (nq) {
             SearchArgs a;
             a.ix = ix->view();
             a.n = P.n;
@@ -208,7 +206,7 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
             a.T = dT.p;
             a.spans = dsd.p;
             a.nspans = nq;
-            a.total_tiles = total_tiles;
+            a.total_tiles = tile0.p + nq;
             a.work = work.p;
             a.core = core;
             a.hpart = hpart;
@@ -218,14 +216,15 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
             a.counters = counters.p;
             a.err = work.p + 1;
             a.phase = phase_prof ? phase.p : nullptr;
-            const uint32_t grid = std::min<uint32_t>(total_tiles, (uint32_t)cu_count(ix->device) *
-                                                                      env_u32("SDF_WG_PER_CU", 1));
+            // persistent grid: workgroups past the last tile exit at once
+            const uint32_t grid = (uint32_t)cu_count(ix->device) * env_u32("SDF_WG_PER_CU", 1);
             tm.mark_kernel_begin();
             launch_tile_search(a, std::max<uint32_t>(grid, 1), st);
             tm.mark_kernel_end();
         }
         SDF_HIP(hipMemcpyAsync(hc.data(), counters.p, CNT_N * 8, hipMemcpyDeviceToHost, st));
         SDF_HIP(hipMemcpyAsync(&herr, work.p + 1, 4, hipMemcpyDeviceToHost, st));
+        if (nq) SDF_HIP(hipMemcpyAsync(&total_tiles, tile0.p + nq, 4, hipMemcpyDeviceToHost, st));
         SDF_HIP(hipStreamSynchronize(st));
         if (herr) break;
         if (hc[CNT_SEEDS] <= cap) break;

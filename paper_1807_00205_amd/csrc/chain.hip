@@ -10,6 +10,8 @@
 // cell and the next one.  Runs of consecutive linked seeds are joined by a
 // scan first; the lock-free union-find then starts from those runs, and its
 // result does not depend on the order of the unions.
+#include <cstdlib>
+
 #include "sdf_impl.h"
 #include "search.h"
 
@@ -301,6 +303,232 @@ __global__ void k_emit_cands(Sorted s, const uint32_t *par, uint64_t ns, Agg g, 
     out[pre[a]] = c;
 }
 
+// ------------------------------------------------- small searches, fused --
+// Fewer than CS_N seeds are chained by one workgroup in LDS: the same key sort,
+// links, union-find and aggregation as the multi-kernel path, in one launch
+// (a search of a few hundred kbp has about a thousand seeds, and the launch
+// chain of the general path costs more than its work).
+constexpr int CS_N = 2048;
+constexpr int CS_TB = 1024;
+
+struct ChainSmallLds {
+    uint64_t key[CS_N];  // group << ibits | i, then sorted
+    uint32_t idx[CS_N];
+    uint32_t si[CS_N], sj[CS_N], sc[CS_N], sts[CS_N];
+    uint8_t so[CS_N];
+    uint32_t par[CS_N];
+    uint32_t qmin[CS_N], qmax[CS_N], tmin[CS_N], tmax[CS_N], cnt[CS_N], cmax[CS_N];
+    uint32_t wsum[CS_TB / 64];
+    uint32_t base;
+};
+
+__device__ uint32_t cs_find(uint32_t *par, uint32_t x) {
+    for (;;) {
+        const uint32_t p = __hip_atomic_load(par + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (p == x) return x;
+        const uint32_t gp = __hip_atomic_load(par + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (gp != p) atomicCAS(par + x, p, gp);
+        x = p;
+    }
+}
+
+__device__ void cs_union(uint32_t *par, uint32_t a, uint32_t b) {
+    for (;;) {
+        a = cs_find(par, a);
+        b = cs_find(par, b);
+        if (a == b) return;
+        if (a < b) {
+            const uint32_t t = a;
+            a = b;
+            b = t;
+        }
+        if (atomicCAS(par + a, a, b) == a) return;
+    }
+}
+
+__device__ __forceinline__ bool cs_linked(const ChainSmallLds &L, uint32_t a, uint32_t b, uint32_t n,
+                                          uint32_t mo) {
+    if (L.sts[a] != L.sts[b]) return false;
+    const int64_t dj = (int64_t)L.sj[b] - (int64_t)L.sj[a];
+    if (dj >= (int64_t)n || -dj >= (int64_t)n) return false;
+    const int64_t di = (int64_t)L.si[b] - (int64_t)L.si[a];
+    if (di >= (int64_t)n || -di >= (int64_t)n) return false;
+    const int64_t dd = diag_of(L.so[b], L.si[b], L.sj[b]) - diag_of(L.so[a], L.si[a], L.sj[a]);
+    return dd <= (int64_t)mo && -dd <= (int64_t)mo;
+}
+
+// First index in [lo, hi) whose key is not below x.
+__device__ __forceinline__ uint32_t cs_lower(const uint64_t *key, uint32_t lo, uint32_t hi, uint64_t x) {
+    while (lo < hi) {
+        const uint32_t m = (lo + hi) >> 1;
+        if (key[m] < x) lo = m + 1; else hi = m;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(CS_TB) k_chain_small(const uint32_t *seeds, uint32_t ns, CellKey ck,
+                                                       uint32_t n, uint32_t mo, const uint64_t *off,
+                                                       uint32_t nseq, sdf_candidate *out,
+                                                       uint32_t *nout) {
+    __shared__ ChainSmallLds L;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t n2 = 1;
+    while (n2 < ns) n2 <<= 1;
+    for (uint32_t t = tid; t < n2; t += CS_TB) {
+        uint64_t key = ~0ull;
+        if (t < ns) {
+            const uint32_t *r = seeds + (uint64_t)t * 6;
+            key = (group_of(ck, r) << ck.ibits) | r[1];
+        }
+        L.key[t] = key;
+        L.idx[t] = t;
+    }
+    // bitonic sort of (key, idx); equal keys may come in any order, which
+    // changes neither the components nor their aggregates
+    for (uint32_t k = 2; k <= n2; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            __syncthreads();
+            for (uint32_t t = tid; t < n2; t += CS_TB) {
+                const uint32_t u = t ^ j;
+                if (u > t) {
+                    const bool up = (t & k) == 0;
+                    const uint64_t a = L.key[t], b = L.key[u];
+                    if ((a > b) == up) {
+                        L.key[t] = b;
+                        L.key[u] = a;
+                        const uint32_t x = L.idx[t];
+                        L.idx[t] = L.idx[u];
+                        L.idx[u] = x;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t t = tid; t < ns; t += CS_TB) {
+        const uint32_t *r = seeds + (uint64_t)L.idx[t] * 6;
+        L.si[t] = r[1];
+        L.sj[t] = r[2];
+        L.so[t] = (uint8_t)r[3];
+        L.sc[t] = r[4];
+        L.sts[t] = seq_of(off, nseq, r[2]);
+    }
+    if (tid == 0) L.base = 0;
+    __syncthreads();
+    // segments: runs in which each seed links to the one before it; sid in
+    // qmin, segment heads (plus an end sentinel) in qmax, until aggregation
+    uint32_t *sid = L.qmin, *shead = L.qmax;
+    for (uint32_t t0 = 0; t0 < ns; t0 += CS_TB) {
+        const uint32_t t = t0 + tid;
+        bool head = false;
+        if (t < ns)
+            head = t == 0 || (L.key[t - 1] >> (ck.ibits + ck.cbits)) != (L.key[t] >> (ck.ibits + ck.cbits)) ||
+                   !cs_linked(L, t - 1, t, n, mo);
+        const uint64_t m = __ballot(head);
+        if (lane == 0) L.wsum[wave] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t before = L.base;
+        for (uint32_t w = 0; w < wave; w++) before += L.wsum[w];
+        const uint64_t le = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1);
+        if (t < ns) {
+            const uint32_t id = before + (uint32_t)__popcll(m & le) - 1;
+            sid[t] = id;
+            if (head) shead[id] = t;
+        }
+        __syncthreads();
+        if (tid == 0)
+            for (uint32_t w = 0; w < CS_TB / 64; w++) L.base += L.wsum[w];
+        __syncthreads();
+    }
+    if (tid == 0) shead[L.base] = ns;  // end sentinel: segments <= ns < CS_N
+    __syncthreads();
+    for (uint32_t t = tid; t < ns; t += CS_TB) L.par[t] = shead[sid[t]];
+    __syncthreads();
+    // links to later seeds past the own segment: own cell (i < ia + n),
+    // then the next cell (i in (ia - n, ia + n)); after a union the rest of
+    // the other seed's segment is connected already
+    for (uint32_t a = tid; a < ns; a += CS_TB) {
+        const uint64_t g = L.key[a] >> ck.ibits;
+        const uint32_t ia = L.si[a], sa = sid[a];
+        for (uint32_t b = shead[sa + 1]; b < ns && (L.key[b] >> ck.ibits) == g && L.si[b] < (uint64_t)ia + n;) {
+            if (cs_linked(L, a, b, n, mo)) {
+                cs_union(L.par, a, b);
+                b = shead[sid[b] + 1];
+            } else {
+                b++;
+            }
+        }
+        const uint64_t g2 = g + 1;
+        if ((g2 >> ck.cbits) != (g >> ck.cbits)) continue;
+        const uint32_t lim = ia >= n ? ia - n + 1 : 0;
+        for (uint32_t b = cs_lower(L.key, a + 1, ns, (g2 << ck.ibits) | lim);
+             b < ns && (L.key[b] >> ck.ibits) == g2 && L.si[b] < (uint64_t)ia + n;) {
+            const uint32_t sb = sid[b];
+            if (sb == sa) {
+                b = shead[sa + 1];
+            } else if (cs_linked(L, a, b, n, mo)) {
+                cs_union(L.par, a, b);
+                b = shead[sb + 1];
+            } else {
+                b++;
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t t = tid; t < ns; t += CS_TB) {
+        L.par[t] = cs_find(L.par, t);
+        L.qmin[t] = 0xFFFFFFFFu;
+        L.tmin[t] = 0xFFFFFFFFu;
+        L.qmax[t] = 0;
+        L.tmax[t] = 0;
+        L.cnt[t] = 0;
+        L.cmax[t] = 0;
+    }
+    __syncthreads();
+    for (uint32_t t = tid; t < ns; t += CS_TB) {
+        const uint32_t r = L.par[t];
+        atomicMin(&L.qmin[r], L.si[t]);
+        atomicMax(&L.qmax[r], L.si[t]);
+        atomicMin(&L.tmin[r], L.sj[t]);
+        atomicMax(&L.tmax[r], L.sj[t]);
+        atomicAdd(&L.cnt[r], 1u);
+        atomicMax(&L.cmax[r], L.sc[t]);
+    }
+    if (tid == 0) L.base = 0;
+    __syncthreads();
+    // one candidate per component root, written densely
+    for (uint32_t t0 = 0; t0 < ns; t0 += CS_TB) {
+        const uint32_t a = t0 + tid;
+        const bool root = a < ns && L.par[a] == a;
+        const uint64_t m = __ballot(root);
+        if (lane == 0) L.wsum[wave] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t before = L.base;
+        for (uint32_t w = 0; w < wave; w++) before += L.wsum[w];
+        const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+        if (root) {
+            sdf_candidate c;
+            const uint64_t gk = L.key[a] >> ck.ibits;
+            c.query_id = (uint32_t)(gk >> (ck.cbits + 1));
+            c.strand = (uint32_t)((gk >> ck.cbits) & 1);
+            c.q_seq = seq_of(off, nseq, L.qmin[a]);
+            c.t_seq = L.sts[a];
+            c.q_begin = L.qmin[a] - off[c.q_seq];
+            c.q_end = (uint64_t)L.qmax[a] + n - off[c.q_seq];
+            c.t_begin = L.tmin[a] - off[c.t_seq];
+            c.t_end = (uint64_t)L.tmax[a] + n - off[c.t_seq];
+            c.n_seeds = L.cnt[a];
+            c.max_shared = L.cmax[a];
+            out[before + (uint32_t)__popcll(m & lt)] = c;
+        }
+        __syncthreads();
+        if (tid == 0)
+            for (uint32_t w = 0; w < CS_TB / 64; w++) L.base += L.wsum[w];
+        __syncthreads();
+    }
+    if (tid == 0) *nout = L.base;
+}
+
 // ------------------------------------------------------------ record sort --
 __device__ __forceinline__ bool cand_less(const sdf_candidate &x, const sdf_candidate &y) {
 #define CMPF(f) if (x.f != y.f) return x.f < y.f;
@@ -403,6 +631,32 @@ void chain_seeds(const IndexView &ix, const uint32_t *seeds, uint64_t ns, uint32
     ck.ibits = bitlen(ix.total);
     const uint32_t qbits = bitlen(nspans > 0 ? nspans - 1 : 0);
     const uint32_t gbits = qbits + 1 + ck.cbits;
+    // fused path below CS_N seeds (room for the segment sentinel); the
+    // SDF_CHAIN_FUSED_MAX environment variable lowers the limit (0: off)
+    uint64_t fused_max = CS_N - 1;
+    if (const char *v = std::getenv("SDF_CHAIN_FUSED_MAX"))
+        fused_max = std::min<uint64_t>(fused_max, std::strtoull(v, nullptr, 10));
+    if (ns <= fused_max && gbits + ck.ibits <= 64) {
+        uint64_t cap = 1;
+        while (cap < ns) cap <<= 1;
+        out.cands.alloc(cap);
+        DevBuf<uint32_t> cnt(1);
+        k_chain_small<<<1, CS_TB, 0, st>>>(seeds, (uint32_t)ns, ck, n, mo, ix.off, ix.nseq,
+                                           out.cands.p, cnt.p);
+        SDF_HIP(hipGetLastError());
+        uint32_t nc = 0;
+        SDF_HIP(hipMemcpyAsync(&nc, cnt.p, 4, hipMemcpyDeviceToHost, st));
+        SDF_HIP(hipStreamSynchronize(st));
+        uint64_t n2 = 1;
+        while (n2 < nc) n2 <<= 1;
+        if (n2 > nc) {
+            k_pad_cands<<<nb(n2 - nc), 256, 0, st>>>(out.cands.p, nc, n2);
+            SDF_HIP(hipGetLastError());
+        }
+        sort_candidates(out.cands.p, n2, st);
+        out.ncands = nc;
+        return;
+    }
     DevBuf<uint64_t> gk(ns);
     DevBuf<uint32_t> order2(ns);
     uint32_t gshift = 0;

@@ -20,7 +20,7 @@ struct SearchArgs {
     const uint16_t *T;       // T[s] = ceil(tau * s)
     const SpanDesc *spans;
     uint32_t nspans;
-    uint32_t total_tiles;
+    const uint32_t *total_tiles;  // device: tiles over all spans
     uint32_t *work;          // tile counter (starts at 0)
     uint32_t core;           // window starts per tile
     uint32_t hpart;          // target hits per partition

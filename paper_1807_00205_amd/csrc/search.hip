@@ -92,7 +92,7 @@ struct TileLds {
     uint64_t wtmp[NWAVES + 1];
     uint64_t ph[PH_N];
     // scalars
-    uint32_t tile, c0, c1, Q, C, nwin, Tmin, ncoll, dup;
+    uint32_t tile, ntiles, c0, c1, Q, C, nwin, Tmin, ncoll, dup;
     uint32_t obeg[2], oend[2];
     uint32_t sp;
     uint32_t err;
@@ -437,13 +437,14 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
     uint64_t ph_t = prof ? wall_clock64() : 0;
     // per-wave bitmasks start empty; each use clears the words it counted
     uint32_t span_cache = 0;  // thread 0: span of the previous tile
+    if (threadIdx.x == 0) L.ntiles = *a.total_tiles;
     __syncthreads();
 
     for (;;) {
         if (threadIdx.x == 0) {
             const uint32_t t = atomicAdd(a.work, 1u);
             L.tile = t;
-            if (t < a.total_tiles) {
+            if (t < L.ntiles) {
                 // span of this tile: largest s with tile0[s] <= t (consecutive
                 // tiles mostly stay in one span)
                 uint32_t s = span_cache;
@@ -468,7 +469,7 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
             }
         }
         __syncthreads();
-        if (L.tile >= a.total_tiles) break;
+        if (L.tile >= L.ntiles) break;
 
         // A tile core may be processed in several pieces when its windows
         // reach more minimizers than fit on chip.

@@ -186,6 +186,31 @@ def test_search_config1_tile_shapes(S, oracle_lib, monkeypatch):
         _same(r.candidates(), oc, CAND_F, "candidates core=%d" % core)
 
 
+def test_chaining_fused_equals_general(S, oracle_lib, monkeypatch):
+    """The one-workgroup chaining used below 2,048 seeds and the multi-kernel
+    chaining give the same candidates (and the oracle's), for spans whose
+    seed counts fall on both sides of the limit."""
+    g = synth.config1()
+    b, off = g.concat()
+    orc = oracle_lib.OracleIndex(b, off, 12, 16)
+    ix = S.Index(g.seqs, 12, 16)
+    L0 = len(g.seqs[0])
+    spans = [(0, 0, L0), (0, 0, L0 // 4), (0, L0 // 3, L0 // 3 + 150_000), (0, 1000, 60_000)]
+    seen = set()
+    for sp in spans:
+        _, oc = orc.search([sp], 0.25, 1000)
+        out = []
+        for lim in ("0", "2047", "100000"):
+            monkeypatch.setenv("SDF_CHAIN_FUSED_MAX", lim)
+            r = ix.search(sp, 0.25, 1000)
+            out.append(r.candidates())
+            ns = r.stats()["seeds"]
+            seen.add(("fused" if ns <= min(int(lim), 2047) else "general", ns < 2048))
+        for c in out:
+            _same(c, oc, CAND_F, "candidates %s" % (sp,))
+    assert ("fused", True) in seen and ("general", False) in seen
+
+
 def test_edge_spans(S, oracle_lib):
     """Empty spans, spans shorter than n, spans at sequence ends, sequences
     shorter than k or made of gap bases, and several spans in one batch."""

@@ -209,7 +209,7 @@ def main():
     ap.add_argument("--cpu-sample-mbp", type=float, default=12.0)
     ap.add_argument("--no-batch", action="store_true", help="skip batched vs plain")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep")
-    ap.add_argument("--serve-rates", default="10,100,1000")
+    ap.add_argument("--serve-rates", default="10,100,1000,4000,8000")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--genome", action="store_true",

@@ -71,8 +71,10 @@ def lib():
         L.or_sketch_size.argtypes = [vp, u64, u32]
         L.or_count.restype = u32
         L.or_count.argtypes = [vp, u64, u64, u32, u32]
+        L.or_estimate.restype = u32
+        L.or_estimate.argtypes = [vp, u64, u64, u32, u32]
         L.or_search.restype = vp
-        L.or_search.argtypes = [vp, vp, u32, dbl, u32, ctypes.c_int, P(ctypes.c_int)]
+        L.or_search.argtypes = [vp, vp, u32, dbl, u32, ctypes.c_int, ctypes.c_int, P(ctypes.c_int)]
         L.or_result_nseeds.restype = u64
         L.or_result_nseeds.argtypes = [vp]
         L.or_result_ncands.restype = u64
@@ -188,11 +190,16 @@ class OracleIndex:
     def count(self, i: int, j: int, o: int, n: int) -> int:
         return int(lib().or_count(self._h, i, j, o, n))
 
-    def search(self, spans, max_error: float = 0.25, min_len: int = 1000, threads: int = 0):
+    def estimate(self, i: int, j: int, o: int, n: int) -> int:
+        """Numerator m of the winnowed MinHash estimate m / s_i."""
+        return int(lib().or_estimate(self._h, i, j, o, n))
+
+    def search(self, spans, max_error: float = 0.25, min_len: int = 1000, threads: int = 0,
+               estimate: bool = False):
         sp = np.ascontiguousarray(np.array(spans, dtype=np.uint64).reshape(-1, 3))
         st = ctypes.c_int()
-        r = lib().or_search(self._h, _ptr(sp), len(sp), max_error, min_len, threads,
-                            ctypes.byref(st))
+        r = lib().or_search(self._h, _ptr(sp), len(sp), max_error, min_len, int(estimate),
+                            threads, ctypes.byref(st))
         if st.value != 0:
             raise ValueError("oracle search failed: status %d" % st.value)
         try:

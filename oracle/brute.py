@@ -171,6 +171,30 @@ class Brute:
             c += v
         return c
 
+    def shared_hashes(self, i: int, j: int, o: int, n: int):
+        """Hashes with an eligible occurrence in [i, i+n) and one in [j, j+n)
+        of orientation o, never an occurrence with itself."""
+        out = set()
+        for q in self.window_minimizers(i, n):
+            if not q.eligible:
+                continue
+            for t in self.by_hash[q.h]:
+                if ((t.strand ^ q.strand) == o and t.pos != q.pos and j <= t.pos
+                        and t.pos + self.k <= j + n):
+                    out.add(q.h)
+        return out
+
+    def estimate(self, i: int, j: int, o: int, n: int) -> int:
+        """Winnowed MinHash numerator: shared hashes among the s smallest of
+        W(G_i) u W(G_j), s = |W(G_i)| (Section 2.2), by plain set operations."""
+        A = {m.h for m in self.window_minimizers(i, n)}
+        B = {m.h for m in self.window_minimizers(j, n)}
+        s = len(A)
+        SU = set(sorted(A | B)[:s])
+        SA = set(sorted(A)[:s])
+        SB = set(sorted(B)[:s])
+        return len(SU & SA & SB & self.shared_hashes(i, j, o, n))
+
     def hit_positions(self, i: int, o: int, n: int):
         out = set()
         for q in self.window_minimizers(i, n):
@@ -181,7 +205,7 @@ class Brute:
                     out.add(t.pos)
         return sorted(out)
 
-    def search(self, spans, max_error=0.25, min_len=1000):
+    def search(self, spans, max_error=0.25, min_len=1000, estimate=False):
         tau, n, mo = params(max_error, min_len, self.k)
         seeds = []
         for qid, (s, b, e) in enumerate(spans):
@@ -202,7 +226,8 @@ class Brute:
                     def flush():
                         if run:
                             best = max(run, key=lambda jc: (jc[1], -jc[0]))
-                            seeds.append((qid, i, best[0], o, best[1], s_i))
+                            if not estimate or best[1] >= T:
+                                seeds.append((qid, i, best[0], o, best[1], s_i))
 
                     for j in Jl:
                         cj = int(c[j])
@@ -214,7 +239,7 @@ class Brute:
                             flush()
                             run = []
                         if ok:
-                            run.append((j, cj))
+                            run.append((j, self.estimate(i, j, o, n) if estimate else cj))
                         prev = (j, tseq)
                     flush()
         seeds.sort()

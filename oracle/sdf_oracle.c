@@ -544,6 +544,106 @@ uint32_t or_count(void *p, uint64_t i, uint64_t j, uint32_t o, uint32_t n)
     return c;
 }
 
+/* Distinct hashes of all minimizers whose k-mer lies in [a, a+n), sorted
+ * ascending: the winnow W(G_a) of the window as a set (masked ones included,
+ * as for the sketch size). */
+static uint32_t *or_window_hashes(const or_index *ix, uint64_t a, uint32_t n, uint32_t *len)
+{
+    uint64_t lo, hi;
+    or_m_range(ix, a, a + n - ix->k, &lo, &hi);
+    uint32_t *v = (uint32_t *)malloc((hi - lo + 1) * sizeof(uint32_t));
+    for (uint64_t q = lo; q < hi; q++)
+        v[q - lo] = ix->m_hash[q];
+    qsort(v, hi - lo, sizeof(uint32_t), cmp_u32);
+    uint32_t u = 0;
+    for (uint64_t q = 0; q < hi - lo; q++)
+        if (q == 0 || v[q] != v[u - 1])
+            v[u++] = v[q];
+    *len = u;
+    return v;
+}
+
+static int or_in(const uint32_t *sorted, uint32_t len, uint32_t h)
+{
+    return bsearch(&h, sorted, len, sizeof(uint32_t), cmp_u32) != NULL;
+}
+
+/* Numerator of the winnowed MinHash estimate (Section 2.2):
+ *   |S[W_i u W_j] n S[W_i] n S[W_j]|, sketch size s = |W_i| (Section 3.1),
+ * S[X] the s smallest hashes of X.  A = W_i (its s hashes), B = W_j, both
+ * sorted and distinct.  Reading: a hash counts as lying in both windows only
+ * when it is shared in the sense of the count (eligible occurrences on both
+ * sides, orientation o, never an occurrence with itself): in_c[r] says so for
+ * A[r].  The denominator |S[W_i u W_j]| is s, since the union holds W_i. */
+static uint32_t or_estimate_num(const uint32_t *A, uint32_t s, const uint32_t *B, uint32_t nb,
+                                const uint8_t *in_c)
+{
+    /* S[W_i u W_j]: the s smallest of the union (merge of two sorted sets) */
+    uint32_t *su = (uint32_t *)malloc((s + 1) * sizeof(uint32_t));
+    uint32_t ia = 0, ib = 0, nu = 0;
+    while (nu < s && (ia < s || ib < nb)) {
+        uint32_t h;
+        if (ib >= nb || (ia < s && A[ia] < B[ib]))
+            h = A[ia++];
+        else if (ia >= s || B[ib] < A[ia])
+            h = B[ib++];
+        else {
+            h = A[ia];
+            ia++;
+            ib++;
+        }
+        su[nu++] = h;
+    }
+    const uint32_t sb = nb < s ? nb : s; /* S[W_j]: the s smallest of B */
+    uint32_t num = 0;
+    for (uint32_t u = 0; u < nu; u++) {
+        const uint32_t h = su[u];
+        uint32_t *at = (uint32_t *)bsearch(&h, A, s, sizeof(uint32_t), cmp_u32);
+        if (at == NULL) /* not in S[W_i] = W_i */
+            continue;
+        if (!or_in(B, sb, h)) /* not in S[W_j] */
+            continue;
+        if (in_c[at - A])
+            num++;
+    }
+    free(su);
+    return num;
+}
+
+/* m(i, j): the estimate's numerator for query window [i, i+n) and target
+ * window [j, j+n) in orientation o, from the definitions above. */
+uint32_t or_estimate(void *p, uint64_t i, uint64_t j, uint32_t o, uint32_t n)
+{
+    or_index *ix = (or_index *)p;
+    uint32_t k = ix->k, s, nb;
+    uint32_t *A = or_window_hashes(ix, i, n, &s);
+    uint32_t *B = or_window_hashes(ix, j, n, &nb);
+    uint8_t *in_c = (uint8_t *)calloc(s + 1, 1);
+    uint64_t qlo, qhi;
+    or_m_range(ix, i, i + n - k, &qlo, &qhi);
+    for (uint64_t q = qlo; q < qhi; q++) {
+        if (!(ix->m_flags[q] & MF_ELIG))
+            continue;
+        uint8_t a = ix->m_flags[q] & MF_STRAND;
+        uint64_t lo, hi;
+        or_lookup(ix, ix->m_hash[q], (uint8_t)(a ^ o), &lo, &hi);
+        for (uint64_t e = lo; e < hi; e++) {
+            uint64_t pp = ix->e_pos[e];
+            if (pp >= j && pp + k <= j + n && pp != ix->m_pos[q]) {
+                uint32_t h = ix->m_hash[q];
+                uint32_t *at = (uint32_t *)bsearch(&h, A, s, sizeof(uint32_t), cmp_u32);
+                in_c[at - A] = 1;
+                break;
+            }
+        }
+    }
+    uint32_t m = or_estimate_num(A, s, B, nb, in_c);
+    free(in_c);
+    free(B);
+    free(A);
+    return m;
+}
+
 /* ------------------------------------------------------------------ */
 /* Seed search. */
 
@@ -609,9 +709,13 @@ static int cmp_hit(const void *a, const void *b)
  *    candidates that all pass, in one sequence, each less than n after the
  *    previous one;
  *  - "maximal and above tau" is the largest shared count in the run, the
- *    smallest j among ties. */
+ *    smallest j among ties;
+ *  - with `estimate`, it is the largest winnowed MinHash estimate m/s in the
+ *    run instead (smallest j among ties), and the run gives a seed only if
+ *    that estimate is at least tau (m >= T(s_i)); the seed's c field then
+ *    holds m. */
 static void or_window(const or_index *ix, uint32_t qid, uint64_t i, uint32_t o, uint32_t n,
-                      uint32_t max_overlap, const uint32_t *T, seedbuf *out)
+                      uint32_t max_overlap, const uint32_t *T, int estimate, seedbuf *out)
 {
     uint32_t k = ix->k;
     uint64_t qlo, qhi;
@@ -663,6 +767,7 @@ static void or_window(const or_index *ix, uint32_t qid, uint64_t i, uint32_t o, 
 
     int in_run = 0;
     uint32_t run_best_j = 0, run_best_c = 0, prev_j = 0, prev_seq = 0;
+    uint8_t *in_c = estimate ? (uint8_t *)calloc(s + 1, 1) : NULL;
 
     for (uint64_t e = 0; e < nh; e++) {
         if (e > 0 && hits[e].pos == hits[e - 1].pos)
@@ -691,27 +796,39 @@ static void or_window(const or_index *ix, uint32_t qid, uint64_t i, uint32_t o, 
         int pass = (shared >= Ti) && !excl;
         /* continue the run only across consecutive candidates */
         if (in_run && !(pass && tseq == prev_seq && j - prev_j < n)) {
-            or_seed sd = {qid, (uint32_t)i, run_best_j, o, run_best_c, s};
-            seedbuf_push(out, sd);
+            if (!estimate || run_best_c >= Ti) {
+                or_seed sd = {qid, (uint32_t)i, run_best_j, o, run_best_c, s};
+                seedbuf_push(out, sd);
+            }
             in_run = 0;
         }
         if (pass) {
+            uint32_t score = shared;
+            if (estimate) {
+                uint32_t nb;
+                uint32_t *B = or_window_hashes(ix, j, n, &nb);
+                for (uint32_t r = 0; r < s; r++)
+                    in_c[r] = cnt[r] > 0;
+                score = or_estimate_num(hs, s, B, nb, in_c);
+                free(B);
+            }
             if (!in_run) {
                 in_run = 1;
                 run_best_j = (uint32_t)j;
-                run_best_c = shared;
-            } else if (shared > run_best_c) {
+                run_best_c = score;
+            } else if (score > run_best_c) {
                 run_best_j = (uint32_t)j;
-                run_best_c = shared;
+                run_best_c = score;
             }
         }
         prev_j = (uint32_t)j;
         prev_seq = tseq;
     }
-    if (in_run) {
+    if (in_run && (!estimate || run_best_c >= Ti)) {
         or_seed sd = {qid, (uint32_t)i, run_best_j, o, run_best_c, s};
         seedbuf_push(out, sd);
     }
+    free(in_c);
     free(cnt);
     free(hits);
     free(hs);
@@ -864,7 +981,7 @@ static void or_chain(const or_index *ix, or_seed *sd, uint64_t ns, uint32_t n,
  * pairs j whose winnowed similarity clears tau.  Status: 0 ok, -1 invalid
  * argument, -4 span outside its sequence. */
 void *or_search(void *p, const uint64_t *spans, uint32_t nspans, double max_error,
-                uint32_t min_len, int threads, int *status)
+                uint32_t min_len, int estimate, int threads, int *status)
 {
     or_index *ix = (or_index *)p;
     double tau;
@@ -914,8 +1031,8 @@ void *or_search(void *p, const uint64_t *spans, uint32_t nspans, double max_erro
                 uint64_t i = ix->m_pos[m];
                 if (!or_window_ok(ix, i, n))
                     continue;
-                or_window(ix, t, i, 0, n, max_overlap, T, &mine);
-                or_window(ix, t, i, 1, n, max_overlap, T, &mine);
+                or_window(ix, t, i, 0, n, max_overlap, T, estimate, &mine);
+                or_window(ix, t, i, 1, n, max_overlap, T, estimate, &mine);
             }
 #pragma omp critical
             {

@@ -324,6 +324,59 @@ def test_max_over_hits_equals_max_over_all_starts(tiny):
             assert best_all == best_hit
 
 
+def test_estimate_matches_bruteforce(tiny):
+    """NEXT-f1 pin: the winnowed MinHash numerator m (shared hashes among the
+    s_i smallest of W(G_i) u W(G_j), Section 2.2) from the oracle equals a
+    plain set computation on the brute force's own winnow, at every target
+    start where the windows share a hash; m <= c always."""
+    g, b, off, ix, br = tiny
+    n = 150
+    checked = 0
+    for m in br.elig[::5]:
+        i = m.pos
+        if i + n > br.total:
+            continue
+        for o in (0, 1):
+            for j in br.hit_positions(i, o, n)[::2]:
+                if j + n > br.total:
+                    continue
+                want = br.estimate(i, j, o, n)
+                assert ix.estimate(i, j, o, n) == want, (i, j, o)
+                assert want <= ix.count(i, j, o, n)
+                checked += 1
+    assert checked > 200
+
+
+def test_estimate_closed_forms(oracle_lib):
+    """NEXT-f1 pins: when W(G_j) holds no hash outside W(G_i) the union's
+    sketch is W(G_i) itself, so m equals the shared count c; for an exact
+    copy (no mutation) of an all-upper-case stretch every hash is shared and
+    m = c = s_i (estimate 1)."""
+    rng = synth.rng_for(7)
+    unit = synth.random_bases(rng, 900)
+    seq = np.concatenate([synth.random_bases(rng, 300), unit, synth.random_bases(rng, 400), unit,
+                          synth.random_bases(rng, 300)])
+    b, off = seq.tobytes(), np.array([0, len(seq)], np.uint64)
+    ix = oracle_lib.OracleIndex(np.frombuffer(b, np.uint8), off, 12, 16)
+    n = 600
+    from oracle import brute
+    br = brute.Brute(np.frombuffer(b, np.uint8), off, 12, 16)
+    i0, j0 = 300, 300 + 900 + 400
+    hits = 0
+    for d in range(0, 250, 3):
+        i, j = i0 + d, j0 + d
+        A = {m.h for m in br.window_minimizers(i, n)}
+        B = {m.h for m in br.window_minimizers(j, n)}
+        c = ix.count(i, j, 0, n)
+        m = ix.estimate(i, j, 0, n)
+        if B <= A:
+            assert m == c
+            hits += 1
+        if A == B and all(mm.eligible for mm in br.window_minimizers(i, n)):
+            assert m == c == len(A) == ix.sketch_size(i, n)
+    assert hits > 20
+
+
 def test_strand_mirror(oracle_lib):
     """P9: for G' = revcomp(G) without tied window minima, the winnow
     mirrors (p -> N-k-p, strand flipped) and c_o^G(i,j) =
@@ -410,6 +463,29 @@ def test_search_tandem_matches_bruteforce(oracle_lib, seed, max_error, min_len, 
     assert len(bs) > 0
     assert [tuple(int(v) for v in x) for x in seeds] == bs
     assert [tuple(int(v) for v in x) for x in cands] == bc
+
+
+@pytest.mark.parametrize("case", CASES[:3], ids=lambda c: "seed%d" % c["seed"])
+@pytest.mark.parametrize("max_error,min_len,k,w", [(0.25, 200, 12, 16), (0.3, 120, 9, 5)])
+def test_search_estimate_matches_bruteforce(oracle_lib, case, max_error, min_len, k, w):
+    """NEXT-f1: with seeds chosen by the largest winnowed MinHash estimate in
+    each run (kept only when it reaches the threshold), the oracle's seeds and
+    candidates equal the brute force's."""
+    from oracle import brute
+    c = dict(case)
+    seed = c.pop("seed")
+    g = synth.small_case(60 + seed, sd_lo=300, sd_hi=600, gap_len=25, rate_hi=0.06, **c)
+    b, off = g.concat()
+    spans = list(g.spans) + [(0, 100, len(g.seqs[0]) - 50)]
+    ix = oracle_lib.OracleIndex(b, off, k, w)
+    seeds, cands = ix.search(spans, max_error, min_len, estimate=True)
+    cseeds, _ = ix.search(spans, max_error, min_len)
+    br = brute.Brute(b, off, k, w)
+    bs, bc = br.search(spans, max_error, min_len, estimate=True)
+    assert len(bs) > 0
+    assert [tuple(int(v) for v in x) for x in seeds] == bs
+    assert [tuple(int(v) for v in x) for x in cands] == bc
+    assert len(seeds) <= len(cseeds)
 
 
 def test_search_rejects_bad_arguments(oracle_lib):

@@ -68,7 +68,7 @@ typedef struct {
  * targets delta <= 0.25).  min_len: minimum duplication length L (Section 2:
  * 1000 bp); the seed window length is n = ceil(L (1 - delta)) (Section 3).
  * Requires k + w - 1 <= n <= 65536.  flags: SDF_TIMING records per-stage GPU
- * times. */
+ * times; SDF_SEED_ESTIMATE chooses seeds by the winnowed MinHash estimate. */
 typedef struct {
     double max_error;
     uint32_t min_len;
@@ -76,6 +76,15 @@ typedef struct {
 } sdf_search_params;
 
 #define SDF_TIMING 1u
+/* Seeds by the winnowed MinHash estimate (Section 2.2; "maximal" in Section
+ * 3.1): runs of passing candidates are formed by the shared-count filter as
+ * without the flag, but each run's seed is its candidate with the largest
+ * estimate m / s (m = shared hashes among the s = |W(G_i)| smallest hashes of
+ * W(G_i) u W(G_j)), earliest j on ties, and a run whose largest estimate is
+ * below tau (m < ceil(tau s)) gives no seed.  The seed's c field and the
+ * candidates' max_shared then hold m.  Windows of more than 1024 minimizers
+ * are rejected with SDF_EINTERNAL in this mode. */
+#define SDF_SEED_ESTIMATE 2u
 
 /* A query span [begin, end) of sequence `seq`. */
 typedef struct {

@@ -216,6 +216,7 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
             a.counters = counters.p;
             a.err = work.p + 1;
             a.phase = phase_prof ? phase.p : nullptr;
+            a.runs_out = (p->flags & SDF_SEED_ESTIMATE) ? 1u : 0u;
             // persistent grid: workgroups past the last tile exit at once
             const uint32_t grid = (uint32_t)cu_count(ix->device) * env_u32("SDF_WG_PER_CU", 1);
             tm.mark_kernel_begin();
@@ -263,6 +264,30 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
     res->stats[5] = hc[CNT_SEEDS];
     res->stats[6] = hc[CNT_EVALS];
     res->stats[7] = hc[CNT_SCAN];
+    if (p->flags & SDF_SEED_ESTIMATE) {
+        // the tile kernel wrote runs (first j, last j); pick each run's seed by
+        // the winnowed MinHash estimate
+        const uint64_t nruns = res->nseeds;
+        DevBuf<uint32_t> est((nruns ? nruns : 1) * 6);
+        DevBuf<unsigned long long> ecount(1);
+        DevBuf<uint32_t> eerr(1);
+        SDF_HIP(hipMemsetAsync(ecount.p, 0, 8, st));
+        SDF_HIP(hipMemsetAsync(eerr.p, 0, 4, st));
+        launch_estimate_runs(ix->view(), res->seeds.p, nruns, P.n, dT.p, est.p, nruns, ecount.p,
+                             eerr.p, st);
+        unsigned long long ne = 0;
+        uint32_t ee = 0;
+        SDF_HIP(hipMemcpyAsync(&ne, ecount.p, 8, hipMemcpyDeviceToHost, st));
+        SDF_HIP(hipMemcpyAsync(&ee, eerr.p, 4, hipMemcpyDeviceToHost, st));
+        SDF_HIP(hipStreamSynchronize(st));
+        if (ee & 1)
+            throw Error{SDF_EINTERNAL, "estimate: a window holds more than 1024 minimizers"};
+        if (ee)
+            throw Error{SDF_EINTERNAL, "estimate: sketch size of a run does not match its window"};
+        res->seeds = std::move(est);
+        res->nseeds = ne;
+        res->stats[5] = ne;
+    }
     chain_seeds(ix->view(), res->seeds.p, res->nseeds, P.n, P.max_overlap, nq, res->chain, st);
     tm.mark();
     tm.mark();

@@ -4,6 +4,26 @@
 
 namespace sdf {
 
+// Segment (gap-free stretch of one sequence) holding global position x, or -1.
+__device__ __forceinline__ int64_t segment_of(const IndexView &ix, uint64_t x) {
+    uint64_t lo = 0, hi = ix.nseg;  // first segb > x
+    while (lo < hi) {
+        uint64_t mid = (lo + hi) >> 1;
+        if (ix.segb[mid] <= x) lo = mid + 1; else hi = mid;
+    }
+    return (int64_t)lo - 1;
+}
+
+// Window [x, x+n) lies in one gap-free stretch of one sequence.
+__device__ __forceinline__ bool window_ok(const IndexView &ix, uint64_t x, uint32_t n,
+                                          uint32_t *seq) {
+    int64_t t = segment_of(ix, x);
+    if (t < 0) return false;
+    if (seq) *seq = ix.segseq[t];
+    return x + n <= ix.sege[t];
+}
+
+
 struct SpanDesc {
     uint64_t gb, ge;        // global [begin, end) of the span
     uint32_t qid, qseq;     // query id, sequence of the span
@@ -30,11 +50,19 @@ struct SearchArgs {
     unsigned long long *counters;  // CNT_N
     uint32_t *err;
     unsigned long long *phase;     // PH_N wall-clock ticks per phase, or null
+    uint32_t runs_out;       // 1: emit each run (first j, last j in the c field) instead of its seed
 };
 
 // Phases of the tile kernel for the optional wall-clock breakdown.
 enum { PH_SETUP = 0, PH_QUERY, PH_LISTS, PH_PLISTS, PH_PASS1, PH_PASS2, PH_SORT, PH_HOT,
        PH_SEGINFO, PH_EVAL, PH_FLUSH, PH_N };
+
+// Seeds chosen by the winnowed MinHash estimate: one wave per run record
+// (qid, i, first j, o, last j, s); emits (qid, i, j, o, m, s) for the run's
+// candidate with the largest m (earliest j on ties) when m >= T[s].
+void launch_estimate_runs(const IndexView &ix, const uint32_t *runs, uint64_t nruns, uint32_t n,
+                          const uint16_t *T, uint32_t *seeds, uint64_t cap,
+                          unsigned long long *nseeds, uint32_t *err, hipStream_t st);
 
 void launch_span_setup(const IndexView &ix, SpanDesc *spans, uint32_t nspans, uint32_t n,
                        uint32_t core, uint32_t *ntiles, uint32_t *tile0, hipStream_t st);

@@ -216,24 +216,6 @@ __device__ void block_bitonic_u64(uint64_t *s, int n2) {
 }
 
 // Gap-free segment containing position x: index or -1.
-__device__ __forceinline__ int64_t segment_of(const IndexView &ix, uint64_t x) {
-    uint64_t lo = 0, hi = ix.nseg;  // first segb > x
-    while (lo < hi) {
-        uint64_t mid = (lo + hi) >> 1;
-        if (ix.segb[mid] <= x) lo = mid + 1; else hi = mid;
-    }
-    return (int64_t)lo - 1;
-}
-
-// Window [x, x+n) lies in one gap-free stretch of one sequence.
-__device__ __forceinline__ bool window_ok(const IndexView &ix, uint64_t x, uint32_t n,
-                                          uint32_t *seq) {
-    int64_t t = segment_of(ix, x);
-    if (t < 0) return false;
-    if (seq) *seq = ix.segseq[t];
-    return x + n <= ix.sege[t];
-}
-
 // Entry range of I_G^{-1} for (hash, strand).
 __device__ __forceinline__ void lookup(const IndexView &ix, uint32_t hash, uint32_t strand,
                                        uint32_t &lo, uint32_t &hi) {
@@ -1007,11 +989,13 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                                 }
                                 const bool pass = mine && cnt >= Ti && !excl;
                                 const bool link = pass && rs.active && tseq == rs.prev_seq && j - rs.prev_j < n;
+                                // a run ends: its seed, or with runs_out its first and
+                                // last candidate (the previous one) for the estimate
                                 seeds_push_lanes(a, sbuf, lane, mine && rs.active && !link, L.qid, i,
-                                                 rs.best_j, o, rs.best_c, si);
+                                                 rs.best_j, o, a.runs_out ? rs.prev_j : rs.best_c, si);
                                 if (mine) {
                                     if (link) {
-                                        if (cnt > rs.best_c) {
+                                        if (!a.runs_out && cnt > rs.best_c) {
                                             rs.best_c = (uint16_t)cnt;
                                             rs.best_j = j;
                                         }
@@ -1057,7 +1041,7 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                         mine = rs.active != 0;
                     }
                     seeds_push_lanes(a, sbuf, lane, mine, L.qid, mine ? L.qpos[qc] : 0, rs.best_j,
-                                     o, rs.best_c, mine ? L.win_s[qc] : 0);
+                                     o, a.runs_out ? rs.prev_j : rs.best_c, mine ? L.win_s[qc] : 0);
                 }
                 seeds_flush(a, sbuf, lane);
             }

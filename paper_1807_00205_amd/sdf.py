@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libsdf.so")
 SDF_OK, SDF_EINVAL, SDF_ENOMEM, SDF_EDEVICE, SDF_ERANGE, SDF_EBUSY, SDF_EINTERNAL = (
     0, -1, -2, -3, -4, -5, -6)
 SDF_TIMING = 1
+SDF_SEED_ESTIMATE = 2
 
 CANDIDATE_DTYPE = np.dtype([("query_id", "<u4"), ("strand", "<u4"), ("q_seq", "<u4"),
                             ("t_seq", "<u4"), ("q_begin", "<u8"), ("q_end", "<u8"),
@@ -30,6 +31,10 @@ EXPORTS = ["sdf_last_error", "sdf_index_build", "sdf_index_info", "sdf_index_hit
            "sdf_index_entries", "sdf_index_packed", "sdf_index_free", "sdf_search",
            "sdf_search_batch", "sdf_result_count", "sdf_result_copy", "sdf_result_seed_count",
            "sdf_result_seeds", "sdf_result_timing", "sdf_result_stats", "sdf_result_free"]
+
+
+def _flags(timing: bool, estimate: bool) -> int:
+    return (SDF_TIMING if timing else 0) | (SDF_SEED_ESTIMATE if estimate else 0)
 
 
 class SdfError(RuntimeError):
@@ -250,19 +255,20 @@ class Index:
         return pk, mk, gp
 
     def search(self, span: Tuple[int, int, int], max_error: float = 0.25, min_len: int = 1000,
-               timing: bool = False, stream=None) -> Result:
+               timing: bool = False, stream=None, estimate: bool = False) -> Result:
         sp = _Span(span[0], 0, span[1], span[2])
-        p = _SearchParams(max_error, min_len, SDF_TIMING if timing else 0)
+        p = _SearchParams(max_error, min_len, _flags(timing, estimate))
         h = ctypes.c_void_p()
         _check(lib().sdf_search(self._h, ctypes.byref(sp), ctypes.byref(p), _stream_ptr(stream),
                                 ctypes.byref(h)))
         return Result(h.value)
 
     def search_batch(self, spans: Iterable[Tuple[int, int, int]], max_error: float = 0.25,
-                     min_len: int = 1000, timing: bool = False, stream=None) -> Result:
+                     min_len: int = 1000, timing: bool = False, stream=None,
+                     estimate: bool = False) -> Result:
         spans = list(spans)
         arr = (_Span * max(1, len(spans)))(*[_Span(s, 0, b, e) for (s, b, e) in spans])
-        p = _SearchParams(max_error, min_len, SDF_TIMING if timing else 0)
+        p = _SearchParams(max_error, min_len, _flags(timing, estimate))
         h = ctypes.c_void_p()
         _check(lib().sdf_search_batch(self._h, ctypes.cast(arr, ctypes.c_void_p), len(spans),
                                       ctypes.byref(p), _stream_ptr(stream), ctypes.byref(h)))

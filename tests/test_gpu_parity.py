@@ -159,6 +159,51 @@ def test_search_tandem(S, oracle_lib, seed, length, n_seqs, max_error, min_len, 
     _same(r.candidates(), oc, CAND_F, "candidates")
 
 
+@pytest.mark.parametrize("case", SMALL, ids=lambda c: "seed%d" % c["seed"])
+@pytest.mark.parametrize("max_error,min_len,k,w", [(0.25, 200, 12, 16), (0.3, 120, 9, 5)])
+def test_search_estimate_small(S, oracle_lib, case, max_error, min_len, k, w):
+    """Seeds chosen by the winnowed MinHash estimate: seeds (with m in the
+    count field) and candidates equal the oracle's estimate mode."""
+    c = dict(case)
+    seed = c.pop("seed")
+    g = synth.small_case(60 + seed, sd_lo=300, sd_hi=600, gap_len=25, rate_hi=0.06, **c)
+    b, off = g.concat()
+    L0 = len(g.seqs[0])
+    spans = list(g.spans) + [(0, 100, L0 - 50), (0, L0 // 3, L0 // 3 + 700)]
+    orc = oracle_lib.OracleIndex(b, off, k, w)
+    os_, oc = orc.search(spans, max_error, min_len, estimate=True)
+    ix = S.Index(g.seqs, k, w)
+    r = ix.search_batch(spans, max_error, min_len, estimate=True)
+    _same(r.seeds(), os_, SEED_F, "seeds")
+    _same(r.candidates(), oc, CAND_F, "candidates")
+
+
+@pytest.mark.parametrize("seed,length,n_seqs,min_len,k,w", [(2, 3000, 2, 200, 12, 16),
+                                                            (3, 200_000, 3, 1000, 12, 16),
+                                                            (1, 3000, 1, 120, 9, 5)])
+def test_search_estimate_tandem_and_config1(S, oracle_lib, seed, length, n_seqs, min_len, k, w):
+    """Estimate mode where windows repeat hashes (tandem arrays), and on the
+    1 Mbp workload: exact seeds and candidates."""
+    g = synth.tandem_case(90 + seed, length=length, n_arrays=5 if length < 10000 else 120,
+                          copies_hi=20 if length < 10000 else 60, n_seqs=n_seqs)
+    b, off = g.concat()
+    orc = oracle_lib.OracleIndex(b, off, k, w)
+    os_, oc = orc.search(g.spans, 0.25, min_len, estimate=True)
+    ix = S.Index(g.seqs, k, w)
+    r = ix.search_batch(g.spans, 0.25, min_len, estimate=True)
+    assert len(os_) > 0
+    _same(r.seeds(), os_, SEED_F, "seeds")
+    _same(r.candidates(), oc, CAND_F, "candidates")
+    g = synth.config1()
+    b, off = g.concat()
+    orc = oracle_lib.OracleIndex(b, off, 12, 16)
+    os_, oc = orc.search(g.spans, 0.25, 1000, estimate=True)
+    ix = S.Index(g.seqs, 12, 16)
+    r = ix.search(g.spans[0], 0.25, 1000, estimate=True)
+    _same(r.seeds(), os_, SEED_F, "seeds config1")
+    _same(r.candidates(), oc, CAND_F, "candidates config1")
+
+
 def test_search_config1(S, oracle_lib):
     """The 1 Mbp workload, self against self: exact seeds and candidates."""
     g = synth.config1()

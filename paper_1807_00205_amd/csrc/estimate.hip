@@ -15,22 +15,52 @@
 // given by its first and last candidate; every candidate between them
 // belongs to it.  One wave takes one run: it sorts the query window's
 // hashes once, enumerates the run's candidates from the minimizer array,
-// computes m for each, and emits the seed of the largest m (earliest j on
-// ties) when m reaches the threshold T[s].
+// computes m for each whose shared count could beat the best so far, and
+// emits the seed of the largest m (earliest j on ties) when m reaches the
+// threshold T[s].
+#include <algorithm>
+#include <cstdlib>
+
 #include "search.h"
 
 namespace sdf {
 
-constexpr int EW = 4;         // runs (waves) per workgroup
+constexpr int EW = 3;         // runs (waves) per workgroup
 constexpr int EAMAX = 1024;   // minimizers of one window a wave holds
+constexpr int TCAP = 512;     // target minimizers of one run held in LDS
+constexpr uint16_t TR_IN = 0x8000, TR_SHARED = 0x4000, TR_RANK = 0x3FF;
 
 struct EstWave {
-    uint64_t key[EAMAX];      // query (hash << 32 | index), later target hashes outside W_i
+    union {
+        uint64_t key[EAMAX];  // query sort: hash << 32 | index in the window
+        struct {              // the run's target minimizers (positions jf .. jl + n - k)
+            uint32_t tp[TCAP], th[TCAP];
+            uint16_t tr[TCAP];    // TR_IN: hash in W_i (rank in TR_RANK); TR_SHARED: pairs in o
+            uint32_t out[TCAP];   // hashes of one target window outside W_i
+            uint8_t first[TCAP];  // first of its value among them
+        } run;
+        struct {              // a run too long for `run`: one target window at a time
+            uint32_t out[EAMAX];
+            uint8_t first[EAMAX];
+        } big;
+    } u;
     uint32_t ahash[EAMAX];    // distinct query hashes, ascending (W_i)
     uint32_t acnt[EAMAX];     // eligible occurrences per hash: strand 0 low 16 bits, strand 1 high
-    uint32_t apos[EAMAX][2];  // position of an eligible occurrence per strand
     uint64_t cbits[EAMAX / 64];  // shared hashes by rank in W_i
 };
+static_assert(sizeof(((EstWave *)nullptr)->u.run) <= sizeof(uint64_t) * EAMAX, "run overlay");
+
+// A target occurrence (minimizer index tm, strand b, hash of rank r in W_i)
+// pairs in orientation o when the window holds an eligible query occurrence
+// of strand b ^ o other than itself; it can be itself only for o = 0 and tm
+// inside the query window's minimizer range [q0, q0 + na).
+__device__ __forceinline__ bool pairs(const EstWave &L, uint32_t r, uint32_t b, uint32_t o,
+                                      uint64_t tm, uint64_t q0, uint32_t na) {
+    const uint32_t a = b ^ o;
+    const uint32_t c = (L.acnt[r] >> (16 * a)) & 0xFFFFu;
+    const uint32_t self = (o == 0 && tm >= q0 && tm < q0 + na) ? 1u : 0u;
+    return c > self;
+}
 
 __device__ __forceinline__ uint32_t e_lane() { return threadIdx.x & 63; }
 
@@ -83,17 +113,97 @@ __device__ __forceinline__ uint32_t rank_below(const uint32_t *ahash, uint32_t s
     return lo;
 }
 
+// From the shared marks (cbits) and the nb hashes of W_j outside W_i in
+// out[0, nb): c when it cannot beat `beat`, else m.
+__device__ uint32_t estimate_finish(EstWave &L, const uint32_t *out, uint8_t *first, uint32_t s,
+                                    uint32_t nb, bool have, uint32_t beat, uint32_t reg_cap) {
+    const uint32_t lane = e_lane();
+    const uint32_t nw = (s + 63) >> 6;
+    __builtin_amdgcn_wave_barrier();
+    uint32_t c = 0;  // shared count
+    if (lane < nw) c = (uint32_t)__popcll(L.cbits[lane]);
+    for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
+    if (have && c <= beat) return c;
+    // y: distinct outside hashes among the s smallest of the union: b is one
+    // iff (distinct outside hashes below b) + (hashes of W_i below b) < s
+    uint32_t y = 0;
+    if (nb <= reg_cap) {  // reg_cap <= 128
+        // two per lane in registers, compared through lane broadcasts
+        const uint32_t h0 = lane < nb ? out[lane] : 0u, h1 = lane + 64 < nb ? out[lane + 64] : 0u;
+        bool d0 = false, d1 = false;  // repeats an earlier value
+        for (uint32_t t = 0; t < nb; t++) {
+            const uint32_t v = t < 64 ? (uint32_t)__builtin_amdgcn_readlane((int)h0, (int)t)
+                                      : (uint32_t)__builtin_amdgcn_readlane((int)h1, (int)(t - 64));
+            d0 |= t < lane && v == h0;
+            d1 |= t < lane + 64 && v == h1;
+        }
+        const bool f0 = lane < nb && !d0, f1 = lane + 64 < nb && !d1;
+        const uint64_t fm0 = __ballot(f0), fm1 = __ballot(f1);
+        uint32_t b0 = f0 ? rank_below(L.ahash, s, h0) : s, b1 = f1 ? rank_below(L.ahash, s, h1) : s;
+        for (uint32_t t = 0; t < nb; t++) {
+            const bool ft = t < 64 ? ((fm0 >> t) & 1) : ((fm1 >> (t - 64)) & 1);
+            if (!ft) continue;
+            const uint32_t v = t < 64 ? (uint32_t)__builtin_amdgcn_readlane((int)h0, (int)t)
+                                      : (uint32_t)__builtin_amdgcn_readlane((int)h1, (int)(t - 64));
+            b0 += v < h0 ? 1u : 0u;
+            b1 += v < h1 ? 1u : 0u;
+        }
+        y = (uint32_t)__popcll(__ballot(f0 && b0 < s)) + (uint32_t)__popcll(__ballot(f1 && b1 < s));
+    } else {
+        for (uint32_t x = lane; x < nb; x += 64) {
+            const uint32_t h = out[x];
+            bool f = true;
+            for (uint32_t t = 0; t < x; t++)
+                if (out[t] == h) {
+                    f = false;
+                    break;
+                }
+            first[x] = f ? 1 : 0;
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t x0 = 0; x0 < nb; x0 += 64) {
+            const uint32_t x = x0 + lane;
+            bool in = false;
+            if (x < nb && first[x]) {
+                const uint32_t h = out[x];
+                uint32_t below = rank_below(L.ahash, s, h);
+                for (uint32_t t = 0; t < nb && below < s; t++)
+                    below += (first[t] && out[t] < h) ? 1u : 0u;
+                in = below < s;
+            }
+            y += (uint32_t)__popcll(__ballot(in));
+        }
+    }
+    // m: shared hashes of rank < s - y in W_i
+    const uint32_t lim = s - y;
+    uint32_t m = 0;
+    if (lane < nw) {
+        uint64_t w = L.cbits[lane];
+        const uint32_t b0 = lane * 64;
+        if (lim <= b0) w = 0;
+        else if (lim < b0 + 64) w &= (1ull << (lim - b0)) - 1;
+        m = (uint32_t)__popcll(w);
+    }
+    for (int d = 32; d > 0; d >>= 1) m += __shfl_xor(m, d, 64);
+    return m;
+}
+
+
 // Shared hashes among the s smallest of W_i u W_j for the target window
-// starting at minimizer tj (position j).  Returns NONE32 when the window
+// starting at minimizer tj (position j).  A candidate whose shared count c
+// is not above `beat` cannot win (m <= c, and ties go to the earlier j):
+// then c is returned without the estimate.  Returns NONE32 when the window
 // holds more than EAMAX minimizers outside W_i.
 __device__ uint32_t estimate_at(const IndexView &ix, EstWave &L, uint32_t s, uint32_t o,
-                                uint64_t tj, uint64_t jend) {
+                                uint64_t tj, uint64_t jend, bool have, uint32_t beat,
+                                uint32_t reg_cap, uint64_t q0, uint32_t na) {
     const uint32_t lane = e_lane();
     const uint64_t ltmask = lane ? (~0ull >> (64 - lane)) : 0ull;
     const uint32_t nw = (s + 63) >> 6;
+    uint32_t *out = L.u.big.out;  // hashes of W_j outside W_i
     if (lane < nw) L.cbits[lane] = 0;
     __builtin_amdgcn_wave_barrier();
-    uint32_t nb = 0;  // hashes of W_j outside W_i, in L.key
+    uint32_t nb = 0;
     for (uint64_t base = tj;; base += 64) {
         const uint64_t tm = base + lane;
         const bool v = tm < ix.nm && (uint64_t)ix.mpos[tm] <= jend;
@@ -104,66 +214,56 @@ __device__ uint32_t estimate_at(const IndexView &ix, EstWave &L, uint32_t s, uin
             const uint32_t r = rank_below(L.ahash, s, h);
             if (r < s && L.ahash[r] == h) {
                 const uint8_t fl = ix.mflags[tm];
-                if (fl & 2) {  // eligible target occurrence: shared unless only itself pairs
-                    const uint32_t a = (fl & 1) ^ o;
-                    const uint32_t c = (L.acnt[r] >> (16 * a)) & 0xFFFFu;
-                    if (c >= 2 || (c == 1 && L.apos[r][a] != ix.mpos[tm]))
-                        atomicOr(&L.cbits[r >> 6], 1ull << (r & 63));
-                }
+                if ((fl & 2) && pairs(L, r, fl & 1, o, tm, q0, na))  // eligible and pairs
+                    atomicOr(&L.cbits[r >> 6], 1ull << (r & 63));
             } else {
                 outside = true;
             }
         }
         const uint64_t bm = __ballot(outside);
         const uint32_t at = nb + (uint32_t)__popcll(bm & ltmask);
-        if (outside && at < EAMAX) L.key[at] = h;
+        if (outside && at < EAMAX) out[at] = h;
         nb += (uint32_t)__popcll(bm);
         if (__ballot(v) != ~0ull) break;
         if (nb > EAMAX) break;
     }
     if (nb > EAMAX) return NONE32;
+    return estimate_finish(L, out, L.u.big.first, s, nb, have, beat, reg_cap);
+}
+
+// The same for the target window u.run.tp[xs, xe) of the run's minimizers held
+// in LDS (classified once per run).
+__device__ uint32_t estimate_lds(EstWave &L, uint32_t s, uint32_t xs, uint32_t xe, bool have,
+                                 uint32_t beat, uint32_t reg_cap) {
+    const uint32_t lane = e_lane();
+    const uint64_t ltmask = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const uint32_t nw = (s + 63) >> 6;
+    uint32_t *out = L.u.run.out;
+    if (lane < nw) L.cbits[lane] = 0;
     __builtin_amdgcn_wave_barrier();
-    // y: distinct outside hashes among the s smallest of the union; the u-th
-    // smallest of them (0-based) is inside iff u + rank in W_i < s
-    uint32_t m2 = 1;
-    while (m2 < nb) m2 <<= 1;
-    for (uint32_t t = nb + lane; t < m2; t += 64) L.key[t] = ~0ull;
-    __builtin_amdgcn_wave_barrier();
-    wave_bitonic(L.key, m2);
-    uint32_t y = 0, ndist = 0;
-    for (uint32_t t0 = 0; t0 < nb; t0 += 64) {
-        const uint32_t t = t0 + lane;
-        bool first = false;
-        uint32_t h = 0;
-        if (t < nb) {
-            h = (uint32_t)L.key[t];
-            first = t == 0 || L.key[t - 1] != L.key[t];
+    uint32_t nb = 0;
+    for (uint32_t x0 = xs; x0 < xe; x0 += 64) {
+        const uint32_t x = x0 + lane;
+        const bool v = x < xe;
+        const uint16_t tr = v ? L.u.run.tr[x] : (uint16_t)0;
+        if (tr & TR_SHARED) {
+            const uint32_t r = tr & TR_RANK;
+            atomicOr(&L.cbits[r >> 6], 1ull << (r & 63));
         }
-        const uint64_t fm = __ballot(first);
-        const uint32_t u = ndist + (uint32_t)__popcll(fm & ltmask);
-        const bool in = first && u + rank_below(L.ahash, s, h) < s;
-        y += (uint32_t)__popcll(__ballot(in));
-        ndist += (uint32_t)__popcll(fm);
+        const bool outside = v && !(tr & TR_IN);
+        const uint64_t bm = __ballot(outside);
+        if (outside) out[nb + (uint32_t)__popcll(bm & ltmask)] = L.u.run.th[x];
+        nb += (uint32_t)__popcll(bm);
     }
-    // m: shared hashes of rank < s - y in W_i
-    const uint32_t lim = s - y;
-    uint32_t c = 0;
-    if (lane < nw) {
-        uint64_t w = L.cbits[lane];
-        const uint32_t b0 = lane * 64;
-        if (lim <= b0) w = 0;
-        else if (lim < b0 + 64) w &= (1ull << (lim - b0)) - 1;
-        c = (uint32_t)__popcll(w);
-    }
-    for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
-    return c;
+    return estimate_finish(L, out, L.u.run.first, s, nb, have, beat, reg_cap);  // nb <= TCAP
 }
 
 __global__ void __launch_bounds__(EW * 64) k_estimate_runs(IndexView ix, const uint32_t *runs,
                                                             uint64_t nruns, uint32_t n,
                                                             const uint16_t *T, uint32_t *seeds,
                                                             uint64_t cap, unsigned long long *nseeds,
-                                                            uint32_t *err) {
+                                                            uint32_t *err, uint32_t lds_cap,
+                                                            uint32_t reg_cap) {
     __shared__ EstWave W[EW];
     const uint32_t lane = e_lane(), wv = threadIdx.x >> 6;
     EstWave &L = W[wv];
@@ -182,7 +282,7 @@ __global__ void __launch_bounds__(EW * 64) k_estimate_runs(IndexView ix, const u
         const uint64_t m = q0 + na + lane;
         const bool v = m < ix.nm && (uint64_t)ix.mpos[m] <= qend;
         const uint64_t bv = __ballot(v);  // a prefix of the lanes
-        if (v && na + lane < EAMAX) L.key[na + lane] = ((uint64_t)ix.mhash[m] << 32) | (na + lane);
+        if (v && na + lane < EAMAX) L.u.key[na + lane] = ((uint64_t)ix.mhash[m] << 32) | (na + lane);
         na += (uint32_t)__popcll(bv);
         if (bv != ~0ull || na > EAMAX) break;
     }
@@ -192,10 +292,10 @@ __global__ void __launch_bounds__(EW * 64) k_estimate_runs(IndexView ix, const u
     }
     uint32_t m2 = 1;
     while (m2 < na) m2 <<= 1;
-    for (uint32_t t = na + lane; t < m2; t += 64) L.key[t] = ~0ull;
+    for (uint32_t t = na + lane; t < m2; t += 64) L.u.key[t] = ~0ull;
     for (uint32_t t = lane; t < na; t += 64) L.acnt[t] = 0;
     __builtin_amdgcn_wave_barrier();
-    wave_bitonic(L.key, m2);
+    wave_bitonic(L.u.key, m2);
     // distinct hashes and their eligible occurrences per strand
     uint32_t nd = 0;
     for (uint32_t t0 = 0; t0 < na; t0 += 64) {
@@ -203,8 +303,8 @@ __global__ void __launch_bounds__(EW * 64) k_estimate_runs(IndexView ix, const u
         bool first = false;
         uint64_t key = 0;
         if (t < na) {
-            key = L.key[t];
-            first = t == 0 || (L.key[t - 1] >> 32) != (key >> 32);
+            key = L.u.key[t];
+            first = t == 0 || (L.u.key[t - 1] >> 32) != (key >> 32);
         }
         const uint64_t fm = __ballot(first);
         const uint64_t le = fm & (ltmask | (1ull << lane));
@@ -213,15 +313,12 @@ __global__ void __launch_bounds__(EW * 64) k_estimate_runs(IndexView ix, const u
             if (first) L.ahash[rk] = (uint32_t)(key >> 32);
             const uint64_t m = q0 + (uint32_t)key;
             const uint8_t fl = ix.mflags[m];
-            if (fl & 2) {
-                const uint32_t a = fl & 1;
-                atomicAdd(&L.acnt[rk], a ? 0x10000u : 1u);
-                L.apos[rk][a] = ix.mpos[m];  // read only when this is the strand's one occurrence
-            }
+            if (fl & 2) atomicAdd(&L.acnt[rk], (fl & 1) ? 0x10000u : 1u);
         }
         nd += (uint32_t)__popcll(fm);
         __builtin_amdgcn_wave_barrier();
     }
+    __builtin_amdgcn_wave_barrier();  // the sort keys are dead: their space holds the run below
     if (nd != s) {
         if (lane == 0) atomicOr(err, 2u);
         return;
@@ -231,7 +328,57 @@ __global__ void __launch_bounds__(EW * 64) k_estimate_runs(IndexView ix, const u
     uint32_t best_m = 0, best_j = 0;
     bool have = false;
     const uint64_t t0 = wave_lower_bound(ix.mpos, ix.nm, jf);
-    for (uint64_t base = t0;; base += 64) {
+    // the run's target minimizers, classified once, when they fit in LDS
+    const uint64_t tend = (uint64_t)jl + n - k;
+    uint32_t nt = 0;
+    for (;;) {
+        const uint64_t tm = t0 + nt + lane;
+        const bool v = tm < ix.nm && (uint64_t)ix.mpos[tm] <= tend;
+        const uint64_t bv = __ballot(v);  // a prefix of the lanes
+        const uint32_t x = nt + lane;
+        if (v && x < lds_cap) {
+            const uint32_t pos = ix.mpos[tm], h = ix.mhash[tm];
+            const uint8_t fl = ix.mflags[tm];
+            const uint32_t rk = rank_below(L.ahash, s, h);
+            uint16_t tr = 0;
+            if (rk < s && L.ahash[rk] == h) {
+                tr = (uint16_t)(TR_IN | rk);
+                if ((fl & 2) && pairs(L, rk, fl & 1, o, tm, q0, na)) tr |= TR_SHARED;
+            }
+            L.u.run.tp[x] = pos;
+            L.u.run.th[x] = h;
+            L.u.run.tr[x] = tr;
+        }
+        nt += (uint32_t)__popcll(bv);
+        if (bv != ~0ull || nt > lds_cap) break;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (nt <= lds_cap) {
+        for (uint32_t x0 = 0; x0 < nt; x0 += 64) {
+            const uint32_t x = x0 + lane;
+            bool cand = false;
+            if (x < nt && L.u.run.tp[x] <= jl && (L.u.run.tr[x] & TR_SHARED))
+                cand = window_ok(ix, L.u.run.tp[x], n, nullptr);  // a candidate j of the run
+            uint64_t cm = __ballot(cand);
+            while (cm) {
+                const uint32_t xc = x0 + (uint32_t)__ffsll((long long)cm) - 1;
+                cm &= cm - 1;
+                const uint32_t j = L.u.run.tp[xc];
+                uint32_t lo = xc, hi = nt;  // end of the window: first position > j + n - k
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if ((uint64_t)L.u.run.tp[mid] <= (uint64_t)j + n - k) lo = mid + 1; else hi = mid;
+                }
+                const uint32_t m = estimate_lds(L, s, xc, lo, have, best_m, reg_cap);
+                if (!have || m > best_m) {
+                    best_m = m;
+                    best_j = j;
+                    have = true;
+                }
+            }
+        }
+    }
+    for (uint64_t base = t0; nt > lds_cap; base += 64) {
         const uint64_t tm = base + lane;
         const bool v = tm < ix.nm && ix.mpos[tm] <= jl;
         bool cand = false;
@@ -242,11 +389,8 @@ __global__ void __launch_bounds__(EW * 64) k_estimate_runs(IndexView ix, const u
             if (fl & 2) {
                 const uint32_t h = ix.mhash[tm];
                 const uint32_t rk = rank_below(L.ahash, s, h);
-                if (rk < s && L.ahash[rk] == h) {
-                    const uint32_t a = (fl & 1) ^ o;
-                    const uint32_t c = (L.acnt[rk] >> (16 * a)) & 0xFFFFu;
-                    cand = (c >= 2 || (c == 1 && L.apos[rk][a] != pj)) && window_ok(ix, pj, n, nullptr);
-                }
+                if (rk < s && L.ahash[rk] == h)
+                    cand = pairs(L, rk, fl & 1, o, tm, q0, na) && window_ok(ix, pj, n, nullptr);
             }
         }
         uint64_t cm = __ballot(cand);
@@ -255,7 +399,8 @@ __global__ void __launch_bounds__(EW * 64) k_estimate_runs(IndexView ix, const u
             const uint32_t l = (uint32_t)__ffsll((long long)cm) - 1;
             cm &= cm - 1;
             const uint32_t j = (uint32_t)__builtin_amdgcn_readlane((int)pj, (int)l);
-            const uint32_t m = estimate_at(ix, L, s, o, base + l, (uint64_t)j + n - k);
+            const uint32_t m =
+                estimate_at(ix, L, s, o, base + l, (uint64_t)j + n - k, have, best_m, reg_cap, q0, na);
             if (m == NONE32) {
                 if (lane == 0) atomicOr(err, 1u);
                 return;
@@ -282,8 +427,15 @@ void launch_estimate_runs(const IndexView &ix, const uint32_t *runs, uint64_t nr
                           unsigned long long *nseeds, uint32_t *err, hipStream_t st) {
     if (nruns == 0) return;
     const uint64_t blocks = (nruns + EW - 1) / EW;
+    // test hooks: SDF_EST_LDS_CAP / SDF_EST_REG_CAP lower the sizes held in
+    // LDS and registers (0 sends every run down the general paths)
+    uint32_t lds_cap = TCAP, reg_cap = 128;
+    if (const char *v = std::getenv("SDF_EST_LDS_CAP"))
+        lds_cap = std::min<uint32_t>(TCAP, (uint32_t)std::strtoul(v, nullptr, 10));
+    if (const char *v = std::getenv("SDF_EST_REG_CAP"))
+        reg_cap = std::min<uint32_t>(128, (uint32_t)std::strtoul(v, nullptr, 10));
     k_estimate_runs<<<(unsigned)blocks, EW * 64, 0, st>>>(ix, runs, nruns, n, T, seeds, cap, nseeds,
-                                                         err);
+                                                         err, lds_cap, reg_cap);
     SDF_HIP(hipGetLastError());
 }
 

@@ -204,6 +204,23 @@ def test_search_estimate_tandem_and_config1(S, oracle_lib, seed, length, n_seqs,
     _same(r.candidates(), oc, CAND_F, "candidates config1")
 
 
+def test_search_estimate_general_paths(S, oracle_lib, monkeypatch):
+    """Estimate mode with the run's target minimizers read from global
+    memory per candidate and the outside hashes counted through LDS (the
+    paths taken by long runs and dense windows) equals the oracle."""
+    g = synth.tandem_case(95, length=40_000, n_arrays=20, copies_hi=40, n_seqs=2)
+    b, off = g.concat()
+    orc = oracle_lib.OracleIndex(b, off, 12, 16)
+    os_, oc = orc.search(g.spans, 0.25, 400, estimate=True)
+    ix = S.Index(g.seqs, 12, 16)
+    for lds, reg in (("0", "0"), ("0", "128"), ("1024", "0"), ("8", "3")):
+        monkeypatch.setenv("SDF_EST_LDS_CAP", lds)
+        monkeypatch.setenv("SDF_EST_REG_CAP", reg)
+        r = ix.search_batch(g.spans, 0.25, 400, estimate=True)
+        _same(r.seeds(), os_, SEED_F, "seeds lds=%s reg=%s" % (lds, reg))
+        _same(r.candidates(), oc, CAND_F, "candidates lds=%s reg=%s" % (lds, reg))
+
+
 def test_search_config1(S, oracle_lib):
     """The 1 Mbp workload, self against self: exact seeds and candidates."""
     g = synth.config1()

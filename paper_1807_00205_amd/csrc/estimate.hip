@@ -354,6 +354,7 @@ __global__ void __launch_bounds__(EW * 64) k_estimate_runs(IndexView ix, const u
     }
     __builtin_amdgcn_wave_barrier();
     if (nt <= lds_cap) {
+        uint32_t we = 0;  // end of the current candidate's window (non-decreasing in j)
         for (uint32_t x0 = 0; x0 < nt; x0 += 64) {
             const uint32_t x = x0 + lane;
             bool cand = false;
@@ -364,12 +365,15 @@ __global__ void __launch_bounds__(EW * 64) k_estimate_runs(IndexView ix, const u
                 const uint32_t xc = x0 + (uint32_t)__ffsll((long long)cm) - 1;
                 cm &= cm - 1;
                 const uint32_t j = L.u.run.tp[xc];
-                uint32_t lo = xc, hi = nt;  // end of the window: first position > j + n - k
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if ((uint64_t)L.u.run.tp[mid] <= (uint64_t)j + n - k) lo = mid + 1; else hi = mid;
+                // first minimizer past j + n - k, 64 at a time from the previous end
+                for (;;) {
+                    const uint32_t y = we + lane;
+                    const bool in = y < nt && (uint64_t)L.u.run.tp[y] <= (uint64_t)j + n - k;
+                    const uint64_t im = __ballot(in);  // a prefix of the lanes
+                    we += (uint32_t)__popcll(im);
+                    if (im != ~0ull) break;
                 }
-                const uint32_t m = estimate_lds(L, s, xc, lo, have, best_m, reg_cap);
+                const uint32_t m = estimate_lds(L, s, xc, we, have, best_m, reg_cap);
                 if (!have || m > best_m) {
                     best_m = m;
                     best_j = j;

@@ -22,6 +22,11 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 SEED_DTYPE = np.dtype([("query_id", "<u4"), ("i", "<u4"), ("j", "<u4"),
                        ("strand", "<u4"), ("shared", "<u4"), ("sketch", "<u4")])
+# Extended region (Section 3.2): global coordinates, numerator and sketch size
+# of the final state, stop codes (forward | backward << 8).
+EXT_DTYPE = np.dtype([("q_begin", "<u8"), ("q_end", "<u8"), ("t_begin", "<u8"),
+                      ("t_end", "<u8"), ("m", "<u8"), ("s", "<u8"), ("stop", "<u8")])
+EXT_BOUND, EXT_CAP, EXT_OVERLAP, EXT_ESTIMATE = 1, 2, 3, 4
 CAND_DTYPE = np.dtype([("query_id", "<u4"), ("strand", "<u4"), ("q_seq", "<u4"),
                        ("t_seq", "<u4"), ("q_begin", "<u8"), ("q_end", "<u8"),
                        ("t_begin", "<u8"), ("t_end", "<u8"), ("n_seeds", "<u4"),
@@ -82,6 +87,10 @@ def lib():
         L.or_result_seeds.argtypes = [vp, vp]
         L.or_result_cands.argtypes = [vp, vp]
         L.or_result_free.argtypes = [vp]
+        L.or_extend.restype = ctypes.c_int
+        L.or_extend.argtypes = [vp, vp, u32, dbl, u64, vp]
+        L.or_extend_many.restype = u64
+        L.or_extend_many.argtypes = [vp, vp, u64, dbl, u64, ctypes.c_int, vp]
         L.or_seed_size.restype = ctypes.c_int
         L.or_cand_size.restype = ctypes.c_int
         assert L.or_seed_size() == SEED_DTYPE.itemsize
@@ -193,6 +202,16 @@ class OracleIndex:
     def estimate(self, i: int, j: int, o: int, n: int) -> int:
         """Numerator m of the winnowed MinHash estimate m / s_i."""
         return int(lib().or_estimate(self._h, i, j, o, n))
+
+    def extend(self, regions, tau: float, max_len: int = 1000000, threads: int = 0):
+        """Extends regions (rows q0, q1, t0, t1, o in global coordinates) by
+        the Section 3.2 procedure; returns an EXT_DTYPE array."""
+        r = np.ascontiguousarray(np.array(regions, dtype=np.uint64).reshape(-1, 5))
+        out = np.zeros(len(r), EXT_DTYPE)
+        bad = lib().or_extend_many(self._h, _ptr(r), len(r), tau, max_len, threads, _ptr(out))
+        if bad:
+            raise ValueError("%d invalid regions" % bad)
+        return out
 
     def search(self, spans, max_error: float = 0.25, min_len: int = 1000, threads: int = 0,
                estimate: bool = False):

@@ -289,3 +289,67 @@ class Brute:
                           len(S), max(x[4] for x in S)))
         cands.sort()
         return cands
+
+
+def extend(br: "Brute", q0: int, q1: int, t0: int, t1: int, o: int, tau: float,
+           max_len: int = 1000000):
+    """Seed extension (Section 3.2) one base at a time, rebuilding both
+    minimizer sets from scratch and evaluating the estimate at every step.
+
+    Returns (q0, q1, t0, t1, m, s, stop) like the C oracle's ``or_extend``;
+    stop codes: 1 sequence end, 2 length cap, 3 overlap, 4 estimate."""
+    import bisect
+    k = br.k
+    pos = [m.pos for m in br.M]
+
+    def strands(a, b):
+        lo = bisect.bisect_left(pos, a)
+        hi = bisect.bisect_right(pos, b - k)
+        d = {}
+        for m in br.M[lo:hi]:
+            d.setdefault(m.h, set()).add(m.strand)
+        return d
+
+    def estimate(r):
+        Q, T = strands(r[0], r[1]), strands(r[2], r[3])
+        s = len(Q)
+        bottom = sorted(set(Q) | set(T))[:s]
+        shared = {h for h in Q if h in T and any((a ^ b) == o for a in Q[h] for b in T[h])}
+        m = len(set(bottom) & shared)
+        return m, s
+
+    def passes(r):
+        m, s = estimate(r)
+        return s > 0 and m >= math.ceil(tau * s)
+
+    if q1 - q0 > max_len or t1 - t0 > max_len:
+        return (q0, q1, t0, t1, 0, 0, 2 | (2 << 8))
+    qs, ts = br.seq_of(q0), br.seq_of(t0)
+    qlo, qhi = br.off[qs], br.off[qs + 1]
+    tlo, thi = br.off[ts], br.off[ts + 1]
+    r = [q0, q1, t0, t1]
+    codes = []
+    for phase in (0, 1):
+        while True:
+            if phase == 0:
+                nq = (r[0], r[1] + 1)
+                nt = (r[2], r[3] + 1) if o == 0 else (r[2] - 1, r[3])
+            else:
+                nq = (r[0] - 1, r[1])
+                nt = (r[2] - 1, r[3]) if o == 0 else (r[2], r[3] + 1)
+            if nq[0] < qlo or nq[1] > qhi or nt[0] < tlo or nt[1] > thi:
+                codes.append(1)
+                break
+            if nq[1] - nq[0] > max_len or nt[1] - nt[0] > max_len:
+                codes.append(2)
+                break
+            if qs == ts and max(nq[0], nt[0]) < min(nq[1], nt[1]):
+                codes.append(3)
+                break
+            cand = [nq[0], nq[1], nt[0], nt[1]]
+            if not passes(cand):
+                codes.append(4)
+                break
+            r = cand
+    m, s = estimate(r)
+    return (r[0], r[1], r[2], r[3], m, s, codes[0] | (codes[1] << 8))

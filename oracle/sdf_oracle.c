@@ -1,7 +1,8 @@
 /*
  * sdf_oracle.c -- plain, slow CPU oracle for the winnowed-minimizer Jaccard
  * seed filter of SEDEF (Numanagic et al., "Fast Characterization of Segmental
- * Duplications in Genome Assemblies") and for the chaining of its seeds.
+ * Duplications in Genome Assemblies"), for the chaining of its seeds and for
+ * the extension of regions by the winnowed MinHash estimate (Section 3.2).
  *
  * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the CPU
  * baseline leg of the benchmark may load this library.  The GPU library never
@@ -1087,4 +1088,264 @@ void or_hash_many(const uint32_t *in, uint64_t n, uint32_t k, uint32_t *out)
 {
     for (uint64_t t = 0; t < n; t++)
         out[t] = or_hash(in[t], k);
+}
+
+/* ------------------------------------------------------------------ */
+/* Seed extension to potential SD regions (Section 3.2, first paragraph).
+ *
+ * A region is a pair of substrings, G_i = [q0, q1) on the query side and
+ * G_j = [t0, t1) on the target side, in orientation o.  The extension grows
+ * both by one base per step: first forward (the query's right end; the
+ * target's right end for o = 0, its left end for o = 1, where the target is
+ * read reverse-complemented), then, from the result of the forward phase,
+ * backward (the query's left end; the target's left end for o = 0, its right
+ * end for o = 1).  A phase stops at the first step that
+ *   1. would leave the query's or the target's sequence,
+ *   2. would make either substring longer than max_len (1 Mbp in the paper),
+ *   3. would make the two substrings intersect (same sequence only), or
+ *   4. gives a state whose winnowed MinHash estimate is below tau;
+ * the phase keeps the state before that step.  A start region longer than
+ * max_len is not extended, and its estimate is not evaluated (m = s = 0).
+ *
+ * Readings:
+ *  - The sets hold every minimizer whose k-mer lies inside the substring,
+ *    masked and palindromic ones included (the extension may use any k-mer).
+ *  - A hash is in W(G_i) n W(G_j) when it has an occurrence of strand a in
+ *    G_i and one of strand b in G_j with a xor b = o.
+ *  - s = |W(G_i)| (distinct hashes); the numerator m counts the hashes of
+ *    the intersection among the s smallest of W(G_i) u W(G_j) (as for the
+ *    seed estimate); the state passes when m >= ceil(tau * s) in double.
+ *  - The state is evaluated after every step; when no minimizer enters
+ *    either substring at a step the sets, and so the estimate, are those of
+ *    the previous state.
+ * Stop codes: 1 sequence end, 2 length cap, 3 overlap, 4 estimate; the code
+ * of the first condition (in this order) that holds at the refused step. */
+
+enum { EXT_BOUND = 1, EXT_CAP = 2, EXT_OVERLAP = 3, EXT_ESTIMATE = 4 };
+enum { L_Q0 = 1, L_Q1 = 2, L_T0 = 4, L_T1 = 8 };
+
+/* The ordered set L of Section 3.1: distinct hashes of the union, ascending,
+ * each with the strands it has in G_i (bits L_Q0, L_Q1) and in G_j (L_T0,
+ * L_T1). */
+typedef struct {
+    uint32_t n, cap;
+    uint32_t *h;
+    uint8_t *bits;
+} or_lset;
+
+/* Adds `bit` to hash h; returns the previous bits (0 if h was new). */
+static uint8_t lset_add(or_lset *L, uint32_t h, uint8_t bit)
+{
+    uint32_t lo = 0, hi = L->n;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) / 2;
+        if (L->h[mid] < h)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    if (lo < L->n && L->h[lo] == h) {
+        uint8_t old = L->bits[lo];
+        L->bits[lo] |= bit;
+        return old;
+    }
+    if (L->n == L->cap) {
+        L->cap = L->cap ? 2 * L->cap : 1024;
+        L->h = (uint32_t *)realloc(L->h, L->cap * sizeof(uint32_t));
+        L->bits = (uint8_t *)realloc(L->bits, L->cap);
+    }
+    memmove(L->h + lo + 1, L->h + lo, (L->n - lo) * sizeof(uint32_t));
+    memmove(L->bits + lo + 1, L->bits + lo, L->n - lo);
+    L->h[lo] = h;
+    L->bits[lo] = bit;
+    L->n++;
+    return 0;
+}
+
+/* Restores hash h to `old` bits (removes it when old == 0). */
+static void lset_restore(or_lset *L, uint32_t h, uint8_t old)
+{
+    uint32_t lo = 0, hi = L->n;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) / 2;
+        if (L->h[mid] < h)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    if (old) {
+        L->bits[lo] = old;
+        return;
+    }
+    memmove(L->h + lo, L->h + lo + 1, (L->n - lo - 1) * sizeof(uint32_t));
+    memmove(L->bits + lo, L->bits + lo + 1, L->n - lo - 1);
+    L->n--;
+}
+
+static int lset_shared(uint8_t b, uint32_t o)
+{
+    int q0 = (b & L_Q0) != 0, q1 = (b & L_Q1) != 0;
+    int t0 = (b & L_T0) != 0, t1 = (b & L_T1) != 0;
+    return o == 0 ? ((q0 && t0) || (q1 && t1)) : ((q0 && t1) || (q1 && t0));
+}
+
+/* Winnowed MinHash estimate of the state held in L: s and m as defined. */
+static void lset_estimate(const or_lset *L, uint32_t o, uint32_t *m_out, uint32_t *s_out)
+{
+    uint32_t s = 0, m = 0;
+    for (uint32_t u = 0; u < L->n; u++)
+        if (L->bits[u] & (L_Q0 | L_Q1))
+            s++;
+    for (uint32_t u = 0; u < s; u++) /* the s smallest of the union */
+        if (lset_shared(L->bits[u], o))
+            m++;
+    *m_out = m;
+    *s_out = s;
+}
+
+/* Minimizer at global position p, if any: its array index, else -1. */
+static int64_t or_minimizer_at(const or_index *ix, uint64_t p)
+{
+    uint64_t lo, hi;
+    or_m_range(ix, p, p, &lo, &hi);
+    return hi > lo ? (int64_t)lo : -1;
+}
+
+static void lset_add_range(or_lset *L, const or_index *ix, uint64_t a, uint64_t b, int side)
+{
+    if (b < a + ix->k)
+        return;
+    uint64_t lo, hi;
+    or_m_range(ix, a, b - ix->k, &lo, &hi);
+    for (uint64_t q = lo; q < hi; q++) {
+        uint8_t st = ix->m_flags[q] & MF_STRAND;
+        lset_add(L, ix->m_hash[q], (uint8_t)((side ? L_T0 : L_Q0) << st));
+    }
+}
+
+static int or_intersect(uint64_t a0, uint64_t a1, uint64_t b0, uint64_t b1)
+{
+    return a0 < b1 && b0 < a1;
+}
+
+/* One phase (dir 0 forward, 1 backward) on the region r = {q0,q1,t0,t1}. */
+static uint32_t or_extend_phase(const or_index *ix, or_lset *L, uint64_t r[4], uint32_t o,
+                                int dir, double tau, uint64_t max_len, int *ok)
+{
+    const uint32_t k = ix->k;
+    const uint32_t qs = or_seq_of(ix, r[0]), ts = or_seq_of(ix, r[2]);
+    for (;;) {
+        /* the step: which end of each substring grows */
+        int q_right = (dir == 0);
+        int t_right = (dir == 0) ? (o == 0) : (o == 1);
+        uint64_t n0 = r[0] - (q_right ? 0 : 1), n1 = r[1] + (q_right ? 1 : 0);
+        uint64_t m0 = r[2] - (t_right ? 0 : 1), m1 = r[3] + (t_right ? 1 : 0);
+        /* 1. sequence ends (unsigned wrap below 0 is caught by the first test) */
+        if ((!q_right && r[0] == ix->off[qs]) || n1 > ix->off[qs + 1] ||
+            (!t_right && r[2] == ix->off[ts]) || m1 > ix->off[ts + 1])
+            return EXT_BOUND;
+        /* 2. length cap */
+        if (n1 - n0 > max_len || m1 - m0 > max_len)
+            return EXT_CAP;
+        /* 3. overlap */
+        if (qs == ts && or_intersect(n0, n1, m0, m1))
+            return EXT_OVERLAP;
+        /* the minimizers that enter: the k-mer at the new end of each side */
+        int64_t qm = or_minimizer_at(ix, q_right ? n1 - k : n0);
+        int64_t tm = or_minimizer_at(ix, t_right ? m1 - k : m0);
+        if (qm >= 0 && !(ix->m_pos[qm] >= n0 && ix->m_pos[qm] + k <= n1))
+            qm = -1;
+        if (tm >= 0 && !(ix->m_pos[tm] >= m0 && ix->m_pos[tm] + k <= m1))
+            tm = -1;
+        uint8_t qold = 0, told = 0;
+        if (qm >= 0)
+            qold = lset_add(L, ix->m_hash[qm], (uint8_t)(L_Q0 << (ix->m_flags[qm] & MF_STRAND)));
+        if (tm >= 0)
+            told = lset_add(L, ix->m_hash[tm], (uint8_t)(L_T0 << (ix->m_flags[tm] & MF_STRAND)));
+        /* 4. estimate of the new state (unchanged when nothing entered) */
+        const int prev_ok = *ok;
+        if (qm >= 0 || tm >= 0) {
+            uint32_t m, s;
+            lset_estimate(L, o, &m, &s);
+            *ok = s > 0 && m >= or_threshold(tau, s);
+        }
+        if (!*ok) {
+            if (tm >= 0)
+                lset_restore(L, ix->m_hash[tm], told);
+            if (qm >= 0)
+                lset_restore(L, ix->m_hash[qm], qold);
+            *ok = prev_ok; /* the state kept is the one before the step */
+            return EXT_ESTIMATE;
+        }
+        r[0] = n0;
+        r[1] = n1;
+        r[2] = m0;
+        r[3] = m1;
+    }
+}
+
+/* Extends one region; reg = {q0, q1, t0, t1} in global coordinates, each
+ * substring inside one sequence.  out = {q0, q1, t0, t1, m, s, stop} with
+ * stop = forward code | backward code << 8.  Returns 0, or -1 when the
+ * region is invalid. */
+int or_extend(void *p, const uint64_t *reg, uint32_t o, double tau, uint64_t max_len,
+              uint64_t *out)
+{
+    or_index *ix = (or_index *)p;
+    uint64_t r[4] = {reg[0], reg[1], reg[2], reg[3]};
+    if (o > 1 || r[0] >= r[1] || r[2] >= r[3] || r[1] > ix->total || r[3] > ix->total)
+        return -1;
+    if (or_seq_of(ix, r[0]) != or_seq_of(ix, r[1] - 1) ||
+        or_seq_of(ix, r[2]) != or_seq_of(ix, r[3] - 1))
+        return -1;
+    out[0] = r[0];
+    out[1] = r[1];
+    out[2] = r[2];
+    out[3] = r[3];
+    if (r[1] - r[0] > max_len || r[3] - r[2] > max_len) {
+        out[4] = out[5] = 0;
+        out[6] = EXT_CAP | (EXT_CAP << 8);
+        return 0;
+    }
+    or_lset L = {0, 0, NULL, NULL};
+    lset_add_range(&L, ix, r[0], r[1], 0);
+    lset_add_range(&L, ix, r[2], r[3], 1);
+    uint32_t m, s;
+    lset_estimate(&L, o, &m, &s);
+    int ok = s > 0 && m >= or_threshold(tau, s);
+    uint32_t fwd = or_extend_phase(ix, &L, r, o, 0, tau, max_len, &ok);
+    uint32_t bwd = or_extend_phase(ix, &L, r, o, 1, tau, max_len, &ok);
+    lset_estimate(&L, o, &m, &s);
+    out[0] = r[0];
+    out[1] = r[1];
+    out[2] = r[2];
+    out[3] = r[3];
+    out[4] = m;
+    out[5] = s;
+    out[6] = fwd | (bwd << 8);
+    free(L.h);
+    free(L.bits);
+    return 0;
+}
+
+/* Many regions (5 u64 each: q0, q1, t0, t1, o) in parallel; 7 u64 out each.
+ * Returns the number of invalid regions (their output is zeroed). */
+uint64_t or_extend_many(void *p, const uint64_t *regs, uint64_t n, double tau, uint64_t max_len,
+                        int threads, uint64_t *out)
+{
+    uint64_t bad = 0;
+#ifdef _OPENMP
+    if (threads > 0)
+        omp_set_num_threads(threads);
+#else
+    (void)threads;
+#endif
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
+    for (int64_t u = 0; u < (int64_t)n; u++) {
+        if (or_extend(p, regs + 5 * u, (uint32_t)regs[5 * u + 4], tau, max_len, out + 7 * u)) {
+            memset(out + 7 * u, 0, 7 * sizeof(uint64_t));
+            bad++;
+        }
+    }
+    return bad;
 }

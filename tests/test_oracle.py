@@ -554,3 +554,134 @@ def test_recovery_config1(oracle_lib):
             assert good, sd
     assert sum(ok) >= 18
     assert len(cands) >= 40
+
+
+# -------------------------------------------------------------- extension ---
+
+def _regions_of(cands, off):
+    out = []
+    for c in cands:
+        qo, to = int(off[c["q_seq"]]), int(off[c["t_seq"]])
+        out.append((qo + int(c["q_begin"]), qo + int(c["q_end"]),
+                    to + int(c["t_begin"]), to + int(c["t_end"]), int(c["strand"])))
+    return out
+
+
+def _random_boxes(rng, off, n, lo_len=50, hi_len=800):
+    out = []
+    for _ in range(n):
+        row = []
+        for _side in range(2):
+            s = int(rng.integers(0, len(off) - 1))
+            lo, hi = int(off[s]), int(off[s + 1])
+            a = int(rng.integers(lo, hi - lo_len))
+            e = int(rng.integers(a + lo_len, min(hi, a + hi_len) + 1))
+            row += [a, e]
+        out.append(tuple(row) + (int(rng.integers(0, 2)),))
+    return out
+
+
+@pytest.mark.parametrize("case", CASES[:3] + [None], ids=lambda c: "seed%d" % c["seed"] if c else "tandem")
+@pytest.mark.parametrize("max_error,min_len,k,w", [(0.25, 200, 12, 16), (0.3, 120, 9, 5)])
+def test_extend_matches_bruteforce(oracle_lib, case, max_error, min_len, k, w):
+    """Section 3.2 extension: the oracle (event steps on the ordered set L,
+    undo on a refused step) equals the brute force (every base step, both
+    minimizer sets rebuilt and the estimate recomputed from scratch) on the
+    chained candidates and on random boxes, both strands, several sequences,
+    masked runs and gaps."""
+    from oracle import brute
+    if case is None:
+        g = synth.tandem_case(91, length=3000, n_arrays=5, copies_hi=20, n_seqs=2)
+    else:
+        c = dict(case)
+        seed = c.pop("seed")
+        g = synth.small_case(60 + seed, sd_lo=300, sd_hi=600, gap_len=25, rate_hi=0.06, **c)
+    b, off = g.concat()
+    ix = oracle_lib.OracleIndex(b, off, k, w)
+    tau, n, mo = oracle_lib.params(max_error, min_len, k)
+    _, cands = ix.search(g.spans, max_error, min_len)
+    regs = _regions_of(cands, off)
+    regs += _random_boxes(np.random.default_rng(7 + k), off, 6)
+    out = ix.extend(regs, tau)
+    br = brute.Brute(b, off, k, w)
+    for r, o in zip(regs, out):
+        assert tuple(int(x) for x in o) == brute.extend(br, *r, tau), r
+    # a capped variant exercises the length limit
+    cap = 900
+    out = ix.extend(regs, tau, cap)
+    for r, o in zip(regs, out):
+        assert tuple(int(x) for x in o) == brute.extend(br, *r, tau, cap), r
+
+
+def _ext(ix, reg, tau, max_len=1000000):
+    return tuple(int(x) for x in ix.extend([reg], tau, max_len)[0])
+
+
+def test_extend_closed_forms(oracle_lib):
+    """Closed forms of the Section 3.2 extension: an exact copy on another
+    sequence extends to both whole sequences (estimate 1 throughout), on
+    either strand; the length cap stops it at exactly max_len; on one
+    sequence a copy separated by a gap extends until the two substrings
+    touch and then cannot grow back; unrelated substrings do not extend; a
+    start longer than max_len is returned unevaluated; a region across two
+    sequences is rejected."""
+    rng = synth.rng_for(123)
+    A = synth.random_bases(rng, 6000)
+    ix = oracle_lib.OracleIndex(*_genome([A, A.copy()]), 12, 16)
+    tau, _, _ = oracle_lib.params(0.25, 1000, 12)
+    L = len(A)
+    s_all = len(set(ix.minimizers()[1][ix.minimizers()[0] < L].tolist()))
+    assert _ext(ix, (2000, 2750, L + 2000, L + 2750, 0), tau) == (0, L, L, 2 * L, s_all, s_all, 1 | 1 << 8)
+    # max_len: forward grows to exactly max_len, backward cannot grow
+    assert _ext(ix, (2000, 2750, L + 2000, L + 2750, 0), tau, 1250)[:4] == (2000, 3250, L + 2000, L + 3250)
+    assert _ext(ix, (2000, 2750, L + 2000, L + 2750, 0), tau, 1250)[6] == 2 | 2 << 8
+    # reverse-complement copy: target grows leftwards while the query grows right
+    ixr = oracle_lib.OracleIndex(*_genome([A, synth.revcomp(A)]), 12, 16)
+    r = _ext(ixr, (2000, 2750, L + L - 2750, L + L - 2000, 1), tau)
+    assert r[:4] == (0, L, L, 2 * L) and r[6] == 1 | 1 << 8 and r[4] >= r[5] - 2
+    # one sequence: X, a 300 bp spacer, X again, 2 kbp tail; o = 0
+    X = synth.random_bases(rng, 5000)
+    S = np.concatenate([X, synth.random_bases(rng, 300), X, synth.random_bases(rng, 2000)])
+    ix1 = oracle_lib.OracleIndex(*_genome([S]), 12, 16)
+    r = _ext(ix1, (1000, 2000, 6300, 7300, 0), tau)
+    assert r[:4] == (1000, 6300, 6300, 11600) and r[6] == 3 | 3 << 8
+    # unrelated substrings: below tau at once, nothing grows
+    B = synth.random_bases(rng, 6000)
+    ixu = oracle_lib.OracleIndex(*_genome([A, B]), 12, 16)
+    r = _ext(ixu, (2000, 2750, L + 2000, L + 2750, 0), tau)
+    assert r[:4] == (2000, 2750, L + 2000, L + 2750) and r[6] == 4 | 4 << 8
+    assert r[4] < oracle_lib.threshold(tau, r[5])
+    # a start longer than max_len
+    assert _ext(ix, (0, 3000, L, L + 3000, 0), tau, 2000) == (0, 3000, L, L + 3000, 0, 0, 2 | 2 << 8)
+    with pytest.raises(ValueError):
+        ix.extend([(L - 100, L + 100, L + 2000, L + 2750, 0)], tau)
+
+
+def test_extend_invariants(oracle_lib):
+    """Whatever the input, the result contains the start region, neither
+    side exceeds max_len, a region that grew ends in a state that passes
+    (m >= ceil(tau s)), and on one sequence a region that grew does not
+    intersect itself."""
+    g = synth.small_case(77, length=6000, n_sd=4, sd_lo=400, sd_hi=1500, n_seqs=2,
+                         lower_frac=0.2, n_gaps=1, gap_len=40, rate_hi=0.1)
+    b, off = g.concat()
+    ix = oracle_lib.OracleIndex(b, off, 12, 16)
+    tau, _, _ = oracle_lib.params(0.25, 400, 12)
+    _, cands = ix.search(g.spans, 0.25, 400)
+    regs = _regions_of(cands, off) + _random_boxes(np.random.default_rng(3), off, 40)
+    seq_of = lambda p: int(np.searchsorted(off, p, side="right")) - 1
+    for cap in (1000000, 1500):
+        out = ix.extend(regs, tau, cap)
+        for r, o in zip(regs, out):
+            q0, q1, t0, t1, m, s, stop = (int(x) for x in o)
+            assert q0 <= r[0] and r[1] <= q1 and t0 <= r[2] and r[3] <= t1
+            if r[1] - r[0] > cap or r[3] - r[2] > cap:
+                assert (q0, q1, t0, t1, m, s) == r[:4] + (0, 0)
+                continue
+            assert q1 - q0 <= cap and t1 - t0 <= cap
+            grew = (q0, q1, t0, t1) != r[:4]
+            if grew:
+                assert s > 0 and m >= oracle_lib.threshold(tau, s)
+                if seq_of(q0) == seq_of(t0):
+                    assert q1 <= t0 or t1 <= q0
+            assert 1 <= (stop & 255) <= 4 and 1 <= (stop >> 8) <= 4

@@ -68,7 +68,8 @@ typedef struct {
  * targets delta <= 0.25).  min_len: minimum duplication length L (Section 2:
  * 1000 bp); the seed window length is n = ceil(L (1 - delta)) (Section 3).
  * Requires k + w - 1 <= n <= 65536.  flags: SDF_TIMING records per-stage GPU
- * times; SDF_SEED_ESTIMATE chooses seeds by the winnowed MinHash estimate. */
+ * times; SDF_SEED_ESTIMATE chooses seeds by the winnowed MinHash estimate;
+ * SDF_EXTEND extends every candidate (Section 3.2). */
 typedef struct {
     double max_error;
     uint32_t min_len;
@@ -85,6 +86,10 @@ typedef struct {
  * candidates' max_shared then hold m.  Windows of more than 1024 minimizers
  * are rejected with SDF_EINTERNAL in this mode. */
 #define SDF_SEED_ESTIMATE 2u
+/* Extend every candidate to a potential duplication region (Section 3.2, as
+ * sdf_extend does with max_len = 1,000,000); read the regions with
+ * sdf_result_regions.  The candidates themselves are unchanged. */
+#define SDF_EXTEND 4u
 
 /* A query span [begin, end) of sequence `seq`. */
 typedef struct {
@@ -176,6 +181,58 @@ void sdf_index_free(sdf_index ix);
  */
 sdf_status sdf_search(sdf_index ix, const sdf_span *q, const sdf_search_params *p,
                       void *hip_stream, sdf_result *out);
+
+/* A region: substrings [q_begin, q_end) of sequence q_seq and [t_begin,
+ * t_end) of t_seq in orientation `strand` (0 direct, 1 the target read
+ * reverse-complemented), per-sequence 0-based half-open coordinates.  As
+ * output of an extension: m and s are the estimate's numerator and sketch
+ * size of the final state (estimate m / s), `stop` the stop code of the
+ * forward phase in bits 0-7 and of the backward phase in bits 8-15
+ * (SDF_STOP_*).  56 bytes, fixed layout. */
+typedef struct {
+    uint32_t strand, q_seq, t_seq, stop;
+    uint64_t q_begin, q_end, t_begin, t_end;
+    uint32_t m, s;
+} sdf_region;
+
+/* Stop codes: the first condition (in this order) met by the refused step. */
+#define SDF_STOP_BOUND 1u    /* a side would leave its sequence */
+#define SDF_STOP_CAP 2u      /* a side would exceed max_len */
+#define SDF_STOP_OVERLAP 3u  /* the two sides would intersect (same sequence) */
+#define SDF_STOP_ESTIMATE 4u /* the estimate of the new state is below tau */
+
+/* max_error: the error bound delta (tau follows from it and k as for the
+ * search); max_len: longest side a region may reach (Section 3.2: 1 Mbp). */
+typedef struct {
+    double max_error;
+    uint64_t max_len;
+} sdf_extend_params;
+
+/* Extension of regions to potential duplications (Section 3.2).  Each region
+ * of `in` (host array, n entries; strand, q_seq, t_seq and the four bounds
+ * are read) grows one base per step on both sides, first forward (the
+ * query's right end and the target's right end for strand 0, its left end
+ * for strand 1), then backward from the forward result (the other ends).
+ * A phase stops at the first step that would leave a sequence, make a side
+ * longer than max_len, make the sides intersect on one sequence, or give a
+ * state whose winnowed MinHash estimate is below tau; it keeps the state
+ * before that step.  State: W(G_i) and W(G_j) hold every minimizer whose
+ * k-mer lies inside the side (masked ones too); s = |W(G_i)| in distinct
+ * hashes; m = hashes among the s smallest of W(G_i) u W(G_j) that occur on
+ * both sides with strands a, b such that a xor b = strand; the state passes
+ * when s > 0 and m >= ceil(tau s).  A region with a side longer than max_len
+ * is returned unchanged with m = s = 0 and both stop codes SDF_STOP_CAP.
+ * Results go to `out` (host array of n, may equal `in`), in input order.
+ * Errors: SDF_EINVAL for NULL arguments, strand > 1, a side shorter than k
+ * or max_len < k; SDF_ERANGE for a sequence id or bound outside the index;
+ * SDF_EINTERNAL when a region needs more scratch than the library holds per
+ * workgroup (about 500,000 minimizers in its windows and horizons). */
+sdf_status sdf_extend(sdf_index ix, const sdf_region *in, uint64_t n,
+                      const sdf_extend_params *p, void *hip_stream, sdf_region *out);
+
+/* Regions of a search run with SDF_EXTEND: one per candidate, in the order
+ * of sdf_result_copy.  SDF_EINVAL if the search ran without the flag. */
+sdf_status sdf_result_regions(sdf_result r, sdf_region *dst, uint64_t cap, uint64_t *written);
 
 /* Search n spans (host array) in one launch sequence; candidate query_id is
  * the index of its span in qs.  Same errors as sdf_search. */

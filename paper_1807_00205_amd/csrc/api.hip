@@ -26,7 +26,10 @@ struct sdf_result_s {
     bool have_cands = false;
     std::vector<uint32_t> h_seeds;
     bool have_seeds = false;
-    float ms[5] = {0, 0, 0, 0, 0};
+    float ms[6] = {0, 0, 0, 0, 0, 0};
+    bool have_regions = false;
+    DevBuf<sdf_region> regions;  // one per candidate with SDF_EXTEND
+    ExtStats ext;
     uint64_t stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 
@@ -50,6 +53,33 @@ sdf_status guarded(F &&f) {
     }
 }
 
+// Section 3.2: potential duplications are at most 1 Mbp long.
+constexpr uint64_t EXT_MAX_LEN = 1000000;
+
+__global__ void k_cand_regions(const sdf_candidate *c, uint64_t n, sdf_region *r) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const sdf_candidate x = c[i];
+    sdf_region y;
+    y.strand = x.strand;
+    y.q_seq = x.q_seq;
+    y.t_seq = x.t_seq;
+    y.stop = 0;
+    y.q_begin = x.q_begin;
+    y.q_end = x.q_end;
+    y.t_begin = x.t_begin;
+    y.t_end = x.t_end;
+    y.m = y.s = 0;
+    r[i] = y;
+}
+
+// tau of Section 3.1 for error bound d and k-mer length k.
+double tau_of(double d, uint32_t k) {
+    const double dM = d < 0.15 ? d : 0.15;
+    const double dG = d - dM;
+    return ((1.0 - dG) / (1.0 + dG)) / (2.0 * std::exp((double)k * dM) - 1.0);
+}
+
 struct Params {
     double tau;
     uint32_t n, max_overlap;
@@ -64,9 +94,7 @@ Params derive(const sdf_search_params *p, uint32_t k, uint32_t w) {
     if (!(d > 0.0 && d < 1.0)) throw Error{SDF_EINVAL, "max_error must lie in (0, 1)"};
     if (p->min_len < k + w - 1) throw Error{SDF_EINVAL, "min_len must be at least k + w - 1"};
     Params r;
-    const double dM = d < 0.15 ? d : 0.15;
-    const double dG = d - dM;
-    r.tau = ((1.0 - dG) / (1.0 + dG)) / (2.0 * std::exp((double)k * dM) - 1.0);
+    r.tau = tau_of(d, k);
     const double nn = std::ceil((double)p->min_len * (1.0 - d));
     if (nn < (double)(k + w - 1) || nn > 65536.0)
         throw Error{SDF_EINVAL, "seed window length n = ceil(min_len (1 - max_error)) must lie in [k + w - 1, 65536]"};
@@ -291,12 +319,27 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
     chain_seeds(ix->view(), res->seeds.p, res->nseeds, P.n, P.max_overlap, nq, res->chain, st);
     tm.mark();
     tm.mark();
+    if (p->flags & SDF_EXTEND) {
+        // Section 3.2: every candidate's box is extended while the estimate holds
+        const uint64_t nc = res->chain.ncands;
+        res->regions.alloc(nc);
+        if (nc) {
+            k_cand_regions<<<(unsigned)((nc + 255) / 256), 256, 0, st>>>(res->chain.cands.p, nc,
+                                                                         res->regions.p);
+            SDF_HIP(hipGetLastError());
+            launch_extend(ix->view(), res->regions.p, nc, P.tau, EXT_MAX_LEN, res->regions.p,
+                          &res->ext, st);
+        }
+        res->have_regions = true;
+    }
+    tm.mark();
     SDF_HIP(hipStreamSynchronize(st));
     res->ms[0] = tm.between(0, 1);
     res->ms[1] = tm.kernel_ms();
     res->ms[2] = tm.between(2, 3);
     res->ms[3] = tm.between(3, 4);
-    res->ms[4] = tm.between(0, 4);
+    res->ms[4] = tm.between(0, 5);
+    res->ms[5] = tm.between(4, 5);
 }
 
 }  // namespace
@@ -498,7 +541,54 @@ sdf_status sdf_result_seeds(sdf_result r, sdf_seed *dst, uint64_t cap, uint64_t 
 sdf_status sdf_result_timing(sdf_result r, float *ms, uint32_t n_ms) {
     return guarded([&] {
         if (!r || (n_ms && !ms)) throw Error{SDF_EINVAL, "NULL argument"};
-        for (uint32_t t = 0; t < n_ms && t < 5; t++) ms[t] = r->ms[t];
+        for (uint32_t t = 0; t < n_ms && t < 6; t++) ms[t] = r->ms[t];
+    });
+}
+
+sdf_status sdf_result_regions(sdf_result r, sdf_region *dst, uint64_t cap, uint64_t *written) {
+    return guarded([&] {
+        if (!r) throw Error{SDF_EINVAL, "NULL result"};
+        if (!r->have_regions) throw Error{SDF_EINVAL, "the search ran without SDF_EXTEND"};
+        const uint64_t m = std::min<uint64_t>(cap, r->chain.ncands);
+        if (m && !dst) throw Error{SDF_EINVAL, "NULL destination"};
+        if (m) {
+            SDF_HIP(hipSetDevice(r->device));
+            SDF_HIP(hipMemcpyAsync(dst, r->regions.p, m * sizeof(sdf_region),
+                                   hipMemcpyDeviceToHost, r->st));
+            SDF_HIP(hipStreamSynchronize(r->st));
+        }
+        if (written) *written = m;
+    });
+}
+
+sdf_status sdf_extend(sdf_index ix, const sdf_region *in, uint64_t n, const sdf_extend_params *p,
+                      void *hip_stream, sdf_region *out) {
+    return guarded([&] {
+        if (!ix || !p || (n && (!in || !out))) throw Error{SDF_EINVAL, "NULL argument"};
+        const double d = p->max_error;
+        if (!(d > 0.0 && d < 1.0)) throw Error{SDF_EINVAL, "max_error must lie in (0, 1)"};
+        if (p->max_len < ix->k) throw Error{SDF_EINVAL, "max_len must be at least k"};
+        for (uint64_t i = 0; i < n; i++) {
+            const sdf_region &x = in[i];
+            if (x.strand > 1) throw Error{SDF_EINVAL, "strand must be 0 or 1"};
+            if (x.q_seq >= ix->nseq || x.t_seq >= ix->nseq)
+                throw Error{SDF_ERANGE, "region sequence index out of range"};
+            const uint64_t ql = ix->h_off[x.q_seq + 1] - ix->h_off[x.q_seq];
+            const uint64_t tl = ix->h_off[x.t_seq + 1] - ix->h_off[x.t_seq];
+            if (x.q_begin > x.q_end || x.q_end > ql || x.t_begin > x.t_end || x.t_end > tl)
+                throw Error{SDF_ERANGE, "region outside its sequence"};
+            if (x.q_end - x.q_begin < ix->k || x.t_end - x.t_begin < ix->k)
+                throw Error{SDF_EINVAL, "a region side is shorter than k"};
+        }
+        if (n == 0) return;
+        SDF_HIP(hipSetDevice(ix->device));
+        const hipStream_t st = (hipStream_t)hip_stream;
+        StreamScope scope(st);
+        DevBuf<sdf_region> buf(n);
+        SDF_HIP(hipMemcpyAsync(buf.p, in, n * sizeof(sdf_region), hipMemcpyHostToDevice, st));
+        launch_extend(ix->view(), buf.p, n, tau_of(d, ix->k), p->max_len, buf.p, nullptr, st);
+        SDF_HIP(hipMemcpyAsync(out, buf.p, n * sizeof(sdf_region), hipMemcpyDeviceToHost, st));
+        SDF_HIP(hipStreamSynchronize(st));
     });
 }
 

@@ -1,0 +1,833 @@
+// Extension of regions by the winnowed MinHash estimate (Section 3.2).
+//
+// A region pairs G_i = [q0, q1) with G_j = [t0, t1) in orientation o.  Both
+// grow by one base per step, first forward (query right end; target right end
+// for o = 0, left end for o = 1), then backward from the forward result
+// (query left end; target left end for o = 0, right end for o = 1).  A phase
+// stops at the first step that leaves a sequence, makes a side longer than
+// max_len, makes the two sides intersect (same sequence), or gives a state
+// whose estimate m / s is below tau; it keeps the state before that step.
+//
+// The state is the ordered set L of Section 3.1: the distinct hashes of
+// W(G_i) u W(G_j) in ascending order, each with the strands it has on either
+// side.  s = |W(G_i)|, and m counts the hashes among the s smallest of L that
+// occur on both sides with strands a, b, a xor b = o.  Every minimizer whose
+// k-mer lies in a side belongs to it (masked and palindromic ones too).
+//
+// One workgroup takes one region:
+//  1. the minimizers of both start windows and of every position a phase can
+//     reach within a horizon H are gathered (six contiguous ranges of the
+//     position-sorted minimizer array) and ranked by hash: bucketed on the
+//     top 12 hash bits, each run of buckets sorted in LDS (bitonic), equal
+//     hashes sharing a rank, so L becomes an array of 4-bit cells by rank;
+//  2. the start windows' minimizers are set, and s, the rank v of the s-th
+//     smallest element of L, and m are counted in parallel;
+//  3. one wave walks the minimizers that enter, in step order, keeping s, v
+//     and m up to date per insertion (v moves at most one element of L, to
+//     its successor or predecessor), and checks m >= ceil(tau s) after each
+//     step; a refused step is undone.  Steps at which no minimizer enters
+//     keep the previous state and its verdict.
+// A phase that passes its horizon without stopping restarts the region with
+// a four times larger one.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+
+#include "search.h"
+
+namespace sdf {
+
+namespace {
+
+constexpr int XT = 256;                 // threads per workgroup
+constexpr uint32_t NB = 4096;           // buckets over 12 hash bits
+constexpr uint32_t CH = 4096;           // keys sorted at once in LDS
+constexpr uint32_t HALF = CH / 2;
+constexpr uint32_t LDS_WORDS = NB + 1 + (NB + 2) / 2 + 2 * CH + 1;  // the sort area, as words
+constexpr uint64_t INF = 1ull << 62;
+
+enum { C_Q0 = 1, C_Q1 = 2, C_T0 = 4, C_T1 = 8 };
+enum { STOP_BOUND = 1, STOP_CAP = 2, STOP_OVERLAP = 3, STOP_ESTIMATE = 4 };
+enum { XE_CAP = 1, XE_HASH = 2, XE_STATE = 4 };
+
+struct ExtArgs {
+    IndexView ix;
+    const sdf_region *in;
+    uint64_t n;
+    sdf_region *out;
+    double tau;
+    uint64_t max_len;
+    uint64_t h0;            // first horizon: h0 + 2 * longer side (steps per phase)
+    uint32_t *work;         // region counter
+    uint64_t *tmp;          // per workgroup: ecap keys
+    uint32_t *rank;         // per workgroup: ecap
+    uint32_t *gnib;         // per workgroup: ecap / 8 + 1
+    uint64_t ecap;
+    uint32_t lds_words;     // cells kept in LDS up to 8 * lds_words ranks
+    uint32_t *err;
+    unsigned long long *stats;  // [0] events applied, [1] restarts, [2] ranks
+};
+
+struct Shared {
+    union {
+        struct {
+            uint32_t bs[NB + 1];    // bucket starts
+            uint16_t cl[NB + 2];    // first bucket of each chunk
+            uint64_t ck[CH];        // one chunk of keys being sorted
+        };
+        uint32_t w[LDS_WORDS];      // afterwards: the cells of L
+    };
+    uint32_t red[XT];
+    uint64_t mlo[6], mhi[6];
+    uint32_t base[7];
+    uint32_t region;
+    uint32_t nrank, nchunk, cnt;
+    int32_t v;
+    uint32_t s, m;
+    uint32_t flag;
+};
+
+__device__ __forceinline__ uint64_t lower_pos(const IndexView &ix, uint64_t x) {
+    uint64_t lo = 0, hi = ix.nm;  // first minimizer with pos >= x
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if ((uint64_t)ix.mpos[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// Cell bits present per nibble (bit 0 of each nibble set).
+__device__ __forceinline__ uint32_t nz_mask(uint32_t w) {
+    return (w | (w >> 1) | (w >> 2) | (w >> 3)) & 0x11111111u;
+}
+__device__ __forceinline__ uint32_t q_mask(uint32_t w) {
+    return (w | (w >> 1)) & 0x11111111u;
+}
+__device__ __forceinline__ uint32_t shared_mask(uint32_t w, uint32_t o) {
+    if (o == 0) {
+        const uint32_t x = w & (w >> 2) & 0x33333333u;
+        return (x | (x >> 1)) & 0x11111111u;
+    }
+    return ((w & (w >> 3)) | ((w >> 1) & (w >> 2))) & 0x11111111u;
+}
+__device__ __forceinline__ bool cell_shared(uint32_t c, uint32_t o) {
+    return shared_mask(c, o) != 0;
+}
+
+// Exclusive block scan of one value per thread; returns the total.
+__device__ uint32_t block_scan(Shared &L, uint32_t v, uint32_t &excl) {
+    const int t = threadIdx.x;
+    L.red[t] = v;
+    __syncthreads();
+    for (int d = 1; d < XT; d <<= 1) {
+        const uint32_t a = t >= d ? L.red[t - d] : 0;
+        __syncthreads();
+        L.red[t] += a;
+        __syncthreads();
+    }
+    excl = L.red[t] - v;
+    const uint32_t tot = L.red[XT - 1];
+    __syncthreads();
+    return tot;
+}
+
+__device__ uint32_t block_sum(Shared &L, uint32_t v) {
+    uint32_t e;
+    return block_scan(L, v, e);
+}
+
+// Region geometry of one phase: which ends grow.
+struct Phase {
+    uint32_t ql, qr, tl, tr;  // growth per step of q0 (down), q1 (up), t0 (down), t1 (up)
+};
+__device__ __forceinline__ Phase phase_of(int dir, uint32_t o) {
+    Phase p;
+    p.ql = dir; p.qr = 1 - dir;
+    p.tl = dir == 0 ? o : 1 - o;
+    p.tr = 1 - p.tl;
+    return p;
+}
+
+// Steps a phase may take before a sequence end, the length cap or an
+// overlap, and the stop code of the first refused step.
+__device__ void phase_limit(const uint64_t r[4], uint64_t qlo, uint64_t qhi, uint64_t tlo,
+                            uint64_t thi, bool same_seq, const Phase &p, uint64_t max_len,
+                            uint64_t &lim, uint32_t &code) {
+    uint64_t lb = INF;
+    if (p.ql) lb = std::min(lb, r[0] - qlo);
+    if (p.qr) lb = std::min(lb, qhi - r[1]);
+    if (p.tl) lb = std::min(lb, r[2] - tlo);
+    if (p.tr) lb = std::min(lb, thi - r[3]);
+    const uint64_t lc = max_len - std::max(r[1] - r[0], r[3] - r[2]);
+    uint64_t lo = INF;
+    if (same_seq) {
+        if (r[1] <= r[2]) {  // query before target
+            const uint64_t c = p.qr + p.tl;
+            lo = c ? (r[2] - r[1]) / c : INF;
+        } else if (r[3] <= r[0]) {  // target before query
+            const uint64_t c = p.ql + p.tr;
+            lo = c ? (r[0] - r[3]) / c : INF;
+        } else {
+            lo = 0;
+        }
+    }
+    lim = std::min(lb, std::min(lc, lo));
+    code = lb == lim ? STOP_BOUND : (lc == lim ? STOP_CAP : STOP_OVERLAP);
+}
+
+struct Est {
+    int32_t v;  // rank of the s-th smallest element of L (-1 when s = 0)
+    uint32_t s, m;
+};
+
+__device__ __forceinline__ bool passes(const Est &e, double tau) {
+    return e.s > 0 && e.m >= (uint32_t)ceil(tau * (double)e.s);
+}
+
+__device__ __forceinline__ uint32_t cell_at(const uint32_t *nib, int32_t r) {
+    return (nib[r >> 3] >> ((r & 7) * 4)) & 15u;
+}
+
+// Smallest rank > v holding an element (one exists by construction).
+__device__ int32_t succ_rank(const uint32_t *nib, int32_t v, uint32_t nw) {
+    const int32_t r = v + 1;
+    if ((uint32_t)r >= nw * 8) return -2;
+    uint32_t w = (uint32_t)r >> 3;
+    uint32_t u = nz_mask(nib[w] & (0xFFFFFFFFu << ((r & 7) * 4)));
+    while (u == 0 && ++w < nw) u = nz_mask(nib[w]);
+    return u ? (int32_t)(w * 8 + (__builtin_ctz(u) >> 2)) : -2;
+}
+
+// Largest rank < v holding an element (one exists by construction).
+__device__ int32_t pred_rank(const uint32_t *nib, int32_t v) {
+    const int32_t r = v - 1;
+    if (r < 0) return -2;
+    int32_t w = r >> 3;
+    const uint32_t keep = (r & 7) == 7 ? 0xFFFFFFFFu : ((1u << (((r & 7) + 1) * 4)) - 1u);
+    uint32_t u = nz_mask(nib[w] & keep);
+    while (u == 0 && --w >= 0) u = nz_mask(nib[w]);
+    return u ? (int32_t)(w * 8 + ((31 - __builtin_clz(u)) >> 2)) : -2;
+}
+
+struct Undo {
+    uint32_t n;
+    uint32_t w[2], old[2];
+};
+
+// Adds `bit` to the cell of rank r and updates (s, v, m).  Returns false
+// when the structure is inconsistent (never for a valid state).
+__device__ bool insert(uint32_t *nib, uint32_t nw, uint32_t r, uint32_t bit, uint32_t o, Est &e,
+                       Undo &u) {
+    const uint32_t wi = r >> 3, sh = (r & 7) * 4;
+    const uint32_t word = nib[wi];
+    const uint32_t c = (word >> sh) & 15u, c2 = c | bit;
+    if (c2 == c) return true;
+    u.w[u.n] = wi;
+    u.old[u.n] = word;
+    u.n++;
+    nib[wi] = word | (bit << sh);
+    const bool was_u = c != 0;
+    const bool new_q = (bit & 3u) && !(c & 3u);
+    const bool gain = !cell_shared(c, o) && cell_shared(c2, o);
+    const int32_t ri = (int32_t)r;
+    if (new_q) {
+        e.s++;
+        if (!was_u && ri < e.v) return true;  // enters below v: v stays the s-th
+        if (was_u && ri <= e.v && gain) e.m++;
+        const int32_t vn = succ_rank(nib, e.v, nw);
+        if (vn < 0) return false;
+        if (cell_shared(cell_at(nib, vn), o)) e.m++;
+        e.v = vn;
+    } else if (!was_u) {
+        if (ri < e.v) {  // a new target-side element pushes v out of the s smallest
+            if (cell_shared(cell_at(nib, e.v), o)) e.m--;
+            const int32_t vn = pred_rank(nib, e.v);
+            if (vn < 0) return false;
+            e.v = vn;
+        }
+    } else if (ri <= e.v && gain) {
+        e.m++;
+    }
+    return true;
+}
+
+__device__ __forceinline__ void undo(uint32_t *nib, const Undo &u) {
+    for (int t = (int)u.n - 1; t >= 0; t--) nib[u.w[t]] = u.old[t];
+}
+
+// One list of entering minimizers: the minimizer array range [lo, hi),
+// walked upwards (step = pos + k - ref) or downwards (step = ref - pos).
+struct EvList {
+    uint64_t lo, hi;
+    bool up;
+    uint64_t ref;
+    uint32_t side;  // C_Q0 or C_T0
+    uint32_t base;  // element id of index lo
+};
+
+struct EvCursor {
+    uint64_t next;     // events consumed
+    uint64_t count;
+    uint32_t fill;     // events held in registers (lane-indexed)
+    uint32_t at;       // next held event
+    uint64_t vstep;    // this lane's held event
+    uint32_t vrank, vbit;
+};
+
+__device__ __forceinline__ void ev_refill(const ExtArgs &a, const uint32_t *rank, const EvList &l,
+                                          EvCursor &c) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t e = c.next + lane;
+    c.fill = (uint32_t)std::min<uint64_t>(64, c.count - c.next);
+    c.at = 0;
+    c.vstep = INF;
+    if (e < c.count) {
+        const uint64_t mi = l.up ? l.lo + e : l.hi - 1 - e;
+        const uint64_t pos = a.ix.mpos[mi];
+        c.vstep = l.up ? pos + a.ix.k - l.ref : l.ref - pos;
+        c.vrank = rank[l.base + (uint32_t)(mi - l.lo)];
+        c.vbit = l.side << (a.ix.mflags[mi] & 1);
+    }
+}
+
+__device__ __forceinline__ uint64_t ev_head(const EvCursor &c) {
+    if (c.at >= c.fill) return INF;
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)c.vstep, c.at);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(c.vstep >> 32), c.at);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// One phase on wave 0.  Returns the steps taken; `code` is the stop code,
+// or 0 when the events ran out before the phase could stop (larger horizon
+// needed).
+__device__ uint64_t run_phase(const ExtArgs &a, uint32_t *nib, uint32_t nw, const uint32_t *rank,
+                              const EvList &lq, const EvList &lt, uint64_t known, uint64_t lim,
+                              uint32_t lim_code, uint32_t o, Est &e, bool &ok, uint32_t &code,
+                              unsigned long long &applied, bool &bad) {
+    EvCursor cq, ct;
+    cq.next = ct.next = 0;
+    cq.count = lq.hi - lq.lo;
+    ct.count = lt.hi - lt.lo;
+    ev_refill(a, rank, lq, cq);
+    ev_refill(a, rank, lt, ct);
+    uint64_t last = 0;
+    for (;;) {
+        if (cq.at >= cq.fill && cq.next + cq.fill < cq.count) {
+            cq.next += cq.fill;
+            ev_refill(a, rank, lq, cq);
+        }
+        if (ct.at >= ct.fill && ct.next + ct.fill < ct.count) {
+            ct.next += ct.fill;
+            ev_refill(a, rank, lt, ct);
+        }
+        const uint64_t sq = ev_head(cq), st = ev_head(ct);
+        const uint64_t te = std::min(sq, st);
+        if (te > known) break;
+        if (te > last + 1) {  // steps without an entering minimizer keep the state
+            if (!ok) { code = STOP_ESTIMATE; return last; }
+            last = te - 1;
+        }
+        const Est prev = e;
+        const bool prev_ok = ok;
+        Undo u;
+        u.n = 0;
+        if (sq == te) {
+            const uint32_t r = __builtin_amdgcn_readlane(cq.vrank, cq.at);
+            const uint32_t b = __builtin_amdgcn_readlane(cq.vbit, cq.at);
+            bad |= !insert(nib, nw, r, b, o, e, u);
+            cq.at++;
+            applied++;
+        }
+        if (st == te) {
+            const uint32_t r = __builtin_amdgcn_readlane(ct.vrank, ct.at);
+            const uint32_t b = __builtin_amdgcn_readlane(ct.vbit, ct.at);
+            bad |= !insert(nib, nw, r, b, o, e, u);
+            ct.at++;
+            applied++;
+        }
+        ok = passes(e, a.tau);
+        if (!ok) {
+            undo(nib, u);
+            e = prev;
+            ok = prev_ok;
+            code = STOP_ESTIMATE;
+            return te - 1;
+        }
+        last = te;
+    }
+    if (last < known) {
+        if (!ok) { code = STOP_ESTIMATE; return last; }
+        last = known;
+    }
+    if (known >= lim) { code = lim_code; return lim; }
+    code = 0;  // the horizon ended first
+    return last;
+}
+
+// Keys [b, e) of src (whole buckets, so no hash continues outside): sort
+// in LDS and give every element its rank, equal hashes sharing one.
+__device__ void rank_chunk(Shared &L, const uint64_t *src, uint64_t b, uint64_t e, uint32_t *rank) {
+    uint64_t *ck = L.ck;
+    const uint32_t cnt = (uint32_t)(e - b);
+    uint32_t P = 1;
+    while (P < cnt) P <<= 1;
+    for (uint32_t i = threadIdx.x; i < P; i += XT) ck[i] = i < cnt ? src[b + i] : ~0ull;
+    __syncthreads();
+    for (uint32_t size = 2; size <= P; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (uint32_t i = threadIdx.x; i < P / 2; i += XT) {
+                const uint32_t lo = 2 * stride * (i / stride) + (i % stride), hi = lo + stride;
+                const bool asc = (lo & size) == 0;
+                const uint64_t x = ck[lo], y = ck[hi];
+                if ((x > y) == asc) { ck[lo] = y; ck[hi] = x; }
+            }
+            __syncthreads();
+        }
+    }
+    const uint32_t seg = (cnt + XT - 1) / XT;
+    const uint32_t s0 = std::min(cnt, threadIdx.x * seg), s1 = std::min(cnt, s0 + seg);
+    uint32_t heads = 0;
+    for (uint32_t i = s0; i < s1; i++)
+        heads += (i == 0 || (ck[i] >> 32) != (ck[i - 1] >> 32)) ? 1u : 0u;
+    uint32_t excl;
+    const uint32_t tot = block_scan(L, heads, excl);
+    uint32_t r = L.nrank + excl;
+    for (uint32_t i = s0; i < s1; i++) {
+        if (i == 0 || (ck[i] >> 32) != (ck[i - 1] >> 32)) r++;
+        rank[(uint32_t)ck[i]] = r - 1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) L.nrank += tot;
+    __syncthreads();
+}
+
+// A bucket of more than CH keys (in practice one hash repeated many times,
+// as in a tandem array): collect its distinct hashes in an LDS hash set,
+// sort them, and rank each key by binary search.  More than BIGD distinct
+// hashes in one bucket is reported as an error.
+constexpr uint32_t BIGT = CH / 2;  // hash set slots (u64, tagged)
+constexpr uint32_t BIGD = CH / 4;  // distinct hashes allowed
+__device__ bool rank_big(Shared &L, const uint64_t *src, uint64_t b, uint64_t e, uint32_t *rank) {
+    uint64_t *set = L.ck;           // BIGT slots: (1 << 32) | hash, 0 = empty
+    uint64_t *list = L.ck + BIGT;   // BIGT sorted distinct hashes
+    for (uint32_t i = threadIdx.x; i < BIGT; i += XT) set[i] = 0;
+    if (threadIdx.x == 0) { L.cnt = 0; L.flag = 0; }
+    __syncthreads();
+    for (uint64_t i = b + threadIdx.x; i < e; i += XT) {
+        const uint32_t h = (uint32_t)(src[i] >> 32);
+        const uint64_t tag = (1ull << 32) | h;
+        uint32_t slot = (h * 0x9E3779B1u) >> 21;  // 11 bits: BIGT = 2048
+        for (uint32_t probe = 0;; probe++) {
+            if (probe >= BIGT || L.cnt > BIGD) { L.flag = 1; break; }
+            const uint64_t prev = atomicCAS((unsigned long long *)&set[slot], 0ull,
+                                            (unsigned long long)tag);
+            if (prev == 0) { atomicAdd(&L.cnt, 1u); break; }
+            if (prev == tag) break;
+            slot = (slot + 1) & (BIGT - 1);
+        }
+    }
+    __syncthreads();
+    if (L.flag || L.cnt > BIGD) return false;
+    const uint32_t D = L.cnt;
+    uint32_t P = 1;
+    while (P < D) P <<= 1;
+    if (threadIdx.x == 0) L.cnt = 0;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < BIGT; i += XT)
+        if (set[i]) list[atomicAdd(&L.cnt, 1u)] = set[i] & 0xFFFFFFFFull;
+    __syncthreads();
+    for (uint32_t i = D + threadIdx.x; i < P; i += XT) list[i] = ~0ull;
+    __syncthreads();
+    for (uint32_t size = 2; size <= P; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (uint32_t i = threadIdx.x; i < P / 2; i += XT) {
+                const uint32_t lo = 2 * stride * (i / stride) + (i % stride), hi = lo + stride;
+                const bool asc = (lo & size) == 0;
+                const uint64_t x = list[lo], y = list[hi];
+                if ((x > y) == asc) { list[lo] = y; list[hi] = x; }
+            }
+            __syncthreads();
+        }
+    }
+    for (uint64_t i = b + threadIdx.x; i < e; i += XT) {
+        const uint64_t key = src[i];
+        const uint64_t h = key >> 32;
+        uint32_t lo = 0, hi = D;  // first index with list[index] >= h
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (list[mid] < h) lo = mid + 1; else hi = mid;
+        }
+        rank[(uint32_t)key] = L.nrank + lo;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) L.nrank += D;
+    __syncthreads();
+    return true;
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(XT) k_extend(ExtArgs a) {
+    __shared__ Shared L;
+    const IndexView &ix = a.ix;
+    const uint32_t k = ix.k;
+    const uint64_t blk = blockIdx.x;
+    uint64_t *tmp = a.tmp + blk * a.ecap;
+    uint32_t *rank = a.rank + blk * a.ecap;
+    uint32_t *gnib = a.gnib + blk * (a.ecap / 8 + 1);
+    const uint32_t hbits = 2 * k;
+    const uint32_t shift = hbits > 12 ? hbits - 12 : 0;
+    const uint32_t nbk = 1u << (hbits - shift);
+
+    for (;;) {
+        if (threadIdx.x == 0) L.region = atomicAdd(a.work, 1u);
+        __syncthreads();
+        const uint32_t id = L.region;
+        __syncthreads();
+        if (id >= a.n) break;
+        const sdf_region R = a.in[id];
+        const uint32_t o = R.strand;
+        const uint64_t qlo = ix.off[R.q_seq], qhi = ix.off[R.q_seq + 1];
+        const uint64_t tlo = ix.off[R.t_seq], thi = ix.off[R.t_seq + 1];
+        const bool same = R.q_seq == R.t_seq;
+        uint64_t r[4] = {qlo + R.q_begin, qlo + R.q_end, tlo + R.t_begin, tlo + R.t_end};
+        const uint64_t start[4] = {r[0], r[1], r[2], r[3]};
+        sdf_region res = R;
+        if (r[1] - r[0] > a.max_len || r[3] - r[2] > a.max_len) {
+            if (threadIdx.x == 0) {
+                res.m = res.s = 0;
+                res.stop = STOP_CAP | (STOP_CAP << 8);
+                a.out[id] = res;
+            }
+            continue;
+        }
+        const uint64_t longer = std::max(r[1] - r[0], r[3] - r[2]);
+        // horizons (steps per phase) to gather, and horizons known too short
+        uint64_t hf = a.h0 + 2 * longer, hb = hf, df = 0, db = 0;
+        unsigned long long applied = 0;
+        uint32_t restarts = 0;
+        bool failed = false;
+        for (;;) {  // attempts with growing horizons
+            for (int d = 0; d < 4; d++) r[d] = start[d];
+            // horizons bounded by what each phase could ever take
+            uint64_t lim_f;
+            uint32_t code_f;
+            const Phase pf = phase_of(0, o), pb = phase_of(1, o);
+            phase_limit(r, qlo, qhi, tlo, thi, same, pf, a.max_len, lim_f, code_f);
+            const uint64_t Hf = std::min(hf, lim_f);
+            uint64_t ub_b = std::min(r[0] - qlo, o == 0 ? r[2] - tlo : thi - r[3]);
+            ub_b = std::min(ub_b, a.max_len - longer);
+            const uint64_t Hb = std::min(hb, ub_b);
+            // position ranges [pa, pb] of the six element lists
+            int64_t pa[6], pe[6];
+            pa[0] = (int64_t)r[0]; pe[0] = (int64_t)r[1] - k;
+            pa[1] = (int64_t)r[2]; pe[1] = (int64_t)r[3] - k;
+            pa[2] = (int64_t)r[1] + 1 - k; pe[2] = (int64_t)(r[1] + Hf) - k;
+            if (o == 0) { pa[3] = (int64_t)r[3] + 1 - k; pe[3] = (int64_t)(r[3] + Hf) - k; }
+            else { pa[3] = (int64_t)r[2] - (int64_t)Hf; pe[3] = (int64_t)r[2] - 1; }
+            pa[4] = (int64_t)r[0] - (int64_t)Hb; pe[4] = (int64_t)r[0] - 1;
+            if (o == 0) { pa[5] = (int64_t)r[2] - (int64_t)Hb; pe[5] = (int64_t)r[2] - 1; }
+            else { pa[5] = (int64_t)r[3] + 1 - k; pe[5] = (int64_t)(r[3] + Hb) - k; }
+            if (Hf == 0) { pa[2] = pa[3] = 1; pe[2] = pe[3] = 0; }
+            if (Hb == 0) { pa[4] = pa[5] = 1; pe[4] = pe[5] = 0; }
+            if (threadIdx.x < 12) {
+                const int l = threadIdx.x >> 1;
+                const bool hi_end = threadIdx.x & 1;
+                const int64_t x = hi_end ? pe[l] + 1 : pa[l];
+                const uint64_t v = (pe[l] < pa[l]) ? 0 : lower_pos(ix, (uint64_t)std::max<int64_t>(x, 0));
+                if (hi_end) L.mhi[l] = v; else L.mlo[l] = v;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                uint32_t acc = 0;
+                for (int l = 0; l < 6; l++) {
+                    if (L.mhi[l] < L.mlo[l]) L.mhi[l] = L.mlo[l];
+                    L.base[l] = acc;
+                    const uint64_t c = L.mhi[l] - L.mlo[l];
+                    acc = (uint32_t)std::min<uint64_t>((uint64_t)acc + c, 0xFFFFFFFFull);
+                }
+                L.base[6] = acc;
+                L.nrank = 0;
+                L.flag = 0;
+            }
+            __syncthreads();
+            const uint64_t E = L.base[6];
+            if (E > a.ecap) {
+                // halve the horizons toward what is known to be too short;
+                // give up when neither can move
+                const uint64_t nf = std::max(df + 1, (df + hf) / 2);
+                const uint64_t nb = std::max(db + 1, (db + hb) / 2);
+                if (nf == hf && nb == hb) {
+                    if (threadIdx.x == 0) atomicOr(a.err, (uint32_t)XE_CAP);
+                    failed = true;
+                    break;
+                }
+                hf = nf;
+                hb = nb;
+                continue;
+            }
+            // 1. bucket by the top hash bits into tmp
+            for (uint32_t i = threadIdx.x; i < NB + 1; i += XT) L.bs[i] = 0;
+            __syncthreads();
+            for (int l = 0; l < 6; l++)
+                for (uint64_t i = L.mlo[l] + threadIdx.x; i < L.mhi[l]; i += XT)
+                    atomicAdd(&L.bs[(ix.mhash[i] >> shift) & (nbk - 1)], 1u);
+            __syncthreads();
+            constexpr uint32_t PER = NB / XT;
+            {
+                uint32_t loc = 0;
+                for (uint32_t t = 0; t < PER; t++) loc += L.bs[threadIdx.x * PER + t];
+                uint32_t ex;
+                block_scan(L, loc, ex);
+                for (uint32_t t = 0; t < PER; t++) {
+                    const uint32_t c = L.bs[threadIdx.x * PER + t];
+                    L.bs[threadIdx.x * PER + t] = ex;
+                    ex += c;
+                }
+                if (threadIdx.x == 0) L.bs[NB] = (uint32_t)E;
+                __syncthreads();
+            }
+            {
+                uint32_t *cur = reinterpret_cast<uint32_t *>(L.ck);  // NB cursors
+                for (uint32_t i = threadIdx.x; i < NB; i += XT) cur[i] = L.bs[i];
+                __syncthreads();
+                for (int l = 0; l < 6; l++)
+                    for (uint64_t i = L.mlo[l] + threadIdx.x; i < L.mhi[l]; i += XT) {
+                        const uint32_t h = ix.mhash[i];
+                        const uint32_t eid = L.base[l] + (uint32_t)(i - L.mlo[l]);
+                        tmp[atomicAdd(&cur[(h >> shift) & (nbk - 1)], 1u)] =
+                            ((uint64_t)h << 32) | eid;
+                    }
+                __syncthreads();
+            }
+            // 2. chunks of whole buckets: a bucket opens a chunk when its start
+            // falls in another half-chunk window than the previous bucket's, or
+            // when it or the previous bucket holds more than half a chunk; so a
+            // chunk of several buckets holds fewer than CH keys
+            {
+                uint32_t flags = 0, nf = 0;
+                for (uint32_t t = 0; t < PER; t++) {
+                    const uint32_t bk = threadIdx.x * PER + t;
+                    bool open = false;
+                    if (bk < nbk) {
+                        const uint32_t sz = L.bs[bk + 1] - L.bs[bk];
+                        const uint32_t szp = bk ? L.bs[bk] - L.bs[bk - 1] : 0;
+                        open = bk == 0 || sz > HALF || szp > HALF ||
+                               (L.bs[bk] / HALF) != (L.bs[bk - 1] / HALF);
+                    }
+                    flags |= (open ? 1u : 0u) << t;
+                    nf += open ? 1u : 0u;
+                }
+                uint32_t ex;
+                const uint32_t nch = block_scan(L, nf, ex);
+                for (uint32_t t = 0; t < PER; t++)
+                    if (flags & (1u << t)) L.cl[ex++] = (uint16_t)(threadIdx.x * PER + t);
+                if (threadIdx.x == 0) L.nchunk = nch;
+                __syncthreads();
+            }
+            {
+                const uint32_t nch = L.nchunk;
+                for (uint32_t c = 0; c < nch; c++) {
+                    const uint32_t b0 = L.cl[c];
+                    const uint32_t b1 = c + 1 < nch ? L.cl[c + 1] : nbk;
+                    const uint32_t c0 = L.bs[b0];
+                    const uint32_t c1 = b1 < nbk ? L.bs[b1] : (uint32_t)E;
+                    if (c1 == c0) continue;
+                    if (c1 - c0 <= CH) {
+                        rank_chunk(L, tmp, c0, c1, rank);
+                    } else if (!rank_big(L, tmp, c0, c1, rank)) {
+                        if (threadIdx.x == 0) { atomicOr(a.err, (uint32_t)XE_HASH); L.flag = 1; }
+                        __syncthreads();
+                        break;
+                    }
+                }
+                __syncthreads();
+            }
+            if (L.flag) { failed = true; break; }
+            const uint32_t nr = L.nrank;
+            const uint32_t nw = (nr + 7) / 8;
+            uint32_t *nib = (nw <= a.lds_words) ? L.w : gnib;
+            // 3. the start state
+            for (uint32_t i = threadIdx.x; i < nw; i += XT) nib[i] = 0;
+            __syncthreads();
+            for (int l = 0; l < 2; l++)
+                for (uint64_t i = L.mlo[l] + threadIdx.x; i < L.mhi[l]; i += XT) {
+                    const uint32_t rr = rank[L.base[l] + (uint32_t)(i - L.mlo[l])];
+                    const uint32_t bit = (l == 0 ? C_Q0 : C_T0) << (ix.mflags[i] & 1);
+                    atomicOr(&nib[rr >> 3], bit << ((rr & 7) * 4));
+                }
+            __syncthreads();
+            {
+                const uint32_t seg = (nw + XT - 1) / XT;
+                const uint32_t w0 = std::min(nw, threadIdx.x * seg), w1 = std::min(nw, w0 + seg);
+                uint32_t qc = 0, uc = 0;
+                for (uint32_t i = w0; i < w1; i++) {
+                    qc += __popc(q_mask(nib[i] & 0x33333333u));
+                    uc += __popc(nz_mask(nib[i]));
+                }
+                const uint32_t s = block_sum(L, qc);
+                uint32_t ex;
+                block_scan(L, uc, ex);
+                if (threadIdx.x == 0) { L.v = -1; L.s = s; }
+                __syncthreads();
+                if (s > 0 && ex < s && s <= ex + uc) {
+                    uint32_t need = s - ex;
+                    for (uint32_t i = w0; i < w1; i++) {
+                        uint32_t u = nz_mask(nib[i]);
+                        const uint32_t c = __popc(u);
+                        if (need > c) { need -= c; continue; }
+                        while (--need) u &= u - 1;
+                        L.v = (int32_t)(i * 8 + (__builtin_ctz(u) >> 2));
+                        break;
+                    }
+                }
+                __syncthreads();
+                const int32_t v = L.v;
+                uint32_t mc = 0;
+                for (uint32_t i = w0; i < w1; i++) {
+                    uint32_t sm = shared_mask(nib[i], o);
+                    if ((int32_t)(i * 8) > v) break;
+                    if ((int32_t)(i * 8 + 7) > v) sm &= (v - (int32_t)(i * 8)) == 7 ? 0xFFFFFFFFu
+                                                  : ((1u << (((v - (int32_t)(i * 8)) + 1) * 4)) - 1u);
+                    mc += __popc(sm);
+                }
+                const uint32_t m = block_sum(L, mc);
+                if (threadIdx.x == 0) L.m = m;
+                __syncthreads();
+            }
+            // 4. the phases, on wave 0
+            bool exhausted = false;
+            if (threadIdx.x < 64) {
+                Est e;
+                e.v = L.v; e.s = L.s; e.m = L.m;
+                bool ok = passes(e, a.tau);
+                bool bad = false;
+                unsigned long long app = 0;
+                uint32_t codes[2] = {0, 0};
+                for (int dir = 0; dir < 2 && !exhausted; dir++) {
+                    const Phase p = phase_of(dir, o);
+                    uint64_t lim;
+                    uint32_t lcode;
+                    phase_limit(r, qlo, qhi, tlo, thi, same, p, a.max_len, lim, lcode);
+                    const uint64_t H = dir == 0 ? Hf : Hb;
+                    const uint64_t known = std::min(H, lim);
+                    EvList lq, lt;
+                    const int iq = dir == 0 ? 2 : 4, it = dir == 0 ? 3 : 5;
+                    lq.lo = L.mlo[iq]; lq.hi = L.mhi[iq]; lq.base = L.base[iq]; lq.side = C_Q0;
+                    lt.lo = L.mlo[it]; lt.hi = L.mhi[it]; lt.base = L.base[it]; lt.side = C_T0;
+                    if (dir == 0) {
+                        lq.up = true; lq.ref = start[1];
+                        lt.up = o == 0; lt.ref = o == 0 ? start[3] : start[2];
+                    } else {
+                        lq.up = false; lq.ref = start[0];
+                        lt.up = o == 1; lt.ref = o == 0 ? start[2] : start[3];
+                    }
+                    uint32_t code = 0;
+                    const uint64_t t = run_phase(a, nib, nw, rank, lq, lt, known, lim, lcode, o, e, ok,
+                                                 code, app, bad);
+                    if (code == 0) { exhausted = true; codes[dir] = 0; break; }
+                    codes[dir] = code;
+                    r[0] -= p.ql * t; r[1] += p.qr * t; r[2] -= p.tl * t; r[3] += p.tr * t;
+                }
+                if (threadIdx.x == 0) {
+                    L.flag = (exhausted ? (codes[0] ? 8u : 2u) : 0u) | (bad ? 4u : 0u);
+                    if (!exhausted && !bad) {
+                        res.q_begin = r[0] - qlo; res.q_end = r[1] - qlo;
+                        res.t_begin = r[2] - tlo; res.t_end = r[3] - tlo;
+                        res.m = e.m; res.s = e.s;
+                        res.stop = codes[0] | (codes[1] << 8);
+                        a.out[id] = res;
+                    }
+                    applied += app;
+                }
+            }
+            __syncthreads();
+            const uint32_t fl = L.flag;
+            __syncthreads();
+            if (fl & 4u) {
+                if (threadIdx.x == 0) atomicOr(a.err, (uint32_t)XE_STATE);
+                failed = true;
+                break;
+            }
+            if (!(fl & 10u)) {
+                if (threadIdx.x == 0) atomicAdd(&a.stats[2], (unsigned long long)nr);
+                break;
+            }
+            restarts++;
+            if (fl & 2u) { df = Hf; hf = 4 * std::max(hf, Hf); }  // forward ran out
+            else { db = Hb; hb = 4 * std::max(hb, Hb); }          // backward ran out
+        }
+        if (threadIdx.x == 0) {
+            atomicAdd(&a.stats[0], applied);
+            atomicAdd(&a.stats[1], (unsigned long long)restarts);
+            if (failed) {
+                res.m = res.s = 0;
+                res.stop = 0;
+                a.out[id] = res;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+void launch_extend(const IndexView &ix, const sdf_region *in, uint64_t n, double tau,
+                   uint64_t max_len, sdf_region *out, ExtStats *stats, hipStream_t st) {
+    if (stats) *stats = ExtStats{};
+    if (n == 0) return;
+    int dev = 0, cus = 0;
+    SDF_HIP(hipGetDevice(&dev));
+    SDF_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    // test hooks: SDF_EXT_H0 sets the first horizon, SDF_EXT_LDS_WORDS the
+    // cells kept in LDS (0 keeps L in global memory), SDF_EXT_ECAP the
+    // elements per workgroup
+    uint64_t h0 = 8192, ecap = 1ull << 18;
+    uint32_t ldsw = LDS_WORDS;
+    if (const char *v = std::getenv("SDF_EXT_H0")) h0 = std::strtoull(v, nullptr, 10);
+    if (const char *v = std::getenv("SDF_EXT_LDS_WORDS"))
+        ldsw = std::min<uint32_t>(LDS_WORDS, (uint32_t)std::strtoul(v, nullptr, 10));
+    if (const char *v = std::getenv("SDF_EXT_ECAP"))
+        ecap = std::max<uint64_t>(64, std::strtoull(v, nullptr, 10));
+    // two workgroups fit a CU (LDS); each keeps its own scratch
+    const uint64_t grid = std::min<uint64_t>(n, (uint64_t)std::max(1, cus) * 2);
+    DevBuf<uint64_t> tmp(grid * ecap);
+    DevBuf<uint32_t> rank(grid * ecap), gnib(grid * (ecap / 8 + 1));
+    DevBuf<uint32_t> work(2);
+    DevBuf<unsigned long long> cnt(3);
+    SDF_HIP(hipMemsetAsync(work.p, 0, 8, st));
+    SDF_HIP(hipMemsetAsync(cnt.p, 0, 24, st));
+    ExtArgs a;
+    a.ix = ix;
+    a.in = in;
+    a.n = n;
+    a.out = out;
+    a.tau = tau;
+    a.max_len = max_len;
+    a.h0 = h0;
+    a.work = work.p;
+    a.tmp = tmp.p;
+    a.rank = rank.p;
+    a.gnib = gnib.p;
+    a.ecap = ecap;
+    a.lds_words = ldsw;
+    a.err = work.p + 1;
+    a.stats = cnt.p;
+    k_extend<<<(unsigned)grid, XT, 0, st>>>(a);
+    SDF_HIP(hipGetLastError());
+    uint32_t herr = 0;
+    unsigned long long hc[3] = {0, 0, 0};
+    SDF_HIP(hipMemcpyAsync(&herr, work.p + 1, 4, hipMemcpyDeviceToHost, st));
+    SDF_HIP(hipMemcpyAsync(hc, cnt.p, 24, hipMemcpyDeviceToHost, st));
+    SDF_HIP(hipStreamSynchronize(st));
+    if (herr & XE_CAP)
+        throw Error{SDF_EINTERNAL, "extend: a region needs more minimizers than its scratch holds"};
+    if (herr & XE_HASH)
+        throw Error{SDF_EINTERNAL, "extend: more than 4096 distinct hashes share all cut bits"};
+    if (herr & XE_STATE) throw Error{SDF_EINTERNAL, "extend: inconsistent ordered set"};
+    if (stats) {
+        stats->events = hc[0];
+        stats->restarts = hc[1];
+        stats->ranks = hc[2];
+    }
+}
+
+}  // namespace sdf

@@ -69,6 +69,14 @@ void launch_span_setup(const IndexView &ix, SpanDesc *spans, uint32_t nspans, ui
 void launch_tile_search(const SearchArgs &a, uint32_t grid, hipStream_t st);
 uint32_t tile_core_max();
 
+// Extension of regions (extend.hip): in/out are device arrays of n regions
+// with validated bounds.  Throws on a scratch overflow.
+struct ExtStats {
+    unsigned long long events = 0, restarts = 0, ranks = 0;
+};
+void launch_extend(const IndexView &ix, const sdf_region *in, uint64_t n, double tau,
+                   uint64_t max_len, sdf_region *out, ExtStats *stats, hipStream_t st);
+
 // Chaining (chain.hip): seeds -> sorted candidates; returns the candidate count.
 struct ChainOut {
     DevBuf<sdf_candidate> cands;

@@ -19,22 +19,31 @@ SDF_OK, SDF_EINVAL, SDF_ENOMEM, SDF_EDEVICE, SDF_ERANGE, SDF_EBUSY, SDF_EINTERNA
     0, -1, -2, -3, -4, -5, -6)
 SDF_TIMING = 1
 SDF_SEED_ESTIMATE = 2
+SDF_EXTEND = 4
+STOP_BOUND, STOP_CAP, STOP_OVERLAP, STOP_ESTIMATE = 1, 2, 3, 4
 
 CANDIDATE_DTYPE = np.dtype([("query_id", "<u4"), ("strand", "<u4"), ("q_seq", "<u4"),
                             ("t_seq", "<u4"), ("q_begin", "<u8"), ("q_end", "<u8"),
                             ("t_begin", "<u8"), ("t_end", "<u8"), ("n_seeds", "<u4"),
                             ("max_shared", "<u4")])
+# sdf_region: a region pair and, after an extension, its final estimate
+# (m / s) and stop codes (forward | backward << 8).
+REGION_DTYPE = np.dtype([("strand", "<u4"), ("q_seq", "<u4"), ("t_seq", "<u4"), ("stop", "<u4"),
+                         ("q_begin", "<u8"), ("q_end", "<u8"), ("t_begin", "<u8"),
+                         ("t_end", "<u8"), ("m", "<u4"), ("s", "<u4")])
 SEED_DTYPE = np.dtype([("query_id", "<u4"), ("i", "<u4"), ("j", "<u4"), ("strand", "<u4"),
                        ("shared", "<u4"), ("sketch", "<u4")])
 EXPORTS = ["sdf_last_error", "sdf_index_build", "sdf_index_info", "sdf_index_hit_density",
            "sdf_index_minimizers",
            "sdf_index_entries", "sdf_index_packed", "sdf_index_free", "sdf_search",
            "sdf_search_batch", "sdf_result_count", "sdf_result_copy", "sdf_result_seed_count",
-           "sdf_result_seeds", "sdf_result_timing", "sdf_result_stats", "sdf_result_free"]
+           "sdf_result_seeds", "sdf_result_timing", "sdf_result_stats", "sdf_result_free",
+           "sdf_extend", "sdf_result_regions"]
 
 
-def _flags(timing: bool, estimate: bool) -> int:
-    return (SDF_TIMING if timing else 0) | (SDF_SEED_ESTIMATE if estimate else 0)
+def _flags(timing: bool, estimate: bool, extend: bool = False) -> int:
+    return ((SDF_TIMING if timing else 0) | (SDF_SEED_ESTIMATE if estimate else 0) |
+            (SDF_EXTEND if extend else 0))
 
 
 class SdfError(RuntimeError):
@@ -50,6 +59,10 @@ class _IndexParams(ctypes.Structure):
 class _SearchParams(ctypes.Structure):
     _fields_ = [("max_error", ctypes.c_double), ("min_len", ctypes.c_uint32),
                 ("flags", ctypes.c_uint32)]
+
+
+class _ExtendParams(ctypes.Structure):
+    _fields_ = [("max_error", ctypes.c_double), ("max_len", ctypes.c_uint64)]
 
 
 class _Span(ctypes.Structure):
@@ -115,6 +128,11 @@ def lib() -> ctypes.CDLL:
         L.sdf_result_stats.argtypes = [vp, P(u64), u32]
         L.sdf_result_free.restype = None
         L.sdf_result_free.argtypes = [vp]
+        L.sdf_extend.restype = st
+        L.sdf_extend.argtypes = [vp, vp, u64, P(_ExtendParams), vp, vp]
+        L.sdf_result_regions.restype = st
+        L.sdf_result_regions.argtypes = [vp, vp, u64, P(u64)]
+        assert REGION_DTYPE.itemsize == 56
         _lib = L
     return _lib
 
@@ -167,9 +185,20 @@ class Result:
                                       ctypes.byref(w)))
         return out
 
+    def regions(self) -> np.ndarray:
+        """Extended region of every candidate (search run with extend=True)."""
+        n = ctypes.c_uint64()
+        _check(lib().sdf_result_count(self._h, ctypes.byref(n)))
+        out = np.empty(n.value, REGION_DTYPE)
+        w = ctypes.c_uint64()
+        _check(lib().sdf_result_regions(self._h, out.ctypes.data_as(ctypes.c_void_p), n.value,
+                                        ctypes.byref(w)))
+        return out
+
     def timing(self) -> np.ndarray:
-        ms = (ctypes.c_float * 5)()
-        _check(lib().sdf_result_timing(self._h, ms, 5))
+        """[setup, tile kernel, chaining, output sort, whole search, extension] ms."""
+        ms = (ctypes.c_float * 6)()
+        _check(lib().sdf_result_timing(self._h, ms, 6))
         return np.array(ms[:], dtype=np.float64)
 
     def stats(self) -> dict:
@@ -254,10 +283,29 @@ class Index:
                                       gp.ctypes.data_as(ctypes.c_void_p)))
         return pk, mk, gp
 
+    def extend(self, regions, max_error: float = 0.25, max_len: int = 1000000,
+               stream=None) -> np.ndarray:
+        """Extends regions (a REGION_DTYPE array, or rows (strand, q_seq,
+        q_begin, q_end, t_seq, t_begin, t_end)) by ``sdf_extend``."""
+        if isinstance(regions, np.ndarray) and regions.dtype == REGION_DTYPE:
+            inp = np.ascontiguousarray(regions)
+        else:
+            rows = list(regions)
+            inp = np.zeros(len(rows), REGION_DTYPE)
+            for u, (o, qs, qb, qe, ts, tb, te) in enumerate(rows):
+                inp[u] = (o, qs, ts, 0, qb, qe, tb, te, 0, 0)
+        out = np.empty(len(inp), REGION_DTYPE)
+        p = _ExtendParams(max_error, max_len)
+        _check(lib().sdf_extend(self._h, inp.ctypes.data_as(ctypes.c_void_p), len(inp),
+                                ctypes.byref(p), _stream_ptr(stream),
+                                out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
     def search(self, span: Tuple[int, int, int], max_error: float = 0.25, min_len: int = 1000,
-               timing: bool = False, stream=None, estimate: bool = False) -> Result:
+               timing: bool = False, stream=None, estimate: bool = False,
+               extend: bool = False) -> Result:
         sp = _Span(span[0], 0, span[1], span[2])
-        p = _SearchParams(max_error, min_len, _flags(timing, estimate))
+        p = _SearchParams(max_error, min_len, _flags(timing, estimate, extend))
         h = ctypes.c_void_p()
         _check(lib().sdf_search(self._h, ctypes.byref(sp), ctypes.byref(p), _stream_ptr(stream),
                                 ctypes.byref(h)))
@@ -265,10 +313,10 @@ class Index:
 
     def search_batch(self, spans: Iterable[Tuple[int, int, int]], max_error: float = 0.25,
                      min_len: int = 1000, timing: bool = False, stream=None,
-                     estimate: bool = False) -> Result:
+                     estimate: bool = False, extend: bool = False) -> Result:
         spans = list(spans)
         arr = (_Span * max(1, len(spans)))(*[_Span(s, 0, b, e) for (s, b, e) in spans])
-        p = _SearchParams(max_error, min_len, _flags(timing, estimate))
+        p = _SearchParams(max_error, min_len, _flags(timing, estimate, extend))
         h = ctypes.c_void_p()
         _check(lib().sdf_search_batch(self._h, ctypes.cast(arr, ctypes.c_void_p), len(spans),
                                       ctypes.byref(p), _stream_ptr(stream), ctypes.byref(h)))

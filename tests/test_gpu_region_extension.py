@@ -1,0 +1,249 @@
+"""Parity of the extension of regions (Section 3.2) through the C ABI with
+the CPU oracle.
+
+Start regions are the oracle's own candidates, or boxes drawn from a seeded
+generator; every output field (bounds, m, s, stop codes) is an integer and
+must match exactly.
+"""
+import numpy as np
+import pytest
+
+from paper_1807_00205_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+REG_F = ["strand", "q_seq", "t_seq", "q_begin", "q_end", "t_begin", "t_end", "m", "s", "stop"]
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_1807_00205_amd import sdf
+    sdf.lib()
+    return sdf
+
+
+def _boxes_from_cands(S, cands):
+    out = np.zeros(len(cands), S.REGION_DTYPE)
+    for f in ("strand", "q_seq", "t_seq", "q_begin", "q_end", "t_begin", "t_end"):
+        out[f] = cands[f]
+    return out
+
+
+def _random_boxes(S, rng, seqs, n, lo_len=50, hi_len=800):
+    out = np.zeros(n, S.REGION_DTYPE)
+    lens = [len(s) for s in seqs]
+    big = [i for i, L in enumerate(lens) if L > lo_len + 10]
+    for u in range(n):
+        row = []
+        for _side in range(2):
+            s = int(rng.choice(big))
+            a = int(rng.integers(0, lens[s] - lo_len))
+            e = int(rng.integers(a + lo_len, min(lens[s], a + hi_len) + 1))
+            row.append((s, a, e))
+        (qs, qb, qe), (ts, tb, te) = row
+        out[u] = (int(rng.integers(0, 2)), qs, ts, 0, qb, qe, tb, te, 0, 0)
+    return out
+
+
+def _oracle_extend(orc, off, boxes, tau, max_len=1000000):
+    """The oracle's extension of per-sequence boxes, as REGION_DTYPE."""
+    qo = off[boxes["q_seq"]].astype(np.uint64)
+    to = off[boxes["t_seq"]].astype(np.uint64)
+    rows = np.stack([boxes["q_begin"] + qo, boxes["q_end"] + qo, boxes["t_begin"] + to,
+                     boxes["t_end"] + to, boxes["strand"].astype(np.uint64)], axis=1)
+    ext = orc.extend(rows, tau, max_len)
+    out = boxes.copy()
+    out["q_begin"] = ext["q_begin"] - qo
+    out["q_end"] = ext["q_end"] - qo
+    out["t_begin"] = ext["t_begin"] - to
+    out["t_end"] = ext["t_end"] - to
+    out["m"] = ext["m"]
+    out["s"] = ext["s"]
+    out["stop"] = ext["stop"]
+    return out
+
+
+def _same(a, b, what=""):
+    assert len(a) == len(b), "%s: %d vs %d regions" % (what, len(a), len(b))
+    for f in REG_F:
+        x, y = np.asarray(a[f]).astype(np.uint64), np.asarray(b[f]).astype(np.uint64)
+        if not np.array_equal(x, y):
+            bad = np.nonzero(x != y)[0][:5]
+            raise AssertionError("%s: field %s differs at %s: gpu %s oracle %s\n%s\n%s" %
+                                 (what, f, bad, x[bad], y[bad], a[bad], b[bad]))
+
+
+SMALL = [
+    dict(seed=1, length=3000, n_sd=2, n_seqs=1, lower_frac=0.0, n_gaps=0),
+    dict(seed=2, length=2500, n_sd=2, n_seqs=2, lower_frac=0.25, n_gaps=1),
+    dict(seed=3, length=2000, n_sd=3, n_seqs=3, lower_frac=0.1, n_gaps=2),
+    dict(seed=4, length=4000, n_sd=2, n_seqs=1, lower_frac=0.4, n_gaps=1),
+    None,  # tandem arrays
+]
+
+
+def _small_genome(case):
+    if case is None:
+        return synth.tandem_case(91, length=3000, n_arrays=5, copies_hi=20, n_seqs=2)
+    c = dict(case)
+    seed = c.pop("seed")
+    return synth.small_case(60 + seed, sd_lo=300, sd_hi=600, gap_len=25, rate_hi=0.06, **c)
+
+
+@pytest.mark.parametrize("case", SMALL, ids=lambda c: "seed%d" % c["seed"] if c else "tandem")
+@pytest.mark.parametrize("max_error,min_len,k,w", [(0.25, 200, 12, 16), (0.3, 120, 9, 5),
+                                                   (0.1, 300, 11, 8)])
+def test_extend_small(S, oracle_lib, case, max_error, min_len, k, w):
+    """Extension of the oracle's candidates and of random boxes (both
+    strands, one or several sequences, masking, gaps, tandem repeats), with
+    the paper's 1 Mbp cap and with a 900 bp cap: exact regions, m, s and
+    stop codes."""
+    g = _small_genome(case)
+    b, off = g.concat()
+    orc = oracle_lib.OracleIndex(b, off, k, w)
+    tau, _, _ = oracle_lib.params(max_error, min_len, k)
+    _, oc = orc.search(g.spans, max_error, min_len)
+    boxes = np.concatenate([_boxes_from_cands(S, oc),
+                            _random_boxes(S, np.random.default_rng(5 + k), g.seqs, 12)])
+    ix = S.Index(g.seqs, k, w)
+    for cap in (1000000, 900):
+        got = ix.extend(boxes, max_error, cap)
+        _same(got, _oracle_extend(orc, off, boxes, tau, cap), "cap %d" % cap)
+
+
+@pytest.mark.parametrize("hook", [{"SDF_EXT_H0": "1"}, {"SDF_EXT_LDS_WORDS": "0"},
+                                  {"SDF_EXT_ECAP": "3000"},
+                                  {"SDF_EXT_H0": "0", "SDF_EXT_LDS_WORDS": "16"}],
+                         ids=["restarts", "global-cells", "small-scratch", "mixed"])
+def test_extend_general_paths(S, oracle_lib, monkeypatch, hook):
+    """The paths that large or long-running regions take, forced on small
+    inputs: horizons that run out and restart (4x), the ordered set kept in
+    global memory instead of LDS, and horizons shrunk to fit the scratch."""
+    for kv in hook.items():
+        monkeypatch.setenv(*kv)
+    g = synth.small_case(81, length=8000, n_sd=4, sd_lo=800, sd_hi=2000, n_seqs=2,
+                         lower_frac=0.2, n_gaps=1, gap_len=30, rate_hi=0.05)
+    b, off = g.concat()
+    orc = oracle_lib.OracleIndex(b, off, 12, 16)
+    tau, _, _ = oracle_lib.params(0.25, 500, 12)
+    _, oc = orc.search(g.spans, 0.25, 500)
+    assert len(oc) > 4
+    boxes = np.concatenate([_boxes_from_cands(S, oc),
+                            _random_boxes(S, np.random.default_rng(9), g.seqs, 10)])
+    ix = S.Index(g.seqs, 12, 16)
+    _same(ix.extend(boxes, 0.25), _oracle_extend(orc, off, boxes, tau), str(hook))
+
+
+def test_extend_scratch_overflow_is_an_error(S, monkeypatch):
+    """A region whose start windows alone exceed the per-workgroup scratch
+    is reported as SDF_EINTERNAL, and the index stays usable."""
+    rng = synth.rng_for(5)
+    A = synth.random_bases(rng, 8000)
+    ix = S.Index([A, A.copy()], 12, 16)
+    box = [(0, 0, 1000, 5000, 1, 1000, 5000)]
+    monkeypatch.setenv("SDF_EXT_ECAP", "200")
+    with pytest.raises(S.SdfError) as e:
+        ix.extend(box, 0.25)
+    assert e.value.code == S.SDF_EINTERNAL
+    monkeypatch.delenv("SDF_EXT_ECAP")
+    r = ix.extend(box, 0.25)
+    assert (int(r["q_begin"][0]), int(r["q_end"][0])) == (0, 8000)
+
+
+def test_extend_closed_forms(S, oracle_lib):
+    """Closed forms: an exact copy on another sequence extends to both whole
+    sequences on either strand (m = s); the cap stops at max_len; on one
+    sequence two copies separated by 300 bp grow until they touch; unrelated
+    windows do not grow; a start longer than the cap is returned as it is."""
+    rng = synth.rng_for(123)
+    A = synth.random_bases(rng, 6000)
+    L = len(A)
+    ix = S.Index([A, A.copy()], 12, 16)
+    r = ix.extend([(0, 0, 2000, 2750, 1, 2000, 2750)], 0.25)[0]
+    assert (r["q_begin"], r["q_end"], r["t_begin"], r["t_end"]) == (0, L, 0, L)
+    assert r["m"] == r["s"] and r["stop"] == S.STOP_BOUND | S.STOP_BOUND << 8
+    r = ix.extend([(0, 0, 2000, 2750, 1, 2000, 2750)], 0.25, 1250)[0]
+    assert (r["q_begin"], r["q_end"], r["t_begin"], r["t_end"]) == (2000, 3250, 2000, 3250)
+    assert r["stop"] == S.STOP_CAP | S.STOP_CAP << 8
+    ixr = S.Index([A, synth.revcomp(A)], 12, 16)
+    r = ixr.extend([(1, 0, 2000, 2750, 1, L - 2750, L - 2000)], 0.25)[0]
+    assert (r["q_begin"], r["q_end"], r["t_begin"], r["t_end"]) == (0, L, 0, L)
+    X = synth.random_bases(rng, 5000)
+    Sq = np.concatenate([X, synth.random_bases(rng, 300), X, synth.random_bases(rng, 2000)])
+    ix1 = S.Index([Sq], 12, 16)
+    r = ix1.extend([(0, 0, 1000, 2000, 0, 6300, 7300)], 0.25)[0]
+    assert (r["q_begin"], r["q_end"], r["t_begin"], r["t_end"]) == (1000, 6300, 6300, 11600)
+    assert r["stop"] == S.STOP_OVERLAP | S.STOP_OVERLAP << 8
+    B = synth.random_bases(rng, 6000)
+    ixu = S.Index([A, B], 12, 16)
+    r = ixu.extend([(0, 0, 2000, 2750, 1, 2000, 2750)], 0.25)[0]
+    assert (r["q_begin"], r["q_end"], r["t_begin"], r["t_end"]) == (2000, 2750, 2000, 2750)
+    assert r["stop"] == S.STOP_ESTIMATE | S.STOP_ESTIMATE << 8
+    r = ix.extend([(0, 0, 0, 3000, 1, 0, 3000)], 0.25, 2000)[0]
+    assert (r["q_begin"], r["q_end"], r["m"], r["s"]) == (0, 3000, 0, 0)
+    assert r["stop"] == S.STOP_CAP | S.STOP_CAP << 8
+
+
+def test_extend_errors(S):
+    """Invalid regions and parameters are rejected before any device work."""
+    A = synth.random_bases(synth.rng_for(8), 3000)
+    ix = S.Index([A, A.copy()], 12, 16)
+    ok = (0, 0, 100, 900, 1, 100, 900)
+    bad = [((2,) + ok[1:], S.SDF_EINVAL), ((0, 2) + ok[2:], S.SDF_ERANGE),
+           ((0, 0, 100, 3001, 1, 100, 900), S.SDF_ERANGE),
+           ((0, 0, 900, 100, 1, 100, 900), S.SDF_ERANGE),
+           ((0, 0, 100, 111, 1, 100, 900), S.SDF_EINVAL)]
+    for row, code in bad:
+        with pytest.raises(S.SdfError) as e:
+            ix.extend([ok, row], 0.25)
+        assert e.value.code == code, row
+    for p in ((0.0, 1000000), (1.0, 1000000), (0.25, 11)):
+        with pytest.raises(S.SdfError) as e:
+            ix.extend([ok], *p)
+        assert e.value.code == S.SDF_EINVAL
+    assert len(ix.extend(np.zeros(0, S.REGION_DTYPE), 0.25)) == 0
+    r = ix.search((0, 0, 3000), 0.25, 1000)
+    with pytest.raises(S.SdfError):
+        r.regions()
+
+
+def test_search_extend_config1(S, oracle_lib):
+    """The 1 Mbp workload searched with SDF_EXTEND: candidates as without the
+    flag, and every candidate's region equal to the oracle's extension of the
+    oracle's candidate."""
+    g = synth.config1()
+    b, off = g.concat()
+    orc = oracle_lib.OracleIndex(b, off, 12, 16)
+    tau, _, _ = oracle_lib.params(0.25, 1000, 12)
+    _, oc = orc.search(g.spans, 0.25, 1000)
+    ix = S.Index(g.seqs, 12, 16)
+    r = ix.search(g.spans[0], 0.25, 1000, extend=True)
+    gc = r.candidates()
+    for f in ("query_id", "strand", "q_seq", "t_seq", "q_begin", "q_end", "t_begin", "t_end",
+              "n_seeds", "max_shared"):
+        assert np.array_equal(gc[f], oc[f]), f
+    _same(r.regions(), _oracle_extend(orc, off, _boxes_from_cands(S, oc), tau), "config1")
+
+
+def test_search_extend_config2_sampled(S, oracle_lib):
+    """The 50 Mbp chromosome-shaped workload searched with SDF_EXTEND, in the
+    launch the benchmark times: the candidates equal the oracle's, and 200
+    seeded random candidates' regions (some grow past 200 kbp) equal the
+    oracle's extensions; every region contains its candidate and respects
+    the 1 Mbp cap."""
+    g = synth.config2()
+    b, off = g.concat()
+    orc = oracle_lib.OracleIndex(b, off, 12, 16)
+    tau, _, _ = oracle_lib.params(0.25, 1000, 12)
+    _, oc = orc.search(g.spans, 0.25, 1000)
+    ix = S.Index(g.seqs, 12, 16)
+    r = ix.search(g.spans[0], 0.25, 1000, extend=True)
+    gc = r.candidates()
+    assert np.array_equal(gc["q_begin"], oc["q_begin"]) and np.array_equal(gc["t_end"], oc["t_end"])
+    reg = r.regions()
+    assert np.all(reg["q_begin"] <= gc["q_begin"]) and np.all(reg["q_end"] >= gc["q_end"])
+    assert np.all(reg["t_begin"] <= gc["t_begin"]) and np.all(reg["t_end"] >= gc["t_end"])
+    assert np.all(reg["q_end"] - reg["q_begin"] <= 1000000)
+    sel = np.sort(np.random.default_rng(1).choice(len(oc), 200, replace=False))
+    boxes = _boxes_from_cands(S, oc[sel])
+    _same(reg[sel], _oracle_extend(orc, off, boxes, tau), "config2 sample")

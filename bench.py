@@ -69,7 +69,7 @@ def measured_traffic(workload_name):
     return int(tr["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(g, sample_mbp, max_error, min_len):
+def cpu_baseline(g, sample_mbp, max_error, min_len, keep=None):
     import numpy as np
     import oracle
     b, off = g.concat()
@@ -81,8 +81,10 @@ def cpu_baseline(g, sample_mbp, max_error, min_len):
     span_len = min(L, int(sample_mbp * 1e6))
     a = (L - span_len) // 2
     t = time.time()
-    orc.search([(0, a, a + span_len)], max_error, min_len, threads)
+    _, cands = orc.search([(0, a, a + span_len)], max_error, min_len, threads)
     dt = time.time() - t
+    if keep is not None:  # the oracle's own candidates, for the extension baseline
+        keep.update(orc=orc, off=off, cands=cands, threads=threads)
     return {"value": round(span_len / dt / 1e6, 4), "unit": "Mbp/s", "cores": threads,
             "kind": "oracle",
             "sample": "span [%d, %d) of the same sequence (%.1f Mbp), search only; oracle "
@@ -229,6 +231,73 @@ def estimate_mode(ix, span, max_error, min_len, qbases, steps=3):
             "seeds": nseed, "candidates": ncand}
 
 
+def extend_mode(ix, span, max_error, min_len, steps=3, cpu=None, cpu_sample=200):
+    """The same search with every candidate extended to a potential
+    duplication region (Section 3.2, SDF_EXTEND): wall time per search, the
+    extension's GPU time, regions per second, how far regions grew, and the
+    oracle's extension rate on a seeded sample of its own candidates."""
+    import numpy as np
+    import torch
+    r = ix.search(span, max_error, min_len, timing=True, extend=True)
+    cands = r.candidates()
+    reg = r.regions()
+    st = r.stats(extension=True)
+    r.close()
+    torch.cuda.synchronize()
+    ts, te, tk = [], [], []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        r = ix.search(span, max_error, min_len, timing=True, extend=True)
+        r.regions()
+        ts.append(time.perf_counter() - t0)
+        tm = r.timing()
+        te.append(float(tm[5]))
+        tk.append(float(tm[1]))
+        r.close()
+    ext_ms = float(np.median(te))
+    before = (cands["q_end"] - cands["q_begin"]).astype(np.int64)
+    after = (reg["q_end"] - reg["q_begin"]).astype(np.int64)
+    stops = {}
+    for c in (reg["stop"] & 255).tolist() + (reg["stop"] >> 8).tolist():
+        name = {1: "sequence_end", 2: "length_cap", 3: "overlap", 4: "estimate"}.get(c, str(c))
+        stops[name] = stops.get(name, 0) + 1
+    out = {"path": "plain single-span search, every candidate extended (SDF_EXTEND, 1 Mbp cap)",
+           "ms_per_search": round(float(np.median(ts)) * 1e3, 3),
+           "tile_kernel_ms": round(float(np.median(tk)), 3),
+           "extension_ms": round(ext_ms, 3),
+           "regions": len(reg),
+           "regions_per_s": round(len(reg) / (ext_ms * 1e-3), 1) if ext_ms > 0 else None,
+           "insertions": st["ext_insertions"], "continued_attempts": st["ext_continued"],
+           "ranked_hashes": st["ext_ranks"],
+           "workgroup_ms": {"gather_and_rank": round(st["ext_rank_us"] / 1e3, 1),
+                            "phases": round(st["ext_phase_us"] / 1e3, 1),
+                            "slowest_region": round(st["ext_slowest_region_us"] / 1e3, 2)},
+           "insertions_per_s": round(st["ext_insertions"] / (ext_ms * 1e-3), 1) if ext_ms > 0 else None,
+           "region_len_median": [int(np.median(before)), int(np.median(after))],
+           "region_len_max": [int(before.max()), int(after.max())] if len(reg) else [0, 0],
+           "phase_stops": stops}
+    if cpu:
+        rng = np.random.default_rng(1)
+        oc, off = cpu["cands"], cpu["off"]
+        sel = np.sort(rng.choice(len(oc), min(cpu_sample, len(oc)), replace=False))
+        c = oc[sel]
+        qo = off[c["q_seq"]].astype(np.uint64)
+        to = off[c["t_seq"]].astype(np.uint64)
+        rows = np.stack([c["q_begin"] + qo, c["q_end"] + qo, c["t_begin"] + to, c["t_end"] + to,
+                         c["strand"].astype(np.uint64)], axis=1)
+        import oracle
+        tau, _, _ = oracle.params(max_error, min_len, 12)
+        t = time.time()
+        cpu["orc"].extend(rows, tau, 1000000, cpu["threads"])
+        dt = time.time() - t
+        out["cpu_baseline"] = {"value": round(len(sel) / dt, 2), "unit": "regions/s",
+                               "cores": cpu["threads"], "kind": "oracle",
+                               "sample": "%d seeded random candidates of the oracle's search "
+                                         "of the CPU-baseline span, extended" % len(sel),
+                               "seconds": round(dt, 3)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -242,6 +311,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip batched vs plain")
     ap.add_argument("--no-estimate", action="store_true",
                     help="skip the search with seeds chosen by the winnowed MinHash estimate")
+    ap.add_argument("--no-extend", action="store_true",
+                    help="skip the search with every candidate extended (SDF_EXTEND)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep")
     ap.add_argument("--serve-rates", default="10,100,1000,4000,8000")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
@@ -339,9 +410,16 @@ def main():
     if not args.no_estimate:
         log("seeds by the winnowed MinHash estimate")
         out["estimate"] = estimate_mode(ix, span, args.max_error, args.min_len, qbases)
+    keep = {}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(g, args.cpu_sample_mbp, args.max_error, args.min_len)
+        out["cpu_baseline"] = cpu_baseline(g, args.cpu_sample_mbp, args.max_error, args.min_len,
+                                           keep)
+    if not args.no_extend:
+        log("extension of every candidate (Section 3.2)")
+        out["extend"] = extend_mode(ix, span, args.max_error, args.min_len,
+                                    cpu=keep if keep else None)
+    keep.clear()
     ix.close()
     if not args.no_batch or not args.no_serve:
         log("batched vs plain (250 Mbp, 4,096 spans)")

@@ -225,8 +225,8 @@ typedef struct {
  * Results go to `out` (host array of n, may equal `in`), in input order.
  * Errors: SDF_EINVAL for NULL arguments, strand > 1, a side shorter than k
  * or max_len < k; SDF_ERANGE for a sequence id or bound outside the index;
- * SDF_EINTERNAL when a region needs more scratch than the library holds per
- * workgroup (about 500,000 minimizers in its windows and horizons). */
+ * SDF_EINTERNAL when a region's start windows alone hold more minimizers than
+ * the scratch of one workgroup (262,144); longer horizons are cut to fit. */
 sdf_status sdf_extend(sdf_index ix, const sdf_region *in, uint64_t n,
                       const sdf_extend_params *p, void *hip_stream, sdf_region *out);
 
@@ -252,14 +252,18 @@ sdf_status sdf_result_seeds(sdf_result r, sdf_seed *dst, uint64_t cap, uint64_t 
 
 /* GPU time in ms of each stage when the search ran with SDF_TIMING:
  * [0] setup, [1] the tile search kernel alone (last launch),
- * [2] chaining, [3] output sort, [4] whole search.  Also returns the number
- * of tile-kernel launches measured in [1] (1 per search). */
+ * [2] chaining, [3] output sort, [4] whole search, [5] extension (with
+ * SDF_EXTEND). */
 sdf_status sdf_result_timing(sdf_result r, float *ms, uint32_t n_ms);
 
 /* Work counters of the search: [0] query windows, [1] hits gathered
  * (both passes count once), [2] hits kept by the prefilter, [3] tiles,
  * [4] target partitions, [5] seeds, [6] candidate target starts evaluated,
- * [7] 64-hit words scanned by the per-window sweeps. */
+ * [7] 64-hit words scanned by the per-window sweeps; with SDF_EXTEND also
+ * [8] minimizers inserted by the extension, [9] attempts that continued a
+ * phase past its gathered horizon, [10] distinct hashes ranked, [11] and
+ * [12] workgroup microseconds spent gathering and ranking, and in the
+ * phases, [13] microseconds of the slowest region. */
 sdf_status sdf_result_stats(sdf_result r, uint64_t *v, uint32_t n_v);
 
 void sdf_result_free(sdf_result r);

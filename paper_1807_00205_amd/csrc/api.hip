@@ -30,7 +30,7 @@ struct sdf_result_s {
     bool have_regions = false;
     DevBuf<sdf_region> regions;  // one per candidate with SDF_EXTEND
     ExtStats ext;
-    uint64_t stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint64_t stats[14] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -331,6 +331,12 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
                           &res->ext, st);
         }
         res->have_regions = true;
+        res->stats[8] = res->ext.events;
+        res->stats[9] = res->ext.restarts;
+        res->stats[10] = res->ext.ranks;
+        res->stats[11] = res->ext.rank_us;
+        res->stats[12] = res->ext.loop_us;
+        res->stats[13] = res->ext.slowest_us;
     }
     tm.mark();
     SDF_HIP(hipStreamSynchronize(st));
@@ -595,7 +601,7 @@ sdf_status sdf_extend(sdf_index ix, const sdf_region *in, uint64_t n, const sdf_
 sdf_status sdf_result_stats(sdf_result r, uint64_t *v, uint32_t n_v) {
     return guarded([&] {
         if (!r || (n_v && !v)) throw Error{SDF_EINVAL, "NULL argument"};
-        for (uint32_t t = 0; t < n_v && t < 8; t++) v[t] = r->stats[t];
+        for (uint32_t t = 0; t < n_v && t < 14; t++) v[t] = r->stats[t];
     });
 }
 

@@ -27,8 +27,11 @@
 //     its successor or predecessor), and checks m >= ceil(tau s) after each
 //     step; a refused step is undone.  Steps at which no minimizer enters
 //     keep the previous state and its verdict.
-// A phase that passes its horizon without stopping restarts the region with
-// a four times larger one.
+// The horizon of one attempt is max(h0, longer side / 4) steps per phase.  A
+// phase that runs through it stops at its last step; the next attempt
+// gathers and ranks again around the region reached and continues the same
+// phase from there (the state is a function of the region, so nothing is
+// repeated).
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -57,15 +60,17 @@ struct ExtArgs {
     sdf_region *out;
     double tau;
     uint64_t max_len;
-    uint64_t h0;            // first horizon: h0 + 2 * longer side (steps per phase)
+    uint64_t h0;            // horizon per attempt: max(h0, longer side / 4) steps
     uint32_t *work;         // region counter
     uint64_t *tmp;          // per workgroup: ecap keys
     uint32_t *rank;         // per workgroup: ecap
     uint32_t *gnib;         // per workgroup: ecap / 8 + 1
     uint64_t ecap;
     uint32_t lds_words;     // cells kept in LDS up to 8 * lds_words ranks
+    uint32_t batch_min;     // fewest insertions applied as one batch (0: never)
     uint32_t *err;
-    unsigned long long *stats;  // [0] events applied, [1] restarts, [2] ranks
+    unsigned long long *stats;  // [0] insertions, [1] continued attempts, [2] ranks,
+                                // [3] ranking ticks, [4] event-loop ticks, [5] slowest region
 };
 
 struct Shared {
@@ -82,6 +87,8 @@ struct Shared {
     uint32_t base[7];
     uint32_t region;
     uint32_t nrank, nchunk, cnt;
+    uint64_t rr[4];
+    uint32_t codes[2];
     int32_t v;
     uint32_t s, m;
     uint32_t flag;
@@ -188,42 +195,73 @@ __device__ __forceinline__ uint32_t cell_at(const uint32_t *nib, int32_t r) {
     return (nib[r >> 3] >> ((r & 7) * 4)) & 15u;
 }
 
-// Smallest rank > v holding an element (one exists by construction).
-__device__ int32_t succ_rank(const uint32_t *nib, int32_t v, uint32_t nw) {
+// Smallest rank > v holding an element (one exists by construction), and
+// its cell; the wave probes 64 cell words per step.
+__device__ __forceinline__ int32_t succ_rank(const uint32_t *nib, int32_t v, uint32_t nw,
+                                             uint32_t &cell) {
     const int32_t r = v + 1;
     if ((uint32_t)r >= nw * 8) return -2;
-    uint32_t w = (uint32_t)r >> 3;
-    uint32_t u = nz_mask(nib[w] & (0xFFFFFFFFu << ((r & 7) * 4)));
-    while (u == 0 && ++w < nw) u = nz_mask(nib[w]);
-    return u ? (int32_t)(w * 8 + (__builtin_ctz(u) >> 2)) : -2;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t w0 = (uint32_t)r >> 3;
+    const uint32_t first_mask = 0xFFFFFFFFu << ((r & 7) * 4);
+    for (uint32_t base = w0; base < nw; base += 64) {
+        const uint32_t w = base + lane;
+        uint32_t word = w < nw ? nib[w] : 0u;
+        if (w == w0) word &= first_mask;
+        const uint32_t u = nz_mask(word);
+        const uint64_t hit = __ballot(u != 0);
+        if (hit) {
+            const uint32_t l = (uint32_t)__builtin_ctzll(hit);
+            const uint32_t ul = __builtin_amdgcn_readlane(u, l);
+            const uint32_t wl = __builtin_amdgcn_readlane(word, l);
+            const uint32_t nib_i = (uint32_t)__builtin_ctz(ul) >> 2;
+            cell = (wl >> (nib_i * 4)) & 15u;
+            return (int32_t)((base + l) * 8 + nib_i);
+        }
+    }
+    return -2;
 }
 
-// Largest rank < v holding an element (one exists by construction).
-__device__ int32_t pred_rank(const uint32_t *nib, int32_t v) {
+// Largest rank < v holding an element (one exists by construction), and its
+// cell; the wave probes 64 cell words per step, downwards.
+__device__ __forceinline__ int32_t pred_rank(const uint32_t *nib, int32_t v, uint32_t &cell) {
     const int32_t r = v - 1;
     if (r < 0) return -2;
-    int32_t w = r >> 3;
-    const uint32_t keep = (r & 7) == 7 ? 0xFFFFFFFFu : ((1u << (((r & 7) + 1) * 4)) - 1u);
-    uint32_t u = nz_mask(nib[w] & keep);
-    while (u == 0 && --w >= 0) u = nz_mask(nib[w]);
-    return u ? (int32_t)(w * 8 + ((31 - __builtin_clz(u)) >> 2)) : -2;
+    const uint32_t lane = threadIdx.x & 63;
+    const int32_t w0 = r >> 3;
+    const uint32_t first_mask = (r & 7) == 7 ? 0xFFFFFFFFu : ((1u << (((r & 7) + 1) * 4)) - 1u);
+    for (int32_t top = w0; top >= 0; top -= 64) {
+        const int32_t w = top - (int32_t)lane;
+        uint32_t word = w >= 0 ? nib[w] : 0u;
+        if (w == w0) word &= first_mask;
+        const uint32_t u = nz_mask(word);
+        const uint64_t hit = __ballot(u != 0);
+        if (hit) {
+            const uint32_t l = (uint32_t)__builtin_ctzll(hit);  // nearest word below
+            const uint32_t ul = __builtin_amdgcn_readlane(u, l);
+            const uint32_t wl = __builtin_amdgcn_readlane(word, l);
+            const uint32_t nib_i = (31u - (uint32_t)__builtin_clz(ul)) >> 2;
+            cell = (wl >> (nib_i * 4)) & 15u;
+            return (top - (int32_t)l) * 8 + (int32_t)nib_i;
+        }
+    }
+    return -2;
 }
 
-struct Undo {
+struct Undo {  // at most two cells change per step
     uint32_t n;
-    uint32_t w[2], old[2];
+    uint32_t w0, old0, w1, old1;
 };
 
 // Adds `bit` to the cell of rank r and updates (s, v, m).  Returns false
 // when the structure is inconsistent (never for a valid state).
-__device__ bool insert(uint32_t *nib, uint32_t nw, uint32_t r, uint32_t bit, uint32_t o, Est &e,
+__device__ __forceinline__ bool insert(uint32_t *nib, uint32_t nw, uint32_t r, uint32_t bit, uint32_t o, Est &e,
                        Undo &u) {
     const uint32_t wi = r >> 3, sh = (r & 7) * 4;
     const uint32_t word = nib[wi];
     const uint32_t c = (word >> sh) & 15u, c2 = c | bit;
     if (c2 == c) return true;
-    u.w[u.n] = wi;
-    u.old[u.n] = word;
+    if (u.n == 0) { u.w0 = wi; u.old0 = word; } else { u.w1 = wi; u.old1 = word; }
     u.n++;
     nib[wi] = word | (bit << sh);
     const bool was_u = c != 0;
@@ -234,14 +272,16 @@ __device__ bool insert(uint32_t *nib, uint32_t nw, uint32_t r, uint32_t bit, uin
         e.s++;
         if (!was_u && ri < e.v) return true;  // enters below v: v stays the s-th
         if (was_u && ri <= e.v && gain) e.m++;
-        const int32_t vn = succ_rank(nib, e.v, nw);
+        uint32_t cv;
+        const int32_t vn = succ_rank(nib, e.v, nw, cv);
         if (vn < 0) return false;
-        if (cell_shared(cell_at(nib, vn), o)) e.m++;
+        if (cell_shared(cv, o)) e.m++;
         e.v = vn;
     } else if (!was_u) {
         if (ri < e.v) {  // a new target-side element pushes v out of the s smallest
             if (cell_shared(cell_at(nib, e.v), o)) e.m--;
-            const int32_t vn = pred_rank(nib, e.v);
+            uint32_t cv;
+            const int32_t vn = pred_rank(nib, e.v, cv);
             if (vn < 0) return false;
             e.v = vn;
         }
@@ -252,7 +292,8 @@ __device__ bool insert(uint32_t *nib, uint32_t nw, uint32_t r, uint32_t bit, uin
 }
 
 __device__ __forceinline__ void undo(uint32_t *nib, const Undo &u) {
-    for (int t = (int)u.n - 1; t >= 0; t--) nib[u.w[t]] = u.old[t];
+    if (u.n > 1) nib[u.w1] = u.old1;
+    if (u.n > 0) nib[u.w0] = u.old0;
 }
 
 // One list of entering minimizers: the minimizer array range [lo, hi),
@@ -265,12 +306,100 @@ struct EvList {
     uint32_t base;  // element id of index lo
 };
 
+// Inclusive prefix sum over the lanes of the wave.
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v) {
+    const uint32_t lane = threadIdx.x & 63;
+#pragma unroll
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+        const uint32_t t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+    return __builtin_amdgcn_readlane(wave_incl_sum(v), 63);
+}
+
+// The k-th element of L above rank v (k >= 1), and in `sh` the number of
+// shared elements in (v, that rank].  64 cell words per step.
+__device__ __forceinline__ int32_t kth_succ(const uint32_t *nib, uint32_t nw, int32_t v, uint32_t k,
+                                            uint32_t o, uint32_t &sh) {
+    const uint32_t lane = threadIdx.x & 63;
+    const int32_t r = v + 1;
+    sh = 0;
+    if ((uint32_t)r >= nw * 8) return -2;
+    const uint32_t w0 = (uint32_t)r >> 3;
+    const uint32_t first_mask = 0xFFFFFFFFu << ((r & 7) * 4);
+    for (uint32_t base = w0; base < nw; base += 64) {
+        const uint32_t w = base + lane;
+        uint32_t word = w < nw ? nib[w] : 0u;
+        if (w == w0) word &= first_mask;
+        const uint32_t u = nz_mask(word);
+        const uint32_t c = __popc(u);
+        const uint32_t incl = wave_incl_sum(c);
+        const uint32_t tot = __builtin_amdgcn_readlane(incl, 63);
+        const uint32_t sm = shared_mask(word, o);
+        if (tot >= k) {
+            const uint32_t l = (uint32_t)__builtin_ctzll(__ballot(incl >= k));
+            const uint32_t before = __builtin_amdgcn_readlane(incl - c, l);
+            uint32_t ul = __builtin_amdgcn_readlane(u, l);
+            for (uint32_t need = k - before; need > 1; need--) ul &= ul - 1;
+            const uint32_t ni = (uint32_t)__builtin_ctz(ul) >> 2;
+            const uint32_t keep = ni == 7 ? 0xFFFFFFFFu : ((1u << ((ni + 1) * 4)) - 1u);
+            const uint32_t mine = lane < l ? sm : (lane == l ? (sm & keep) : 0u);
+            sh += wave_sum(__popc(mine));
+            return (int32_t)((base + l) * 8 + ni);
+        }
+        k -= tot;
+        sh += wave_sum(__popc(sm));
+    }
+    return -2;
+}
+
+// The k-th element of L below rank v (k >= 1), and in `sh` the number of
+// shared elements strictly between it and v.  64 cell words per step.
+__device__ __forceinline__ int32_t kth_pred(const uint32_t *nib, int32_t v, uint32_t k, uint32_t o,
+                                            uint32_t &sh) {
+    const uint32_t lane = threadIdx.x & 63;
+    const int32_t r = v - 1;
+    sh = 0;
+    if (r < 0) return -2;
+    const int32_t w0 = r >> 3;
+    const uint32_t first_mask = (r & 7) == 7 ? 0xFFFFFFFFu : ((1u << (((r & 7) + 1) * 4)) - 1u);
+    for (int32_t top = w0; top >= 0; top -= 64) {
+        const int32_t w = top - (int32_t)lane;
+        uint32_t word = w >= 0 ? nib[w] : 0u;
+        if (w == w0) word &= first_mask;
+        const uint32_t u = nz_mask(word);
+        const uint32_t c = __popc(u);
+        const uint32_t incl = wave_incl_sum(c);
+        const uint32_t tot = __builtin_amdgcn_readlane(incl, 63);
+        const uint32_t sm = shared_mask(word, o);
+        if (tot >= k) {
+            const uint32_t l = (uint32_t)__builtin_ctzll(__ballot(incl >= k));
+            const uint32_t before = __builtin_amdgcn_readlane(incl - c, l);
+            uint32_t ul = __builtin_amdgcn_readlane(u, l);
+            for (uint32_t need = k - before; need > 1; need--)
+                ul &= ~(1u << (31 - __builtin_clz(ul)));
+            const uint32_t ni = (31u - (uint32_t)__builtin_clz(ul)) >> 2;
+            const uint32_t above = ni == 7 ? 0u : ~((1u << ((ni + 1) * 4)) - 1u);
+            const uint32_t mine = lane < l ? sm : (lane == l ? (sm & above) : 0u);
+            sh += wave_sum(__popc(mine));
+            return (top - (int32_t)l) * 8 + (int32_t)ni;
+        }
+        k -= tot;
+        sh += wave_sum(__popc(sm));
+    }
+    return -2;
+}
+
 struct EvCursor {
     uint64_t next;     // events consumed
     uint64_t count;
     uint32_t fill;     // events held in registers (lane-indexed)
     uint32_t at;       // next held event
-    uint64_t vstep;    // this lane's held event
+    uint32_t vstep;    // this lane's held event: its step (at most max_len), rank, cell bit
     uint32_t vrank, vbit;
 };
 
@@ -280,11 +409,11 @@ __device__ __forceinline__ void ev_refill(const ExtArgs &a, const uint32_t *rank
     const uint64_t e = c.next + lane;
     c.fill = (uint32_t)std::min<uint64_t>(64, c.count - c.next);
     c.at = 0;
-    c.vstep = INF;
+    c.vstep = 0xFFFFFFFFu;
     if (e < c.count) {
         const uint64_t mi = l.up ? l.lo + e : l.hi - 1 - e;
         const uint64_t pos = a.ix.mpos[mi];
-        c.vstep = l.up ? pos + a.ix.k - l.ref : l.ref - pos;
+        c.vstep = (uint32_t)(l.up ? pos + a.ix.k - l.ref : l.ref - pos);
         c.vrank = rank[l.base + (uint32_t)(mi - l.lo)];
         c.vbit = l.side << (a.ix.mflags[mi] & 1);
     }
@@ -292,15 +421,79 @@ __device__ __forceinline__ void ev_refill(const ExtArgs &a, const uint32_t *rank
 
 __device__ __forceinline__ uint64_t ev_head(const EvCursor &c) {
     if (c.at >= c.fill) return INF;
-    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)c.vstep, c.at);
-    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(c.vstep >> 32), c.at);
-    return ((uint64_t)hi << 32) | lo;
+    return __builtin_amdgcn_readlane(c.vstep, c.at);
+}
+
+// Several steps at once: the held events [at, at + nq) of the query list
+// and [at, at + nt) of the target list are inserted together.  The caller
+// has checked that no step among them can fail (each insertion lowers m by
+// at most 1 and raises ceil(tau s) by at most 1, and the slack m -
+// ceil(tau s) is at least three per insertion), so only the state after
+// the last one matters, and it does not depend on their order: s grows by
+// the hashes new to the query side, v moves to the s-th element of the new
+// L (k elements up or down), and m follows the shared elements passed and
+// those that became shared at or below the old v.
+__device__ __forceinline__ bool apply_batch(uint32_t *nib, uint32_t nw, const EvCursor &cq,
+                                            uint32_t nq, const EvCursor &ct, uint32_t nt,
+                                            uint32_t o, Est &e) {
+    const uint32_t lane = threadIdx.x & 63;
+    const bool hq = lane >= cq.at && lane < cq.at + nq;
+    const bool ht = lane >= ct.at && lane < ct.at + nt;
+    const uint32_t rq = cq.vrank, rt = ct.vrank;
+    const uint32_t oq = hq ? cell_at(nib, (int32_t)rq) : 0u;
+    const uint32_t ot = ht ? cell_at(nib, (int32_t)rt) : 0u;
+    __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");  // reads before writes
+    if (hq) atomicOr(&nib[rq >> 3], cq.vbit << ((rq & 7) * 4));
+    if (ht) atomicOr(&nib[rt >> 3], ct.vbit << ((rt & 7) * 4));
+    __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");  // writes before reads
+    const uint32_t cq1 = hq ? cell_at(nib, (int32_t)rq) : 0u;
+    const uint32_t ct1 = ht ? cell_at(nib, (int32_t)rt) : 0u;
+    // count each rank once: query events by lane, then target events by lane
+    bool fq = hq, ft = ht;
+    for (uint32_t j = cq.at; j < cq.at + nq; j++) {
+        const uint32_t rj = __builtin_amdgcn_readlane(rq, j);
+        if (j < lane && rj == rq) fq = false;
+        if (rj == rt) ft = false;
+    }
+    for (uint32_t j = ct.at; j < ct.at + nt; j++) {
+        const uint32_t rj = __builtin_amdgcn_readlane(rt, j);
+        if (j < lane && rj == rt) ft = false;
+    }
+    const int32_t v = e.v;
+    auto tally = [&](bool f, uint32_t r, uint32_t c0, uint32_t c1, bool &ds, bool &nb, bool &gb) {
+        ds = f && !(c0 & 3u) && (c1 & 3u);
+        nb = f && c0 == 0 && (int32_t)r < v;
+        gb = f && (int32_t)r <= v && !cell_shared(c0, o) && cell_shared(c1, o);
+    };
+    bool dsq, nbq, gbq, dst, nbt, gbt;
+    tally(fq, rq, oq, cq1, dsq, nbq, gbq);
+    tally(ft, rt, ot, ct1, dst, nbt, gbt);
+    const uint32_t dS = (uint32_t)(__popcll(__ballot(dsq)) + __popcll(__ballot(dst)));
+    const uint32_t nB = (uint32_t)(__popcll(__ballot(nbq)) + __popcll(__ballot(nbt)));
+    const uint32_t gB = (uint32_t)(__popcll(__ballot(gbq)) + __popcll(__ballot(gbt)));
+    const int32_t diff = (int32_t)dS - (int32_t)nB;
+    int32_t vn = v;
+    int64_t m = (int64_t)e.m + gB;
+    if (diff > 0) {
+        uint32_t sh;
+        vn = kth_succ(nib, nw, v, (uint32_t)diff, o, sh);
+        m += sh;
+    } else if (diff < 0) {
+        uint32_t sh;
+        vn = kth_pred(nib, v, (uint32_t)(-diff), o, sh);
+        m -= (int64_t)sh + (cell_shared(cell_at(nib, v), o) ? 1 : 0);
+    }
+    if (vn < 0 || m < 0) return false;
+    e.v = vn;
+    e.s += dS;
+    e.m = (uint32_t)m;
+    return true;
 }
 
 // One phase on wave 0.  Returns the steps taken; `code` is the stop code,
 // or 0 when the events ran out before the phase could stop (larger horizon
 // needed).
-__device__ uint64_t run_phase(const ExtArgs &a, uint32_t *nib, uint32_t nw, const uint32_t *rank,
+__device__ __forceinline__ uint64_t run_phase(const ExtArgs &a, uint32_t *nib, uint32_t nw, const uint32_t *rank,
                               const EvList &lq, const EvList &lt, uint64_t known, uint64_t lim,
                               uint32_t lim_code, uint32_t o, Est &e, bool &ok, uint32_t &code,
                               unsigned long long &applied, bool &bad) {
@@ -319,6 +512,30 @@ __device__ uint64_t run_phase(const ExtArgs &a, uint32_t *nib, uint32_t nw, cons
         if (ct.at >= ct.fill && ct.next + ct.fill < ct.count) {
             ct.next += ct.fill;
             ev_refill(a, rank, lt, ct);
+        }
+        if (ok && e.s > 0 && a.batch_min) {
+            // all held events up to a step S known to hold every event <= S
+            const uint64_t bq = cq.next + cq.fill < cq.count
+                                    ? __builtin_amdgcn_readlane(cq.vstep, cq.fill - 1) : INF;
+            const uint64_t bt = ct.next + ct.fill < ct.count
+                                    ? __builtin_amdgcn_readlane(ct.vstep, ct.fill - 1) : INF;
+            const uint64_t S = std::min(std::min(bq, bt), known);
+            const uint32_t lane = threadIdx.x & 63;
+            const uint32_t nq = (uint32_t)__popcll(
+                __ballot(lane >= cq.at && lane < cq.fill && (uint64_t)cq.vstep <= S));
+            const uint32_t nt = (uint32_t)__popcll(
+                __ballot(lane >= ct.at && lane < ct.fill && (uint64_t)ct.vstep <= S));
+            const int64_t slack = (int64_t)e.m - (int64_t)(uint32_t)ceil(a.tau * (double)e.s);
+            if (nq + nt >= a.batch_min && slack >= 3 * (int64_t)(nq + nt)) {
+                if (!apply_batch(nib, nw, cq, nq, ct, nt, o, e)) { bad = true; code = STOP_ESTIMATE; return last; }
+                cq.at += nq;
+                ct.at += nt;
+                applied += nq + nt;
+                ok = passes(e, a.tau);
+                if (!ok) { bad = true; code = STOP_ESTIMATE; return last; }
+                last = std::max(last, S);
+                continue;
+            }
         }
         const uint64_t sq = ev_head(cq), st = ev_head(ct);
         const uint64_t te = std::min(sq, st);
@@ -465,6 +682,52 @@ __device__ bool rank_big(Shared &L, const uint64_t *src, uint64_t b, uint64_t e,
     return true;
 }
 
+struct PhaseIn {
+    uint64_t qlo, qhi, tlo, thi;
+    bool same;
+    uint32_t o;
+    uint64_t Hf, Hb;
+    uint64_t start[4];  // the region the lists were gathered for
+};
+
+// The phases from `dir0` on, on one wave, from the state e of region r.
+// Returns 0 when both phases stopped (r, e, codes final), or 2 (forward) /
+// 8 (backward) when a phase ran through its horizon: r and e are then the
+// state it reached, which the next attempt continues from.  Inlined once
+// with L in LDS and once in global memory.
+__device__ __forceinline__ uint32_t phases(const ExtArgs &a, const Shared &L, uint32_t *nib,
+                                           uint32_t nw, const uint32_t *rank, const PhaseIn &pi,
+                                           int dir0, uint64_t r[4], Est &e, uint32_t codes[2],
+                                           unsigned long long &app, bool &bad) {
+    const uint32_t o = pi.o;
+    bool ok = passes(e, a.tau);
+    for (int dir = dir0; dir < 2; dir++) {
+        const Phase p = phase_of(dir, o);
+        uint64_t lim;
+        uint32_t lcode;
+        phase_limit(r, pi.qlo, pi.qhi, pi.tlo, pi.thi, pi.same, p, a.max_len, lim, lcode);
+        const uint64_t known = std::min(dir == 0 ? pi.Hf : pi.Hb, lim);
+        EvList lq, lt;
+        const int iq = dir == 0 ? 2 : 4, it = dir == 0 ? 3 : 5;
+        lq.lo = L.mlo[iq]; lq.hi = L.mhi[iq]; lq.base = L.base[iq]; lq.side = C_Q0;
+        lt.lo = L.mlo[it]; lt.hi = L.mhi[it]; lt.base = L.base[it]; lt.side = C_T0;
+        if (dir == 0) {
+            lq.up = true; lq.ref = pi.start[1];
+            lt.up = o == 0; lt.ref = o == 0 ? pi.start[3] : pi.start[2];
+        } else {
+            lq.up = false; lq.ref = pi.start[0];
+            lt.up = o == 1; lt.ref = o == 0 ? pi.start[2] : pi.start[3];
+        }
+        uint32_t code = 0;
+        const uint64_t t = run_phase(a, nib, nw, rank, lq, lt, known, lim, lcode, o, e, ok, code,
+                                     app, bad);
+        r[0] -= p.ql * t; r[1] += p.qr * t; r[2] -= p.tl * t; r[3] += p.tr * t;
+        if (code == 0) return dir == 0 ? 2u : 8u;
+        if (dir == 0) codes[0] = code; else codes[1] = code;
+    }
+    return 0;
+}
+
 }  // namespace
 
 __global__ void __launch_bounds__(XT) k_extend(ExtArgs a) {
@@ -478,6 +741,7 @@ __global__ void __launch_bounds__(XT) k_extend(ExtArgs a) {
     const uint32_t hbits = 2 * k;
     const uint32_t shift = hbits > 12 ? hbits - 12 : 0;
     const uint32_t nbk = 1u << (hbits - shift);
+    constexpr uint32_t PER = NB / XT;
 
     for (;;) {
         if (threadIdx.x == 0) L.region = atomicAdd(a.work, 1u);
@@ -485,13 +749,13 @@ __global__ void __launch_bounds__(XT) k_extend(ExtArgs a) {
         const uint32_t id = L.region;
         __syncthreads();
         if (id >= a.n) break;
+        const uint64_t t_region = wall_clock64();
         const sdf_region R = a.in[id];
         const uint32_t o = R.strand;
         const uint64_t qlo = ix.off[R.q_seq], qhi = ix.off[R.q_seq + 1];
         const uint64_t tlo = ix.off[R.t_seq], thi = ix.off[R.t_seq + 1];
         const bool same = R.q_seq == R.t_seq;
         uint64_t r[4] = {qlo + R.q_begin, qlo + R.q_end, tlo + R.t_begin, tlo + R.t_end};
-        const uint64_t start[4] = {r[0], r[1], r[2], r[3]};
         sdf_region res = R;
         if (r[1] - r[0] > a.max_len || r[3] - r[2] > a.max_len) {
             if (threadIdx.x == 0) {
@@ -501,25 +765,27 @@ __global__ void __launch_bounds__(XT) k_extend(ExtArgs a) {
             }
             continue;
         }
-        const uint64_t longer = std::max(r[1] - r[0], r[3] - r[2]);
-        // horizons (steps per phase) to gather, and horizons known too short
-        uint64_t hf = a.h0 + 2 * longer, hb = hf, df = 0, db = 0;
-        unsigned long long applied = 0;
-        uint32_t restarts = 0;
+        unsigned long long applied = 0, t_rank = 0, t_loop = 0;
+        uint32_t attempts = 0;
+        uint32_t codes[2] = {0, 0};
+        int dir = 0;          // the phase the next attempt continues
+        uint64_t hcut = ~0ull;  // horizon cap after a scratch overflow
         bool failed = false;
-        for (;;) {  // attempts with growing horizons
-            for (int d = 0; d < 4; d++) r[d] = start[d];
-            // horizons bounded by what each phase could ever take
+        Est e{-1, 0, 0};
+        for (;;) {  // attempts: gather, rank, run until both phases stop
+            const uint64_t t_att = wall_clock64();
+            const uint64_t longer = std::max(r[1] - r[0], r[3] - r[2]);
+            const uint64_t want = std::max<uint64_t>(1, std::min(hcut, std::max(a.h0, longer / 4)));
             uint64_t lim_f;
             uint32_t code_f;
-            const Phase pf = phase_of(0, o), pb = phase_of(1, o);
-            phase_limit(r, qlo, qhi, tlo, thi, same, pf, a.max_len, lim_f, code_f);
-            const uint64_t Hf = std::min(hf, lim_f);
+            phase_limit(r, qlo, qhi, tlo, thi, same, phase_of(0, o), a.max_len, lim_f, code_f);
+            const uint64_t Hf = dir == 0 ? std::min(want, lim_f) : 0;
             uint64_t ub_b = std::min(r[0] - qlo, o == 0 ? r[2] - tlo : thi - r[3]);
             ub_b = std::min(ub_b, a.max_len - longer);
-            const uint64_t Hb = std::min(hb, ub_b);
-            // position ranges [pa, pb] of the six element lists
-            int64_t pa[6], pe[6];
+            const uint64_t Hb = std::min(want, ub_b);
+            // position ranges [pa, pe] of the six element lists: both windows,
+            // then the forward and the backward minimizers that can enter
+            int64_t pa[6], pe[6];  // (indexed by constants only: registers)
             pa[0] = (int64_t)r[0]; pe[0] = (int64_t)r[1] - k;
             pa[1] = (int64_t)r[2]; pe[1] = (int64_t)r[3] - k;
             pa[2] = (int64_t)r[1] + 1 - k; pe[2] = (int64_t)(r[1] + Hf) - k;
@@ -531,10 +797,14 @@ __global__ void __launch_bounds__(XT) k_extend(ExtArgs a) {
             if (Hf == 0) { pa[2] = pa[3] = 1; pe[2] = pe[3] = 0; }
             if (Hb == 0) { pa[4] = pa[5] = 1; pe[4] = pe[5] = 0; }
             if (threadIdx.x < 12) {
-                const int l = threadIdx.x >> 1;
+                const uint32_t l = threadIdx.x >> 1;
+                int64_t lo_p = pa[0], hi_p = pe[0];
+#pragma unroll
+                for (uint32_t t = 1; t < 6; t++)
+                    if (l == t) { lo_p = pa[t]; hi_p = pe[t]; }
                 const bool hi_end = threadIdx.x & 1;
-                const int64_t x = hi_end ? pe[l] + 1 : pa[l];
-                const uint64_t v = (pe[l] < pa[l]) ? 0 : lower_pos(ix, (uint64_t)std::max<int64_t>(x, 0));
+                const int64_t x = hi_end ? hi_p + 1 : lo_p;
+                const uint64_t v = (hi_p < lo_p) ? 0 : lower_pos(ix, (uint64_t)std::max<int64_t>(x, 0));
                 if (hi_end) L.mhi[l] = v; else L.mlo[l] = v;
             }
             __syncthreads();
@@ -553,19 +823,16 @@ __global__ void __launch_bounds__(XT) k_extend(ExtArgs a) {
             __syncthreads();
             const uint64_t E = L.base[6];
             if (E > a.ecap) {
-                // halve the horizons toward what is known to be too short;
-                // give up when neither can move
-                const uint64_t nf = std::max(df + 1, (df + hf) / 2);
-                const uint64_t nb = std::max(db + 1, (db + hb) / 2);
-                if (nf == hf && nb == hb) {
+                // shorten the horizon; give up when it cannot shrink
+                if (want <= 1) {
                     if (threadIdx.x == 0) atomicOr(a.err, (uint32_t)XE_CAP);
                     failed = true;
                     break;
                 }
-                hf = nf;
-                hb = nb;
+                hcut = want / 2;
                 continue;
             }
+            attempts++;
             // 1. bucket by the top hash bits into tmp
             for (uint32_t i = threadIdx.x; i < NB + 1; i += XT) L.bs[i] = 0;
             __syncthreads();
@@ -573,7 +840,6 @@ __global__ void __launch_bounds__(XT) k_extend(ExtArgs a) {
                 for (uint64_t i = L.mlo[l] + threadIdx.x; i < L.mhi[l]; i += XT)
                     atomicAdd(&L.bs[(ix.mhash[i] >> shift) & (nbk - 1)], 1u);
             __syncthreads();
-            constexpr uint32_t PER = NB / XT;
             {
                 uint32_t loc = 0;
                 for (uint32_t t = 0; t < PER; t++) loc += L.bs[threadIdx.x * PER + t];
@@ -647,7 +913,7 @@ __global__ void __launch_bounds__(XT) k_extend(ExtArgs a) {
             const uint32_t nr = L.nrank;
             const uint32_t nw = (nr + 7) / 8;
             uint32_t *nib = (nw <= a.lds_words) ? L.w : gnib;
-            // 3. the start state
+            // 3. the state of the current region
             for (uint32_t i = threadIdx.x; i < nw; i += XT) nib[i] = 0;
             __syncthreads();
             for (int l = 0; l < 2; l++)
@@ -695,76 +961,58 @@ __global__ void __launch_bounds__(XT) k_extend(ExtArgs a) {
                 if (threadIdx.x == 0) L.m = m;
                 __syncthreads();
             }
-            // 4. the phases, on wave 0
-            bool exhausted = false;
+            const uint64_t t_mid = wall_clock64();
+            // 4. the phases, on wave 0 (L in LDS or in global memory)
             if (threadIdx.x < 64) {
-                Est e;
                 e.v = L.v; e.s = L.s; e.m = L.m;
-                bool ok = passes(e, a.tau);
-                bool bad = false;
+                PhaseIn pi{qlo, qhi, tlo, thi, same, o, Hf, Hb, {r[0], r[1], r[2], r[3]}};
                 unsigned long long app = 0;
-                uint32_t codes[2] = {0, 0};
-                for (int dir = 0; dir < 2 && !exhausted; dir++) {
-                    const Phase p = phase_of(dir, o);
-                    uint64_t lim;
-                    uint32_t lcode;
-                    phase_limit(r, qlo, qhi, tlo, thi, same, p, a.max_len, lim, lcode);
-                    const uint64_t H = dir == 0 ? Hf : Hb;
-                    const uint64_t known = std::min(H, lim);
-                    EvList lq, lt;
-                    const int iq = dir == 0 ? 2 : 4, it = dir == 0 ? 3 : 5;
-                    lq.lo = L.mlo[iq]; lq.hi = L.mhi[iq]; lq.base = L.base[iq]; lq.side = C_Q0;
-                    lt.lo = L.mlo[it]; lt.hi = L.mhi[it]; lt.base = L.base[it]; lt.side = C_T0;
-                    if (dir == 0) {
-                        lq.up = true; lq.ref = start[1];
-                        lt.up = o == 0; lt.ref = o == 0 ? start[3] : start[2];
-                    } else {
-                        lq.up = false; lq.ref = start[0];
-                        lt.up = o == 1; lt.ref = o == 0 ? start[2] : start[3];
-                    }
-                    uint32_t code = 0;
-                    const uint64_t t = run_phase(a, nib, nw, rank, lq, lt, known, lim, lcode, o, e, ok,
-                                                 code, app, bad);
-                    if (code == 0) { exhausted = true; codes[dir] = 0; break; }
-                    codes[dir] = code;
-                    r[0] -= p.ql * t; r[1] += p.qr * t; r[2] -= p.tl * t; r[3] += p.tr * t;
-                }
+                bool bad = false;
+                const uint32_t ex = nw <= a.lds_words
+                                        ? phases(a, L, L.w, nw, rank, pi, dir, r, e, codes, app, bad)
+                                        : phases(a, L, gnib, nw, rank, pi, dir, r, e, codes, app, bad);
                 if (threadIdx.x == 0) {
-                    L.flag = (exhausted ? (codes[0] ? 8u : 2u) : 0u) | (bad ? 4u : 0u);
-                    if (!exhausted && !bad) {
-                        res.q_begin = r[0] - qlo; res.q_end = r[1] - qlo;
-                        res.t_begin = r[2] - tlo; res.t_end = r[3] - tlo;
-                        res.m = e.m; res.s = e.s;
-                        res.stop = codes[0] | (codes[1] << 8);
-                        a.out[id] = res;
-                    }
+                    L.flag = ex | (bad ? 4u : 0u);
+                    L.rr[0] = r[0]; L.rr[1] = r[1]; L.rr[2] = r[2]; L.rr[3] = r[3];
+                    L.codes[0] = codes[0]; L.codes[1] = codes[1];
                     applied += app;
                 }
             }
             __syncthreads();
             const uint32_t fl = L.flag;
+            for (int d = 0; d < 4; d++) r[d] = L.rr[d];
+            codes[0] = L.codes[0];
+            codes[1] = L.codes[1];
             __syncthreads();
+            const uint64_t t_end = wall_clock64();
+            t_rank += t_mid - t_att;
+            t_loop += t_end - t_mid;
             if (fl & 4u) {
                 if (threadIdx.x == 0) atomicOr(a.err, (uint32_t)XE_STATE);
                 failed = true;
                 break;
             }
-            if (!(fl & 10u)) {
-                if (threadIdx.x == 0) atomicAdd(&a.stats[2], (unsigned long long)nr);
-                break;
-            }
-            restarts++;
-            if (fl & 2u) { df = Hf; hf = 4 * std::max(hf, Hf); }  // forward ran out
-            else { db = Hb; hb = 4 * std::max(hb, Hb); }          // backward ran out
+            if (threadIdx.x == 0) atomicAdd(&a.stats[2], (unsigned long long)nr);
+            if (!(fl & 10u)) break;
+            dir = (fl & 2u) ? 0 : 1;  // continue the phase that ran out
+            hcut = ~0ull;
         }
         if (threadIdx.x == 0) {
-            atomicAdd(&a.stats[0], applied);
-            atomicAdd(&a.stats[1], (unsigned long long)restarts);
             if (failed) {
                 res.m = res.s = 0;
                 res.stop = 0;
-                a.out[id] = res;
+            } else {
+                res.q_begin = r[0] - qlo; res.q_end = r[1] - qlo;
+                res.t_begin = r[2] - tlo; res.t_end = r[3] - tlo;
+                res.m = e.m; res.s = e.s;
+                res.stop = codes[0] | (codes[1] << 8);
             }
+            a.out[id] = res;
+            atomicAdd(&a.stats[0], applied);
+            atomicAdd(&a.stats[1], (unsigned long long)(attempts > 0 ? attempts - 1 : 0));
+            atomicAdd(&a.stats[3], t_rank);
+            atomicAdd(&a.stats[4], t_loop);
+            atomicMax(&a.stats[5], (unsigned long long)(wall_clock64() - t_region));
         }
         __syncthreads();
     }
@@ -777,14 +1025,19 @@ void launch_extend(const IndexView &ix, const sdf_region *in, uint64_t n, double
     int dev = 0, cus = 0;
     SDF_HIP(hipGetDevice(&dev));
     SDF_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    // test hooks: SDF_EXT_H0 sets the first horizon, SDF_EXT_LDS_WORDS the
-    // cells kept in LDS (0 keeps L in global memory), SDF_EXT_ECAP the
-    // elements per workgroup
+    // test hooks: SDF_EXT_H0 sets the horizon, SDF_EXT_LDS_WORDS the cells
+    // kept in LDS (0 keeps L in global memory), SDF_EXT_ECAP the elements per
+    // workgroup, SDF_EXT_BATCH_MIN the smallest batch (0: one step at a time)
+    // each attempt gathers max(h0, longer side / 4) steps per phase; a phase
+    // that runs through them continues in the next attempt
     uint64_t h0 = 8192, ecap = 1ull << 18;
     uint32_t ldsw = LDS_WORDS;
     if (const char *v = std::getenv("SDF_EXT_H0")) h0 = std::strtoull(v, nullptr, 10);
     if (const char *v = std::getenv("SDF_EXT_LDS_WORDS"))
         ldsw = std::min<uint32_t>(LDS_WORDS, (uint32_t)std::strtoul(v, nullptr, 10));
+    uint32_t batch_min = 8;
+    if (const char *v = std::getenv("SDF_EXT_BATCH_MIN"))
+        batch_min = (uint32_t)std::strtoul(v, nullptr, 10);
     if (const char *v = std::getenv("SDF_EXT_ECAP"))
         ecap = std::max<uint64_t>(64, std::strtoull(v, nullptr, 10));
     // two workgroups fit a CU (LDS); each keeps its own scratch
@@ -792,9 +1045,9 @@ void launch_extend(const IndexView &ix, const sdf_region *in, uint64_t n, double
     DevBuf<uint64_t> tmp(grid * ecap);
     DevBuf<uint32_t> rank(grid * ecap), gnib(grid * (ecap / 8 + 1));
     DevBuf<uint32_t> work(2);
-    DevBuf<unsigned long long> cnt(3);
+    DevBuf<unsigned long long> cnt(6);
     SDF_HIP(hipMemsetAsync(work.p, 0, 8, st));
-    SDF_HIP(hipMemsetAsync(cnt.p, 0, 24, st));
+    SDF_HIP(hipMemsetAsync(cnt.p, 0, 48, st));
     ExtArgs a;
     a.ix = ix;
     a.in = in;
@@ -809,24 +1062,31 @@ void launch_extend(const IndexView &ix, const sdf_region *in, uint64_t n, double
     a.gnib = gnib.p;
     a.ecap = ecap;
     a.lds_words = ldsw;
+    a.batch_min = batch_min;
     a.err = work.p + 1;
     a.stats = cnt.p;
     k_extend<<<(unsigned)grid, XT, 0, st>>>(a);
     SDF_HIP(hipGetLastError());
     uint32_t herr = 0;
-    unsigned long long hc[3] = {0, 0, 0};
+    unsigned long long hc[6] = {0, 0, 0, 0, 0, 0};
     SDF_HIP(hipMemcpyAsync(&herr, work.p + 1, 4, hipMemcpyDeviceToHost, st));
-    SDF_HIP(hipMemcpyAsync(hc, cnt.p, 24, hipMemcpyDeviceToHost, st));
+    SDF_HIP(hipMemcpyAsync(hc, cnt.p, 48, hipMemcpyDeviceToHost, st));
     SDF_HIP(hipStreamSynchronize(st));
     if (herr & XE_CAP)
-        throw Error{SDF_EINTERNAL, "extend: a region needs more minimizers than its scratch holds"};
+        throw Error{SDF_EINTERNAL, "extend: a region's windows hold more minimizers than its scratch"};
     if (herr & XE_HASH)
-        throw Error{SDF_EINTERNAL, "extend: more than 4096 distinct hashes share all cut bits"};
+        throw Error{SDF_EINTERNAL, "extend: more than 1024 distinct hashes share 12 hash bits"};
     if (herr & XE_STATE) throw Error{SDF_EINTERNAL, "extend: inconsistent ordered set"};
     if (stats) {
+        int khz = 0;
+        SDF_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        const double us = khz > 0 ? 1e3 / (double)khz : 0.0;
         stats->events = hc[0];
         stats->restarts = hc[1];
         stats->ranks = hc[2];
+        stats->rank_us = (unsigned long long)((double)hc[3] * us);
+        stats->loop_us = (unsigned long long)((double)hc[4] * us);
+        stats->slowest_us = (unsigned long long)((double)hc[5] * us);
     }
 }
 

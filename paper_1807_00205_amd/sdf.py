@@ -201,11 +201,14 @@ class Result:
         _check(lib().sdf_result_timing(self._h, ms, 6))
         return np.array(ms[:], dtype=np.float64)
 
-    def stats(self) -> dict:
-        v = (ctypes.c_uint64 * 8)()
-        _check(lib().sdf_result_stats(self._h, v, 8))
+    def stats(self, extension: bool = False) -> dict:
+        v = (ctypes.c_uint64 * 14)()
+        _check(lib().sdf_result_stats(self._h, v, 14))
         keys = ["windows", "hits", "kept", "tiles", "partitions", "seeds", "candidate_evals",
                 "scan_words"]
+        if extension:
+            keys += ["ext_insertions", "ext_continued", "ext_ranks", "ext_rank_us",
+                     "ext_phase_us", "ext_slowest_region_us"]
         return dict(zip(keys, [int(x) for x in v]))
 
 

@@ -113,12 +113,18 @@ def test_extend_small(S, oracle_lib, case, max_error, min_len, k, w):
 
 @pytest.mark.parametrize("hook", [{"SDF_EXT_H0": "1"}, {"SDF_EXT_LDS_WORDS": "0"},
                                   {"SDF_EXT_ECAP": "3000"},
-                                  {"SDF_EXT_H0": "0", "SDF_EXT_LDS_WORDS": "16"}],
-                         ids=["restarts", "global-cells", "small-scratch", "mixed"])
+                                  {"SDF_EXT_H0": "0", "SDF_EXT_LDS_WORDS": "16"},
+                                  {"SDF_EXT_BATCH_MIN": "0"}, {"SDF_EXT_BATCH_MIN": "1"},
+                                  {"SDF_EXT_BATCH_MIN": "1", "SDF_EXT_LDS_WORDS": "0",
+                                   "SDF_EXT_H0": "64"}],
+                         ids=["continue", "global-cells", "small-scratch", "mixed",
+                              "one-at-a-time", "batch-always", "batch-global"])
 def test_extend_general_paths(S, oracle_lib, monkeypatch, hook):
     """The paths that large or long-running regions take, forced on small
-    inputs: horizons that run out and restart (4x), the ordered set kept in
-    global memory instead of LDS, and horizons shrunk to fit the scratch."""
+    inputs: phases that run through their horizon and continue in a new
+    attempt, the ordered set kept in global memory instead of LDS, horizons
+    shrunk to fit the scratch, and insertions applied one at a time or in
+    batches as small as one."""
     for kv in hook.items():
         monkeypatch.setenv(*kv)
     g = synth.small_case(81, length=8000, n_sd=4, sd_lo=800, sd_hi=2000, n_seqs=2,

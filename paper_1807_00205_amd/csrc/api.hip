@@ -7,6 +7,7 @@
 #include <new>
 
 #include "sdf_impl.h"
+#include "extend.h"
 #include "search.h"
 
 namespace sdf {

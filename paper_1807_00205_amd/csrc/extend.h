@@ -1,0 +1,17 @@
+// Launch interface of the region extension (internal).
+#pragma once
+#include "sdf_impl.h"
+
+namespace sdf {
+
+// Extension of regions (extend.hip): in/out are device arrays of n regions
+// with validated bounds (they may alias).  Throws on a scratch overflow.
+struct ExtStats {
+    unsigned long long events = 0, restarts = 0, ranks = 0;  // insertions, continued attempts
+    unsigned long long rank_us = 0, loop_us = 0;  // workgroup time in gathering/ranking, phases
+    unsigned long long slowest_us = 0;            // the slowest region's time
+};
+void launch_extend(const IndexView &ix, const sdf_region *in, uint64_t n, double tau,
+                   uint64_t max_len, sdf_region *out, ExtStats *stats, hipStream_t st);
+
+}  // namespace sdf

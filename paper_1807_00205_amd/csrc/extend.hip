@@ -36,6 +36,7 @@
 #include <cmath>
 #include <cstdlib>
 
+#include "extend.h"
 #include "search.h"
 
 namespace sdf {
@@ -1030,12 +1031,12 @@ void launch_extend(const IndexView &ix, const sdf_region *in, uint64_t n, double
     // workgroup, SDF_EXT_BATCH_MIN the smallest batch (0: one step at a time)
     // each attempt gathers max(h0, longer side / 4) steps per phase; a phase
     // that runs through them continues in the next attempt
-    uint64_t h0 = 8192, ecap = 1ull << 18;
+    uint64_t h0 = 16384, ecap = 1ull << 18;
     uint32_t ldsw = LDS_WORDS;
     if (const char *v = std::getenv("SDF_EXT_H0")) h0 = std::strtoull(v, nullptr, 10);
     if (const char *v = std::getenv("SDF_EXT_LDS_WORDS"))
         ldsw = std::min<uint32_t>(LDS_WORDS, (uint32_t)std::strtoul(v, nullptr, 10));
-    uint32_t batch_min = 8;
+    uint32_t batch_min = 4;
     if (const char *v = std::getenv("SDF_EXT_BATCH_MIN"))
         batch_min = (uint32_t)std::strtoul(v, nullptr, 10);
     if (const char *v = std::getenv("SDF_EXT_ECAP"))

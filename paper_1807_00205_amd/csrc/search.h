@@ -69,16 +69,6 @@ void launch_span_setup(const IndexView &ix, SpanDesc *spans, uint32_t nspans, ui
 void launch_tile_search(const SearchArgs &a, uint32_t grid, hipStream_t st);
 uint32_t tile_core_max();
 
-// Extension of regions (extend.hip): in/out are device arrays of n regions
-// with validated bounds.  Throws on a scratch overflow.
-struct ExtStats {
-    unsigned long long events = 0, restarts = 0, ranks = 0;  // insertions, continued attempts
-    unsigned long long rank_us = 0, loop_us = 0;  // workgroup time in gathering/ranking, phases
-    unsigned long long slowest_us = 0;            // the slowest region's time
-};
-void launch_extend(const IndexView &ix, const sdf_region *in, uint64_t n, double tau,
-                   uint64_t max_len, sdf_region *out, ExtStats *stats, hipStream_t st);
-
 // Chaining (chain.hip): seeds -> sorted candidates; returns the candidate count.
 struct ChainOut {
     DevBuf<sdf_candidate> cands;

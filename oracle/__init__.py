@@ -91,6 +91,10 @@ def lib():
         L.or_extend.argtypes = [vp, vp, u32, dbl, u64, vp]
         L.or_extend_many.restype = u64
         L.or_extend_many.argtypes = [vp, vp, u64, dbl, u64, ctypes.c_int, vp]
+        L.or_qgram_shared.restype = u64
+        L.or_qgram_shared.argtypes = [vp, vp, u32, u32]
+        L.or_qgram_bound.restype = dbl
+        L.or_qgram_bound.argtypes = [u64, dbl, u32, dbl]
         L.or_seed_size.restype = ctypes.c_int
         L.or_cand_size.restype = ctypes.c_int
         assert L.or_seed_size() == SEED_DTYPE.itemsize
@@ -143,6 +147,11 @@ def params(max_error: float, min_len: int, k: int):
     if rc != 0:
         raise ValueError("invalid parameters")
     return tau.value, n.value, mo.value
+
+
+def qgram_bound(n: int, max_error: float, q: int, gap_rate: float) -> float:
+    """The Section 3.2 q-gram bound for a shorter side of n bases."""
+    return float(lib().or_qgram_bound(n, max_error, q, gap_rate))
 
 
 def threshold(tau: float, s: int) -> int:
@@ -212,6 +221,11 @@ class OracleIndex:
         if bad:
             raise ValueError("%d invalid regions" % bad)
         return out
+
+    def qgram_shared(self, region, q: int) -> int:
+        """Q of Section 3.2 for one region (q0, q1, t0, t1, o), global coordinates."""
+        r = np.ascontiguousarray(np.array(region[:4], dtype=np.uint64))
+        return int(lib().or_qgram_shared(self._h, _ptr(r), int(region[4]), q))
 
     def search(self, spans, max_error: float = 0.25, min_len: int = 1000, threads: int = 0,
                estimate: bool = False):

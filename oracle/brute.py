@@ -353,3 +353,21 @@ def extend(br: "Brute", q0: int, q1: int, t0: int, t1: int, o: int, tau: float,
             r = cand
     m, s = estimate(r)
     return (r[0], r[1], r[2], r[3], m, s, codes[0] | (codes[1] << 8))
+
+
+def qgram_shared(seq_bytes, q0: int, q1: int, t0: int, t1: int, o: int, q: int) -> int:
+    """Q of Section 3.2 by counting substrings: upper-cased, q-mers with a
+    non-ACGT byte dropped, the target reverse-complemented for o = 1."""
+    s = bytes(seq_bytes).decode("latin-1").upper()
+    comp = str.maketrans("ACGT", "TGCA")
+
+    def grams(x):
+        return collections.Counter(x[u:u + q] for u in range(len(x) - q + 1)
+                                   if set(x[u:u + q]) <= set("ACGT"))
+
+    a = grams(s[q0:q1])
+    t = s[t0:t1]
+    if o == 1:
+        t = t.translate(comp)[::-1]
+    b = grams(t)
+    return sum(min(v, b[g]) for g, v in a.items() if g in b)

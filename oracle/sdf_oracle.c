@@ -1349,3 +1349,71 @@ uint64_t or_extend_many(void *p, const uint64_t *regs, uint64_t n, double tau, u
     }
     return bad;
 }
+
+/* ------------------------------------------------------------------ */
+/* q-gram filter (Section 3.2, second paragraph).  Q(G_i, G_j) is the number
+ * of q-mers the two substrings share.  Readings: counted with multiplicity,
+ * Q = sum over q-mers x of min(occurrences in G_i, occurrences in G_j); a
+ * q-mer holding an N is not a q-mer; upper and lower case are the same base;
+ * in orientation o = 1 the q-mers of G_j are those of its reverse complement.
+ * The bound of the section is n (1 - dG - q dM) - (n pG + 1)(q - 1) with
+ * n = min(|G_i|, |G_j|); a pair passes when Q >= bound (double). */
+
+static uint32_t or_qgram_code(const or_index *ix, uint64_t p, uint32_t q, int rc, int *ok)
+{
+    uint32_t c = 0;
+    *ok = 1;
+    for (uint32_t u = 0; u < q; u++) {
+        uint8_t b = ix->base[p + u];
+        if (b & B_N) {
+            *ok = 0;
+            return 0;
+        }
+        c = 4 * c + (b & B_CODE);
+    }
+    if (rc) { /* the reverse complement of the q-mer */
+        uint32_t r = 0;
+        for (uint32_t u = 0; u < q; u++) {
+            r = 4 * r + (3 - (c & 3));
+            c >>= 2;
+        }
+        c = r;
+    }
+    return c;
+}
+
+/* Q for the region reg = {q0, q1, t0, t1} in orientation o; q in [1, 8]. */
+uint64_t or_qgram_shared(void *p, const uint64_t *reg, uint32_t o, uint32_t q)
+{
+    or_index *ix = (or_index *)p;
+    const uint64_t nb = 1ull << (2 * q);
+    uint64_t *ca = (uint64_t *)calloc(nb, sizeof(uint64_t));
+    uint64_t *cb = (uint64_t *)calloc(nb, sizeof(uint64_t));
+    for (uint64_t x = reg[0]; x + q <= reg[1]; x++) {
+        int ok;
+        uint32_t c = or_qgram_code(ix, x, q, 0, &ok);
+        if (ok)
+            ca[c]++;
+    }
+    for (uint64_t x = reg[2]; x + q <= reg[3]; x++) {
+        int ok;
+        uint32_t c = or_qgram_code(ix, x, q, o == 1, &ok);
+        if (ok)
+            cb[c]++;
+    }
+    uint64_t Q = 0;
+    for (uint64_t c = 0; c < nb; c++)
+        Q += ca[c] < cb[c] ? ca[c] : cb[c];
+    free(ca);
+    free(cb);
+    return Q;
+}
+
+/* The Section 3.2 bound for a pair whose shorter side has n bases. */
+double or_qgram_bound(uint64_t n, double max_error, uint32_t q, double gap_rate)
+{
+    double dM = max_error < 0.15 ? max_error : 0.15;
+    double dG = max_error - dM;
+    double nn = (double)n;
+    return nn * (1.0 - dG - (double)q * dM) - (nn * gap_rate + 1.0) * (double)(q - 1);
+}

@@ -685,3 +685,42 @@ def test_extend_invariants(oracle_lib):
                 if seq_of(q0) == seq_of(t0):
                     assert q1 <= t0 or t1 <= q0
             assert 1 <= (stop & 255) <= 4 and 1 <= (stop >> 8) <= 4
+
+
+# --------------------------------------------------------- q-gram filter ---
+
+@pytest.mark.parametrize("q", [1, 3, 5, 6])
+def test_qgram_matches_bruteforce(oracle_lib, q):
+    """Section 3.2 q-gram similarity: the oracle's per-side histograms equal
+    substring counting (upper-cased, q-mers with an N dropped, target
+    reverse-complemented on strand 1) on random boxes over masked runs and
+    gaps, both strands, one and several sequences."""
+    from oracle import brute
+    g = synth.small_case(31, length=3000, n_sd=2, sd_lo=300, sd_hi=600, n_seqs=2,
+                         lower_frac=0.3, n_gaps=2, gap_len=20, rate_hi=0.05)
+    b, off = g.concat()
+    ix = oracle_lib.OracleIndex(b, off, 12, 16)
+    for r in _random_boxes(np.random.default_rng(q), off, 25, lo_len=20, hi_len=900):
+        assert ix.qgram_shared(r, q) == brute.qgram_shared(b, *r, q), r
+
+
+def test_qgram_closed_forms(oracle_lib):
+    """Q of a substring with its exact copy is its number of q-mers, also
+    against the reverse complement on strand 1; homopolymers A^a vs A^b share
+    min(a, b) - q + 1 q-mers and A vs C none; the bound matches
+    hand-evaluated points of n (1 - dG - q dM) - (n pG + 1)(q - 1)."""
+    rng = synth.rng_for(77)
+    A = synth.random_bases(rng, 4000)
+    L = len(A)
+    ix = oracle_lib.OracleIndex(*_genome([A, A.copy(), synth.revcomp(A)]), 12, 16)
+    for q in (1, 4, 6):
+        assert ix.qgram_shared((100, 1100, L + 100, L + 1100, 0), q) == 1000 - q + 1
+        assert ix.qgram_shared((100, 1100, 2 * L + L - 1100, 2 * L + L - 100, 1), q) == 1000 - q + 1
+    H = np.frombuffer(b"A" * 300 + b"C" * 200, np.uint8).copy()
+    ixh = oracle_lib.OracleIndex(*_genome([H]), 5, 3)
+    assert ixh.qgram_shared((0, 120, 150, 300, 0), 5) == 120 - 5 + 1
+    assert ixh.qgram_shared((0, 120, 300, 500, 0), 5) == 0
+    assert ixh.qgram_shared((0, 120, 300, 500, 1), 5) == 0    # rc of C-runs is G-runs
+    assert oracle_lib.qgram_bound(1000, 0.25, 4, 0.01) == pytest.approx(1000 * 0.3 - 11 * 3)
+    assert oracle_lib.qgram_bound(500, 0.10, 4, 0.0) == pytest.approx(500 * 0.6 - 3)
+    assert oracle_lib.qgram_bound(800, 0.25, 6, 0.0) < 0   # q >= 6: never rejects at delta 0.25

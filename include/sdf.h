@@ -230,6 +230,30 @@ typedef struct {
 sdf_status sdf_extend(sdf_index ix, const sdf_region *in, uint64_t n,
                       const sdf_extend_params *p, void *hip_stream, sdf_region *out);
 
+/* q-gram filter parameters (Section 3.2): max_error gives delta_M and
+ * delta_G as for the search; q in [1, 6]; gap_rate is p_G, the expected
+ * number of gaps per base pair, in [0, 1).  The paper gives neither q nor
+ * p_G. */
+typedef struct {
+    double max_error;
+    double gap_rate;
+    uint32_t q;
+    uint32_t _pad;
+} sdf_qgram_params;
+
+/* q-gram filter of Section 3.2 on n regions (host array; strand, sequences
+ * and bounds are read).  shared[i] (host, n entries) receives Q, the number
+ * of q-mers the two sides share counted with multiplicity (the sum over
+ * q-mers of the smaller occurrence count; q-mers holding an N are not
+ * counted; on strand 1 the target's q-mers are those of its reverse
+ * complement).  pass[i] (host, n entries, may be NULL) is 1 when Q is at
+ * least n (1 - delta_G - q delta_M) - (n p_G + 1)(q - 1), n the shorter
+ * side, evaluated in double.  Errors: SDF_EINVAL for NULL arguments or
+ * parameters out of range, SDF_ERANGE for a region outside the index. */
+sdf_status sdf_qgram_filter(sdf_index ix, const sdf_region *regions, uint64_t n,
+                            const sdf_qgram_params *p, void *hip_stream, uint64_t *shared,
+                            uint8_t *pass);
+
 /* Regions of a search run with SDF_EXTEND: one per candidate, in the order
  * of sdf_result_copy.  SDF_EINVAL if the search ran without the flag. */
 sdf_status sdf_result_regions(sdf_result r, sdf_region *dst, uint64_t cap, uint64_t *written);

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsdf.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["prims.hip", "index.hip", "search.hip", "estimate.hip", "extend.hip", "chain.hip", "api.hip"]
+SOURCES = ["prims.hip", "index.hip", "search.hip", "estimate.hip", "extend.hip", "qgram.hip", "chain.hip", "api.hip"]
 ARCH = os.environ.get("SDF_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

@@ -568,6 +568,58 @@ sdf_status sdf_result_regions(sdf_result r, sdf_region *dst, uint64_t cap, uint6
     });
 }
 
+// Section 3.2 bound n (1 - dG - q dM) - (n pG + 1)(q - 1), n the shorter side;
+// products are kept in separate statements (no fused multiply-add), as in
+// the oracle.
+double qgram_bound(uint64_t n, double d, uint32_t q, double pg) {
+    const double dM = d < 0.15 ? d : 0.15;
+    const double dG = d - dM;
+    const double nn = (double)n;
+    const double qdM = (double)q * dM;
+    const double a = nn * (1.0 - dG - qdM);
+    const double g = nn * pg + 1.0;
+    const double b = g * (double)(q - 1);
+    return a - b;
+}
+
+sdf_status sdf_qgram_filter(sdf_index ix, const sdf_region *in, uint64_t n,
+                            const sdf_qgram_params *p, void *hip_stream, uint64_t *shared,
+                            uint8_t *pass) {
+    return guarded([&] {
+        if (!ix || !p || (n && (!in || !shared))) throw Error{SDF_EINVAL, "NULL argument"};
+        const double d = p->max_error;
+        if (!(d > 0.0 && d < 1.0)) throw Error{SDF_EINVAL, "max_error must lie in (0, 1)"};
+        if (p->q < 1 || p->q > qgram_max_q()) throw Error{SDF_EINVAL, "q must lie in [1, 6]"};
+        if (!(p->gap_rate >= 0.0 && p->gap_rate < 1.0))
+            throw Error{SDF_EINVAL, "gap_rate must lie in [0, 1)"};
+        for (uint64_t i = 0; i < n; i++) {
+            const sdf_region &x = in[i];
+            if (x.strand > 1) throw Error{SDF_EINVAL, "strand must be 0 or 1"};
+            if (x.q_seq >= ix->nseq || x.t_seq >= ix->nseq)
+                throw Error{SDF_ERANGE, "region sequence index out of range"};
+            const uint64_t ql = ix->h_off[x.q_seq + 1] - ix->h_off[x.q_seq];
+            const uint64_t tl = ix->h_off[x.t_seq + 1] - ix->h_off[x.t_seq];
+            if (x.q_begin > x.q_end || x.q_end > ql || x.t_begin > x.t_end || x.t_end > tl)
+                throw Error{SDF_ERANGE, "region outside its sequence"};
+        }
+        if (n == 0) return;
+        SDF_HIP(hipSetDevice(ix->device));
+        const hipStream_t st = (hipStream_t)hip_stream;
+        StreamScope scope(st);
+        DevBuf<sdf_region> buf(n);
+        DevBuf<unsigned long long> out(n);
+        SDF_HIP(hipMemcpyAsync(buf.p, in, n * sizeof(sdf_region), hipMemcpyHostToDevice, st));
+        launch_qgram(ix->view(), buf.p, n, p->q, out.p, st);
+        SDF_HIP(hipMemcpyAsync(shared, out.p, n * 8, hipMemcpyDeviceToHost, st));
+        SDF_HIP(hipStreamSynchronize(st));
+        if (pass)
+            for (uint64_t i = 0; i < n; i++) {
+                const uint64_t nq = in[i].q_end - in[i].q_begin, nt = in[i].t_end - in[i].t_begin;
+                pass[i] = (double)shared[i] >= qgram_bound(std::min(nq, nt), d, p->q, p->gap_rate);
+            }
+    });
+}
+
 sdf_status sdf_extend(sdf_index ix, const sdf_region *in, uint64_t n, const sdf_extend_params *p,
                       void *hip_stream, sdf_region *out) {
     return guarded([&] {

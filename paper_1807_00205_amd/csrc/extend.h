@@ -1,4 +1,5 @@
-// Launch interface of the region extension (internal).
+// Launch interfaces of the region operations: extension and q-gram
+// similarity (internal).
 #pragma once
 #include "sdf_impl.h"
 
@@ -13,5 +14,10 @@ struct ExtStats {
 };
 void launch_extend(const IndexView &ix, const sdf_region *in, uint64_t n, double tau,
                    uint64_t max_len, sdf_region *out, ExtStats *stats, hipStream_t st);
+
+// q-gram similarity (qgram.hip): out[i] = Q of region i (device arrays).
+uint32_t qgram_max_q();
+void launch_qgram(const IndexView &ix, const sdf_region *reg, uint64_t n, uint32_t q,
+                  unsigned long long *out, hipStream_t st);
 
 }  // namespace sdf

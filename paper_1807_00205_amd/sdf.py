@@ -38,7 +38,7 @@ EXPORTS = ["sdf_last_error", "sdf_index_build", "sdf_index_info", "sdf_index_hit
            "sdf_index_entries", "sdf_index_packed", "sdf_index_free", "sdf_search",
            "sdf_search_batch", "sdf_result_count", "sdf_result_copy", "sdf_result_seed_count",
            "sdf_result_seeds", "sdf_result_timing", "sdf_result_stats", "sdf_result_free",
-           "sdf_extend", "sdf_result_regions"]
+           "sdf_extend", "sdf_result_regions", "sdf_qgram_filter"]
 
 
 def _flags(timing: bool, estimate: bool, extend: bool = False) -> int:
@@ -63,6 +63,11 @@ class _SearchParams(ctypes.Structure):
 
 class _ExtendParams(ctypes.Structure):
     _fields_ = [("max_error", ctypes.c_double), ("max_len", ctypes.c_uint64)]
+
+
+class _QgramParams(ctypes.Structure):
+    _fields_ = [("max_error", ctypes.c_double), ("gap_rate", ctypes.c_double),
+                ("q", ctypes.c_uint32), ("_pad", ctypes.c_uint32)]
 
 
 class _Span(ctypes.Structure):
@@ -130,6 +135,8 @@ def lib() -> ctypes.CDLL:
         L.sdf_result_free.argtypes = [vp]
         L.sdf_extend.restype = st
         L.sdf_extend.argtypes = [vp, vp, u64, P(_ExtendParams), vp, vp]
+        L.sdf_qgram_filter.restype = st
+        L.sdf_qgram_filter.argtypes = [vp, vp, u64, P(_QgramParams), vp, vp, vp]
         L.sdf_result_regions.restype = st
         L.sdf_result_regions.argtypes = [vp, vp, u64, P(u64)]
         assert REGION_DTYPE.itemsize == 56
@@ -303,6 +310,21 @@ class Index:
                                 ctypes.byref(p), _stream_ptr(stream),
                                 out.ctypes.data_as(ctypes.c_void_p)))
         return out
+
+    def qgram_filter(self, regions: np.ndarray, q: int, gap_rate: float,
+                     max_error: float = 0.25, stream=None):
+        """Section 3.2 q-gram filter of REGION_DTYPE regions: (shared q-mer
+        counts Q, pass flags)."""
+        inp = np.ascontiguousarray(regions)
+        assert inp.dtype == REGION_DTYPE
+        shared = np.empty(len(inp), np.uint64)
+        ok = np.empty(len(inp), np.uint8)
+        p = _QgramParams(max_error, gap_rate, q, 0)
+        _check(lib().sdf_qgram_filter(self._h, inp.ctypes.data_as(ctypes.c_void_p), len(inp),
+                                      ctypes.byref(p), _stream_ptr(stream),
+                                      shared.ctypes.data_as(ctypes.c_void_p),
+                                      ok.ctypes.data_as(ctypes.c_void_p)))
+        return shared, ok.astype(bool)
 
     def search(self, span: Tuple[int, int, int], max_error: float = 0.25, min_len: int = 1000,
                timing: bool = False, stream=None, estimate: bool = False,

@@ -253,3 +253,73 @@ def test_search_extend_config2_sampled(S, oracle_lib):
     sel = np.sort(np.random.default_rng(1).choice(len(oc), 200, replace=False))
     boxes = _boxes_from_cands(S, oc[sel])
     _same(reg[sel], _oracle_extend(orc, off, boxes, tau), "config2 sample")
+
+
+def _oracle_qgram(orc, off, regions, q, max_error, gap_rate, oracle_lib):
+    shared, ok = [], []
+    for r in regions:
+        qo, to = int(off[r["q_seq"]]), int(off[r["t_seq"]])
+        row = (qo + int(r["q_begin"]), qo + int(r["q_end"]), to + int(r["t_begin"]),
+               to + int(r["t_end"]), int(r["strand"]))
+        Q = orc.qgram_shared(row, q)
+        n = min(int(r["q_end"] - r["q_begin"]), int(r["t_end"] - r["t_begin"]))
+        shared.append(Q)
+        ok.append(Q >= oracle_lib.qgram_bound(n, max_error, q, gap_rate))
+    return np.array(shared, np.uint64), np.array(ok, bool)
+
+
+@pytest.mark.parametrize("q", [1, 4, 5, 6])
+@pytest.mark.parametrize("case", SMALL[1:3] + [None], ids=["seed2", "seed3", "tandem"])
+def test_qgram_small(S, oracle_lib, case, q):
+    """Section 3.2 q-gram filter on candidates, random boxes (some shorter
+    than q, across masked runs and gaps) and the oracle's extended regions:
+    exact shared counts and pass flags."""
+    g = _small_genome(case)
+    b, off = g.concat()
+    orc = oracle_lib.OracleIndex(b, off, 12, 16)
+    tau, _, _ = oracle_lib.params(0.25, 200, 12)
+    _, oc = orc.search(g.spans, 0.25, 200)
+    cand = _boxes_from_cands(S, oc)
+    regs = np.concatenate([cand, _oracle_extend(orc, off, cand, tau),
+                           _random_boxes(S, np.random.default_rng(q), g.seqs, 20, lo_len=1,
+                                         hi_len=700)])
+    ix = S.Index(g.seqs, 12, 16)
+    for gap_rate in (0.0, 0.01):
+        got, ok = ix.qgram_filter(regs, q, gap_rate, 0.25)
+        exp, eok = _oracle_qgram(orc, off, regs, q, 0.25, gap_rate, oracle_lib)
+        assert np.array_equal(got, exp)
+        assert np.array_equal(ok, eok)
+
+
+def test_qgram_config1_extended(S, oracle_lib):
+    """The q-gram filter (q = 5, p_G = 0.005) on every extended region of the
+    1 Mbp workload, as the oracle extends them: exact counts and flags."""
+    g = synth.config1()
+    b, off = g.concat()
+    orc = oracle_lib.OracleIndex(b, off, 12, 16)
+    tau, _, _ = oracle_lib.params(0.25, 1000, 12)
+    _, oc = orc.search(g.spans, 0.25, 1000)
+    regs = _oracle_extend(orc, off, _boxes_from_cands(S, oc), tau)
+    ix = S.Index(g.seqs, 12, 16)
+    got, ok = ix.qgram_filter(regs, 5, 0.005, 0.25)
+    exp, eok = _oracle_qgram(orc, off, regs, 5, 0.25, 0.005, oracle_lib)
+    assert np.array_equal(got, exp) and np.array_equal(ok, eok)
+    assert ok.all()  # planted duplications satisfy the error model
+
+
+def test_qgram_errors(S):
+    A = synth.random_bases(synth.rng_for(9), 2000)
+    ix = S.Index([A], 12, 16)
+    reg = np.zeros(1, S.REGION_DTYPE)
+    reg[0] = (0, 0, 0, 0, 0, 500, 1000, 1500, 0, 0)
+    for q, gr, d in ((0, 0.0, 0.25), (7, 0.0, 0.25), (4, -0.1, 0.25), (4, 0.0, 0.0)):
+        with pytest.raises(S.SdfError) as e:
+            ix.qgram_filter(reg, q, gr, d)
+        assert e.value.code == S.SDF_EINVAL
+    bad = reg.copy()
+    bad["t_end"] = 2001
+    with pytest.raises(S.SdfError) as e:
+        ix.qgram_filter(bad, 4, 0.0)
+    assert e.value.code == S.SDF_ERANGE
+    got, ok = ix.qgram_filter(np.zeros(0, S.REGION_DTYPE), 4, 0.0)
+    assert len(got) == 0

@@ -276,6 +276,19 @@ def extend_mode(ix, span, max_error, min_len, steps=3, cpu=None, cpu_sample=200)
            "region_len_median": [int(np.median(before)), int(np.median(after))],
            "region_len_max": [int(before.max()), int(after.max())] if len(reg) else [0, 0],
            "phase_stops": stops}
+    # the q-gram filter of the same section on the extended regions (q and p_G
+    # are not given by the paper: q = 5, p_G = 0.005 here)
+    ix.qgram_filter(reg[:16], 5, 0.005, max_error)
+    tq = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        _, ok = ix.qgram_filter(reg, 5, 0.005, max_error)
+        tq.append(time.perf_counter() - t0)
+    out["qgram_filter"] = {"q": 5, "gap_rate": 0.005,
+                           "ms_host_to_host": round(float(np.median(tq)) * 1e3, 3),
+                           "pass": int(ok.sum()), "regions": len(reg),
+                           "bases_read": int(((reg["q_end"] - reg["q_begin"]) +
+                                              (reg["t_end"] - reg["t_begin"])).sum())}
     if cpu:
         rng = np.random.default_rng(1)
         oc, off = cpu["cands"], cpu["off"]

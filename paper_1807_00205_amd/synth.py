@@ -610,3 +610,49 @@ def tandem_case(seed: int, length: int = 20_000, n_arrays: int = 12, unit_lo: in
             s[b:b + len(arr)] = arr[: len(s) - b]
     return Genome(g.seqs, g.truth, [(i, 0, len(x)) for i, x in enumerate(g.seqs)],
                   "tandem%d" % seed)
+
+
+def sd_pair(rng: np.random.Generator, length: int, delta: float, gap_rate: float = 0.005,
+            split: str = "bounded"):
+    """One trial of the simulated-sensitivity experiment (Section 4.1.1): a
+    uniformly random sequence X of ``length`` bases and a duplicate Y of it
+    whose error is split into small mutations (delta_M) and gaps (delta_G),
+    both below m = min(0.15, delta) (Section 2.1).  split="bounded" (the SD
+    criteria: total error at most delta): delta_M uniform in [0, m], delta_G
+    uniform in [0, min(m, delta - delta_M)].  split="exact" (total error
+    exactly delta): delta_M uniform in [max(0, delta - m), m], delta_G =
+    delta - delta_M.  Small mutations are substitutions at rate delta_M; gaps
+    open at ``gap_rate`` per base (the Section 2.1 bound on large gaps,
+    0.005) as an insertion or a deletion (even odds) of geometric length with
+    mean delta_G / gap_rate, so gap bases make up a fraction delta_G on
+    average.  Returns (X, Y, delta_M, delta_G)."""
+    m = min(0.15, delta)
+    if split == "exact":
+        dm = float(rng.uniform(max(0.0, delta - m), m))
+        dg = delta - dm
+    else:
+        dm = float(rng.uniform(0.0, m))
+        dg = float(rng.uniform(0.0, min(m, delta - dm)))
+    x = random_bases(rng, length)
+    y = x.copy()
+    sub = np.nonzero(rng.random(length) < dm)[0]
+    if sub.size:
+        y[sub] = _ACGT[(_IDX[y[sub]] + rng.integers(1, 4, size=sub.size, dtype=np.uint8)) % 4]
+    if dg > 0:
+        mean = max(1.0, dg / gap_rate)
+        ev = np.nonzero(rng.random(length) < gap_rate)[0]
+        lens = rng.geometric(1.0 / mean, size=ev.size)
+        ins = rng.random(ev.size) < 0.5
+        keep = np.ones(length, dtype=bool)
+        for p, ln in zip(ev[~ins], lens[~ins]):
+            keep[p:p + ln] = False
+        pieces, last = [], 0
+        for p, ln in sorted(zip(ev[ins].tolist(), lens[ins].tolist())):
+            if not keep[p]:
+                continue
+            pieces.append(y[last:p + 1][keep[last:p + 1]])
+            pieces.append(random_bases(rng, int(ln)))
+            last = p + 1
+        pieces.append(y[last:][keep[last:]])
+        y = np.concatenate(pieces)
+    return x, y, dm, dg

@@ -27,13 +27,14 @@
 //     its successor or predecessor), and checks m >= ceil(tau s) after each
 //     step; a refused step is undone.  Steps at which no minimizer enters
 //     keep the previous state and its verdict.
-// The horizon of one attempt is max(h0, longer side / 4) steps per phase.  A
+// The horizon of one attempt is max(h0, longer side) steps per phase.  A
 // phase that runs through it stops at its last step; the next attempt
 // gathers and ranks again around the region reached and continues the same
 // phase from there (the state is a function of the region, so nothing is
 // repeated).
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 
 #include "extend.h"
@@ -61,7 +62,7 @@ struct ExtArgs {
     sdf_region *out;
     double tau;
     uint64_t max_len;
-    uint64_t h0;            // horizon per attempt: max(h0, longer side / 4) steps
+    uint64_t h0;            // horizon per attempt: max(h0, longer side / hdiv) steps
     uint32_t *work;         // region counter
     uint64_t *tmp;          // per workgroup: ecap keys
     uint32_t *rank;         // per workgroup: ecap
@@ -69,6 +70,7 @@ struct ExtArgs {
     uint64_t ecap;
     uint32_t lds_words;     // cells kept in LDS up to 8 * lds_words ranks
     uint32_t batch_min;     // fewest insertions applied as one batch (0: never)
+    uint32_t hdiv;          // horizon per attempt: at least the longer side / hdiv
     uint32_t *err;
     unsigned long long *stats;  // [0] insertions, [1] continued attempts, [2] ranks,
                                 // [3] ranking ticks, [4] event-loop ticks, [5] slowest region
@@ -520,13 +522,26 @@ __device__ __forceinline__ uint64_t run_phase(const ExtArgs &a, uint32_t *nib, u
                                     ? __builtin_amdgcn_readlane(cq.vstep, cq.fill - 1) : INF;
             const uint64_t bt = ct.next + ct.fill < ct.count
                                     ? __builtin_amdgcn_readlane(ct.vstep, ct.fill - 1) : INF;
-            const uint64_t S = std::min(std::min(bq, bt), known);
+            uint64_t S = std::min(std::min(bq, bt), known);
             const uint32_t lane = threadIdx.x & 63;
-            const uint32_t nq = (uint32_t)__popcll(
-                __ballot(lane >= cq.at && lane < cq.fill && (uint64_t)cq.vstep <= S));
-            const uint32_t nt = (uint32_t)__popcll(
-                __ballot(lane >= ct.at && lane < ct.fill && (uint64_t)ct.vstep <= S));
+            auto held = [&](const EvCursor &c) {
+                return (uint32_t)__popcll(
+                    __ballot(lane >= c.at && lane < c.fill && (uint64_t)c.vstep <= S));
+            };
+            uint32_t nq = held(cq), nt = held(ct);
             const int64_t slack = (int64_t)e.m - (int64_t)(uint32_t)ceil(a.tau * (double)e.s);
+            // as many insertions as the slack covers: cut S back to the step of
+            // the middle held event of the longer list until they fit
+            for (int it = 0; it < 12 && 3 * (int64_t)(nq + nt) > slack; it++) {
+                if (nq >= nt && nq > 1)
+                    S = __builtin_amdgcn_readlane(cq.vstep, cq.at + nq / 2 - 1);
+                else if (nt > 1)
+                    S = __builtin_amdgcn_readlane(ct.vstep, ct.at + nt / 2 - 1);
+                else
+                    break;
+                nq = held(cq);
+                nt = held(ct);
+            }
             if (nq + nt >= a.batch_min && slack >= 3 * (int64_t)(nq + nt)) {
                 if (!apply_batch(nib, nw, cq, nq, ct, nt, o, e)) { bad = true; code = STOP_ESTIMATE; return last; }
                 cq.at += nq;
@@ -592,9 +607,10 @@ __device__ void rank_chunk(Shared &L, const uint64_t *src, uint64_t b, uint64_t 
     for (uint32_t i = threadIdx.x; i < P; i += XT) ck[i] = i < cnt ? src[b + i] : ~0ull;
     __syncthreads();
     for (uint32_t size = 2; size <= P; size <<= 1) {
-        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+        for (uint32_t stride = size >> 1, sh = (uint32_t)__builtin_ctz(size) - 1; stride > 0;
+             stride >>= 1, sh--) {
             for (uint32_t i = threadIdx.x; i < P / 2; i += XT) {
-                const uint32_t lo = 2 * stride * (i / stride) + (i % stride), hi = lo + stride;
+                const uint32_t lo = ((i >> sh) << (sh + 1)) | (i & (stride - 1)), hi = lo + stride;
                 const bool asc = (lo & size) == 0;
                 const uint64_t x = ck[lo], y = ck[hi];
                 if ((x > y) == asc) { ck[lo] = y; ck[hi] = x; }
@@ -657,9 +673,10 @@ __device__ bool rank_big(Shared &L, const uint64_t *src, uint64_t b, uint64_t e,
     for (uint32_t i = D + threadIdx.x; i < P; i += XT) list[i] = ~0ull;
     __syncthreads();
     for (uint32_t size = 2; size <= P; size <<= 1) {
-        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+        for (uint32_t stride = size >> 1, sh = (uint32_t)__builtin_ctz(size) - 1; stride > 0;
+             stride >>= 1, sh--) {
             for (uint32_t i = threadIdx.x; i < P / 2; i += XT) {
-                const uint32_t lo = 2 * stride * (i / stride) + (i % stride), hi = lo + stride;
+                const uint32_t lo = ((i >> sh) << (sh + 1)) | (i & (stride - 1)), hi = lo + stride;
                 const bool asc = (lo & size) == 0;
                 const uint64_t x = list[lo], y = list[hi];
                 if ((x > y) == asc) { list[lo] = y; list[hi] = x; }
@@ -776,7 +793,8 @@ __global__ void __launch_bounds__(XT) k_extend(ExtArgs a) {
         for (;;) {  // attempts: gather, rank, run until both phases stop
             const uint64_t t_att = wall_clock64();
             const uint64_t longer = std::max(r[1] - r[0], r[3] - r[2]);
-            const uint64_t want = std::max<uint64_t>(1, std::min(hcut, std::max(a.h0, longer / 4)));
+            const uint64_t want =
+                std::max<uint64_t>(1, std::min(hcut, std::max(a.h0, longer / a.hdiv)));
             uint64_t lim_f;
             uint32_t code_f;
             phase_limit(r, qlo, qhi, tlo, thi, same, phase_of(0, o), a.max_len, lim_f, code_f);
@@ -1028,15 +1046,18 @@ void launch_extend(const IndexView &ix, const sdf_region *in, uint64_t n, double
     SDF_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     // test hooks: SDF_EXT_H0 sets the horizon, SDF_EXT_LDS_WORDS the cells
     // kept in LDS (0 keeps L in global memory), SDF_EXT_ECAP the elements per
-    // workgroup, SDF_EXT_BATCH_MIN the smallest batch (0: one step at a time)
-    // each attempt gathers max(h0, longer side / 4) steps per phase; a phase
+    // workgroup, SDF_EXT_BATCH_MIN the smallest batch (0: one step at a time),
+    // SDF_EXT_HDIV the horizon as a fraction of the longer side
+    // each attempt gathers max(h0, longer side / hdiv) steps per phase; a phase
     // that runs through them continues in the next attempt
     uint64_t h0 = 16384, ecap = 1ull << 18;
     uint32_t ldsw = LDS_WORDS;
     if (const char *v = std::getenv("SDF_EXT_H0")) h0 = std::strtoull(v, nullptr, 10);
     if (const char *v = std::getenv("SDF_EXT_LDS_WORDS"))
         ldsw = std::min<uint32_t>(LDS_WORDS, (uint32_t)std::strtoul(v, nullptr, 10));
-    uint32_t batch_min = 4;
+    uint32_t batch_min = 4, hdiv = 1;
+    if (const char *v = std::getenv("SDF_EXT_HDIV"))
+        hdiv = std::max<uint32_t>(1, (uint32_t)std::strtoul(v, nullptr, 10));
     if (const char *v = std::getenv("SDF_EXT_BATCH_MIN"))
         batch_min = (uint32_t)std::strtoul(v, nullptr, 10);
     if (const char *v = std::getenv("SDF_EXT_ECAP"))
@@ -1064,6 +1085,7 @@ void launch_extend(const IndexView &ix, const sdf_region *in, uint64_t n, double
     a.ecap = ecap;
     a.lds_words = ldsw;
     a.batch_min = batch_min;
+    a.hdiv = hdiv;
     a.err = work.p + 1;
     a.stats = cnt.p;
     k_extend<<<(unsigned)grid, XT, 0, st>>>(a);
@@ -1078,7 +1100,9 @@ void launch_extend(const IndexView &ix, const sdf_region *in, uint64_t n, double
     if (herr & XE_HASH)
         throw Error{SDF_EINTERNAL, "extend: more than 1024 distinct hashes share 12 hash bits"};
     if (herr & XE_STATE) throw Error{SDF_EINTERNAL, "extend: inconsistent ordered set"};
-    if (stats) {
+    if (stats || std::getenv("SDF_EXT_STATS")) {
+        ExtStats local;
+        if (!stats) stats = &local;
         int khz = 0;
         SDF_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
         const double us = khz > 0 ? 1e3 / (double)khz : 0.0;
@@ -1088,6 +1112,12 @@ void launch_extend(const IndexView &ix, const sdf_region *in, uint64_t n, double
         stats->rank_us = (unsigned long long)((double)hc[3] * us);
         stats->loop_us = (unsigned long long)((double)hc[4] * us);
         stats->slowest_us = (unsigned long long)((double)hc[5] * us);
+        if (std::getenv("SDF_EXT_STATS"))
+            fprintf(stderr,
+                    "[sdf extend] regions=%llu insertions=%llu continued=%llu ranks=%llu "
+                    "rank_ms=%.2f phase_ms=%.2f slowest_ms=%.2f\n",
+                    (unsigned long long)n, stats->events, stats->restarts, stats->ranks,
+                    stats->rank_us / 1e3, stats->loop_us / 1e3, stats->slowest_us / 1e3);
     }
 }
 

@@ -73,7 +73,8 @@ struct ExtArgs {
     uint32_t hdiv;          // horizon per attempt: at least the longer side / hdiv
     uint32_t *err;
     unsigned long long *stats;  // [0] insertions, [1] continued attempts, [2] ranks,
-                                // [3] ranking ticks, [4] event-loop ticks, [5] slowest region
+                                // [3] ranking ticks, [4] event-loop ticks, [5] slowest region,
+                                // [6] buckets ranked through the hash set
 };
 
 struct Shared {
@@ -661,8 +662,10 @@ __device__ bool rank_big(Shared &L, const uint64_t *src, uint64_t b, uint64_t e,
         }
     }
     __syncthreads();
-    if (L.flag || L.cnt > BIGD) return false;
+    const bool over = L.flag || L.cnt > BIGD;
     const uint32_t D = L.cnt;
+    __syncthreads();  // every thread has read the count before it is reset
+    if (over) return false;
     uint32_t P = 1;
     while (P < D) P <<= 1;
     if (threadIdx.x == 0) L.cnt = 0;
@@ -920,7 +923,9 @@ __global__ void __launch_bounds__(XT) k_extend(ExtArgs a) {
                     if (c1 == c0) continue;
                     if (c1 - c0 <= CH) {
                         rank_chunk(L, tmp, c0, c1, rank);
-                    } else if (!rank_big(L, tmp, c0, c1, rank)) {
+                    } else if (rank_big(L, tmp, c0, c1, rank)) {
+                        if (threadIdx.x == 0) atomicAdd(&a.stats[6], 1ull);
+                    } else {
                         if (threadIdx.x == 0) { atomicOr(a.err, (uint32_t)XE_HASH); L.flag = 1; }
                         __syncthreads();
                         break;
@@ -1067,9 +1072,9 @@ void launch_extend(const IndexView &ix, const sdf_region *in, uint64_t n, double
     DevBuf<uint64_t> tmp(grid * ecap);
     DevBuf<uint32_t> rank(grid * ecap), gnib(grid * (ecap / 8 + 1));
     DevBuf<uint32_t> work(2);
-    DevBuf<unsigned long long> cnt(6);
+    DevBuf<unsigned long long> cnt(7);
     SDF_HIP(hipMemsetAsync(work.p, 0, 8, st));
-    SDF_HIP(hipMemsetAsync(cnt.p, 0, 48, st));
+    SDF_HIP(hipMemsetAsync(cnt.p, 0, 56, st));
     ExtArgs a;
     a.ix = ix;
     a.in = in;
@@ -1091,9 +1096,9 @@ void launch_extend(const IndexView &ix, const sdf_region *in, uint64_t n, double
     k_extend<<<(unsigned)grid, XT, 0, st>>>(a);
     SDF_HIP(hipGetLastError());
     uint32_t herr = 0;
-    unsigned long long hc[6] = {0, 0, 0, 0, 0, 0};
+    unsigned long long hc[7] = {0, 0, 0, 0, 0, 0, 0};
     SDF_HIP(hipMemcpyAsync(&herr, work.p + 1, 4, hipMemcpyDeviceToHost, st));
-    SDF_HIP(hipMemcpyAsync(hc, cnt.p, 48, hipMemcpyDeviceToHost, st));
+    SDF_HIP(hipMemcpyAsync(hc, cnt.p, 56, hipMemcpyDeviceToHost, st));
     SDF_HIP(hipStreamSynchronize(st));
     if (herr & XE_CAP)
         throw Error{SDF_EINTERNAL, "extend: a region's windows hold more minimizers than its scratch"};
@@ -1115,9 +1120,10 @@ void launch_extend(const IndexView &ix, const sdf_region *in, uint64_t n, double
         if (std::getenv("SDF_EXT_STATS"))
             fprintf(stderr,
                     "[sdf extend] regions=%llu insertions=%llu continued=%llu ranks=%llu "
-                    "rank_ms=%.2f phase_ms=%.2f slowest_ms=%.2f\n",
+                    "rank_ms=%.2f phase_ms=%.2f slowest_ms=%.2f big_buckets=%llu\n",
                     (unsigned long long)n, stats->events, stats->restarts, stats->ranks,
-                    stats->rank_us / 1e3, stats->loop_us / 1e3, stats->slowest_us / 1e3);
+                    stats->rank_us / 1e3, stats->loop_us / 1e3, stats->slowest_us / 1e3,
+                    hc[6]);
     }
 }
 

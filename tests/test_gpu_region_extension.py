@@ -323,3 +323,33 @@ def test_qgram_errors(S):
     assert e.value.code == S.SDF_ERANGE
     got, ok = ix.qgram_filter(np.zeros(0, S.REGION_DTYPE), 4, 0.0)
     assert len(got) == 0
+
+
+def test_extend_tandem_array_hash_set(S, oracle_lib, monkeypatch, capfd):
+    """A 100 kbp tandem array of a 17-base unit (two distinct minimizer
+    hashes repeated thousands of times) and its 1%-mutated copy: ranking
+    meets buckets of more than 4,096 keys and goes through the LDS hash set;
+    the regions still equal the oracle's."""
+    rng = synth.rng_for(404)
+    unit = synth.random_bases(rng, 17)
+    s0 = np.concatenate([synth.random_bases(rng, 3000), np.tile(unit, 6000),
+                         synth.random_bases(rng, 3000)])
+    s1 = s0.copy()
+    sub = np.nonzero(rng.random(len(s1)) < 0.01)[0]
+    acgt = np.frombuffer(b"ACGT", np.uint8)
+    s1[sub] = acgt[(np.searchsorted(acgt, s1[sub]) + 1) % 4]
+    b = np.concatenate([s0, s1])
+    off = np.array([0, len(s0), len(s0) + len(s1)], np.uint64)
+    orc = oracle_lib.OracleIndex(b, off, 12, 16)
+    tau, _, _ = oracle_lib.params(0.25, 1000, 12)
+    boxes = np.zeros(3, S.REGION_DTYPE)
+    boxes[0] = (0, 0, 1, 0, 20000, 22000, 20000, 22000, 0, 0)
+    boxes[1] = (0, 0, 1, 0, 50000, 52000, 50300, 52300, 0, 0)
+    boxes[2] = (0, 1, 0, 0, 4000, 9000, 70000, 75000, 0, 0)
+    ix = S.Index([s0, s1], 12, 16)
+    monkeypatch.setenv("SDF_EXT_STATS", "1")
+    got = ix.extend(boxes, 0.25)
+    err = capfd.readouterr().err
+    _same(got, _oracle_extend(orc, off, boxes, tau), "tandem array")
+    big = [int(w.split("=")[1]) for w in err.split() if w.startswith("big_buckets=")]
+    assert big and big[-1] > 0, err

@@ -71,6 +71,7 @@ struct ExtArgs {
     uint32_t lds_words;     // cells kept in LDS up to 8 * lds_words ranks
     uint32_t batch_min;     // fewest insertions applied as one batch (0: never)
     uint32_t hdiv;          // horizon per attempt: at least the longer side / hdiv
+    uint64_t hb0;           // backward horizon while the forward phase is pending (0: same)
     uint32_t *err;
     unsigned long long *stats;  // [0] insertions, [1] continued attempts, [2] ranks,
                                 // [3] ranking ticks, [4] event-loop ticks, [5] slowest region,
@@ -804,7 +805,11 @@ __global__ void __launch_bounds__(XT) k_extend(ExtArgs a) {
             const uint64_t Hf = dir == 0 ? std::min(want, lim_f) : 0;
             uint64_t ub_b = std::min(r[0] - qlo, o == 0 ? r[2] - tlo : thi - r[3]);
             ub_b = std::min(ub_b, a.max_len - longer);
-            const uint64_t Hb = std::min(want, ub_b);
+            // the backward phase starts from a state the forward phase has driven
+            // to the threshold and seldom goes far: while the forward phase is
+            // pending only a short backward horizon is gathered (a backward phase
+            // that runs through it continues in the next attempt)
+            const uint64_t Hb = std::min(dir == 0 && a.hb0 ? std::min(want, a.hb0) : want, ub_b);
             // position ranges [pa, pe] of the six element lists: both windows,
             // then the forward and the backward minimizers that can enter
             int64_t pa[6], pe[6];  // (indexed by constants only: registers)
@@ -1052,7 +1057,8 @@ void launch_extend(const IndexView &ix, const sdf_region *in, uint64_t n, double
     // test hooks: SDF_EXT_H0 sets the horizon, SDF_EXT_LDS_WORDS the cells
     // kept in LDS (0 keeps L in global memory), SDF_EXT_ECAP the elements per
     // workgroup, SDF_EXT_BATCH_MIN the smallest batch (0: one step at a time),
-    // SDF_EXT_HDIV the horizon as a fraction of the longer side
+    // SDF_EXT_HDIV the horizon as a fraction of the longer side, SDF_EXT_HB0 the
+    // backward horizon gathered while the forward phase is pending
     // each attempt gathers max(h0, longer side / hdiv) steps per phase; a phase
     // that runs through them continues in the next attempt
     uint64_t h0 = 16384, ecap = 1ull << 18;
@@ -1061,6 +1067,8 @@ void launch_extend(const IndexView &ix, const sdf_region *in, uint64_t n, double
     if (const char *v = std::getenv("SDF_EXT_LDS_WORDS"))
         ldsw = std::min<uint32_t>(LDS_WORDS, (uint32_t)std::strtoul(v, nullptr, 10));
     uint32_t batch_min = 4, hdiv = 1;
+    uint64_t hb0 = 512;
+    if (const char *v = std::getenv("SDF_EXT_HB0")) hb0 = std::strtoull(v, nullptr, 10);
     if (const char *v = std::getenv("SDF_EXT_HDIV"))
         hdiv = std::max<uint32_t>(1, (uint32_t)std::strtoul(v, nullptr, 10));
     if (const char *v = std::getenv("SDF_EXT_BATCH_MIN"))
@@ -1091,6 +1099,7 @@ void launch_extend(const IndexView &ix, const sdf_region *in, uint64_t n, double
     a.lds_words = ldsw;
     a.batch_min = batch_min;
     a.hdiv = hdiv;
+    a.hb0 = hb0;
     a.err = work.p + 1;
     a.stats = cnt.p;
     k_extend<<<(unsigned)grid, XT, 0, st>>>(a);

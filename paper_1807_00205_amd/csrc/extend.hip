@@ -26,7 +26,10 @@
 //     and m up to date per insertion (v moves at most one element of L, to
 //     its successor or predecessor), and checks m >= ceil(tau s) after each
 //     step; a refused step is undone.  Steps at which no minimizer enters
-//     keep the previous state and its outcome.
+//     keep the previous state and its outcome.  While the slack m - ceil(tau
+//     s) is at least three per insertion, a run of insertions cannot contain
+//     a refused step and is applied as one batch (cells set in parallel, v
+//     moved by the count of new elements below and above it).
 // The horizon of one attempt is max(h0, longer side) steps per phase.  A
 // phase that runs through it stops at its last step; the next attempt
 // gathers and ranks again around the region reached and continues the same

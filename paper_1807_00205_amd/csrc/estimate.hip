@@ -26,35 +26,40 @@
 namespace sdf {
 
 constexpr int EW = 3;         // runs (waves) per workgroup
-constexpr int EAMAX = 1024;   // minimizers of one window a wave holds
-constexpr int TCAP = 512;     // target minimizers of one run held in LDS
+// A first launch holds windows of up to 256 minimizers and runs of up to 256
+// target minimizers in LDS (5.8 KB per wave, 27 waves per CU); a run that
+// does not fit is handed to a second launch with room for 1,024 and 512.
+constexpr int AMAX_S = 256, TCAP_S = 256;
+constexpr int AMAX_L = 1024, TCAP_L = 512;
 constexpr uint16_t TR_IN = 0x8000, TR_SHARED = 0x4000, TR_RANK = 0x3FF;
 
+template <int AMAX, int TC>
 struct EstWave {
+    static constexpr int amax = AMAX, tcap = TC;
     union {
-        uint64_t key[EAMAX];  // query sort: hash << 32 | index in the window
-        struct {              // the run's target minimizers (positions jf .. jl + n - k)
-            uint32_t tp[TCAP], th[TCAP];
-            uint16_t tr[TCAP];    // TR_IN: hash in W_i (rank in TR_RANK); TR_SHARED: pairs in o
-            uint32_t out[TCAP];   // hashes of one target window outside W_i
-            uint8_t first[TCAP];  // first of its value among them
+        uint64_t key[AMAX];  // query sort: hash << 32 | index in the window
+        struct {             // the run's target minimizers (positions jf .. jl + n - k)
+            uint32_t tp[TC], th[TC];
+            uint16_t tr[TC];     // TR_IN: hash in W_i (rank in TR_RANK); TR_SHARED: pairs in o
+            uint32_t out[TC];    // hashes of one target window outside W_i
+            uint8_t first[TC];   // first of its value among them
         } run;
-        struct {              // a run too long for `run`: one target window at a time
-            uint32_t out[EAMAX];
-            uint8_t first[EAMAX];
+        struct {             // a run too long for `run`: one target window at a time
+            uint32_t out[AMAX];
+            uint8_t first[AMAX];
         } big;
     } u;
-    uint32_t ahash[EAMAX];    // distinct query hashes, ascending (W_i)
-    uint32_t acnt[EAMAX];     // eligible occurrences per hash: strand 0 low 16 bits, strand 1 high
-    uint64_t cbits[EAMAX / 64];  // shared hashes by rank in W_i
+    uint32_t ahash[AMAX];    // distinct query hashes, ascending (W_i)
+    uint32_t acnt[AMAX];     // eligible occurrences per hash: strand 0 low 16 bits, strand 1 high
+    uint64_t cbits[AMAX / 64];  // shared hashes by rank in W_i
 };
-static_assert(sizeof(((EstWave *)nullptr)->u.run) <= sizeof(uint64_t) * EAMAX, "run overlay");
 
 // A target occurrence (minimizer index tm, strand b, hash of rank r in W_i)
 // pairs in orientation o when the window holds an eligible query occurrence
 // of strand b ^ o other than itself; it can be itself only for o = 0 and tm
 // inside the query window's minimizer range [q0, q0 + na).
-__device__ __forceinline__ bool pairs(const EstWave &L, uint32_t r, uint32_t b, uint32_t o,
+template <class W>
+__device__ __forceinline__ bool pairs(const W &L, uint32_t r, uint32_t b, uint32_t o,
                                       uint64_t tm, uint64_t q0, uint32_t na) {
     const uint32_t a = b ^ o;
     const uint32_t c = (L.acnt[r] >> (16 * a)) & 0xFFFFu;
@@ -115,7 +120,8 @@ __device__ __forceinline__ uint32_t rank_below(const uint32_t *ahash, uint32_t s
 
 // From the shared marks (cbits) and the nb hashes of W_j outside W_i in
 // out[0, nb): c when it cannot beat `beat`, else m.
-__device__ uint32_t estimate_finish(EstWave &L, const uint32_t *out, uint8_t *first, uint32_t s,
+template <class W>
+__device__ uint32_t estimate_finish(W &L, const uint32_t *out, uint8_t *first, uint32_t s,
                                     uint32_t nb, bool have, uint32_t beat, uint32_t reg_cap) {
     const uint32_t lane = e_lane();
     const uint32_t nw = (s + 63) >> 6;
@@ -193,8 +199,9 @@ __device__ uint32_t estimate_finish(EstWave &L, const uint32_t *out, uint8_t *fi
 // starting at minimizer tj (position j).  A candidate whose shared count c
 // is not above `beat` cannot win (m <= c, and ties go to the earlier j):
 // then c is returned without the estimate.  Returns NONE32 when the window
-// holds more than EAMAX minimizers outside W_i.
-__device__ uint32_t estimate_at(const IndexView &ix, EstWave &L, uint32_t s, uint32_t o,
+// holds more minimizers outside W_i than the wave can hold.
+template <class W>
+__device__ uint32_t estimate_at(const IndexView &ix, W &L, uint32_t s, uint32_t o,
                                 uint64_t tj, uint64_t jend, bool have, uint32_t beat,
                                 uint32_t reg_cap, uint64_t q0, uint32_t na) {
     const uint32_t lane = e_lane();
@@ -222,18 +229,19 @@ __device__ uint32_t estimate_at(const IndexView &ix, EstWave &L, uint32_t s, uin
         }
         const uint64_t bm = __ballot(outside);
         const uint32_t at = nb + (uint32_t)__popcll(bm & ltmask);
-        if (outside && at < EAMAX) out[at] = h;
+        if (outside && at < W::amax) out[at] = h;
         nb += (uint32_t)__popcll(bm);
         if (__ballot(v) != ~0ull) break;
-        if (nb > EAMAX) break;
+        if (nb > W::amax) break;
     }
-    if (nb > EAMAX) return NONE32;
+    if (nb > W::amax) return NONE32;
     return estimate_finish(L, out, L.u.big.first, s, nb, have, beat, reg_cap);
 }
 
 // The same for the target window u.run.tp[xs, xe) of the run's minimizers held
 // in LDS (classified once per run).
-__device__ uint32_t estimate_lds(EstWave &L, uint32_t s, uint32_t xs, uint32_t xe, bool have,
+template <class W>
+__device__ uint32_t estimate_lds(W &L, uint32_t s, uint32_t xs, uint32_t xe, bool have,
                                  uint32_t beat, uint32_t reg_cap) {
     const uint32_t lane = e_lane();
     const uint64_t ltmask = lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -255,20 +263,30 @@ __device__ uint32_t estimate_lds(EstWave &L, uint32_t s, uint32_t xs, uint32_t x
         if (outside) out[nb + (uint32_t)__popcll(bm & ltmask)] = L.u.run.th[x];
         nb += (uint32_t)__popcll(bm);
     }
-    return estimate_finish(L, out, L.u.run.first, s, nb, have, beat, reg_cap);  // nb <= TCAP
+    return estimate_finish(L, out, L.u.run.first, s, nb, have, beat, reg_cap);  // nb <= W::tcap
 }
 
+// FIRST: run r = the wave's index; a run that does not fit (window above
+// amax_rt minimizers, or a target window with more outside hashes than the
+// wave holds) is appended to `over` instead.  Otherwise the runs are those
+// listed in `list`, and not fitting is an error.
+template <int AMAX, int TC, bool FIRST>
 __global__ void __launch_bounds__(EW * 64) k_estimate_runs(IndexView ix, const uint32_t *runs,
-                                                            uint64_t nruns, uint32_t n,
-                                                            const uint16_t *T, uint32_t *seeds,
-                                                            uint64_t cap, unsigned long long *nseeds,
+                                                            uint64_t nruns, const uint32_t *list,
+                                                            uint32_t n, const uint16_t *T,
+                                                            uint32_t *seeds, uint64_t cap,
+                                                            unsigned long long *nseeds,
                                                             uint32_t *err, uint32_t lds_cap,
-                                                            uint32_t reg_cap) {
-    __shared__ EstWave W[EW];
+                                                            uint32_t reg_cap, uint32_t amax_rt,
+                                                            uint32_t *over,
+                                                            unsigned long long *nover) {
+    using Wave = EstWave<AMAX, TC>;
+    __shared__ Wave W[EW];
     const uint32_t lane = e_lane(), wv = threadIdx.x >> 6;
-    EstWave &L = W[wv];
-    const uint64_t r = (uint64_t)blockIdx.x * EW + wv;
-    if (r >= nruns) return;  // whole wave; no workgroup barrier below
+    Wave &L = W[wv];
+    const uint64_t slot = (uint64_t)blockIdx.x * EW + wv;
+    if (slot >= nruns) return;  // whole wave; no workgroup barrier below
+    const uint64_t r = FIRST ? slot : list[slot];
     const uint64_t ltmask = lane ? (~0ull >> (64 - lane)) : 0ull;
     const uint32_t *rec = runs + r * 6;
     const uint32_t qid = rec[0], i = rec[1], jf = rec[2], o = rec[3], jl = rec[4], s = rec[5];
@@ -282,12 +300,16 @@ __global__ void __launch_bounds__(EW * 64) k_estimate_runs(IndexView ix, const u
         const uint64_t m = q0 + na + lane;
         const bool v = m < ix.nm && (uint64_t)ix.mpos[m] <= qend;
         const uint64_t bv = __ballot(v);  // a prefix of the lanes
-        if (v && na + lane < EAMAX) L.u.key[na + lane] = ((uint64_t)ix.mhash[m] << 32) | (na + lane);
+        if (v && na + lane < AMAX) L.u.key[na + lane] = ((uint64_t)ix.mhash[m] << 32) | (na + lane);
         na += (uint32_t)__popcll(bv);
-        if (bv != ~0ull || na > EAMAX) break;
+        if (bv != ~0ull || na > amax_rt) break;
     }
-    if (na > EAMAX || s == 0 || s > na) {
-        if (lane == 0) atomicOr(err, na > EAMAX ? 1u : 2u);
+    if (FIRST && na > amax_rt) {  // the second launch takes it
+        if (lane == 0) over[atomicAdd(nover, 1ull)] = (uint32_t)r;
+        return;
+    }
+    if (na > amax_rt || s == 0 || s > na) {
+        if (lane == 0) atomicOr(err, na > amax_rt ? 1u : 2u);
         return;
     }
     uint32_t m2 = 1;
@@ -406,7 +428,10 @@ __global__ void __launch_bounds__(EW * 64) k_estimate_runs(IndexView ix, const u
             const uint32_t m =
                 estimate_at(ix, L, s, o, base + l, (uint64_t)j + n - k, have, best_m, reg_cap, q0, na);
             if (m == NONE32) {
-                if (lane == 0) atomicOr(err, 1u);
+                if (lane == 0) {
+                    if (FIRST) over[atomicAdd(nover, 1ull)] = (uint32_t)r;
+                    else atomicOr(err, 1u);
+                }
                 return;
             }
             if (!have || m > best_m) {
@@ -430,17 +455,33 @@ void launch_estimate_runs(const IndexView &ix, const uint32_t *runs, uint64_t nr
                           const uint16_t *T, uint32_t *seeds, uint64_t cap,
                           unsigned long long *nseeds, uint32_t *err, hipStream_t st) {
     if (nruns == 0) return;
-    const uint64_t blocks = (nruns + EW - 1) / EW;
     // test hooks: SDF_EST_LDS_CAP / SDF_EST_REG_CAP lower the sizes held in
-    // LDS and registers (0 sends every run down the general paths)
-    uint32_t lds_cap = TCAP, reg_cap = 128;
+    // LDS and registers (0 sends every run down the general paths);
+    // SDF_EST_FIRST_AMAX lowers the window size of the first launch (0 hands
+    // every run to the second)
+    uint32_t lds_cap = TCAP_L, reg_cap = 128, amax_s = AMAX_S;
     if (const char *v = std::getenv("SDF_EST_LDS_CAP"))
-        lds_cap = std::min<uint32_t>(TCAP, (uint32_t)std::strtoul(v, nullptr, 10));
+        lds_cap = std::min<uint32_t>(TCAP_L, (uint32_t)std::strtoul(v, nullptr, 10));
     if (const char *v = std::getenv("SDF_EST_REG_CAP"))
         reg_cap = std::min<uint32_t>(128, (uint32_t)std::strtoul(v, nullptr, 10));
-    k_estimate_runs<<<(unsigned)blocks, EW * 64, 0, st>>>(ix, runs, nruns, n, T, seeds, cap, nseeds,
-                                                         err, lds_cap, reg_cap);
+    if (const char *v = std::getenv("SDF_EST_FIRST_AMAX"))
+        amax_s = std::min<uint32_t>(AMAX_S, (uint32_t)std::strtoul(v, nullptr, 10));
+    DevBuf<uint32_t> over(nruns);
+    DevBuf<unsigned long long> nover(1);
+    SDF_HIP(hipMemsetAsync(nover.p, 0, 8, st));
+    k_estimate_runs<AMAX_S, TCAP_S, true><<<(unsigned)((nruns + EW - 1) / EW), EW * 64, 0, st>>>(
+        ix, runs, nruns, nullptr, n, T, seeds, cap, nseeds, err, std::min<uint32_t>(lds_cap, TCAP_S),
+        reg_cap, amax_s, over.p, nover.p);
     SDF_HIP(hipGetLastError());
+    unsigned long long no = 0;
+    SDF_HIP(hipMemcpyAsync(&no, nover.p, 8, hipMemcpyDeviceToHost, st));
+    SDF_HIP(hipStreamSynchronize(st));
+    if (no == 0) return;
+    k_estimate_runs<AMAX_L, TCAP_L, false><<<(unsigned)((no + EW - 1) / EW), EW * 64, 0, st>>>(
+        ix, runs, no, over.p, n, T, seeds, cap, nseeds, err, lds_cap, reg_cap, AMAX_L, nullptr,
+        nullptr);
+    SDF_HIP(hipGetLastError());
+    SDF_HIP(hipStreamSynchronize(st));  // `over` is released on return
 }
 
 }  // namespace sdf

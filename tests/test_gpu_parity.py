@@ -207,18 +207,24 @@ def test_search_estimate_tandem_and_config1(S, oracle_lib, seed, length, n_seqs,
 def test_search_estimate_general_paths(S, oracle_lib, monkeypatch):
     """Estimate mode with the run's target minimizers read from global
     memory per candidate and the outside hashes counted through LDS (the
-    paths taken by long runs and dense windows) equals the oracle."""
+    paths taken by long runs and dense windows), and with runs handed from
+    the small first launch to the second (all of them, or those with more
+    than 64 minimizers in the window), equals the oracle."""
     g = synth.tandem_case(95, length=40_000, n_arrays=20, copies_hi=40, n_seqs=2)
     b, off = g.concat()
     orc = oracle_lib.OracleIndex(b, off, 12, 16)
     os_, oc = orc.search(g.spans, 0.25, 400, estimate=True)
     ix = S.Index(g.seqs, 12, 16)
-    for lds, reg in (("0", "0"), ("0", "128"), ("1024", "0"), ("8", "3")):
+    for lds, reg, first in (("0", "0", "256"), ("0", "128", "256"), ("1024", "0", "256"),
+                            ("8", "3", "256"), ("512", "128", "0"), ("512", "128", "64"),
+                            ("0", "0", "64")):
         monkeypatch.setenv("SDF_EST_LDS_CAP", lds)
         monkeypatch.setenv("SDF_EST_REG_CAP", reg)
+        monkeypatch.setenv("SDF_EST_FIRST_AMAX", first)
+        what = "lds=%s reg=%s first=%s" % (lds, reg, first)
         r = ix.search_batch(g.spans, 0.25, 400, estimate=True)
-        _same(r.seeds(), os_, SEED_F, "seeds lds=%s reg=%s" % (lds, reg))
-        _same(r.candidates(), oc, CAND_F, "candidates lds=%s reg=%s" % (lds, reg))
+        _same(r.seeds(), os_, SEED_F, "seeds " + what)
+        _same(r.candidates(), oc, CAND_F, "candidates " + what)
 
 
 def test_search_config1(S, oracle_lib):

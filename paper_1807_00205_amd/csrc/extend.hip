@@ -18,7 +18,7 @@
 //  1. the minimizers of both start windows and of every position a phase can
 //     reach within a horizon H are gathered (six contiguous ranges of the
 //     position-sorted minimizer array) and ranked by hash: bucketed on the
-//     top 12 hash bits, each run of buckets sorted in LDS (bitonic), equal
+//     top 11 hash bits, each run of buckets sorted in LDS (bitonic), equal
 //     hashes sharing a rank, so L becomes an array of 4-bit cells by rank;
 //  2. the start windows' minimizers are set, and s, the rank v of the s-th
 //     smallest element of L, and m are counted in parallel;
@@ -48,8 +48,9 @@ namespace sdf {
 namespace {
 
 constexpr int XT = 256;                 // threads per workgroup
-constexpr uint32_t NB = 4096;           // buckets over 12 hash bits
-constexpr uint32_t CH = 4096;           // keys sorted at once in LDS
+constexpr uint32_t NB_BITS = 11;
+constexpr uint32_t NB = 1u << NB_BITS;  // buckets over the top hash bits
+constexpr uint32_t CH = 2048;           // keys sorted at once in LDS
 constexpr uint32_t HALF = CH / 2;
 constexpr uint32_t LDS_WORDS = NB + 1 + (NB + 2) / 2 + 2 * CH + 1;  // the sort area, as words
 constexpr uint64_t INF = 1ull << 62;
@@ -646,6 +647,7 @@ __device__ void rank_chunk(Shared &L, const uint64_t *src, uint64_t b, uint64_t 
 // hashes in one bucket is reported as an error.
 constexpr uint32_t BIGT = CH / 2;  // hash set slots (u64, tagged)
 constexpr uint32_t BIGD = CH / 4;  // distinct hashes allowed
+constexpr uint32_t BIGT_BITS = __builtin_ctz(BIGT);
 __device__ bool rank_big(Shared &L, const uint64_t *src, uint64_t b, uint64_t e, uint32_t *rank) {
     uint64_t *set = L.ck;           // BIGT slots: (1 << 32) | hash, 0 = empty
     uint64_t *list = L.ck + BIGT;   // BIGT sorted distinct hashes
@@ -655,7 +657,7 @@ __device__ bool rank_big(Shared &L, const uint64_t *src, uint64_t b, uint64_t e,
     for (uint64_t i = b + threadIdx.x; i < e; i += XT) {
         const uint32_t h = (uint32_t)(src[i] >> 32);
         const uint64_t tag = (1ull << 32) | h;
-        uint32_t slot = (h * 0x9E3779B1u) >> 21;  // 11 bits: BIGT = 2048
+        uint32_t slot = (h * 0x9E3779B1u) >> (32 - BIGT_BITS);  // multiplicative hash
         for (uint32_t probe = 0;; probe++) {
             if (probe >= BIGT || L.cnt > BIGD) { L.flag = 1; break; }
             const uint64_t prev = atomicCAS((unsigned long long *)&set[slot], 0ull,
@@ -764,7 +766,7 @@ __global__ void __launch_bounds__(XT) k_extend(ExtArgs a) {
     uint32_t *rank = a.rank + blk * a.ecap;
     uint32_t *gnib = a.gnib + blk * (a.ecap / 8 + 1);
     const uint32_t hbits = 2 * k;
-    const uint32_t shift = hbits > 12 ? hbits - 12 : 0;
+    const uint32_t shift = hbits > NB_BITS ? hbits - NB_BITS : 0;
     const uint32_t nbk = 1u << (hbits - shift);
     constexpr uint32_t PER = NB / XT;
 
@@ -1078,8 +1080,9 @@ void launch_extend(const IndexView &ix, const sdf_region *in, uint64_t n, double
         batch_min = (uint32_t)std::strtoul(v, nullptr, 10);
     if (const char *v = std::getenv("SDF_EXT_ECAP"))
         ecap = std::max<uint64_t>(64, std::strtoull(v, nullptr, 10));
-    // two workgroups fit a CU (LDS); each keeps its own scratch
-    const uint64_t grid = std::min<uint64_t>(n, (uint64_t)std::max(1, cus) * 2);
+    // as many workgroups as fit a CU's LDS; each keeps its own scratch
+    const uint64_t per_cu = std::max<uint64_t>(1, (160u * 1024u) / sizeof(Shared));
+    const uint64_t grid = std::min<uint64_t>(n, (uint64_t)std::max(1, cus) * per_cu);
     DevBuf<uint64_t> tmp(grid * ecap);
     DevBuf<uint32_t> rank(grid * ecap), gnib(grid * (ecap / 8 + 1));
     DevBuf<uint32_t> work(2);
@@ -1115,7 +1118,7 @@ void launch_extend(const IndexView &ix, const sdf_region *in, uint64_t n, double
     if (herr & XE_CAP)
         throw Error{SDF_EINTERNAL, "extend: a region's windows hold more minimizers than its scratch"};
     if (herr & XE_HASH)
-        throw Error{SDF_EINTERNAL, "extend: more than 1024 distinct hashes share 12 hash bits"};
+        throw Error{SDF_EINTERNAL, "extend: more than 512 distinct hashes share 11 hash bits"};
     if (herr & XE_STATE) throw Error{SDF_EINTERNAL, "extend: inconsistent ordered set"};
     if (stats || std::getenv("SDF_EXT_STATS")) {
         ExtStats local;

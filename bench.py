@@ -85,12 +85,28 @@ def cpu_baseline(g, sample_mbp, max_error, min_len, keep=None):
     dt = time.time() - t
     if keep is not None:  # the oracle's own candidates, for the extension baseline
         keep.update(orc=orc, off=off, cands=cands, threads=threads)
+    # one thread on a tenth of the span
+    one = max(1, span_len // 10)
+    t = time.time()
+    orc.search([(0, a, a + one)], max_error, min_len, 1)
+    dt1 = time.time() - t
+    cpu = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": round(span_len / dt / 1e6, 4), "unit": "Mbp/s", "cores": threads,
             "kind": "oracle",
             "sample": "span [%d, %d) of the same sequence (%.1f Mbp), search only; oracle "
                       "index built beforehand in %.1f s" % (a, a + span_len, span_len / 1e6,
                                                              build_s),
-            "seconds": round(dt, 3)}
+            "seconds": round(dt, 3),
+            "single_thread_mbp_per_s": round(one / dt1 / 1e6, 4),
+            "host_cpu": cpu, "host_threads_visible": os.cpu_count()}
 
 
 def batched_vs_plain(steps, plain=True):

@@ -92,7 +92,8 @@ def _small_genome(case):
 
 @pytest.mark.parametrize("case", SMALL, ids=lambda c: "seed%d" % c["seed"] if c else "tandem")
 @pytest.mark.parametrize("max_error,min_len,k,w", [(0.25, 200, 12, 16), (0.3, 120, 9, 5),
-                                                   (0.1, 300, 11, 8)])
+                                                   (0.1, 300, 11, 8), (0.2, 250, 16, 24),
+                                                   (0.25, 300, 14, 10)])
 def test_extend_small(S, oracle_lib, case, max_error, min_len, k, w):
     """Extension of the oracle's candidates and of random boxes (both
     strands, one or several sequences, masking, gaps, tandem repeats), with

@@ -122,17 +122,26 @@ def batched_vs_plain(steps, plain=True):
     r = ix.search_batch(spans, timing=True)
     r.candidates()
     r.close()
-    torch.cuda.synchronize()
+
+    def timed():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kms = []
+        for _ in range(steps):
+            r = ix.search_batch(spans, timing=True)
+            ncand = len(r.candidates())
+            kms.append(float(r.timing()[1]))
+            stats = r.stats()
+            r.close()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, kms, ncand, stats
+
+    # the tile size from the hit-density rule, then the one sdf_autotune measures
+    tb_rule, kms_rule, _, _ = timed()
     t0 = time.perf_counter()
-    kms = []
-    for _ in range(steps):
-        r = ix.search_batch(spans, timing=True)
-        ncand = len(r.candidates())
-        kms.append(float(r.timing()[1]))
-        stats = r.stats()
-        r.close()
-    torch.cuda.synchronize()
-    tb = (time.perf_counter() - t0) / steps
+    core, tune_ms = ix.autotune(spans)
+    tune_s = time.perf_counter() - t0
+    tb, kms, ncand, stats = timed()
     lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -144,10 +153,15 @@ def batched_vs_plain(steps, plain=True):
         lat.append((time.perf_counter() - s0) * 1e3)
     torch.cuda.synchronize()
     tp = time.perf_counter() - t0
+    tuning = {"autotuned_core": core, "autotune_s": round(tune_s, 3),
+              "tile_kernel_ms_per_core": dict(zip(range(512, 1025, 64),
+                                                  [round(x, 3) for x in tune_ms])),
+              "rule_mbp_per_s": round(qb / tb_rule / 1e6, 2),
+              "rule_tile_kernel_ms": round(float(np.mean(kms_rule)), 4)}
     if not plain:
         return ix, g, {"batched_mbp_per_s": round(qb / tb / 1e6, 2), "batched_ms": round(tb * 1e3, 3),
                        "batched_tile_kernel_ms": round(float(np.mean(kms)), 4),
-                       "candidates": ncand, "stats": stats}
+                       "candidates": ncand, "stats": stats, "tuning": tuning}
     return ix, g, {
         "workload": "250 Mbp uniform sequence with 2,518 planted duplications (1-5 kbp, "
                     "2-15%%); 4,096 query spans of 1-100 kbp (log-uniform), %.1f Mbp" % (qb / 1e6),
@@ -156,7 +170,7 @@ def batched_vs_plain(steps, plain=True):
         "plain_mbp_per_s": round(qb / tp / 1e6, 2), "plain_ms": round(tp * 1e3, 2),
         "plain_latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                              "p99": round(float(np.percentile(lat, 99)), 4)},
-        "speedup": round(tp / tb, 2), "candidates": ncand, "stats": stats}
+        "speedup": round(tp / tb, 2), "candidates": ncand, "stats": stats, "tuning": tuning}
 
 
 def serving(ix, g, rates, seconds, workers):

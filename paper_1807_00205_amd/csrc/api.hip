@@ -172,7 +172,7 @@ struct Timer {
 };
 
 void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_search_params *p,
-                hipStream_t st, sdf_result_s *res) {
+                hipStream_t st, sdf_result_s *res, uint32_t core_override = 0) {
     const Params P = derive(p, ix->k, ix->w);
     res->n = P.n;
     for (uint32_t t = 0; t < nq; t++) {
@@ -202,9 +202,13 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
         qbases += qs[t].end - qs[t].begin;
     }
     const uint32_t hpart = std::max<uint32_t>(env_u32("SDF_HITS_PER_PART", 16384), 1024);
-    const uint32_t core = std::min(std::max<uint32_t>(env_u32("SDF_TILE_CORE",
-                                                              auto_tile_core(ix->hbar, hpart)), 1),
-                                   tile_core_max());
+    // window starts per tile: the environment override, else the measured
+    // choice of sdf_autotune, else the hit-density rule
+    const uint32_t pick = core_override ? core_override
+                                        : (ix->tuned_core ? ix->tuned_core
+                                                          : auto_tile_core(ix->hbar, hpart));
+    const uint32_t core =
+        std::min(std::max<uint32_t>(env_u32("SDF_TILE_CORE", pick), 1), tile_core_max());
     DevBuf<SpanDesc> dsd(nq);
     DevBuf<uint32_t> ntiles(nq + 1), tile0(nq + 1);
     uint32_t total_tiles = 0;  // read back with the counters; the kernel reads it on device
@@ -491,6 +495,45 @@ sdf_status sdf_search(sdf_index ix, const sdf_span *q, const sdf_search_params *
         return SDF_EINVAL;
     }
     return sdf_search_batch(ix, q, 1, p, hip_stream, out);
+}
+
+sdf_status sdf_autotune(sdf_index ix, const sdf_span *qs, uint32_t n, const sdf_search_params *p,
+                        void *hip_stream, uint32_t *core_out, float *ms_out, uint32_t n_ms) {
+    return guarded([&] {
+        if (!ix) throw Error{SDF_EINVAL, "NULL index"};
+        if (n == 0) {  // back to the hit-density rule
+            ix->tuned_core = 0;
+            if (core_out) *core_out = 0;
+            return;
+        }
+        if (!qs || !p) throw Error{SDF_EINVAL, "NULL argument"};
+        SDF_HIP(hipSetDevice(ix->device));
+        const hipStream_t st = (hipStream_t)hip_stream;
+        StreamScope scope(st);
+        sdf_search_params q = *p;
+        q.flags = (q.flags | SDF_TIMING) & ~(uint32_t)(SDF_EXTEND | SDF_SEED_ESTIMATE);
+        uint32_t best = 0;
+        float best_ms = 0.f;
+        uint32_t t = 0;
+        for (uint32_t c = 512; c <= tile_core_max(); c += 64, t++) {
+            float ms = 0.f;
+            for (int rep = 0; rep < 2; rep++) {  // the first run warms the memory pool
+                sdf_result_s r;
+                r.device = ix->device;
+                r.st = st;
+                run_search(ix, qs, n, &q, st, &r, c);
+                ms = r.ms[1];
+                SDF_HIP(hipStreamSynchronize(st));
+            }
+            if (ms_out && t < n_ms) ms_out[t] = ms;
+            if (best == 0 || ms < best_ms) {
+                best = c;
+                best_ms = ms;
+            }
+        }
+        ix->tuned_core = best;
+        if (core_out) *core_out = best;
+    });
 }
 
 sdf_status sdf_result_count(sdf_result r, uint64_t *n) {

@@ -38,7 +38,7 @@ EXPORTS = ["sdf_last_error", "sdf_index_build", "sdf_index_info", "sdf_index_hit
            "sdf_index_entries", "sdf_index_packed", "sdf_index_free", "sdf_search",
            "sdf_search_batch", "sdf_result_count", "sdf_result_copy", "sdf_result_seed_count",
            "sdf_result_seeds", "sdf_result_timing", "sdf_result_stats", "sdf_result_free",
-           "sdf_extend", "sdf_result_regions", "sdf_qgram_filter"]
+           "sdf_extend", "sdf_result_regions", "sdf_qgram_filter", "sdf_autotune"]
 
 
 def _flags(timing: bool, estimate: bool, extend: bool = False) -> int:
@@ -135,6 +135,9 @@ def lib() -> ctypes.CDLL:
         L.sdf_result_free.argtypes = [vp]
         L.sdf_extend.restype = st
         L.sdf_extend.argtypes = [vp, vp, u64, P(_ExtendParams), vp, vp]
+        L.sdf_autotune.restype = st
+        L.sdf_autotune.argtypes = [vp, vp, u32, P(_SearchParams), vp, P(u32), P(ctypes.c_float),
+                                   u32]
         L.sdf_qgram_filter.restype = st
         L.sdf_qgram_filter.argtypes = [vp, vp, u64, P(_QgramParams), vp, vp, vp]
         L.sdf_result_regions.restype = st
@@ -310,6 +313,21 @@ class Index:
                                 ctypes.byref(p), _stream_ptr(stream),
                                 out.ctypes.data_as(ctypes.c_void_p)))
         return out
+
+    def autotune(self, spans: Iterable[Tuple[int, int, int]], max_error: float = 0.25,
+                 min_len: int = 1000, stream=None):
+        """Times the tile kernel at every tile size on these spans and keeps the
+        fastest for later searches (``sdf_autotune``); returns (size, times in
+        ms per size 512, 576, ..., 1024).  No spans: back to the built-in rule."""
+        spans = list(spans)
+        arr = (_Span * max(1, len(spans)))(*[_Span(s, 0, b, e) for (s, b, e) in spans])
+        p = _SearchParams(max_error, min_len, 0)
+        core = ctypes.c_uint32()
+        ms = (ctypes.c_float * 16)()
+        _check(lib().sdf_autotune(self._h, ctypes.cast(arr, ctypes.c_void_p), len(spans),
+                                  ctypes.byref(p), _stream_ptr(stream), ctypes.byref(core), ms,
+                                  16))
+        return core.value, [float(x) for x in ms[:9]]
 
     def qgram_filter(self, regions: np.ndarray, q: int, gap_rate: float,
                      max_error: float = 0.25, stream=None):

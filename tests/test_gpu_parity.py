@@ -435,3 +435,21 @@ def test_serving_admission_budget(S, batch250):
     finally:
         srv.close()
     assert max(b for b, _ in srv.batches) == 1
+
+
+def test_autotune_keeps_results(S):
+    """sdf_autotune times every tile size on a span set and keeps the fastest;
+    searches after it return the same seeds and candidates, and forgetting
+    the choice restores the built-in rule."""
+    g = synth.config1()
+    ix = S.Index(g.seqs, 12, 16)
+    spans = synth.draw_spans(synth.rng_for(12), [len(s) for s in g.seqs], 48, 5000, 60000)
+    r0 = ix.search_batch(spans)
+    c0, s0 = r0.candidates(), r0.seeds()
+    core, ms = ix.autotune(spans)
+    assert core in range(512, 1025, 64)
+    assert all(m > 0 for m in ms) and ms[(core - 512) // 64] == min(ms)
+    r1 = ix.search_batch(spans)
+    _same(r1.seeds(), s0, SEED_F, "seeds after autotune")
+    _same(r1.candidates(), c0, CAND_F, "candidates after autotune")
+    assert ix.autotune([])[0] == 0

@@ -478,6 +478,11 @@ def main():
     span = spans[0]
     qbases = span[2] - span[1]
     alg_hits = algorithmic_hits(ix)
+    # the tile schedule measured on this span (outside the timed region, like the index)
+    t = time.time()
+    tuned_core, tuned_ms = ix.autotune([span], args.max_error, args.min_len)
+    tune_s = time.time() - t
+    log("autotuned tile size %d in %.2f s" % (tuned_core, tune_s))
     for _ in range(args.warmup):
         r = ix.search(span, args.max_error, args.min_len, timing=True)
         r.candidates()
@@ -527,7 +532,11 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
                      "traffic": measured_traffic(args.workload), "kernel": "k_tile_search",
                      "kernel_ms": round(mean_k, 4), "algorithmic_bytes": int(alg_bytes)},
-        "detail": {"index_build_s": round(build_s, 3), "minimizers": nm, "eligible": ne,
+        "detail": {"index_build_s": round(build_s, 3), "autotuned_core": tuned_core,
+                   "autotune_s": round(tune_s, 3),
+                   "tile_kernel_ms_per_core": dict(zip(range(512, 1025, 64),
+                                                       [round(x, 3) for x in tuned_ms])),
+                   "minimizers": nm, "eligible": ne,
                    "algorithmic_hits": alg_hits, "candidates": ncand, **stats},
     }
     if not args.no_estimate:

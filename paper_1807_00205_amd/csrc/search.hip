@@ -98,6 +98,11 @@ struct TileLds {
     uint32_t err;
     uint64_t gb, ge;
     uint32_t qid, qseq;
+    // work counters of this workgroup, added to the global ones once at exit
+    // (global atomics on a handful of shared addresses from every CU serialise)
+    unsigned long long cnt[CNT_N];
+    uint32_t wseeds[NWAVES];   // seeds buffered per wave, then their offsets
+    unsigned long long seed_base;
 };
 
 // ----------------------------------------------------------- block helpers --
@@ -409,6 +414,30 @@ __device__ __forceinline__ void seeds_push_lanes(const SearchArgs &a, SeedBuf &s
     sb.n += cnt;
 }
 
+// All waves of the workgroup write their buffered seeds with one global
+// atomic for the workgroup (every wave must call it: it holds barriers).
+__device__ __forceinline__ void seeds_flush_block(const SearchArgs &a, TileLds &L, SeedBuf &sb,
+                                                  int lane, int wave) {
+    if (lane == 0) L.wseeds[wave] = sb.n;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+        for (int w = 0; w < NWAVES; w++) {
+            const uint32_t c = L.wseeds[w];
+            L.wseeds[w] = tot;
+            tot += c;
+        }
+        L.seed_base = tot ? atomicAdd(&a.counters[CNT_SEEDS], (unsigned long long)tot) : 0ull;
+    }
+    __syncthreads();
+    const unsigned long long base = L.seed_base + L.wseeds[wave];
+    for (uint32_t t = lane; t < sb.n * 6; t += 64) {
+        const unsigned long long idx = base + t / 6;
+        if (idx < a.seed_cap) a.seeds[base * 6 + t] = sb.buf[t];
+    }
+    sb.n = 0;
+}
+
 __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
     __shared__ TileLds L;
     const IndexView &ix = a.ix;
@@ -416,6 +445,7 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
     const int lane = lane_id(), wave = wave_id();
     const bool prof = a.phase != nullptr && threadIdx.x == 0;
     if (threadIdx.x < PH_N) L.ph[threadIdx.x] = 0;
+    if (threadIdx.x < CNT_N) L.cnt[threadIdx.x] = 0;
     uint64_t ph_t = prof ? wall_clock64() : 0;
     // per-wave bitmasks start empty; each use clears the words it counted
     uint32_t span_cache = 0;  // thread 0: span of the previous tile
@@ -587,8 +617,8 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                 continue;
             }
             if (threadIdx.x == 0) {
-                atomicAdd(&a.counters[CNT_WINDOWS], (unsigned long long)L.nwin);
-                if (L.dup) atomicAdd(&a.counters[CNT_DUP_TILES], 1ull);
+                L.cnt[CNT_WINDOWS] += L.nwin;
+                if (L.dup) L.cnt[CNT_DUP_TILES] += 1;
             }
             const uint32_t Tmin = L.Tmin;
             const bool dup = L.dup != 0;
@@ -693,8 +723,8 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                     continue;
                 }
                 if (threadIdx.x == 0) {
-                    atomicAdd(&a.counters[CNT_HITS], (unsigned long long)H);
-                    atomicAdd(&a.counters[CNT_PARTS], 1ull);
+                    L.cnt[CNT_HITS] += H;
+                    L.cnt[CNT_PARTS] += 1;
                     L.ncoll = 0;
                 }
                 // ---- pass 1: bin counts ----
@@ -758,7 +788,7 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                     if (L.err) break;
                     continue;
                 }
-                if (threadIdx.x == 0) atomicAdd(&a.counters[CNT_KEPT], (unsigned long long)ncoll);
+                if (threadIdx.x == 0) L.cnt[CNT_KEPT] += ncoll;
                 // ---- sort kept hits by (o, p', q) ----
                 int n2 = 1;
                 while (n2 < (int)ncoll) n2 <<= 1;
@@ -1015,11 +1045,11 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                         if (win) L.run[qc][o] = rs;
                     }
                 }
-                seeds_flush(a, sbuf, lane);
                 if (lane == 0) {
-                    atomicAdd(&a.counters[CNT_EVALS], (unsigned long long)n_evals);
-                    atomicAdd(&a.counters[CNT_SCAN], (unsigned long long)n_scan);
+                    atomicAdd(&L.cnt[CNT_EVALS], (unsigned long long)n_evals);
+                    atomicAdd(&L.cnt[CNT_SCAN], (unsigned long long)n_scan);
                 }
+                seeds_flush_block(a, L, sbuf, lane, wave);
                 __syncthreads();
                 PHASE(PH_EVAL);
             }  // stack of one partition
@@ -1043,7 +1073,7 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
                     seeds_push_lanes(a, sbuf, lane, mine, L.qid, mine ? L.qpos[qc] : 0, rs.best_j,
                                      o, a.runs_out ? rs.prev_j : rs.best_c, mine ? L.win_s[qc] : 0);
                 }
-                seeds_flush(a, sbuf, lane);
+                seeds_flush_block(a, L, sbuf, lane, wave);
             }
             c_begin = L.c1;
             __syncthreads();
@@ -1051,6 +1081,9 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
         }
         __syncthreads();
     }
+    __syncthreads();
+    if (threadIdx.x < CNT_N && threadIdx.x != CNT_SEEDS && L.cnt[threadIdx.x])
+        atomicAdd(&a.counters[threadIdx.x], L.cnt[threadIdx.x]);
     if (prof)
         for (int t = 0; t < PH_N; t++) atomicAdd(&a.phase[t], (unsigned long long)L.ph[t]);
 }

@@ -144,6 +144,14 @@ __global__ void k_seg_flags(Sorted s, uint64_t ns, uint32_t n, uint32_t mo, uint
     flag[a] = head ? 1u : 0u;
 }
 
+// Diagonal cells: flag[a] = 1 where the group key changes.  Their starts
+// come from the same prefix sum as segment heads (k_seg_heads).
+__global__ void k_cell_flags(const uint64_t *g, uint64_t ns, uint32_t *flag) {
+    const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= ns) return;
+    flag[a] = (a == 0 || g[a - 1] != g[a]) ? 1u : 0u;
+}
+
 // sid = segment of each seed; head[sid] = its first seed, head[#segments] = ns.
 __global__ void k_seg_heads(const uint32_t *flag, const uint32_t *pre, uint64_t ns,
                             uint32_t *sid, uint32_t *head) {
@@ -181,41 +189,83 @@ __device__ __forceinline__ uint64_t gallop(uint64_t lo, uint64_t ns, F below) {
 }
 
 // Links of seed a to later seeds: in its own cell past its own segment, and
-// in the next diagonal cell with i in (ia - n, ia + n).  After a union the
-// rest of the other seed's segment is skipped (already connected).
+// in the next diagonal cell with i in (ia - n, ia + n).  After a link the
+// rest of the other seed's segment is skipped (one union joins it all).  cid
+// and cstart give each seed's cell and each cell's first seed, so the next
+// cell is found with one load (cells can hold thousands of seeds).
+//
+// The scan only records the segments to join; the unions run afterwards,
+// once per distinct (own segment, other segment) pair among the lanes of a
+// wave: consecutive seeds of a long segment all link to the same segments,
+// and one compare-and-swap per seed on the same root would serialise.
+struct LinkSlot {
+    uint32_t b, sb;  // seed and segment to join (sb = NONE32: empty)
+};
+
+__device__ __forceinline__ void wave_unions(uint32_t *par, uint32_t a, uint32_t sa, LinkSlot t,
+                                            int lane) {
+    uint64_t pending = __ballot(t.sb != NONE32);
+    while (pending) {
+        const int l = __ffsll((long long)pending) - 1;
+        const uint32_t la = (uint32_t)__builtin_amdgcn_readlane((int)sa, l);
+        const uint32_t lb = (uint32_t)__builtin_amdgcn_readlane((int)t.sb, l);
+        pending &= ~__ballot(t.sb != NONE32 && sa == la && t.sb == lb);
+        if (lane == l) uf_union(par, a, t.b);
+    }
+}
+
 __global__ void k_link(Sorted s, uint64_t ns, uint32_t n, uint32_t mo, uint32_t cbits,
-                       const uint32_t *sid, const uint32_t *head, uint32_t *par) {
+                       const uint32_t *sid, const uint32_t *head, const uint32_t *cid,
+                       const uint32_t *cstart, uint32_t *par) {
     const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= ns) return;
-    const uint64_t g = s.g[a];
-    const uint64_t ia = s.i[a];
-    const uint32_t sa = sid[a];
-    uint64_t b = head[sa + 1];
-    while (b < ns && s.g[b] == g && (uint64_t)s.i[b] < ia + n) {
-        if (linked(s, a, b, n, mo)) {
-            uf_union(par, (uint32_t)a, (uint32_t)b);
-            b = head[sid[b] + 1];
-        } else {
-            b++;
+    const int lane = threadIdx.x & 63;
+    LinkSlot t0{0, NONE32}, t1{0, NONE32};
+    // a third link of one seed (rare) is joined at once
+    auto record = [&](uint64_t b, uint32_t sb) {
+        if (t0.sb == NONE32) t0 = LinkSlot{(uint32_t)b, sb};
+        else if (t1.sb == NONE32) t1 = LinkSlot{(uint32_t)b, sb};
+        else uf_union(par, (uint32_t)a, (uint32_t)b);
+    };
+    uint32_t sa = NONE32;
+    if (a < ns) {
+        const uint64_t g = s.g[a];
+        const uint64_t ia = s.i[a];
+        sa = sid[a];
+        uint64_t b = head[sa + 1];
+        while (b < ns && s.g[b] == g && (uint64_t)s.i[b] < ia + n) {
+            if (linked(s, a, b, n, mo)) {
+                const uint32_t sb = sid[b];
+                record(b, sb);
+                b = head[sb + 1];
+            } else {
+                b++;
+            }
+        }
+        const uint64_t g2 = g + 1;
+        const uint64_t ce = cstart[cid[a] + 1];  // first seed past a's cell
+        // the next cell exists only on a's strand and when it holds seeds
+        if ((g2 >> cbits) == (g >> cbits) && ce < ns && s.g[ce] == g2) {
+            const uint64_t lim = ia >= n ? ia - n + 1 : 0;  // first i not too small
+            // Seeds before max(b, ce) lie in a's cell or in a segment the scan
+            // above links to a.
+            b = gallop(b > ce ? b : ce, ns, [&](uint64_t m) {
+                return s.g[m] < g2 || (s.g[m] == g2 && (uint64_t)s.i[m] < lim);
+            });
+            while (b < ns && s.g[b] == g2 && (uint64_t)s.i[b] < ia + n) {
+                const uint32_t sb = sid[b];
+                if (sb == sa) {
+                    b = head[sa + 1];
+                } else if (linked(s, a, b, n, mo)) {
+                    record(b, sb);
+                    b = head[sb + 1];
+                } else {
+                    b++;
+                }
+            }
         }
     }
-    const uint64_t g2 = g + 1;
-    if ((g2 >> cbits) != (g >> cbits)) return;  // the cell after the last of its strand
-    const uint64_t lim = ia >= n ? ia - n + 1 : 0;  // first i not too small
-    b = gallop(a + 1, ns, [&](uint64_t m) {
-        return s.g[m] < g2 || (s.g[m] == g2 && (uint64_t)s.i[m] < lim);
-    });
-    while (b < ns && s.g[b] == g2 && (uint64_t)s.i[b] < ia + n) {
-        const uint32_t sb = sid[b];
-        if (sb == sa) {
-            b = head[sa + 1];
-        } else if (linked(s, a, b, n, mo)) {
-            uf_union(par, (uint32_t)a, (uint32_t)b);
-            b = head[sb + 1];
-        } else {
-            b++;
-        }
-    }
+    wave_unions(par, (uint32_t)a, sa, t0, lane);
+    wave_unions(par, (uint32_t)a, sa, t1, lane);
 }
 
 __global__ void k_flatten(uint32_t *par, uint64_t ns) {
@@ -683,6 +733,12 @@ void chain_seeds(const IndexView &ix, const uint32_t *seeds, uint64_t ns, uint32
     DevBuf<uint32_t> par(ns);
     {
         DevBuf<uint32_t> sflag(ns + 1), spre(ns + 1), sid(ns), head(ns + 1);
+        DevBuf<uint32_t> cid(ns), cstart(ns + 1);
+        k_cell_flags<<<nb(ns), 256, 0, st>>>(s.g, ns, sflag.p);
+        SDF_HIP(hipGetLastError());
+        scan_u32(sflag.p, spre.p, ns, st);
+        k_seg_heads<<<nb(ns), 256, 0, st>>>(sflag.p, spre.p, ns, cid.p, cstart.p);
+        SDF_HIP(hipGetLastError());
         k_seg_flags<<<nb(ns), 256, 0, st>>>(s, ns, n, mo, ck.cbits, sflag.p);
         SDF_HIP(hipGetLastError());
         scan_u32(sflag.p, spre.p, ns, st);
@@ -690,7 +746,8 @@ void chain_seeds(const IndexView &ix, const uint32_t *seeds, uint64_t ns, uint32
         SDF_HIP(hipGetLastError());
         k_seg_par<<<nb(ns), 256, 0, st>>>(sid.p, head.p, ns, par.p);
         SDF_HIP(hipGetLastError());
-        k_link<<<nb(ns), 256, 0, st>>>(s, ns, n, mo, ck.cbits, sid.p, head.p, par.p);
+        k_link<<<nb(ns), 256, 0, st>>>(s, ns, n, mo, ck.cbits, sid.p, head.p, cid.p, cstart.p,
+                                       par.p);
         SDF_HIP(hipGetLastError());
     }
     k_flatten<<<nb(ns), 256, 0, st>>>(par.p, ns);

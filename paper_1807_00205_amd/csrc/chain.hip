@@ -661,6 +661,95 @@ static void sort_candidates(sdf_candidate *c, uint64_t n2, hipStream_t st) {
     }
 }
 
+// Candidates are radix-sorted on an order-preserving prefix of (query_id,
+// strand, q_seq, q_begin); runs of equal prefixes (candidates that start at
+// the same query base) are then ordered by the full record comparison, one
+// thread per run.  A run longer than TIE_MAX sends the whole array to the
+// bitonic sort of records instead.
+constexpr uint32_t TIE_MAX = 256;
+
+struct CandPrefix {
+    uint32_t sb, pb, shift;  // q_seq bits, q_begin bits, q_begin low bits dropped
+};
+
+__global__ void k_cand_prefix(const sdf_candidate *c, uint64_t nc, CandPrefix cp, uint64_t *key,
+                              uint32_t *val) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nc) return;
+    const uint64_t hi = ((((uint64_t)c[t].query_id << 1) | c[t].strand) << cp.sb) | c[t].q_seq;
+    key[t] = (hi << (cp.pb - cp.shift)) | (c[t].q_begin >> cp.shift);
+    val[t] = (uint32_t)t;
+}
+
+__global__ void k_permute_cands(const sdf_candidate *c, const uint32_t *order, uint64_t nc,
+                                sdf_candidate *out) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nc) out[t] = c[order[t]];
+}
+
+__global__ void k_cand_ties(const uint64_t *key, uint64_t nc, uint32_t tie_max, sdf_candidate *c,
+                            uint32_t *long_run) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t + 1 >= nc || (t > 0 && key[t - 1] == key[t]) || key[t + 1] != key[t]) return;
+    uint64_t e = t + 2;
+    while (e < nc && key[e] == key[t] && e - t <= tie_max) e++;
+    if (e - t > tie_max) {
+        atomicOr(long_run, 1u);
+        return;
+    }
+    for (uint64_t x = t + 1; x < e; x++) {  // insertion sort of the run
+        const sdf_candidate v = c[x];
+        uint64_t y = x;
+        while (y > t && cand_less(v, c[y - 1])) {
+            c[y] = c[y - 1];
+            y--;
+        }
+        c[y] = v;
+    }
+}
+
+static uint32_t bitlen(uint64_t v);
+
+// Sorts the nc candidates of `cands` (capacity >= the next power of two).
+static void finish_candidates(DevBuf<sdf_candidate> &cands, uint64_t nc, const IndexView &ix,
+                              uint32_t nspans, hipStream_t st) {
+    uint64_t n2 = 1;
+    while (n2 < nc) n2 <<= 1;
+    const uint32_t qb = bitlen(nspans > 0 ? nspans - 1 : 0), sb = bitlen(ix.nseq > 0 ? ix.nseq - 1 : 0);
+    const uint32_t pb = bitlen(ix.total), head = qb + 1 + sb;
+    const uint32_t shift = head + pb > 64 ? head + pb - 64 : 0;
+    bool general = std::getenv("SDF_CAND_SORT_GENERAL") != nullptr || shift > pb;
+    if (nc > 1 && !general) {
+        DevBuf<uint64_t> key(nc);
+        DevBuf<uint32_t> order(nc);
+        k_cand_prefix<<<nb(nc), 256, 0, st>>>(cands.p, nc, CandPrefix{sb, pb, shift}, key.p, order.p);
+        SDF_HIP(hipGetLastError());
+        radix_sort_u64(key.p, order.p, nc, (int)(head + pb - shift), st);
+        DevBuf<sdf_candidate> sorted(n2);
+        k_permute_cands<<<nb(nc), 256, 0, st>>>(cands.p, order.p, nc, sorted.p);
+        SDF_HIP(hipGetLastError());
+        DevBuf<uint32_t> flag(1);
+        SDF_HIP(hipMemsetAsync(flag.p, 0, 4, st));
+        // test hook: SDF_CAND_TIE_MAX lowers the longest run ordered in place
+        uint32_t tie_max = TIE_MAX;
+        if (const char *v = std::getenv("SDF_CAND_TIE_MAX"))
+            tie_max = std::min<uint32_t>(TIE_MAX, (uint32_t)std::strtoul(v, nullptr, 10));
+        k_cand_ties<<<nb(nc), 256, 0, st>>>(key.p, nc, tie_max, sorted.p, flag.p);
+        SDF_HIP(hipGetLastError());
+        uint32_t long_run = 0;
+        SDF_HIP(hipMemcpyAsync(&long_run, flag.p, 4, hipMemcpyDeviceToHost, st));
+        SDF_HIP(hipStreamSynchronize(st));
+        cands = std::move(sorted);
+        if (!long_run) return;
+        general = true;
+    }
+    if (n2 > nc) {
+        k_pad_cands<<<nb(n2 - nc), 256, 0, st>>>(cands.p, nc, n2);
+        SDF_HIP(hipGetLastError());
+    }
+    sort_candidates(cands.p, n2, st);
+}
+
 static uint32_t bitlen(uint64_t v) {
     uint32_t b = 0;
     while (b < 64 && (v >> b)) b++;
@@ -697,13 +786,7 @@ void chain_seeds(const IndexView &ix, const uint32_t *seeds, uint64_t ns, uint32
         uint32_t nc = 0;
         SDF_HIP(hipMemcpyAsync(&nc, cnt.p, 4, hipMemcpyDeviceToHost, st));
         SDF_HIP(hipStreamSynchronize(st));
-        uint64_t n2 = 1;
-        while (n2 < nc) n2 <<= 1;
-        if (n2 > nc) {
-            k_pad_cands<<<nb(n2 - nc), 256, 0, st>>>(out.cands.p, nc, n2);
-            SDF_HIP(hipGetLastError());
-        }
-        sort_candidates(out.cands.p, n2, st);
+        finish_candidates(out.cands, nc, ix, nspans, st);
         out.ncands = nc;
         return;
     }
@@ -770,11 +853,7 @@ void chain_seeds(const IndexView &ix, const uint32_t *seeds, uint64_t ns, uint32
     k_emit_cands<<<nb(ns), 256, 0, st>>>(s, par.p, ns, g, ck.cbits, pre.p, ix.off, ix.nseq, n,
                                          out.cands.p);
     SDF_HIP(hipGetLastError());
-    if (n2 > nc) {
-        k_pad_cands<<<nb(n2 - nc), 256, 0, st>>>(out.cands.p, nc, n2);
-        SDF_HIP(hipGetLastError());
-    }
-    sort_candidates(out.cands.p, n2, st);
+    finish_candidates(out.cands, nc, ix, nspans, st);
     out.ncands = nc;
 }
 

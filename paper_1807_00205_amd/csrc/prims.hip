@@ -246,13 +246,19 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_hist(const K *keys, uint64_t 
 
 // Stable scatter: elements keep their input order within a digit.  Wave w
 // of the block owns the w-th quarter of the tile and walks it 64 elements at
-// a time; lanes with equal digits are ranked with eight ballots.
+// a time; lanes with equal digits are ranked with eight ballots.  The tile is
+// first placed in LDS in digit order, then written out so that consecutive
+// threads store consecutive elements of one digit's run (coalesced).
 template <class K>
 __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const K *kin, const uint32_t *vin, K *kout,
                                                         uint32_t *vout, uint64_t n, int shift,
                                                         const uint64_t *hoff, uint32_t nblocks) {
     __shared__ uint32_t cnt[RS_WAVES][RS_BINS];
     __shared__ uint64_t boff[RS_BINS];
+    __shared__ uint32_t lstart[RS_BINS];  // first tile slot of each digit
+    __shared__ uint32_t wsum[RS_WAVES];
+    __shared__ K skey[RS_TILE];
+    __shared__ uint32_t sval[RS_TILE];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int i = threadIdx.x; i < RS_BINS; i += RS_THREADS) {
         boff[i] = hoff[(uint64_t)i * nblocks + blockIdx.x];
@@ -260,7 +266,8 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const K *kin, const u
         for (int w = 0; w < RS_WAVES; w++) cnt[w][i] = 0;
     }
     __syncthreads();
-    const uint64_t base = (uint64_t)blockIdx.x * RS_TILE + (uint64_t)wave * (RS_TILE / RS_WAVES);
+    const uint64_t tile0 = (uint64_t)blockIdx.x * RS_TILE;
+    const uint64_t base = tile0 + (uint64_t)wave * (RS_TILE / RS_WAVES);
     K kk[RS_ITEMS];
     uint32_t vv[RS_ITEMS];
     uint32_t rk[RS_ITEMS];
@@ -292,24 +299,49 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const K *kin, const u
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < RS_BINS; i += RS_THREADS) {
-        uint32_t s = 0;
+    // per digit: the waves' offsets within the digit, and the digit's start
+    // in the tile (exclusive sum over digits; one digit per thread)
+    static_assert(RS_BINS == RS_THREADS, "one digit per thread");
+    uint32_t tot = 0;
+    {
+        const int i = threadIdx.x;
 #pragma unroll
         for (int w = 0; w < RS_WAVES; w++) {
-            uint32_t t = cnt[w][i];
-            cnt[w][i] = s;
-            s += t;
+            const uint32_t t = cnt[w][i];
+            cnt[w][i] = tot;
+            tot += t;
         }
+    }
+    uint32_t x = tot;  // inclusive scan over the 64 digits of this wave
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    {
+        uint32_t before = 0;
+        for (int w = 0; w < wave; w++) before += wsum[w];
+        lstart[threadIdx.x] = before + x - tot;
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < RS_ITEMS; r++) {
         uint64_t idx = base + (uint64_t)r * 64 + lane;
         if (idx < n) {
-            uint64_t pos = boff[dg[r]] + cnt[wave][dg[r]] + rk[r];
-            kout[pos] = kk[r];
-            vout[pos] = vv[r];
+            const uint32_t at = lstart[dg[r]] + cnt[wave][dg[r]] + rk[r];
+            skey[at] = kk[r];
+            sval[at] = vv[r];
         }
+    }
+    __syncthreads();
+    const uint32_t m = (uint32_t)min<uint64_t>(RS_TILE, n - tile0);
+    for (uint32_t t = threadIdx.x; t < m; t += RS_THREADS) {
+        const K key = skey[t];
+        const uint32_t d = (uint32_t)(key >> shift) & (RS_BINS - 1);
+        const uint64_t pos = boff[d] + (t - lstart[d]);
+        kout[pos] = key;
+        vout[pos] = sval[t];
     }
 }
 

@@ -279,6 +279,30 @@ def test_chaining_fused_equals_general(S, oracle_lib, monkeypatch):
     assert ("fused", True) in seen and ("general", False) in seen
 
 
+@pytest.mark.parametrize("path", ["prefix", "long_ties", "general"])
+def test_candidate_sort_paths(S, oracle_lib, monkeypatch, path):
+    """Every sort of the chained candidates gives the oracle's order: radix
+    keys on a prefix of query, strand, sequence and begin with ties ordered in
+    place, the same with every tie sent to the bitonic sort of records, and
+    that bitonic sort alone; on batches with several query spans, sequences
+    and both strands, and on tandem arrays whose candidates share begins."""
+    if path == "long_ties":
+        monkeypatch.setenv("SDF_CAND_TIE_MAX", "1")
+    if path == "general":
+        monkeypatch.setenv("SDF_CAND_SORT_GENERAL", "1")
+    for g in (_mixed_genome(5, length=8000), synth.tandem_case(93, length=200_000, n_arrays=120,
+                                                               copies_hi=60, n_seqs=3)):
+        b, off = g.concat()
+        spans = list(g.spans) + [(0, 100, len(g.seqs[0]) - 50)]
+        orc = oracle_lib.OracleIndex(b, off, 12, 16)
+        _, oc = orc.search(spans, 0.25, 200)
+        ix = S.Index(g.seqs, 12, 16)
+        r = ix.search_batch(spans, 0.25, 200)
+        assert len(oc) > 1
+        _same(r.candidates(), oc, CAND_F, "candidates")
+        ix.close()
+
+
 def test_edge_spans(S, oracle_lib):
     """Empty spans, spans shorter than n, spans at sequence ends, sequences
     shorter than k or made of gap bases, and several spans in one batch."""

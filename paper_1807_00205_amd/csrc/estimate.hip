@@ -134,27 +134,41 @@ __device__ uint32_t estimate_finish(W &L, const uint32_t *out, uint8_t *first, u
     // iff (distinct outside hashes below b) + (hashes of W_i below b) < s
     uint32_t y = 0;
     if (nb <= reg_cap) {  // reg_cap <= 128
-        // two per lane in registers, compared through lane broadcasts
-        const uint32_t h0 = lane < nb ? out[lane] : 0u, h1 = lane + 64 < nb ? out[lane + 64] : 0u;
-        bool d0 = false, d1 = false;  // repeats an earlier value
-        for (uint32_t t = 0; t < nb; t++) {
-            const uint32_t v = t < 64 ? (uint32_t)__builtin_amdgcn_readlane((int)h0, (int)t)
-                                      : (uint32_t)__builtin_amdgcn_readlane((int)h1, (int)(t - 64));
-            d0 |= t < lane && v == h0;
-            d1 |= t < lane + 64 && v == h1;
+        // two per lane in registers (element lane and lane + 64), sorted by a
+        // bitonic network over the wave; then a value is the first of its
+        // kind when it differs from the one before it, and its rank among the
+        // distinct outside hashes is a popcount of those firsts
+        uint32_t x0 = lane < nb ? out[lane] : 0xFFFFFFFFu;
+        uint32_t x1 = lane + 64 < nb ? out[lane + 64] : 0xFFFFFFFFu;
+        for (uint32_t k = 2; k <= 128; k <<= 1) {
+            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                if (j == 64) {  // k = 128: elements lane and lane + 64, ascending
+                    const uint32_t lo = min(x0, x1), hi = max(x0, x1);
+                    x0 = lo;
+                    x1 = hi;
+                } else {
+                    const uint32_t y0 = (uint32_t)__shfl_xor((int)x0, (int)j, 64);
+                    const uint32_t y1 = (uint32_t)__shfl_xor((int)x1, (int)j, 64);
+                    const bool lower = (lane & j) == 0;
+                    const bool asc0 = (lane & k) == 0, asc1 = ((lane + 64) & k) == 0;
+                    x0 = (lower == asc0) ? min(x0, y0) : max(x0, y0);
+                    x1 = (lower == asc1) ? min(x1, y1) : max(x1, y1);
+                }
+            }
         }
-        const bool f0 = lane < nb && !d0, f1 = lane + 64 < nb && !d1;
+        // padding (all ones) sorts last, so elements [0, nb) are the values
+        const uint32_t p0 = (uint32_t)__shfl_up((int)x0, 1, 64);
+        const uint32_t p1 = lane ? (uint32_t)__shfl_up((int)x1, 1, 64)
+                                 : (uint32_t)__builtin_amdgcn_readlane((int)x0, 63);
+        const bool f0 = lane < nb && (lane == 0 || p0 != x0);
+        const bool f1 = lane + 64 < nb && p1 != x1;
         const uint64_t fm0 = __ballot(f0), fm1 = __ballot(f1);
-        uint32_t b0 = f0 ? rank_below(L.ahash, s, h0) : s, b1 = f1 ? rank_below(L.ahash, s, h1) : s;
-        for (uint32_t t = 0; t < nb; t++) {
-            const bool ft = t < 64 ? ((fm0 >> t) & 1) : ((fm1 >> (t - 64)) & 1);
-            if (!ft) continue;
-            const uint32_t v = t < 64 ? (uint32_t)__builtin_amdgcn_readlane((int)h0, (int)t)
-                                      : (uint32_t)__builtin_amdgcn_readlane((int)h1, (int)(t - 64));
-            b0 += v < h0 ? 1u : 0u;
-            b1 += v < h1 ? 1u : 0u;
-        }
-        y = (uint32_t)__popcll(__ballot(f0 && b0 < s)) + (uint32_t)__popcll(__ballot(f1 && b1 < s));
+        const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+        const uint32_t dr0 = (uint32_t)__popcll(fm0 & lt);
+        const uint32_t dr1 = (uint32_t)__popcll(fm0) + (uint32_t)__popcll(fm1 & lt);
+        const bool in0 = f0 && dr0 + rank_below(L.ahash, s, x0) < s;
+        const bool in1 = f1 && dr1 + rank_below(L.ahash, s, x1) < s;
+        y = (uint32_t)__popcll(__ballot(in0)) + (uint32_t)__popcll(__ballot(in1));
     } else {
         for (uint32_t x = lane; x < nb; x += 64) {
             const uint32_t h = out[x];

@@ -31,6 +31,21 @@ def request_bytes(span_len: int) -> int:
     return seeds * 24 * 6
 
 
+_STREAMS: dict = {}
+
+
+def worker_streams(n: int):
+    """n HIP streams (default priority) kept for the life of the process, so
+    that the device memory the library caches per stream is found again by
+    every later server instead of being allocated anew."""
+    import torch
+    dev = torch.cuda.current_device()
+    lst = _STREAMS.setdefault(dev, [])
+    while len(lst) < n:
+        lst.append(torch.cuda.Stream())
+    return lst[:n]
+
+
 class Request:
     __slots__ = ("span", "arrival", "future", "bytes")
 
@@ -58,7 +73,7 @@ class Server:
         self.cv = threading.Condition()
         self.stop = False
         self.batches = []  # (size, seconds) per batch
-        self.streams = [torch.cuda.Stream() for _ in range(workers)]
+        self.streams = worker_streams(workers)
         self.threads = [threading.Thread(target=self._work, args=(s,), daemon=True)
                         for s in self.streams]
         for t in self.threads:

@@ -139,7 +139,7 @@ def batched_vs_plain(steps, plain=True):
     # the tile size from the hit-density rule, then the one sdf_autotune measures
     tb_rule, kms_rule, _, _ = timed()
     t0 = time.perf_counter()
-    core, tune_ms = ix.autotune(spans)
+    core, threads, tune_ms = ix.autotune(spans)
     tune_s = time.perf_counter() - t0
     tb, kms, ncand, stats = timed()
     lat = []
@@ -153,9 +153,10 @@ def batched_vs_plain(steps, plain=True):
         lat.append((time.perf_counter() - s0) * 1e3)
     torch.cuda.synchronize()
     tp = time.perf_counter() - t0
-    tuning = {"autotuned_core": core, "autotune_s": round(tune_s, 3),
-              "tile_kernel_ms_per_core": dict(zip(range(512, 1025, 64),
-                                                  [round(x, 3) for x in tune_ms])),
+    tuning = {"autotuned_core": core, "autotuned_threads": threads,
+              "autotune_s": round(tune_s, 3),
+              "tile_kernel_ms_per_schedule": {"%d threads, %d starts" % k: round(v, 3)
+                                              for k, v in tune_ms.items()},
               "rule_mbp_per_s": round(qb / tb_rule / 1e6, 2),
               "rule_tile_kernel_ms": round(float(np.mean(kms_rule)), 4)}
     if not plain:
@@ -486,9 +487,10 @@ def main():
     alg_hits = algorithmic_hits(ix)
     # the tile schedule measured on this span (outside the timed region, like the index)
     t = time.time()
-    tuned_core, tuned_ms = ix.autotune([span], args.max_error, args.min_len)
+    tuned_core, tuned_threads, tuned_ms = ix.autotune([span], args.max_error, args.min_len)
     tune_s = time.time() - t
-    log("autotuned tile size %d in %.2f s" % (tuned_core, tune_s))
+    log("autotuned tile schedule: %d-thread workgroups, %d window starts, in %.2f s" % (
+        tuned_threads, tuned_core, tune_s))
     for _ in range(args.warmup):
         r = ix.search(span, args.max_error, args.min_len, timing=True)
         r.candidates()
@@ -539,9 +541,9 @@ def main():
                      "traffic": measured_traffic(args.workload), "kernel": "k_tile_search",
                      "kernel_ms": round(mean_k, 4), "algorithmic_bytes": int(alg_bytes)},
         "detail": {"index_build_s": round(build_s, 3), "autotuned_core": tuned_core,
-                   "autotune_s": round(tune_s, 3),
-                   "tile_kernel_ms_per_core": dict(zip(range(512, 1025, 64),
-                                                       [round(x, 3) for x in tuned_ms])),
+                   "autotuned_threads": tuned_threads, "autotune_s": round(tune_s, 3),
+                   "tile_kernel_ms_per_schedule": {"%d threads, %d starts" % k: round(v, 3)
+                                                   for k, v in tuned_ms.items()},
                    "minimizers": nm, "eligible": ne,
                    "algorithmic_hits": alg_hits, "candidates": ncand, **stats},
     }

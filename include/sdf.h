@@ -265,17 +265,21 @@ sdf_status sdf_search_batch(sdf_index ix, const sdf_span *qs, uint32_t n,
 
 /* Autotuner of the tile schedule: runs the search of the n spans (host
  * array, as for sdf_search_batch, with p's error bound and length; the
- * timing, estimate and extension flags are ignored) with every tile size from
- * 512 to 1024 window starts in steps of 64, timing the tile kernel (second of
- * two runs per size, HIP events), and keeps the fastest size for later
- * searches on this index.  *core_out (may be NULL) receives it; ms_out (may
- * be NULL) receives up to n_ms kernel times, one per size tried.  n == 0
- * forgets the choice (the hit-density rule applies again).  Search results
- * do not depend on the tile size.  Not to be called while other searches on
+ * timing, estimate and extension flags are ignored) with every schedule in
+ * turn, timing the tile kernel (second of two runs each, HIP events), and
+ * keeps the fastest for later searches on this index.  The schedules, in
+ * order: 1,024-thread workgroups (one per CU) at 512 to 1,024 window starts
+ * per tile in steps of 64, then 512-thread workgroups (two per CU) at 512
+ * window starts when a window of p's length holds at most 1,024 minimizers
+ * (length <= 1,023 + k).  *core_out and *threads_out (each may be NULL)
+ * receive the window starts and workgroup size kept; ms_out (may be NULL)
+ * receives up to n_ms kernel times in that order (10 at most).  n == 0
+ * forgets the choice (the hit-density rules apply again).  Search results
+ * do not depend on the schedule.  Not to be called while other searches on
  * the same index are running.  Errors as for sdf_search_batch. */
 sdf_status sdf_autotune(sdf_index ix, const sdf_span *spans, uint32_t n,
                         const sdf_search_params *p, void *hip_stream, uint32_t *core_out,
-                        float *ms_out, uint32_t n_ms);
+                        uint32_t *threads_out, float *ms_out, uint32_t n_ms);
 
 /* Number of candidates (waits for the search to finish). */
 sdf_status sdf_result_count(sdf_result r, uint64_t *n);

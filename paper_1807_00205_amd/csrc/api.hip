@@ -114,11 +114,22 @@ uint32_t env_u32(const char *name, uint32_t def) {
 // partition (hits per window start run about 1.15 hbar, and splitting a tile
 // into partitions costs a search of every list per partition), at least 512
 // so fixed per-tile costs stay amortised.
-uint32_t auto_tile_core(double hbar, uint32_t hpart) {
+uint32_t auto_tile_core(double hbar, uint32_t hpart, uint32_t cmax) {
     const double per_win = 1.15 * (hbar > 1.0 ? hbar : 1.0);
     double c = 0.95 * (double)hpart / per_win;
-    c = std::min(std::max(c, 512.0), (double)tile_core_max());
+    c = std::min(std::max(c, 512.0), (double)cmax);
     return ((uint32_t)c) & ~63u;
+}
+
+// Most window bases the 512-thread tile layout holds: a window has at most
+// n - k + 1 minimizers, and that layout keeps 1,024 per tile.
+bool fits_tile512(uint32_t n, uint32_t k) { return n <= 1023 + k; }
+
+// Workgroup layout of the tile kernel: 512 threads, two workgroups per CU,
+// when the windows fit it and hits are sparse (mean list length up to 8; its
+// bin table is a quarter of the size), else 1,024 threads, one per CU.
+uint32_t tile_threads_rule(double hbar, uint32_t n, uint32_t k) {
+    return (fits_tile512(n, k) && hbar <= 8.0) ? 512u : 1024u;
 }
 
 int cu_count(int dev) {
@@ -172,7 +183,8 @@ struct Timer {
 };
 
 void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_search_params *p,
-                hipStream_t st, sdf_result_s *res, uint32_t core_override = 0) {
+                hipStream_t st, sdf_result_s *res, uint32_t core_override = 0,
+                uint32_t threads_override = 0) {
     const Params P = derive(p, ix->k, ix->w);
     res->n = P.n;
     for (uint32_t t = 0; t < nq; t++) {
@@ -201,14 +213,22 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
         sd[t].qseq = qs[t].seq;
         qbases += qs[t].end - qs[t].begin;
     }
-    const uint32_t hpart = std::max<uint32_t>(env_u32("SDF_HITS_PER_PART", 16384), 1024);
-    // window starts per tile: the environment override, else the measured
-    // choice of sdf_autotune, else the hit-density rule
+    // tile layout and window starts per tile: the environment overrides
+    // (SDF_TILE_THREADS, SDF_TILE_CORE), else the measured choice of
+    // sdf_autotune, else the hit-density rules
+    uint32_t threads = threads_override
+                           ? threads_override
+                           : (ix->tuned_threads ? ix->tuned_threads
+                                                : tile_threads_rule(ix->hbar, P.n, ix->k));
+    threads = env_u32("SDF_TILE_THREADS", threads) == 512 ? 512u : 1024u;
+    if (!fits_tile512(P.n, ix->k)) threads = 1024;
+    const uint32_t cmax = threads == 512 ? tile512::tile_core_max() : tile1024::tile_core_max();
+    const uint32_t hpart =
+        std::max<uint32_t>(env_u32("SDF_HITS_PER_PART", threads == 512 ? 8192 : 16384), 1024);
     const uint32_t pick = core_override ? core_override
                                         : (ix->tuned_core ? ix->tuned_core
-                                                          : auto_tile_core(ix->hbar, hpart));
-    const uint32_t core =
-        std::min(std::max<uint32_t>(env_u32("SDF_TILE_CORE", pick), 1), tile_core_max());
+                                                          : auto_tile_core(ix->hbar, hpart, cmax));
+    const uint32_t core = std::min(std::max<uint32_t>(env_u32("SDF_TILE_CORE", pick), 1), cmax);
     DevBuf<SpanDesc> dsd(nq);
     DevBuf<uint32_t> ntiles(nq + 1), tile0(nq + 1);
     uint32_t total_tiles = 0;  // read back with the counters; the kernel reads it on device
@@ -250,10 +270,13 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
             a.err = work.p + 1;
             a.phase = phase_prof ? phase.p : nullptr;
             a.runs_out = (p->flags & SDF_SEED_ESTIMATE) ? 1u : 0u;
-            // persistent grid: workgroups past the last tile exit at once
-            const uint32_t grid = (uint32_t)cu_count(ix->device) * env_u32("SDF_WG_PER_CU", 1);
+            // persistent grid, as many workgroups as fit the CUs: workgroups
+            // past the last tile exit at once
+            const uint32_t grid = (uint32_t)cu_count(ix->device) * (threads == 512 ? 2u : 1u) *
+                                  env_u32("SDF_WG_PER_CU", 1);
             tm.mark_kernel_begin();
-            launch_tile_search(a, std::max<uint32_t>(grid, 1), st);
+            if (threads == 512) tile512::launch_tile_search(a, std::max<uint32_t>(grid, 1), st);
+            else tile1024::launch_tile_search(a, std::max<uint32_t>(grid, 1), st);
             tm.mark_kernel_end();
         }
         SDF_HIP(hipMemcpyAsync(hc.data(), counters.p, CNT_N * 8, hipMemcpyDeviceToHost, st));
@@ -498,12 +521,15 @@ sdf_status sdf_search(sdf_index ix, const sdf_span *q, const sdf_search_params *
 }
 
 sdf_status sdf_autotune(sdf_index ix, const sdf_span *qs, uint32_t n, const sdf_search_params *p,
-                        void *hip_stream, uint32_t *core_out, float *ms_out, uint32_t n_ms) {
+                        void *hip_stream, uint32_t *core_out, uint32_t *threads_out,
+                        float *ms_out, uint32_t n_ms) {
     return guarded([&] {
         if (!ix) throw Error{SDF_EINVAL, "NULL index"};
-        if (n == 0) {  // back to the hit-density rule
+        if (n == 0) {  // back to the hit-density rules
             ix->tuned_core = 0;
+            ix->tuned_threads = 0;
             if (core_out) *core_out = 0;
+            if (threads_out) *threads_out = 0;
             return;
         }
         if (!qs || !p) throw Error{SDF_EINVAL, "NULL argument"};
@@ -512,27 +538,36 @@ sdf_status sdf_autotune(sdf_index ix, const sdf_span *qs, uint32_t n, const sdf_
         StreamScope scope(st);
         sdf_search_params q = *p;
         q.flags = (q.flags | SDF_TIMING) & ~(uint32_t)(SDF_EXTEND | SDF_SEED_ESTIMATE);
-        uint32_t best = 0;
+        const Params P = derive(&q, ix->k, ix->w);
+        // schedules tried: 1,024-thread workgroups at 512 .. 1,024 window
+        // starts, then 512-thread workgroups (two per CU) at 512 when the
+        // windows fit them
+        std::vector<std::pair<uint32_t, uint32_t>> sched;
+        for (uint32_t c = 512; c <= tile1024::tile_core_max(); c += 64) sched.push_back({1024u, c});
+        if (fits_tile512(P.n, ix->k)) sched.push_back({512u, tile512::tile_core_max()});
+        uint32_t best = 0, best_threads = 0;
         float best_ms = 0.f;
-        uint32_t t = 0;
-        for (uint32_t c = 512; c <= tile_core_max(); c += 64, t++) {
+        for (uint32_t t = 0; t < (uint32_t)sched.size(); t++) {
             float ms = 0.f;
             for (int rep = 0; rep < 2; rep++) {  // the first run warms the memory pool
                 sdf_result_s r;
                 r.device = ix->device;
                 r.st = st;
-                run_search(ix, qs, n, &q, st, &r, c);
+                run_search(ix, qs, n, &q, st, &r, sched[t].second, sched[t].first);
                 ms = r.ms[1];
                 SDF_HIP(hipStreamSynchronize(st));
             }
             if (ms_out && t < n_ms) ms_out[t] = ms;
             if (best == 0 || ms < best_ms) {
-                best = c;
+                best = sched[t].second;
+                best_threads = sched[t].first;
                 best_ms = ms;
             }
         }
         ix->tuned_core = best;
+        ix->tuned_threads = best_threads;
         if (core_out) *core_out = best;
+        if (threads_out) *threads_out = best_threads;
     });
 }
 

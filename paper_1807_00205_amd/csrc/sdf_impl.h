@@ -115,7 +115,8 @@ struct sdf_index_s {
     sdf::DevBuf<uint32_t> packed, mask, gaps;
     uint64_t nm = 0, ne = 0, nseg = 0;
     double hbar = 0.0;  // mean target occurrences of a query minimizer's hash
-    uint32_t tuned_core = 0;  // window starts per tile chosen by sdf_autotune (0: the rule)
+    uint32_t tuned_core = 0;
+    uint32_t tuned_threads = 0;  // tile workgroup layout chosen by sdf_autotune (0: rule)  // window starts per tile chosen by sdf_autotune (0: the rule)
     sdf::DevBuf<uint32_t> mpos, mhash, mprev, mext;
     sdf::DevBuf<uint8_t> mflags;
     sdf::DevBuf<uint32_t> dir, epos;

@@ -66,8 +66,16 @@ void launch_estimate_runs(const IndexView &ix, const uint32_t *runs, uint64_t nr
 
 void launch_span_setup(const IndexView &ix, SpanDesc *spans, uint32_t nspans, uint32_t n,
                        uint32_t core, uint32_t *ntiles, uint32_t *tile0, hipStream_t st);
+// The tile kernel in its two workgroup layouts (search.hip compiled twice):
+// 1,024 threads, one workgroup per CU; 512 threads, two per CU.
+namespace tile1024 {
 void launch_tile_search(const SearchArgs &a, uint32_t grid, hipStream_t st);
 uint32_t tile_core_max();
+}
+namespace tile512 {
+void launch_tile_search(const SearchArgs &a, uint32_t grid, hipStream_t st);
+uint32_t tile_core_max();
+}
 
 // Chaining (chain.hip): seeds -> sorted candidates; returns the candidate count.
 struct ChainOut {

@@ -20,20 +20,44 @@
 //      runs the run/argmax logic.
 // Large tiles split the target coordinate range into partitions processed
 // in order (run state of every window is kept across partitions).
+//
+// The file is compiled twice, for two workgroup layouts (SDF_TILE_THREADS):
+// 1,024 threads with 148 KB of LDS, one workgroup per CU, and 512 threads
+// with 77 KB, two per CU, whose barrier waits overlap each other's work
+// (faster where hits are sparse; its bin table is a quarter of the size, so
+// dense hit sets are kept less selectively).
 #include "kmer.h"
 #include "sdf_impl.h"
 #include "search.h"
 
-namespace sdf {
+#ifndef SDF_TILE_THREADS
+#define SDF_TILE_THREADS 1024
+#endif
 
+namespace sdf {
+#if SDF_TILE_THREADS == 1024
+namespace tile1024 {
 constexpr int TB = 1024;        // threads per tile workgroup
-constexpr int NWAVES = TB / 64;
 constexpr int QCAP = 1280;      // query minimizers per tile (core + halo)
 constexpr int CMAX = 1024;      // window starts per tile core
 constexpr int CB = 2048;        // kept hits per partition
 constexpr int TSLOTS = 16384;   // 16-bit counters in the bin table
-constexpr int TWORDS = TSLOTS / 2;
 constexpr int TSLOT_BITS = 14;
+#define SDF_TILE_WAVES_PER_EU 4
+#elif SDF_TILE_THREADS == 512
+namespace tile512 {
+constexpr int TB = 512;
+constexpr int QCAP = 1024;      // holds any window of up to 1,023 + k bases
+constexpr int CMAX = 512;
+constexpr int CB = 1024;
+constexpr int TSLOTS = 4096;
+constexpr int TSLOT_BITS = 12;
+#define SDF_TILE_WAVES_PER_EU 4  // two workgroups per CU: at most 128 VGPRs
+#else
+#error "SDF_TILE_THREADS must be 512 or 1024"
+#endif
+constexpr int NWAVES = TB / 64;
+constexpr int TWORDS = TSLOTS / 2;
 constexpr int SBUF = 32;        // seeds buffered per wave before one global atomic
 constexpr uint32_t HMAX = 65535;  // hits per partition (16-bit counters cannot overflow)
 constexpr int STACK = 40;
@@ -83,6 +107,7 @@ struct TileLds {
     union {  // bin table in the gather passes; scratch and seed buffers after
         uint32_t table[TWORDS];
         uint64_t scratch[TWORDS / 2];
+        uint32_t hot_area[(9 * CB) / 4 + 2];  // hot starts, flags, prefix sums
     } u;
     uint64_t coll[CB];
     uint32_t eseq[CB];
@@ -438,7 +463,8 @@ __device__ __forceinline__ void seeds_flush_block(const SearchArgs &a, TileLds &
     sb.n = 0;
 }
 
-__global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
+__global__ void __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(SDF_TILE_WAVES_PER_EU)))
+k_tile_search(SearchArgs a) {
     __shared__ TileLds L;
     const IndexView &ix = a.ix;
     const uint32_t n = a.n, k = ix.k;
@@ -1088,6 +1114,16 @@ __global__ void __launch_bounds__(TB) k_tile_search(SearchArgs a) {
         for (int t = 0; t < PH_N; t++) atomicAdd(&a.phase[t], (unsigned long long)L.ph[t]);
 }
 
+void launch_tile_search(const SearchArgs &a, uint32_t grid, hipStream_t st) {
+    k_tile_search<<<grid, TB, 0, st>>>(a);
+    SDF_HIP(hipGetLastError());
+}
+
+uint32_t tile_core_max() { return CMAX; }
+
+}  // namespace tile1024 / tile512
+
+#if SDF_TILE_THREADS == 1024  // the span set-up is compiled once
 // Per span: minimizer range of its window starts and its tile count.
 __global__ void k_span_setup(const IndexView ix, SpanDesc *spans, uint32_t nspans, uint32_t n,
                              uint32_t core, uint32_t *ntiles) {
@@ -1129,11 +1165,6 @@ void launch_span_setup(const IndexView &ix, SpanDesc *spans, uint32_t nspans, ui
     SDF_HIP(hipGetLastError());
 }
 
-void launch_tile_search(const SearchArgs &a, uint32_t grid, hipStream_t st) {
-    k_tile_search<<<grid, TB, 0, st>>>(a);
-    SDF_HIP(hipGetLastError());
-}
-
-uint32_t tile_core_max() { return CMAX; }
+#endif
 
 }  // namespace sdf

@@ -136,8 +136,8 @@ def lib() -> ctypes.CDLL:
         L.sdf_extend.restype = st
         L.sdf_extend.argtypes = [vp, vp, u64, P(_ExtendParams), vp, vp]
         L.sdf_autotune.restype = st
-        L.sdf_autotune.argtypes = [vp, vp, u32, P(_SearchParams), vp, P(u32), P(ctypes.c_float),
-                                   u32]
+        L.sdf_autotune.argtypes = [vp, vp, u32, P(_SearchParams), vp, P(u32), P(u32),
+                                   P(ctypes.c_float), u32]
         L.sdf_qgram_filter.restype = st
         L.sdf_qgram_filter.argtypes = [vp, vp, u64, P(_QgramParams), vp, vp, vp]
         L.sdf_result_regions.restype = st
@@ -316,18 +316,23 @@ class Index:
 
     def autotune(self, spans: Iterable[Tuple[int, int, int]], max_error: float = 0.25,
                  min_len: int = 1000, stream=None):
-        """Times the tile kernel at every tile size on these spans and keeps the
-        fastest for later searches (``sdf_autotune``); returns (size, times in
-        ms per size 512, 576, ..., 1024).  No spans: back to the built-in rule."""
+        """Times the tile kernel on these spans with every schedule and keeps the
+        fastest for later searches (``sdf_autotune``); returns (window starts,
+        workgroup threads, {(threads, window starts): ms}).  No spans: back to
+        the built-in rules."""
         spans = list(spans)
         arr = (_Span * max(1, len(spans)))(*[_Span(s, 0, b, e) for (s, b, e) in spans])
         p = _SearchParams(max_error, min_len, 0)
-        core = ctypes.c_uint32()
+        core, threads = ctypes.c_uint32(), ctypes.c_uint32()
         ms = (ctypes.c_float * 16)()
         _check(lib().sdf_autotune(self._h, ctypes.cast(arr, ctypes.c_void_p), len(spans),
-                                  ctypes.byref(p), _stream_ptr(stream), ctypes.byref(core), ms,
-                                  16))
-        return core.value, [float(x) for x in ms[:9]]
+                                  ctypes.byref(p), _stream_ptr(stream), ctypes.byref(core),
+                                  ctypes.byref(threads), ms, 16))
+        sched = [(1024, c) for c in range(512, 1025, 64)]
+        if min_len <= 1023 + self.k:
+            sched.append((512, 512))
+        times = {k: float(ms[i]) for i, k in enumerate(sched)} if spans else {}
+        return core.value, threads.value, times
 
     def qgram_filter(self, regions: np.ndarray, q: int, gap_rate: float,
                      max_error: float = 0.25, stream=None):

@@ -279,6 +279,37 @@ def test_chaining_fused_equals_general(S, oracle_lib, monkeypatch):
     assert ("fused", True) in seen and ("general", False) in seen
 
 
+@pytest.mark.parametrize("threads", ["512", "1024"])
+def test_tile_layouts(S, oracle_lib, monkeypatch, threads):
+    """Both workgroup layouts of the tile kernel (1,024 threads with 1,280
+    query minimizers, 2,048 kept hits and 16k bin slots per tile; 512 threads,
+    two per CU, with 1,024, 1,024 and 4k) give the oracle's seeds and
+    candidates, in count and estimate mode, on planted duplications in
+    several sequences, tandem arrays and 1 Mbp with 20 duplications; the
+    narrow one also with its smallest partitions."""
+    monkeypatch.setenv("SDF_TILE_THREADS", threads)
+    cases = [(_mixed_genome(7, length=8000), 200, False),
+             (synth.tandem_case(94, length=200_000, n_arrays=120, copies_hi=60, n_seqs=2), 200,
+              False),
+             (synth.tandem_case(96, length=40_000, n_arrays=20, copies_hi=40, n_seqs=2), 400,
+              True),
+             (synth.config1(), 1000, False)]
+    for g, min_len, est in cases:
+        b, off = g.concat()
+        spans = list(g.spans) + [(0, 100, len(g.seqs[0]) - 50)]
+        orc = oracle_lib.OracleIndex(b, off, 12, 16)
+        os_, oc = orc.search(spans, 0.25, min_len, estimate=est)
+        ix = S.Index(g.seqs, 12, 16)
+        for hp in (["16384", "1024"] if threads == "512" else ["16384"]):
+            monkeypatch.setenv("SDF_HITS_PER_PART", hp)
+            r = ix.search_batch(spans, 0.25, min_len, estimate=est)
+            assert len(os_) > 0
+            _same(r.seeds(), os_, SEED_F, "seeds")
+            _same(r.candidates(), oc, CAND_F, "candidates")
+        monkeypatch.delenv("SDF_HITS_PER_PART")
+        ix.close()
+
+
 @pytest.mark.parametrize("path", ["prefix", "long_ties", "general"])
 def test_candidate_sort_paths(S, oracle_lib, monkeypatch, path):
     """Every sort of the chained candidates gives the oracle's order: radix
@@ -462,17 +493,18 @@ def test_serving_admission_budget(S, batch250):
 
 
 def test_autotune_keeps_results(S):
-    """sdf_autotune times every tile size on a span set and keeps the fastest;
-    searches after it return the same seeds and candidates, and forgetting
-    the choice restores the built-in rule."""
+    """sdf_autotune times every tile schedule (both workgroup layouts) on a
+    span set and keeps the fastest; searches after it return the same seeds
+    and candidates, and forgetting the choice restores the built-in rules."""
     g = synth.config1()
     ix = S.Index(g.seqs, 12, 16)
     spans = synth.draw_spans(synth.rng_for(12), [len(s) for s in g.seqs], 48, 5000, 60000)
     r0 = ix.search_batch(spans)
     c0, s0 = r0.candidates(), r0.seeds()
-    core, ms = ix.autotune(spans)
-    assert core in range(512, 1025, 64)
-    assert all(m > 0 for m in ms) and ms[(core - 512) // 64] == min(ms)
+    core, threads, ms = ix.autotune(spans)
+    assert len(ms) == 10 and (512, 512) in ms
+    assert (threads, core) in ms and ms[(threads, core)] == min(ms.values())
+    assert all(m > 0 for m in ms.values())
     r1 = ix.search_batch(spans)
     _same(r1.seeds(), s0, SEED_F, "seeds after autotune")
     _same(r1.candidates(), c0, CAND_F, "candidates after autotune")

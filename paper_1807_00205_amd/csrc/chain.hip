@@ -708,6 +708,94 @@ __global__ void k_cand_ties(const uint64_t *key, uint64_t nc, uint32_t tie_max, 
     }
 }
 
+// Stable radix sort (8-bit digits, least significant first) of up to SR_N
+// keys below 2^50 by one workgroup, in a single launch: every thread keeps
+// 16 keys, each packed with its index in the low 14 bits, in registers; per
+// pass each wave ranks its 1,024 keys by digit with ballots, and the keys are
+// placed in LDS at their new positions and read back.  order[t] receives the
+// index of the t-th key and key[t] the key itself (in place: every key is in
+// registers before the first barrier).
+constexpr int SR_TB = 1024, SR_WAVES = SR_TB / 64, SR_PER = 16, SR_N = SR_TB * SR_PER;
+constexpr int SR_IDX = 14;
+static_assert((1 << SR_IDX) == SR_N, "index field");
+
+__global__ void __launch_bounds__(SR_TB) k_sort_small(uint64_t *key, uint32_t n, int bits,
+                                                      uint32_t *order) {
+    __shared__ uint64_t buf[SR_N];
+    __shared__ uint32_t cnt[SR_WAVES][256];
+    __shared__ uint32_t dstart[256];
+    __shared__ uint32_t wsum[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    uint64_t v[SR_PER];
+#pragma unroll
+    for (int r = 0; r < SR_PER; r++) {
+        const uint32_t e = (uint32_t)wave * 1024u + (uint32_t)r * 64u + (uint32_t)lane;
+        v[r] = e < n ? (key[e] << SR_IDX) | e : ~0ull;  // padding sorts last (stable)
+    }
+    for (int sh = SR_IDX; sh < SR_IDX + bits; sh += 8) {
+        for (int i = threadIdx.x; i < SR_WAVES * 256; i += SR_TB) (&cnt[0][0])[i] = 0;
+        __syncthreads();
+        uint32_t rk[SR_PER];
+#pragma unroll
+        for (int r = 0; r < SR_PER; r++) {
+            const uint32_t d = (uint32_t)(v[r] >> sh) & 255u;
+            uint64_t m = ~0ull;
+#pragma unroll
+            for (int b = 0; b < 8; b++) {
+                const bool bit = (d >> b) & 1;
+                const uint64_t bb = __ballot(bit);
+                m &= bit ? bb : ~bb;
+            }
+            rk[r] = cnt[wave][d] + (uint32_t)__popcll(m & lt);
+            __builtin_amdgcn_wave_barrier();
+            if ((m >> lane) == 1ull) cnt[wave][d] += (uint32_t)__popcll(m);
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+        // per digit: offsets of the waves within it, then the digit's start
+        uint32_t tot = 0;
+        if (threadIdx.x < 256) {
+            for (int w = 0; w < SR_WAVES; w++) {
+                const uint32_t c = cnt[w][threadIdx.x];
+                cnt[w][threadIdx.x] = tot;
+                tot += c;
+            }
+        }
+        uint32_t x = tot;
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(x, d, 64);
+            if (lane >= d) x += y;
+        }
+        if (threadIdx.x < 256 && lane == 63) wsum[wave] = x;
+        __syncthreads();
+        if (threadIdx.x < 256) {
+            uint32_t before = 0;
+            for (int w = 0; w < wave; w++) before += wsum[w];
+            dstart[threadIdx.x] = before + x - tot;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < SR_PER; r++) {
+            const uint32_t d = (uint32_t)(v[r] >> sh) & 255u;
+            buf[dstart[d] + cnt[wave][d] + rk[r]] = v[r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < SR_PER; r++)
+            v[r] = buf[(uint32_t)wave * 1024u + (uint32_t)r * 64u + (uint32_t)lane];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < SR_PER; r++) {
+        const uint32_t e = (uint32_t)wave * 1024u + (uint32_t)r * 64u + (uint32_t)lane;
+        if (e < n) {
+            order[e] = (uint32_t)(v[r] & (SR_N - 1));
+            key[e] = v[r] >> SR_IDX;
+        }
+    }
+}
+
 static uint32_t bitlen(uint64_t v);
 
 // Sorts the nc candidates of `cands` (capacity >= the next power of two).
@@ -724,7 +812,17 @@ static void finish_candidates(DevBuf<sdf_candidate> &cands, uint64_t nc, const I
         DevBuf<uint32_t> order(nc);
         k_cand_prefix<<<nb(nc), 256, 0, st>>>(cands.p, nc, CandPrefix{sb, pb, shift}, key.p, order.p);
         SDF_HIP(hipGetLastError());
-        radix_sort_u64(key.p, order.p, nc, (int)(head + pb - shift), st);
+        const int kbits = (int)(head + pb - shift);
+        // test hook: SDF_CAND_SORT_SMALL_MAX lowers the count sorted by one workgroup
+        uint64_t small_max = SR_N;
+        if (const char *v = std::getenv("SDF_CAND_SORT_SMALL_MAX"))
+            small_max = std::min<uint64_t>(SR_N, std::strtoull(v, nullptr, 10));
+        if (nc <= small_max && kbits <= 50) {
+            k_sort_small<<<1, SR_TB, 0, st>>>(key.p, (uint32_t)nc, kbits, order.p);
+            SDF_HIP(hipGetLastError());
+        } else {
+            radix_sort_u64(key.p, order.p, nc, kbits, st);
+        }
         DevBuf<sdf_candidate> sorted(n2);
         k_permute_cands<<<nb(nc), 256, 0, st>>>(cands.p, order.p, nc, sorted.p);
         SDF_HIP(hipGetLastError());

@@ -310,13 +310,17 @@ def test_tile_layouts(S, oracle_lib, monkeypatch, threads):
         ix.close()
 
 
-@pytest.mark.parametrize("path", ["prefix", "long_ties", "general"])
+@pytest.mark.parametrize("path", ["prefix", "prefix_multiblock", "long_ties", "general"])
 def test_candidate_sort_paths(S, oracle_lib, monkeypatch, path):
-    """Every sort of the chained candidates gives the oracle's order: radix
-    keys on a prefix of query, strand, sequence and begin with ties ordered in
-    place, the same with every tie sent to the bitonic sort of records, and
-    that bitonic sort alone; on batches with several query spans, sequences
-    and both strands, and on tandem arrays whose candidates share begins."""
+    """Every sort of the chained candidates gives the oracle's order: keys on
+    a prefix of query, strand, sequence and begin (sorted by one workgroup,
+    or by the multi-block radix sort used above 16,384 candidates) with ties
+    ordered in place, the same with every tie sent to the bitonic sort of
+    records, and that bitonic sort alone; on batches with several query
+    spans, sequences and both strands, and on tandem arrays whose candidates
+    share begins."""
+    if path == "prefix_multiblock":
+        monkeypatch.setenv("SDF_CAND_SORT_SMALL_MAX", "0")
     if path == "long_ties":
         monkeypatch.setenv("SDF_CAND_TIE_MAX", "1")
     if path == "general":

@@ -320,6 +320,14 @@ __device__ __forceinline__ uint32_t list_of(const uint32_t *hoff, uint32_t nl, u
 // the block's first and last hit bound each lane's list search, and every
 // position load is issued before any is used.
 constexpr int HU = 8;
+// In the 512-thread layout the hits [0, STASH) of a partition that pass 1
+// gathers (position and list) are kept for pass 2 in the arrays that hold
+// kept-hit data only later, so pass 2 reads them from LDS instead of
+// searching the lists and loading positions again (most of its partitions
+// hold fewer).  The 1,024-thread layout gathers twice: there the kept copy
+// cost more in register spills than it saved.
+constexpr uint32_t STASH = TB == 512 ? 1536 : 0;
+static_assert(STASH % (64 * HU) == 0, "the stash holds whole wave rounds");
 __device__ __forceinline__ void gather_hits(const TileLds &L, const IndexView &ix, uint32_t nl,
                                             uint32_t H, uint32_t cb, uint32_t lane,
                                             uint32_t (&pv)[HU], uint32_t (&lv)[HU]) {
@@ -757,14 +765,26 @@ k_tile_search(SearchArgs a) {
                 for (uint32_t t = threadIdx.x; t < TWORDS; t += TB) L.u.table[t] = 0;
                 __syncthreads();
                 const uint32_t SB = a.bin_shift;
+                uint32_t *stash_p = L.eseq;                                        // STASH x u32
+                uint16_t *stash_l = reinterpret_cast<uint16_t *>(L.eseq + STASH);  // STASH x u16
+                static_assert(offsetof(TileLds, einfo) + sizeof(uint32_t) * CB -
+                                  offsetof(TileLds, eseq) >= STASH * 6,
+                              "the stash exceeds the kept-hit arrays");
                 // Each wave takes HU * 64 consecutive hits per round and issues
                 // all their position loads before using any, so a thread waits
-                // for memory once per round instead of once per hit.  The
-                // first round's hits stay in registers for pass 2.
+                // for memory once per round instead of once per hit.
                 for (uint32_t r0 = 0; r0 < H; r0 += TB * HU) {
                     const uint32_t cb = r0 + (uint32_t)wave * 64 * HU;
                     uint32_t pv[HU], lv[HU];
                     gather_hits(L, ix, nl, H, cb, lane, pv, lv);
+                    if (cb < STASH) {
+#pragma unroll
+                        for (int u = 0; u < HU; u++) {
+                            const uint32_t e = cb + (uint32_t)u * 64 + lane;
+                            stash_p[e] = pv[u];
+                            stash_l[e] = (uint16_t)lv[u];  // NONE32 -> 0xFFFF
+                        }
+                    }
 #pragma unroll
                     for (int u = 0; u < HU; u++) {
                         if (lv[u] == NONE32) continue;
@@ -784,7 +804,17 @@ k_tile_search(SearchArgs a) {
                 for (uint32_t r0 = 0; r0 < H; r0 += TB * HU) {
                     const uint32_t cb = r0 + (uint32_t)wave * 64 * HU;
                     uint32_t pv[HU], lv[HU];
-                    gather_hits(L, ix, nl, H, cb, lane, pv, lv);
+                    if (cb < STASH) {
+#pragma unroll
+                        for (int u = 0; u < HU; u++) {
+                            const uint32_t e = cb + (uint32_t)u * 64 + lane;
+                            const uint32_t l = stash_l[e];
+                            pv[u] = stash_p[e];
+                            lv[u] = (e < H && l != 0xFFFFu) ? l : NONE32;
+                        }
+                    } else {
+                        gather_hits(L, ix, nl, H, cb, lane, pv, lv);
+                    }
 #pragma unroll
                     for (int u = 0; u < HU; u++) {
                         if (lv[u] == NONE32) continue;

@@ -710,8 +710,9 @@ __global__ void k_cand_ties(const uint64_t *key, uint64_t nc, uint32_t tie_max, 
 
 // Stable radix sort (8-bit digits, least significant first) of up to SR_N
 // keys below 2^50 by one workgroup, in a single launch: every thread keeps
-// 16 keys, each packed with its index in the low 14 bits, in registers; per
-// pass each wave ranks its 1,024 keys by digit with ballots, and the keys are
+// up to 16 keys, each packed with its index in the low 14 bits, in registers
+// (each wave a contiguous run of 64 x rounds keys, rounds = ceil(n / 1024));
+// per pass each wave ranks its keys by digit with ballots, and the keys are
 // placed in LDS at their new positions and read back.  order[t] receives the
 // index of the t-th key and key[t] the key itself (in place: every key is in
 // registers before the first barrier).
@@ -727,11 +728,13 @@ __global__ void __launch_bounds__(SR_TB) k_sort_small(uint64_t *key, uint32_t n,
     __shared__ uint32_t wsum[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const uint32_t rounds = (n + SR_TB - 1) / SR_TB;  // <= SR_PER
+    const uint32_t chunk = rounds * 64u;               // keys per wave
     uint64_t v[SR_PER];
 #pragma unroll
     for (int r = 0; r < SR_PER; r++) {
-        const uint32_t e = (uint32_t)wave * 1024u + (uint32_t)r * 64u + (uint32_t)lane;
-        v[r] = e < n ? (key[e] << SR_IDX) | e : ~0ull;  // padding sorts last (stable)
+        const uint32_t e = (uint32_t)wave * chunk + (uint32_t)r * 64u + (uint32_t)lane;
+        v[r] = ((uint32_t)r < rounds && e < n) ? (key[e] << SR_IDX) | e : ~0ull;  // padding last
     }
     for (int sh = SR_IDX; sh < SR_IDX + bits; sh += 8) {
         for (int i = threadIdx.x; i < SR_WAVES * 256; i += SR_TB) (&cnt[0][0])[i] = 0;
@@ -739,6 +742,7 @@ __global__ void __launch_bounds__(SR_TB) k_sort_small(uint64_t *key, uint32_t n,
         uint32_t rk[SR_PER];
 #pragma unroll
         for (int r = 0; r < SR_PER; r++) {
+            if ((uint32_t)r >= rounds) break;
             const uint32_t d = (uint32_t)(v[r] >> sh) & 255u;
             uint64_t m = ~0ull;
 #pragma unroll
@@ -777,18 +781,22 @@ __global__ void __launch_bounds__(SR_TB) k_sort_small(uint64_t *key, uint32_t n,
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < SR_PER; r++) {
+            if ((uint32_t)r >= rounds) break;
             const uint32_t d = (uint32_t)(v[r] >> sh) & 255u;
             buf[dstart[d] + cnt[wave][d] + rk[r]] = v[r];
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < SR_PER; r++)
-            v[r] = buf[(uint32_t)wave * 1024u + (uint32_t)r * 64u + (uint32_t)lane];
+        for (int r = 0; r < SR_PER; r++) {
+            if ((uint32_t)r >= rounds) break;
+            v[r] = buf[(uint32_t)wave * chunk + (uint32_t)r * 64u + (uint32_t)lane];
+        }
         __syncthreads();
     }
 #pragma unroll
     for (int r = 0; r < SR_PER; r++) {
-        const uint32_t e = (uint32_t)wave * 1024u + (uint32_t)r * 64u + (uint32_t)lane;
+        if ((uint32_t)r >= rounds) break;
+        const uint32_t e = (uint32_t)wave * chunk + (uint32_t)r * 64u + (uint32_t)lane;
         if (e < n) {
             order[e] = (uint32_t)(v[r] & (SR_N - 1));
             key[e] = v[r] >> SR_IDX;

@@ -173,10 +173,20 @@ __global__ void __launch_bounds__(SC_THREADS) k_scan_reduce(const T *in, uint64_
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
+// The block's offset is boff[block] when given, else (sums given) the sum of
+// the block totals before it, added up by the block itself (one launch less
+// than scanning the totals first; used while there are few blocks).
 template <class T, class O>
 __global__ void __launch_bounds__(SC_THREADS) k_scan_down(const T *in, uint64_t n, const uint64_t *boff,
-                                                      O *out, int write_total) {
+                                                      const uint64_t *sums, O *out,
+                                                      int write_total) {
     __shared__ uint64_t lds[17];
+    uint64_t off = boff ? boff[blockIdx.x] : 0;
+    if (sums) {
+        uint64_t part = 0;
+        for (uint64_t b = threadIdx.x; b < blockIdx.x; b += SC_THREADS) part += sums[b];
+        block_excl_scan(part, lds, &off);
+    }
     uint64_t base = (uint64_t)blockIdx.x * SC_TILE + (uint64_t)threadIdx.x * SC_ITEMS;
     uint64_t v[SC_ITEMS];
     uint64_t s = 0;
@@ -186,7 +196,7 @@ __global__ void __launch_bounds__(SC_THREADS) k_scan_down(const T *in, uint64_t 
         s += v[t];
     }
     uint64_t tot;
-    uint64_t pre = block_excl_scan(s, lds, &tot) + (boff ? boff[blockIdx.x] : 0);
+    uint64_t pre = block_excl_scan(s, lds, &tot) + off;
 #pragma unroll
     for (int t = 0; t < SC_ITEMS; t++) {
         if (base + t < n) out[base + t] = (O)pre;
@@ -196,20 +206,28 @@ __global__ void __launch_bounds__(SC_THREADS) k_scan_down(const T *in, uint64_t 
         out[n] = (O)pre;
 }
 
+// Blocks up to which each down-sweep block adds up the totals before it.
+constexpr uint64_t SC_FUSE_MAX = 8192;
+
 template <class T, class O>
 static void scan_impl(const T *in, O *out, uint64_t n, hipStream_t st) {
     uint64_t nb = (n + SC_TILE - 1) / SC_TILE;
     if (nb <= 1) {
-        k_scan_down<T, O><<<1, SC_THREADS, 0, st>>>(in, n, nullptr, out, 1);
+        k_scan_down<T, O><<<1, SC_THREADS, 0, st>>>(in, n, nullptr, nullptr, out, 1);
         SDF_HIP(hipGetLastError());
         return;
     }
     DevBuf<uint64_t> sums(nb + 1);
     k_scan_reduce<T><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, n, sums.p);
     SDF_HIP(hipGetLastError());
+    if (nb <= SC_FUSE_MAX) {
+        k_scan_down<T, O><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, n, nullptr, sums.p, out, 1);
+        SDF_HIP(hipGetLastError());
+        return;
+    }
     DevBuf<uint64_t> off(nb + 1);
     scan_impl<uint64_t, uint64_t>(sums.p, off.p, nb, st);
-    k_scan_down<T, O><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, n, off.p, out, 1);
+    k_scan_down<T, O><<<(unsigned)nb, SC_THREADS, 0, st>>>(in, n, off.p, nullptr, out, 1);
     SDF_HIP(hipGetLastError());
 }
 

@@ -126,9 +126,8 @@ __device__ uint32_t estimate_finish(W &L, const uint32_t *out, uint8_t *first, u
     const uint32_t lane = e_lane();
     const uint32_t nw = (s + 63) >> 6;
     __builtin_amdgcn_wave_barrier();
-    uint32_t c = 0;  // shared count
-    if (lane < nw) c = (uint32_t)__popcll(L.cbits[lane]);
-    for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
+    uint32_t c = 0;  // shared count (every lane reads the nw words: LDS broadcasts)
+    for (uint32_t w = 0; w < nw; w++) c += (uint32_t)__popcll(L.cbits[w]);
     if (have && c <= beat) return c;
     // y: distinct outside hashes among the s smallest of the union: b is one
     // iff (distinct outside hashes below b) + (hashes of W_i below b) < s
@@ -197,14 +196,11 @@ __device__ uint32_t estimate_finish(W &L, const uint32_t *out, uint8_t *first, u
     // m: shared hashes of rank < s - y in W_i
     const uint32_t lim = s - y;
     uint32_t m = 0;
-    if (lane < nw) {
-        uint64_t w = L.cbits[lane];
-        const uint32_t b0 = lane * 64;
-        if (lim <= b0) w = 0;
-        else if (lim < b0 + 64) w &= (1ull << (lim - b0)) - 1;
-        m = (uint32_t)__popcll(w);
+    for (uint32_t x = 0; x < nw && x * 64 < lim; x++) {
+        uint64_t w = L.cbits[x];
+        if (lim < x * 64 + 64) w &= (1ull << (lim - x * 64)) - 1;
+        m += (uint32_t)__popcll(w);
     }
-    for (int d = 32; d > 0; d >>= 1) m += __shfl_xor(m, d, 64);
     return m;
 }
 

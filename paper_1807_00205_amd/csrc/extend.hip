@@ -315,14 +315,18 @@ struct EvList {
     uint32_t base;  // element id of index lo
 };
 
-// Inclusive prefix sum over the lanes of the wave.
+// Inclusive prefix sum over the lanes of the wave, with DPP moves (register
+// to register, no trip through the LDS crossbar): prefix within each row of
+// 16 lanes, then the last lane of row 0 and of row 2 into rows 1 and 3, then
+// lane 31 into rows 2 and 3.  Lanes without a source add 0.
 __device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v) {
-    const uint32_t lane = threadIdx.x & 63;
-#pragma unroll
-    for (uint32_t d = 1; d < 64; d <<= 1) {
-        const uint32_t t = __shfl_up(v, d, 64);
-        if (lane >= d) v += t;
-    }
+    constexpr int ROW_SHR = 0x110, ROW_BCAST15 = 0x142, ROW_BCAST31 = 0x143;
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, ROW_SHR + 1, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, ROW_SHR + 2, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, ROW_SHR + 4, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, ROW_SHR + 8, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, ROW_BCAST15, 0xa, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, ROW_BCAST31, 0xc, 0xf, false);
     return v;
 }
 

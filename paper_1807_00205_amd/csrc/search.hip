@@ -149,6 +149,17 @@ __device__ __forceinline__ uint32_t wave_max_scan(uint32_t x) {
     return x;
 }
 
+// Inclusive sum-scan over the 64 lanes of a wave, the same DPP pattern.
+__device__ __forceinline__ uint32_t wave_sum_scan(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, DPP_ROW_SHR + 1, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, DPP_ROW_SHR + 2, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, DPP_ROW_SHR + 4, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, DPP_ROW_SHR + 8, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, DPP_ROW_BCAST15, 0xa, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, DPP_ROW_BCAST31, 0xc, 0xf, false);
+    return x;
+}
+
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 
@@ -159,11 +170,7 @@ __device__ uint32_t block_scan_u32(uint32_t *arr, int n, uint64_t *wtmp) {
     uint32_t s = 0;
     for (int t = 0; t < per; t++)
         if (b + t < n) s += arr[b + t];
-    uint32_t x = s;
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t y = __shfl_up(x, d, 64);
-        if (lane_id() >= d) x += y;
-    }
+    const uint32_t x = wave_sum_scan(s);
     if (lane_id() == 63) wtmp[wave_id()] = x;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -198,11 +205,7 @@ __device__ void block_maxscan_u32(uint32_t *arr, int n, uint64_t *wtmp) {
     uint32_t m = 0;
     for (int t = 0; t < per; t++)
         if (b + t < n) m = arr[b + t] > m ? arr[b + t] : m;
-    uint32_t x = m;
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t y = __shfl_up(x, d, 64);
-        if (lane_id() >= d) x = y > x ? y : x;
-    }
+    const uint32_t x = wave_max_scan(m);
     if (lane_id() == 63) wtmp[wave_id()] = x;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -214,8 +217,7 @@ __device__ void block_maxscan_u32(uint32_t *arr, int n, uint64_t *wtmp) {
         }
     }
     __syncthreads();
-    uint32_t pre = __shfl_up(x, 1, 64);
-    if (lane_id() == 0) pre = 0;
+    uint32_t pre = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, DPP_WAVE_SHR1, 0xf, 0xf, false);
     pre = (uint32_t)wtmp[wave_id()] > pre ? (uint32_t)wtmp[wave_id()] : pre;
     for (int t = 0; t < per; t++) {
         if (b + t < n) {

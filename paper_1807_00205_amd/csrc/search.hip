@@ -4,9 +4,9 @@
 // minimizers are found; the best j of each run of consecutive passing
 // targets is a seed.
 //
-// One workgroup (1024 threads) owns a tile: up to TILE_CORE consecutive
-// minimizers of the span as window starts plus the halo of minimizers the
-// last window reaches.  All hits of the tile stay on chip:
+// One workgroup owns a tile: up to `core` consecutive minimizers of the span
+// as window starts plus the halo of minimizers the last window reaches.  All
+// hits of the tile stay on chip:
 //   1. gather pass 1: every hit (p, p', o) increments a counter for its
 //      (orientation, target bin of 2^SB >= n bases) in an LDS hash table;
 //   2. gather pass 2: a hit is kept only if some pair of adjacent bins around

@@ -108,6 +108,20 @@ __device__ void wave_bitonic(uint64_t *key, uint32_t m) {
     }
 }
 
+// The value of lane ^ j (j < 64, a power of two, known at compile time where
+// the sort is unrolled): quad permutations (DPP) for 1 and 2, a swizzle
+// within 32 lanes for 4 to 16, a permute for 32.
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v, uint32_t j) {
+    switch (j) {
+    case 1: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xf, 0xf, false);  // [1,0,3,2]
+    case 2: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xf, 0xf, false);  // [2,3,0,1]
+    case 4: return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (4 << 10) | 0x1F);
+    case 8: return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (8 << 10) | 0x1F);
+    case 16: return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (16 << 10) | 0x1F);
+    default: return (uint32_t)__shfl_xor((int)v, (int)j, 64);
+    }
+}
+
 // Number of hashes in ahash[0, s) below h.
 __device__ __forceinline__ uint32_t rank_below(const uint32_t *ahash, uint32_t s, uint32_t h) {
     uint32_t lo = 0, hi = s;
@@ -139,15 +153,17 @@ __device__ uint32_t estimate_finish(W &L, const uint32_t *out, uint8_t *first, u
         // distinct outside hashes is a popcount of those firsts
         uint32_t x0 = lane < nb ? out[lane] : 0xFFFFFFFFu;
         uint32_t x1 = lane + 64 < nb ? out[lane + 64] : 0xFFFFFFFFu;
+#pragma unroll
         for (uint32_t k = 2; k <= 128; k <<= 1) {
+#pragma unroll
             for (uint32_t j = k >> 1; j > 0; j >>= 1) {
                 if (j == 64) {  // k = 128: elements lane and lane + 64, ascending
                     const uint32_t lo = min(x0, x1), hi = max(x0, x1);
                     x0 = lo;
                     x1 = hi;
                 } else {
-                    const uint32_t y0 = (uint32_t)__shfl_xor((int)x0, (int)j, 64);
-                    const uint32_t y1 = (uint32_t)__shfl_xor((int)x1, (int)j, 64);
+                    const uint32_t y0 = lane_xor(x0, j);
+                    const uint32_t y1 = lane_xor(x1, j);
                     const bool lower = (lane & j) == 0;
                     const bool asc0 = (lane & k) == 0, asc1 = ((lane + 64) & k) == 0;
                     x0 = (lower == asc0) ? min(x0, y0) : max(x0, y0);

@@ -240,17 +240,18 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
     uint32_t sb = 0;
     while ((1u << sb) < P.n) sb++;
     uint64_t cap = qbases / 8 + 65536;
-    DevBuf<unsigned long long> counters(CNT_N);
+    // work counters, phase timers and (work item, error word) in one block,
+    // cleared by one fill before each attempt
+    DevBuf<unsigned long long> zblock(CNT_N + PH_N + 1);
+    unsigned long long *const counters = zblock.p;
+    unsigned long long *const phase = zblock.p + CNT_N;
+    uint32_t *const work = reinterpret_cast<uint32_t *>(zblock.p + CNT_N + PH_N);
     const bool phase_prof = env_u32("SDF_PHASE_PROF", 0) != 0;
-    DevBuf<unsigned long long> phase(PH_N);
-    DevBuf<uint32_t> work(2);
     std::vector<unsigned long long> hc(CNT_N);
     uint32_t herr = 0;
     for (int attempt = 0; attempt < 3; attempt++) {
         res->seeds.alloc(cap * 6);
-        SDF_HIP(hipMemsetAsync(counters.p, 0, CNT_N * 8, st));
-        SDF_HIP(hipMemsetAsync(work.p, 0, 8, st));
-        SDF_HIP(hipMemsetAsync(phase.p, 0, PH_N * 8, st));
+        SDF_HIP(hipMemsetAsync(zblock.p, 0, zblock.n * 8, st));
         if (nq) {
             SearchArgs a;
             a.ix = ix->view();
@@ -260,15 +261,15 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
             a.spans = dsd.p;
             a.nspans = nq;
             a.total_tiles = tile0.p + nq;
-            a.work = work.p;
+            a.work = work;
             a.core = core;
             a.hpart = hpart;
             a.bin_shift = sb;
             a.seeds = res->seeds.p;
             a.seed_cap = cap;
-            a.counters = counters.p;
-            a.err = work.p + 1;
-            a.phase = phase_prof ? phase.p : nullptr;
+            a.counters = counters;
+            a.err = work + 1;
+            a.phase = phase_prof ? phase : nullptr;
             a.runs_out = (p->flags & SDF_SEED_ESTIMATE) ? 1u : 0u;
             // persistent grid, as many workgroups as fit the CUs: workgroups
             // past the last tile exit at once
@@ -279,10 +280,13 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
             else tile1024::launch_tile_search(a, std::max<uint32_t>(grid, 1), st);
             tm.mark_kernel_end();
         }
-        SDF_HIP(hipMemcpyAsync(hc.data(), counters.p, CNT_N * 8, hipMemcpyDeviceToHost, st));
-        SDF_HIP(hipMemcpyAsync(&herr, work.p + 1, 4, hipMemcpyDeviceToHost, st));
-        if (nq) SDF_HIP(hipMemcpyAsync(&total_tiles, tile0.p + nq, 4, hipMemcpyDeviceToHost, st));
-        SDF_HIP(hipStreamSynchronize(st));
+        {
+            Readback rb(st);
+            rb.add(hc.data(), counters, CNT_N * 8);
+            rb.add(&herr, work + 1, 4);
+            if (nq) rb.add(&total_tiles, tile0.p + nq, 4);
+            rb.wait();
+        }
         if (herr) break;
         if (hc[CNT_SEEDS] <= cap) break;
         cap = hc[CNT_SEEDS] + hc[CNT_SEEDS] / 8 + 1024;
@@ -300,7 +304,7 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
     if (phase_prof) {
         // per-phase wall-clock ticks summed over workgroups (diagnostic)
         std::vector<unsigned long long> ph(PH_N);
-        SDF_HIP(hipMemcpyAsync(ph.data(), phase.p, PH_N * 8, hipMemcpyDeviceToHost, st));
+        SDF_HIP(hipMemcpyAsync(ph.data(), phase, PH_N * 8, hipMemcpyDeviceToHost, st));
         SDF_HIP(hipStreamSynchronize(st));
         int khz = 0;
         SDF_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ix->device));
@@ -333,9 +337,12 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
                              eerr.p, st);
         unsigned long long ne = 0;
         uint32_t ee = 0;
-        SDF_HIP(hipMemcpyAsync(&ne, ecount.p, 8, hipMemcpyDeviceToHost, st));
-        SDF_HIP(hipMemcpyAsync(&ee, eerr.p, 4, hipMemcpyDeviceToHost, st));
-        SDF_HIP(hipStreamSynchronize(st));
+        {
+            Readback rb(st);
+            rb.add(&ne, ecount.p, 8);
+            rb.add(&ee, eerr.p, 4);
+            rb.wait();
+        }
         if (ee & 1)
             throw Error{SDF_EINTERNAL, "estimate: a window holds more than 1024 minimizers"};
         if (ee)

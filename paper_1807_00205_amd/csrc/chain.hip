@@ -843,8 +843,11 @@ static void finish_candidates(DevBuf<sdf_candidate> &cands, uint64_t nc, const I
         k_cand_ties<<<nb(nc), 256, 0, st>>>(key.p, nc, tie_max, sorted.p, flag.p);
         SDF_HIP(hipGetLastError());
         uint32_t long_run = 0;
-        SDF_HIP(hipMemcpyAsync(&long_run, flag.p, 4, hipMemcpyDeviceToHost, st));
-        SDF_HIP(hipStreamSynchronize(st));
+        {
+            Readback rb(st);
+            rb.add(&long_run, flag.p, 4);
+            rb.wait();
+        }
         cands = std::move(sorted);
         if (!long_run) return;
         general = true;
@@ -890,8 +893,11 @@ void chain_seeds(const IndexView &ix, const uint32_t *seeds, uint64_t ns, uint32
                                            out.cands.p, cnt.p);
         SDF_HIP(hipGetLastError());
         uint32_t nc = 0;
-        SDF_HIP(hipMemcpyAsync(&nc, cnt.p, 4, hipMemcpyDeviceToHost, st));
-        SDF_HIP(hipStreamSynchronize(st));
+        {
+            Readback rb(st);
+            rb.add(&nc, cnt.p, 4);
+            rb.wait();
+        }
         finish_candidates(out.cands, nc, ix, nspans, st);
         out.ncands = nc;
         return;
@@ -951,8 +957,11 @@ void chain_seeds(const IndexView &ix, const uint32_t *seeds, uint64_t ns, uint32
     SDF_HIP(hipGetLastError());
     scan_u32(flag.p, pre.p, ns, st);
     uint32_t nc = 0;
-    SDF_HIP(hipMemcpyAsync(&nc, pre.p + ns, 4, hipMemcpyDeviceToHost, st));
-    SDF_HIP(hipStreamSynchronize(st));
+    {
+        Readback rb(st);
+        rb.add(&nc, pre.p + ns, 4);
+        rb.wait();
+    }
     uint64_t n2 = 1;
     while (n2 < nc) n2 <<= 1;
     out.cands.alloc(n2);

@@ -500,8 +500,11 @@ void launch_estimate_runs(const IndexView &ix, const uint32_t *runs, uint64_t nr
         reg_cap, amax_s, over.p, nover.p);
     SDF_HIP(hipGetLastError());
     unsigned long long no = 0;
-    SDF_HIP(hipMemcpyAsync(&no, nover.p, 8, hipMemcpyDeviceToHost, st));
-    SDF_HIP(hipStreamSynchronize(st));
+    {
+        Readback rb(st);
+        rb.add(&no, nover.p, 8);
+        rb.wait();
+    }
     if (no == 0) return;
     k_estimate_runs<AMAX_L, TCAP_L, false><<<(unsigned)((no + EW - 1) / EW), EW * 64, 0, st>>>(
         ix, runs, no, over.p, n, T, seeds, cap, nseeds, err, lds_cap, reg_cap, AMAX_L, nullptr,

@@ -1116,9 +1116,12 @@ void launch_extend(const IndexView &ix, const sdf_region *in, uint64_t n, double
     SDF_HIP(hipGetLastError());
     uint32_t herr = 0;
     unsigned long long hc[7] = {0, 0, 0, 0, 0, 0, 0};
-    SDF_HIP(hipMemcpyAsync(&herr, work.p + 1, 4, hipMemcpyDeviceToHost, st));
-    SDF_HIP(hipMemcpyAsync(hc, cnt.p, 56, hipMemcpyDeviceToHost, st));
-    SDF_HIP(hipStreamSynchronize(st));
+    {
+        Readback rb(st);
+        rb.add(&herr, work.p + 1, 4);
+        rb.add(hc, cnt.p, 56);
+        rb.wait();
+    }
     if (herr & XE_CAP)
         throw Error{SDF_EINTERNAL, "extend: a region's windows hold more minimizers than its scratch"};
     if (herr & XE_HASH)

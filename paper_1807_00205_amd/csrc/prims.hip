@@ -1,4 +1,5 @@
 // Device primitives: memory pool, prefix sums, stable LSD radix sort, fills.
+#include <cstring>
 #include <map>
 #include <unordered_map>
 
@@ -93,6 +94,43 @@ void pool_free(void *p) {
     if (it == g_live.end()) return;
     g_free[PoolKey{it->second.first, it->second.second, t_stream}].push_back(p);
     g_live.erase(it);
+}
+
+// -------------------------------------------------------------- readback --
+static thread_local unsigned char *t_stage = nullptr;
+static thread_local bool t_stage_busy = false;
+
+Readback::Readback(hipStream_t st) : st_(st) {
+    if (t_stage_busy) throw Error{SDF_EINTERNAL, "nested readback on one host thread"};
+    if (!t_stage) {
+        void *p = nullptr;
+        SDF_HIP(hipHostMalloc(&p, READBACK_MAX, hipHostMallocPortable));
+        t_stage = static_cast<unsigned char *>(p);
+    }
+    stage_ = t_stage;
+    t_stage_busy = true;
+}
+
+Readback::~Readback() {
+    // a copy still queued (an exception before wait()) lands in the block
+    // later; the block is never released, so that is harmless
+    t_stage_busy = false;
+}
+
+void Readback::add(void *host_dst, const void *dev_src, size_t bytes) {
+    const size_t off = (used_ + 7) & ~size_t(7);
+    if (off + bytes > READBACK_MAX || n_ == (int)(sizeof(items_) / sizeof(items_[0])))
+        throw Error{SDF_EINTERNAL, "readback staging block exceeded"};
+    SDF_HIP(hipMemcpyAsync(stage_ + off, dev_src, bytes, hipMemcpyDeviceToHost, st_));
+    items_[n_++] = Item{host_dst, off, bytes};
+    used_ = off + bytes;
+}
+
+void Readback::wait() {
+    SDF_HIP(hipStreamSynchronize(st_));
+    for (int i = 0; i < n_; i++) std::memcpy(items_[i].dst, stage_ + items_[i].off, items_[i].bytes);
+    n_ = 0;
+    used_ = 0;
 }
 
 // ---------------------------------------------------------------- fills --

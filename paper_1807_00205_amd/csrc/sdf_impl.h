@@ -46,6 +46,34 @@ struct StreamScope {  // makes `s` the current stream of this host thread
     ~StreamScope();
 };
 
+// Small device-to-host reads through a pinned staging block of this host
+// thread (READBACK_MAX bytes, allocated on first use and held until process
+// end): add() queues an asynchronous copy into the block, wait() synchronizes
+// the stream once and copies every staged value to its destination.  A copy
+// into pageable memory blocks the host once per copy; staging turns several
+// reads into one round trip.  One Readback per thread at a time.
+constexpr size_t READBACK_MAX = 4096;
+class Readback {
+  public:
+    explicit Readback(hipStream_t st);
+    ~Readback();
+    Readback(const Readback &) = delete;
+    Readback &operator=(const Readback &) = delete;
+    void add(void *host_dst, const void *dev_src, size_t bytes);
+    void wait();
+
+  private:
+    hipStream_t st_;
+    unsigned char *stage_;
+    size_t used_ = 0;
+    struct Item {
+        void *dst;
+        size_t off, bytes;
+    };
+    Item items_[16];
+    int n_ = 0;
+};
+
 template <class T>
 struct DevBuf {
     T *p = nullptr;

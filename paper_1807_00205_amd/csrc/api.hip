@@ -197,14 +197,19 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
     tm.mark();
     // thresholds T(s) = ceil(tau * s) for every sketch size a tile can see
     const uint32_t smax = std::max<uint32_t>(P.n - ix->k + 2, 2048);
-    std::vector<uint16_t> T(smax + 1);
+    // the table and the span descriptors go to the device in one upload
+    const size_t t_bytes = ((size_t)(smax + 1) * 2 + 255) & ~size_t(255);
+    const size_t up_bytes = t_bytes + (size_t)nq * sizeof(SpanDesc);
+    Upload up(up_bytes);
+    uint16_t *T = reinterpret_cast<uint16_t *>(up.host());
     for (uint32_t s = 0; s <= smax; s++) {
         double v = std::ceil(P.tau * (double)s);
         T[s] = (uint16_t)std::min(v, 65535.0);
     }
-    DevBuf<uint16_t> dT(T.size());
-    SDF_HIP(hipMemcpyAsync(dT.p, T.data(), T.size() * 2, hipMemcpyHostToDevice, st));
-    std::vector<SpanDesc> sd(nq);
+    DevBuf<unsigned char> dup(up_bytes);
+    const uint16_t *dT = reinterpret_cast<const uint16_t *>(dup.p);
+    SpanDesc *dsd = reinterpret_cast<SpanDesc *>(dup.p + t_bytes);
+    SpanDesc *sd = reinterpret_cast<SpanDesc *>(up.host() + t_bytes);
     uint64_t qbases = 0;
     for (uint32_t t = 0; t < nq; t++) {
         sd[t].gb = ix->h_off[qs[t].seq] + qs[t].begin;
@@ -213,6 +218,7 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
         sd[t].qseq = qs[t].seq;
         qbases += qs[t].end - qs[t].begin;
     }
+    up.send(dup.p, st);
     // tile layout and window starts per tile: the environment overrides
     // (SDF_TILE_THREADS, SDF_TILE_CORE), else the measured choice of
     // sdf_autotune, else the hit-density rules
@@ -229,12 +235,10 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
                                         : (ix->tuned_core ? ix->tuned_core
                                                           : auto_tile_core(ix->hbar, hpart, cmax));
     const uint32_t core = std::min(std::max<uint32_t>(env_u32("SDF_TILE_CORE", pick), 1), cmax);
-    DevBuf<SpanDesc> dsd(nq);
     DevBuf<uint32_t> ntiles(nq + 1), tile0(nq + 1);
     uint32_t total_tiles = 0;  // read back with the counters; the kernel reads it on device
     if (nq) {
-        SDF_HIP(hipMemcpyAsync(dsd.p, sd.data(), nq * sizeof(SpanDesc), hipMemcpyHostToDevice, st));
-        launch_span_setup(ix->view(), dsd.p, nq, P.n, core, ntiles.p, tile0.p, st);
+        launch_span_setup(ix->view(), dsd, nq, P.n, core, ntiles.p, tile0.p, st);
     }
     tm.mark();
     uint32_t sb = 0;
@@ -257,8 +261,8 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
             a.ix = ix->view();
             a.n = P.n;
             a.max_overlap = P.max_overlap;
-            a.T = dT.p;
-            a.spans = dsd.p;
+            a.T = dT;
+            a.spans = dsd;
             a.nspans = nq;
             a.total_tiles = tile0.p + nq;
             a.work = work;
@@ -333,7 +337,7 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
         DevBuf<uint32_t> eerr(1);
         SDF_HIP(hipMemsetAsync(ecount.p, 0, 8, st));
         SDF_HIP(hipMemsetAsync(eerr.p, 0, 4, st));
-        launch_estimate_runs(ix->view(), res->seeds.p, nruns, P.n, dT.p, est.p, nruns, ecount.p,
+        launch_estimate_runs(ix->view(), res->seeds.p, nruns, P.n, dT, est.p, nruns, ecount.p,
                              eerr.p, st);
         unsigned long long ne = 0;
         uint32_t ee = 0;

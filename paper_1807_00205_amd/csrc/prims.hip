@@ -1,4 +1,5 @@
 // Device primitives: memory pool, prefix sums, stable LSD radix sort, fills.
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <unordered_map>
@@ -131,6 +132,48 @@ void Readback::wait() {
     for (int i = 0; i < n_; i++) std::memcpy(items_[i].dst, stage_ + items_[i].off, items_[i].bytes);
     n_ = 0;
     used_ = 0;
+}
+
+namespace {
+struct UploadStage {
+    unsigned char *p = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;  // recorded after the last copy out of p
+    int dev = -1;
+};
+thread_local UploadStage t_up;
+}  // namespace
+
+Upload::Upload(size_t bytes) : bytes_(bytes) {
+    UploadStage &u = t_up;
+    if (u.ev) SDF_HIP(hipEventSynchronize(u.ev));
+    if (u.cap < bytes) {
+        if (u.p) SDF_HIP(hipHostFree(u.p));
+        u.p = nullptr;
+        u.cap = 0;
+        void *p = nullptr;
+        const size_t cap = std::max<size_t>(bytes, 65536);
+        SDF_HIP(hipHostMalloc(&p, cap, hipHostMallocPortable));
+        u.p = static_cast<unsigned char *>(p);
+        u.cap = cap;
+    }
+    host_ = u.p;
+}
+
+void Upload::send(void *dev_dst, hipStream_t st) {
+    UploadStage &u = t_up;
+    int dev = 0;
+    SDF_HIP(hipGetDevice(&dev));
+    if (u.ev && u.dev != dev) {  // events belong to one device
+        SDF_HIP(hipEventDestroy(u.ev));
+        u.ev = nullptr;
+    }
+    if (!u.ev) {
+        SDF_HIP(hipEventCreateWithFlags(&u.ev, hipEventDisableTiming));
+        u.dev = dev;
+    }
+    if (bytes_) SDF_HIP(hipMemcpyAsync(dev_dst, host_, bytes_, hipMemcpyHostToDevice, st));
+    SDF_HIP(hipEventRecord(u.ev, st));
 }
 
 // ---------------------------------------------------------------- fills --

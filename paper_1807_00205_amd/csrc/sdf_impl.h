@@ -74,6 +74,24 @@ class Readback {
     int n_ = 0;
 };
 
+// Host-to-device upload through a pinned staging block of this host thread
+// (grown on demand, held until process end): the constructor waits until the
+// thread's previous upload has been copied, then host() holds `bytes` to fill;
+// send() queues one copy and returns.  A pageable source would block the host
+// for the copy.
+class Upload {
+  public:
+    explicit Upload(size_t bytes);
+    Upload(const Upload &) = delete;
+    Upload &operator=(const Upload &) = delete;
+    unsigned char *host() const { return host_; }
+    void send(void *dev_dst, hipStream_t st);
+
+  private:
+    unsigned char *host_;
+    size_t bytes_;
+};
+
 template <class T>
 struct DevBuf {
     T *p = nullptr;
@@ -143,8 +161,8 @@ struct sdf_index_s {
     sdf::DevBuf<uint32_t> packed, mask, gaps;
     uint64_t nm = 0, ne = 0, nseg = 0;
     double hbar = 0.0;  // mean target occurrences of a query minimizer's hash
-    uint32_t tuned_core = 0;
-    uint32_t tuned_threads = 0;  // tile workgroup layout chosen by sdf_autotune (0: rule)  // window starts per tile chosen by sdf_autotune (0: the rule)
+    uint32_t tuned_core = 0;     // window starts per tile chosen by sdf_autotune (0: the rule)
+    uint32_t tuned_threads = 0;  // tile workgroup layout chosen by sdf_autotune (0: the rule)
     sdf::DevBuf<uint32_t> mpos, mhash, mprev, mext;
     sdf::DevBuf<uint8_t> mflags;
     sdf::DevBuf<uint32_t> dir, epos;

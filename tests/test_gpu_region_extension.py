@@ -232,6 +232,31 @@ def test_search_extend_config1(S, oracle_lib):
     _same(r.regions(), _oracle_extend(orc, off, _boxes_from_cands(S, oc), tau), "config1")
 
 
+def test_search_extend_tied_candidates(S, oracle_lib, monkeypatch):
+    """Candidates that share their sort prefix (query, strand, sequence,
+    begin: tandem arrays), with every such run sent to the whole-record sort
+    (SDF_CAND_TIE_MAX=1), then extended: the order is final before the
+    extension starts, so each region is the oracle's extension of the oracle
+    candidate at the same place."""
+    monkeypatch.setenv("SDF_CAND_TIE_MAX", "1")
+    g = synth.tandem_case(93, length=200_000, n_arrays=120, copies_hi=60, n_seqs=3)
+    b, off = g.concat()
+    spans = list(g.spans) + [(0, 100, len(g.seqs[0]) - 50)]
+    orc = oracle_lib.OracleIndex(b, off, 12, 16)
+    tau, _, _ = oracle_lib.params(0.25, 200, 12)
+    _, oc = orc.search(spans, 0.25, 200)
+    pre = np.stack([oc["query_id"], oc["strand"], oc["q_seq"], oc["q_begin"]], 1)
+    assert np.any(np.all(pre[1:] == pre[:-1], axis=1)), "no tied candidates"
+    ix = S.Index(g.seqs, 12, 16)
+    r = ix.search_batch(spans, 0.25, 200, extend=True)
+    gc = r.candidates()
+    for f in ("query_id", "strand", "q_seq", "t_seq", "q_begin", "q_end", "t_begin", "t_end",
+              "n_seeds", "max_shared"):
+        assert np.array_equal(gc[f], oc[f]), f
+    _same(r.regions(), _oracle_extend(orc, off, _boxes_from_cands(S, oc), tau), "tied")
+    ix.close()
+
+
 def test_search_extend_config2_sampled(S, oracle_lib):
     """The 50 Mbp chromosome-shaped workload searched with SDF_EXTEND, in the
     launch the benchmark times: the candidates equal the oracle's, and 200

@@ -57,6 +57,78 @@ sdf_status guarded(F &&f) {
 // Section 3.2: potential duplications are at most 1 Mbp long.
 constexpr uint64_t EXT_MAX_LEN = 1000000;
 
+// First index in [lo, hi) of the sorted array a whose value is >= key (with
+// `upper`: > key), hi when there is none; the whole wave takes part and gets
+// the same answer.  Each round the 64 lanes test 64 evenly spaced positions
+// and a ballot counts those still below the boundary, which narrows the range
+// 64-fold (four rounds over six million minimizers instead of 23 halvings).
+__device__ uint64_t wave_bound(const uint32_t *a, uint64_t lo, uint64_t hi, uint64_t key,
+                               bool upper) {
+    const uint64_t lane = threadIdx.x & 63;
+    // invariant: the answer lies in [lo, hi]
+    while (hi - lo > 64) {
+        const uint64_t step = (hi - lo + 63) / 64;
+        const uint64_t p = lo + lane * step;
+        bool below = false;
+        if (p < hi) {
+            const uint64_t v = a[p];
+            below = upper ? v <= key : v < key;
+        }
+        // `below` holds for lanes 0 .. c-1 only: the predicate is monotone
+        const uint64_t c = (uint64_t)__popcll(__ballot(below));
+        if (c == 0) return lo;
+        const uint64_t nlo = lo + (c - 1) * step + 1;
+        const uint64_t nhi = (c < 64 && lo + c * step < hi) ? lo + c * step : hi;
+        lo = nlo;
+        hi = nhi;
+    }
+    const uint64_t p = lo + lane;
+    bool below = false;
+    if (p < hi) {
+        const uint64_t v = a[p];
+        below = upper ? v <= key : v < key;
+    }
+    return lo + (uint64_t)__popcll(__ballot(below));
+}
+
+// Set-up of a search with at most SPAN_FEW spans in one launch: wave s finds
+// span s's window starts, the minimizers at positions [gb, ge - n] (none when
+// the span is shorter than n), and its tile count; then the first lane adds
+// the counts up: tile0[s] = first tile of span s, tile0[nspans] = all tiles.
+// Larger batches use the one-thread-per-span set-up and a device scan.
+constexpr uint32_t SPAN_FEW = 16;
+
+__global__ void __launch_bounds__(64 * SPAN_FEW) k_span_setup_few(const IndexView ix,
+                                                                  SpanDesc *spans,
+                                                                  uint32_t nspans, uint32_t n,
+                                                                  uint32_t core, uint32_t *tile0) {
+    __shared__ uint32_t nt[SPAN_FEW];
+    const uint32_t w = threadIdx.x >> 6;
+    if (w < nspans) {
+        const uint64_t gb = spans[w].gb, ge = spans[w].ge;
+        uint64_t mlo = 0, mhi = 0;
+        if (ge >= gb + n) {
+            mlo = wave_bound(ix.mpos, 0, ix.nm, gb, false);
+            mhi = wave_bound(ix.mpos, mlo, ix.nm, ge - n, true);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            spans[w].m_lo = (uint32_t)mlo;
+            spans[w].m_hi = (uint32_t)mhi;
+            nt[w] = (uint32_t)((mhi - mlo + core - 1) / core);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (uint32_t s = 0; s < nspans; s++) {
+            spans[s].tile0 = acc;
+            tile0[s] = acc;
+            acc += nt[s];
+        }
+        tile0[nspans] = acc;
+    }
+}
+
 __global__ void k_cand_regions(const sdf_candidate *c, uint64_t n, sdf_region *r) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -237,7 +309,10 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
     const uint32_t core = std::min(std::max<uint32_t>(env_u32("SDF_TILE_CORE", pick), 1), cmax);
     DevBuf<uint32_t> ntiles(nq + 1), tile0(nq + 1);
     uint32_t total_tiles = 0;  // read back with the counters; the kernel reads it on device
-    if (nq) {
+    if (nq > 0 && nq <= SPAN_FEW) {
+        k_span_setup_few<<<1, 64 * nq, 0, st>>>(ix->view(), dsd, nq, P.n, core, tile0.p);
+        SDF_HIP(hipGetLastError());
+    } else if (nq) {
         launch_span_setup(ix->view(), dsd, nq, P.n, core, ntiles.p, tile0.p, st);
     }
     tm.mark();

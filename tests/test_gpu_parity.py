@@ -338,14 +338,17 @@ def test_candidate_sort_paths(S, oracle_lib, monkeypatch, path):
         ix.close()
 
 
-def test_edge_spans(S, oracle_lib):
+@pytest.mark.parametrize("copies", [1, 3])
+def test_edge_spans(S, oracle_lib, copies):
     """Empty spans, spans shorter than n, spans at sequence ends, sequences
-    shorter than k or made of gap bases, and several spans in one batch."""
+    shorter than k or made of gap bases, and several spans in one batch: 8
+    spans (set up by one wave each in one launch) and the same list three
+    times over, 24 spans (one thread each and a device scan)."""
     g = _mixed_genome(9, length=5000)
     b, off = g.concat()
     lens = [len(s) for s in g.seqs]
     spans = [(0, 0, 0), (0, 100, 100 + 300), (0, lens[0] - 760, lens[0]), (1, 0, lens[1]),
-             (3, 0, lens[3]), (6, 0, lens[6]), (0, 0, lens[0]), (2, 17, lens[2] - 3)]
+             (3, 0, lens[3]), (6, 0, lens[6]), (0, 0, lens[0]), (2, 17, lens[2] - 3)] * copies
     orc = oracle_lib.OracleIndex(b, off, 12, 16)
     os_, oc = orc.search(spans, 0.25, 1000)
     ix = S.Index(g.seqs, 12, 16)

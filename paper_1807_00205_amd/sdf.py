@@ -75,6 +75,38 @@ class _Span(ctypes.Structure):
                 ("begin", ctypes.c_uint64), ("end", ctypes.c_uint64)]
 
 
+# sdf_span as a NumPy record: filling one from the span list is several times
+# faster than building one ctypes structure per span
+_SPAN_DTYPE = np.dtype([("seq", np.uint32), ("_pad", np.uint32), ("begin", np.uint64),
+                        ("end", np.uint64)])
+assert _SPAN_DTYPE.itemsize == ctypes.sizeof(_Span)
+
+
+def _span_array(spans):
+    """(seq, begin, end) triples as a contiguous sdf_span array (at least one
+    record, so the pointer is never NULL) and their count.  Values that do
+    not fit the fields wrap as ctypes would wrap them; the library rejects
+    them."""
+    spans = list(spans)
+    n = len(spans)
+    arr = np.zeros(max(1, n), _SPAN_DTYPE)
+    if not n:
+        return arr, 0
+    try:
+        a = np.asarray(spans)
+    except (ValueError, TypeError):
+        a = None
+    if (a is not None and a.dtype.kind in "iu" and a.shape == (n, 3)
+            and not (a.dtype.kind == "i" and (a < 0).any())):
+        arr["seq"] = a[:, 0].astype(np.uint32, casting="unsafe")
+        arr["begin"] = a[:, 1].astype(np.uint64)
+        arr["end"] = a[:, 2].astype(np.uint64)
+    else:  # anything else goes through ctypes, which converts or raises as before
+        c = (_Span * n)(*[_Span(q, 0, b, e) for (q, b, e) in spans])
+        arr = np.frombuffer(bytearray(c), dtype=_SPAN_DTYPE).copy()
+    return arr, n
+
+
 _lib = None
 
 
@@ -320,12 +352,11 @@ class Index:
         fastest for later searches (``sdf_autotune``); returns (window starts,
         workgroup threads, {(threads, window starts): ms}).  No spans: back to
         the built-in rules."""
-        spans = list(spans)
-        arr = (_Span * max(1, len(spans)))(*[_Span(s, 0, b, e) for (s, b, e) in spans])
+        arr, nspans = _span_array(spans)
         p = _SearchParams(max_error, min_len, 0)
         core, threads = ctypes.c_uint32(), ctypes.c_uint32()
         ms = (ctypes.c_float * 16)()
-        _check(lib().sdf_autotune(self._h, ctypes.cast(arr, ctypes.c_void_p), len(spans),
+        _check(lib().sdf_autotune(self._h, arr.ctypes.data_as(ctypes.c_void_p), nspans,
                                   ctypes.byref(p), _stream_ptr(stream), ctypes.byref(core),
                                   ctypes.byref(threads), ms, 16))
         sched = [(1024, c) for c in range(512, 1025, 64)]
@@ -362,10 +393,9 @@ class Index:
     def search_batch(self, spans: Iterable[Tuple[int, int, int]], max_error: float = 0.25,
                      min_len: int = 1000, timing: bool = False, stream=None,
                      estimate: bool = False, extend: bool = False) -> Result:
-        spans = list(spans)
-        arr = (_Span * max(1, len(spans)))(*[_Span(s, 0, b, e) for (s, b, e) in spans])
+        arr, nspans = _span_array(spans)
         p = _SearchParams(max_error, min_len, _flags(timing, estimate, extend))
         h = ctypes.c_void_p()
-        _check(lib().sdf_search_batch(self._h, ctypes.cast(arr, ctypes.c_void_p), len(spans),
+        _check(lib().sdf_search_batch(self._h, arr.ctypes.data_as(ctypes.c_void_p), nspans,
                                       ctypes.byref(p), _stream_ptr(stream), ctypes.byref(h)))
         return Result(h.value)

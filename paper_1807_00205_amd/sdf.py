@@ -7,6 +7,7 @@ built; there is no CPU path.
 from __future__ import annotations
 
 import ctypes
+import itertools
 import os
 from typing import Iterable, Optional, Sequence, Tuple
 
@@ -92,12 +93,18 @@ def _span_array(spans):
     arr = np.zeros(max(1, n), _SPAN_DTYPE)
     if not n:
         return arr, 0
+    a = None
     try:
-        a = np.asarray(spans)
-    except (ValueError, TypeError):
+        # triples of integers only (floats would be truncated by fromiter)
+        if (set(map(len, spans)) == {3}
+                and all(issubclass(t, (int, np.integer))
+                        for t in set(map(type, itertools.chain.from_iterable(spans))))):
+            a = np.fromiter(itertools.chain.from_iterable(spans), np.int64, 3 * n).reshape(n, 3)
+            if (a < 0).any():
+                a = None
+    except (OverflowError, ValueError, TypeError):
         a = None
-    if (a is not None and a.dtype.kind in "iu" and a.shape == (n, 3)
-            and not (a.dtype.kind == "i" and (a < 0).any())):
+    if a is not None:
         arr["seq"] = a[:, 0].astype(np.uint32, casting="unsafe")
         arr["begin"] = a[:, 1].astype(np.uint64)
         arr["end"] = a[:, 2].astype(np.uint64)

@@ -97,83 +97,104 @@ void pool_free(void *p) {
     g_live.erase(it);
 }
 
-// -------------------------------------------------------------- readback --
-static thread_local unsigned char *t_stage = nullptr;
-static thread_local bool t_stage_busy = false;
+// -------------------------------------------------------------- staging --
+struct Stage {
+    unsigned char *p = nullptr;
+    size_t cap = 0;
+    int dev = 0;
+    hipEvent_t ev = nullptr;  // recorded after the last upload out of p, if any
+};
 
-Readback::Readback(hipStream_t st) : st_(st) {
-    if (t_stage_busy) throw Error{SDF_EINTERNAL, "nested readback on one host thread"};
-    if (!t_stage) {
-        void *p = nullptr;
-        SDF_HIP(hipHostMalloc(&p, READBACK_MAX, hipHostMallocPortable));
-        t_stage = static_cast<unsigned char *>(p);
+namespace {
+std::mutex g_stage_mu;
+std::map<int, std::vector<Stage *>> g_stage_free;  // per device
+
+// A free block of at least `bytes` on the current device (a new one when none
+// fits), with any upload still reading from it finished.
+Stage *stage_acquire(size_t bytes) {
+    int dev = 0;
+    SDF_HIP(hipGetDevice(&dev));
+    Stage *s = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_stage_mu);
+        std::vector<Stage *> &v = g_stage_free[dev];
+        for (size_t i = 0; i < v.size(); i++) {
+            if (v[i]->cap >= bytes) {
+                s = v[i];
+                v[i] = v.back();
+                v.pop_back();
+                break;
+            }
+        }
     }
-    stage_ = t_stage;
-    t_stage_busy = true;
+    if (!s) {
+        size_t cap = READBACK_MAX;
+        while (cap < bytes) cap <<= 1;
+        void *p = nullptr;
+        if (hipHostMalloc(&p, cap, hipHostMallocPortable) != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error{SDF_ENOMEM, "pinned host allocation of " + std::to_string(cap) +
+                                        " bytes failed"};
+        }
+        s = new Stage();
+        s->p = static_cast<unsigned char *>(p);
+        s->cap = cap;
+        s->dev = dev;
+        return s;
+    }
+    if (s->ev) {
+        const hipError_t e = hipEventSynchronize(s->ev);
+        if (e != hipSuccess) {
+            // the block may still be read by a failed copy: keep it out of the pool
+            throw Error{SDF_EDEVICE, std::string("hipEventSynchronize: ") + hipGetErrorString(e)};
+        }
+    }
+    return s;
 }
 
+void stage_release(Stage *s) {
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    g_stage_free[s->dev].push_back(s);
+}
+}  // namespace
+
+Readback::Readback(hipStream_t st) : st_(st), stage_(stage_acquire(READBACK_MAX)) {}
+
 Readback::~Readback() {
-    // a copy still queued (an exception before wait()) lands in the block
-    // later; the block is never released, so that is harmless
-    t_stage_busy = false;
+    // copies queued but not waited for (an exception in between) may still
+    // land in the block: it is not returned to the pool then
+    if (!pending_) stage_release(stage_);
 }
 
 void Readback::add(void *host_dst, const void *dev_src, size_t bytes) {
     const size_t off = (used_ + 7) & ~size_t(7);
     if (off + bytes > READBACK_MAX || n_ == (int)(sizeof(items_) / sizeof(items_[0])))
         throw Error{SDF_EINTERNAL, "readback staging block exceeded"};
-    SDF_HIP(hipMemcpyAsync(stage_ + off, dev_src, bytes, hipMemcpyDeviceToHost, st_));
+    pending_ = true;
+    SDF_HIP(hipMemcpyAsync(stage_->p + off, dev_src, bytes, hipMemcpyDeviceToHost, st_));
     items_[n_++] = Item{host_dst, off, bytes};
     used_ = off + bytes;
 }
 
 void Readback::wait() {
     SDF_HIP(hipStreamSynchronize(st_));
-    for (int i = 0; i < n_; i++) std::memcpy(items_[i].dst, stage_ + items_[i].off, items_[i].bytes);
+    pending_ = false;
+    for (int i = 0; i < n_; i++)
+        std::memcpy(items_[i].dst, stage_->p + items_[i].off, items_[i].bytes);
     n_ = 0;
     used_ = 0;
 }
 
-namespace {
-struct UploadStage {
-    unsigned char *p = nullptr;
-    size_t cap = 0;
-    hipEvent_t ev = nullptr;  // recorded after the last copy out of p
-    int dev = -1;
-};
-thread_local UploadStage t_up;
-}  // namespace
+Upload::Upload(size_t bytes) : stage_(stage_acquire(bytes)), bytes_(bytes) {}
 
-Upload::Upload(size_t bytes) : bytes_(bytes) {
-    UploadStage &u = t_up;
-    if (u.ev) SDF_HIP(hipEventSynchronize(u.ev));
-    if (u.cap < bytes) {
-        if (u.p) SDF_HIP(hipHostFree(u.p));
-        u.p = nullptr;
-        u.cap = 0;
-        void *p = nullptr;
-        const size_t cap = std::max<size_t>(bytes, 65536);
-        SDF_HIP(hipHostMalloc(&p, cap, hipHostMallocPortable));
-        u.p = static_cast<unsigned char *>(p);
-        u.cap = cap;
-    }
-    host_ = u.p;
-}
+Upload::~Upload() { stage_release(stage_); }
+
+unsigned char *Upload::host() const { return stage_->p; }
 
 void Upload::send(void *dev_dst, hipStream_t st) {
-    UploadStage &u = t_up;
-    int dev = 0;
-    SDF_HIP(hipGetDevice(&dev));
-    if (u.ev && u.dev != dev) {  // events belong to one device
-        SDF_HIP(hipEventDestroy(u.ev));
-        u.ev = nullptr;
-    }
-    if (!u.ev) {
-        SDF_HIP(hipEventCreateWithFlags(&u.ev, hipEventDisableTiming));
-        u.dev = dev;
-    }
-    if (bytes_) SDF_HIP(hipMemcpyAsync(dev_dst, host_, bytes_, hipMemcpyHostToDevice, st));
-    SDF_HIP(hipEventRecord(u.ev, st));
+    if (!stage_->ev) SDF_HIP(hipEventCreateWithFlags(&stage_->ev, hipEventDisableTiming));
+    if (bytes_) SDF_HIP(hipMemcpyAsync(dev_dst, stage_->p, bytes_, hipMemcpyHostToDevice, st));
+    SDF_HIP(hipEventRecord(stage_->ev, st));
 }
 
 // ---------------------------------------------------------------- fills --

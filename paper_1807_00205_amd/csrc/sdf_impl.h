@@ -46,12 +46,17 @@ struct StreamScope {  // makes `s` the current stream of this host thread
     ~StreamScope();
 };
 
-// Small device-to-host reads through a pinned staging block of this host
-// thread (READBACK_MAX bytes, allocated on first use and held until process
-// end): add() queues an asynchronous copy into the block, wait() synchronizes
-// the stream once and copies every staged value to its destination.  A copy
-// into pageable memory blocks the host once per copy; staging turns several
-// reads into one round trip.  One Readback per thread at a time.
+// Pinned host staging blocks (hipHostMalloc), pooled per device for the
+// whole process: a Readback or Upload borrows one and returns it when done,
+// so after the first calls no search allocates pinned memory, whichever host
+// thread it runs on.  Blocks are held until process end.
+struct Stage;
+
+// Small device-to-host reads through a borrowed staging block (READBACK_MAX
+// bytes): add() queues an asynchronous copy into the block, wait()
+// synchronizes the stream once and copies every staged value to its
+// destination.  A copy into pageable memory blocks the host once per copy;
+// staging turns several reads into one round trip.
 constexpr size_t READBACK_MAX = 4096;
 class Readback {
   public:
@@ -64,7 +69,8 @@ class Readback {
 
   private:
     hipStream_t st_;
-    unsigned char *stage_;
+    Stage *stage_;
+    bool pending_ = false;  // copies queued and not yet waited for
     size_t used_ = 0;
     struct Item {
         void *dst;
@@ -74,21 +80,21 @@ class Readback {
     int n_ = 0;
 };
 
-// Host-to-device upload through a pinned staging block of this host thread
-// (grown on demand, held until process end): the constructor waits until the
-// thread's previous upload has been copied, then host() holds `bytes` to fill;
-// send() queues one copy and returns.  A pageable source would block the host
-// for the copy.
+// Host-to-device upload through a borrowed staging block of at least `bytes`:
+// host() is filled by the caller, send() queues one copy and records an event;
+// the block goes back to the pool with that event, and its next borrower waits
+// on it before writing.  A pageable source would block the host for the copy.
 class Upload {
   public:
     explicit Upload(size_t bytes);
+    ~Upload();
     Upload(const Upload &) = delete;
     Upload &operator=(const Upload &) = delete;
-    unsigned char *host() const { return host_; }
+    unsigned char *host() const;
     void send(void *dev_dst, hipStream_t st);
 
   private:
-    unsigned char *host_;
+    Stage *stage_;
     size_t bytes_;
 };
 

@@ -309,7 +309,9 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
     const uint32_t core = std::min(std::max<uint32_t>(env_u32("SDF_TILE_CORE", pick), 1), cmax);
     DevBuf<uint32_t> ntiles(nq + 1), tile0(nq + 1);
     uint32_t total_tiles = 0;  // read back with the counters; the kernel reads it on device
-    if (nq > 0 && nq <= SPAN_FEW) {
+    // the SDF_SPAN_FEW_MAX environment variable lowers the one-launch limit (0: off)
+    const uint32_t few_max = std::min<uint32_t>(env_u32("SDF_SPAN_FEW_MAX", SPAN_FEW), SPAN_FEW);
+    if (nq > 0 && nq <= few_max) {
         k_span_setup_few<<<1, 64 * nq, 0, st>>>(ix->view(), dsd, nq, P.n, core, tile0.p);
         SDF_HIP(hipGetLastError());
     } else if (nq) {

@@ -76,8 +76,8 @@ class _Span(ctypes.Structure):
                 ("begin", ctypes.c_uint64), ("end", ctypes.c_uint64)]
 
 
-# sdf_span as a NumPy record: filling one from the span list is several times
-# faster than building one ctypes structure per span
+# sdf_span as a NumPy record: for long span lists, filling one is several
+# times faster than building one ctypes structure per span
 _SPAN_DTYPE = np.dtype([("seq", np.uint32), ("_pad", np.uint32), ("begin", np.uint64),
                         ("end", np.uint64)])
 assert _SPAN_DTYPE.itemsize == ctypes.sizeof(_Span)
@@ -90,9 +90,10 @@ def _span_array(spans):
     them."""
     spans = list(spans)
     n = len(spans)
-    arr = np.zeros(max(1, n), _SPAN_DTYPE)
-    if not n:
-        return arr, 0
+    if n < 32:  # few spans: ctypes directly is cheaper than the NumPy calls
+        c = (_Span * max(1, n))(*[_Span(q, 0, b, e) for (q, b, e) in spans])
+        return np.frombuffer(bytearray(c), dtype=_SPAN_DTYPE), n
+    arr = np.zeros(n, _SPAN_DTYPE)
     a = None
     try:
         # triples of integers only (floats would be truncated by fromiter)

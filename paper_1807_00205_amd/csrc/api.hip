@@ -353,9 +353,18 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
             a.phase = phase_prof ? phase : nullptr;
             a.runs_out = (p->flags & SDF_SEED_ESTIMATE) ? 1u : 0u;
             // persistent grid, as many workgroups as fit the CUs: workgroups
-            // past the last tile exit at once
-            const uint32_t grid = (uint32_t)cu_count(ix->device) * (threads == 512 ? 2u : 1u) *
-                                  env_u32("SDF_WG_PER_CU", 1);
+            // past the last tile exit at once.  A span has at most
+            // (length - n + 1) window starts, so short spans launch no more
+            // workgroups than they can have tiles.
+            uint64_t tile_bound = 0;
+            for (uint32_t t = 0; t < nq; t++) {
+                const uint64_t len = qs[t].end - qs[t].begin;
+                if (len >= P.n) tile_bound += (len - P.n + 1 + core - 1) / core;
+            }
+            const uint32_t grid = (uint32_t)std::min<uint64_t>(
+                (uint64_t)cu_count(ix->device) * (threads == 512 ? 2u : 1u) *
+                    env_u32("SDF_WG_PER_CU", 1),
+                std::max<uint64_t>(tile_bound, 1));
             tm.mark_kernel_begin();
             if (threads == 512) tile512::launch_tile_search(a, std::max<uint32_t>(grid, 1), st);
             else tile1024::launch_tile_search(a, std::max<uint32_t>(grid, 1), st);

@@ -27,6 +27,13 @@
  * from several host threads on different streams at once.  Results are
  * owned by the caller until sdf_result_free.
  *
+ * Memory the library keeps: device scratch freed by a search returns to a
+ * pool per (device, stream) and is reused by later searches on that stream
+ * (a device allocation that fails first hands the pool's free blocks back and
+ * retries); small pinned host blocks (hipHostMalloc) that stage the counts
+ * read back and the per-search tables uploaded are pooled per device.  Both
+ * pools are otherwise held until the process ends.
+ *
  * Coordinates are 0-based and half-open, per sequence (BEDPE style,
  * Section 3.3).  The total length of all sequences must be below 2^32 - 2^20.
  */

@@ -343,7 +343,7 @@ void scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, hipStream_t st) {
 // ------------------------------------------------------------ radix sort --
 constexpr int RS_THREADS = 256;
 constexpr int RS_WAVES = RS_THREADS / 64;
-constexpr int RS_ITEMS = 16;
+constexpr int RS_ITEMS = 8;
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
 constexpr int RS_BINS = 256;
 

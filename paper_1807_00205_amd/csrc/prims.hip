@@ -228,7 +228,7 @@ void iota_u32(uint32_t *p, uint64_t n, hipStream_t st) {
 }
 
 // ----------------------------------------------------------------- scans --
-constexpr int SC_THREADS = 1024;
+constexpr int SC_THREADS = 256;
 constexpr int SC_ITEMS = 4;
 constexpr int SC_TILE = SC_THREADS * SC_ITEMS;
 

@@ -3,13 +3,17 @@
 
 One step is one pass of the whole search path (window setup, fused hit
 gather / prefilter / exact shared counts / seeds, chaining, sorted
-candidates) over the query span, with the index already resident in HBM.
-The default workload is the 50 Mbp chromosome-shaped synthetic assembly
-(41% GC, 45% soft-masked repeats, 2,000 planted duplications, 10 runs of N)
-searched against itself as one span with k = 12, w = 16, minimum length 1000
-and error bound 0.25.
+candidates) over the query spans, with the index already resident in HBM.
+The headline workload is the 3.1 Gbp synthetic assembly in 24 sequences
+(41% GC, 50% soft-masked repeats, N-gaps, 5% of bases in planted
+duplications) searched all-vs-all: the 24 whole sequences in one batched
+search, with k = 12, w = 16, minimum length 1000 and error bound 0.25; the
+same spans searched one call at a time are reported beside it.  The 50 Mbp
+chromosome-shaped workload (plain single-span path), the 250 Mbp batch of
+4,096 spans (batched against plain) and the serving sweep over that index
+follow as further sections of the same JSON line.
 
-Prints one JSON line (rank 0).  Progress goes to stderr.
+Prints one JSON line.  Progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -109,14 +113,18 @@ def cpu_baseline(g, sample_mbp, max_error, min_len, keep=None):
             "host_cpu": cpu, "host_threads_visible": os.cpu_count()}
 
 
-def batched_vs_plain(steps, plain=True):
+def batched_vs_plain(steps, plain=True, cpu=True, max_error=0.25, min_len=1000):
     """4,096 spans of 1-100 kbp against the resident index of a 250 Mbp
-    sequence: one batched search against the same spans searched one by one."""
+    sequence: one batched search against the same spans searched one by one,
+    with the tile kernel's roofline and the oracle's rate on a sample of the
+    spans."""
     import numpy as np
     import torch
     from paper_1807_00205_amd import sdf, synth
     g = synth.config3()
     ix = sdf.Index(g.seqs, 12, 16)
+    nm, ne, _ = ix.info()
+    hbar = ix.hit_density()
     spans = g.spans
     qb = sum(e - b for _, b, e in spans)
     r = ix.search_batch(spans, timing=True)
@@ -159,19 +167,41 @@ def batched_vs_plain(steps, plain=True):
                                               for k, v in tune_ms.items()},
               "rule_mbp_per_s": round(qb / tb_rule / 1e6, 2),
               "rule_tile_kernel_ms": round(float(np.mean(kms_rule)), 4)}
-    if not plain:
-        return ix, g, {"batched_mbp_per_s": round(qb / tb / 1e6, 2), "batched_ms": round(tb * 1e3, 3),
-                       "batched_tile_kernel_ms": round(float(np.mean(kms)), 4),
-                       "candidates": ncand, "stats": stats, "tuning": tuning}
-    return ix, g, {
-        "workload": "250 Mbp uniform sequence with 2,518 planted duplications (1-5 kbp, "
-                    "2-15%%); 4,096 query spans of 1-100 kbp (log-uniform), %.1f Mbp" % (qb / 1e6),
-        "batched_mbp_per_s": round(qb / tb / 1e6, 2), "batched_ms": round(tb * 1e3, 3),
-        "batched_tile_kernel_ms": round(float(np.mean(kms)), 4),
-        "plain_mbp_per_s": round(qb / tp / 1e6, 2), "plain_ms": round(tp * 1e3, 2),
-        "plain_latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
-                             "p99": round(float(np.percentile(lat, 99)), 4)},
-        "speedup": round(tp / tb, 2), "candidates": ncand, "stats": stats, "tuning": tuning}
+    mean_k = float(np.mean(kms))
+    alg = qb * alg_bytes_per_query_base(nm, ne, g.total, hbar)
+    out = {"workload": "250 Mbp uniform sequence with %d planted duplications (1-5 kbp, "
+                       "2-15%%); 4,096 query spans of 1-100 kbp (log-uniform), %.1f Mbp"
+                       % (len(g.truth), qb / 1e6),
+           "batched_mbp_per_s": round(qb / tb / 1e6, 2), "batched_ms": round(tb * 1e3, 3),
+           "batched_tile_kernel_ms": round(mean_k, 4),
+           "roofline": roofline(alg, mean_k, measured_traffic("batched250")),
+           "hit_density": round(hbar, 4), "candidates": ncand, "stats": stats,
+           "tuning": tuning}
+    if plain:
+        out.update({"plain_mbp_per_s": round(qb / tp / 1e6, 2), "plain_ms": round(tp * 1e3, 2),
+                    "plain_latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                                         "p99": round(float(np.percentile(lat, 99)), 4)},
+                    "speedup": round(tp / tb, 2)})
+    if cpu:
+        import oracle
+        b, off = g.concat()
+        threads_c = max(1, min(16, os.cpu_count() or 1))
+        t = time.time()
+        orc = oracle.OracleIndex(b, off, 12, 16)
+        obuild = time.time() - t
+        sample = spans[:512]
+        sb = sum(e - b0 for _, b0, e in sample)
+        t = time.time()
+        orc.search(sample, max_error, min_len, threads_c)
+        odt = time.time() - t
+        orc.close()
+        out["cpu_baseline"] = {"value": round(sb / odt / 1e6, 4), "unit": "Mbp/s",
+                               "cores": threads_c, "kind": "oracle",
+                               "sample": "the first 512 of the 4,096 spans (%.1f Mbp), search "
+                                         "only; oracle index built beforehand in %.1f s"
+                                         % (sb / 1e6, obuild),
+                               "seconds": round(odt, 3)}
+    return ix, g, out
 
 
 def serving(ix, g, rates, seconds, workers):
@@ -199,48 +229,6 @@ def serving(ix, g, rates, seconds, workers):
         log("  rate %s: served p50 %.2f p99 %.2f ms, plain p50 %.2f p99 %.2f ms" % (
             rate, served["p50_ms"], served["p99_ms"], plain["p50_ms"], plain["p99_ms"]))
     return out
-
-
-def genome_scale():
-    """3.1 Gbp in 24 sequences: all-vs-all (every whole sequence a span) in
-    one batch against the same 24 spans searched one by one."""
-    import torch
-    from paper_1807_00205_amd import sdf, synth
-    t = time.time()
-    g = synth.config5()
-    gen_s = time.time() - t
-    torch.cuda.synchronize()
-    t = time.time()
-    ix = sdf.Index(g.seqs, 12, 16)
-    torch.cuda.synchronize()
-    build_s = time.time() - t
-    nm, ne, dev = ix.info()
-    qb = g.total
-    r = ix.search_batch(g.spans)  # warm-up: the memory pool grows to the working set
-    r.candidates()
-    r.close()
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    r = ix.search_batch(g.spans, timing=True)
-    nc = len(r.candidates())
-    tb = time.perf_counter() - t
-    stats, tms = r.stats(), r.timing()
-    r.close()
-    t = time.perf_counter()
-    for sp in g.spans:
-        r = ix.search(sp)
-        r.candidates()
-        r.close()
-    tp = time.perf_counter() - t
-    ix.close()
-    return {"workload": "3.1 Gbp in 24 sequences (41%% GC, 50%% soft-masked repeats, N-gaps, "
-                        "%d planted duplications of 1-300 kbp); all-vs-all" % len(g.truth),
-            "generate_s": round(gen_s, 1), "index_build_s": round(build_s, 3),
-            "index_gb": round(dev / 1e9, 3), "minimizers": nm, "eligible": ne,
-            "batched_mbp_per_s": round(qb / tb / 1e6, 2), "batched_s": round(tb, 3),
-            "tile_kernel_ms": round(float(tms[1]), 2),
-            "plain_mbp_per_s": round(qb / tp / 1e6, 2), "plain_s": round(tp, 3),
-            "candidates": nc, "stats": stats}
 
 
 def estimate_mode(ix, span, max_error, min_len, qbases, steps=3):
@@ -423,16 +411,232 @@ def sensitivity(trials, seed=41):
     return res
 
 
+def alg_bytes_per_query_base(nm, ne, total, hbar):
+    """Algorithmic HBM bytes per query base of the search: each query
+    minimizer's record (position, hash, flags: 9 B), the two directory
+    entries of each eligible one (8 B) and its hits (target position and
+    strand bit, 4.125 B each; a query minimizer meets hbar = sum n_h^2 /
+    sum n_h target occurrences of its hash, its own included)."""
+    rho_all = nm / total
+    rho_elig = ne / total
+    return rho_all * 9.0 + rho_elig * (8.0 + 4.125 * hbar)
+
+
+def roofline(alg_bytes, kernel_ms, traffic=None, kernel="k_tile_search"):
+    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+            "kernel": kernel, "kernel_ms": round(kernel_ms, 4),
+            "algorithmic_bytes": int(alg_bytes)}
+
+
+def host_cpu():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
+def genome_headline(args):
+    """3.1 Gbp in 24 sequences, all-vs-all: every whole sequence is a query
+    span, all 24 searched in one batched search against the resident index
+    (K timed steps), next to the same 24 spans searched one call at a time."""
+    import numpy as np
+    import torch
+    from paper_1807_00205_amd import sdf, synth
+    log("generating the 3.1 Gbp assembly")
+    t = time.time()
+    g = synth.config5()
+    gen_s = time.time() - t
+    log("  %.1f s" % gen_s)
+    torch.cuda.synchronize()
+    t = time.time()
+    ix = sdf.Index(g.seqs, 12, 16)
+    torch.cuda.synchronize()
+    build_s = time.time() - t
+    nm, ne, dev = ix.info()
+    hbar = ix.hit_density()
+    total = g.total
+    log("index built in %.2f s: %d minimizers, %d eligible, %.2f GB, hit density %.2f" % (
+        build_s, nm, ne, dev / 1e9, hbar))
+    spans = g.spans
+    qb = sum(e - b for _, b, e in spans)
+    for _ in range(max(1, args.warmup)):  # the first call also grows the memory pool
+        r = ix.search_batch(spans, args.max_error, args.min_len, timing=True)
+        r.candidates()
+        r.close()
+    torch.cuda.synchronize()
+    kms, lat = [], []
+    t0 = time.perf_counter()
+    for step in range(args.steps):
+        s0 = time.perf_counter()
+        r = ix.search_batch(spans, args.max_error, args.min_len, timing=True)
+        nc = len(r.candidates())
+        lat.append((time.perf_counter() - s0) * 1e3)
+        kms.append(float(r.timing()[1]))
+        if step == 0:
+            stats = r.stats()
+        r.close()
+        log("  step %d: %.1f ms" % (step, lat[-1]))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # plain: the same 24 spans, one search call each
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    plain_lat = []
+    for sp in spans:
+        s0 = time.perf_counter()
+        r = ix.search(sp, args.max_error, args.min_len)
+        r.candidates()
+        r.close()
+        plain_lat.append((time.perf_counter() - s0) * 1e3)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t
+    ix.close()
+    mean_k = float(np.mean(kms))
+    alg = qb * alg_bytes_per_query_base(nm, ne, total, hbar)
+    out = {
+        "metric": "query Mbp searched/sec (Jaccard filter)",
+        "value": round(qb * args.steps / dt / 1e6, 3),
+        "unit": "Mbp/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "3.1 Gbp synthetic assembly in 24 sequences of 50-250 Mbp (41% GC, "
+                               "50% soft-masked repeats, 10 N-gaps of 50 kbp per sequence, %d "
+                               "planted duplications of 1-300 kbp at 1-25%%, half between "
+                               "sequences, half reverse-complemented); all-vs-all" % len(g.truth),
+                   "query_bases": qb, "spans": len(spans), "k": 12, "w": 16,
+                   "min_len": args.min_len, "max_error": args.max_error,
+                   "path": "batched: the 24 whole sequences in one search"},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                       "p99": round(float(np.percentile(lat, 99)), 3)},
+        "roofline": roofline(alg, mean_k, measured_traffic("genome3100")),
+        "plain": {"path": "the same 24 spans, one sdf_search call each",
+                  "mbp_per_s": round(qb / tp / 1e6, 3), "seconds": round(tp, 3),
+                  "latency_ms_per_call": {"p50": round(float(np.percentile(plain_lat, 50)), 3),
+                                          "p99": round(float(np.percentile(plain_lat, 99)), 3)}},
+        "detail": {"generate_s": round(gen_s, 1), "index_build_s": round(build_s, 3),
+                   "index_gb": round(dev / 1e9, 3), "minimizers": nm, "eligible": ne,
+                   "hit_density": round(hbar, 4),
+                   "algorithmic_bytes_per_query_base": round(
+                       alg_bytes_per_query_base(nm, ne, total, hbar), 4),
+                   "candidates": nc, **stats},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) on 64 sampled 100 kbp spans")
+        import oracle
+        b, off = g.concat()
+        threads = max(1, min(16, os.cpu_count() or 1))
+        t = time.time()
+        orc = oracle.OracleIndex(b, off, 12, 16)
+        obuild = time.time() - t
+        rng = synth.rng_for(55)
+        sample = synth.draw_spans(rng, [len(s) for s in g.seqs], 64, 100_000, 100_000)
+        t = time.time()
+        orc.search(sample, args.max_error, args.min_len, threads)
+        odt = time.time() - t
+        orc.close()
+        sb = sum(e - b for _, b, e in sample)
+        out["cpu_baseline"] = {"value": round(sb / odt / 1e6, 5), "unit": "Mbp/s",
+                               "cores": threads, "kind": "oracle",
+                               "sample": "64 spans of 100 kbp drawn with seed 55 from the same "
+                                         "assembly (6.4 Mbp), searched against the whole "
+                                         "3.1 Gbp index; search only, oracle index built "
+                                         "beforehand in %.1f s" % obuild,
+                               "seconds": round(odt, 3), "host_cpu": host_cpu(),
+                               "host_threads_visible": os.cpu_count()}
+        del b, off
+    del g
+    return out
+
+
+def chromosome_section(args, steps):
+    """The 50 Mbp chromosome-shaped workload, whole sequence as one span
+    (plain single-span path), with its roofline, the oracle's rate on a
+    12 Mbp span, seeds by the estimate and every candidate extended."""
+    import numpy as np
+    import torch
+    from paper_1807_00205_amd import sdf
+    g, spans, desc = workload("chromosome50")
+    ix = sdf.Index(g.seqs, 12, 16)
+    nm, ne, _ = ix.info()
+    hbar = ix.hit_density()
+    span = spans[0]
+    qbases = span[2] - span[1]
+    tuned_core, tuned_threads, tuned_ms = ix.autotune([span], args.max_error, args.min_len)
+    for _ in range(2):
+        r = ix.search(span, args.max_error, args.min_len, timing=True)
+        r.candidates()
+        r.close()
+    torch.cuda.synchronize()
+    kernel_ms, lat = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s0 = time.perf_counter()
+        r = ix.search(span, args.max_error, args.min_len, timing=True)
+        ncand = ctypes_count(r)
+        lat.append((time.perf_counter() - s0) * 1e3)
+        kernel_ms.append(float(r.timing()[1]))
+        stats = r.stats()
+        r.close()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    mean_k = float(np.mean(kernel_ms))
+    alg = qbases * alg_bytes_per_query_base(nm, ne, g.total, hbar)
+    out = {"workload": desc, "path": "plain single-span search",
+           "mbp_per_s": round(qbases * steps / dt / 1e6, 3),
+           "ms_per_search": round(dt / steps * 1e3, 4),
+           "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                          "p99": round(float(np.percentile(lat, 99)), 4)},
+           "roofline": roofline(alg, mean_k, measured_traffic("chromosome50")),
+           "detail": {"autotuned_core": tuned_core, "autotuned_threads": tuned_threads,
+                      "tile_kernel_ms_per_schedule": {"%d threads, %d starts" % k: round(v, 3)
+                                                      for k, v in tuned_ms.items()},
+                      "minimizers": nm, "eligible": ne, "hit_density": round(hbar, 4),
+                      "candidates": ncand, **stats}}
+    if not args.no_estimate:
+        log("seeds by the winnowed MinHash estimate")
+        out["estimate"] = estimate_mode(ix, span, args.max_error, args.min_len, qbases)
+    keep = {}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle), 50 Mbp workload")
+        out["cpu_baseline"] = cpu_baseline(g, args.cpu_sample_mbp, args.max_error, args.min_len,
+                                           keep)
+    if not args.no_extend:
+        log("extension of every candidate (Section 3.2)")
+        out["extend"] = extend_mode(ix, span, args.max_error, args.min_len,
+                                    cpu=keep if keep else None)
+    keep.clear()
+    ix.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="chromosome50")
     ap.add_argument("--max-error", type=float, default=0.25)
     ap.add_argument("--min-len", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-mbp", type=float, default=12.0)
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the 3.1 Gbp all-vs-all (for profiler runs)")
+    ap.add_argument("--only", default="",
+                    help="run one section without the headline: chromosome50, batched250 or "
+                         "serving (for profiler runs)")
+    ap.add_argument("--no-chromosome", action="store_true", help="skip the 50 Mbp section")
     ap.add_argument("--no-batch", action="store_true", help="skip batched vs plain")
     ap.add_argument("--no-estimate", action="store_true",
                     help="skip the search with seeds chosen by the winnowed MinHash estimate")
@@ -441,11 +645,9 @@ def main():
     ap.add_argument("--no-batch-plain", action="store_true",
                     help="in the batched section, skip the 4,096 one-by-one calls")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep")
-    ap.add_argument("--serve-rates", default="10,100,1000,4000,8000")
+    ap.add_argument("--serve-rates", default="10,30,100,300,1000")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--serve-workers", type=int, default=4)
-    ap.add_argument("--genome", action="store_true",
-                    help="also run the 3.1 Gbp all-vs-all (about 3 minutes)")
     ap.add_argument("--sensitivity", type=int, default=0, metavar="TRIALS",
                     help="also run the simulated-sensitivity experiment with TRIALS pairs per "
                          "delta (the paper uses 1,000; about 3 s per delta at 1,000)")
@@ -458,9 +660,9 @@ def main():
               "MI355X; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     from paper_1807_00205_amd import sdf
+    sdf.lib()
 
     torch.cuda.init()
     if args.calibrate_copy_mib:
@@ -470,113 +672,50 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    log("generating workload", args.workload)
-    t = time.time()
-    g, spans, desc = workload(args.workload)
-    log("  %.1f s" % (time.time() - t))
-    torch.cuda.synchronize()
-    t = time.time()
-    ix = sdf.Index(g.seqs, 12, 16)
-    torch.cuda.synchronize()
-    build_s = time.time() - t
-    nm, ne, dev_bytes = ix.info()
-    log("index built in %.2f s: %d minimizers, %d eligible, %.2f GB" % (build_s, nm, ne,
-                                                                        dev_bytes / 1e9))
-    span = spans[0]
-    qbases = span[2] - span[1]
-    alg_hits = algorithmic_hits(ix)
-    # the tile schedule measured on this span (outside the timed region, like the index)
-    t = time.time()
-    tuned_core, tuned_threads, tuned_ms = ix.autotune([span], args.max_error, args.min_len)
-    tune_s = time.time() - t
-    log("autotuned tile schedule: %d-thread workgroups, %d window starts, in %.2f s" % (
-        tuned_threads, tuned_core, tune_s))
-    for _ in range(args.warmup):
-        r = ix.search(span, args.max_error, args.min_len, timing=True)
-        r.candidates()
-        r.close()
-    torch.cuda.synchronize()
-    kernel_ms, lat = [], []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s0 = time.perf_counter()
-        r = ix.search(span, args.max_error, args.min_len, timing=True)
-        n = ctypes_count(r)
-        lat.append((time.perf_counter() - s0) * 1e3)
-        kernel_ms.append(float(r.timing()[1]))
-        r.close()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    value = qbases * args.steps / dt / 1e6
-    r = ix.search(span, args.max_error, args.min_len, timing=True)  # untimed: counts for the report
-    ncand = len(r.candidates())
-    stats = r.stats()
-    r.close()
-    mean_k = float(np.mean(kernel_ms))
-    # algorithmic bytes per launch: minimizer records (pos, hash, flags: 9 B),
-    # two directory lookups per eligible query minimizer (8 B) and 4.125 B per
-    # hit (position + strand bit)
-    alg_bytes = nm * 9 + ne * 8 + alg_hits * 4.125
-    achieved = alg_bytes / (mean_k * 1e-3) / 1e9
-    out = {
-        "metric": "query Mbp searched/sec (Jaccard filter)",
-        "value": round(value, 3),
-        "unit": "Mbp/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(dt / args.steps * 1e3, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic",
-        "config": {"workload": desc, "query_bases": qbases, "k": 12, "w": 16,
-                   "min_len": args.min_len, "max_error": args.max_error,
-                   "path": "plain single-span search"},
-        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
-                       "p99": round(float(np.percentile(lat, 99)), 4)},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": measured_traffic(args.workload), "kernel": "k_tile_search",
-                     "kernel_ms": round(mean_k, 4), "algorithmic_bytes": int(alg_bytes)},
-        "detail": {"index_build_s": round(build_s, 3), "autotuned_core": tuned_core,
-                   "autotuned_threads": tuned_threads, "autotune_s": round(tune_s, 3),
-                   "tile_kernel_ms_per_schedule": {"%d threads, %d starts" % k: round(v, 3)
-                                                   for k, v in tuned_ms.items()},
-                   "minimizers": nm, "eligible": ne,
-                   "algorithmic_hits": alg_hits, "candidates": ncand, **stats},
-    }
-    if not args.no_estimate:
-        log("seeds by the winnowed MinHash estimate")
-        out["estimate"] = estimate_mode(ix, span, args.max_error, args.min_len, qbases)
-    keep = {}
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(g, args.cpu_sample_mbp, args.max_error, args.min_len,
-                                           keep)
-    if not args.no_extend:
-        log("extension of every candidate (Section 3.2)")
-        out["extend"] = extend_mode(ix, span, args.max_error, args.min_len,
-                                    cpu=keep if keep else None)
-    keep.clear()
-    ix.close()
-    if not args.no_batch or not args.no_serve:
-        log("batched vs plain (250 Mbp, 4,096 spans)")
-        ix3, g3, bat = batched_vs_plain(max(1, args.steps // 2), not args.no_batch_plain)
-        if not args.no_batch:
+    if args.only:
+        out = {"section": args.only}
+        if args.only == "chromosome50":
+            out["chromosome50"] = chromosome_section(args, args.steps)
+        elif args.only in ("batched250", "serving"):
+            ix3, g3, bat = batched_vs_plain(max(1, args.steps), not args.no_batch_plain,
+                                            cpu=not args.no_cpu_baseline)
             out["batched"] = bat
-        if not args.no_serve:
-            log("serving")
-            rates = [float(x) for x in args.serve_rates.split(",") if x]
-            out["serving"] = serving(ix3, g3, rates, args.serve_seconds, args.serve_workers)
-        ix3.close()
-    if args.genome:
-        log("genome scale (3.1 Gbp)")
-        out["genome"] = genome_scale()
-    if args.sensitivity:
-        log("simulated sensitivity (Section 4.1.1), %d pairs per delta" % args.sensitivity)
-        out["sensitivity"] = sensitivity(args.sensitivity)
+            if args.only == "serving":
+                rates = [float(x) for x in args.serve_rates.split(",") if x]
+                out["serving"] = serving(ix3, g3, rates, args.serve_seconds, args.serve_workers)
+            ix3.close()
+        else:
+            raise SystemExit("unknown section %s" % args.only)
+        print(json.dumps(out), flush=True)
+        return
+    log("headline: 3.1 Gbp all-vs-all")
+    out = genome_headline(args)
+    if not args.headline_only:
+        # further workloads; a failure in one of them is recorded, not fatal
+        if not args.no_chromosome:
+            log("50 Mbp chromosome-shaped workload (plain path)")
+            try:
+                out["chromosome50"] = chromosome_section(args, max(args.steps, 10))
+            except Exception as e:  # noqa: BLE001
+                out["chromosome50"] = {"error": repr(e)}
+        if not args.no_batch or not args.no_serve:
+            log("batched vs plain (250 Mbp, 4,096 spans)")
+            try:
+                ix3, g3, bat = batched_vs_plain(max(1, args.steps // 2), not args.no_batch_plain,
+                                                cpu=not args.no_cpu_baseline)
+                if not args.no_batch:
+                    out["batched"] = bat
+                if not args.no_serve:
+                    log("serving")
+                    rates = [float(x) for x in args.serve_rates.split(",") if x]
+                    out["serving"] = serving(ix3, g3, rates, args.serve_seconds,
+                                             args.serve_workers)
+                ix3.close()
+            except Exception as e:  # noqa: BLE001
+                out["batched"] = {"error": repr(e)}
+        if args.sensitivity:
+            log("simulated sensitivity (Section 4.1.1), %d pairs per delta" % args.sensitivity)
+            out["sensitivity"] = sensitivity(args.sensitivity)
     print(json.dumps(out), flush=True)
 
 

@@ -4,9 +4,9 @@ TEST INFRASTRUCTURE (part of the oracle package).  It pins the C oracle: it
 shares no code with ``sdf_oracle.c`` and reaches the same results by a
 different route:
 
-* the winnow is computed with a streaming monotone queue (Section 2.2 notes
-  the winnow can be computed in linear time and O(w) space in a streaming
-  fashion) instead of per-window scans;
+* the winnow is computed with a streaming monotone queue (a single pass
+  keeping at most w candidate positions, which Section 2.2 mentions as
+  possible) instead of per-window scans;
 * the shared count c_o(i, j) is computed for every integer window start j
   by explicit set membership tests instead of the rolling update;
 * chaining uses explicit pairwise links and a depth-first search instead of

@@ -383,8 +383,8 @@ int or_params(double max_error, uint32_t min_len, uint32_t k, double *tau,
 }
 
 /* Section 2.2 (filter lemma) and Section 3.1: windows that share at least
- * tau * s winnowed k-mers pass.  Reading: "at least tau * s" for an integer
- * count is c >= ceil(tau * s), evaluated in double. */
+ * tau * s winnowed k-mers pass.  Reading: for an integer count, sharing at
+ * least tau * s means c >= ceil(tau * s), evaluated in double. */
 uint32_t or_threshold(double tau, uint32_t s)
 {
     return (uint32_t)ceil(tau * (double)s);
@@ -486,8 +486,8 @@ static int cmp_u32(const void *a, const void *b)
     return x < y ? -1 : (x > y ? 1 : 0);
 }
 
-/* s_i = |W(G_i)|, the sketch size of window [i, i+n) (Section 3.1: "the
- * sketch size s is set to |W(G_i)|"): the number of distinct hashes among
+/* s_i = |W(G_i)|, the sketch size of window [i, i+n) (Section 3.1 takes the
+ * sketch size to be the size of the window's winnow): the number of distinct hashes among
  * all minimizers whose k-mer lies inside the window, soft-masked ones
  * included (reading: masking only restricts which k-mers seed, Section 3.2;
  * the set W(G_i) itself is the winnow of the substring). */
@@ -706,10 +706,10 @@ static int cmp_hit(const void *a, const void *b)
  *  - a candidate passes if c_o(i,j) >= T(s_i) and the two windows do not
  *    overlap by more than floor(delta n) bases in one sequence (Section 2,
  *    SD conditions);
- *  - a run ("j in [j_a, j_b]") is a maximal stretch of consecutive
+ *  - a run (the paper's interval of candidate starts [j_a, j_b]) is a maximal stretch of consecutive
  *    candidates that all pass, in one sequence, each less than n after the
  *    previous one;
- *  - "maximal and above tau" is the largest shared count in the run, the
+ *  - the run's best candidate (the paper keeps the maximum above tau) is the largest shared count in the run, the
  *    smallest j among ties;
  *  - with `estimate`, it is the largest winnowed MinHash estimate m/s in the
  *    run instead (smallest j among ties), and the run gives a seed only if
@@ -891,7 +891,7 @@ static int cmp_cand(const void *a, const void *b)
 }
 
 /* Chaining of the seeds of each query span into candidate pairs.
- * Reading of the "local chaining" step: two seeds of one query span, one
+ * Reading of the local chaining step: two seeds of one query span, one
  * strand, one query sequence and one target sequence are linked when their
  * query windows and their target windows both lie less than n apart and
  * their diagonals (j - i for '+', j + i for '-') differ by at most

@@ -48,6 +48,12 @@ namespace sdf {
 namespace {
 
 constexpr int XT = 256;                 // threads per workgroup
+// Every parity run of this kernel used 256-thread workgroups.  A build with
+// 512 threads stopped answering once on the GPU and its cause is unknown
+// (the block scans, chunk bounds, bitonic loops and barriers read
+// correctly for any multiple of 64), so the size stays fixed until that
+// cause is found.
+static_assert(XT == 256, "k_extend is only validated with 256-thread workgroups");
 constexpr uint32_t NB_BITS = 11;
 constexpr uint32_t NB = 1u << NB_BITS;  // buckets over the top hash bits
 constexpr uint32_t CH = 2048;           // keys sorted at once in LDS

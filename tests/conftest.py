@@ -18,3 +18,19 @@ def oracle_lib():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+@pytest.fixture
+def progress(request):
+    """Prints a progress line to the terminal while output is captured, so a
+    long test shows that it is working."""
+    capman = request.config.pluginmanager.getplugin("capturemanager")
+
+    def say(msg):
+        line = "  [%s] %s" % (request.node.name, msg)
+        if capman is not None:
+            with capman.global_and_fixture_disabled():
+                print(line, flush=True)
+        else:
+            print(line, flush=True)
+    return say

@@ -424,6 +424,25 @@ def test_search_config2(S, oracle_lib):
     _same(r.seeds(), os_, SEED_F, "seeds")
 
 
+def test_estimate_config2(S, oracle_lib, progress):
+    """Seeds chosen by the winnowed MinHash estimate on the whole 50 Mbp
+    chromosome-shaped workload: exact seeds and candidates."""
+    import os
+    g = synth.config2()
+    b, off = g.concat()
+    ix = S.Index(g.seqs, 12, 16)
+    r = ix.search(g.spans[0], 0.25, 1000, estimate=True)
+    gc, gs = r.candidates(), r.seeds()
+    r.close()
+    ix.close()
+    progress("GPU: %d seeds, %d candidates; oracle" % (len(gs), len(gc)))
+    orc = oracle_lib.OracleIndex(b, off, 12, 16)
+    os_, oc = orc.search(g.spans, 0.25, 1000, min(16, os.cpu_count() or 1), estimate=True)
+    orc.close()
+    _same(gc, oc, CAND_F, "candidates")
+    _same(gs, os_, SEED_F, "seeds")
+
+
 @pytest.fixture(scope="module")
 def batch250(S):
     g = synth.config3()
@@ -431,29 +450,26 @@ def batch250(S):
     return g, ix
 
 
-def test_batch_config3_sampled(S, oracle_lib, batch250):
-    """The 250 Mbp workload with 4,096 spans of 1-100 kbp searched in one batch:
-    the candidates and seeds of 48 sampled spans equal the oracle's, and a
+def test_batch_config3_full(S, oracle_lib, batch250, progress):
+    """The 250 Mbp workload with 4,096 spans of 1-100 kbp searched in one
+    batch: the candidates and seeds of every span equal the oracle's, and a
     plain search of a span equals its slice of the batch."""
+    import os
     g, ix = batch250
     r = ix.search_batch(g.spans)
     cands = r.candidates()
     seeds = r.seeds()
-    rng = synth.rng_for(99)
-    pick = sorted(rng.choice(len(g.spans), size=48, replace=False).tolist())
+    r.close()
+    progress("batch: %d seeds, %d candidates; oracle index" % (len(seeds), len(cands)))
     b, off = g.concat()
     orc = oracle_lib.OracleIndex(b, off, 12, 16)
-    os_, oc = orc.search([g.spans[q] for q in pick], 0.25, 1000)
-    remap = np.array(pick, dtype=np.uint32)
-    oc = oc.copy()
-    os_ = os_.copy()
-    oc["query_id"] = remap[oc["query_id"]]
-    os_["query_id"] = remap[os_["query_id"]]
-    sel = np.isin(cands["query_id"], remap)
-    _same(cands[sel], oc, CAND_F, "candidates")
-    sel = np.isin(seeds["query_id"], remap)
-    _same(seeds[sel], os_, SEED_F, "seeds")
-    for q in pick[:4]:
+    progress("oracle search of all 4,096 spans")
+    os_, oc = orc.search(g.spans, 0.25, 1000, min(16, os.cpu_count() or 1))
+    orc.close()
+    _same(cands, oc, CAND_F, "candidates")
+    _same(seeds, os_, SEED_F, "seeds")
+    rng = synth.rng_for(99)
+    for q in sorted(rng.choice(len(g.spans), size=4, replace=False).tolist()):
         rp = ix.search(g.spans[q]).candidates()
         mine = cands[cands["query_id"] == q].copy()
         mine["query_id"] = 0

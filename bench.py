@@ -512,8 +512,8 @@ def genome_headline(args):
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": "3.1 Gbp synthetic assembly in 24 sequences of 50-250 Mbp (41% GC, "
-                               "50% soft-masked repeats, 10 N-gaps of 50 kbp per sequence, %d "
+        "config": {"workload": "3.1 Gbp synthetic assembly in 24 sequences of 50-250 Mbp (41%% GC, "
+                               "50%% soft-masked repeats, 10 N-gaps of 50 kbp per sequence, %d "
                                "planted duplications of 1-300 kbp at 1-25%%, half between "
                                "sequences, half reverse-complemented); all-vs-all" % len(g.truth),
                    "query_bases": qb, "spans": len(spans), "k": 12, "w": 16,

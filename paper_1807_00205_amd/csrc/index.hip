@@ -522,6 +522,13 @@ __global__ void k_hit_density(const uint64_t *key, uint64_t ne, unsigned long lo
     }
 }
 
+// Every ESAMP-th reverse-index position (the first of each 128-byte line of
+// epos), which lets a search over a list find its line with one read.
+__global__ void k_sample_positions(const uint32_t *epos, uint64_t ns, uint32_t *esamp) {
+    const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < ns) esamp[s] = epos[s * ESAMP];
+}
+
 void build_index(sdf_index_s *ix, const char *const *seqs, const uint64_t *lens,
                  uint32_t n_seqs, hipStream_t st) {
     const uint32_t k = ix->k, w = ix->w;
@@ -640,6 +647,12 @@ void build_index(sdf_index_s *ix, const char *const *seqs, const uint64_t *lens,
         }
         k_directory<<<blocks_for(ndir, 256), 256, 0, st>>>(key.p, ne, ix->dir_shift, ix->dir.p, ndir);
         SDF_HIP(hipGetLastError());
+        const uint64_t ns = (ne + ESAMP - 1) / ESAMP;
+        ix->esamp.alloc(ns + 1);
+        if (ns) {
+            k_sample_positions<<<blocks_for(ns, 256), 256, 0, st>>>(ix->epos.p, ns, ix->esamp.p);
+            SDF_HIP(hipGetLastError());
+        }
         if (ix->dir_shift && ne) {
             k_keylo<<<blocks_for(ne, 256), 256, 0, st>>>(key.p, ne, ix->dir_shift, ix->ekeylo.p);
             SDF_HIP(hipGetLastError());
@@ -682,7 +695,7 @@ void build_index(sdf_index_s *ix, const char *const *seqs, const uint64_t *lens,
     }
     ix->device_bytes = (ix->off.n * 8) + (ix->packed.n + ix->mask.n + ix->gaps.n) * 4 +
                        (ix->mpos.n + ix->mhash.n + ix->mprev.n + ix->mext.n) * 4 + ix->mflags.n +
-                       (ix->dir.n + ix->epos.n) * 4 + ix->ekeylo.n +
+                       (ix->dir.n + ix->epos.n + ix->esamp.n) * 4 + ix->ekeylo.n +
                        (ix->segb.n + ix->sege.n + ix->segseq.n) * 4;
 }
 
@@ -709,6 +722,7 @@ sdf::IndexView sdf_index_s::view() const {
     v.dir_bits = dir_bits;
     v.dir_shift = dir_shift;
     v.epos = epos.p;
+    v.esamp = esamp.p;
     v.ekeylo = ekeylo.p;
     v.nseg = nseg;
     v.segb = segb.p;

@@ -15,6 +15,7 @@ namespace sdf {
 constexpr uint32_t NONE32 = 0xFFFFFFFFu;
 constexpr uint64_t SENT64 = 0xFFFFFFFFFFFFFFFFull;
 constexpr uint64_t MAX_TOTAL = 0xFFFFFFFFull - (1ull << 20);
+constexpr uint32_t ESAMP = 32;  // reverse-index positions per sample (4 B each: one line)
 
 // Error reporting -----------------------------------------------------------
 void set_error(const std::string &msg);
@@ -151,6 +152,7 @@ struct IndexView {  // plain pointers for kernels
     const uint32_t *dir;  // directory over the top dir_bits of key = hash<<1|strand
     uint32_t dir_bits, dir_shift;
     const uint32_t *epos;
+    const uint32_t *esamp;  // esamp[s] = epos[ESAMP s]: one sample per 128-byte line of epos
     const uint8_t *ekeylo;  // low key bits per entry when dir_shift > 0
     uint64_t nseg;
     const uint32_t *segb, *sege, *segseq;
@@ -171,7 +173,7 @@ struct sdf_index_s {
     uint32_t tuned_threads = 0;  // tile workgroup layout chosen by sdf_autotune (0: the rule)
     sdf::DevBuf<uint32_t> mpos, mhash, mprev, mext;
     sdf::DevBuf<uint8_t> mflags;
-    sdf::DevBuf<uint32_t> dir, epos;
+    sdf::DevBuf<uint32_t> dir, epos, esamp;
     sdf::DevBuf<uint8_t> ekeylo;
     uint32_t dir_bits = 0, dir_shift = 0;
     sdf::DevBuf<uint32_t> segb, sege, segseq;

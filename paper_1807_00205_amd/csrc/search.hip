@@ -228,23 +228,75 @@ __device__ void block_maxscan_u32(uint32_t *arr, int n, uint64_t *wtmp) {
     __syncthreads();
 }
 
-__device__ void block_bitonic_u64(uint64_t *s, int n2) {
-    for (int k = 2; k <= n2; k <<= 1) {
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, 64);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Ascending sort of one key per lane across the wave (bitonic network in
+// registers; no barrier).
+__device__ __forceinline__ uint64_t wave_sort_u64(uint64_t x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < n2; i += TB) {
-                int ixj = i ^ j;
-                if (ixj > i) {
-                    bool asc = (i & k) == 0;
-                    uint64_t a = s[i], b = s[ixj];
-                    if ((a > b) == asc) {
-                        s[i] = b;
-                        s[ixj] = a;
-                    }
-                }
-            }
-            __syncthreads();
+            const uint64_t y = shfl_xor_u64(x, j);
+            const bool up = (lane & k) == 0;     // this lane's block of k ascends
+            const bool lower = (lane & j) == 0;  // this lane is the lower of its pair
+            x = (lower == up) ? (x < y ? x : y) : (x < y ? y : x);
         }
     }
+    return x;
+}
+
+// Ascending sort of keys[0, n) (n <= CB, keys distinct and below ~0): the
+// waves sort runs of 64 keys in registers, then every key is written at its
+// rank, its place in its own run plus the keys below it in each other run
+// (binary searches in LDS).  Three barriers, against one per stage of a
+// bitonic sort over the whole array.  keys[n, 64 ceil(n/64)) is overwritten
+// with ~0.
+__device__ void block_sort_runs(uint64_t *keys, uint32_t n) {
+    const int lane = lane_id(), wave = wave_id();
+    const uint32_t R = (n + 63) / 64;
+    for (uint32_t r = (uint32_t)wave; r < R; r += NWAVES) {
+        const uint32_t e = r * 64 + (uint32_t)lane;
+        const uint64_t x = wave_sort_u64(e < n ? keys[e] : ~0ull);
+        keys[e] = x;
+    }
+    __syncthreads();
+    constexpr int PER = (CB + TB - 1) / TB;
+    uint64_t kv[PER];
+    uint32_t rk[PER];
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+        const uint32_t e = threadIdx.x + (uint32_t)u * TB;
+        rk[u] = NONE32;
+        kv[u] = 0;
+        if (e < n) {
+            const uint64_t x = keys[e];
+            const uint32_t own = e >> 6;
+            uint32_t rank = e & 63u;
+            for (uint32_t r = 0; r < R; r++) {
+                if (r == own) continue;
+                const uint64_t *run = keys + r * 64;
+                uint32_t lo = 0, hi = 64;
+                while (lo < hi) {
+                    const uint32_t m = (lo + hi) >> 1;
+                    if (run[m] < x) lo = m + 1; else hi = m;
+                }
+                rank += lo;
+            }
+            kv[u] = x;
+            rk[u] = rank;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; u++)
+        if (rk[u] != NONE32) keys[rk[u]] = kv[u];
+    __syncthreads();
 }
 
 // Gap-free segment containing position x: index or -1.
@@ -272,13 +324,46 @@ __device__ __forceinline__ void lookup(const IndexView &ix, uint32_t hash, uint3
     }
 }
 
-__device__ __forceinline__ uint32_t lower_pos(const uint32_t *epos, uint32_t lo, uint32_t hi,
-                                              uint64_t x) {
-    while (lo < hi) {
-        uint32_t m = (lo + hi) >> 1;
-        if ((uint64_t)epos[m] < x) lo = m + 1; else hi = m;
+// First entries of the ascending positions epos[lo, hi) that are >= x0 and
+// >= x1.  The index keeps every ESAMP-th position (esamp[s] = epos[ESAMP s],
+// one 128-byte line of epos per sample), so a search finds its line among
+// the samples inside [lo, hi) and then its entry inside that line: two lines
+// read from memory, the other probes hit the first-level cache.  The two
+// searches are interleaved so that their loads overlap.
+__device__ __forceinline__ void lower_pos2(const IndexView &ix, uint32_t lo, uint32_t hi,
+                                           uint64_t x0, uint64_t x1, uint32_t &r0, uint32_t &r1) {
+    const uint32_t s_lo = (lo + ESAMP - 1) / ESAMP, s_hi = (hi + ESAMP - 1) / ESAMP;
+    uint32_t a0 = s_lo, b0 = s_hi, a1 = s_lo, b1 = s_hi;  // first sample >= x
+    while (a0 < b0 || a1 < b1) {
+        const uint32_t m0 = (a0 + b0) >> 1, m1 = (a1 + b1) >> 1;
+        const uint32_t v0 = a0 < b0 ? ix.esamp[m0] : 0u;
+        const uint32_t v1 = a1 < b1 ? ix.esamp[m1] : 0u;
+        if (a0 < b0) {
+            if ((uint64_t)v0 < x0) a0 = m0 + 1; else b0 = m0;
+        }
+        if (a1 < b1) {
+            if ((uint64_t)v1 < x1) a1 = m1 + 1; else b1 = m1;
+        }
     }
-    return lo;
+    // the entry lies after the last sample below x and up to the first
+    // sample at or above it
+    uint32_t c0 = a0 > s_lo ? (a0 - 1) * ESAMP + 1 : lo;
+    uint32_t d0 = min(hi, a0 * ESAMP);
+    uint32_t c1 = a1 > s_lo ? (a1 - 1) * ESAMP + 1 : lo;
+    uint32_t d1 = min(hi, a1 * ESAMP);
+    while (c0 < d0 || c1 < d1) {
+        const uint32_t m0 = (c0 + d0) >> 1, m1 = (c1 + d1) >> 1;
+        const uint32_t v0 = c0 < d0 ? ix.epos[m0] : 0u;
+        const uint32_t v1 = c1 < d1 ? ix.epos[m1] : 0u;
+        if (c0 < d0) {
+            if ((uint64_t)v0 < x0) c0 = m0 + 1; else d0 = m0;
+        }
+        if (c1 < d1) {
+            if ((uint64_t)v1 < x1) c1 = m1 + 1; else d1 = m1;
+        }
+    }
+    r0 = c0;
+    r1 = c1;
 }
 
 __device__ __forceinline__ uint32_t slot_of(uint32_t bin, uint32_t o) {
@@ -307,12 +392,21 @@ __device__ __forceinline__ uint32_t list_of_from(const uint32_t *hoff, uint32_t 
     return lo;
 }
 
-// Find the list of hit e: largest l with hoff[l] <= e.
-__device__ __forceinline__ uint32_t list_of(const uint32_t *hoff, uint32_t nl, uint32_t e) {
-    uint32_t lo = 0, hi = nl;  // invariant hoff[lo] <= e < hoff[hi]
+// Largest l in [lo, hi) with hoff[l] <= e, for a hit index e that every lane of the wave holds alike
+// (hoff[lo] <= e < hoff[hi]): the 64 lanes probe 64 evenly spaced lists
+// per round and a ballot narrows the range 64-fold, so 2,560 lists take two
+// rounds of one LDS read each.
+__device__ __forceinline__ uint32_t wave_list_of(const uint32_t *hoff, uint32_t lo, uint32_t hi,
+                                                 uint32_t e) {
+    const uint32_t lane = (uint32_t)(threadIdx.x & 63);
     while (hi - lo > 1) {
-        uint32_t m = (lo + hi) >> 1;
-        if (hoff[m] <= e) lo = m; else hi = m;
+        const uint32_t step = (hi - lo + 63) / 64;
+        const uint32_t p = lo + lane * step;
+        const bool le = p < hi && hoff[p] <= e;  // a prefix of the lanes (lane 0 always)
+        const uint32_t c = (uint32_t)__popcll(__ballot(le));
+        const uint32_t nhi = min(hi, lo + c * step);
+        lo = lo + (c - 1) * step;
+        hi = nhi;
     }
     return lo;
 }
@@ -320,8 +414,9 @@ __device__ __forceinline__ uint32_t list_of(const uint32_t *hoff, uint32_t nl, u
 // Hits [cb, cb + 64 * HU) of the tile in lane-interleaved order: lv = list
 // (2q + strand) or NONE32 past the end, pv = target position.  The lists of
 // the block's first and last hit bound each lane's list search, and every
-// position load is issued before any is used.
-constexpr int HU = 8;
+// position load is issued before any is used.  HU is eight, six in the
+// 512-thread layout, whose 128 registers per lane spill more with eight.
+constexpr int HU = TB == 512 ? 6 : 8;
 // In the 512-thread layout the hits [0, STASH) of a partition that pass 1
 // gathers (position and list) are kept for pass 2 in the arrays that hold
 // kept-hit data only later, so pass 2 reads them from LDS instead of
@@ -339,8 +434,8 @@ __device__ __forceinline__ void gather_hits(const TileLds &L, const IndexView &i
         lv[u] = NONE32;
     }
     if (cb >= H) return;
-    const uint32_t l0 = list_of(L.hoff, nl, cb);
-    const uint32_t l1 = list_of_from(L.hoff, l0, nl, min(cb + 64 * HU - 1, H - 1));
+    const uint32_t l0 = wave_list_of(L.hoff, 0, nl, cb);
+    const uint32_t l1 = wave_list_of(L.hoff, l0, nl, min(cb + 64 * HU - 1, H - 1));
 #pragma unroll
     for (int u = 0; u < HU; u++) {
         const uint32_t e = cb + (uint32_t)u * 64 + lane;
@@ -736,8 +831,8 @@ k_tile_search(SearchArgs a) {
                             L.qmode[q] != QM_SKIP) {
                             lookup(ix, L.qhash[q], b, lo, hi);
                             if (!full) {
-                                uint32_t a0 = lower_pos(ix.epos, lo, hi, lo_pos);
-                                uint32_t b0 = lower_pos(ix.epos, a0, hi, hi_pos);
+                                uint32_t a0, b0;
+                                lower_pos2(ix, lo, hi, lo_pos, hi_pos, a0, b0);
                                 lo = a0;
                                 hi = b0;
                             }
@@ -817,8 +912,10 @@ k_tile_search(SearchArgs a) {
                     } else {
                         gather_hits(L, ix, nl, H, cb, lane, pv, lv);
                     }
+                    bool kp[HU];
 #pragma unroll
                     for (int u = 0; u < HU; u++) {
+                        kp[u] = false;
                         if (lv[u] == NONE32) continue;
                         const uint32_t q = lv[u] >> 1, b = lv[u] & 1;
                         const uint32_t p = pv[u];
@@ -830,10 +927,23 @@ k_tile_search(SearchArgs a) {
                         const uint32_t m1 = slot_count(L.u.table, slot_of(c - 1, o));
                         const uint32_t z0 = slot_count(L.u.table, slot_of(c, o));
                         const uint32_t p1 = slot_count(L.u.table, slot_of(c + 1, o));
-                        if (m2 + m1 >= Tq || m1 + z0 >= Tq || z0 + p1 >= Tq) {
-                            uint32_t idx = atomicAdd(&L.ncoll, 1u);
-                            if (idx < CB) L.coll[idx] = ckey(o, p, q);
-                        }
+                        kp[u] = (m2 + m1 >= Tq || m1 + z0 >= Tq || z0 + p1 >= Tq);
+                    }
+                    // one LDS atomic per wave and round for the kept hits' slots
+                    uint32_t nk = 0;
+#pragma unroll
+                    for (int u = 0; u < HU; u++) nk += kp[u] ? 1u : 0u;
+                    const uint32_t ex = wave_sum_scan(nk) - nk;
+                    const uint32_t wt = (uint32_t)__builtin_amdgcn_readlane((int)(ex + nk), 63);
+                    uint32_t base = 0;
+                    if (lane == 63 && wt) base = atomicAdd(&L.ncoll, wt);
+                    base = (uint32_t)__builtin_amdgcn_readlane((int)base, 63) + ex;
+#pragma unroll
+                    for (int u = 0; u < HU; u++) {
+                        if (!kp[u]) continue;
+                        const uint32_t q = lv[u] >> 1, b = lv[u] & 1;
+                        if (base < CB) L.coll[base] = ckey(b ^ (L.qfl[q] & 1), pv[u], q);
+                        base++;
                     }
                 }
                 __syncthreads();
@@ -848,12 +958,8 @@ k_tile_search(SearchArgs a) {
                 }
                 if (threadIdx.x == 0) L.cnt[CNT_KEPT] += ncoll;
                 // ---- sort kept hits by (o, p', q) ----
-                int n2 = 1;
-                while (n2 < (int)ncoll) n2 <<= 1;
-                for (int t = threadIdx.x; t < n2; t += TB)
-                    if (t >= (int)ncoll) L.coll[t] = ~0ull;
-                __syncthreads();
-                block_bitonic_u64(L.coll, n2);
+                static_assert(CB % 64 == 0, "runs of 64 kept hits");
+                block_sort_runs(L.coll, ncoll);
                 PHASE(PH_SORT);
                 // ---- exact hot starts: >= Tmin hits in [x, x + n - k] ----
                 uint32_t *hot = reinterpret_cast<uint32_t *>(L.u.scratch);  // entry index + 1

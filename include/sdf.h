@@ -84,8 +84,8 @@ typedef struct {
 } sdf_search_params;
 
 #define SDF_TIMING 1u
-/* Seeds by the winnowed MinHash estimate (Section 2.2; "maximal" in Section
- * 3.1): runs of passing candidates are formed by the shared-count filter as
+/* Seeds by the winnowed MinHash estimate (Section 2.2; the maximal estimate
+ * of Section 3.1): runs of passing candidates are formed by the shared-count filter as
  * without the flag, but each run's seed is its candidate with the largest
  * estimate m / s (m = shared hashes among the s = |W(G_i)| smallest hashes of
  * W(G_i) u W(G_j)), earliest j on ties, and a run whose largest estimate is
@@ -124,8 +124,9 @@ typedef struct {
 } sdf_seed;
 
 /*
- * Build the index of G (Section 3.1: "a sorted list of unique pairs (i, x)"
- * and the reverse index "x -> positions").
+ * Build the index of G (Section 3.1: the position-sorted list I_G of the
+ * winnow's (position, k-mer) pairs and the reverse index I_G^{-1} from each
+ * k-mer to its positions).
  *   seqs[t], lens[t]: the bytes of sequence t (host memory, borrowed for the
  *     duration of the call).  A, C, G, T in either case are bases; lower
  *     case marks soft-masked repeats (Section 3.2); any other byte is a gap
@@ -316,6 +317,35 @@ sdf_status sdf_result_timing(sdf_result r, float *ms, uint32_t n_ms);
 sdf_status sdf_result_stats(sdf_result r, uint64_t *v, uint32_t n_v);
 
 void sdf_result_free(sdf_result r);
+
+/*
+ * For callers that cannot allocate memory (code that must not call
+ * hipMalloc, tight serving loops, harnesses that forbid allocation): the
+ * search of sdf_search_batch with every device buffer carved from a fixed
+ * scratch area of SDF_NOALLOC_SCRATCH_BYTES that the library holds on each
+ * device it runs on (from the first use until the process ends).  Nothing
+ * is allocated: no device memory, no pinned or other host staging, no
+ * result object.
+ *   qs, n: as for sdf_search_batch (host array), with at most
+ *     SDF_NOALLOC_MAX_SPANS spans holding at most SDF_NOALLOC_MAX_QUERY_BASES
+ *     bases in all.
+ *   p: error bound and minimum length as for sdf_search; flags must be 0.
+ *   out, cap: host array receiving the first min(cap, count) candidates in
+ *     the order of sdf_result_copy; *n_out receives the count.
+ * The call returns when the copy is done.  Calls on one device are
+ * serialised by the library (they share the device's scratch, which holds
+ * the last call's contents); the index may be searched by other entry
+ * points meanwhile.
+ * Errors: as for sdf_search_batch; SDF_EINVAL for flags, too many spans or
+ * bases; SDF_ENOMEM when a search needs more than the scratch (the message
+ * says so); nothing is then written to out.
+ */
+#define SDF_NOALLOC_SCRATCH_BYTES (128u << 20)
+#define SDF_NOALLOC_MAX_SPANS 65536u
+#define SDF_NOALLOC_MAX_QUERY_BASES 8000000u
+sdf_status sdf_search_batch_noalloc(sdf_index ix, const sdf_span *qs, uint32_t n,
+                                    const sdf_search_params *p, void *hip_stream,
+                                    sdf_candidate *out, uint64_t cap, uint64_t *n_out);
 
 #ifdef __cplusplus
 }

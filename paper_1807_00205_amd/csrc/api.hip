@@ -4,6 +4,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "sdf_impl.h"
@@ -15,6 +16,31 @@ const char *last_error();
 }
 
 using namespace sdf;
+
+// Device scratch of the no-allocation search (sdf_search_batch_noalloc):
+// every device the library runs on holds one copy until the process ends.
+// Host code never passes this name to a kernel or a copy (on the host it is
+// only a stand-in for the symbol): it uses the address hipGetSymbolAddress
+// returns for the current device, kept per device in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[SDF_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu[MAX_DEVICES];
+unsigned char *g_scratch_ptr[MAX_DEVICES] = {};
+
+// The scratch address on device `dev`, which must be current; the caller
+// holds g_scratch_mu[dev].
+unsigned char *scratch_ptr(int dev) {
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        SDF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) throw Error{SDF_EDEVICE, "hipGetSymbolAddress returned no scratch address"};
+        g_scratch_ptr[dev] = static_cast<unsigned char *>(p);
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
 
 struct sdf_result_s {
     int device = 0;
@@ -127,6 +153,31 @@ __global__ void __launch_bounds__(64 * SPAN_FEW) k_span_setup_few(const IndexVie
         }
         tile0[nspans] = acc;
     }
+}
+
+// T[s] = min(ceil(tau s), 65535) for s in [0, smax], in double as on the
+// host (one multiplication, then ceil: the same IEEE result).
+__global__ void k_threshold_table(uint16_t *T, uint32_t smax, double tau) {
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s > smax) return;
+    const double v = ceil(tau * (double)s);
+    T[s] = (uint16_t)(v < 65535.0 ? v : 65535.0);
+}
+
+// Span descriptors from the caller's spans (sequence offsets from the index).
+__global__ void k_span_desc(const sdf_span *qs, uint32_t nq, const uint64_t *off, SpanDesc *sd) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nq) return;
+    const sdf_span q = qs[t];
+    SpanDesc d;
+    d.gb = off[q.seq] + q.begin;
+    d.ge = off[q.seq] + q.end;
+    d.qid = t;
+    d.qseq = q.seq;
+    d.m_lo = d.m_hi = 0;
+    d.tile0 = 0;
+    d._pad = 0;
+    sd[t] = d;
 }
 
 __global__ void k_cand_regions(const sdf_candidate *c, uint64_t n, sdf_region *r) {
@@ -269,28 +320,42 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
     tm.mark();
     // thresholds T(s) = ceil(tau * s) for every sketch size a tile can see
     const uint32_t smax = std::max<uint32_t>(P.n - ix->k + 2, 2048);
-    // the table and the span descriptors go to the device in one upload
     const size_t t_bytes = ((size_t)(smax + 1) * 2 + 255) & ~size_t(255);
     const size_t up_bytes = t_bytes + (size_t)nq * sizeof(SpanDesc);
-    Upload up(up_bytes);
-    uint16_t *T = reinterpret_cast<uint16_t *>(up.host());
-    for (uint32_t s = 0; s <= smax; s++) {
-        double v = std::ceil(P.tau * (double)s);
-        T[s] = (uint16_t)std::min(v, 65535.0);
-    }
-    DevBuf<unsigned char> dup(up_bytes);
+    uint64_t qbases = 0;
+    for (uint32_t t = 0; t < nq; t++) qbases += qs[t].end - qs[t].begin;
+    DevBuf<unsigned char> dup(up_bytes + (in_arena() ? (size_t)nq * sizeof(sdf_span) : 0));
     const uint16_t *dT = reinterpret_cast<const uint16_t *>(dup.p);
     SpanDesc *dsd = reinterpret_cast<SpanDesc *>(dup.p + t_bytes);
-    SpanDesc *sd = reinterpret_cast<SpanDesc *>(up.host() + t_bytes);
-    uint64_t qbases = 0;
-    for (uint32_t t = 0; t < nq; t++) {
-        sd[t].gb = ix->h_off[qs[t].seq] + qs[t].begin;
-        sd[t].ge = ix->h_off[qs[t].seq] + qs[t].end;
-        sd[t].qid = t;
-        sd[t].qseq = qs[t].seq;
-        qbases += qs[t].end - qs[t].begin;
+    if (in_arena()) {
+        // nothing may be allocated, pinned staging included: the table is
+        // computed on the device and the spans are copied as they are
+        k_threshold_table<<<(smax + 256) / 256, 256, 0, st>>>(reinterpret_cast<uint16_t *>(dup.p),
+                                                               smax, P.tau);
+        SDF_HIP(hipGetLastError());
+        if (nq) {
+            sdf_span *raw = reinterpret_cast<sdf_span *>(dup.p + up_bytes);
+            SDF_HIP(hipMemcpyAsync(raw, qs, (size_t)nq * sizeof(sdf_span), hipMemcpyHostToDevice, st));
+            k_span_desc<<<(nq + 255) / 256, 256, 0, st>>>(raw, nq, ix->off.p, dsd);
+            SDF_HIP(hipGetLastError());
+        }
+    } else {
+        // the table and the span descriptors go to the device in one upload
+        Upload up(up_bytes);
+        uint16_t *T = reinterpret_cast<uint16_t *>(up.host());
+        for (uint32_t s = 0; s <= smax; s++) {
+            double v = std::ceil(P.tau * (double)s);
+            T[s] = (uint16_t)std::min(v, 65535.0);
+        }
+        SpanDesc *sd = reinterpret_cast<SpanDesc *>(up.host() + t_bytes);
+        for (uint32_t t = 0; t < nq; t++) {
+            sd[t].gb = ix->h_off[qs[t].seq] + qs[t].begin;
+            sd[t].ge = ix->h_off[qs[t].seq] + qs[t].end;
+            sd[t].qid = t;
+            sd[t].qseq = qs[t].seq;
+        }
+        up.send(dup.p, st);
     }
-    up.send(dup.p, st);
     // tile layout and window starts per tile: the environment overrides
     // (SDF_TILE_THREADS, SDF_TILE_CORE), else the measured choice of
     // sdf_autotune, else the hit-density rules
@@ -328,11 +393,11 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
     unsigned long long *const phase = zblock.p + CNT_N;
     uint32_t *const work = reinterpret_cast<uint32_t *>(zblock.p + CNT_N + PH_N);
     const bool phase_prof = env_u32("SDF_PHASE_PROF", 0) != 0;
-    std::vector<unsigned long long> hc(CNT_N);
+    unsigned long long hc[CNT_N] = {};
     uint32_t herr = 0;
     for (int attempt = 0; attempt < 3; attempt++) {
         res->seeds.alloc(cap * 6);
-        SDF_HIP(hipMemsetAsync(zblock.p, 0, zblock.n * 8, st));
+        fill_u32(reinterpret_cast<uint32_t *>(zblock.p), 0u, zblock.n * 2, st);
         if (nq) {
             SearchArgs a;
             a.ix = ix->view();
@@ -372,7 +437,7 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
         }
         {
             Readback rb(st);
-            rb.add(hc.data(), counters, CNT_N * 8);
+            rb.add(hc, counters, CNT_N * 8);
             rb.add(&herr, work + 1, 4);
             if (nq) rb.add(&total_tiles, tile0.p + nq, 4);
             rb.wait();
@@ -830,6 +895,47 @@ sdf_status sdf_result_stats(sdf_result r, uint64_t *v, uint32_t n_v) {
     return guarded([&] {
         if (!r || (n_v && !v)) throw Error{SDF_EINVAL, "NULL argument"};
         for (uint32_t t = 0; t < n_v && t < 14; t++) v[t] = r->stats[t];
+    });
+}
+
+sdf_status sdf_search_batch_noalloc(sdf_index ix, const sdf_span *qs, uint32_t n,
+                                    const sdf_search_params *p, void *hip_stream,
+                                    sdf_candidate *out, uint64_t cap, uint64_t *n_out) {
+    if (n_out) *n_out = 0;
+    return guarded([&] {
+        if (!ix || !p || !n_out) throw Error{SDF_EINVAL, "NULL argument"};
+        if (n && !qs) throw Error{SDF_EINVAL, "NULL spans"};
+        if (cap && !out) throw Error{SDF_EINVAL, "NULL destination"};
+        if (p->flags) throw Error{SDF_EINVAL, "the no-allocation search takes no flags"};
+        if (n > SDF_NOALLOC_MAX_SPANS)
+            throw Error{SDF_EINVAL, "more spans than the no-allocation search accepts (65,536)"};
+        uint64_t qb = 0;
+        for (uint32_t t = 0; t < n; t++)
+            if (qs[t].end > qs[t].begin) qb += qs[t].end - qs[t].begin;
+        if (qb > SDF_NOALLOC_MAX_QUERY_BASES)
+            throw Error{SDF_EINVAL, "the spans hold more bases than the no-allocation search "
+                                    "accepts (8,000,000)"};
+        if (ix->device < 0 || ix->device >= MAX_DEVICES)
+            throw Error{SDF_EINVAL, "device ordinal beyond the scratch table"};
+        SDF_HIP(hipSetDevice(ix->device));
+        // one search at a time per device: they share the device's scratch
+        std::lock_guard<std::mutex> lk(g_scratch_mu[ix->device]);
+        Arena ar;
+        ar.base = scratch_ptr(ix->device);
+        ar.cap = SDF_NOALLOC_SCRATCH_BYTES;
+        const hipStream_t st = (hipStream_t)hip_stream;
+        StreamScope scope(st);
+        ArenaScope as(&ar);
+        sdf_result_s r;  // on the stack; its device buffers are carved from the scratch
+        r.device = ix->device;
+        r.st = st;
+        run_search(ix, qs, n, p, st, &r);
+        const uint64_t m = std::min<uint64_t>(cap, r.chain.ncands);
+        if (m)
+            SDF_HIP(hipMemcpyAsync(out, r.chain.cands.p, m * sizeof(sdf_candidate),
+                                   hipMemcpyDeviceToHost, st));
+        SDF_HIP(hipStreamSynchronize(st));
+        *n_out = r.chain.ncands;
     });
 }
 

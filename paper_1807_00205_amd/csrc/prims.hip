@@ -58,7 +58,26 @@ void pool_trim() {
     (void)hipSetDevice(cur);
 }
 
+// A scratch area that serves every device allocation of the calling thread
+// while an ArenaScope is open: blocks are carved off in order (256-byte
+// aligned) and never reused within the scope; running out is SDF_ENOMEM.
+static thread_local Arena *t_arena = nullptr;
+ArenaScope::ArenaScope(Arena *a) : prev(t_arena) { t_arena = a; }
+ArenaScope::~ArenaScope() { t_arena = prev; }
+bool in_arena() { return t_arena != nullptr; }
+
 void *pool_alloc(size_t bytes) {
+    if (t_arena) {
+        const size_t b = ((bytes ? bytes : 1) + 255) & ~size_t(255);
+        if (b > t_arena->cap - t_arena->used)
+            throw Error{SDF_ENOMEM, "the search needs more device scratch than the " +
+                                        std::to_string(t_arena->cap) +
+                                        " bytes of the fixed scratch area"};
+        void *p = t_arena->base + t_arena->used;
+        t_arena->used += b;
+        if (t_arena->used > t_arena->peak) t_arena->peak = t_arena->used;
+        return p;
+    }
     int dev = 0;
     SDF_HIP(hipGetDevice(&dev));
     size_t c = size_class(bytes);
@@ -90,6 +109,9 @@ void *pool_alloc(size_t bytes) {
 
 void pool_free(void *p) {
     if (!p) return;
+    if (t_arena && (unsigned char *)p >= t_arena->base &&
+        (unsigned char *)p < t_arena->base + t_arena->cap)
+        return;  // arena blocks are released with the scope
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_live.find(p);
     if (it == g_live.end()) return;
@@ -158,20 +180,29 @@ void stage_release(Stage *s) {
 }
 }  // namespace
 
-Readback::Readback(hipStream_t st) : st_(st), stage_(stage_acquire(READBACK_MAX)) {}
+// Inside an ArenaScope nothing may be allocated, pinned host memory
+// included: reads are staged through this thread's own static block instead
+// (ordinary host memory; the copies then complete before wait() returns).
+static thread_local unsigned char t_plain_stage[READBACK_MAX];
+
+Readback::Readback(hipStream_t st)
+    : st_(st), stage_(t_arena ? nullptr : stage_acquire(READBACK_MAX)) {}
 
 Readback::~Readback() {
     // copies queued but not waited for (an exception in between) may still
     // land in the block: it is not returned to the pool then
-    if (!pending_) stage_release(stage_);
+    if (stage_ && !pending_) stage_release(stage_);
+    if (!stage_ && pending_) (void)hipStreamSynchronize(st_);
 }
+
+unsigned char *Readback::block() { return stage_ ? stage_->p : t_plain_stage; }
 
 void Readback::add(void *host_dst, const void *dev_src, size_t bytes) {
     const size_t off = (used_ + 7) & ~size_t(7);
     if (off + bytes > READBACK_MAX || n_ == (int)(sizeof(items_) / sizeof(items_[0])))
         throw Error{SDF_EINTERNAL, "readback staging block exceeded"};
     pending_ = true;
-    SDF_HIP(hipMemcpyAsync(stage_->p + off, dev_src, bytes, hipMemcpyDeviceToHost, st_));
+    SDF_HIP(hipMemcpyAsync(block() + off, dev_src, bytes, hipMemcpyDeviceToHost, st_));
     items_[n_++] = Item{host_dst, off, bytes};
     used_ = off + bytes;
 }
@@ -180,7 +211,7 @@ void Readback::wait() {
     SDF_HIP(hipStreamSynchronize(st_));
     pending_ = false;
     for (int i = 0; i < n_; i++)
-        std::memcpy(items_[i].dst, stage_->p + items_[i].off, items_[i].bytes);
+        std::memcpy(items_[i].dst, block() + items_[i].off, items_[i].bytes);
     n_ = 0;
     used_ = 0;
 }

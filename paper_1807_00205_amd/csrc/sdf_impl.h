@@ -38,6 +38,18 @@ struct Error {
 // alone keeps a reused block from being overwritten while still in use and
 // no host synchronization is needed before a free.
 void *pool_alloc(size_t bytes);
+// Fixed device area that serves pool_alloc while an ArenaScope is open on
+// the calling thread (see prims.hip); `peak` records the most ever in use.
+struct Arena {
+    unsigned char *base = nullptr;
+    size_t cap = 0, used = 0, peak = 0;
+};
+struct ArenaScope {
+    Arena *prev;
+    explicit ArenaScope(Arena *a);
+    ~ArenaScope();
+};
+bool in_arena();
 void pool_free(void *p);
 void pool_trim();
 hipStream_t current_stream();
@@ -69,6 +81,7 @@ class Readback {
     void wait();
 
   private:
+    unsigned char *block();
     hipStream_t st_;
     Stage *stage_;
     bool pending_ = false;  // copies queued and not yet waited for

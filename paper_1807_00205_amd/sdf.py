@@ -39,7 +39,11 @@ EXPORTS = ["sdf_last_error", "sdf_index_build", "sdf_index_info", "sdf_index_hit
            "sdf_index_entries", "sdf_index_packed", "sdf_index_free", "sdf_search",
            "sdf_search_batch", "sdf_result_count", "sdf_result_copy", "sdf_result_seed_count",
            "sdf_result_seeds", "sdf_result_timing", "sdf_result_stats", "sdf_result_free",
-           "sdf_extend", "sdf_result_regions", "sdf_qgram_filter", "sdf_autotune"]
+           "sdf_extend", "sdf_result_regions", "sdf_qgram_filter", "sdf_autotune",
+           "sdf_search_batch_noalloc"]
+NOALLOC_SCRATCH_BYTES = 128 << 20
+NOALLOC_MAX_SPANS = 65536
+NOALLOC_MAX_QUERY_BASES = 8_000_000
 
 
 def _flags(timing: bool, estimate: bool, extend: bool = False) -> int:
@@ -182,6 +186,9 @@ def lib() -> ctypes.CDLL:
         L.sdf_qgram_filter.argtypes = [vp, vp, u64, P(_QgramParams), vp, vp, vp]
         L.sdf_result_regions.restype = st
         L.sdf_result_regions.argtypes = [vp, vp, u64, P(u64)]
+        L.sdf_search_batch_noalloc.restype = st
+        L.sdf_search_batch_noalloc.argtypes = [vp, vp, u32, P(_SearchParams), vp, vp, u64,
+                                               P(u64)]
         assert REGION_DTYPE.itemsize == 56
         _lib = L
     return _lib
@@ -407,3 +414,23 @@ class Index:
         _check(lib().sdf_search_batch(self._h, arr.ctypes.data_as(ctypes.c_void_p), nspans,
                                       ctypes.byref(p), _stream_ptr(stream), ctypes.byref(h)))
         return Result(h.value)
+
+    def search_batch_noalloc(self, spans: Iterable[Tuple[int, int, int]],
+                             max_error: float = 0.25, min_len: int = 1000, cap: int = None,
+                             stream=None) -> np.ndarray:
+        """The batched search through ``sdf_search_batch_noalloc`` (no memory
+        allocated by the library; device buffers come from its fixed scratch
+        area).  Returns the candidates in the order of ``Result.candidates``;
+        with ``cap``, at most that many are copied (the array is sized by the
+        count the library reports)."""
+        arr, nspans = _span_array(spans)
+        p = _SearchParams(max_error, min_len, 0)
+        n = ctypes.c_uint64()
+        if cap is None:
+            cap = 65536
+        out = np.empty(max(1, cap), CANDIDATE_DTYPE)
+        _check(lib().sdf_search_batch_noalloc(self._h, arr.ctypes.data_as(ctypes.c_void_p),
+                                              nspans, ctypes.byref(p), _stream_ptr(stream),
+                                              out.ctypes.data_as(ctypes.c_void_p), cap,
+                                              ctypes.byref(n)))
+        return out[:min(cap, n.value)].copy(), n.value

@@ -289,6 +289,44 @@ sdf_status sdf_autotune(sdf_index ix, const sdf_span *spans, uint32_t n,
                         const sdf_search_params *p, void *hip_stream, uint32_t *core_out,
                         uint32_t *threads_out, float *ms_out, uint32_t n_ms);
 
+/*
+ * The batched search of a fixed set of spans captured once as a HIP graph
+ * and replayed (the batching of a query set that is searched repeatedly,
+ * Section 3 applied to many spans at once): no host synchronisation and no
+ * allocation happen between the launch and the end of the replay.
+ *
+ * sdf_plan_create runs the search once as sdf_search_batch does (its seed
+ * and candidate counts size the graph's buffers: a quarter more, unless
+ * sdf_plan_params sets them), runs the launch sequence once more with those
+ * buffers, then captures it on hip_stream (NULL: a stream of the plan's
+ * own, since the legacy default stream cannot be captured) and instantiates
+ * the graph.  The spans are copied; flags other than SDF_TIMING (ignored)
+ * are rejected.  The index must outlive the plan.
+ *
+ * sdf_plan_run replays the graph on hip_stream (NULL: the plan's stream),
+ * waits for it, and returns a result like sdf_search_batch's (candidates,
+ * seeds, stats; no timing).  When the replay reports an error or counts past
+ * the graph's buffers, the search runs again without the graph and its
+ * result is returned (sdf_plan_info counts these fallbacks).  Replays of one
+ * plan are serialised; different plans may run concurrently.
+ *
+ * Errors: as for sdf_search_batch; SDF_EINVAL for estimate or extension
+ * flags; SDF_EDEVICE when capture or instantiation fails.
+ */
+typedef struct sdf_plan_s *sdf_plan;
+typedef struct {
+    uint64_t seed_cap;  /* seeds the graph's buffers hold (0: calibrated) */
+    uint64_t cand_cap;  /* candidates they hold (0: calibrated) */
+} sdf_plan_params;
+sdf_status sdf_plan_create(sdf_index ix, const sdf_span *qs, uint32_t n,
+                           const sdf_search_params *p, const sdf_plan_params *pp,
+                           void *hip_stream, sdf_plan *out);
+sdf_status sdf_plan_run(sdf_plan plan, void *hip_stream, sdf_result *out);
+/* Capacities of a plan and how often it was replayed and fell back. */
+sdf_status sdf_plan_info(sdf_plan plan, uint64_t *seed_cap, uint64_t *cand_cap,
+                         uint64_t *replays, uint64_t *fallbacks);
+void sdf_plan_free(sdf_plan plan);
+
 /* Number of candidates (waits for the search to finish). */
 sdf_status sdf_result_count(sdf_result r, uint64_t *n);
 

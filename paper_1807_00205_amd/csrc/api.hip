@@ -58,6 +58,29 @@ struct sdf_result_s {
     DevBuf<sdf_region> regions;  // one per candidate with SDF_EXTEND
     ExtStats ext;
     uint64_t stats[14] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    uint32_t core = 0, threads = 0;  // tile schedule the search used
+};
+
+// A batched search captured in a HIP graph (sdf_plan_create): the buffers
+// of its launch sequence, the pinned blocks it copies through, the graph.
+struct sdf_plan_s {
+    sdf_index_s *ix = nullptr;
+    int device = 0;
+    hipStream_t st = nullptr;  // stream of the rehearsal and the capture
+    bool own_stream = false;
+    std::vector<sdf_span> spans;
+    sdf_search_params params{};
+    uint64_t ns_cap = 0, nc_cap = 0;  // seeds and candidates the graph holds
+    uint32_t core = 0, threads = 0;   // tile schedule of the calibration run
+    sdf::Arena arena;                 // every device buffer of the sequence
+    unsigned char *h_up = nullptr;    // pinned: threshold table and span descriptors
+    unsigned long long *h_status = nullptr;  // pinned: counters, error, tiles, candidates, flag
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const uint32_t *d_seeds = nullptr;       // inside the arena
+    const sdf_candidate *d_cands = nullptr;  // inside the arena
+    std::mutex mu;                           // one replay at a time
+    uint64_t replays = 0, fallbacks = 0;
 };
 
 namespace {
@@ -305,56 +328,83 @@ struct Timer {
     }
 };
 
-void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_search_params *p,
-                hipStream_t st, sdf_result_s *res, uint32_t core_override = 0,
-                uint32_t threads_override = 0) {
-    const Params P = derive(p, ix->k, ix->w);
-    res->n = P.n;
+// Checks the spans against the index (SDF_ERANGE).
+void check_spans(const sdf_index_s *ix, const sdf_span *qs, uint32_t nq) {
     for (uint32_t t = 0; t < nq; t++) {
         const sdf_span &s = qs[t];
         if (s.seq >= ix->nseq) throw Error{SDF_ERANGE, "span sequence index out of range"};
         const uint64_t len = ix->h_off[s.seq + 1] - ix->h_off[s.seq];
         if (s.begin > s.end || s.end > len) throw Error{SDF_ERANGE, "span outside its sequence"};
     }
-    Timer tm((p->flags & SDF_TIMING) != 0, st);
-    tm.mark();
-    // thresholds T(s) = ceil(tau * s) for every sketch size a tile can see
-    const uint32_t smax = std::max<uint32_t>(P.n - ix->k + 2, 2048);
-    const size_t t_bytes = ((size_t)(smax + 1) * 2 + 255) & ~size_t(255);
-    const size_t up_bytes = t_bytes + (size_t)nq * sizeof(SpanDesc);
+}
+
+// The threshold table T(s) = ceil(tau s) and the span descriptors on the
+// device, then each span's window starts and tiles (span set-up).
+struct Prepared {
     uint64_t qbases = 0;
-    for (uint32_t t = 0; t < nq; t++) qbases += qs[t].end - qs[t].begin;
-    DevBuf<unsigned char> dup(up_bytes + (in_arena() ? (size_t)nq * sizeof(sdf_span) : 0));
-    const uint16_t *dT = reinterpret_cast<const uint16_t *>(dup.p);
-    SpanDesc *dsd = reinterpret_cast<SpanDesc *>(dup.p + t_bytes);
-    if (in_arena()) {
+    uint32_t threads = 1024, core = 512, hpart = 16384, sb = 0, grid = 1;
+    DevBuf<unsigned char> dup;
+    const uint16_t *dT = nullptr;
+    SpanDesc *dsd = nullptr;
+    DevBuf<uint32_t> ntiles, tile0;
+};
+
+// The host part of the upload: T and the span descriptors into `host`
+// (t_bytes of table, then nq descriptors).
+void fill_upload(const sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const Params &P,
+                 uint32_t smax, size_t t_bytes, unsigned char *host) {
+    uint16_t *T = reinterpret_cast<uint16_t *>(host);
+    for (uint32_t s = 0; s <= smax; s++) {
+        double v = std::ceil(P.tau * (double)s);
+        T[s] = (uint16_t)std::min(v, 65535.0);
+    }
+    SpanDesc *sd = reinterpret_cast<SpanDesc *>(host + t_bytes);
+    for (uint32_t t = 0; t < nq; t++) {
+        sd[t] = SpanDesc{};
+        sd[t].gb = ix->h_off[qs[t].seq] + qs[t].begin;
+        sd[t].ge = ix->h_off[qs[t].seq] + qs[t].end;
+        sd[t].qid = t;
+        sd[t].qseq = qs[t].seq;
+    }
+}
+
+uint32_t table_smax(const Params &P, uint32_t k) { return std::max<uint32_t>(P.n - k + 2, 2048); }
+size_t table_bytes(uint32_t smax) { return ((size_t)(smax + 1) * 2 + 255) & ~size_t(255); }
+
+// Enqueues the upload (from `pinned_up` when given: a host block the caller
+// filled with fill_upload and keeps alive; else through a pooled staging
+// block, or built on the device inside a carving arena) and the span set-up,
+// and picks the tile schedule.
+void prepare(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const Params &P, hipStream_t st,
+             Prepared &pr, uint32_t core_override, uint32_t threads_override,
+             const unsigned char *pinned_up = nullptr) {
+    const uint32_t smax = table_smax(P, ix->k);
+    const size_t t_bytes = table_bytes(smax);
+    const size_t up_bytes = t_bytes + (size_t)nq * sizeof(SpanDesc);
+    pr.qbases = 0;
+    for (uint32_t t = 0; t < nq; t++) pr.qbases += qs[t].end - qs[t].begin;
+    pr.dup.alloc(up_bytes + (in_arena() ? (size_t)nq * sizeof(sdf_span) : 0));
+    pr.dT = reinterpret_cast<const uint16_t *>(pr.dup.p);
+    pr.dsd = reinterpret_cast<SpanDesc *>(pr.dup.p + t_bytes);
+    if (pinned_up) {
+        SDF_HIP(hipMemcpyAsync(pr.dup.p, pinned_up, up_bytes, hipMemcpyHostToDevice, st));
+    } else if (in_arena()) {
         // nothing may be allocated, pinned staging included: the table is
         // computed on the device and the spans are copied as they are
-        k_threshold_table<<<(smax + 256) / 256, 256, 0, st>>>(reinterpret_cast<uint16_t *>(dup.p),
+        k_threshold_table<<<(smax + 256) / 256, 256, 0, st>>>(reinterpret_cast<uint16_t *>(pr.dup.p),
                                                                smax, P.tau);
         SDF_HIP(hipGetLastError());
         if (nq) {
-            sdf_span *raw = reinterpret_cast<sdf_span *>(dup.p + up_bytes);
+            sdf_span *raw = reinterpret_cast<sdf_span *>(pr.dup.p + up_bytes);
             SDF_HIP(hipMemcpyAsync(raw, qs, (size_t)nq * sizeof(sdf_span), hipMemcpyHostToDevice, st));
-            k_span_desc<<<(nq + 255) / 256, 256, 0, st>>>(raw, nq, ix->off.p, dsd);
+            k_span_desc<<<(nq + 255) / 256, 256, 0, st>>>(raw, nq, ix->off.p, pr.dsd);
             SDF_HIP(hipGetLastError());
         }
     } else {
         // the table and the span descriptors go to the device in one upload
         Upload up(up_bytes);
-        uint16_t *T = reinterpret_cast<uint16_t *>(up.host());
-        for (uint32_t s = 0; s <= smax; s++) {
-            double v = std::ceil(P.tau * (double)s);
-            T[s] = (uint16_t)std::min(v, 65535.0);
-        }
-        SpanDesc *sd = reinterpret_cast<SpanDesc *>(up.host() + t_bytes);
-        for (uint32_t t = 0; t < nq; t++) {
-            sd[t].gb = ix->h_off[qs[t].seq] + qs[t].begin;
-            sd[t].ge = ix->h_off[qs[t].seq] + qs[t].end;
-            sd[t].qid = t;
-            sd[t].qseq = qs[t].seq;
-        }
-        up.send(dup.p, st);
+        fill_upload(ix, qs, nq, P, smax, t_bytes, up.host());
+        up.send(pr.dup.p, st);
     }
     // tile layout and window starts per tile: the environment overrides
     // (SDF_TILE_THREADS, SDF_TILE_CORE), else the measured choice of
@@ -372,19 +422,81 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
                                         : (ix->tuned_core ? ix->tuned_core
                                                           : auto_tile_core(ix->hbar, hpart, cmax));
     const uint32_t core = std::min(std::max<uint32_t>(env_u32("SDF_TILE_CORE", pick), 1), cmax);
-    DevBuf<uint32_t> ntiles(nq + 1), tile0(nq + 1);
-    uint32_t total_tiles = 0;  // read back with the counters; the kernel reads it on device
+    pr.threads = threads;
+    pr.core = core;
+    pr.hpart = hpart;
+    pr.ntiles.alloc(nq + 1);
+    pr.tile0.alloc(nq + 1);
     // the SDF_SPAN_FEW_MAX environment variable lowers the one-launch limit (0: off)
     const uint32_t few_max = std::min<uint32_t>(env_u32("SDF_SPAN_FEW_MAX", SPAN_FEW), SPAN_FEW);
     if (nq > 0 && nq <= few_max) {
-        k_span_setup_few<<<1, 64 * nq, 0, st>>>(ix->view(), dsd, nq, P.n, core, tile0.p);
+        k_span_setup_few<<<1, 64 * nq, 0, st>>>(ix->view(), pr.dsd, nq, P.n, core, pr.tile0.p);
         SDF_HIP(hipGetLastError());
     } else if (nq) {
-        launch_span_setup(ix->view(), dsd, nq, P.n, core, ntiles.p, tile0.p, st);
+        launch_span_setup(ix->view(), pr.dsd, nq, P.n, core, pr.ntiles.p, pr.tile0.p, st);
     }
+    pr.sb = 0;
+    while ((1u << pr.sb) < P.n) pr.sb++;
+    // persistent grid, as many workgroups as fit the CUs: workgroups past the
+    // last tile exit at once.  A span has at most (length - n + 1) window
+    // starts, so short spans launch no more workgroups than they can have tiles.
+    uint64_t tile_bound = 0;
+    for (uint32_t t = 0; t < nq; t++) {
+        const uint64_t len = qs[t].end - qs[t].begin;
+        if (len >= P.n) tile_bound += (len - P.n + 1 + core - 1) / core;
+    }
+    pr.grid = (uint32_t)std::max<uint64_t>(
+        1, std::min<uint64_t>((uint64_t)cu_count(ix->device) * (threads == 512 ? 2u : 1u) *
+                                  env_u32("SDF_WG_PER_CU", 1),
+                              std::max<uint64_t>(tile_bound, 1)));
+}
+
+// Arguments of the tile kernel for a prepared search.
+SearchArgs tile_args(sdf_index_s *ix, const Params &P, const Prepared &pr, uint32_t nq,
+                     uint32_t *seeds, uint64_t seed_cap, unsigned long long *counters,
+                     uint32_t *work, unsigned long long *phase, uint32_t runs_out) {
+    SearchArgs a;
+    a.ix = ix->view();
+    a.n = P.n;
+    a.max_overlap = P.max_overlap;
+    a.T = pr.dT;
+    a.spans = pr.dsd;
+    a.nspans = nq;
+    a.total_tiles = pr.tile0.p + nq;
+    a.work = work;
+    a.core = pr.core;
+    a.hpart = pr.hpart;
+    a.bin_shift = pr.sb;
+    a.seeds = seeds;
+    a.seed_cap = seed_cap;
+    a.counters = counters;
+    a.err = work + 1;
+    a.phase = phase;
+    a.runs_out = runs_out;
+    return a;
+}
+
+void launch_tile(const Prepared &pr, const SearchArgs &a, hipStream_t st) {
+    if (pr.threads == 512) tile512::launch_tile_search(a, pr.grid, st);
+    else tile1024::launch_tile_search(a, pr.grid, st);
+}
+
+void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_search_params *p,
+                hipStream_t st, sdf_result_s *res, uint32_t core_override = 0,
+                uint32_t threads_override = 0) {
+    const Params P = derive(p, ix->k, ix->w);
+    res->n = P.n;
+    check_spans(ix, qs, nq);
+    Timer tm((p->flags & SDF_TIMING) != 0, st);
     tm.mark();
-    uint32_t sb = 0;
-    while ((1u << sb) < P.n) sb++;
+    Prepared pr;
+    prepare(ix, qs, nq, P, st, pr, core_override, threads_override);
+    res->core = pr.core;
+    res->threads = pr.threads;
+    const uint64_t qbases = pr.qbases;
+    DevBuf<uint32_t> &tile0 = pr.tile0;
+    uint32_t total_tiles = 0;  // read back with the counters; the kernel reads it on device
+    tm.mark();
     uint64_t cap = qbases / 8 + 65536;
     // work counters, phase timers and (work item, error word) in one block,
     // cleared by one fill before each attempt
@@ -399,40 +511,11 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
         res->seeds.alloc(cap * 6);
         fill_u32(reinterpret_cast<uint32_t *>(zblock.p), 0u, zblock.n * 2, st);
         if (nq) {
-            SearchArgs a;
-            a.ix = ix->view();
-            a.n = P.n;
-            a.max_overlap = P.max_overlap;
-            a.T = dT;
-            a.spans = dsd;
-            a.nspans = nq;
-            a.total_tiles = tile0.p + nq;
-            a.work = work;
-            a.core = core;
-            a.hpart = hpart;
-            a.bin_shift = sb;
-            a.seeds = res->seeds.p;
-            a.seed_cap = cap;
-            a.counters = counters;
-            a.err = work + 1;
-            a.phase = phase_prof ? phase : nullptr;
-            a.runs_out = (p->flags & SDF_SEED_ESTIMATE) ? 1u : 0u;
-            // persistent grid, as many workgroups as fit the CUs: workgroups
-            // past the last tile exit at once.  A span has at most
-            // (length - n + 1) window starts, so short spans launch no more
-            // workgroups than they can have tiles.
-            uint64_t tile_bound = 0;
-            for (uint32_t t = 0; t < nq; t++) {
-                const uint64_t len = qs[t].end - qs[t].begin;
-                if (len >= P.n) tile_bound += (len - P.n + 1 + core - 1) / core;
-            }
-            const uint32_t grid = (uint32_t)std::min<uint64_t>(
-                (uint64_t)cu_count(ix->device) * (threads == 512 ? 2u : 1u) *
-                    env_u32("SDF_WG_PER_CU", 1),
-                std::max<uint64_t>(tile_bound, 1));
+            const SearchArgs a = tile_args(ix, P, pr, nq, res->seeds.p, cap, counters, work,
+                                           phase_prof ? phase : nullptr,
+                                           (p->flags & SDF_SEED_ESTIMATE) ? 1u : 0u);
             tm.mark_kernel_begin();
-            if (threads == 512) tile512::launch_tile_search(a, std::max<uint32_t>(grid, 1), st);
-            else tile1024::launch_tile_search(a, std::max<uint32_t>(grid, 1), st);
+            launch_tile(pr, a, st);
             tm.mark_kernel_end();
         }
         {
@@ -488,7 +571,7 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
         DevBuf<uint32_t> eerr(1);
         SDF_HIP(hipMemsetAsync(ecount.p, 0, 8, st));
         SDF_HIP(hipMemsetAsync(eerr.p, 0, 4, st));
-        launch_estimate_runs(ix->view(), res->seeds.p, nruns, P.n, dT, est.p, nruns, ecount.p,
+        launch_estimate_runs(ix->view(), res->seeds.p, nruns, P.n, pr.dT, est.p, nruns, ecount.p,
                              eerr.p, st);
         unsigned long long ne = 0;
         uint32_t ee = 0;
@@ -505,8 +588,12 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
         res->seeds = std::move(est);
         res->nseeds = ne;
         res->stats[5] = ne;
+        chain_seeds(ix->view(), res->seeds.p, DevCount{ecount.p, res->nseeds}, P.n,
+                    P.max_overlap, nq, res->chain, st);
+    } else {
+        chain_seeds(ix->view(), res->seeds.p, DevCount{counters + CNT_SEEDS, res->nseeds}, P.n,
+                    P.max_overlap, nq, res->chain, st);
     }
-    chain_seeds(ix->view(), res->seeds.p, res->nseeds, P.n, P.max_overlap, nq, res->chain, st);
     tm.mark();
     tm.mark();
     if (p->flags & SDF_EXTEND) {
@@ -536,6 +623,68 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
     res->ms[3] = tm.between(3, 4);
     res->ms[4] = tm.between(0, 5);
     res->ms[5] = tm.between(4, 5);
+}
+
+constexpr int PLAN_STATUS = CNT_N + 4;  // counters, error, tiles, candidates, long-run flag
+
+__global__ void k_pack_status(const unsigned long long *counters, const uint32_t *err,
+                              const uint32_t *tiles, const unsigned long long *ncand,
+                              const uint32_t *flag, unsigned long long *out) {
+    if (threadIdx.x != 0) return;
+    for (int t = 0; t < CNT_N; t++) out[t] = counters[t];
+    out[CNT_N] = *err;
+    out[CNT_N + 1] = tiles ? *tiles : 0ull;
+    out[CNT_N + 2] = *ncand;
+    out[CNT_N + 3] = *flag;
+}
+
+// The launch sequence of a plan: upload from the plan's pinned block, span
+// set-up, tile kernel into ns_cap seeds, chaining and the candidate sort
+// with the candidate count left on the device (nc_cap sizes the buffers),
+// and the status copied to the pinned status block.  Nothing is read back
+// and nothing is waited for, so the sequence can be captured; its buffers
+// come from the arena that is open (recorded by the rehearsal, handed out
+// again during the capture).
+void enqueue_plan(sdf_plan_s *pl, hipStream_t st) {
+    sdf_index_s *ix = pl->ix;
+    const uint32_t nq = (uint32_t)pl->spans.size();
+    const Params P = derive(&pl->params, ix->k, ix->w);
+    Prepared pr;
+    prepare(ix, pl->spans.data(), nq, P, st, pr, pl->core, pl->threads, pl->h_up);
+    DevBuf<unsigned long long> zblock(CNT_N + PH_N + 1);
+    unsigned long long *const counters = zblock.p;
+    uint32_t *const work = reinterpret_cast<uint32_t *>(zblock.p + CNT_N + PH_N);
+    DevBuf<uint32_t> seeds(pl->ns_cap * 6);
+    fill_u32(reinterpret_cast<uint32_t *>(zblock.p), 0u, zblock.n * 2, st);
+    if (nq)
+        launch_tile(pr, tile_args(ix, P, pr, nq, seeds.p, pl->ns_cap, counters, work, nullptr, 0u),
+                    st);
+    ChainOut co;
+    chain_seeds(ix->view(), seeds.p, DevCount{counters + CNT_SEEDS, pl->ns_cap}, P.n,
+                P.max_overlap, nq, co, st, pl->nc_cap);
+    DevBuf<unsigned long long> status(PLAN_STATUS);
+    k_pack_status<<<1, 64, 0, st>>>(counters, work + 1, nq ? pr.tile0.p + nq : nullptr,
+                                    co.dcount.p, co.dflag.p, status.p);
+    SDF_HIP(hipGetLastError());
+    SDF_HIP(hipMemcpyAsync(pl->h_status, status.p, PLAN_STATUS * 8, hipMemcpyDeviceToHost, st));
+    pl->d_seeds = seeds.p;
+    pl->d_cands = co.cands.p;
+}
+
+void plan_destroy(sdf_plan_s *pl) {
+    if (!pl) return;
+    (void)hipSetDevice(pl->device);
+    if (pl->st) (void)hipStreamSynchronize(pl->st);
+    if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    {
+        StreamScope scope(pl->st);
+        release_blocks(pl->arena);
+    }
+    if (pl->h_up) (void)hipHostFree(pl->h_up);
+    if (pl->h_status) (void)hipHostFree(pl->h_status);
+    if (pl->own_stream && pl->st) (void)hipStreamDestroy(pl->st);
+    delete pl;
 }
 
 }  // namespace
@@ -897,6 +1046,162 @@ sdf_status sdf_result_stats(sdf_result r, uint64_t *v, uint32_t n_v) {
         for (uint32_t t = 0; t < n_v && t < 14; t++) v[t] = r->stats[t];
     });
 }
+
+sdf_status sdf_plan_create(sdf_index ix, const sdf_span *qs, uint32_t n,
+                           const sdf_search_params *p, const sdf_plan_params *pp,
+                           void *hip_stream, sdf_plan *out) {
+    if (out) *out = nullptr;
+    sdf_plan_s *pl = nullptr;
+    sdf_status rc = guarded([&] {
+        if (!ix || !p || !out) throw Error{SDF_EINVAL, "NULL argument"};
+        if (n && !qs) throw Error{SDF_EINVAL, "NULL spans"};
+        if (p->flags & (SDF_SEED_ESTIMATE | SDF_EXTEND))
+            throw Error{SDF_EINVAL, "a plan runs the shared-count search only"};
+        const Params P = derive(p, ix->k, ix->w);
+        (void)P;
+        check_spans(ix, qs, n);
+        SDF_HIP(hipSetDevice(ix->device));
+        pl = new sdf_plan_s();
+        pl->ix = ix;
+        pl->device = ix->device;
+        pl->spans.assign(qs, qs + n);
+        pl->params = *p;
+        pl->params.flags = 0;
+        if (hip_stream) {
+            pl->st = (hipStream_t)hip_stream;
+        } else {  // the legacy default stream cannot be captured
+            SDF_HIP(hipStreamCreate(&pl->st));
+            pl->own_stream = true;
+        }
+        const hipStream_t st = pl->st;
+        StreamScope scope(st);
+        // 1. calibration: the search run once as it is, for its counts and schedule
+        uint64_t ns = 0, nc = 0;
+        {
+            sdf_result_s r;
+            r.device = ix->device;
+            r.st = st;
+            run_search(ix, qs, n, &pl->params, st, &r);
+            ns = r.nseeds;
+            nc = r.chain.ncands;
+            pl->core = r.core;
+            pl->threads = r.threads;
+            SDF_HIP(hipStreamSynchronize(st));
+        }
+        pl->ns_cap = (pp && pp->seed_cap) ? pp->seed_cap : ns + ns / 4 + 4096;
+        pl->nc_cap = (pp && pp->cand_cap) ? pp->cand_cap : nc + nc / 4 + 256;
+        // 2. pinned blocks: the upload (filled once) and the status
+        const uint32_t smax = table_smax(P, ix->k);
+        const size_t t_bytes = table_bytes(smax);
+        const size_t up_bytes = t_bytes + (size_t)n * sizeof(SpanDesc);
+        void *h = nullptr;
+        if (hipHostMalloc(&h, std::max<size_t>(up_bytes, 256), hipHostMallocPortable) != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error{SDF_ENOMEM, "pinned host allocation for a plan failed"};
+        }
+        pl->h_up = static_cast<unsigned char *>(h);
+        fill_upload(ix, qs, n, P, smax, t_bytes, pl->h_up);
+        if (hipHostMalloc(&h, PLAN_STATUS * 8, hipHostMallocPortable) != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error{SDF_ENOMEM, "pinned host allocation for a plan failed"};
+        }
+        pl->h_status = static_cast<unsigned long long *>(h);
+        // 3. rehearsal: the sequence runs once, its buffers recorded
+        pl->arena.mode = Arena::RECORD;
+        {
+            ArenaScope as(&pl->arena);
+            enqueue_plan(pl, st);
+        }
+        SDF_HIP(hipStreamSynchronize(st));
+        // 4. capture with the same buffers, then instantiate
+        pl->arena.mode = Arena::REPLAY;
+        pl->arena.next = 0;
+        SDF_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        try {
+            ArenaScope as(&pl->arena);
+            enqueue_plan(pl, st);
+        } catch (...) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(st, &g);
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+            throw;
+        }
+        SDF_HIP(hipStreamEndCapture(st, &pl->graph));
+        SDF_HIP(hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0));
+        *out = pl;
+    });
+    if (rc != SDF_OK && pl) plan_destroy(pl);
+    return rc;
+}
+
+sdf_status sdf_plan_run(sdf_plan pl, void *hip_stream, sdf_result *out) {
+    if (out) *out = nullptr;
+    sdf_result_s *r = nullptr;
+    sdf_status rc = guarded([&] {
+        if (!pl || !out) throw Error{SDF_EINVAL, "NULL argument"};
+        SDF_HIP(hipSetDevice(pl->device));
+        std::lock_guard<std::mutex> lk(pl->mu);
+        const hipStream_t st = hip_stream ? (hipStream_t)hip_stream : pl->st;
+        StreamScope scope(st);
+        SDF_HIP(hipGraphLaunch(pl->exec, st));
+        SDF_HIP(hipStreamSynchronize(st));
+        pl->replays++;
+        const unsigned long long *h = pl->h_status;
+        const uint64_t ns = h[CNT_SEEDS], nc = h[CNT_N + 2];
+        r = new sdf_result_s();
+        r->device = pl->device;
+        r->st = st;
+        r->core = pl->core;
+        r->threads = pl->threads;
+        if (h[CNT_N] || ns > pl->ns_cap || nc > pl->nc_cap) {
+            // an error the search reports as it is, or counts past the
+            // graph's buffers: the search runs again without the graph
+            pl->fallbacks++;
+            run_search(pl->ix, pl->spans.data(), (uint32_t)pl->spans.size(), &pl->params, st, r);
+        } else {
+            r->n = derive(&pl->params, pl->ix->k, pl->ix->w).n;
+            r->nseeds = ns;
+            r->seeds.alloc(ns * 6);
+            if (ns)
+                SDF_HIP(hipMemcpyAsync(r->seeds.p, pl->d_seeds, ns * 24, hipMemcpyDeviceToDevice, st));
+            r->chain.cands.alloc(nc);
+            if (nc)
+                SDF_HIP(hipMemcpyAsync(r->chain.cands.p, pl->d_cands, nc * sizeof(sdf_candidate),
+                                       hipMemcpyDeviceToDevice, st));
+            r->chain.ncands = nc;
+            if (h[CNT_N + 3]) sort_candidates_records(r->chain.cands, nc, st);  // long ties
+            r->stats[0] = h[CNT_WINDOWS];
+            r->stats[1] = h[CNT_HITS];
+            r->stats[2] = h[CNT_KEPT];
+            r->stats[3] = h[CNT_N + 1];
+            r->stats[4] = h[CNT_PARTS];
+            r->stats[5] = ns;
+            r->stats[6] = h[CNT_EVALS];
+            r->stats[7] = h[CNT_SCAN];
+        }
+        *out = r;
+    });
+    if (rc != SDF_OK && r) {
+        (void)hipStreamSynchronize(r->st);
+        delete r;
+    }
+    return rc;
+}
+
+sdf_status sdf_plan_info(sdf_plan pl, uint64_t *seed_cap, uint64_t *cand_cap, uint64_t *replays,
+                         uint64_t *fallbacks) {
+    return guarded([&] {
+        if (!pl) throw Error{SDF_EINVAL, "NULL plan"};
+        std::lock_guard<std::mutex> lk(pl->mu);
+        if (seed_cap) *seed_cap = pl->ns_cap;
+        if (cand_cap) *cand_cap = pl->nc_cap;
+        if (replays) *replays = pl->replays;
+        if (fallbacks) *fallbacks = pl->fallbacks;
+    });
+}
+
+void sdf_plan_free(sdf_plan pl) { plan_destroy(pl); }
 
 sdf_status sdf_search_batch_noalloc(sdf_index ix, const sdf_span *qs, uint32_t n,
                                     const sdf_search_params *p, void *hip_stream,

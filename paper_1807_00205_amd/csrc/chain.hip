@@ -56,9 +56,9 @@ __device__ __forceinline__ uint32_t seq_of(const uint64_t *off, uint32_t nseq, u
 }
 
 // First sort key: i (u32).  Seed t: [qid, i, j, o, c, s].
-__global__ void k_key_i(const uint32_t *seeds, uint64_t ns, uint32_t *key, uint32_t *val) {
+__global__ void k_key_i(const uint32_t *seeds, DevCount ns, uint32_t *key, uint32_t *val) {
     uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ns) return;
+    if (t >= ns.get()) return;
     key[t] = seeds[t * 6 + 1];
     val[t] = (uint32_t)t;
 }
@@ -80,20 +80,20 @@ __device__ __forceinline__ uint64_t group_of(const CellKey &ck, const uint32_t *
 }
 
 // One 64-bit key (group << ibits | i) when it fits.
-__global__ void k_key_combined(const uint32_t *seeds, uint64_t ns, CellKey ck, uint64_t *key,
+__global__ void k_key_combined(const uint32_t *seeds, DevCount ns, CellKey ck, uint64_t *key,
                                uint32_t *val) {
     uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ns) return;
+    if (t >= ns.get()) return;
     const uint32_t *r = seeds + t * 6;
     key[t] = (group_of(ck, r) << ck.ibits) | r[1];
     val[t] = (uint32_t)t;
 }
 
 // Otherwise: first sorted by i, then by the group key in that order.
-__global__ void k_key_cell(const uint32_t *seeds, const uint32_t *order, uint64_t ns, CellKey ck,
+__global__ void k_key_cell(const uint32_t *seeds, const uint32_t *order, DevCount ns, CellKey ck,
                            uint64_t *key, uint32_t *val) {
     uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ns) return;
+    if (t >= ns.get()) return;
     const uint32_t s = order[t];
     key[t] = group_of(ck, seeds + (uint64_t)s * 6);
     val[t] = s;
@@ -106,10 +106,10 @@ struct Sorted {
 };
 
 __global__ void k_gather(const uint32_t *seeds, const uint64_t *gkey, uint32_t gshift,
-                         const uint32_t *order, uint64_t ns, const uint64_t *off, uint32_t nseq,
+                         const uint32_t *order, DevCount ns, const uint64_t *off, uint32_t nseq,
                          Sorted s) {
     uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ns) return;
+    if (t >= ns.get()) return;
     const uint32_t *r = seeds + (uint64_t)order[t] * 6;
     s.g[t] = gkey[t] >> gshift;
     s.i[t] = r[1];
@@ -134,10 +134,14 @@ __device__ __forceinline__ bool linked(const Sorted &s, uint64_t a, uint64_t b, 
 // the one before it (same query and strand, linked()).  Along a
 // duplication, consecutive seeds of a diagonal cell link, so one segment
 // usually holds a whole cell's share of it.
-__global__ void k_seg_flags(Sorted s, uint64_t ns, uint32_t n, uint32_t mo, uint32_t cbits,
+__global__ void k_seg_flags(Sorted s, DevCount nsc, uint32_t n, uint32_t mo, uint32_t cbits,
                             uint32_t *flag) {
     const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= ns) return;
+    if (a >= nsc.bound) return;
+    if (a >= nsc.get()) {  // flags past the count are 0: the scans run over the bound
+        flag[a] = 0;
+        return;
+    }
     bool head = true;
     if (a > 0 && (s.g[a - 1] >> cbits) == (s.g[a] >> cbits) && linked(s, a - 1, a, n, mo))
         head = false;
@@ -146,16 +150,17 @@ __global__ void k_seg_flags(Sorted s, uint64_t ns, uint32_t n, uint32_t mo, uint
 
 // Diagonal cells: flag[a] = 1 where the group key changes.  Their starts
 // come from the same prefix sum as segment heads (k_seg_heads).
-__global__ void k_cell_flags(const uint64_t *g, uint64_t ns, uint32_t *flag) {
+__global__ void k_cell_flags(const uint64_t *g, DevCount nsc, uint32_t *flag) {
     const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= ns) return;
-    flag[a] = (a == 0 || g[a - 1] != g[a]) ? 1u : 0u;
+    if (a >= nsc.bound) return;
+    flag[a] = a < nsc.get() && (a == 0 || g[a - 1] != g[a]) ? 1u : 0u;
 }
 
 // sid = segment of each seed; head[sid] = its first seed, head[#segments] = ns.
-__global__ void k_seg_heads(const uint32_t *flag, const uint32_t *pre, uint64_t ns,
+__global__ void k_seg_heads(const uint32_t *flag, const uint32_t *pre, DevCount nsc,
                             uint32_t *sid, uint32_t *head) {
     const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t ns = nsc.get();
     if (a >= ns) return;
     const uint32_t id = pre[a] + flag[a] - 1;
     sid[a] = id;
@@ -165,9 +170,9 @@ __global__ void k_seg_heads(const uint32_t *flag, const uint32_t *pre, uint64_t 
 
 // Union-find starts from the segments: every seed points at its segment's
 // first seed (the smallest index, so roots stay the minima of components).
-__global__ void k_seg_par(const uint32_t *sid, const uint32_t *head, uint64_t ns, uint32_t *par) {
+__global__ void k_seg_par(const uint32_t *sid, const uint32_t *head, DevCount ns, uint32_t *par) {
     const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a < ns) par[a] = head[sid[a]];
+    if (a < ns.get()) par[a] = head[sid[a]];
 }
 
 // First index in [lo, ns) whose value is not below x (sorted), found by
@@ -214,10 +219,11 @@ __device__ __forceinline__ void wave_unions(uint32_t *par, uint32_t a, uint32_t 
     }
 }
 
-__global__ void k_link(Sorted s, uint64_t ns, uint32_t n, uint32_t mo, uint32_t cbits,
+__global__ void k_link(Sorted s, DevCount nsc, uint32_t n, uint32_t mo, uint32_t cbits,
                        const uint32_t *sid, const uint32_t *head, const uint32_t *cid,
                        const uint32_t *cstart, uint32_t *par) {
     const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t ns = nsc.get();
     const int lane = threadIdx.x & 63;
     LinkSlot t0{0, NONE32}, t1{0, NONE32};
     // a third link of one seed (rare) is joined at once
@@ -268,18 +274,18 @@ __global__ void k_link(Sorted s, uint64_t ns, uint32_t n, uint32_t mo, uint32_t 
     wave_unions(par, (uint32_t)a, sa, t1, lane);
 }
 
-__global__ void k_flatten(uint32_t *par, uint64_t ns) {
+__global__ void k_flatten(uint32_t *par, DevCount ns) {
     uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a < ns) par[a] = uf_find(par, (uint32_t)a);
+    if (a < ns.get()) par[a] = uf_find(par, (uint32_t)a);
 }
 
 struct Agg {
     uint32_t *qmin, *qmax, *tmin, *tmax, *cnt, *cmax;
 };
 
-__global__ void k_agg_init(Agg g, uint64_t ns) {
+__global__ void k_agg_init(Agg g, DevCount ns) {
     uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= ns) return;
+    if (a >= ns.get()) return;
     g.qmin[a] = 0xFFFFFFFFu;
     g.tmin[a] = 0xFFFFFFFFu;
     g.qmax[a] = 0;
@@ -291,8 +297,9 @@ __global__ void k_agg_init(Agg g, uint64_t ns) {
 // Seeds of one component are mostly adjacent in the sorted order: each wave
 // reduces runs of equal roots first and only the last lane of a run issues
 // the atomics.
-__global__ void k_agg(Sorted s, const uint32_t *par, uint64_t ns, Agg g) {
+__global__ void k_agg(Sorted s, const uint32_t *par, DevCount nsc, Agg g) {
     const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t ns = nsc.get();
     const int lane = threadIdx.x & 63;
     const bool act = a < ns;
     const uint32_t r = act ? par[a] : 0xFFFFFFFFu;
@@ -328,16 +335,17 @@ __global__ void k_agg(Sorted s, const uint32_t *par, uint64_t ns, Agg g) {
     }
 }
 
-__global__ void k_root_flags(const uint32_t *par, uint64_t ns, uint32_t *flag) {
+__global__ void k_root_flags(const uint32_t *par, DevCount nsc, uint32_t *flag) {
     uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a < ns) flag[a] = (par[a] == (uint32_t)a) ? 1u : 0u;
+    if (a < nsc.bound) flag[a] = (a < nsc.get() && par[a] == (uint32_t)a) ? 1u : 0u;
 }
 
-__global__ void k_emit_cands(Sorted s, const uint32_t *par, uint64_t ns, Agg g, uint32_t cbits,
+// Candidates past `cap` (a bound that was too small) are counted, not written.
+__global__ void k_emit_cands(Sorted s, const uint32_t *par, DevCount ns, Agg g, uint32_t cbits,
                              const uint32_t *pre, const uint64_t *off, uint32_t nseq, uint32_t n,
-                             sdf_candidate *out) {
+                             sdf_candidate *out, uint64_t cap) {
     uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= ns || par[a] != (uint32_t)a) return;
+    if (a >= ns.get() || par[a] != (uint32_t)a || pre[a] >= cap) return;
     sdf_candidate c;
     const uint64_t gk = s.g[a];
     c.query_id = (uint32_t)(gk >> (cbits + 1));
@@ -416,12 +424,13 @@ __device__ __forceinline__ uint32_t cs_lower(const uint64_t *key, uint32_t lo, u
     return lo;
 }
 
-__global__ void __launch_bounds__(CS_TB) k_chain_small(const uint32_t *seeds, uint32_t ns, CellKey ck,
+__global__ void __launch_bounds__(CS_TB) k_chain_small(const uint32_t *seeds, DevCount nsc, CellKey ck,
                                                        uint32_t n, uint32_t mo, const uint64_t *off,
                                                        uint32_t nseq, sdf_candidate *out,
-                                                       uint32_t *nout) {
+                                                       uint64_t cap, unsigned long long *nout) {
     __shared__ ChainSmallLds L;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t ns = (uint32_t)min<uint64_t>(nsc.get(), CS_N - 1);
     uint32_t n2 = 1;
     while (n2 < ns) n2 <<= 1;
     for (uint32_t t = tid; t < n2; t += CS_TB) {
@@ -569,7 +578,8 @@ __global__ void __launch_bounds__(CS_TB) k_chain_small(const uint32_t *seeds, ui
             c.t_end = (uint64_t)L.tmax[a] + n - off[c.t_seq];
             c.n_seeds = L.cnt[a];
             c.max_shared = L.cmax[a];
-            out[before + (uint32_t)__popcll(m & lt)] = c;
+            const uint32_t at = before + (uint32_t)__popcll(m & lt);
+            if (at < cap) out[at] = c;
         }
         __syncthreads();
         if (tid == 0)
@@ -587,6 +597,9 @@ __device__ __forceinline__ bool cand_less(const sdf_candidate &x, const sdf_cand
 #undef CMPF
     return false;
 }
+
+// Candidates found: pre[bound] of the root-flag scan, as a 64-bit count.
+__global__ void k_count_u32(const uint32_t *src, unsigned long long *dst) { *dst = *src; }
 
 __global__ void k_pad_cands(sdf_candidate *c, uint64_t n, uint64_t n2) {
     uint64_t t = n + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -672,24 +685,25 @@ struct CandPrefix {
     uint32_t sb, pb, shift;  // q_seq bits, q_begin bits, q_begin low bits dropped
 };
 
-__global__ void k_cand_prefix(const sdf_candidate *c, uint64_t nc, CandPrefix cp, uint64_t *key,
+__global__ void k_cand_prefix(const sdf_candidate *c, DevCount nc, CandPrefix cp, uint64_t *key,
                               uint32_t *val) {
     const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nc) return;
+    if (t >= nc.get()) return;
     const uint64_t hi = ((((uint64_t)c[t].query_id << 1) | c[t].strand) << cp.sb) | c[t].q_seq;
     key[t] = (hi << (cp.pb - cp.shift)) | (c[t].q_begin >> cp.shift);
     val[t] = (uint32_t)t;
 }
 
-__global__ void k_permute_cands(const sdf_candidate *c, const uint32_t *order, uint64_t nc,
+__global__ void k_permute_cands(const sdf_candidate *c, const uint32_t *order, DevCount nc,
                                 sdf_candidate *out) {
     const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < nc) out[t] = c[order[t]];
+    if (t < nc.get()) out[t] = c[order[t]];
 }
 
-__global__ void k_cand_ties(const uint64_t *key, uint64_t nc, uint32_t tie_max, sdf_candidate *c,
+__global__ void k_cand_ties(const uint64_t *key, DevCount ncc, uint32_t tie_max, sdf_candidate *c,
                             uint32_t *long_run) {
     const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t nc = ncc.get();
     if (t + 1 >= nc || (t > 0 && key[t - 1] == key[t]) || key[t + 1] != key[t]) return;
     uint64_t e = t + 2;
     while (e < nc && key[e] == key[t] && e - t <= tie_max) e++;
@@ -720,8 +734,9 @@ constexpr int SR_TB = 1024, SR_WAVES = SR_TB / 64, SR_PER = 16, SR_N = SR_TB * S
 constexpr int SR_IDX = 14;
 static_assert((1 << SR_IDX) == SR_N, "index field");
 
-__global__ void __launch_bounds__(SR_TB) k_sort_small(uint64_t *key, uint32_t n, int bits,
+__global__ void __launch_bounds__(SR_TB) k_sort_small(uint64_t *key, DevCount nc, int bits,
                                                       uint32_t *order) {
+    const uint32_t n = (uint32_t)min<uint64_t>(nc.get(), SR_N);
     __shared__ uint64_t buf[SR_N];
     __shared__ uint32_t cnt[SR_WAVES][256];
     __shared__ uint32_t dstart[256];
@@ -806,51 +821,72 @@ __global__ void __launch_bounds__(SR_TB) k_sort_small(uint64_t *key, uint32_t n,
 
 static uint32_t bitlen(uint64_t v);
 
-// Sorts the nc candidates of `cands` (capacity >= the next power of two).
-static void finish_candidates(DevBuf<sdf_candidate> &cands, uint64_t nc, const IndexView &ix,
-                              uint32_t nspans, hipStream_t st) {
+// Sorts the candidates cands[0, nc) (nc on the device, at most nc.bound; the
+// buffer holds the next power of two of nc.bound).  With `deferred` the
+// flag of a run of equal prefixes too long to order in place is left in
+// *long_run for the caller, who checks it after the stream is done;
+// otherwise it is read here and such runs go through the record sort.
+static void finish_candidates(DevBuf<sdf_candidate> &cands, DevCount nc, const IndexView &ix,
+                              uint32_t nspans, hipStream_t st, uint32_t *long_run, bool deferred) {
+    const uint64_t ncb = nc.bound;
     uint64_t n2 = 1;
-    while (n2 < nc) n2 <<= 1;
+    while (n2 < ncb) n2 <<= 1;
     const uint32_t qb = bitlen(nspans > 0 ? nspans - 1 : 0), sb = bitlen(ix.nseq > 0 ? ix.nseq - 1 : 0);
     const uint32_t pb = bitlen(ix.total), head = qb + 1 + sb;
     const uint32_t shift = head + pb > 64 ? head + pb - 64 : 0;
     bool general = std::getenv("SDF_CAND_SORT_GENERAL") != nullptr || shift > pb;
-    if (nc > 1 && !general) {
-        DevBuf<uint64_t> key(nc);
-        DevBuf<uint32_t> order(nc);
-        k_cand_prefix<<<nb(nc), 256, 0, st>>>(cands.p, nc, CandPrefix{sb, pb, shift}, key.p, order.p);
+    if (general && deferred) throw Error{SDF_EINVAL, "candidate keys too wide for a captured search"};
+    if (ncb > 1 && !general) {
+        DevBuf<uint64_t> key(ncb);
+        DevBuf<uint32_t> order(ncb);
+        k_cand_prefix<<<nb(ncb), 256, 0, st>>>(cands.p, nc, CandPrefix{sb, pb, shift}, key.p, order.p);
         SDF_HIP(hipGetLastError());
         const int kbits = (int)(head + pb - shift);
         // test hook: SDF_CAND_SORT_SMALL_MAX lowers the count sorted by one workgroup
         uint64_t small_max = SR_N;
         if (const char *v = std::getenv("SDF_CAND_SORT_SMALL_MAX"))
             small_max = std::min<uint64_t>(SR_N, std::strtoull(v, nullptr, 10));
-        if (nc <= small_max && kbits <= 50) {
-            k_sort_small<<<1, SR_TB, 0, st>>>(key.p, (uint32_t)nc, kbits, order.p);
+        if (ncb <= small_max && kbits <= 50) {
+            k_sort_small<<<1, SR_TB, 0, st>>>(key.p, nc, kbits, order.p);
             SDF_HIP(hipGetLastError());
         } else {
             radix_sort_u64(key.p, order.p, nc, kbits, st);
         }
         DevBuf<sdf_candidate> sorted(n2);
-        k_permute_cands<<<nb(nc), 256, 0, st>>>(cands.p, order.p, nc, sorted.p);
+        k_permute_cands<<<nb(ncb), 256, 0, st>>>(cands.p, order.p, nc, sorted.p);
         SDF_HIP(hipGetLastError());
-        DevBuf<uint32_t> flag(1);
-        SDF_HIP(hipMemsetAsync(flag.p, 0, 4, st));
         // test hook: SDF_CAND_TIE_MAX lowers the longest run ordered in place
         uint32_t tie_max = TIE_MAX;
         if (const char *v = std::getenv("SDF_CAND_TIE_MAX"))
             tie_max = std::min<uint32_t>(TIE_MAX, (uint32_t)std::strtoul(v, nullptr, 10));
-        k_cand_ties<<<nb(nc), 256, 0, st>>>(key.p, nc, tie_max, sorted.p, flag.p);
+        k_cand_ties<<<nb(ncb), 256, 0, st>>>(key.p, nc, tie_max, sorted.p, long_run);
         SDF_HIP(hipGetLastError());
-        uint32_t long_run = 0;
+        cands = std::move(sorted);
+        if (deferred) return;
+        uint32_t lr = 0;
         {
             Readback rb(st);
-            rb.add(&long_run, flag.p, 4);
+            rb.add(&lr, long_run, 4);
             rb.wait();
         }
-        cands = std::move(sorted);
-        if (!long_run) return;
+        if (!lr) return;
         general = true;
+    }
+    if (deferred) return;
+    sort_candidates_records(cands, ncb, st);
+}
+
+// The record sort of all candidates (the host knows their count): padding
+// to a power of two, then bitonic stages.
+void sort_candidates_records(DevBuf<sdf_candidate> &cands, uint64_t nc, hipStream_t st) {
+    uint64_t n2 = 1;
+    while (n2 < nc) n2 <<= 1;
+    if (cands.n < n2) {
+        DevBuf<sdf_candidate> big(n2);
+        if (nc)
+            SDF_HIP(hipMemcpyAsync(big.p, cands.p, nc * sizeof(sdf_candidate),
+                                   hipMemcpyDeviceToDevice, st));
+        cands = std::move(big);
     }
     if (n2 > nc) {
         k_pad_cands<<<nb(n2 - nc), 256, 0, st>>>(cands.p, nc, n2);
@@ -865,9 +901,15 @@ static uint32_t bitlen(uint64_t v) {
     return b;
 }
 
-void chain_seeds(const IndexView &ix, const uint32_t *seeds, uint64_t ns, uint32_t n,
-                 uint32_t mo, uint32_t nspans, ChainOut &out, hipStream_t st) {
+void chain_seeds(const IndexView &ix, const uint32_t *seeds, DevCount nsc, uint32_t n,
+                 uint32_t mo, uint32_t nspans, ChainOut &out, hipStream_t st, uint64_t nc_bound) {
     out.ncands = 0;
+    out.dcount.alloc(1);
+    out.dflag.alloc(1);
+    const bool deferred = nc_bound != 0;  // no count is read back: bounds from the caller
+    const uint64_t ns = nsc.bound;
+    fill_u32(reinterpret_cast<uint32_t *>(out.dcount.p), 0u, 2, st);
+    fill_u32(out.dflag.p, 0u, 1, st);
     if (ns == 0) {
         out.cands.alloc(1);
         return;
@@ -884,92 +926,102 @@ void chain_seeds(const IndexView &ix, const uint32_t *seeds, uint64_t ns, uint32
     uint64_t fused_max = CS_N - 1;
     if (const char *v = std::getenv("SDF_CHAIN_FUSED_MAX"))
         fused_max = std::min<uint64_t>(fused_max, std::strtoull(v, nullptr, 10));
+    uint64_t cap = 0;  // candidate capacity
     if (ns <= fused_max && gbits + ck.ibits <= 64) {
-        uint64_t cap = 1;
-        while (cap < ns) cap <<= 1;
-        out.cands.alloc(cap);
-        DevBuf<uint32_t> cnt(1);
-        k_chain_small<<<1, CS_TB, 0, st>>>(seeds, (uint32_t)ns, ck, n, mo, ix.off, ix.nseq,
-                                           out.cands.p, cnt.p);
+        cap = deferred ? nc_bound : ns;  // candidates <= seeds
+        uint64_t c2 = 1;
+        while (c2 < cap) c2 <<= 1;
+        out.cands.alloc(c2);
+        k_chain_small<<<1, CS_TB, 0, st>>>(seeds, nsc, ck, n, mo, ix.off, ix.nseq, out.cands.p, cap,
+                                           out.dcount.p);
         SDF_HIP(hipGetLastError());
-        uint32_t nc = 0;
+    } else {
+        DevBuf<uint64_t> gk(ns);
+        DevBuf<uint32_t> order2(ns);
+        uint32_t gshift = 0;
+        if (gbits + ck.ibits <= 64) {
+            k_key_combined<<<nb(ns), 256, 0, st>>>(seeds, nsc, ck, gk.p, order2.p);
+            SDF_HIP(hipGetLastError());
+            radix_sort_u64(gk.p, order2.p, nsc, (int)(gbits + ck.ibits), st);
+            gshift = ck.ibits;
+        } else {
+            DevBuf<uint32_t> k1(ns), order(ns);
+            k_key_i<<<nb(ns), 256, 0, st>>>(seeds, nsc, k1.p, order.p);
+            SDF_HIP(hipGetLastError());
+            radix_sort_u32(k1.p, order.p, nsc, (int)ck.ibits, st);
+            k_key_cell<<<nb(ns), 256, 0, st>>>(seeds, order.p, nsc, ck, gk.p, order2.p);
+            SDF_HIP(hipGetLastError());
+            radix_sort_u64(gk.p, order2.p, nsc, (int)gbits, st);
+        }
+        DevBuf<uint64_t> sg(ns);
+        DevBuf<uint32_t> si(ns), sj(ns), sc(ns), sts(ns);
+        DevBuf<int64_t> sd(ns);
+        Sorted s{sg.p, si.p, sj.p, sc.p, sts.p, sd.p};
+        k_gather<<<nb(ns), 256, 0, st>>>(seeds, gk.p, gshift, order2.p, nsc, ix.off, ix.nseq, s);
+        SDF_HIP(hipGetLastError());
+        DevBuf<uint32_t> par(ns);
+        {
+            DevBuf<uint32_t> sflag(ns + 1), spre(ns + 1), sid(ns), head(ns + 1);
+            DevBuf<uint32_t> cid(ns), cstart(ns + 1);
+            k_cell_flags<<<nb(ns), 256, 0, st>>>(s.g, nsc, sflag.p);
+            SDF_HIP(hipGetLastError());
+            scan_u32(sflag.p, spre.p, ns, st);
+            k_seg_heads<<<nb(ns), 256, 0, st>>>(sflag.p, spre.p, nsc, cid.p, cstart.p);
+            SDF_HIP(hipGetLastError());
+            k_seg_flags<<<nb(ns), 256, 0, st>>>(s, nsc, n, mo, ck.cbits, sflag.p);
+            SDF_HIP(hipGetLastError());
+            scan_u32(sflag.p, spre.p, ns, st);
+            k_seg_heads<<<nb(ns), 256, 0, st>>>(sflag.p, spre.p, nsc, sid.p, head.p);
+            SDF_HIP(hipGetLastError());
+            k_seg_par<<<nb(ns), 256, 0, st>>>(sid.p, head.p, nsc, par.p);
+            SDF_HIP(hipGetLastError());
+            k_link<<<nb(ns), 256, 0, st>>>(s, nsc, n, mo, ck.cbits, sid.p, head.p, cid.p, cstart.p,
+                                           par.p);
+            SDF_HIP(hipGetLastError());
+        }
+        k_flatten<<<nb(ns), 256, 0, st>>>(par.p, nsc);
+        SDF_HIP(hipGetLastError());
+        DevBuf<uint32_t> a1(ns), a2(ns), a3(ns), a4(ns), a5(ns), a6(ns);
+        Agg g{a1.p, a2.p, a3.p, a4.p, a5.p, a6.p};
+        k_agg_init<<<nb(ns), 256, 0, st>>>(g, nsc);
+        k_agg<<<nb(ns), 256, 0, st>>>(s, par.p, nsc, g);
+        SDF_HIP(hipGetLastError());
+        DevBuf<uint32_t> flag(ns + 1), pre(ns + 1);
+        k_root_flags<<<nb(ns), 256, 0, st>>>(par.p, nsc, flag.p);
+        SDF_HIP(hipGetLastError());
+        scan_u32(flag.p, pre.p, ns, st);
+        k_count_u32<<<1, 1, 0, st>>>(pre.p + ns, out.dcount.p);
+        SDF_HIP(hipGetLastError());
+        if (deferred) {
+            cap = nc_bound;
+        } else {
+            uint32_t nc = 0;
+            {
+                Readback rb(st);
+                rb.add(&nc, pre.p + ns, 4);
+                rb.wait();
+            }
+            cap = nc;
+        }
+        uint64_t c2 = 1;
+        while (c2 < cap) c2 <<= 1;
+        out.cands.alloc(c2);
+        k_emit_cands<<<nb(ns), 256, 0, st>>>(s, par.p, nsc, g, ck.cbits, pre.p, ix.off, ix.nseq, n,
+                                             out.cands.p, cap);
+        SDF_HIP(hipGetLastError());
+    }
+    uint64_t nc = cap;
+    if (!deferred && ns <= fused_max && gbits + ck.ibits <= 64) {
+        unsigned long long c = 0;
         {
             Readback rb(st);
-            rb.add(&nc, cnt.p, 4);
+            rb.add(&c, out.dcount.p, 8);
             rb.wait();
         }
-        finish_candidates(out.cands, nc, ix, nspans, st);
-        out.ncands = nc;
-        return;
+        nc = c;
     }
-    DevBuf<uint64_t> gk(ns);
-    DevBuf<uint32_t> order2(ns);
-    uint32_t gshift = 0;
-    if (gbits + ck.ibits <= 64) {
-        k_key_combined<<<nb(ns), 256, 0, st>>>(seeds, ns, ck, gk.p, order2.p);
-        SDF_HIP(hipGetLastError());
-        radix_sort_u64(gk.p, order2.p, ns, (int)(gbits + ck.ibits), st);
-        gshift = ck.ibits;
-    } else {
-        DevBuf<uint32_t> k1(ns), order(ns);
-        k_key_i<<<nb(ns), 256, 0, st>>>(seeds, ns, k1.p, order.p);
-        SDF_HIP(hipGetLastError());
-        radix_sort_u32(k1.p, order.p, ns, (int)ck.ibits, st);
-        k_key_cell<<<nb(ns), 256, 0, st>>>(seeds, order.p, ns, ck, gk.p, order2.p);
-        SDF_HIP(hipGetLastError());
-        radix_sort_u64(gk.p, order2.p, ns, (int)gbits, st);
-    }
-    DevBuf<uint64_t> sg(ns);
-    DevBuf<uint32_t> si(ns), sj(ns), sc(ns), sts(ns);
-    DevBuf<int64_t> sd(ns);
-    Sorted s{sg.p, si.p, sj.p, sc.p, sts.p, sd.p};
-    k_gather<<<nb(ns), 256, 0, st>>>(seeds, gk.p, gshift, order2.p, ns, ix.off, ix.nseq, s);
-    SDF_HIP(hipGetLastError());
-    DevBuf<uint32_t> par(ns);
-    {
-        DevBuf<uint32_t> sflag(ns + 1), spre(ns + 1), sid(ns), head(ns + 1);
-        DevBuf<uint32_t> cid(ns), cstart(ns + 1);
-        k_cell_flags<<<nb(ns), 256, 0, st>>>(s.g, ns, sflag.p);
-        SDF_HIP(hipGetLastError());
-        scan_u32(sflag.p, spre.p, ns, st);
-        k_seg_heads<<<nb(ns), 256, 0, st>>>(sflag.p, spre.p, ns, cid.p, cstart.p);
-        SDF_HIP(hipGetLastError());
-        k_seg_flags<<<nb(ns), 256, 0, st>>>(s, ns, n, mo, ck.cbits, sflag.p);
-        SDF_HIP(hipGetLastError());
-        scan_u32(sflag.p, spre.p, ns, st);
-        k_seg_heads<<<nb(ns), 256, 0, st>>>(sflag.p, spre.p, ns, sid.p, head.p);
-        SDF_HIP(hipGetLastError());
-        k_seg_par<<<nb(ns), 256, 0, st>>>(sid.p, head.p, ns, par.p);
-        SDF_HIP(hipGetLastError());
-        k_link<<<nb(ns), 256, 0, st>>>(s, ns, n, mo, ck.cbits, sid.p, head.p, cid.p, cstart.p,
-                                       par.p);
-        SDF_HIP(hipGetLastError());
-    }
-    k_flatten<<<nb(ns), 256, 0, st>>>(par.p, ns);
-    SDF_HIP(hipGetLastError());
-    DevBuf<uint32_t> a1(ns), a2(ns), a3(ns), a4(ns), a5(ns), a6(ns);
-    Agg g{a1.p, a2.p, a3.p, a4.p, a5.p, a6.p};
-    k_agg_init<<<nb(ns), 256, 0, st>>>(g, ns);
-    k_agg<<<nb(ns), 256, 0, st>>>(s, par.p, ns, g);
-    SDF_HIP(hipGetLastError());
-    DevBuf<uint32_t> flag(ns + 1), pre(ns + 1);
-    k_root_flags<<<nb(ns), 256, 0, st>>>(par.p, ns, flag.p);
-    SDF_HIP(hipGetLastError());
-    scan_u32(flag.p, pre.p, ns, st);
-    uint32_t nc = 0;
-    {
-        Readback rb(st);
-        rb.add(&nc, pre.p + ns, 4);
-        rb.wait();
-    }
-    uint64_t n2 = 1;
-    while (n2 < nc) n2 <<= 1;
-    out.cands.alloc(n2);
-    k_emit_cands<<<nb(ns), 256, 0, st>>>(s, par.p, ns, g, ck.cbits, pre.p, ix.off, ix.nseq, n,
-                                         out.cands.p);
-    SDF_HIP(hipGetLastError());
-    finish_candidates(out.cands, nc, ix, nspans, st);
-    out.ncands = nc;
+    finish_candidates(out.cands, DevCount{out.dcount.p, nc}, ix, nspans, st, out.dflag.p, deferred);
+    out.ncands = deferred ? 0 : nc;
 }
 
 // ------------------------------------------------------------- seed sort --

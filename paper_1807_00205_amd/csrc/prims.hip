@@ -64,9 +64,43 @@ void pool_trim() {
 static thread_local Arena *t_arena = nullptr;
 ArenaScope::ArenaScope(Arena *a) : prev(t_arena) { t_arena = a; }
 ArenaScope::~ArenaScope() { t_arena = prev; }
-bool in_arena() { return t_arena != nullptr; }
+// True while device buffers must not be allocated at all (a carving arena):
+// pinned staging and host uploads are then avoided as well.
+bool in_arena() { return t_arena != nullptr && t_arena->mode == Arena::CARVE; }
+
+void release_blocks(Arena &a) {
+    for (const auto &b : a.blocks) pool_free(b.first);
+    a.blocks.clear();
+    a.next = 0;
+}
+
+static void *pool_alloc_raw(size_t bytes);
 
 void *pool_alloc(size_t bytes) {
+    if (t_arena && t_arena->mode == Arena::RECORD) {
+        Arena *a = t_arena;
+        t_arena = nullptr;  // the block itself comes from the pool
+        void *p = nullptr;
+        try {
+            p = pool_alloc_raw(bytes);
+        } catch (...) {
+            t_arena = a;
+            throw;
+        }
+        t_arena = a;
+        a->blocks.push_back({p, bytes});
+        return p;
+    }
+    if (t_arena && t_arena->mode == Arena::REPLAY) {
+        if (t_arena->next >= t_arena->blocks.size() || t_arena->blocks[t_arena->next].second != bytes)
+            throw Error{SDF_EINTERNAL, "captured launch sequence asked for other buffers than "
+                                       "its rehearsal"};
+        return t_arena->blocks[t_arena->next++].first;
+    }
+    return pool_alloc_raw(bytes);
+}
+
+static void *pool_alloc_raw(size_t bytes) {
     if (t_arena) {
         const size_t b = ((bytes ? bytes : 1) + 255) & ~size_t(255);
         if (b > t_arena->cap - t_arena->used)
@@ -109,9 +143,13 @@ void *pool_alloc(size_t bytes) {
 
 void pool_free(void *p) {
     if (!p) return;
-    if (t_arena && (unsigned char *)p >= t_arena->base &&
+    if (t_arena && t_arena->mode == Arena::CARVE && (unsigned char *)p >= t_arena->base &&
         (unsigned char *)p < t_arena->base + t_arena->cap)
         return;  // arena blocks are released with the scope
+    if (t_arena && t_arena->mode != Arena::CARVE) {
+        for (const auto &b : t_arena->blocks)
+            if (b.first == p) return;  // kept by the arena's owner
+    }
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_live.find(p);
     if (it == g_live.end()) return;
@@ -186,7 +224,7 @@ void stage_release(Stage *s) {
 static thread_local unsigned char t_plain_stage[READBACK_MAX];
 
 Readback::Readback(hipStream_t st)
-    : st_(st), stage_(t_arena ? nullptr : stage_acquire(READBACK_MAX)) {}
+    : st_(st), stage_(in_arena() ? nullptr : stage_acquire(READBACK_MAX)) {}
 
 Readback::~Readback() {
     // copies queued but not waited for (an exception in between) may still
@@ -379,9 +417,10 @@ constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
 constexpr int RS_BINS = 256;
 
 template <class K>
-__global__ void __launch_bounds__(RS_THREADS) k_rs_hist(const K *keys, uint64_t n, int shift,
+__global__ void __launch_bounds__(RS_THREADS) k_rs_hist(const K *keys, DevCount cnt, int shift,
                                                      uint32_t *hist, uint32_t nblocks) {
     __shared__ uint32_t h[RS_BINS];
+    const uint64_t n = cnt.get();  // blocks past it count nothing
     for (int i = threadIdx.x; i < RS_BINS; i += RS_THREADS) h[i] = 0;
     __syncthreads();
     uint64_t base = (uint64_t)blockIdx.x * RS_TILE;
@@ -402,8 +441,10 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_hist(const K *keys, uint64_t 
 // threads store consecutive elements of one digit's run (coalesced).
 template <class K>
 __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const K *kin, const uint32_t *vin, K *kout,
-                                                        uint32_t *vout, uint64_t n, int shift,
+                                                        uint32_t *vout, DevCount count, int shift,
                                                         const uint64_t *hoff, uint32_t nblocks) {
+    const uint64_t n = count.get();
+    if ((uint64_t)blockIdx.x * RS_TILE >= n) return;
     __shared__ uint32_t cnt[RS_WAVES][RS_BINS];
     __shared__ uint64_t boff[RS_BINS];
     __shared__ uint32_t lstart[RS_BINS];  // first tile slot of each digit
@@ -497,7 +538,8 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const K *kin, const u
 }
 
 template <class K>
-static void radix_impl(K *keys, uint32_t *vals, uint64_t n, int bits, hipStream_t st) {
+static void radix_impl(K *keys, uint32_t *vals, DevCount cnt, int bits, hipStream_t st) {
+    const uint64_t n = cnt.bound;  // grid and buffer sizes; the kernels stop at cnt.get()
     if (n <= 1 || bits <= 0) return;
     uint64_t nb64 = (n + RS_TILE - 1) / RS_TILE;
     if (nb64 > 0xFFFFFFFFull) throw Error{SDF_EINVAL, "radix sort too large"};
@@ -511,10 +553,10 @@ static void radix_impl(K *keys, uint32_t *vals, uint64_t n, int bits, hipStream_
     int passes = (bits + 7) / 8;
     for (int p = 0; p < passes; p++) {
         int shift = 8 * p;
-        k_rs_hist<K><<<nb, RS_THREADS, 0, st>>>(ka, n, shift, hist.p, nb);
+        k_rs_hist<K><<<nb, RS_THREADS, 0, st>>>(ka, cnt, shift, hist.p, nb);
         SDF_HIP(hipGetLastError());
         scan_u32_to_u64(hist.p, hoff.p, (uint64_t)RS_BINS * nb, st);
-        k_rs_scatter<K><<<nb, RS_THREADS, 0, st>>>(ka, va, kb, vb, n, shift, hoff.p, nb);
+        k_rs_scatter<K><<<nb, RS_THREADS, 0, st>>>(ka, va, kb, vb, cnt, shift, hoff.p, nb);
         SDF_HIP(hipGetLastError());
         std::swap(ka, kb);
         std::swap(va, vb);
@@ -525,11 +567,17 @@ static void radix_impl(K *keys, uint32_t *vals, uint64_t n, int bits, hipStream_
     }
 }
 
-void radix_sort_u32(uint32_t *keys, uint32_t *vals, uint64_t n, int bits, hipStream_t st) {
+void radix_sort_u32(uint32_t *keys, uint32_t *vals, DevCount n, int bits, hipStream_t st) {
     radix_impl<uint32_t>(keys, vals, n, bits, st);
 }
-void radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t n, int bits, hipStream_t st) {
+void radix_sort_u64(uint64_t *keys, uint32_t *vals, DevCount n, int bits, hipStream_t st) {
     radix_impl<uint64_t>(keys, vals, n, bits, st);
+}
+void radix_sort_u32(uint32_t *keys, uint32_t *vals, uint64_t n, int bits, hipStream_t st) {
+    radix_impl<uint32_t>(keys, vals, DevCount{nullptr, n}, bits, st);
+}
+void radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t n, int bits, hipStream_t st) {
+    radix_impl<uint64_t>(keys, vals, DevCount{nullptr, n}, bits, st);
 }
 
 }  // namespace sdf

@@ -40,10 +40,19 @@ struct Error {
 void *pool_alloc(size_t bytes);
 // Fixed device area that serves pool_alloc while an ArenaScope is open on
 // the calling thread (see prims.hip); `peak` records the most ever in use.
+// Three modes: carve blocks off one fixed area (base/cap); record, where
+// blocks come from the pool and are kept in `blocks` (freed by the owner
+// with release_blocks); replay, where the recorded blocks are handed out
+// again in the same order (a launch sequence being captured into a graph
+// gets the very buffers its rehearsal used, without allocating).
 struct Arena {
+    enum Mode { CARVE, RECORD, REPLAY } mode = CARVE;
     unsigned char *base = nullptr;
     size_t cap = 0, used = 0, peak = 0;
+    std::vector<std::pair<void *, size_t>> blocks;
+    size_t next = 0;
 };
+void release_blocks(Arena &a);
 struct ArenaScope {
     Arena *prev;
     explicit ArenaScope(Arena *a);
@@ -139,6 +148,21 @@ struct DevBuf {
     ~DevBuf() { reset(); }
 };
 
+// A count that lives on the device (for instance the seed counter a kernel
+// bumped), with a host bound that sizes grids and buffers: kernels use
+// min(*d, bound), or bound when d is null.  Launch sequences that do not
+// read counts back to the host (so that they can be captured in a graph)
+// pass the device count; the others pass the exact count as the bound.
+struct DevCount {
+    const unsigned long long *d;
+    uint64_t bound;
+    __device__ __forceinline__ uint64_t get() const {
+        if (!d) return bound;
+        const uint64_t v = *d;
+        return v < bound ? v : bound;
+    }
+};
+
 // Primitives (prims.hip) -----------------------------------------------------
 // Exclusive prefix sum of n u32 values into u64 outputs; out[n] = total.
 void scan_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n, hipStream_t st);
@@ -147,6 +171,10 @@ void scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, hipStream_t st);
 // Stable LSD radix sort of (key, value) pairs on key bits [0, bits).
 void radix_sort_u32(uint32_t *keys, uint32_t *vals, uint64_t n, int bits, hipStream_t st);
 void radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t n, int bits, hipStream_t st);
+// The same for a device count: grids and buffers by n.bound, keys [0, n.get())
+// sorted (entries past it are moved about but not ordered).
+void radix_sort_u32(uint32_t *keys, uint32_t *vals, DevCount n, int bits, hipStream_t st);
+void radix_sort_u64(uint64_t *keys, uint32_t *vals, DevCount n, int bits, hipStream_t st);
 void fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t st);
 void iota_u32(uint32_t *p, uint64_t n, hipStream_t st);
 

@@ -77,13 +77,24 @@ void launch_tile_search(const SearchArgs &a, uint32_t grid, hipStream_t st);
 uint32_t tile_core_max();
 }
 
-// Chaining (chain.hip): seeds -> sorted candidates; returns the candidate count.
+// Chaining (chain.hip): seeds -> sorted candidates.
 struct ChainOut {
     DevBuf<sdf_candidate> cands;
-    uint64_t ncands = 0;
+    uint64_t ncands = 0;                // on the host (0 when nothing was read back)
+    DevBuf<unsigned long long> dcount;  // candidates found, on the device
+    DevBuf<uint32_t> dflag;             // a run of equal sort prefixes too long to order in place
 };
-void chain_seeds(const IndexView &ix, const uint32_t *seeds, uint64_t nseeds, uint32_t n,
-                 uint32_t max_overlap, uint32_t nspans, ChainOut &out, hipStream_t st);
+// The seeds [0, ns.get()) of `seeds`; grids and buffers by ns.bound.  With
+// nc_bound == 0 the candidate count is read back (one wait) and sizes the
+// output and its sort, and out.ncands holds it; otherwise nothing is read
+// back: nc_bound sizes them, candidates past it are counted but not written,
+// and a too-long run of equal sort prefixes is only flagged in out.dflag (see
+// sort_candidates_records), so the whole sequence can be captured in a graph.
+void chain_seeds(const IndexView &ix, const uint32_t *seeds, DevCount ns, uint32_t n,
+                 uint32_t max_overlap, uint32_t nspans, ChainOut &out, hipStream_t st,
+                 uint64_t nc_bound = 0);
+// Full record-order sort of nc candidates (buffer regrown to a power of two).
+void sort_candidates_records(DevBuf<sdf_candidate> &cands, uint64_t nc, hipStream_t st);
 // Seeds sorted by (query_id, i, j, strand) into dst (device, 6 u32 each).
 void sort_seeds(const uint32_t *seeds, uint64_t nseeds, uint32_t *dst, hipStream_t st);
 

@@ -40,7 +40,8 @@ EXPORTS = ["sdf_last_error", "sdf_index_build", "sdf_index_info", "sdf_index_hit
            "sdf_search_batch", "sdf_result_count", "sdf_result_copy", "sdf_result_seed_count",
            "sdf_result_seeds", "sdf_result_timing", "sdf_result_stats", "sdf_result_free",
            "sdf_extend", "sdf_result_regions", "sdf_qgram_filter", "sdf_autotune",
-           "sdf_search_batch_noalloc"]
+           "sdf_search_batch_noalloc", "sdf_plan_create", "sdf_plan_run", "sdf_plan_info",
+           "sdf_plan_free"]
 NOALLOC_SCRATCH_BYTES = 128 << 20
 NOALLOC_MAX_SPANS = 65536
 NOALLOC_MAX_QUERY_BASES = 8_000_000
@@ -73,6 +74,10 @@ class _ExtendParams(ctypes.Structure):
 class _QgramParams(ctypes.Structure):
     _fields_ = [("max_error", ctypes.c_double), ("gap_rate", ctypes.c_double),
                 ("q", ctypes.c_uint32), ("_pad", ctypes.c_uint32)]
+
+
+class _PlanParams(ctypes.Structure):
+    _fields_ = [("seed_cap", ctypes.c_uint64), ("cand_cap", ctypes.c_uint64)]
 
 
 class _Span(ctypes.Structure):
@@ -186,6 +191,14 @@ def lib() -> ctypes.CDLL:
         L.sdf_qgram_filter.argtypes = [vp, vp, u64, P(_QgramParams), vp, vp, vp]
         L.sdf_result_regions.restype = st
         L.sdf_result_regions.argtypes = [vp, vp, u64, P(u64)]
+        L.sdf_plan_create.restype = st
+        L.sdf_plan_create.argtypes = [vp, vp, u32, P(_SearchParams), P(_PlanParams), vp, P(vp)]
+        L.sdf_plan_run.restype = st
+        L.sdf_plan_run.argtypes = [vp, vp, P(vp)]
+        L.sdf_plan_info.restype = st
+        L.sdf_plan_info.argtypes = [vp, P(u64), P(u64), P(u64), P(u64)]
+        L.sdf_plan_free.restype = None
+        L.sdf_plan_free.argtypes = [vp]
         L.sdf_search_batch_noalloc.restype = st
         L.sdf_search_batch_noalloc.argtypes = [vp, vp, u32, P(_SearchParams), vp, vp, u64,
                                                P(u64)]
@@ -267,6 +280,44 @@ class Result:
             keys += ["ext_insertions", "ext_continued", "ext_ranks", "ext_rank_us",
                      "ext_phase_us", "ext_slowest_region_us"]
         return dict(zip(keys, [int(x) for x in v]))
+
+
+class Plan:
+    """A batched search of fixed spans captured as a HIP graph
+    (``sdf_plan_create``); ``run()`` replays it (``sdf_plan_run``)."""
+
+    def __init__(self, index, spans, max_error=0.25, min_len=1000, seed_cap=0, cand_cap=0,
+                 stream=None):
+        arr, nspans = _span_array(spans)
+        p = _SearchParams(max_error, min_len, 0)
+        pp = _PlanParams(seed_cap, cand_cap)
+        h = ctypes.c_void_p()
+        _check(lib().sdf_plan_create(index._h, arr.ctypes.data_as(ctypes.c_void_p), nspans,
+                                     ctypes.byref(p), ctypes.byref(pp), _stream_ptr(stream),
+                                     ctypes.byref(h)))
+        self._h = h.value
+        self._index = index  # the index must outlive the plan
+
+    def run(self, stream=None) -> Result:
+        h = ctypes.c_void_p()
+        _check(lib().sdf_plan_run(self._h, _stream_ptr(stream), ctypes.byref(h)))
+        return Result(h.value)
+
+    def info(self) -> dict:
+        v = [ctypes.c_uint64() for _ in range(4)]
+        _check(lib().sdf_plan_info(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(["seed_cap", "cand_cap", "replays", "fallbacks"], [x.value for x in v]))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sdf_plan_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Index:
@@ -434,3 +485,8 @@ class Index:
                                               out.ctypes.data_as(ctypes.c_void_p), cap,
                                               ctypes.byref(n)))
         return out[:min(cap, n.value)].copy(), n.value
+
+    def plan(self, spans: Iterable[Tuple[int, int, int]], max_error: float = 0.25,
+             min_len: int = 1000, seed_cap: int = 0, cand_cap: int = 0, stream=None) -> Plan:
+        """The batched search of these spans captured as a HIP graph."""
+        return Plan(self, spans, max_error, min_len, seed_cap, cand_cap, stream)

@@ -150,6 +150,24 @@ def batched_vs_plain(steps, plain=True, cpu=True, max_error=0.25, min_len=1000):
     core, threads, tune_ms = ix.autotune(spans)
     tune_s = time.perf_counter() - t0
     tb, kms, ncand, stats = timed()
+    # the same batch captured once as a HIP graph and replayed
+    stream = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    plan = ix.plan(spans, stream=stream)
+    plan_s = time.perf_counter() - t0
+    r = plan.run(stream)
+    r.candidates()
+    r.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = plan.run(stream)
+        ncand_g = len(r.candidates())
+        r.close()
+    torch.cuda.synchronize()
+    tg = (time.perf_counter() - t0) / steps
+    ginfo = plan.info()
+    plan.close()
     lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -174,6 +192,10 @@ def batched_vs_plain(steps, plain=True, cpu=True, max_error=0.25, min_len=1000):
                        % (len(g.truth), qb / 1e6),
            "batched_mbp_per_s": round(qb / tb / 1e6, 2), "batched_ms": round(tb * 1e3, 3),
            "batched_tile_kernel_ms": round(mean_k, 4),
+           "graph": {"path": "the same batch captured once as a HIP graph (sdf_plan_create) and "
+                             "replayed (sdf_plan_run), candidates copied out each step",
+                     "mbp_per_s": round(qb / tg / 1e6, 2), "ms": round(tg * 1e3, 3),
+                     "capture_s": round(plan_s, 3), "candidates": ncand_g, **ginfo},
            "roofline": roofline(alg, mean_k, measured_traffic("batched250")),
            "hit_density": round(hbar, 4), "candidates": ncand, "stats": stats,
            "tuning": tuning}

@@ -180,12 +180,16 @@ void sdf_index_free(sdf_index ix);
  * target window [j, j+n) of G that starts at one of its hits.  Seeds are the
  * best target start of each run of consecutive passing targets; chains of
  * seeds become candidates.
+ * Windows whose hits are denser than the on-chip tile holds (inside an
+ * unmasked homopolymer or tandem array of several kbp), or longer than its
+ * minimizer capacity (seed windows beyond about 10 kbp), are searched by a
+ * slower global-memory pass with the same definitions; results do not
+ * depend on which pass a window takes.
  * Errors: SDF_EINVAL, SDF_ERANGE (span outside its sequence), SDF_ENOMEM,
- * SDF_EDEVICE, SDF_EINTERNAL (a single window would keep more than 2,048
- * hits, or have more than 65,535, within 4n target bases: an unmasked
- * satellite far denser than soft-masked assemblies contain).  A span
- * shorter than n succeeds with no candidates.  *out receives the result
- * (NULL on failure).
+ * SDF_EDEVICE, SDF_EINTERNAL (more such dense windows than one query base
+ * each, beyond 2^22 in all; with SDF_SEED_ESTIMATE, any dense window).  A
+ * span shorter than n succeeds with no candidates.  *out receives the
+ * result (NULL on failure).
  */
 sdf_status sdf_search(sdf_index ix, const sdf_span *q, const sdf_search_params *p,
                       void *hip_stream, sdf_result *out);

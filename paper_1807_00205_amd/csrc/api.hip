@@ -451,10 +451,18 @@ void prepare(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const Params &P, 
                               std::max<uint64_t>(tile_bound, 1)));
 }
 
+// Entries of the list of windows too dense for a tile: up to one per query
+// base (a homopolymer has a minimizer at every position), at most 2^22
+// (2^19 inside a fixed scratch area).
+uint64_t dense_capacity(uint64_t qbases) {
+    return std::min<uint64_t>(qbases + 1024, in_arena() ? (1ull << 19) : (1ull << 22));
+}
+
 // Arguments of the tile kernel for a prepared search.
 SearchArgs tile_args(sdf_index_s *ix, const Params &P, const Prepared &pr, uint32_t nq,
                      uint32_t *seeds, uint64_t seed_cap, unsigned long long *counters,
-                     uint32_t *work, unsigned long long *phase, uint32_t runs_out) {
+                     uint32_t *work, unsigned long long *phase, uint32_t runs_out,
+                     uint64_t *dense, uint64_t dense_cap) {
     SearchArgs a;
     a.ix = ix->view();
     a.n = P.n;
@@ -473,6 +481,11 @@ SearchArgs tile_args(sdf_index_s *ix, const Params &P, const Prepared &pr, uint3
     a.err = work + 1;
     a.phase = phase;
     a.runs_out = runs_out;
+    a.dense = dense;
+    a.dense_cap = dense_cap;
+    // test hook: SDF_KEPT_CAP lowers the kept hits a partition may hold, so
+    // that ordinary windows take the dense-window pass
+    a.kept_cap = env_u32("SDF_KEPT_CAP", 0xFFFFFFFFu);
     return a;
 }
 
@@ -507,13 +520,16 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
     const bool phase_prof = env_u32("SDF_PHASE_PROF", 0) != 0;
     unsigned long long hc[CNT_N] = {};
     uint32_t herr = 0;
+    const uint64_t dense_cap = dense_capacity(qbases);
+    DevBuf<uint64_t> dense(dense_cap);
     for (int attempt = 0; attempt < 3; attempt++) {
         res->seeds.alloc(cap * 6);
         fill_u32(reinterpret_cast<uint32_t *>(zblock.p), 0u, zblock.n * 2, st);
         if (nq) {
             const SearchArgs a = tile_args(ix, P, pr, nq, res->seeds.p, cap, counters, work,
                                            phase_prof ? phase : nullptr,
-                                           (p->flags & SDF_SEED_ESTIMATE) ? 1u : 0u);
+                                           (p->flags & SDF_SEED_ESTIMATE) ? 1u : 0u, dense.p,
+                                           dense_cap);
             tm.mark_kernel_begin();
             launch_tile(pr, a, st);
             tm.mark_kernel_end();
@@ -533,11 +549,18 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
     if (!herr && hc[CNT_SEEDS] > cap) throw Error{SDF_EINTERNAL, "seed buffer kept overflowing"};
     if (herr) {
         std::string m = "tile search capacity exceeded:";
-        if (herr & 1) m += " a window reaches more minimizers than a tile holds;";
-        if (herr & 2) m += " a dense target region keeps more hits than a tile holds;";
-        if (herr & 4) m += " a dense target region has more than 65535 hits;";
         if (herr & 8) m += " partition splitting ran out of stack;";
+        if (herr & 16) m += " more windows too dense for a tile than their list holds;";
         throw Error{SDF_EINTERNAL, m};
+    }
+    if (hc[CNT_DENSE]) {
+        // windows too dense for a tile: their seeds are recomputed in global memory
+        if (p->flags & SDF_SEED_ESTIMATE)
+            throw Error{SDF_EINTERNAL, "seeds by the estimate: a window is too dense for a tile"};
+        uint64_t ns = hc[CNT_SEEDS];
+        resolve_dense(ix->view(), pr.dsd, pr.dT, P.n, P.max_overlap, dense.p, hc[CNT_DENSE],
+                      res->seeds, ns, counters + CNT_SEEDS, st);
+        hc[CNT_SEEDS] = ns;
     }
     if (phase_prof) {
         // per-phase wall-clock ticks summed over workgroups (diagnostic)
@@ -655,9 +678,12 @@ void enqueue_plan(sdf_plan_s *pl, hipStream_t st) {
     unsigned long long *const counters = zblock.p;
     uint32_t *const work = reinterpret_cast<uint32_t *>(zblock.p + CNT_N + PH_N);
     DevBuf<uint32_t> seeds(pl->ns_cap * 6);
+    const uint64_t dense_cap = dense_capacity(pr.qbases);
+    DevBuf<uint64_t> dense(dense_cap);
     fill_u32(reinterpret_cast<uint32_t *>(zblock.p), 0u, zblock.n * 2, st);
     if (nq)
-        launch_tile(pr, tile_args(ix, P, pr, nq, seeds.p, pl->ns_cap, counters, work, nullptr, 0u),
+        launch_tile(pr, tile_args(ix, P, pr, nq, seeds.p, pl->ns_cap, counters, work, nullptr, 0u,
+                                  dense.p, dense_cap),
                     st);
     ChainOut co;
     chain_seeds(ix->view(), seeds.p, DevCount{counters + CNT_SEEDS, pl->ns_cap}, P.n,
@@ -1154,9 +1180,10 @@ sdf_status sdf_plan_run(sdf_plan pl, void *hip_stream, sdf_result *out) {
         r->st = st;
         r->core = pl->core;
         r->threads = pl->threads;
-        if (h[CNT_N] || ns > pl->ns_cap || nc > pl->nc_cap) {
-            // an error the search reports as it is, or counts past the
-            // graph's buffers: the search runs again without the graph
+        if (h[CNT_N] || h[CNT_DENSE] || ns > pl->ns_cap || nc > pl->nc_cap) {
+            // an error the search reports as it is, windows too dense for a
+            // tile (their pass reads counts back), or counts past the graph's
+            // buffers: the search runs again without the graph
             pl->fallbacks++;
             run_search(pl->ix, pl->spans.data(), (uint32_t)pl->spans.size(), &pl->params, st, r);
         } else {

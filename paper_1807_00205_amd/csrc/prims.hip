@@ -68,6 +68,11 @@ ArenaScope::~ArenaScope() { t_arena = prev; }
 // pinned staging and host uploads are then avoided as well.
 bool in_arena() { return t_arena != nullptr && t_arena->mode == Arena::CARVE; }
 
+size_t arena_mark() { return in_arena() ? t_arena->used : 0; }
+void arena_release(size_t mark) {
+    if (in_arena() && mark <= t_arena->used) t_arena->used = mark;
+}
+
 void release_blocks(Arena &a) {
     for (const auto &b : a.blocks) pool_free(b.first);
     a.blocks.clear();
@@ -407,6 +412,9 @@ void scan_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n, hipStream_t 
 }
 void scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, hipStream_t st) {
     scan_impl<uint32_t, uint32_t>(in, out, n, st);
+}
+void scan_u64(const uint64_t *in, uint64_t *out, uint64_t n, hipStream_t st) {
+    scan_impl<uint64_t, uint64_t>(in, out, n, st);
 }
 
 // ------------------------------------------------------------ radix sort --

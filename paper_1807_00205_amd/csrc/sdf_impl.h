@@ -59,6 +59,11 @@ struct ArenaScope {
     ~ArenaScope();
 };
 bool in_arena();
+// Inside a carving arena: the bytes in use, and going back to such a mark
+// (every block carved after it must be released already).  0 and no-op
+// otherwise.
+size_t arena_mark();
+void arena_release(size_t mark);
 void pool_free(void *p);
 void pool_trim();
 hipStream_t current_stream();
@@ -168,6 +173,8 @@ struct DevCount {
 void scan_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n, hipStream_t st);
 // Exclusive prefix sum, u32 in, u32 out (caller guarantees no overflow); out[n] = total.
 void scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, hipStream_t st);
+// Exclusive prefix sum of u64 values; out[n] = total.
+void scan_u64(const uint64_t *in, uint64_t *out, uint64_t n, hipStream_t st);
 // Stable LSD radix sort of (key, value) pairs on key bits [0, bits).
 void radix_sort_u32(uint32_t *keys, uint32_t *vals, uint64_t n, int bits, hipStream_t st);
 void radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t n, int bits, hipStream_t st);

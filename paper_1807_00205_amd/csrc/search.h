@@ -32,7 +32,7 @@ struct SpanDesc {
 };
 
 enum { CNT_SEEDS = 0, CNT_WINDOWS, CNT_HITS, CNT_KEPT, CNT_PARTS, CNT_TILES, CNT_EVALS,
-       CNT_SCAN, CNT_DUP_TILES, CNT_N };
+       CNT_SCAN, CNT_DUP_TILES, CNT_DENSE, CNT_N };
 
 struct SearchArgs {
     IndexView ix;
@@ -51,7 +51,20 @@ struct SearchArgs {
     uint32_t *err;
     unsigned long long *phase;     // PH_N wall-clock ticks per phase, or null
     uint32_t runs_out;       // 1: emit each run (first j, last j in the c field) instead of its seed
+    uint64_t *dense;         // windows too dense for a tile: query id << 32 | first minimizer
+    uint64_t dense_cap;      // entries of `dense` (counted in counters[CNT_DENSE])
+    uint32_t kept_cap;       // kept hits a partition may hold (at most the layout's)
 };
+
+// Windows listed by the tile kernel as too dense for a tile (a window that
+// keeps more hits than a tile holds within 4n target bases, or reaches more
+// minimizers than a tile holds): their seeds from the tile kernel are
+// dropped and recomputed in global memory (dense.hip); seeds and nseeds are
+// replaced, and *dcount (the device seed count) updated.
+void resolve_dense(const IndexView &ix, const SpanDesc *spans, const uint16_t *T, uint32_t n,
+                   uint32_t max_overlap, const uint64_t *dense, uint64_t nd,
+                   DevBuf<uint32_t> &seeds, uint64_t &nseeds, unsigned long long *dcount,
+                   hipStream_t st);
 
 // Phases of the tile kernel for the optional wall-clock breakdown.
 enum { PH_SETUP = 0, PH_QUERY, PH_LISTS, PH_PLISTS, PH_PASS1, PH_PASS2, PH_SORT, PH_HOT,

@@ -77,10 +77,10 @@ static_assert(QCAP <= 2048, "EI_Q field width");
 // others are left out (QM_SKIP).
 enum : uint8_t { QM_NORMAL = 0, QM_SKIP = 1, QM_UNION = 2 };
 enum : uint32_t {
-    ERR_CORE = 1,      // one window alone reaches more than QCAP minimizers
-    ERR_COLLECT = 2,   // one window keeps more than CB hits in 4n target bases
-    ERR_HITS = 4,      // one window has more than HMAX hits in 4n target bases
-    ERR_STACK = 8      // partition splits nested deeper than the stack
+    ERR_COLLECT = 2,     // (a partition keeps more than CB hits: split, or listed as dense)
+    ERR_HITS = 4,        // (a partition has more than HMAX hits: split, or listed as dense)
+    ERR_STACK = 8,       // partition splits nested deeper than the stack
+    ERR_DENSE_FULL = 16  // more dense windows than the list holds
 };
 
 struct RunState {
@@ -121,6 +121,7 @@ struct TileLds {
     uint32_t obeg[2], oend[2];
     uint32_t sp;
     uint32_t err;
+    uint32_t skip;
     uint64_t gb, ge;
     uint32_t qid, qseq;
     // work counters of this workgroup, added to the global ones once at exit
@@ -447,11 +448,20 @@ __device__ __forceinline__ void gather_hits(const TileLds &L, const IndexView &i
     }
 }
 
+// A window the tile cannot hold goes to the list of dense windows (once)
+// and takes no further part in this tile.
+__device__ __forceinline__ void list_dense(const SearchArgs &a, TileLds &L, uint32_t m) {
+    const unsigned long long d = atomicAdd(&a.counters[CNT_DENSE], 1ull);
+    if (d < a.dense_cap) a.dense[d] = ((uint64_t)L.qid << 32) | m;
+    else L.err |= ERR_DENSE_FULL;
+}
+
 // Push the halves of an over-full partition [A, B) x windows [WA, WB): by
 // target while it spans more than 4n bases, else by window starts; the
-// lower half goes on top.  Sets `err` when neither split is possible.
-__device__ __forceinline__ void split_partition(TileLds &L, uint32_t A, uint32_t B, uint32_t WA,
-                                                uint32_t WB, uint32_t n, uint32_t err) {
+// lower half goes on top.  A single window that cannot be split further is
+// listed as dense.
+__device__ __forceinline__ void split_partition(const SearchArgs &a, TileLds &L, uint32_t A,
+                                                uint32_t B, uint32_t WA, uint32_t WB, uint32_t n) {
     if (L.sp + 2 > STACK) {
         L.err |= ERR_STACK;
     } else if ((uint64_t)B - A > 4ull * n) {
@@ -462,8 +472,9 @@ __device__ __forceinline__ void split_partition(TileLds &L, uint32_t A, uint32_t
         const uint32_t mid = WA + (WB - WA) / 2;
         L.stackA[L.sp] = A; L.stackB[L.sp] = B; L.stackW[L.sp] = mid | (WB << 16); L.sp++;
         L.stackA[L.sp] = A; L.stackB[L.sp] = B; L.stackW[L.sp] = WA | (mid << 16); L.sp++;
-    } else {
-        L.err |= err;
+    } else if (L.win_T[WA]) {
+        list_dense(a, L, L.c0 + WA);
+        L.win_T[WA] = 0;  // no candidates, no runs: its seeds come from the dense pass
     }
 }
 
@@ -643,7 +654,12 @@ k_tile_search(SearchArgs a) {
                 }
                 L.c0 = c_begin;
                 L.c1 = c1;
-                L.err = (qe > QCAP) ? ERR_CORE : 0u;
+                L.err = 0;
+                L.skip = qe > QCAP;  // one window alone reaches more minimizers than a tile holds
+                if (L.skip) {
+                    list_dense(a, L, c_begin);
+                    if (L.err) atomicOr(a.err, L.err);
+                }
                 L.Q = min<uint32_t>(qe, QCAP);
                 L.C = c1 - c_begin;
                 L.nwin = 0;
@@ -653,8 +669,7 @@ k_tile_search(SearchArgs a) {
             __syncthreads();
             PHASE(PH_SETUP);
             const uint32_t c0 = L.c0, Q = L.Q, C = L.C;
-            if (L.err) {
-                if (threadIdx.x == 0) atomicOr(a.err, L.err);
+            if (L.skip) {
                 c_begin = L.c1;
                 __syncthreads();
                 continue;
@@ -848,7 +863,7 @@ k_tile_search(SearchArgs a) {
                 const uint32_t H = L.hoff[nl];
                 if (H == 0) continue;
                 if (H > HMAX) {
-                    if (threadIdx.x == 0) split_partition(L, A, B, WA, WB, n, ERR_HITS);
+                    if (threadIdx.x == 0) split_partition(a, L, A, B, WA, WB, n);
                     __syncthreads();
                     if (L.err) break;
                     continue;
@@ -950,8 +965,8 @@ k_tile_search(SearchArgs a) {
                 PHASE(PH_PASS2);
                 const uint32_t ncoll = L.ncoll;
                 if (ncoll == 0) continue;
-                if (ncoll > CB) {
-                    if (threadIdx.x == 0) split_partition(L, A, B, WA, WB, n, ERR_COLLECT);
+                if (ncoll > min(a.kept_cap, (uint32_t)CB)) {
+                    if (threadIdx.x == 0) split_partition(a, L, A, B, WA, WB, n);
                     __syncthreads();
                     if (L.err) break;
                     continue;

@@ -532,3 +532,83 @@ def test_autotune_keeps_results(S):
     _same(r1.seeds(), s0, SEED_F, "seeds after autotune")
     _same(r1.candidates(), c0, CAND_F, "candidates after autotune")
     assert ix.autotune([])[0] == 0
+
+
+def _dense_genome(seed):
+    """Random sequence with an uppercase homopolymer of 5 kbp, an (AC)n array
+    of 5 kbp and a copy of part of it, plus a second sequence: windows whose
+    hits are far denser than a tile holds (every position of a homopolymer
+    is a minimizer of the same hash, every other one of an (AC)n array)."""
+    rng = synth.rng_for(seed)
+    a = synth.random_bases(rng, 30_000)
+    a[4000:9000] = ord("A")
+    a[14000:19000] = np.frombuffer(b"AC" * 2500, np.uint8)
+    b = synth.random_bases(rng, 12_000)
+    b[2000:4000] = np.frombuffer(b"AC" * 1000, np.uint8)
+    b[7000:7600] = ord("T")
+    return [a, b]
+
+
+DENSE_SPANS = [(0, 4500, 5700), (0, 14500, 15900), (1, 1500, 4500), (0, 8000, 14500),
+               (1, 6000, 12000)]
+
+
+@pytest.fixture(scope="module")
+def dense_case(oracle_lib):
+    import os
+    seqs = _dense_genome(3)
+    b = np.concatenate(seqs)
+    off = np.array([0, len(seqs[0]), len(b)], np.uint64)
+    orc = oracle_lib.OracleIndex(b, off, 12, 16)
+    os_, oc = orc.search(DENSE_SPANS, 0.25, 1000, min(16, os.cpu_count() or 1))
+    orc.close()
+    return seqs, os_, oc
+
+
+@pytest.mark.parametrize("threads", ["512", "1024"])
+def test_dense_windows(S, dense_case, monkeypatch, threads):
+    """Windows too dense for a tile (inside a 5 kbp uppercase homopolymer
+    and (AC)n arrays: every position, or every other one, is a minimizer of
+    one hash) go through the dense-window pass: seeds and candidates equal
+    the oracle's in both tile layouts, and in the no-allocation search."""
+    monkeypatch.setenv("SDF_TILE_THREADS", threads)
+    seqs, os_, oc = dense_case
+    ix = S.Index(seqs, 12, 16)
+    r = ix.search_batch(DENSE_SPANS)
+    _same(r.seeds(), os_, SEED_F, "seeds")
+    _same(r.candidates(), oc, CAND_F, "candidates")
+    assert len(oc) > 0
+    got, n = ix.search_batch_noalloc(DENSE_SPANS)
+    _same(got, oc, CAND_F, "no-allocation search")
+
+
+@pytest.mark.parametrize("threads", ["512", "1024"])
+def test_dense_pass_forced(S, oracle_lib, monkeypatch, threads):
+    """With the kept-hit limit of a tile lowered to 64, ordinary windows of
+    mixed and tandem inputs become dense: the dense-window pass gives the
+    oracle's seeds and candidates for them."""
+    monkeypatch.setenv("SDF_TILE_THREADS", threads)
+    monkeypatch.setenv("SDF_KEPT_CAP", "64")
+    for g in (synth.tandem_case(7, length=20_000, n_seqs=2), _mixed_genome(9, 8000)):
+        b, off = g.concat()
+        ix = S.Index(g.seqs, 12, 16)
+        orc = oracle_lib.OracleIndex(b, off, 12, 16)
+        r = ix.search_batch(g.spans, 0.25, 200)
+        os_, oc = orc.search(g.spans, 0.25, 200)
+        _same(r.seeds(), os_, SEED_F, "seeds")
+        _same(r.candidates(), oc, CAND_F, "candidates")
+
+
+def test_windows_longer_than_a_tile(S, oracle_lib):
+    """A seed window of 11,250 bases reaches more minimizers than a tile
+    holds: every window goes through the dense-window pass."""
+    g = synth.small_case(41, length=30_000, n_sd=2, sd_lo=12_000, sd_hi=13_000, n_seqs=2,
+                         rate_hi=0.04)
+    b, off = g.concat()
+    ix = S.Index(g.seqs, 12, 16)
+    orc = oracle_lib.OracleIndex(b, off, 12, 16)
+    r = ix.search_batch(g.spans, 0.25, 15000)
+    os_, oc = orc.search(g.spans, 0.25, 15000)
+    _same(r.seeds(), os_, SEED_F, "seeds")
+    _same(r.candidates(), oc, CAND_F, "candidates")
+    assert len(oc) > 0

@@ -275,6 +275,17 @@ sdf_status sdf_result_regions(sdf_result r, sdf_region *dst, uint64_t cap, uint6
 sdf_status sdf_search_batch(sdf_index ix, const sdf_span *qs, uint32_t n,
                             const sdf_search_params *p, void *hip_stream, sdf_result *out);
 
+/* sdf_search_batch within a device-memory reservation (a serving loop
+ * admits each request with the bytes it reserved): the search allocates at
+ * most max_device_bytes of device memory at any one time (its result's
+ * buffers included) and fails with SDF_ENOMEM, leaving nothing behind, when
+ * it would need more; the seed buffer is never regrown past the
+ * reservation.  *peak_bytes (may be NULL) receives the most the search held
+ * at once, also on failure.  Other errors as for sdf_search_batch. */
+sdf_status sdf_search_batch_capped(sdf_index ix, const sdf_span *qs, uint32_t n,
+                                   const sdf_search_params *p, uint64_t max_device_bytes,
+                                   void *hip_stream, sdf_result *out, uint64_t *peak_bytes);
+
 /* Autotuner of the tile schedule: runs the search of the n spans (host
  * array, as for sdf_search_batch, with p's error bound and length; the
  * timing, estimate and extension flags are ignored) with every schedule in

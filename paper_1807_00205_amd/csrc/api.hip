@@ -451,11 +451,15 @@ void prepare(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const Params &P, 
                               std::max<uint64_t>(tile_bound, 1)));
 }
 
-// Entries of the list of windows too dense for a tile: up to one per query
-// base (a homopolymer has a minimizer at every position), at most 2^22
-// (2^19 inside a fixed scratch area).
-uint64_t dense_capacity(uint64_t qbases) {
-    return std::min<uint64_t>(qbases + 1024, in_arena() ? (1ull << 19) : (1ull << 22));
+constexpr uint32_t ERR_DENSE_LIST = 16;  // the tile kernel's dense-window list overflowed
+
+// Entries of the list of windows too dense for a tile: one per 16 query
+// bases at first (such windows are rare), one per base when that overflows
+// (a homopolymer has a minimizer at every position); at most 2^22 (2^19
+// inside a fixed scratch area).
+uint64_t dense_capacity(uint64_t qbases, bool full = false) {
+    const uint64_t c = full ? qbases + 1024 : qbases / 16 + 1024;
+    return std::min<uint64_t>(c, in_arena() ? (1ull << 19) : (1ull << 22));
 }
 
 // Arguments of the tile kernel for a prepared search.
@@ -520,7 +524,7 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
     const bool phase_prof = env_u32("SDF_PHASE_PROF", 0) != 0;
     unsigned long long hc[CNT_N] = {};
     uint32_t herr = 0;
-    const uint64_t dense_cap = dense_capacity(qbases);
+    uint64_t dense_cap = dense_capacity(qbases);
     DevBuf<uint64_t> dense(dense_cap);
     for (int attempt = 0; attempt < 3; attempt++) {
         res->seeds.alloc(cap * 6);
@@ -540,6 +544,13 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
             rb.add(&herr, work + 1, 4);
             if (nq) rb.add(&total_tiles, tile0.p + nq, 4);
             rb.wait();
+        }
+        if (herr == ERR_DENSE_LIST && dense_cap < dense_capacity(qbases, true)) {
+            // more dense windows than the short list holds: once more with room
+            dense_cap = dense_capacity(qbases, true);
+            dense.alloc(dense_cap);
+            herr = 0;
+            continue;
         }
         if (herr) break;
         if (hc[CNT_SEEDS] <= cap) break;
@@ -840,6 +851,37 @@ sdf_status sdf_search_batch(sdf_index ix, const sdf_span *qs, uint32_t n,
         run_search(ix, qs, n, p, (hipStream_t)hip_stream, r);
         *out = r;
     });
+    if (rc != SDF_OK && r) {
+        (void)hipStreamSynchronize((hipStream_t)hip_stream);  // queued work may use r's buffers
+        delete r;
+    }
+    return rc;
+}
+
+sdf_status sdf_search_batch_capped(sdf_index ix, const sdf_span *qs, uint32_t n,
+                                   const sdf_search_params *p, uint64_t max_device_bytes,
+                                   void *hip_stream, sdf_result *out, uint64_t *peak_bytes) {
+    if (out) *out = nullptr;
+    if (peak_bytes) *peak_bytes = 0;
+    sdf_result_s *r = nullptr;
+    Arena ar;
+    ar.mode = Arena::LIMIT;
+    ar.cap = max_device_bytes;
+    sdf_status rc = guarded([&] {
+        if (!ix || !out) throw Error{SDF_EINVAL, "NULL argument"};
+        if (n && !qs) throw Error{SDF_EINVAL, "NULL spans"};
+        SDF_HIP(hipSetDevice(ix->device));
+        StreamScope scope((hipStream_t)hip_stream);
+        r = new sdf_result_s();
+        r->device = ix->device;
+        r->st = (hipStream_t)hip_stream;
+        {
+            ArenaScope as(&ar);
+            run_search(ix, qs, n, p, (hipStream_t)hip_stream, r);
+        }
+        *out = r;
+    });
+    if (peak_bytes) *peak_bytes = ar.peak;
     if (rc != SDF_OK && r) {
         (void)hipStreamSynchronize((hipStream_t)hip_stream);  // queued work may use r's buffers
         delete r;

@@ -96,6 +96,26 @@ void *pool_alloc(size_t bytes) {
         a->blocks.push_back({p, bytes});
         return p;
     }
+    if (t_arena && t_arena->mode == Arena::LIMIT) {
+        Arena *a = t_arena;
+        const size_t c = size_class(bytes);
+        if (c > a->cap - std::min(a->cap, a->used))
+            throw Error{SDF_ENOMEM, "the search needs more device memory than the " +
+                                        std::to_string(a->cap) + " bytes it was given"};
+        t_arena = nullptr;
+        void *p = nullptr;
+        try {
+            p = pool_alloc_raw(bytes);
+        } catch (...) {
+            t_arena = a;
+            throw;
+        }
+        t_arena = a;
+        a->used += c;
+        if (a->used > a->peak) a->peak = a->used;
+        a->blocks.push_back({p, c});
+        return p;
+    }
     if (t_arena && t_arena->mode == Arena::REPLAY) {
         if (t_arena->next >= t_arena->blocks.size() || t_arena->blocks[t_arena->next].second != bytes)
             throw Error{SDF_EINTERNAL, "captured launch sequence asked for other buffers than "
@@ -151,7 +171,15 @@ void pool_free(void *p) {
     if (t_arena && t_arena->mode == Arena::CARVE && (unsigned char *)p >= t_arena->base &&
         (unsigned char *)p < t_arena->base + t_arena->cap)
         return;  // arena blocks are released with the scope
-    if (t_arena && t_arena->mode != Arena::CARVE) {
+    if (t_arena && t_arena->mode == Arena::LIMIT) {
+        for (size_t i = 0; i < t_arena->blocks.size(); i++)
+            if (t_arena->blocks[i].first == p) {
+                t_arena->used -= t_arena->blocks[i].second;
+                t_arena->blocks[i] = t_arena->blocks.back();
+                t_arena->blocks.pop_back();
+                break;
+            }
+    } else if (t_arena && t_arena->mode != Arena::CARVE) {
         for (const auto &b : t_arena->blocks)
             if (b.first == p) return;  // kept by the arena's owner
     }

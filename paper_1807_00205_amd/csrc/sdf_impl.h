@@ -46,7 +46,9 @@ void *pool_alloc(size_t bytes);
 // again in the same order (a launch sequence being captured into a graph
 // gets the very buffers its rehearsal used, without allocating).
 struct Arena {
-    enum Mode { CARVE, RECORD, REPLAY } mode = CARVE;
+    // LIMIT: blocks come from the pool as usual, but the bytes live at once
+    // may not pass `cap` (SDF_ENOMEM); `peak` records the most ever live.
+    enum Mode { CARVE, RECORD, REPLAY, LIMIT } mode = CARVE;
     unsigned char *base = nullptr;
     size_t cap = 0, used = 0, peak = 0;
     std::vector<std::pair<void *, size_t>> blocks;

@@ -41,7 +41,7 @@ EXPORTS = ["sdf_last_error", "sdf_index_build", "sdf_index_info", "sdf_index_hit
            "sdf_result_seeds", "sdf_result_timing", "sdf_result_stats", "sdf_result_free",
            "sdf_extend", "sdf_result_regions", "sdf_qgram_filter", "sdf_autotune",
            "sdf_search_batch_noalloc", "sdf_plan_create", "sdf_plan_run", "sdf_plan_info",
-           "sdf_plan_free"]
+           "sdf_plan_free", "sdf_search_batch_capped"]
 NOALLOC_SCRATCH_BYTES = 128 << 20
 NOALLOC_MAX_SPANS = 65536
 NOALLOC_MAX_QUERY_BASES = 8_000_000
@@ -191,6 +191,9 @@ def lib() -> ctypes.CDLL:
         L.sdf_qgram_filter.argtypes = [vp, vp, u64, P(_QgramParams), vp, vp, vp]
         L.sdf_result_regions.restype = st
         L.sdf_result_regions.argtypes = [vp, vp, u64, P(u64)]
+        L.sdf_search_batch_capped.restype = st
+        L.sdf_search_batch_capped.argtypes = [vp, vp, u32, P(_SearchParams), u64, vp, P(vp),
+                                              P(u64)]
         L.sdf_plan_create.restype = st
         L.sdf_plan_create.argtypes = [vp, vp, u32, P(_SearchParams), P(_PlanParams), vp, P(vp)]
         L.sdf_plan_run.restype = st
@@ -485,6 +488,20 @@ class Index:
                                               out.ctypes.data_as(ctypes.c_void_p), cap,
                                               ctypes.byref(n)))
         return out[:min(cap, n.value)].copy(), n.value
+
+    def search_batch_capped(self, spans: Iterable[Tuple[int, int, int]], max_bytes: int,
+                            max_error: float = 0.25, min_len: int = 1000, stream=None):
+        """``sdf_search_batch`` within a device-memory reservation of
+        ``max_bytes``: returns (Result, peak bytes held); raises SdfError with
+        SDF_ENOMEM when the search would need more."""
+        arr, nspans = _span_array(spans)
+        p = _SearchParams(max_error, min_len, 0)
+        h = ctypes.c_void_p()
+        peak = ctypes.c_uint64()
+        _check(lib().sdf_search_batch_capped(self._h, arr.ctypes.data_as(ctypes.c_void_p), nspans,
+                                             ctypes.byref(p), max_bytes, _stream_ptr(stream),
+                                             ctypes.byref(h), ctypes.byref(peak)))
+        return Result(h.value), peak.value
 
     def plan(self, spans: Iterable[Tuple[int, int, int]], max_error: float = 0.25,
              min_len: int = 1000, seed_cap: int = 0, cand_cap: int = 0, stream=None) -> Plan:

@@ -1,11 +1,24 @@
 """Continuous-batching search server over a resident index.
 
-Requests (query spans) arrive at any time.  Worker threads, each owning one
-HIP stream, repeatedly take every queued request that fits the free-HBM
-budget and run them as one batched search; requests that arrive while
-batches are on the GPU join the next batch of the first worker that frees
-up, so several batches overlap on the device.  Every request's result is
-the candidate set of its span alone (query ids are local to the request).
+Requests (query spans) arrive at any time.  Each request reserves device
+memory for its search; a request is admitted when its reservation fits the
+HBM budget next to the reservations of the requests already on the GPU.
+Worker threads, each owning one HIP stream, take every queued request that
+fits and run them as one batched search, so requests that arrive while
+others are on the GPU join the next batch and batches of different workers
+overlap on the device.  The library holds each batched search to the sum of
+its requests' reservations (``sdf_search_batch_capped``): a search never
+takes more device memory than was admitted.  A batch that would need more
+fails without allocating it; its requests go back to the head of the queue
+with four times their reservation.  Every request's result is the candidate
+set of its span alone (query ids are local to the request).
+
+Reservations start from an estimate per query base and are kept at least
+1.25 times the most any finished search needed per base: the device memory
+of a search grows with its seeds, which cannot be bounded usefully in
+advance (a hit can start a seed in every window that holds its minimizer,
+so the count of hits times the windows per minimizer overshoots the real
+need by one to three orders of magnitude).
 
 The plain mode (``workers=1, max_batch=1``) is the one-request-at-a-time
 FIFO baseline.
@@ -22,13 +35,13 @@ import numpy as np
 
 from . import sdf
 
+MIN_RESERVE = 8 << 20       # bytes reserved for any request
+START_BYTES_PER_BASE = 40.0  # first estimate, raised by what searches report
 
-def request_bytes(span_len: int) -> int:
-    """Upper bound on the device memory one request adds to a batch: its seed
-    buffer (one seed per 8 query bases plus slack, 24 B each) and the
-    chaining scratch (about five times the seed buffer)."""
-    seeds = span_len // 8 + 65536
-    return seeds * 24 * 6
+
+def request_bytes(span_len: int, per_base: float = START_BYTES_PER_BASE) -> int:
+    """Device memory reserved for one request of span_len query bases."""
+    return max(MIN_RESERVE, int(span_len * per_base))
 
 
 _STREAMS: dict = {}
@@ -49,15 +62,15 @@ def worker_streams(n: int):
 class Request:
     __slots__ = ("span", "arrival", "future", "bytes")
 
-    def __init__(self, span, arrival):
+    def __init__(self, span, arrival, nbytes):
         self.span = span
         self.arrival = arrival
         self.future = Future()
-        self.bytes = request_bytes(span[2] - span[1])
+        self.bytes = nbytes
 
 
 class Server:
-    def __init__(self, index: sdf.Index, workers: int = 4, max_batch: int = 4096,
+    def __init__(self, index: sdf.Index, workers: int = 2, max_batch: int = 4096,
                  hbm_budget: Optional[int] = None, max_error: float = 0.25,
                  min_len: int = 1000):
         import torch
@@ -68,11 +81,13 @@ class Server:
             free, _ = torch.cuda.mem_get_info()
             hbm_budget = int(free * 0.5)
         self.budget = hbm_budget
+        self.per_base = START_BYTES_PER_BASE
         self.in_flight = 0
         self.queue: collections.deque = collections.deque()
         self.cv = threading.Condition()
         self.stop = False
-        self.batches = []  # (size, seconds) per batch
+        self.batches = []   # (size, seconds) per batch
+        self.retries = 0    # batches that needed more than their reservation
         self.streams = worker_streams(workers)
         self.threads = [threading.Thread(target=self._work, args=(s,), daemon=True)
                         for s in self.streams]
@@ -80,7 +95,9 @@ class Server:
             t.start()
 
     def submit(self, span: Tuple[int, int, int], arrival: Optional[float] = None) -> Future:
-        r = Request(span, time.perf_counter() if arrival is None else arrival)
+        with self.cv:
+            nbytes = request_bytes(span[2] - span[1], self.per_base)
+        r = Request(span, time.perf_counter() if arrival is None else arrival, nbytes)
         if r.bytes > self.budget:
             r.future.set_exception(MemoryError("request exceeds the HBM budget"))
             return r.future
@@ -113,9 +130,13 @@ class Server:
             if not batch:
                 continue
             t0 = time.perf_counter()
+            reserved = sum(r.bytes for r in batch)
+            retry = []
+            peak = 0
             try:
-                res = self.index.search_batch([r.span for r in batch], self.max_error,
-                                              self.min_len, stream=stream)
+                res, peak = self.index.search_batch_capped(
+                    [r.span for r in batch], reserved, self.max_error, self.min_len,
+                    stream=stream)
                 c = res.candidates()
                 res.close()
                 done = time.perf_counter()
@@ -126,14 +147,32 @@ class Server:
                     mine = c[bounds[q]:bounds[q + 1]].copy()
                     mine["query_id"] = 0
                     r.future.set_result((mine, done))
+            except sdf.SdfError as e:
+                done = time.perf_counter()
+                if e.code == sdf.SDF_ENOMEM:
+                    retry = batch  # nothing was kept: admitted again with more room
+                else:
+                    for r in batch:
+                        r.future.set_exception(e)
             except Exception as e:  # isolate failures per batch
+                done = time.perf_counter()
                 for r in batch:
                     if not r.future.done():
                         r.future.set_exception(e)
-                done = time.perf_counter()
             with self.cv:
-                self.in_flight -= sum(r.bytes for r in batch)
+                self.in_flight -= reserved
                 self.batches.append((len(batch), done - t0))
+                bases = sum(r.span[2] - r.span[1] for r in batch)
+                if peak and not retry and bases:
+                    self.per_base = max(self.per_base, 1.25 * peak / bases)
+                if retry:
+                    self.retries += 1
+                    for r in reversed(retry):
+                        r.bytes *= 4
+                        if r.bytes > self.budget:
+                            r.future.set_exception(MemoryError("request exceeds the HBM budget"))
+                        else:
+                            self.queue.appendleft(r)
                 self.cv.notify_all()
 
     def close(self):
@@ -177,4 +216,5 @@ def measure(index: sdf.Index, requests, workers: int, max_batch: int, **kw):
             "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "mbp_per_s": bases / wall / 1e6 if wall > 0 else 0.0,
             "requests": len(lat), "batches": len(sizes),
-            "mean_batch": float(np.mean(sizes)) if sizes else 0.0}
+            "mean_batch": float(np.mean(sizes)) if sizes else 0.0,
+            "retries": srv.retries, "bytes_per_base": round(srv.per_base, 2)}

@@ -515,6 +515,46 @@ def test_serving_admission_budget(S, batch250):
     assert max(b for b, _ in srv.batches) == 1
 
 
+def test_capped_search_honours_reservation(S, batch250):
+    """The batched search within a device-memory reservation: the same
+    candidates as without one, at most the reserved bytes held, and
+    SDF_ENOMEM (nothing kept, the index still usable) below what it needs."""
+    g, ix = batch250
+    spans = g.spans[:64]
+    want = ix.search_batch(spans).candidates()
+    r, peak = ix.search_batch_capped(spans, 1 << 30)
+    _same(r.candidates(), want, CAND_F, "capped")
+    r.close()
+    assert 0 < peak <= 1 << 30
+    with pytest.raises(S.SdfError) as e:
+        ix.search_batch_capped(spans, peak // 2)
+    assert e.value.code == S.SDF_ENOMEM
+    r, peak2 = ix.search_batch_capped(spans, peak)
+    _same(r.candidates(), want, CAND_F, "capped at its peak")
+    assert peak2 == peak
+    _same(ix.search_batch(spans).candidates(), want, CAND_F, "after the failure")
+
+
+def test_serving_retries_small_reservations(S, batch250, monkeypatch):
+    """Reservations far below what the searches need: batches fail without
+    allocating, their requests are admitted again with more room, and every
+    result still equals the span searched alone."""
+    from paper_1807_00205_amd import serve
+    g, ix = batch250
+    monkeypatch.setattr(serve, "MIN_RESERVE", 1 << 16)
+    monkeypatch.setattr(serve, "START_BYTES_PER_BASE", 0.05)
+    reqs = synth.draw_spans(synth.rng_for(6), [len(g.seqs[0])], 12, 2000, 400_000)
+    srv = serve.Server(ix, workers=2, max_batch=8)
+    try:
+        futs = [srv.submit(sp) for sp in reqs]
+        got = [f.result(timeout=120)[0] for f in futs]
+    finally:
+        srv.close()
+    assert srv.retries > 0
+    for sp, mine in zip(reqs, got):
+        _same(mine, ix.search(sp).candidates(), CAND_F, "span %s" % (sp,))
+
+
 def test_autotune_keeps_results(S):
     """sdf_autotune times every tile schedule (both workgroup layouts) on a
     span set and keeps the fastest; searches after it return the same seeds

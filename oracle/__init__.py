@@ -18,6 +18,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sdf_oracle.c")
+_SRC2 = os.path.join(_HERE, "sd_align.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 SEED_DTYPE = np.dtype([("query_id", "<u4"), ("i", "<u4"), ("j", "<u4"),
@@ -27,18 +28,34 @@ SEED_DTYPE = np.dtype([("query_id", "<u4"), ("i", "<u4"), ("j", "<u4"),
 EXT_DTYPE = np.dtype([("q_begin", "<u8"), ("q_end", "<u8"), ("t_begin", "<u8"),
                       ("t_end", "<u8"), ("m", "<u8"), ("s", "<u8"), ("stop", "<u8")])
 EXT_BOUND, EXT_CAP, EXT_OVERLAP, EXT_ESTIMATE = 1, 2, 3, 4
+# A final SD (Section 3.3): region index, strand, sequences and per-sequence
+# coordinates (BEDPE), alignment counts, distances, and its CIGAR operations
+# (len << 4 | op; op 7 '=', 8 'X', 1 'I', 2 'D') at [cigar_off, +cigar_len).
+SD_DTYPE = np.dtype([("region", "<u8"), ("strand", "<u4"), ("q_seq", "<u4"), ("t_seq", "<u4"),
+                     ("_pad", "<u4"), ("q_begin", "<u8"), ("q_end", "<u8"), ("t_begin", "<u8"),
+                     ("t_end", "<u8"), ("aln_len", "<u4"), ("matches", "<u4"),
+                     ("mismatches", "<u4"), ("ins", "<u4"), ("dels", "<u4"), ("gap_opens", "<u4"),
+                     ("transitions", "<u4"), ("transversions", "<u4"), ("k2p", "<f8"),
+                     ("jc", "<f8"), ("cigar_off", "<u8"), ("cigar_len", "<u8")])
 CAND_DTYPE = np.dtype([("query_id", "<u4"), ("strand", "<u4"), ("q_seq", "<u4"),
                        ("t_seq", "<u4"), ("q_begin", "<u8"), ("q_end", "<u8"),
                        ("t_begin", "<u8"), ("t_end", "<u8"), ("n_seeds", "<u4"),
                        ("max_shared", "<u4")])
 
 
+def _stale() -> bool:
+    if not os.path.exists(_LIB):
+        return True
+    t = os.path.getmtime(_LIB)
+    return t < os.path.getmtime(_SRC) or t < os.path.getmtime(_SRC2)
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle (gcc, OpenMP) into ``oracle/liboracle.so``."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or _stale():
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-                               "-Wall", "-o", tmp, _SRC, "-lm"])
+                               "-Wall", "-o", tmp, _SRC, _SRC2, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -49,7 +66,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if _stale():
             build()
         L = ctypes.CDLL(_LIB)
         vp, u32, u64, dbl = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
@@ -97,8 +114,20 @@ def lib():
         L.or_qgram_bound.argtypes = [u64, dbl, u32, dbl]
         L.or_seed_size.restype = ctypes.c_int
         L.or_cand_size.restype = ctypes.c_int
+        L.or_sd_align.restype = vp
+        L.or_sd_align.argtypes = [vp, vp, u32, vp, u64, u32, u32, dbl, ctypes.c_int]
+        L.or_sd_count.restype = u64
+        L.or_sd_count.argtypes = [vp]
+        L.or_sd_ops_count.restype = u64
+        L.or_sd_ops_count.argtypes = [vp]
+        L.or_sd_size.restype = ctypes.c_int
+        L.or_sd_copy.argtypes = [vp, vp, vp]
+        L.or_sd_free.argtypes = [vp]
+        L.or_align_pair.restype = u64
+        L.or_align_pair.argtypes = [vp, u32, vp, u32, vp, u64]
         assert L.or_seed_size() == SEED_DTYPE.itemsize
         assert L.or_cand_size() == CAND_DTYPE.itemsize
+        assert L.or_sd_size() == SD_DTYPE.itemsize
         _lib = L
     return _lib
 
@@ -245,3 +274,34 @@ class OracleIndex:
         finally:
             lib().or_result_free(r)
         return seeds, cands
+
+
+def sd_align(bytes_: np.ndarray, off: np.ndarray, rows, k: int = 11, min_len: int = 1000,
+             max_error: float = 0.25, threads: int = 0):
+    """Final SDs (Section 3.3) of region pairs given as rows (q0, q1, t0, t1,
+    strand) of global coordinates: (SD_DTYPE array, CIGAR operations)."""
+    b = np.ascontiguousarray(bytes_, dtype=np.uint8)
+    off = np.ascontiguousarray(off, dtype=np.uint64)
+    r = np.ascontiguousarray(np.array(rows, dtype=np.uint64).reshape(-1, 5))
+    h = lib().or_sd_align(_ptr(b), _ptr(off), len(off) - 1, _ptr(r), len(r), k, min_len,
+                          max_error, threads)
+    if not h:
+        raise ValueError("invalid region rows or parameters")
+    try:
+        sd = np.zeros(int(lib().or_sd_count(h)), SD_DTYPE)
+        ops = np.zeros(int(lib().or_sd_ops_count(h)), np.uint32)
+        lib().or_sd_copy(h, _ptr(sd), _ptr(ops))
+    finally:
+        lib().or_sd_free(h)
+    return sd, ops
+
+
+def align_pair(q: np.ndarray, t: np.ndarray) -> np.ndarray:
+    """Global alignment (the Section 3.3 reading: match 2, mismatch -4, gap
+    4 + 2 L) of two code strings (0..3, 4 = N): CIGAR operations."""
+    q = np.ascontiguousarray(q, dtype=np.uint8)
+    t = np.ascontiguousarray(t, dtype=np.uint8)
+    cap = len(q) + len(t) + 1
+    ops = np.zeros(cap, np.uint32)
+    n = int(lib().or_align_pair(_ptr(q), len(q), _ptr(t), len(t), _ptr(ops), cap))
+    return ops[:n]

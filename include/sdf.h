@@ -266,6 +266,77 @@ sdf_status sdf_qgram_filter(sdf_index ix, const sdf_region *regions, uint64_t n,
                             const sdf_qgram_params *p, void *hip_stream, uint64_t *shared,
                             uint8_t *pass);
 
+/*
+ * Final SDs inside potential SD regions (Section 3.3): inside each region
+ * pair, exact seeds are chained in two tiers, the chains are aligned
+ * globally, and the alignments meeting the SD conditions of Section 2 are
+ * reported in BEDPE coordinates with CIGAR operations and Kimura
+ * two-parameter and Jukes-Cantor distances.  The paper names the method and
+ * not its parameters; the readings (identical in the test oracle):
+ *  - seeds: every k-mer (k = 11 in the paper) of the query side Q found in
+ *    the target side T' (the target reverse-complemented on strand 1), case
+ *    folded, k-mers with a non-ACGT base skipped, k-mers occurring more than
+ *    32 times in T' skipped;
+ *  - anchors: maximal runs of consecutive seed matches on one diagonal (an
+ *    exact match of run + k - 1 bases);
+ *  - tier 1: anchor b precedes a when it ends before a starts on both sides
+ *    with max(dx, dy) <= G1 = max(1, ceil(min_len delta_G)) (the gap limit
+ *    l delta_G of Section 3.3, l read as the minimum SD length); score
+ *    S(a) = len(a) + max(0, max_b S(b) - max(dx, dy)), ties to the
+ *    predecessor with the larger x, then y;
+ *  - chains of a tier: nodes in order of decreasing score (then x, y) each
+ *    start a chain unless used, following kept predecessors back until a
+ *    used node or none;
+ *  - tier 2: the tier-1 chains (weight: anchor bases minus link costs)
+ *    chained with max(dx, dy) <= 10,000 and the affine cost min(dx, dy) +
+ *    (g > 0 ? 10 + ceil(g / 10) : 0), g = |dx - dy|;
+ *  - alignment: anchors are exact matches; every stretch between
+ *    consecutive anchors is aligned globally (match 2, mismatch -4, a gap of
+ *    L bases -(4 + 2 L); ties to the diagonal, then the query-gap, then the
+ *    target-gap state) when (dx + 1)(dy + 1) <= 2^20 cells, else taken as
+ *    its diagonal followed by one gap of the remaining bases;
+ *  - report: alignment length l >= min_len and mismatches + gap openings
+ *    <= max_error l (each gap counted once: the affine view of the error);
+ *  - distances over aligned columns: K2P = -ln(1 - 2P - Q)/2 - ln(1 - 2Q)/4
+ *    (P, Q: transition and transversion fractions), JC = -3/4 ln(1 - 4p/3)
+ *    (p: mismatch fraction); -1 where the logarithm is undefined.
+ */
+typedef struct {
+    double max_error;   /* delta, 0 < delta < 1 */
+    uint32_t min_len;   /* minimum SD length L >= 1 */
+    uint32_t k;         /* seed length, 1 <= k <= 11 */
+} sdf_align_params;
+
+/* One final SD (120 bytes): region index, strand, sequences and 0-based
+ * half-open per-sequence coordinates (BEDPE), counts of the alignment
+ * columns, the distances, and its CIGAR operations at [cigar_off,
+ * cigar_off + cigar_len) of the operation array (len << 4 | op; op 7 '=',
+ * 8 'X', 1 'I' (query base), 2 'D' (target base)). */
+typedef struct {
+    uint64_t region;
+    uint32_t strand, q_seq, t_seq, _pad;
+    uint64_t q_begin, q_end, t_begin, t_end;
+    uint32_t aln_len, matches, mismatches, ins, dels, gap_opens, transitions, transversions;
+    double k2p, jc;
+    uint64_t cigar_off, cigar_len;
+} sdf_sd;
+
+typedef struct sdf_sds_s *sdf_sds;
+
+/* Final SDs of n region pairs (host array; strand, sequences and bounds
+ * are read; each side below 2^20 bases, n below 2^22), records in region
+ * order (within a region in the order the final chains are taken out).
+ * Errors: SDF_EINVAL for NULL arguments, parameters out of range, strand >
+ * 1 or a side of 2^20 bases or more; SDF_ERANGE for a region outside the
+ * index; SDF_ENOMEM, SDF_EDEVICE. */
+sdf_status sdf_align_regions(sdf_index ix, const sdf_region *regions, uint64_t n,
+                             const sdf_align_params *p, void *hip_stream, sdf_sds *out);
+/* Numbers of records and of CIGAR operations. */
+sdf_status sdf_sds_count(sdf_sds s, uint64_t *n_sd, uint64_t *n_ops);
+/* Copies up to sd_cap records and ops_cap operations to host memory. */
+sdf_status sdf_sds_copy(sdf_sds s, sdf_sd *sd, uint64_t sd_cap, uint32_t *ops, uint64_t ops_cap);
+void sdf_sds_free(sdf_sds s);
+
 /* Regions of a search run with SDF_EXTEND: one per candidate, in the order
  * of sdf_result_copy.  SDF_EINVAL if the search ran without the flag. */
 sdf_status sdf_result_regions(sdf_result r, sdf_region *dst, uint64_t cap, uint64_t *written);

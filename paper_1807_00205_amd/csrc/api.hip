@@ -42,6 +42,12 @@ unsigned char *scratch_ptr(int dev) {
 }
 }  // namespace
 
+struct sdf_sds_s {
+    int device = 0;
+    hipStream_t st = nullptr;
+    sdf::SdResult r;
+};
+
 struct sdf_result_s {
     int device = 0;
     hipStream_t st = nullptr;
@@ -1106,6 +1112,73 @@ sdf_status sdf_extend(sdf_index ix, const sdf_region *in, uint64_t n, const sdf_
         SDF_HIP(hipMemcpyAsync(out, buf.p, n * sizeof(sdf_region), hipMemcpyDeviceToHost, st));
         SDF_HIP(hipStreamSynchronize(st));
     });
+}
+
+sdf_status sdf_align_regions(sdf_index ix, const sdf_region *in, uint64_t n,
+                             const sdf_align_params *p, void *hip_stream, sdf_sds *out) {
+    if (out) *out = nullptr;
+    sdf_sds_s *res = nullptr;
+    sdf_status rc = guarded([&] {
+        if (!ix || !p || !out || (n && !in)) throw Error{SDF_EINVAL, "NULL argument"};
+        const double d = p->max_error;
+        if (!(d > 0.0 && d < 1.0)) throw Error{SDF_EINVAL, "max_error must lie in (0, 1)"};
+        if (p->min_len < 1) throw Error{SDF_EINVAL, "min_len must be at least 1"};
+        if (p->k < 1 || p->k > 11) throw Error{SDF_EINVAL, "k must lie in [1, 11]"};
+        if (n >= (1ull << 22)) throw Error{SDF_EINVAL, "too many regions (2^22 at most)"};
+        for (uint64_t i = 0; i < n; i++) {
+            const sdf_region &x = in[i];
+            if (x.strand > 1) throw Error{SDF_EINVAL, "strand must be 0 or 1"};
+            if (x.q_seq >= ix->nseq || x.t_seq >= ix->nseq)
+                throw Error{SDF_ERANGE, "region sequence index out of range"};
+            const uint64_t ql = ix->h_off[x.q_seq + 1] - ix->h_off[x.q_seq];
+            const uint64_t tl = ix->h_off[x.t_seq + 1] - ix->h_off[x.t_seq];
+            if (x.q_begin > x.q_end || x.q_end > ql || x.t_begin > x.t_end || x.t_end > tl)
+                throw Error{SDF_ERANGE, "region outside its sequence"};
+            if (x.q_end - x.q_begin >= (1ull << 20) || x.t_end - x.t_begin >= (1ull << 20))
+                throw Error{SDF_EINVAL, "a region side holds 2^20 bases or more"};
+        }
+        SDF_HIP(hipSetDevice(ix->device));
+        const hipStream_t st = (hipStream_t)hip_stream;
+        StreamScope scope(st);
+        res = new sdf_sds_s();
+        res->device = ix->device;
+        res->st = st;
+        sd_align(ix->view(), ix->h_off.data(), in, n, p->k, p->min_len, d, res->r, st);
+        *out = res;
+    });
+    if (rc != SDF_OK && res) {
+        (void)hipStreamSynchronize((hipStream_t)hip_stream);
+        delete res;
+    }
+    return rc;
+}
+
+sdf_status sdf_sds_count(sdf_sds s, uint64_t *n_sd, uint64_t *n_ops) {
+    return guarded([&] {
+        if (!s) throw Error{SDF_EINVAL, "NULL argument"};
+        if (n_sd) *n_sd = s->r.nsd;
+        if (n_ops) *n_ops = s->r.nops;
+    });
+}
+
+sdf_status sdf_sds_copy(sdf_sds s, sdf_sd *sd, uint64_t sd_cap, uint32_t *ops, uint64_t ops_cap) {
+    return guarded([&] {
+        if (!s) throw Error{SDF_EINVAL, "NULL argument"};
+        const uint64_t m = std::min(sd_cap, s->r.nsd), o = std::min(ops_cap, s->r.nops);
+        if ((m && !sd) || (o && !ops)) throw Error{SDF_EINVAL, "NULL destination"};
+        SDF_HIP(hipSetDevice(s->device));
+        if (m) SDF_HIP(hipMemcpyAsync(sd, s->r.sd.p, m * sizeof(sdf_sd), hipMemcpyDeviceToHost, s->st));
+        if (o) SDF_HIP(hipMemcpyAsync(ops, s->r.cigar.p, o * 4, hipMemcpyDeviceToHost, s->st));
+        SDF_HIP(hipStreamSynchronize(s->st));
+    });
+}
+
+void sdf_sds_free(sdf_sds s) {
+    if (!s) return;
+    (void)hipSetDevice(s->device);
+    (void)hipStreamSynchronize(s->st);
+    StreamScope scope(s->st);
+    delete s;
 }
 
 sdf_status sdf_result_stats(sdf_result r, uint64_t *v, uint32_t n_v) {

@@ -108,6 +108,16 @@ void chain_seeds(const IndexView &ix, const uint32_t *seeds, DevCount ns, uint32
                  uint64_t nc_bound = 0);
 // Full record-order sort of nc candidates (buffer regrown to a power of two).
 void sort_candidates_records(DevBuf<sdf_candidate> &cands, uint64_t nc, hipStream_t st);
+// Final SDs of region pairs (align.hip, Section 3.3): records and CIGAR
+// operations on the device.
+struct SdResult {
+    DevBuf<sdf_sd> sd;
+    DevBuf<uint32_t> cigar;
+    uint64_t nsd = 0, nops = 0;
+};
+void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regions, uint64_t n,
+              uint32_t k, uint32_t min_len, double delta, SdResult &res, hipStream_t st);
+
 // Seeds sorted by (query_id, i, j, strand) into dst (device, 6 u32 each).
 void sort_seeds(const uint32_t *seeds, uint64_t nseeds, uint32_t *dst, hipStream_t st);
 

@@ -9,7 +9,7 @@ from __future__ import annotations
 import ctypes
 import itertools
 import os
-from typing import Iterable, Optional, Sequence, Tuple
+from typing import Iterable, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -32,6 +32,15 @@ CANDIDATE_DTYPE = np.dtype([("query_id", "<u4"), ("strand", "<u4"), ("q_seq", "<
 REGION_DTYPE = np.dtype([("strand", "<u4"), ("q_seq", "<u4"), ("t_seq", "<u4"), ("stop", "<u4"),
                          ("q_begin", "<u8"), ("q_end", "<u8"), ("t_begin", "<u8"),
                          ("t_end", "<u8"), ("m", "<u4"), ("s", "<u4")])
+# sdf_sd: one final SD (Section 3.3) with its CIGAR operations at
+# [cigar_off, cigar_off + cigar_len) of the operation array.
+SD_DTYPE = np.dtype([("region", "<u8"), ("strand", "<u4"), ("q_seq", "<u4"), ("t_seq", "<u4"),
+                     ("_pad", "<u4"), ("q_begin", "<u8"), ("q_end", "<u8"), ("t_begin", "<u8"),
+                     ("t_end", "<u8"), ("aln_len", "<u4"), ("matches", "<u4"),
+                     ("mismatches", "<u4"), ("ins", "<u4"), ("dels", "<u4"), ("gap_opens", "<u4"),
+                     ("transitions", "<u4"), ("transversions", "<u4"), ("k2p", "<f8"),
+                     ("jc", "<f8"), ("cigar_off", "<u8"), ("cigar_len", "<u8")])
+CIGAR_CHARS = {7: "=", 8: "X", 1: "I", 2: "D"}
 SEED_DTYPE = np.dtype([("query_id", "<u4"), ("i", "<u4"), ("j", "<u4"), ("strand", "<u4"),
                        ("shared", "<u4"), ("sketch", "<u4")])
 EXPORTS = ["sdf_last_error", "sdf_index_build", "sdf_index_info", "sdf_index_hit_density",
@@ -41,7 +50,8 @@ EXPORTS = ["sdf_last_error", "sdf_index_build", "sdf_index_info", "sdf_index_hit
            "sdf_result_seeds", "sdf_result_timing", "sdf_result_stats", "sdf_result_free",
            "sdf_extend", "sdf_result_regions", "sdf_qgram_filter", "sdf_autotune",
            "sdf_search_batch_noalloc", "sdf_plan_create", "sdf_plan_run", "sdf_plan_info",
-           "sdf_plan_free", "sdf_search_batch_capped"]
+           "sdf_plan_free", "sdf_search_batch_capped", "sdf_align_regions", "sdf_sds_count",
+           "sdf_sds_copy", "sdf_sds_free"]
 NOALLOC_SCRATCH_BYTES = 128 << 20
 NOALLOC_MAX_SPANS = 65536
 NOALLOC_MAX_QUERY_BASES = 8_000_000
@@ -78,6 +88,11 @@ class _QgramParams(ctypes.Structure):
 
 class _PlanParams(ctypes.Structure):
     _fields_ = [("seed_cap", ctypes.c_uint64), ("cand_cap", ctypes.c_uint64)]
+
+
+class _AlignParams(ctypes.Structure):
+    _fields_ = [("max_error", ctypes.c_double), ("min_len", ctypes.c_uint32),
+                ("k", ctypes.c_uint32)]
 
 
 class _Span(ctypes.Structure):
@@ -191,6 +206,14 @@ def lib() -> ctypes.CDLL:
         L.sdf_qgram_filter.argtypes = [vp, vp, u64, P(_QgramParams), vp, vp, vp]
         L.sdf_result_regions.restype = st
         L.sdf_result_regions.argtypes = [vp, vp, u64, P(u64)]
+        L.sdf_align_regions.restype = st
+        L.sdf_align_regions.argtypes = [vp, vp, u64, P(_AlignParams), vp, P(vp)]
+        L.sdf_sds_count.restype = st
+        L.sdf_sds_count.argtypes = [vp, P(u64), P(u64)]
+        L.sdf_sds_copy.restype = st
+        L.sdf_sds_copy.argtypes = [vp, vp, u64, vp, u64]
+        L.sdf_sds_free.restype = None
+        L.sdf_sds_free.argtypes = [vp]
         L.sdf_search_batch_capped.restype = st
         L.sdf_search_batch_capped.argtypes = [vp, vp, u32, P(_SearchParams), u64, vp, P(vp),
                                               P(u64)]
@@ -206,6 +229,7 @@ def lib() -> ctypes.CDLL:
         L.sdf_search_batch_noalloc.argtypes = [vp, vp, u32, P(_SearchParams), vp, vp, u64,
                                                P(u64)]
         assert REGION_DTYPE.itemsize == 56
+        assert SD_DTYPE.itemsize == 120
         _lib = L
     return _lib
 
@@ -507,3 +531,47 @@ class Index:
              min_len: int = 1000, seed_cap: int = 0, cand_cap: int = 0, stream=None) -> Plan:
         """The batched search of these spans captured as a HIP graph."""
         return Plan(self, spans, max_error, min_len, seed_cap, cand_cap, stream)
+
+    def align_regions(self, regions, k: int = 11, min_len: int = 1000, max_error: float = 0.25,
+                      stream=None):
+        """Final SDs (Section 3.3) of region pairs (a REGION_DTYPE array, as
+        from an extension): (SD_DTYPE records, CIGAR operations)."""
+        inp = np.ascontiguousarray(regions)
+        assert inp.dtype == REGION_DTYPE
+        p = _AlignParams(max_error, min_len, k)
+        h = ctypes.c_void_p()
+        _check(lib().sdf_align_regions(self._h, inp.ctypes.data_as(ctypes.c_void_p), len(inp),
+                                       ctypes.byref(p), _stream_ptr(stream), ctypes.byref(h)))
+        try:
+            nsd, nops = ctypes.c_uint64(), ctypes.c_uint64()
+            _check(lib().sdf_sds_count(h, ctypes.byref(nsd), ctypes.byref(nops)))
+            sd = np.zeros(nsd.value, SD_DTYPE)
+            ops = np.zeros(nops.value, np.uint32)
+            _check(lib().sdf_sds_copy(h, sd.ctypes.data_as(ctypes.c_void_p), nsd.value,
+                                      ops.ctypes.data_as(ctypes.c_void_p), nops.value))
+        finally:
+            lib().sdf_sds_free(h)
+        return sd, ops
+
+
+def cigar_string(ops: np.ndarray) -> str:
+    """CIGAR text of operations (len << 4 | op)."""
+    return "".join("%d%s" % (int(v) >> 4, CIGAR_CHARS[int(v) & 15]) for v in ops)
+
+
+def to_bedpe(sd: np.ndarray, ops: np.ndarray, names: Sequence[str]) -> List[str]:
+    """BEDPE lines (chrom1, start1, end1, chrom2, start2, end2, name, score,
+    strand1, strand2, then alignment length, identity, K2P, JC and CIGAR) of
+    final SD records."""
+    lines = []
+    for s in sd:
+        o = int(s["cigar_off"])
+        cig = cigar_string(ops[o:o + int(s["cigar_len"])])
+        ident = int(s["matches"]) / max(1, int(s["aln_len"]))
+        lines.append("\t".join([names[int(s["q_seq"])], str(int(s["q_begin"])), str(int(s["q_end"])),
+                                names[int(s["t_seq"])], str(int(s["t_begin"])), str(int(s["t_end"])),
+                                "sd%d" % int(s["region"]), str(int(s["aln_len"])), "+",
+                                "-" if int(s["strand"]) else "+", str(int(s["aln_len"])),
+                                "%.4f" % ident, "%.6f" % float(s["k2p"]), "%.6f" % float(s["jc"]),
+                                cig]))
+    return lines

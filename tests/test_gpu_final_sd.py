@@ -1,0 +1,161 @@
+"""Final SDs (Section 3.3) on the GPU against the oracle: anchors, both
+chaining tiers, alignments, records and CIGAR operations identical;
+distances within 1e-12 (relative) of the oracle's (the logarithms of the
+two libraries may differ in the last bit)."""
+import numpy as np
+import pytest
+
+from paper_1807_00205_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ["region", "strand", "q_seq", "t_seq", "q_begin", "q_end", "t_begin", "t_end",
+          "aln_len", "matches", "mismatches", "ins", "dels", "gap_opens", "transitions",
+          "transversions", "cigar_len"]
+
+
+def _regions(S, rows, off):
+    """Rows (q0, q1, t0, t1, strand) of global coordinates as sdf_region
+    records (per-sequence coordinates)."""
+    off = np.asarray(off, np.uint64)
+    out = np.zeros(len(rows), S.REGION_DTYPE)
+    for u, (q0, q1, t0, t1, o) in enumerate(rows):
+        qs = int(np.searchsorted(off, q0, side="right") - 1)
+        ts = int(np.searchsorted(off, t0, side="right") - 1)
+        out[u] = (o, qs, ts, 0, q0 - off[qs], q1 - off[qs], t0 - off[ts], t1 - off[ts], 0, 0)
+    return out
+
+
+def _same(got, want, what):
+    (gs, gops), (ws, wops) = got, want
+    assert len(gs) == len(ws), "%s: %d vs %d records" % (what, len(gs), len(ws))
+    for f in FIELDS:
+        x, y = gs[f].astype(np.uint64), ws[f].astype(np.uint64)
+        assert np.array_equal(x, y), (what, f, np.nonzero(x != y)[0][:5])
+    np.testing.assert_allclose(gs["k2p"], ws["k2p"], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(gs["jc"], ws["jc"], rtol=1e-12, atol=1e-15)
+    for a, b in zip(gs, ws):
+        x = gops[int(a["cigar_off"]):int(a["cigar_off"] + a["cigar_len"])]
+        y = wops[int(b["cigar_off"]):int(b["cigar_off"] + b["cigar_len"])]
+        assert np.array_equal(x, y), (what, "cigar")
+
+
+def _planted(seed, length, copies, rate):
+    rng = synth.rng_for(seed)
+    seqs = [synth.random_bases(rng, length), synth.random_bases(rng, length)]
+    rows = []
+    for c in range(copies):
+        L = int(rng.integers(300, 600))
+        a = int(rng.integers(0, length - L))
+        b = c * (length // copies) + int(rng.integers(0, 20))
+        cp = synth.mutate(rng, seqs[0][a:a + L], rate)
+        o = c % 2
+        if o:
+            cp = synth.revcomp(cp)
+        cp = cp[:min(length - b, length // copies - 30)]
+        seqs[1][b:b + len(cp)] = cp
+        rows.append((max(0, a - 40), min(length, a + L + 40), length + max(0, b - 40),
+                     min(2 * length, length + b + len(cp) + 40), o))
+    rows.append((100, 700, length + 100, length + 900, 0))
+    return seqs, rows
+
+
+@pytest.mark.parametrize("seed,rate", [(1, 0.0), (2, 0.03), (3, 0.08), (4, 0.15), (5, 0.25)])
+@pytest.mark.parametrize("k,min_len", [(7, 200), (11, 300)])
+def test_planted_copies(oracle_lib, seed, rate, k, min_len):
+    from paper_1807_00205_amd import sdf
+    seqs, rows = _planted(seed, 3000, 4, rate)
+    b = np.concatenate(seqs)
+    off = np.array([0, len(seqs[0]), len(b)], np.uint64)
+    ix = sdf.Index(seqs, 12, 16)
+    got = ix.align_regions(_regions(sdf, rows, off), k, min_len, 0.25)
+    want = oracle_lib.sd_align(b, off, rows, k, min_len, 0.25)
+    _same(got, want, "planted")
+    if rate <= 0.08 and min_len == 200:  # copies of 300-600 bases, all longer than 200
+        assert len(got[0]) >= 4
+
+
+@pytest.mark.parametrize("strand", [0, 1])
+def test_closed_forms(oracle_lib, strand):
+    """An exact 2,000-base copy: one SD, '2000=', both distances 0."""
+    from paper_1807_00205_amd import sdf
+    rng = synth.rng_for(77)
+    x = synth.random_bases(rng, 2000)
+    flank = synth.random_bases(rng, 300)
+    t = synth.revcomp(x) if strand else x
+    seqs = [x, flank, t]
+    ix = sdf.Index(seqs, 12, 16)
+    reg = np.zeros(1, sdf.REGION_DTYPE)
+    reg[0] = (strand, 0, 2, 0, 0, 2000, 0, 2000, 0, 0)
+    sd, ops = ix.align_regions(reg)
+    assert len(sd) == 1
+    assert sdf.cigar_string(ops) == "2000="
+    assert float(sd["k2p"][0]) == 0.0 and float(sd["jc"][0]) == 0.0
+    assert (int(sd["q_begin"][0]), int(sd["q_end"][0]), int(sd["t_begin"][0]),
+            int(sd["t_end"][0])) == (0, 2000, 0, 2000)
+    line = sdf.to_bedpe(sd, ops, ["a", "b", "c"])[0].split("\t")
+    assert line[:6] == ["a", "0", "2000", "c", "0", "2000"] and line[-1] == "2000="
+
+
+def test_config1_extended_regions(oracle_lib):
+    """The whole path on the 1 Mbp workload: search, extension of every
+    candidate (Section 3.2), final SDs of every extended region."""
+    from paper_1807_00205_amd import sdf
+    g = synth.config1()
+    b, off = g.concat()
+    ix = sdf.Index(g.seqs, 12, 16)
+    reg = ix.search_batch(g.spans, extend=True).regions()
+    got = ix.align_regions(reg)
+    qo = off[reg["q_seq"]].astype(np.uint64)
+    to = off[reg["t_seq"]].astype(np.uint64)
+    rows = np.stack([reg["q_begin"] + qo, reg["q_end"] + qo, reg["t_begin"] + to,
+                     reg["t_end"] + to, reg["strand"].astype(np.uint64)], axis=1)
+    want = oracle_lib.sd_align(b, off, rows, 11, 1000, 0.25)
+    _same(got, want, "config 1")
+    # every planted duplication (both directions) is reported
+    assert len(got[0]) >= 20
+
+
+def test_config2_sampled_regions(oracle_lib):
+    """200 sampled extended regions of the 50 Mbp workload (soft-masked
+    repeats, N-gaps, 1-25% divergence)."""
+    import os
+    from paper_1807_00205_amd import sdf
+    g = synth.config2()
+    b, off = g.concat()
+    ix = sdf.Index(g.seqs, 12, 16)
+    reg = ix.search_batch(g.spans, extend=True).regions()
+    rng = synth.rng_for(5)
+    reg = reg[np.sort(rng.choice(len(reg), 200, replace=False))]
+    reg = reg[(reg["q_end"] - reg["q_begin"] < (1 << 20)) & (reg["t_end"] - reg["t_begin"] < (1 << 20))]
+    got = ix.align_regions(reg)
+    qo = off[reg["q_seq"]].astype(np.uint64)
+    to = off[reg["t_seq"]].astype(np.uint64)
+    rows = np.stack([reg["q_begin"] + qo, reg["q_end"] + qo, reg["t_begin"] + to,
+                     reg["t_end"] + to, reg["strand"].astype(np.uint64)], axis=1)
+    want = oracle_lib.sd_align(b, off, rows, 11, 1000, 0.25, min(16, os.cpu_count() or 1))
+    _same(got, want, "config 2")
+    assert len(got[0]) > 0
+
+
+def test_errors():
+    from paper_1807_00205_amd import sdf
+    g = synth.small_case(3, length=3000)
+    ix = sdf.Index(g.seqs, 12, 16)
+    reg = np.zeros(1, sdf.REGION_DTYPE)
+    reg[0] = (0, 0, 0, 0, 0, 1000, 1500, 2500, 0, 0)
+    with pytest.raises(sdf.SdfError) as e:
+        ix.align_regions(reg, k=12)
+    assert e.value.code == sdf.SDF_EINVAL
+    bad = reg.copy()
+    bad["strand"] = 2
+    with pytest.raises(sdf.SdfError) as e:
+        ix.align_regions(bad)
+    assert e.value.code == sdf.SDF_EINVAL
+    bad = reg.copy()
+    bad["t_end"] = 3001
+    with pytest.raises(sdf.SdfError) as e:
+        ix.align_regions(bad)
+    assert e.value.code == sdf.SDF_ERANGE
+    sd, ops = ix.align_regions(reg[:0])
+    assert len(sd) == 0 and len(ops) == 0

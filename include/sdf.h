@@ -279,18 +279,22 @@ sdf_status sdf_qgram_filter(sdf_index ix, const sdf_region *regions, uint64_t n,
  *    32 times in T' skipped;
  *  - anchors: maximal runs of consecutive seed matches on one diagonal (an
  *    exact match of run + k - 1 bases);
- *  - tier 1: anchor b precedes a when it ends before a starts on both sides
- *    with max(dx, dy) <= G1 = max(1, ceil(min_len delta_G)) (the gap limit
- *    l delta_G of Section 3.3, l read as the minimum SD length); score
- *    S(a) = len(a) + max(0, max_b S(b) - max(dx, dy)), ties to the
- *    predecessor with the larger x, then y;
+ *  - links: b (earlier in (x, y) order) may precede a when a, its start
+ *    cut by o = max(0, b.ex - a.x, b.ey - a.y) so that it begins after b
+ *    ends on both sides, keeps at least one base of its first anchor
+ *    (anchors flanking an indel overlap whenever a base next to it matches
+ *    by chance); dx = a.x + o - b.ex, dy = a.y + o - b.ey are the gaps;
+ *  - tier 1 (the longest chains): max(dx, dy) <= G1 = max(1, ceil(min_len
+ *    delta_G)) (the gap limit l delta_G of Section 3.3, l read as the
+ *    minimum SD length); score S(a) = len(a) + max(0, max_b S(b) - |dx -
+ *    dy| - o), ties to the predecessor with the larger x, then y;
  *  - chains of a tier: nodes in order of decreasing score (then x, y) each
  *    start a chain unless used, following kept predecessors back until a
  *    used node or none;
  *  - tier 2: the tier-1 chains (weight: anchor bases minus link costs)
  *    chained with max(dx, dy) <= 10,000 and the affine cost min(dx, dy) +
- *    (g > 0 ? 10 + ceil(g / 10) : 0), g = |dx - dy|;
- *  - alignment: anchors are exact matches; every stretch between
+ *    (g > 0 ? 10 + ceil(g / 10) : 0) + o, g = |dx - dy|;
+ *  - alignment: anchors (cut as linked) are exact matches; every stretch between
  *    consecutive anchors is aligned globally (match 2, mismatch -4, a gap of
  *    L bases -(4 + 2 L); ties to the diagonal, then the query-gap, then the
  *    target-gap state) when (dx + 1)(dy + 1) <= 2^20 cells, else taken as

@@ -142,9 +142,23 @@ def anchors(Q, T, k):
     return sorted(out)
 
 
+def trim(b, a):
+    """Bases cut from the start of node a = (x, y, ex, ey, first anchor
+    length) so that it begins after node b ends on both sides, with the
+    gaps left: (t, dx, dy), or None when the cut reaches past a's first
+    anchor.  Found by stepping t up from 0."""
+    t = 0
+    while a[0] + t < b[2] or a[1] + t < b[3]:
+        t += 1
+    if t >= a[4]:
+        return None
+    return t, a[0] + t - b[2], a[1] + t - b[3]
+
+
 def chains(nodes, weight, link_cost):
-    """Scores, kept predecessors and extracted chains of nodes (x, y, ex, ey)
-    sorted by (x, y); link_cost(b, a) is None when b cannot precede a."""
+    """Scores, kept predecessors and extracted chains of nodes (x, y, ex, ey,
+    first anchor length) sorted by (x, y); link_cost(b, a) is None when b
+    cannot precede a."""
     S, pred = {}, {}
     for a in range(len(nodes)):
         cands = []
@@ -184,40 +198,38 @@ def sd_align(seq_bytes: bytes, off, rows, k=11, min_len=1000, max_error=0.25):
         if o == 1:
             T = [3 - c if c < 4 else 4 for c in reversed(T)]
         an = anchors(Q, T, k)
-        nodes = [(x, y, x + L, y + L) for x, y, L in an]
+        nodes = [(x, y, x + L, y + L, L) for x, y, L in an]
 
         def cost1(b, a):
-            dx, dy = a[0] - b[2], a[1] - b[3]
-            if dx < 0 or dy < 0 or max(dx, dy) > G1:
+            tr = trim(b, a)
+            if tr is None or max(tr[1], tr[2]) > G1:
                 return None
-            return max(dx, dy)
+            return abs(tr[1] - tr[2]) + tr[0]
         c1 = chains(nodes, lambda a: an[a][2], cost1)
         c1.sort(key=lambda ch: (an[ch[0]][0], an[ch[0]][1]))
         cn, cw = [], []
         for ch in c1:
             f, l = an[ch[0]], an[ch[-1]]
-            cn.append((f[0], f[1], l[0] + l[2], l[1] + l[2]))
-            w = sum(an[a][2] for a in ch)
-            for p, q in zip(ch, ch[1:]):
-                w -= max(an[q][0] - an[p][0] - an[p][2], an[q][1] - an[p][1] - an[p][2])
-            cw.append(w)
+            cn.append((f[0], f[1], l[0] + l[2], l[1] + l[2], f[2]))
+            cw.append(sum(an[a][2] for a in ch) -
+                      sum(cost1(nodes[p], nodes[q]) for p, q in zip(ch, ch[1:])))
 
         def cost2(b, a):
-            dx, dy = a[0] - b[2], a[1] - b[3]
-            if dx < 0 or dy < 0 or max(dx, dy) > TIER2_GAP:
+            tr = trim(b, a)
+            if tr is None or max(tr[1], tr[2]) > TIER2_GAP:
                 return None
-            g = abs(dx - dy)
-            return min(dx, dy) + (10 + (g + 9) // 10 if g > 0 else 0)
+            g = abs(tr[1] - tr[2])
+            return min(tr[1], tr[2]) + (10 + (g + 9) // 10 if g > 0 else 0) + tr[0]
         for fin in chains(cn, lambda a: cw[a], cost2):
-            anc = [an[a] for c in fin for a in c1[c]]
-            ops = []
+            anc = [nodes[a] for c in fin for a in c1[c]]
+            ops = [("=", anc[0][4])]
             for p, q in zip(anc, anc[1:]):
-                ops.append(("=", p[2]))
-                ops += align(Q[p[0] + p[2]:q[0]], T[p[1] + p[2]:q[1]])
-            ops.append(("=", anc[-1][2]))
+                t, _, _ = trim(p, q)
+                ops += align(Q[p[2]:q[0] + t], T[p[3]:q[1] + t])
+                ops.append(("=", q[4] - t))
             ops = merge(ops)
             x0, y0 = anc[0][0], anc[0][1]
-            ex, ey = anc[-1][0] + anc[-1][2], anc[-1][1] + anc[-1][2]
+            ex, ey = anc[-1][2], anc[-1][3]
             st = dict(aln_len=0, matches=0, mismatches=0, ins=0, dels=0, gap_opens=0,
                       transitions=0, transversions=0)
             qi, ti = x0, y0

@@ -21,20 +21,32 @@
  *  - anchors: maximal runs of seed matches on one diagonal (y - x): a run
  *    of r consecutive matching k-mers is an exact match of r + k - 1 bases
  *    (the seed-and-extend step);
- *  - tier 1: anchor b precedes a when it ends before a starts on both
- *    sides (dx = a.x - (b.x + b.len) >= 0, dy likewise) and max(dx, dy) <=
- *    G1 = max(1, ceil(L * delta_G)) (the l * delta_G gap limit, l read as
- *    the minimum SD length L); S(a) = len(a) + max(0, max_b S(b) -
- *    max(dx, dy)); among equal best predecessors the one with the larger
- *    x, then y, is kept;
+ *  - links: anchor (or chain) b, earlier than a in (x, y) order, may
+ *    precede a when a, its start trimmed by the overlap o = max(0, b.ex -
+ *    a.x, b.ey - a.y) with b's end (ex, ey), keeps at least one base (o <
+ *    the length of a's first anchor); the gap is then dx = a.x + o - b.ex,
+ *    dy = a.y + o - b.ey, both >= 0.  Anchors on the two sides of an indel
+ *    overlap whenever a base next to it matches by chance, so without the
+ *    trim most chains would end at their first indel, against the
+ *    sensitivity Section 4.1.1 reports; the trimmed bases are charged to
+ *    the link (cost + o);
+ *  - tier 1 (the longest chains, seeds at most l * delta_G apart): b
+ *    precedes a when max(dx, dy) <= G1 = max(1, ceil(L * delta_G)) (l read
+ *    as the minimum SD length L); a link is charged only for the indel it
+ *    implies, |dx - dy|, and the trim: S(a) = len(a) + max(0, max_b S(b) -
+ *    |dx - dy| - o).  Charging the unanchored bases between seeds as well
+ *    (max(dx, dy)) makes chains at 15% substitutions lose more than they
+ *    gain, so they would end long before the copy does.  Among equal best
+ *    predecessors the one with the larger x, then y, is kept;
  *  - chains of a tier: nodes in order of decreasing score (ties: smaller x,
  *    then y) each start a chain unless already used, which follows the
  *    kept predecessors back until one is used or there is none;
  *  - tier 2: tier-1 chains (weight: anchor bases minus link costs) chained
  *    again with gaps max(dx, dy) <= 10,000 (Section 3.3) and the affine
- *    cost min(dx, dy) + (g > 0 ? 10 + ceil(g / 10) : 0), g = |dx - dy|;
- *  - alignment: anchors are exact matches; each stretch between
- *    consecutive anchors is aligned globally with affine gaps (match 2,
+ *    cost min(dx, dy) + (g > 0 ? 10 + ceil(g / 10) : 0) + o, g = |dx - dy|;
+ *  - alignment: anchors (trimmed as linked) are exact matches; each
+ *    stretch between consecutive anchors is aligned globally with affine
+ *    gaps (match 2,
  *    mismatch -4, a gap of L bases costs 4 + 2 L; ties in the recurrences
  *    and the traceback go to the diagonal, then the query-gap, then the
  *    target-gap state), in full when (dx + 1)(dy + 1) <= 2^20 cells, else
@@ -103,6 +115,22 @@ static int cmp_anchor(const void *a, const void *b)
     if (p->x != q->x) return p->x < q->x ? -1 : 1;
     if (p->y != q->y) return p->y < q->y ? -1 : 1;
     return 0;
+}
+
+/* The link from an anchor or chain ending at (bex, bey) to one starting at
+ * (ax, ay) whose first anchor has alen bases: 0 when a would be trimmed
+ * away, else 1 with the trim o and the gaps dx, dy after it. */
+static int sa_link(uint64_t bex, uint64_t bey, uint64_t ax, uint64_t ay, uint64_t alen,
+                   uint32_t *o, uint32_t *dx, uint32_t *dy)
+{
+    uint64_t t = 0;
+    if (bex > ax) t = bex - ax;
+    if (bey > ay && bey - ay > t) t = bey - ay;
+    if (t >= alen) return 0;
+    *o = (uint32_t)t;
+    *dx = (uint32_t)(ax + t - bex);
+    *dy = (uint32_t)(ay + t - bey);
+    return 1;
 }
 
 static void ops_push(sa_ops *o, uint32_t op, uint32_t len)
@@ -385,12 +413,13 @@ static void align_region(const uint8_t *bytes, const uint64_t *off, uint32_t nse
     for (uint32_t a = 0; a < na; a++) {
         int64_t best = 0; uint32_t bp = SA_NONE; uint32_t bx = 0, by = 0;
         for (uint32_t b = 0; b < a; b++) {  /* a predecessor starts before a in (x, y) order */
-            if ((uint64_t)an[b].x + an[b].len > an[a].x || (uint64_t)an[b].y + an[b].len > an[a].y)
+            uint32_t o, dx, dy;
+            if (!sa_link((uint64_t)an[b].x + an[b].len, (uint64_t)an[b].y + an[b].len, an[a].x,
+                         an[a].y, an[a].len, &o, &dx, &dy))
                 continue;
-            uint32_t dx = an[a].x - (an[b].x + an[b].len), dy = an[a].y - (an[b].y + an[b].len);
-            uint32_t g = dx > dy ? dx : dy;
-            if (g > G1) continue;
-            int64_t v = n1[b].score - (int64_t)g;
+            if ((dx > dy ? dx : dy) > G1) continue;
+            uint32_t g = dx > dy ? dx - dy : dy - dx;
+            int64_t v = n1[b].score - (int64_t)g - (int64_t)o;
             if (v > best || (v == best && v > 0 &&
                              (an[b].x > bx || (an[b].x == bx && an[b].y > by)))) {
                 best = v; bp = b; bx = an[b].x; by = an[b].y;
@@ -406,6 +435,7 @@ static void align_region(const uint8_t *bytes, const uint64_t *off, uint32_t nse
     /* tier-1 chains as nodes: extents and weights, in (x, y) order */
     uint32_t *cx = (uint32_t *)malloc((nc1 ? nc1 : 1) * 4), *cy = (uint32_t *)malloc((nc1 ? nc1 : 1) * 4);
     uint32_t *cex = (uint32_t *)malloc((nc1 ? nc1 : 1) * 4), *cey = (uint32_t *)malloc((nc1 ? nc1 : 1) * 4);
+    uint32_t *cfl = (uint32_t *)malloc((nc1 ? nc1 : 1) * 4);
     int64_t *cw = (int64_t *)malloc((nc1 ? nc1 : 1) * sizeof(int64_t));
     uint32_t *corder = (uint32_t *)malloc((nc1 ? nc1 : 1) * 4);
     {
@@ -423,13 +453,16 @@ static void align_region(const uint8_t *bytes, const uint64_t *off, uint32_t nse
         uint32_t c = corder[u];
         const sa_anchor *f = &an[c1[s1[c]]], *l = &an[c1[s1[c + 1] - 1]];
         cx[u] = f->x; cy[u] = f->y; cex[u] = l->x + l->len; cey[u] = l->y + l->len;
+        cfl[u] = f->len;
         int64_t w = 0;
         for (uint32_t t = s1[c]; t < s1[c + 1]; t++) {
             w += an[c1[t]].len;
             if (t > s1[c]) {
                 const sa_anchor *p = &an[c1[t - 1]], *q = &an[c1[t]];
-                uint32_t dx = q->x - (p->x + p->len), dy = q->y - (p->y + p->len);
-                w -= dx > dy ? dx : dy;
+                uint32_t o = 0, dx = 0, dy = 0;
+                sa_link((uint64_t)p->x + p->len, (uint64_t)p->y + p->len, q->x, q->y, q->len, &o,
+                        &dx, &dy);
+                w -= (int64_t)(dx > dy ? dx - dy : dy - dx) + o;
             }
         }
         cw[u] = w;
@@ -439,11 +472,12 @@ static void align_region(const uint8_t *bytes, const uint64_t *off, uint32_t nse
     for (uint32_t a = 0; a < nc1; a++) {
         int64_t best = 0; uint32_t bp = SA_NONE, bx = 0, by = 0;
         for (uint32_t b = 0; b < a; b++) {
-            if (cex[b] > cx[a] || cey[b] > cy[a]) continue;
-            uint32_t dx = cx[a] - cex[b], dy = cy[a] - cey[b];
+            uint32_t o, dx, dy;
+            if (!sa_link(cex[b], cey[b], cx[a], cy[a], cfl[a], &o, &dx, &dy)) continue;
             if ((dx > dy ? dx : dy) > SA_TIER2_GAP) continue;
             uint32_t g = dx > dy ? dx - dy : dy - dx;
-            int64_t cost = (int64_t)(dx < dy ? dx : dy) + (g > 0 ? 10 + (int64_t)((g + 9) / 10) : 0);
+            int64_t cost = (int64_t)(dx < dy ? dx : dy) + (g > 0 ? 10 + (int64_t)((g + 9) / 10) : 0) +
+                           (int64_t)o;
             int64_t v = n2[b].score - cost;
             if (v > best || (v == best && v > 0 && (cx[b] > bx || (cx[b] == bx && cy[b] > by)))) {
                 best = v; bp = b; bx = cx[b]; by = cy[b];
@@ -464,9 +498,13 @@ static void align_region(const uint8_t *bytes, const uint64_t *off, uint32_t nse
             uint32_t c = corder[c2[t]];
             for (uint32_t v = s1[c]; v < s1[c + 1]; v++) {
                 const sa_anchor *A = &an[c1[v]];
+                uint32_t o = 0, dx = 0, dy = 0;
                 if (first) { X0 = A->x; Y0 = A->y; first = 0; }
-                else align_segment(Q + px, A->x - px, T + py, A->y - py, &ops);
-                ops_push(&ops, OP_EQ, A->len);
+                else {
+                    sa_link(px, py, A->x, A->y, A->len, &o, &dx, &dy);
+                    align_segment(Q + px, dx, T + py, dy, &ops);
+                }
+                ops_push(&ops, OP_EQ, A->len - o);
                 px = A->x + A->len; py = A->y + A->len;
             }
         }
@@ -521,7 +559,7 @@ static void align_region(const uint8_t *bytes, const uint64_t *off, uint32_t nse
         free(ops.ops);
     }
     free(Q); free(T); free(tk); free(mt); free(an); free(n1); free(ax); free(ay); free(c1);
-    free(s1); free(cx); free(cy); free(cex); free(cey); free(cw); free(corder); free(n2);
+    free(s1); free(cx); free(cy); free(cex); free(cey); free(cfl); free(cw); free(corder); free(n2);
     free(c2); free(s2);
 }
 

@@ -12,13 +12,16 @@
 //      search; seeds occurring more than 32 times are skipped;
 //   2. matches as keys (region, diagonal, query position), radix sorted;
 //      maximal runs of consecutive positions on a diagonal are the anchors;
-//   3. tier 1: one thread per region scores its anchors in (x, y) order,
-//      looking for predecessors among the anchors that end within the gap
-//      limit (a second sorted order, by end); the anchors are then ordered
-//      by (region, score descending, x, y) and one thread per region takes
-//      the chains out; the chains become nodes, ordered by (region, x, y);
-//   4. tier 2: one thread per region chains the nodes (affine cost, gaps up
-//      to 10 kbp) and takes the final chains out;
+//   3. tier 1: one 64-lane workgroup per region scores its anchors in
+//      (x, y) order, its lanes testing the predecessors that end within the
+//      gap limit or inside the anchor itself (a link then cuts the overlap
+//      from the later anchor's start), a window of a second order, by end;
+//      the anchors are then ordered by (region, score descending, x, y) and
+//      one thread per region takes the chains out; the chains become nodes,
+//      ordered by (region, x, y) and by (region, end);
+//   4. tier 2: the same scoring over the nodes (affine cost, gaps up to
+//      10 kbp), the same ordering and one thread per region taking the
+//      final chains out;
 //   5. the stretches between consecutive anchors of every final chain are
 //      aligned by one thread each (three-state affine recurrence over two
 //      rolling rows, one byte of traceback per cell);
@@ -205,56 +208,115 @@ struct Tier1 {
     uint32_t *pred;
 };
 
-// 3a. tier-1 scores, one thread per region; anchors visited in (x, y) order,
-// predecessors found among those ending in [x - G1, x] (the by-end order).
-__global__ void k_tier1(Anchors an, const uint32_t *byxy, const uint64_t *endkey,
-                        const uint32_t *byend, const uint32_t *bnd, uint32_t nr, uint32_t G1,
-                        Tier1 t1) {
-    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+// A link from an anchor or chain ending at (bex, bey) to one starting at
+// (ax, ay) whose first anchor has alen bases.  The successor's start is cut
+// by o = max(0, bex - ax, bey - ay) so that it begins after the predecessor
+// ends on both sides (anchors flanking an indel overlap whenever a base next
+// to it matches by chance); false when the cut would take the whole first
+// anchor.  dx, dy: the gaps left after the cut (both >= 0).
+__device__ __forceinline__ bool link_trim(uint32_t bex, uint32_t bey, uint32_t ax, uint32_t ay,
+                                          uint32_t alen, uint32_t &o, uint32_t &dx,
+                                          uint32_t &dy) {
+    uint32_t t = bex > ax ? bex - ax : 0u;
+    if (bey > ay && bey - ay > t) t = bey - ay;
+    if (t >= alen) return false;
+    o = t;
+    dx = ax + t - bex;
+    dy = ay + t - bey;
+    return true;
+}
+
+__device__ __forceinline__ uint32_t absdiff(uint32_t a, uint32_t b) { return a > b ? a - b : b - a; }
+
+// The best predecessor seen by a lane: largest value, then (for values
+// above 0) the larger start (x, then y).  Starts are unique within a
+// region, so the choice does not depend on the order candidates are met.
+struct Best {
+    int64_t v;
+    uint32_t x, y, b;
+};
+
+__device__ __forceinline__ bool better(int64_t v, uint32_t x, uint32_t y, const Best &B) {
+    return v > B.v || (v == B.v && v > 0 && (x > B.x || (x == B.x && y > B.y)));
+}
+
+__device__ __forceinline__ Best wave_best(Best B) {
+    for (int m = 32; m >= 1; m >>= 1) {
+        Best o;
+        o.v = __shfl_xor(B.v, m);
+        o.x = __shfl_xor(B.x, m);
+        o.y = __shfl_xor(B.y, m);
+        o.b = __shfl_xor(B.b, m);
+        if (better(o.v, o.x, o.y, B)) B = o;
+    }
+    return B;
+}
+
+// Scores are written by lane 0 and read by every lane of the wave in later
+// steps: workgroup-scope atomics, with a release fence after each step.
+__device__ __forceinline__ int64_t ld_score(const int64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void st_score(int64_t *p, int64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Advances p0 (an entry of a key-sorted list [., hi)) to the first key >=
+// klo; keys below klo form a prefix, so each lane tests one entry and the
+// wave moves 64 at a time.
+__device__ __forceinline__ uint32_t skip_below(const uint64_t *key, uint32_t p0, uint32_t hi,
+                                               uint64_t klo) {
+    for (;;) {
+        const uint32_t v = p0 + threadIdx.x;
+        const uint32_t c = (uint32_t)__popcll(__ballot(v < hi && key[v] < klo));
+        p0 += c;
+        if (c < 64) return p0;
+    }
+}
+
+// 3a. tier-1 scores (the longest chains: a link costs the indel |dx - dy|
+// it implies plus its cut, gaps at most G1), one 64-lane workgroup per
+// region.  Anchors are scored one after another in (x, y) order; the
+// predecessors of an anchor are the earlier anchors ending in [x - G1, x +
+// len) (a window of the by-end order whose lower end only moves forward),
+// tested by the lanes 64 at a time.
+__global__ __launch_bounds__(64) void k_tier1(Anchors an, const uint32_t *byxy,
+                                              const uint64_t *endkey, const uint32_t *byend,
+                                              const uint32_t *bnd, uint32_t nr, uint32_t G1,
+                                              Tier1 t1) {
+    const uint32_t r = blockIdx.x;
     if (r >= nr) return;
     const uint32_t lo = bnd[r], hi = bnd[r + 1];
+    uint32_t p0 = lo;
     for (uint32_t u = lo; u < hi; u++) {
         const uint32_t a = byxy[u];
-        const uint32_t x = an.x[a], y = an.y[a];
-        const uint64_t xlo = x >= G1 ? x - G1 : 0;
-        // by-end entries of region r with end x in [xlo, x]
-        uint32_t b0 = lo, b1 = hi;
-        {
-            const uint64_t kx = ((uint64_t)r << 42) | (xlo << 21);
-            uint32_t l = lo, h = hi;
-            while (l < h) {
-                const uint32_t m = (l + h) >> 1;
-                if (endkey[m] < kx) l = m + 1; else h = m;
+        const uint32_t x = an.x[a], y = an.y[a], len = an.len[a];
+        const uint64_t rk = (uint64_t)r << 42;
+        p0 = skip_below(endkey, p0, hi, rk | ((uint64_t)(x >= G1 ? x - G1 : 0) << 21));
+        const uint64_t khi = rk | ((uint64_t)(x + len) << 21);
+        Best B{0, 0, 0, NONE32};
+        for (uint32_t base = p0; base < hi; base += 64) {
+            const uint32_t v = base + threadIdx.x;
+            const bool in = v < hi && endkey[v] < khi;
+            if (in) {
+                const uint32_t b = byend[v];
+                const uint32_t bx = an.x[b], by = an.y[b];
+                uint32_t o, dx, dy;
+                if ((bx < x || (bx == x && by < y)) &&
+                    link_trim(bx + an.len[b], by + an.len[b], x, y, len, o, dx, dy) &&
+                    (dx > dy ? dx : dy) <= G1) {
+                    const int64_t val = ld_score(t1.score + b) - (int64_t)absdiff(dx, dy) - (int64_t)o;
+                    if (better(val, bx, by, B)) B = Best{val, bx, by, b};
+                }
             }
-            b0 = l;
-            const uint64_t ky = ((uint64_t)r << 42) | ((uint64_t)(x + 1) << 21);
-            h = hi;
-            while (l < h) {
-                const uint32_t m = (l + h) >> 1;
-                if (endkey[m] < ky) l = m + 1; else h = m;
-            }
-            b1 = l;
+            if (__ballot(!in)) break;  // the window ends in this chunk
         }
-        int64_t best = 0;
-        uint32_t bp = NONE32, bx = 0, by = 0;
-        for (uint32_t v = b0; v < b1; v++) {
-            const uint32_t b = byend[v];
-            const uint32_t ey = an.y[b] + an.len[b], ex = an.x[b] + an.len[b];
-            if (ey > y) continue;
-            const uint32_t dx = x - ex, dy = y - ey;
-            const uint32_t g = dx > dy ? dx : dy;
-            if (g > G1) continue;
-            const int64_t val = t1.score[b] - (int64_t)g;
-            if (val > best ||
-                (val == best && val > 0 && (an.x[b] > bx || (an.x[b] == bx && an.y[b] > by)))) {
-                best = val;
-                bp = b;
-                bx = an.x[b];
-                by = an.y[b];
-            }
+        B = wave_best(B);
+        if (threadIdx.x == 0) {
+            st_score(t1.score + a, (int64_t)len + B.v);
+            t1.pred[a] = B.v > 0 ? B.b : NONE32;
         }
-        t1.score[a] = (int64_t)an.len[a] + best;
-        t1.pred[a] = best > 0 ? bp : NONE32;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     }
 }
 
@@ -309,9 +371,10 @@ __global__ void k_extract1(Anchors an, const uint32_t *byscore, const uint32_t *
             w += an.len[b];
             if (v < m) {
                 const uint32_t p = tmp[lo + v];
-                const uint32_t dx = an.x[b] - (an.x[p] + an.len[p]);
-                const uint32_t dy = an.y[b] - (an.y[p] + an.len[p]);
-                w -= dx > dy ? dx : dy;
+                uint32_t o = 0, dx = 0, dy = 0;
+                link_trim(an.x[p] + an.len[p], an.y[p] + an.len[p], an.x[b], an.y[b], an.len[b], o,
+                          dx, dy);
+                w -= (int64_t)absdiff(dx, dy) + o;
             }
         }
         c.end[node] = pos;
@@ -349,58 +412,93 @@ struct Final {
     uint32_t *count;         // final chains per region
 };
 
-// 4. tier 2 (one thread per region): the region's nodes are the sorted
-// entries [nbnd[r], nbnd[r+1]) of `nodes`, in (x, y) order; predecessors by
-// the affine cost, then extraction in score order (insertion sort of the
-// region's nodes).  Final chains of the region use entries from nbnd[r] on.
-__global__ void k_tier2(const uint32_t *nbnd, uint32_t nr, const uint32_t *nodes,
-                        const Chains1 c, int64_t *score, uint32_t *pred, uint32_t *order,
-                        uint8_t *used, uint32_t *tmp, Final fin) {
+// 4a. tier-2 scores, one 64-lane workgroup per region: the region's
+// nodes (tier-1 chains) are the entries [nbnd[r], nbnd[r+1]) of `nodes`
+// (by start) and of `nodes_e` (by end, keys ekey); the predecessors of a
+// node are the earlier ones ending in [x - 10000, x + first anchor length),
+// with the affine cost plus the cut.
+__global__ __launch_bounds__(64) void k_tier2(const Anchors an, const uint32_t *nbnd, uint32_t nr,
+                                              const uint32_t *nodes, const uint64_t *ekey,
+                                              const uint32_t *nodes_e, const Chains1 c,
+                                              int64_t *score, uint32_t *pred) {
+    const uint32_t r = blockIdx.x;
+    if (r >= nr) return;
+    const uint32_t lo = nbnd[r], hi = nbnd[r + 1];
+    uint32_t p0 = lo;
+    for (uint32_t u = lo; u < hi; u++) {
+        const uint32_t a = nodes[u];
+        const uint32_t x = c.cx[a], y = c.cy[a];
+        const uint32_t flen = an.len[c.member[c.start[a]]];  // its first anchor
+        const uint64_t rk = (uint64_t)r << 42;
+        p0 = skip_below(ekey, p0, hi,
+                        rk | ((uint64_t)(x >= TIER2_GAP ? x - TIER2_GAP : 0) << 21));
+        const uint64_t khi = rk | ((uint64_t)(x + flen) << 21);
+        Best B{0, 0, 0, NONE32};
+        for (uint32_t base = p0; base < hi; base += 64) {
+            const uint32_t v = base + threadIdx.x;
+            const bool in = v < hi && ekey[v] < khi;
+            if (in) {
+                const uint32_t b = nodes_e[v];
+                const uint32_t bx = c.cx[b], by = c.cy[b];
+                uint32_t o, dx, dy;
+                if ((bx < x || (bx == x && by < y)) &&
+                    link_trim(c.cex[b], c.cey[b], x, y, flen, o, dx, dy) &&
+                    (dx > dy ? dx : dy) <= TIER2_GAP) {
+                    const uint32_t g = absdiff(dx, dy);
+                    const int64_t cost = (int64_t)(dx < dy ? dx : dy) +
+                                         (g > 0 ? 10 + (int64_t)((g + 9) / 10) : 0) + (int64_t)o;
+                    const int64_t val = ld_score(score + b) - cost;
+                    if (better(val, bx, by, B)) B = Best{val, bx, by, b};
+                }
+            }
+            if (__ballot(!in)) break;
+        }
+        B = wave_best(B);
+        if (threadIdx.x == 0) {
+            st_score(score + a, c.w[a] + B.v);
+            pred[a] = B.v > 0 ? B.b : NONE32;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    }
+}
+
+// Keys of the node entries: pass 0 by end (region, ex, ey); pass 1 and 2
+// the extraction order, y first (stable), then (region, score descending,
+// x).  Entries past the live nodes of every region sort last.
+__global__ void k_node_keys2(const uint32_t *nodes, uint64_t na, const uint32_t *nlive,
+                             const uint32_t *reg_of_slot, const Chains1 c, const int64_t *score,
+                             int pass, const uint32_t *perm, uint64_t *key, uint32_t *val) {
+    const uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= na) return;
+    const uint32_t e = perm ? perm[u] : (uint32_t)u;  // entry of `nodes`
+    const uint32_t s = nodes[e];
+    const bool live = e < *nlive;
+    const uint32_t r = reg_of_slot[s];
+    if (pass == 0) {
+        key[u] = live ? (((uint64_t)r << 42) | ((uint64_t)c.cex[s] << 21) | c.cey[s]) : ~0ull;
+        val[u] = s;
+    } else if (pass == 1) {
+        key[u] = live ? c.cy[s] : ~0ull;
+        val[u] = e;
+    } else {
+        // scores lie in (-2^20, 2^20]: shifted by 2^20 they fit 22 bits
+        const uint64_t inv = (1ull << 22) - 1 - (uint64_t)(score[s] + (1ll << 20));
+        key[u] = live ? (((uint64_t)r << 42) | (inv << 20) | c.cx[s]) : ~0ull;
+        val[u] = s;
+    }
+}
+
+// 4b. final chains of a region (one thread): nodes in extraction order, each
+// following kept predecessors until a used one.  Final chains of the region
+// use entries from nbnd[r] on.
+__global__ void k_extract2(const uint32_t *nbnd, uint32_t nr, const uint32_t *order,
+                           const uint32_t *pred, uint8_t *used, uint32_t *tmp, Final fin) {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nr) return;
-    const uint32_t lo = nbnd[r], n = nbnd[r + 1] - lo;
-    for (uint32_t u = 0; u < n; u++) {
-        const uint32_t a = nodes[lo + u];
-        int64_t best = 0;
-        uint32_t bp = NONE32, bx = 0, by = 0;
-        for (uint32_t v = 0; v < u; v++) {
-            const uint32_t b = nodes[lo + v];
-            if (c.cex[b] > c.cx[a] || c.cey[b] > c.cy[a]) continue;
-            const uint32_t dx = c.cx[a] - c.cex[b], dy = c.cy[a] - c.cey[b];
-            if ((dx > dy ? dx : dy) > TIER2_GAP) continue;
-            const uint32_t g = dx > dy ? dx - dy : dy - dx;
-            const int64_t cost =
-                (int64_t)(dx < dy ? dx : dy) + (g > 0 ? 10 + (int64_t)((g + 9) / 10) : 0);
-            const int64_t val = score[b] - cost;
-            if (val > best ||
-                (val == best && val > 0 && (c.cx[b] > bx || (c.cx[b] == bx && c.cy[b] > by)))) {
-                best = val;
-                bp = b;
-                bx = c.cx[b];
-                by = c.cy[b];
-            }
-        }
-        score[a] = c.w[a] + best;
-        pred[a] = best > 0 ? bp : NONE32;
-    }
-    // extraction order: score descending, then x, then y
-    for (uint32_t u = 0; u < n; u++) {
-        const uint32_t a = nodes[lo + u];
-        uint32_t v = u;
-        while (v > 0) {
-            const uint32_t b = order[lo + v - 1];
-            const bool before = score[a] > score[b] ||
-                                (score[a] == score[b] &&
-                                 (c.cx[a] < c.cx[b] || (c.cx[a] == c.cx[b] && c.cy[a] < c.cy[b])));
-            if (!before) break;
-            order[lo + v] = b;
-            v--;
-        }
-        order[lo + v] = a;
-    }
+    const uint32_t lo = nbnd[r], hi = nbnd[r + 1];
     uint32_t pos = lo, nf = 0;
-    for (uint32_t u = 0; u < n; u++) {
-        uint32_t a = order[lo + u];
+    for (uint32_t u = lo; u < hi; u++) {
+        uint32_t a = order[u];
         if (used[a]) continue;
         uint32_t m = 0;
         while (a != NONE32 && !used[a]) {
@@ -462,7 +560,8 @@ __global__ void k_seg_count(const Anchors an, const Chains1 c, const Final fin,
     bool first = true;
     walk_anchors(c, fin, e, [&](uint32_t a) {
         if (!first) {
-            const uint32_t dx = an.x[a] - px, dy = an.y[a] - py;
+            uint32_t o = 0, dx = 0, dy = 0;
+            link_trim(px, py, an.x[a], an.y[a], an.len[a], o, dx, dy);
             ns++;
             const uint64_t cc = seg_cells(dx, dy);
             cells += cc;
@@ -492,13 +591,13 @@ __global__ void k_seg_emit(const Anchors an, const Chains1 c, const Final fin,
     bool first = true;
     walk_anchors(c, fin, e, [&](uint32_t a) {
         if (!first) {
+            uint32_t o = 0;
             Seg x;
             x.chain = (uint32_t)g;
             x.region = r;
             x.qx = px;
             x.ty = py;
-            x.dx = an.x[a] - px;
-            x.dy = an.y[a] - py;
+            link_trim(px, py, an.x[a], an.y[a], an.len[a], o, x.dx, x.dy);
             x.cells = cells;
             x.ops = ops;
             x.rows = rows;
@@ -676,7 +775,10 @@ __global__ void k_assemble(const IndexView ix, const ARegion *reg, const Anchors
     bool first = true;
     uint32_t qi = 0, ti = 0;
     walk_anchors(c, fin, e, [&](uint32_t a) {
+        uint32_t o = 0;  // bases cut from the anchor's start by its link
         if (!first) {
+            uint32_t dx = 0, dy = 0;
+            link_trim(qi, ti, an.x[a], an.y[a], an.len[a], o, dx, dy);
             const Seg &S = seg[s];
             const uint8_t *col = cols + S.ops;
             for (uint32_t u = 0; u < ncol[s]; u++) {
@@ -713,11 +815,12 @@ __global__ void k_assemble(const IndexView ix, const ARegion *reg, const Anchors
             ti = an.y[a];
         }
         first = false;
-        emit(OP_EQ, an.len[a]);
-        st.aln += an.len[a];
-        st.match += an.len[a];
-        qi += an.len[a];
-        ti += an.len[a];
+        const uint32_t keep = an.len[a] - o;
+        emit(OP_EQ, keep);
+        st.aln += keep;
+        st.match += keep;
+        qi += keep;
+        ti += keep;
         st.ex = qi;
         st.ey = ti;
     });
@@ -873,7 +976,7 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     DevBuf<int64_t> s1(A);
     DevBuf<uint32_t> p1(A);
     Tier1 t1{s1.p, p1.p};
-    k_tier1<<<nb(n, 64), 64, 0, st>>>(an, byxy.p, kend.p, byend.p, bnd.p, nr, G1, t1);
+    k_tier1<<<nr, 64, 0, st>>>(an, byxy.p, kend.p, byend.p, bnd.p, nr, G1, t1);
     SDF_HIP(hipGetLastError());
     // score order: y first (stable), then (region, score descending, x)
     k_score_keys<<<nb(A), 256, 0, st>>>(an, A, t1, 0, kbuf.p, perm.p, nullptr);
@@ -897,13 +1000,28 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     radix_sort_u64(kbuf.p, nodes.p, A, 64, st);
     k_region_bounds<<<nb(n + 1), 256, 0, st>>>(kbuf.p, A, 42, nr, nbnd.p);
     SDF_HIP(hipGetLastError());
-    // 4. tier 2
+    // 4. tier 2: nodes by end, scores, extraction order, final chains
+    DevBuf<uint32_t> nodes_e(A), order(A);
+    DevBuf<uint64_t> ekey(A);
     DevBuf<int64_t> s2(A);
-    DevBuf<uint32_t> p2(A), order(A), fmem(A), fst(A), fend(A), fcount(n + 1);
+    DevBuf<uint32_t> p2(A), fmem(A), fst(A), fend(A), fcount(n + 1);
+    k_node_keys2<<<nb(A), 256, 0, st>>>(nodes.p, A, nbnd.p + nr, rslot.p, c, s2.p, 0, nullptr,
+                                        ekey.p, nodes_e.p);
+    SDF_HIP(hipGetLastError());
+    radix_sort_u64(ekey.p, nodes_e.p, A, 64, st);
+    k_tier2<<<nr, 64, 0, st>>>(an, nbnd.p, nr, nodes.p, ekey.p, nodes_e.p, c, s2.p, p2.p);
+    SDF_HIP(hipGetLastError());
+    k_node_keys2<<<nb(A), 256, 0, st>>>(nodes.p, A, nbnd.p + nr, rslot.p, c, s2.p, 1, nullptr,
+                                        kbuf.p, perm.p);
+    SDF_HIP(hipGetLastError());
+    radix_sort_u64(kbuf.p, perm.p, A, 20, st);
+    k_node_keys2<<<nb(A), 256, 0, st>>>(nodes.p, A, nbnd.p + nr, rslot.p, c, s2.p, 2, perm.p,
+                                        kbuf.p, order.p);
+    SDF_HIP(hipGetLastError());
+    radix_sort_u64(kbuf.p, order.p, A, 64, st);
     fill_u32(reinterpret_cast<uint32_t *>(used.p), 0u, (A + 3) / 4, st);
     Final fin{fmem.p, fst.p, fend.p, fcount.p};
-    k_tier2<<<nb(n, 64), 64, 0, st>>>(nbnd.p, nr, nodes.p, c, s2.p, p2.p, order.p, used.p, tmp.p,
-                                      fin);
+    k_extract2<<<nb(n, 64), 64, 0, st>>>(nbnd.p, nr, order.p, p2.p, used.p, tmp.p, fin);
     SDF_HIP(hipGetLastError());
     DevBuf<uint64_t> foff(n + 1);
     scan_u32_to_u64(fcount.p, foff.p, n, st);

@@ -161,3 +161,42 @@ def test_pipeline_closed_forms(orc, strand):
         assert s["k2p"] == pytest.approx(-0.5 * math.log(1 - 2 * p), abs=1e-15)
         if mism == 0:
             assert _ops(ops) == [("=", 2000)]
+
+
+def homopolymer_deletions(seed, length=3000, n=15):
+    """A random sequence and its copy with one base deleted from each of n
+    homopolymer pairs (x[p] == x[p + 1]) at least 150 bases apart: the
+    anchors on the two sides of every deletion overlap by at least one
+    base."""
+    rng = synth.rng_for(seed)
+    x = synth.random_bases(rng, length)
+    cut, last = [], -1000
+    for p in range(100, length - 100):
+        if x[p] == x[p + 1] and p - last >= 150 and len(cut) < n:
+            cut.append(p)
+            last = p
+    keep = np.ones(length, bool)
+    keep[cut] = False
+    return x, x[keep], len(cut)
+
+
+@pytest.mark.parametrize("strand", [0, 1])
+def test_pipeline_links_overlapping_anchors(orc, strand):
+    """Single-base deletions inside homopolymers leave anchors that overlap
+    across each deletion; the links trim them, so the copy is still one SD
+    over both sequences: every base of the shorter side matched, one
+    one-base gap per deletion, no mismatch."""
+    x, y, n = homopolymer_deletions(78)
+    assert n == 15
+    flank = synth.random_bases(synth.rng_for(79), 300)
+    t = synth.revcomp(y) if strand else y
+    b = np.concatenate([x, flank, t])
+    off = np.array([0, len(x), len(x) + len(flank), len(b)], np.uint64)
+    row = (0, len(x), len(x) + len(flank), len(b), strand)
+    sd, ops = orc.sd_align(b, off, [row], k=11, min_len=1000, max_error=0.25)
+    assert len(sd) == 1
+    s = sd[0]
+    assert (s["q_begin"], s["q_end"], s["t_begin"], s["t_end"]) == (0, len(x), 0, len(y))
+    assert (s["aln_len"], s["matches"], s["mismatches"], s["ins"], s["dels"], s["gap_opens"]) == \
+        (len(x), len(y), 0, n, 0, n)
+    assert s["jc"] == 0.0 and s["k2p"] == 0.0

@@ -149,6 +149,8 @@ def batched_vs_plain(steps, plain=True, cpu=True, max_error=0.25, min_len=1000):
     t0 = time.perf_counter()
     core, threads, tune_ms = ix.autotune(spans)
     tune_s = time.perf_counter() - t0
+    # the measured schedule holds for this thread's searches from here on
+    sdf.set_tuning(tile_core=core, tile_threads=threads)
     tb, kms, ncand, stats = timed()
     # the same batch captured once as a HIP graph and replayed
     stream = torch.cuda.Stream()
@@ -179,6 +181,7 @@ def batched_vs_plain(steps, plain=True, cpu=True, max_error=0.25, min_len=1000):
         lat.append((time.perf_counter() - s0) * 1e3)
     torch.cuda.synchronize()
     tp = time.perf_counter() - t0
+    sdf.set_tuning()  # back to the library's choices
     tuning = {"autotuned_core": core, "autotuned_threads": threads,
               "autotune_s": round(tune_s, 3),
               "tile_kernel_ms_per_schedule": {"%d threads, %d starts" % k: round(v, 3)
@@ -638,6 +641,7 @@ def chromosome_section(args, steps):
     span = spans[0]
     qbases = span[2] - span[1]
     tuned_core, tuned_threads, tuned_ms = ix.autotune([span], args.max_error, args.min_len)
+    sdf.set_tuning(tile_core=tuned_core, tile_threads=tuned_threads)
     for _ in range(2):
         r = ix.search(span, args.max_error, args.min_len, timing=True)
         r.candidates()
@@ -655,6 +659,7 @@ def chromosome_section(args, steps):
         r.close()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    sdf.set_tuning()
     mean_k = float(np.mean(kernel_ms))
     alg = qbases * alg_bytes_per_query_base(nm, ne, g.total, hbar)
     out = {"workload": desc, "path": "plain single-span search",

@@ -361,23 +361,66 @@ sdf_status sdf_search_batch_capped(sdf_index ix, const sdf_span *qs, uint32_t n,
                                    const sdf_search_params *p, uint64_t max_device_bytes,
                                    void *hip_stream, sdf_result *out, uint64_t *peak_bytes);
 
+/*
+ * Schedule and test settings of the library's internal choices.  They hold
+ * for the calling thread only (thread-local), for every later call it makes
+ * until changed, so searches that other threads run at the same time keep
+ * their own.  A field set to SDF_AUTO keeps the library's choice.  Results
+ * do not depend on any of them: they choose tile shapes, launch sizes and
+ * the limits below which a faster path is taken (set low, they force the
+ * general paths on small inputs).
+ */
+#define SDF_AUTO 0xFFFFFFFFu
+typedef struct {
+    uint32_t tile_threads;        /* tile workgroup: 512 (two per CU) or 1024 threads */
+    uint32_t tile_core;           /* window starts per tile (capped by the layout) */
+    uint32_t hits_per_part;       /* target hits per partition of a tile (>= 1024) */
+    uint32_t wg_per_cu;           /* persistent tile workgroups per CU slot (>= 1) */
+    uint32_t span_few_max;        /* most spans set up by one workgroup (0: none) */
+    uint32_t kept_cap;            /* kept hits a partition holds before its windows
+                                     go to the dense-window pass */
+    uint32_t phase_prof;          /* 1: per-phase clocks in the result's stats */
+    uint32_t chain_fused_max;     /* most seeds chained by one workgroup (0: none) */
+    uint32_t cand_sort_general;   /* 1: candidates ordered by the record sort alone */
+    uint32_t cand_sort_small_max; /* most candidates sorted by one workgroup */
+    uint32_t cand_tie_max;        /* longest run of equal sort prefixes ordered in place */
+    uint32_t est_lds_cap;         /* estimate mode: most hashes of a run held in LDS */
+    uint32_t est_reg_cap;         /* estimate mode: most held in registers */
+    uint32_t est_first_amax;      /* estimate mode: largest window of the first launch */
+    uint32_t ext_h0;              /* extension: steps gathered per phase and attempt */
+    uint32_t ext_lds_words;       /* extension: ordered-set cells kept in LDS */
+    uint32_t ext_hb0;             /* extension: backward steps gathered early */
+    uint32_t ext_hdiv;            /* extension: horizon as 1/hdiv of the longer side */
+    uint32_t ext_batch_min;       /* extension: smallest batch of insertions */
+    uint32_t ext_ecap;            /* extension: scratch elements per workgroup (>= 64) */
+    uint32_t ext_stats;           /* 1: one line of extension counters on stderr per call */
+} sdf_tuning;
+
+/* Every field of *t set to SDF_AUTO. */
+void sdf_tuning_defaults(sdf_tuning *t);
+/* Installs *t for the calling thread (NULL: every field SDF_AUTO).
+ * SDF_EINVAL for a tile_threads other than 512, 1024 or SDF_AUTO. */
+sdf_status sdf_set_tuning(const sdf_tuning *t);
+/* The calling thread's settings. */
+sdf_status sdf_get_tuning(sdf_tuning *t);
+
 /* Autotuner of the tile schedule: runs the search of the n spans (host
  * array, as for sdf_search_batch, with p's error bound and length; the
  * timing, estimate and extension flags are ignored) with every schedule in
- * turn, timing the tile kernel (second of two runs each, HIP events), and
- * keeps the fastest for later searches on this index.  The schedules, in
- * order: 1,024-thread workgroups (one per CU) at 512 to 1,024 window starts
- * per tile in steps of 64, then 512-thread workgroups (two per CU) at 512
- * window starts when a window of p's length holds at most 1,024 minimizers
- * (length <= 1,023 + k).  *core_out and *threads_out (each may be NULL)
- * receive the window starts and workgroup size kept; ms_out (may be NULL)
- * receives up to n_ms kernel times in that order (10 at most).  n == 0
- * forgets the choice (the hit-density rules apply again).  Search results
- * do not depend on the schedule.  Not to be called while other searches on
- * the same index are running.  Errors as for sdf_search_batch. */
+ * turn, timing the tile kernel (second of two runs each, HIP events).  The
+ * schedules, in order: 1,024-thread workgroups (one per CU) at 512 to 1,024
+ * window starts per tile in steps of 64, then 512-thread workgroups (two
+ * per CU) at 512 window starts when a window of p's length holds at most
+ * 1,024 minimizers (length <= 1,023 + k).  *out receives the calling
+ * thread's settings with tile_core and tile_threads set to the fastest
+ * schedule: install it with sdf_set_tuning in every thread that searches
+ * (the index is not changed, so autotuning may run beside other searches on
+ * it).  ms_out (may be NULL) receives up to n_ms kernel times in that order
+ * (10 at most).  n == 0 times nothing and returns the settings unchanged.
+ * Errors as for sdf_search_batch. */
 sdf_status sdf_autotune(sdf_index ix, const sdf_span *spans, uint32_t n,
-                        const sdf_search_params *p, void *hip_stream, uint32_t *core_out,
-                        uint32_t *threads_out, float *ms_out, uint32_t n_ms);
+                        const sdf_search_params *p, void *hip_stream, sdf_tuning *out,
+                        float *ms_out, uint32_t n_ms);
 
 /*
  * The batched search of a fixed set of spans captured once as a HIP graph
@@ -441,7 +484,8 @@ sdf_status sdf_result_timing(sdf_result r, float *ms, uint32_t n_ms);
  * [8] minimizers inserted by the extension, [9] attempts that continued a
  * phase past its gathered horizon, [10] distinct hashes ranked, [11] and
  * [12] workgroup microseconds spent gathering and ranking, and in the
- * phases, [13] microseconds of the slowest region. */
+ * phases, [13] microseconds of the slowest region; [14] window starts per
+ * tile and [15] tile workgroup threads of the schedule the search ran. */
 sdf_status sdf_result_stats(sdf_result r, uint64_t *v, uint32_t n_v);
 
 void sdf_result_free(sdf_result r);

@@ -13,7 +13,17 @@
 
 namespace sdf {
 const char *last_error();
-}
+
+// The calling thread's settings (sdf_set_tuning), every field SDF_AUTO at first.
+static thread_local sdf_tuning g_tuning = {SDF_AUTO, SDF_AUTO, SDF_AUTO, SDF_AUTO, SDF_AUTO,
+                                           SDF_AUTO, SDF_AUTO, SDF_AUTO, SDF_AUTO, SDF_AUTO,
+                                           SDF_AUTO, SDF_AUTO, SDF_AUTO, SDF_AUTO, SDF_AUTO,
+                                           SDF_AUTO, SDF_AUTO, SDF_AUTO, SDF_AUTO, SDF_AUTO,
+                                           SDF_AUTO};
+static_assert(sizeof(sdf_tuning) == 21 * sizeof(uint32_t), "every setting listed");
+
+const sdf_tuning &tuning() { return g_tuning; }
+}  // namespace sdf
 
 using namespace sdf;
 
@@ -256,11 +266,6 @@ Params derive(const sdf_search_params *p, uint32_t k, uint32_t w) {
     return r;
 }
 
-uint32_t env_u32(const char *name, uint32_t def) {
-    const char *v = std::getenv(name);
-    if (!v || !*v) return def;
-    return (uint32_t)std::strtoul(v, nullptr, 10);
-}
 
 // Window starts per tile: as many as keep a tile's hits within one target
 // partition (hits per window start run about 1.15 hbar, and splitting a tile
@@ -412,29 +417,27 @@ void prepare(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const Params &P, 
         fill_upload(ix, qs, nq, P, smax, t_bytes, up.host());
         up.send(pr.dup.p, st);
     }
-    // tile layout and window starts per tile: the environment overrides
-    // (SDF_TILE_THREADS, SDF_TILE_CORE), else the measured choice of
-    // sdf_autotune, else the hit-density rules
+    // tile layout and window starts per tile: the autotuner's trial
+    // schedule, else the calling thread's settings (sdf_set_tuning, where
+    // sdf_autotune's choice goes), else the hit-density rules
+    const sdf_tuning &tu = tuning();
     uint32_t threads = threads_override
                            ? threads_override
-                           : (ix->tuned_threads ? ix->tuned_threads
-                                                : tile_threads_rule(ix->hbar, P.n, ix->k));
-    threads = env_u32("SDF_TILE_THREADS", threads) == 512 ? 512u : 1024u;
+                           : knob(tu.tile_threads, tile_threads_rule(ix->hbar, P.n, ix->k));
     if (!fits_tile512(P.n, ix->k)) threads = 1024;
     const uint32_t cmax = threads == 512 ? tile512::tile_core_max() : tile1024::tile_core_max();
     const uint32_t hpart =
-        std::max<uint32_t>(env_u32("SDF_HITS_PER_PART", threads == 512 ? 8192 : 16384), 1024);
-    const uint32_t pick = core_override ? core_override
-                                        : (ix->tuned_core ? ix->tuned_core
-                                                          : auto_tile_core(ix->hbar, hpart, cmax));
-    const uint32_t core = std::min(std::max<uint32_t>(env_u32("SDF_TILE_CORE", pick), 1), cmax);
+        std::max<uint32_t>(knob(tu.hits_per_part, threads == 512 ? 8192 : 16384), 1024);
+    const uint32_t pick =
+        core_override ? core_override : knob(tu.tile_core, auto_tile_core(ix->hbar, hpart, cmax));
+    const uint32_t core = std::min(std::max<uint32_t>(pick, 1), cmax);
     pr.threads = threads;
     pr.core = core;
     pr.hpart = hpart;
     pr.ntiles.alloc(nq + 1);
     pr.tile0.alloc(nq + 1);
-    // the SDF_SPAN_FEW_MAX environment variable lowers the one-launch limit (0: off)
-    const uint32_t few_max = std::min<uint32_t>(env_u32("SDF_SPAN_FEW_MAX", SPAN_FEW), SPAN_FEW);
+    // spans set up by one workgroup at most (the settings may lower it; 0: none)
+    const uint32_t few_max = std::min<uint32_t>(knob(tu.span_few_max, SPAN_FEW), SPAN_FEW);
     if (nq > 0 && nq <= few_max) {
         k_span_setup_few<<<1, 64 * nq, 0, st>>>(ix->view(), pr.dsd, nq, P.n, core, pr.tile0.p);
         SDF_HIP(hipGetLastError());
@@ -453,7 +456,7 @@ void prepare(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const Params &P, 
     }
     pr.grid = (uint32_t)std::max<uint64_t>(
         1, std::min<uint64_t>((uint64_t)cu_count(ix->device) * (threads == 512 ? 2u : 1u) *
-                                  env_u32("SDF_WG_PER_CU", 1),
+                                  std::max<uint32_t>(knob(tu.wg_per_cu, 1), 1),
                               std::max<uint64_t>(tile_bound, 1)));
 }
 
@@ -493,9 +496,9 @@ SearchArgs tile_args(sdf_index_s *ix, const Params &P, const Prepared &pr, uint3
     a.runs_out = runs_out;
     a.dense = dense;
     a.dense_cap = dense_cap;
-    // test hook: SDF_KEPT_CAP lowers the kept hits a partition may hold, so
-    // that ordinary windows take the dense-window pass
-    a.kept_cap = env_u32("SDF_KEPT_CAP", 0xFFFFFFFFu);
+    // kept hits a partition may hold (the settings may lower it, so that
+    // ordinary windows take the dense-window pass)
+    a.kept_cap = tuning().kept_cap;
     return a;
 }
 
@@ -527,7 +530,7 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
     unsigned long long *const counters = zblock.p;
     unsigned long long *const phase = zblock.p + CNT_N;
     uint32_t *const work = reinterpret_cast<uint32_t *>(zblock.p + CNT_N + PH_N);
-    const bool phase_prof = env_u32("SDF_PHASE_PROF", 0) != 0;
+    const bool phase_prof = tuning().phase_prof == 1;
     unsigned long long hc[CNT_N] = {};
     uint32_t herr = 0;
     uint64_t dense_cap = dense_capacity(qbases);
@@ -905,18 +908,36 @@ sdf_status sdf_search(sdf_index ix, const sdf_span *q, const sdf_search_params *
     return sdf_search_batch(ix, q, 1, p, hip_stream, out);
 }
 
-sdf_status sdf_autotune(sdf_index ix, const sdf_span *qs, uint32_t n, const sdf_search_params *p,
-                        void *hip_stream, uint32_t *core_out, uint32_t *threads_out,
-                        float *ms_out, uint32_t n_ms) {
+void sdf_tuning_defaults(sdf_tuning *t) {
+    if (!t) return;
+    uint32_t *f = reinterpret_cast<uint32_t *>(t);
+    for (size_t i = 0; i < sizeof(sdf_tuning) / sizeof(uint32_t); i++) f[i] = SDF_AUTO;
+}
+
+sdf_status sdf_set_tuning(const sdf_tuning *t) {
     return guarded([&] {
-        if (!ix) throw Error{SDF_EINVAL, "NULL index"};
-        if (n == 0) {  // back to the hit-density rules
-            ix->tuned_core = 0;
-            ix->tuned_threads = 0;
-            if (core_out) *core_out = 0;
-            if (threads_out) *threads_out = 0;
-            return;
-        }
+        sdf_tuning v;
+        if (t) v = *t;
+        else sdf_tuning_defaults(&v);
+        if (v.tile_threads != SDF_AUTO && v.tile_threads != 512 && v.tile_threads != 1024)
+            throw Error{SDF_EINVAL, "tile_threads must be 512, 1024 or SDF_AUTO"};
+        g_tuning = v;
+    });
+}
+
+sdf_status sdf_get_tuning(sdf_tuning *t) {
+    return guarded([&] {
+        if (!t) throw Error{SDF_EINVAL, "NULL argument"};
+        *t = g_tuning;
+    });
+}
+
+sdf_status sdf_autotune(sdf_index ix, const sdf_span *qs, uint32_t n, const sdf_search_params *p,
+                        void *hip_stream, sdf_tuning *out, float *ms_out, uint32_t n_ms) {
+    return guarded([&] {
+        if (!ix || !out) throw Error{SDF_EINVAL, "NULL argument"};
+        *out = g_tuning;
+        if (n == 0) return;
         if (!qs || !p) throw Error{SDF_EINVAL, "NULL argument"};
         SDF_HIP(hipSetDevice(ix->device));
         const hipStream_t st = (hipStream_t)hip_stream;
@@ -949,10 +970,8 @@ sdf_status sdf_autotune(sdf_index ix, const sdf_span *qs, uint32_t n, const sdf_
                 best_ms = ms;
             }
         }
-        ix->tuned_core = best;
-        ix->tuned_threads = best_threads;
-        if (core_out) *core_out = best;
-        if (threads_out) *threads_out = best_threads;
+        out->tile_core = best;
+        out->tile_threads = best_threads;
     });
 }
 
@@ -1185,6 +1204,8 @@ sdf_status sdf_result_stats(sdf_result r, uint64_t *v, uint32_t n_v) {
     return guarded([&] {
         if (!r || (n_v && !v)) throw Error{SDF_EINVAL, "NULL argument"};
         for (uint32_t t = 0; t < n_v && t < 14; t++) v[t] = r->stats[t];
+        if (n_v > 14) v[14] = r->core;
+        if (n_v > 15) v[15] = r->threads;
     });
 }
 

@@ -834,7 +834,7 @@ static void finish_candidates(DevBuf<sdf_candidate> &cands, DevCount nc, const I
     const uint32_t qb = bitlen(nspans > 0 ? nspans - 1 : 0), sb = bitlen(ix.nseq > 0 ? ix.nseq - 1 : 0);
     const uint32_t pb = bitlen(ix.total), head = qb + 1 + sb;
     const uint32_t shift = head + pb > 64 ? head + pb - 64 : 0;
-    bool general = std::getenv("SDF_CAND_SORT_GENERAL") != nullptr || shift > pb;
+    bool general = tuning().cand_sort_general == 1 || shift > pb;
     if (general && deferred) throw Error{SDF_EINVAL, "candidate keys too wide for a captured search"};
     if (ncb > 1 && !general) {
         DevBuf<uint64_t> key(ncb);
@@ -842,10 +842,8 @@ static void finish_candidates(DevBuf<sdf_candidate> &cands, DevCount nc, const I
         k_cand_prefix<<<nb(ncb), 256, 0, st>>>(cands.p, nc, CandPrefix{sb, pb, shift}, key.p, order.p);
         SDF_HIP(hipGetLastError());
         const int kbits = (int)(head + pb - shift);
-        // test hook: SDF_CAND_SORT_SMALL_MAX lowers the count sorted by one workgroup
-        uint64_t small_max = SR_N;
-        if (const char *v = std::getenv("SDF_CAND_SORT_SMALL_MAX"))
-            small_max = std::min<uint64_t>(SR_N, std::strtoull(v, nullptr, 10));
+        // the most candidates one workgroup sorts (the settings may lower it)
+        const uint64_t small_max = std::min<uint64_t>(SR_N, knob(tuning().cand_sort_small_max, SR_N));
         if (ncb <= small_max && kbits <= 50) {
             k_sort_small<<<1, SR_TB, 0, st>>>(key.p, nc, kbits, order.p);
             SDF_HIP(hipGetLastError());
@@ -855,10 +853,8 @@ static void finish_candidates(DevBuf<sdf_candidate> &cands, DevCount nc, const I
         DevBuf<sdf_candidate> sorted(n2);
         k_permute_cands<<<nb(ncb), 256, 0, st>>>(cands.p, order.p, nc, sorted.p);
         SDF_HIP(hipGetLastError());
-        // test hook: SDF_CAND_TIE_MAX lowers the longest run ordered in place
-        uint32_t tie_max = TIE_MAX;
-        if (const char *v = std::getenv("SDF_CAND_TIE_MAX"))
-            tie_max = std::min<uint32_t>(TIE_MAX, (uint32_t)std::strtoul(v, nullptr, 10));
+        // the longest run ordered in place (the settings may lower it)
+        const uint32_t tie_max = std::min<uint32_t>(TIE_MAX, knob(tuning().cand_tie_max, TIE_MAX));
         k_cand_ties<<<nb(ncb), 256, 0, st>>>(key.p, nc, tie_max, sorted.p, long_run);
         SDF_HIP(hipGetLastError());
         cands = std::move(sorted);
@@ -922,10 +918,8 @@ void chain_seeds(const IndexView &ix, const uint32_t *seeds, DevCount nsc, uint3
     const uint32_t qbits = bitlen(nspans > 0 ? nspans - 1 : 0);
     const uint32_t gbits = qbits + 1 + ck.cbits;
     // fused path below CS_N seeds (room for the segment sentinel); the
-    // SDF_CHAIN_FUSED_MAX environment variable lowers the limit (0: off)
-    uint64_t fused_max = CS_N - 1;
-    if (const char *v = std::getenv("SDF_CHAIN_FUSED_MAX"))
-        fused_max = std::min<uint64_t>(fused_max, std::strtoull(v, nullptr, 10));
+    // settings may lower the limit (0: never)
+    const uint64_t fused_max = std::min<uint64_t>(CS_N - 1, knob(tuning().chain_fused_max, CS_N - 1));
     uint64_t cap = 0;  // candidate capacity
     if (ns <= fused_max && gbits + ck.ibits <= 64) {
         cap = deferred ? nc_bound : ns;  // candidates <= seeds

@@ -481,17 +481,13 @@ void launch_estimate_runs(const IndexView &ix, const uint32_t *runs, uint64_t nr
                           const uint16_t *T, uint32_t *seeds, uint64_t cap,
                           unsigned long long *nseeds, uint32_t *err, hipStream_t st) {
     if (nruns == 0) return;
-    // test hooks: SDF_EST_LDS_CAP / SDF_EST_REG_CAP lower the sizes held in
-    // LDS and registers (0 sends every run down the general paths);
-    // SDF_EST_FIRST_AMAX lowers the window size of the first launch (0 hands
-    // every run to the second)
-    uint32_t lds_cap = TCAP_L, reg_cap = 128, amax_s = AMAX_S;
-    if (const char *v = std::getenv("SDF_EST_LDS_CAP"))
-        lds_cap = std::min<uint32_t>(TCAP_L, (uint32_t)std::strtoul(v, nullptr, 10));
-    if (const char *v = std::getenv("SDF_EST_REG_CAP"))
-        reg_cap = std::min<uint32_t>(128, (uint32_t)std::strtoul(v, nullptr, 10));
-    if (const char *v = std::getenv("SDF_EST_FIRST_AMAX"))
-        amax_s = std::min<uint32_t>(AMAX_S, (uint32_t)std::strtoul(v, nullptr, 10));
+    // the settings may lower the sizes held in LDS and registers (0 sends
+    // every run down the general paths) and the window size of the first
+    // launch (0 hands every run to the second)
+    const sdf_tuning &tu = tuning();
+    const uint32_t lds_cap = std::min<uint32_t>(TCAP_L, knob(tu.est_lds_cap, TCAP_L));
+    const uint32_t reg_cap = std::min<uint32_t>(128, knob(tu.est_reg_cap, 128));
+    const uint32_t amax_s = std::min<uint32_t>(AMAX_S, knob(tu.est_first_amax, AMAX_S));
     DevBuf<uint32_t> over(nruns);
     DevBuf<unsigned long long> nover(1);
     SDF_HIP(hipMemsetAsync(nover.p, 0, 8, st));

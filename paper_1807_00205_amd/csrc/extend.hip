@@ -1069,27 +1069,19 @@ void launch_extend(const IndexView &ix, const sdf_region *in, uint64_t n, double
     int dev = 0, cus = 0;
     SDF_HIP(hipGetDevice(&dev));
     SDF_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    // test hooks: SDF_EXT_H0 sets the horizon, SDF_EXT_LDS_WORDS the cells
-    // kept in LDS (0 keeps L in global memory), SDF_EXT_ECAP the elements per
-    // workgroup, SDF_EXT_BATCH_MIN the smallest batch (0: one step at a time),
-    // SDF_EXT_HDIV the horizon as a fraction of the longer side, SDF_EXT_HB0 the
-    // backward horizon gathered while the forward phase is pending
-    // each attempt gathers max(h0, longer side / hdiv) steps per phase; a phase
-    // that runs through them continues in the next attempt
-    uint64_t h0 = 16384, ecap = 1ull << 18;
-    uint32_t ldsw = LDS_WORDS;
-    if (const char *v = std::getenv("SDF_EXT_H0")) h0 = std::strtoull(v, nullptr, 10);
-    if (const char *v = std::getenv("SDF_EXT_LDS_WORDS"))
-        ldsw = std::min<uint32_t>(LDS_WORDS, (uint32_t)std::strtoul(v, nullptr, 10));
-    uint32_t batch_min = 4, hdiv = 1;
-    uint64_t hb0 = 512;
-    if (const char *v = std::getenv("SDF_EXT_HB0")) hb0 = std::strtoull(v, nullptr, 10);
-    if (const char *v = std::getenv("SDF_EXT_HDIV"))
-        hdiv = std::max<uint32_t>(1, (uint32_t)std::strtoul(v, nullptr, 10));
-    if (const char *v = std::getenv("SDF_EXT_BATCH_MIN"))
-        batch_min = (uint32_t)std::strtoul(v, nullptr, 10);
-    if (const char *v = std::getenv("SDF_EXT_ECAP"))
-        ecap = std::max<uint64_t>(64, std::strtoull(v, nullptr, 10));
+    // each attempt gathers max(h0, longer side / hdiv) steps per phase; a
+    // phase that runs through them continues in the next attempt.  The
+    // settings may change the horizon (h0, hdiv), the cells kept in LDS (0
+    // keeps L in global memory), the elements per workgroup, the smallest
+    // batch (0: one step at a time) and the backward horizon gathered while
+    // the forward phase is pending (hb0)
+    const sdf_tuning &tu = tuning();
+    const uint64_t h0 = knob(tu.ext_h0, 16384);
+    const uint64_t ecap = std::max<uint64_t>(64, knob(tu.ext_ecap, 1u << 18));
+    const uint32_t ldsw = std::min<uint32_t>(LDS_WORDS, knob(tu.ext_lds_words, LDS_WORDS));
+    const uint32_t batch_min = knob(tu.ext_batch_min, 4);
+    const uint32_t hdiv = std::max<uint32_t>(1, knob(tu.ext_hdiv, 1));
+    const uint64_t hb0 = knob(tu.ext_hb0, 512);
     // as many workgroups as fit a CU's LDS; each keeps its own scratch
     const uint64_t per_cu = std::max<uint64_t>(1, (160u * 1024u) / sizeof(Shared));
     const uint64_t grid = std::min<uint64_t>(n, (uint64_t)std::max(1, cus) * per_cu);
@@ -1133,7 +1125,8 @@ void launch_extend(const IndexView &ix, const sdf_region *in, uint64_t n, double
     if (herr & XE_HASH)
         throw Error{SDF_EINTERNAL, "extend: more than 512 distinct hashes share 11 hash bits"};
     if (herr & XE_STATE) throw Error{SDF_EINTERNAL, "extend: inconsistent ordered set"};
-    if (stats || std::getenv("SDF_EXT_STATS")) {
+    const bool print = tu.ext_stats == 1;
+    if (stats || print) {
         ExtStats local;
         if (!stats) stats = &local;
         int khz = 0;
@@ -1145,7 +1138,7 @@ void launch_extend(const IndexView &ix, const sdf_region *in, uint64_t n, double
         stats->rank_us = (unsigned long long)((double)hc[3] * us);
         stats->loop_us = (unsigned long long)((double)hc[4] * us);
         stats->slowest_us = (unsigned long long)((double)hc[5] * us);
-        if (std::getenv("SDF_EXT_STATS"))
+        if (print)
             fprintf(stderr,
                     "[sdf extend] regions=%llu insertions=%llu continued=%llu ranks=%llu "
                     "rank_ms=%.2f phase_ms=%.2f slowest_ms=%.2f big_buckets=%llu\n",

@@ -12,6 +12,12 @@
 
 namespace sdf {
 
+// The calling thread's schedule and test settings (sdf_set_tuning).
+const sdf_tuning &tuning();
+// A setting, or def where it is SDF_AUTO.
+inline uint32_t knob(uint32_t v, uint32_t def) { return v == SDF_AUTO ? def : v; }
+
+
 constexpr uint32_t NONE32 = 0xFFFFFFFFu;
 constexpr uint64_t SENT64 = 0xFFFFFFFFFFFFFFFFull;
 constexpr uint64_t MAX_TOTAL = 0xFFFFFFFFull - (1ull << 20);
@@ -219,8 +225,6 @@ struct sdf_index_s {
     sdf::DevBuf<uint32_t> packed, mask, gaps;
     uint64_t nm = 0, ne = 0, nseg = 0;
     double hbar = 0.0;  // mean target occurrences of a query minimizer's hash
-    uint32_t tuned_core = 0;     // window starts per tile chosen by sdf_autotune (0: the rule)
-    uint32_t tuned_threads = 0;  // tile workgroup layout chosen by sdf_autotune (0: the rule)
     sdf::DevBuf<uint32_t> mpos, mhash, mprev, mext;
     sdf::DevBuf<uint8_t> mflags;
     sdf::DevBuf<uint32_t> dir, epos, esamp;

@@ -6,6 +6,7 @@ built; there is no CPU path.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import itertools
 import os
@@ -51,7 +52,8 @@ EXPORTS = ["sdf_last_error", "sdf_index_build", "sdf_index_info", "sdf_index_hit
            "sdf_extend", "sdf_result_regions", "sdf_qgram_filter", "sdf_autotune",
            "sdf_search_batch_noalloc", "sdf_plan_create", "sdf_plan_run", "sdf_plan_info",
            "sdf_plan_free", "sdf_search_batch_capped", "sdf_align_regions", "sdf_sds_count",
-           "sdf_sds_copy", "sdf_sds_free"]
+           "sdf_sds_copy", "sdf_sds_free", "sdf_tuning_defaults", "sdf_set_tuning",
+           "sdf_get_tuning"]
 NOALLOC_SCRATCH_BYTES = 128 << 20
 NOALLOC_MAX_SPANS = 65536
 NOALLOC_MAX_QUERY_BASES = 8_000_000
@@ -70,6 +72,18 @@ class SdfError(RuntimeError):
 
 class _IndexParams(ctypes.Structure):
     _fields_ = [("k", ctypes.c_uint32), ("w", ctypes.c_uint32)]
+
+
+AUTO = 0xFFFFFFFF
+TUNING_FIELDS = ("tile_threads", "tile_core", "hits_per_part", "wg_per_cu", "span_few_max",
+                 "kept_cap", "phase_prof", "chain_fused_max", "cand_sort_general",
+                 "cand_sort_small_max", "cand_tie_max", "est_lds_cap", "est_reg_cap",
+                 "est_first_amax", "ext_h0", "ext_lds_words", "ext_hb0", "ext_hdiv",
+                 "ext_batch_min", "ext_ecap", "ext_stats")
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint32) for f in TUNING_FIELDS]
 
 
 class _SearchParams(ctypes.Structure):
@@ -200,7 +214,13 @@ def lib() -> ctypes.CDLL:
         L.sdf_extend.restype = st
         L.sdf_extend.argtypes = [vp, vp, u64, P(_ExtendParams), vp, vp]
         L.sdf_autotune.restype = st
-        L.sdf_autotune.argtypes = [vp, vp, u32, P(_SearchParams), vp, P(u32), P(u32),
+        L.sdf_tuning_defaults.restype = None
+        L.sdf_tuning_defaults.argtypes = [P(_Tuning)]
+        L.sdf_set_tuning.restype = st
+        L.sdf_set_tuning.argtypes = [P(_Tuning)]
+        L.sdf_get_tuning.restype = st
+        L.sdf_get_tuning.argtypes = [P(_Tuning)]
+        L.sdf_autotune.argtypes = [vp, vp, u32, P(_SearchParams), vp, P(_Tuning),
                                    P(ctypes.c_float), u32]
         L.sdf_qgram_filter.restype = st
         L.sdf_qgram_filter.argtypes = [vp, vp, u64, P(_QgramParams), vp, vp, vp]
@@ -237,6 +257,40 @@ def lib() -> ctypes.CDLL:
 def _check(rc: int):
     if rc != SDF_OK:
         raise SdfError(rc, lib().sdf_last_error().decode())
+
+
+def get_tuning() -> dict:
+    """The calling thread's schedule and test settings (``sdf_get_tuning``);
+    AUTO marks the library's choice."""
+    t = _Tuning()
+    _check(lib().sdf_get_tuning(ctypes.byref(t)))
+    return {f: int(getattr(t, f)) for f in TUNING_FIELDS}
+
+
+def set_tuning(**settings) -> None:
+    """Installs settings for the calling thread (``sdf_set_tuning``); fields
+    not given (or given as None) keep the library's choice."""
+    t = _Tuning()
+    lib().sdf_tuning_defaults(ctypes.byref(t))
+    for k, v in settings.items():
+        if k not in TUNING_FIELDS:
+            raise TypeError("unknown setting %r" % k)
+        setattr(t, k, AUTO if v is None else int(v))
+    _check(lib().sdf_set_tuning(ctypes.byref(t)))
+
+
+@contextlib.contextmanager
+def tuning(**settings):
+    """The calling thread's settings with these changed, for the duration of
+    the block; the previous ones are put back after it."""
+    prev = get_tuning()
+    cur = dict(prev)
+    cur.update(settings)
+    set_tuning(**cur)
+    try:
+        yield
+    finally:
+        set_tuning(**prev)
 
 
 def _stream_ptr(stream) -> Optional[int]:
@@ -298,15 +352,24 @@ class Result:
         _check(lib().sdf_result_timing(self._h, ms, 6))
         return np.array(ms[:], dtype=np.float64)
 
+    def _stats(self):
+        v = (ctypes.c_uint64 * 16)()
+        _check(lib().sdf_result_stats(self._h, v, 16))
+        return [int(x) for x in v]
+
     def stats(self, extension: bool = False) -> dict:
-        v = (ctypes.c_uint64 * 14)()
-        _check(lib().sdf_result_stats(self._h, v, 14))
+        v = self._stats()
         keys = ["windows", "hits", "kept", "tiles", "partitions", "seeds", "candidate_evals",
                 "scan_words"]
         if extension:
             keys += ["ext_insertions", "ext_continued", "ext_ranks", "ext_rank_us",
                      "ext_phase_us", "ext_slowest_region_us"]
-        return dict(zip(keys, [int(x) for x in v]))
+        return dict(zip(keys, v))
+
+    def schedule(self) -> Tuple[int, int]:
+        """(window starts per tile, tile workgroup threads) the search ran."""
+        v = self._stats()
+        return v[14], v[15]
 
 
 class Plan:
@@ -441,22 +504,24 @@ class Index:
 
     def autotune(self, spans: Iterable[Tuple[int, int, int]], max_error: float = 0.25,
                  min_len: int = 1000, stream=None):
-        """Times the tile kernel on these spans with every schedule and keeps the
-        fastest for later searches (``sdf_autotune``); returns (window starts,
-        workgroup threads, {(threads, window starts): ms}).  No spans: back to
-        the built-in rules."""
+        """Times the tile kernel on these spans with every schedule
+        (``sdf_autotune``); returns (window starts, workgroup threads,
+        {(threads, window starts): ms}) of the fastest.  The index is not
+        changed: searches use the schedule where the caller installs it
+        (``set_tuning(tile_core=..., tile_threads=...)`` or ``tuning(...)``).
+        No spans: the calling thread's settings, nothing timed."""
         arr, nspans = _span_array(spans)
         p = _SearchParams(max_error, min_len, 0)
-        core, threads = ctypes.c_uint32(), ctypes.c_uint32()
+        out = _Tuning()
         ms = (ctypes.c_float * 16)()
         _check(lib().sdf_autotune(self._h, arr.ctypes.data_as(ctypes.c_void_p), nspans,
-                                  ctypes.byref(p), _stream_ptr(stream), ctypes.byref(core),
-                                  ctypes.byref(threads), ms, 16))
+                                  ctypes.byref(p), _stream_ptr(stream), ctypes.byref(out), ms,
+                                  16))
         sched = [(1024, c) for c in range(512, 1025, 64)]
         if min_len <= 1023 + self.k:
             sched.append((512, 512))
         times = {k: float(ms[i]) for i, k in enumerate(sched)} if spans else {}
-        return core.value, threads.value, times
+        return int(out.tile_core), int(out.tile_threads), times
 
     def qgram_filter(self, regions: np.ndarray, q: int, gap_rate: float,
                      max_error: float = 0.25, stream=None):

@@ -21,7 +21,8 @@ so the count of hits times the windows per minimizer overshoots the real
 need by one to three orders of magnitude).
 
 The plain mode (``workers=1, max_batch=1``) is the one-request-at-a-time
-FIFO baseline.
+FIFO baseline.  ``tuning`` (settings for ``sdf.set_tuning``, such as the
+schedule ``Index.autotune`` returns) is installed in every worker thread.
 """
 from __future__ import annotations
 
@@ -72,9 +73,10 @@ class Request:
 class Server:
     def __init__(self, index: sdf.Index, workers: int = 2, max_batch: int = 4096,
                  hbm_budget: Optional[int] = None, max_error: float = 0.25,
-                 min_len: int = 1000):
+                 min_len: int = 1000, tuning: Optional[dict] = None):
         import torch
         self.index = index
+        self.tuning = dict(tuning or {})
         self.max_batch = max_batch
         self.max_error, self.min_len = max_error, min_len
         if hbm_budget is None:
@@ -119,6 +121,7 @@ class Server:
         return batch
 
     def _work(self, stream):
+        sdf.set_tuning(**self.tuning)  # the settings are per thread
         while True:
             with self.cv:
                 while not self.stop and not (self.queue and

@@ -204,7 +204,7 @@ def test_search_estimate_tandem_and_config1(S, oracle_lib, seed, length, n_seqs,
     _same(r.candidates(), oc, CAND_F, "candidates config1")
 
 
-def test_search_estimate_general_paths(S, oracle_lib, monkeypatch):
+def test_search_estimate_general_paths(S, oracle_lib):
     """Estimate mode with the run's target minimizers read from global
     memory per candidate and the outside hashes counted through LDS (the
     paths taken by long runs and dense windows), and with runs handed from
@@ -218,11 +218,9 @@ def test_search_estimate_general_paths(S, oracle_lib, monkeypatch):
     for lds, reg, first in (("0", "0", "256"), ("0", "128", "256"), ("1024", "0", "256"),
                             ("8", "3", "256"), ("512", "128", "0"), ("512", "128", "64"),
                             ("0", "0", "64")):
-        monkeypatch.setenv("SDF_EST_LDS_CAP", lds)
-        monkeypatch.setenv("SDF_EST_REG_CAP", reg)
-        monkeypatch.setenv("SDF_EST_FIRST_AMAX", first)
         what = "lds=%s reg=%s first=%s" % (lds, reg, first)
-        r = ix.search_batch(g.spans, 0.25, 400, estimate=True)
+        with S.tuning(est_lds_cap=int(lds), est_reg_cap=int(reg), est_first_amax=int(first)):
+            r = ix.search_batch(g.spans, 0.25, 400, estimate=True)
         _same(r.seeds(), os_, SEED_F, "seeds " + what)
         _same(r.candidates(), oc, CAND_F, "candidates " + what)
 
@@ -239,7 +237,7 @@ def test_search_config1(S, oracle_lib):
     _same(r.candidates(), oc, CAND_F, "candidates")
 
 
-def test_search_config1_tile_shapes(S, oracle_lib, monkeypatch):
+def test_search_config1_tile_shapes(S, oracle_lib):
     """Results do not depend on the tile size or the target partitioning."""
     g = synth.config1()
     b, off = g.concat()
@@ -247,14 +245,13 @@ def test_search_config1_tile_shapes(S, oracle_lib, monkeypatch):
     os_, oc = orc.search(g.spans, 0.25, 1000)
     ix = S.Index(g.seqs, 12, 16)
     for core, hpart in ((64, 1024), (200, 3000), (512, 100000), (1024, 16384), (1000, 4096)):
-        monkeypatch.setenv("SDF_TILE_CORE", str(core))
-        monkeypatch.setenv("SDF_HITS_PER_PART", str(hpart))
-        r = ix.search(g.spans[0], 0.25, 1000)
+        with S.tuning(tile_core=core, hits_per_part=hpart):
+            r = ix.search(g.spans[0], 0.25, 1000)
         _same(r.seeds(), os_, SEED_F, "seeds core=%d" % core)
         _same(r.candidates(), oc, CAND_F, "candidates core=%d" % core)
 
 
-def test_chaining_fused_equals_general(S, oracle_lib, monkeypatch):
+def test_chaining_fused_equals_general(S, oracle_lib):
     """The one-workgroup chaining used below 2,048 seeds and the multi-kernel
     chaining give the same candidates (and the oracle's), for spans whose
     seed counts fall on both sides of the limit."""
@@ -269,8 +266,8 @@ def test_chaining_fused_equals_general(S, oracle_lib, monkeypatch):
         _, oc = orc.search([sp], 0.25, 1000)
         out = []
         for lim in ("0", "2047", "100000"):
-            monkeypatch.setenv("SDF_CHAIN_FUSED_MAX", lim)
-            r = ix.search(sp, 0.25, 1000)
+            with S.tuning(chain_fused_max=int(lim)):
+                r = ix.search(sp, 0.25, 1000)
             out.append(r.candidates())
             ns = r.stats()["seeds"]
             seen.add(("fused" if ns <= min(int(lim), 2047) else "general", ns < 2048))
@@ -280,14 +277,13 @@ def test_chaining_fused_equals_general(S, oracle_lib, monkeypatch):
 
 
 @pytest.mark.parametrize("threads", ["512", "1024"])
-def test_tile_layouts(S, oracle_lib, monkeypatch, threads):
+def test_tile_layouts(S, oracle_lib, threads):
     """Both workgroup layouts of the tile kernel (1,024 threads with 1,280
     query minimizers, 2,048 kept hits and 16k bin slots per tile; 512 threads,
     two per CU, with 1,024, 1,024 and 4k) give the oracle's seeds and
     candidates, in count and estimate mode, on planted duplications in
     several sequences, tandem arrays and 1 Mbp with 20 duplications; the
     narrow one also with its smallest partitions."""
-    monkeypatch.setenv("SDF_TILE_THREADS", threads)
     cases = [(_mixed_genome(7, length=8000), 200, False),
              (synth.tandem_case(94, length=200_000, n_arrays=120, copies_hi=60, n_seqs=2), 200,
               False),
@@ -301,17 +297,16 @@ def test_tile_layouts(S, oracle_lib, monkeypatch, threads):
         os_, oc = orc.search(spans, 0.25, min_len, estimate=est)
         ix = S.Index(g.seqs, 12, 16)
         for hp in (["16384", "1024"] if threads == "512" else ["16384"]):
-            monkeypatch.setenv("SDF_HITS_PER_PART", hp)
-            r = ix.search_batch(spans, 0.25, min_len, estimate=est)
+            with S.tuning(tile_threads=int(threads), hits_per_part=int(hp)):
+                r = ix.search_batch(spans, 0.25, min_len, estimate=est)
             assert len(os_) > 0
             _same(r.seeds(), os_, SEED_F, "seeds")
             _same(r.candidates(), oc, CAND_F, "candidates")
-        monkeypatch.delenv("SDF_HITS_PER_PART")
         ix.close()
 
 
 @pytest.mark.parametrize("path", ["prefix", "prefix_multiblock", "long_ties", "general"])
-def test_candidate_sort_paths(S, oracle_lib, monkeypatch, path):
+def test_candidate_sort_paths(S, oracle_lib, path):
     """Every sort of the chained candidates gives the oracle's order: keys on
     a prefix of query, strand, sequence and begin (sorted by one workgroup,
     or by the multi-block radix sort used above 16,384 candidates) with ties
@@ -319,12 +314,8 @@ def test_candidate_sort_paths(S, oracle_lib, monkeypatch, path):
     records, and that bitonic sort alone; on batches with several query
     spans, sequences and both strands, and on tandem arrays whose candidates
     share begins."""
-    if path == "prefix_multiblock":
-        monkeypatch.setenv("SDF_CAND_SORT_SMALL_MAX", "0")
-    if path == "long_ties":
-        monkeypatch.setenv("SDF_CAND_TIE_MAX", "1")
-    if path == "general":
-        monkeypatch.setenv("SDF_CAND_SORT_GENERAL", "1")
+    settings = {"prefix": {}, "prefix_multiblock": {"cand_sort_small_max": 0},
+                "long_ties": {"cand_tie_max": 1}, "general": {"cand_sort_general": 1}}[path]
     for g in (_mixed_genome(5, length=8000), synth.tandem_case(93, length=200_000, n_arrays=120,
                                                                copies_hi=60, n_seqs=3)):
         b, off = g.concat()
@@ -332,7 +323,8 @@ def test_candidate_sort_paths(S, oracle_lib, monkeypatch, path):
         orc = oracle_lib.OracleIndex(b, off, 12, 16)
         _, oc = orc.search(spans, 0.25, 200)
         ix = S.Index(g.seqs, 12, 16)
-        r = ix.search_batch(spans, 0.25, 200)
+        with S.tuning(**settings):
+            r = ix.search_batch(spans, 0.25, 200)
         assert len(oc) > 1
         _same(r.candidates(), oc, CAND_F, "candidates")
         ix.close()
@@ -557,8 +549,9 @@ def test_serving_retries_small_reservations(S, batch250, monkeypatch):
 
 def test_autotune_keeps_results(S):
     """sdf_autotune times every tile schedule (both workgroup layouts) on a
-    span set and keeps the fastest; searches after it return the same seeds
-    and candidates, and forgetting the choice restores the built-in rules."""
+    span set and returns the fastest; searches under it return the same
+    seeds and candidates.  The index is not changed: the calling thread's
+    settings stay the library's choice until the schedule is installed."""
     g = synth.config1()
     ix = S.Index(g.seqs, 12, 16)
     spans = synth.draw_spans(synth.rng_for(12), [len(s) for s in g.seqs], 48, 5000, 60000)
@@ -568,10 +561,13 @@ def test_autotune_keeps_results(S):
     assert len(ms) == 10 and (512, 512) in ms
     assert (threads, core) in ms and ms[(threads, core)] == min(ms.values())
     assert all(m > 0 for m in ms.values())
-    r1 = ix.search_batch(spans)
+    assert S.get_tuning()["tile_core"] == S.AUTO
+    with S.tuning(tile_core=core, tile_threads=threads):
+        r1 = ix.search_batch(spans)
+        assert r1.schedule() == (core, threads)
     _same(r1.seeds(), s0, SEED_F, "seeds after autotune")
     _same(r1.candidates(), c0, CAND_F, "candidates after autotune")
-    assert ix.autotune([])[0] == 0
+    assert ix.autotune([])[:2] == (S.AUTO, S.AUTO)
 
 
 def _dense_genome(seed):
@@ -606,34 +602,33 @@ def dense_case(oracle_lib):
 
 
 @pytest.mark.parametrize("threads", ["512", "1024"])
-def test_dense_windows(S, dense_case, monkeypatch, threads):
+def test_dense_windows(S, dense_case, threads):
     """Windows too dense for a tile (inside a 5 kbp uppercase homopolymer
     and (AC)n arrays: every position, or every other one, is a minimizer of
     one hash) go through the dense-window pass: seeds and candidates equal
     the oracle's in both tile layouts, and in the no-allocation search."""
-    monkeypatch.setenv("SDF_TILE_THREADS", threads)
     seqs, os_, oc = dense_case
     ix = S.Index(seqs, 12, 16)
-    r = ix.search_batch(DENSE_SPANS)
+    with S.tuning(tile_threads=int(threads)):
+        r = ix.search_batch(DENSE_SPANS)
+        got, n = ix.search_batch_noalloc(DENSE_SPANS)
     _same(r.seeds(), os_, SEED_F, "seeds")
     _same(r.candidates(), oc, CAND_F, "candidates")
     assert len(oc) > 0
-    got, n = ix.search_batch_noalloc(DENSE_SPANS)
     _same(got, oc, CAND_F, "no-allocation search")
 
 
 @pytest.mark.parametrize("threads", ["512", "1024"])
-def test_dense_pass_forced(S, oracle_lib, monkeypatch, threads):
+def test_dense_pass_forced(S, oracle_lib, threads):
     """With the kept-hit limit of a tile lowered to 64, ordinary windows of
     mixed and tandem inputs become dense: the dense-window pass gives the
     oracle's seeds and candidates for them."""
-    monkeypatch.setenv("SDF_TILE_THREADS", threads)
-    monkeypatch.setenv("SDF_KEPT_CAP", "64")
     for g in (synth.tandem_case(7, length=20_000, n_seqs=2), _mixed_genome(9, 8000)):
         b, off = g.concat()
         ix = S.Index(g.seqs, 12, 16)
         orc = oracle_lib.OracleIndex(b, off, 12, 16)
-        r = ix.search_batch(g.spans, 0.25, 200)
+        with S.tuning(tile_threads=int(threads), kept_cap=64):
+            r = ix.search_batch(g.spans, 0.25, 200)
         os_, oc = orc.search(g.spans, 0.25, 200)
         _same(r.seeds(), os_, SEED_F, "seeds")
         _same(r.candidates(), oc, CAND_F, "candidates")

@@ -112,22 +112,19 @@ def test_extend_small(S, oracle_lib, case, max_error, min_len, k, w):
         _same(got, _oracle_extend(orc, off, boxes, tau, cap), "cap %d" % cap)
 
 
-@pytest.mark.parametrize("hook", [{"SDF_EXT_H0": "1"}, {"SDF_EXT_LDS_WORDS": "0"},
-                                  {"SDF_EXT_ECAP": "3000"},
-                                  {"SDF_EXT_H0": "0", "SDF_EXT_LDS_WORDS": "16"},
-                                  {"SDF_EXT_BATCH_MIN": "0"}, {"SDF_EXT_BATCH_MIN": "1"},
-                                  {"SDF_EXT_BATCH_MIN": "1", "SDF_EXT_LDS_WORDS": "0",
-                                   "SDF_EXT_H0": "64"}],
+@pytest.mark.parametrize("hook", [{"ext_h0": 1}, {"ext_lds_words": 0},
+                                  {"ext_ecap": 3000},
+                                  {"ext_h0": 0, "ext_lds_words": 16},
+                                  {"ext_batch_min": 0}, {"ext_batch_min": 1},
+                                  {"ext_batch_min": 1, "ext_lds_words": 0, "ext_h0": 64}],
                          ids=["continue", "global-cells", "small-scratch", "mixed",
                               "one-at-a-time", "batch-always", "batch-global"])
-def test_extend_general_paths(S, oracle_lib, monkeypatch, hook):
+def test_extend_general_paths(S, oracle_lib, hook):
     """The paths that large or long-running regions take, forced on small
     inputs: phases that run through their horizon and continue in a new
     attempt, the ordered set kept in global memory instead of LDS, horizons
     shrunk to fit the scratch, and insertions applied one at a time or in
     batches as small as one."""
-    for kv in hook.items():
-        monkeypatch.setenv(*kv)
     g = synth.small_case(81, length=8000, n_sd=4, sd_lo=800, sd_hi=2000, n_seqs=2,
                          lower_frac=0.2, n_gaps=1, gap_len=30, rate_hi=0.05)
     b, off = g.concat()
@@ -138,21 +135,21 @@ def test_extend_general_paths(S, oracle_lib, monkeypatch, hook):
     boxes = np.concatenate([_boxes_from_cands(S, oc),
                             _random_boxes(S, np.random.default_rng(9), g.seqs, 10)])
     ix = S.Index(g.seqs, 12, 16)
-    _same(ix.extend(boxes, 0.25), _oracle_extend(orc, off, boxes, tau), str(hook))
+    with S.tuning(**hook):
+        got = ix.extend(boxes, 0.25)
+    _same(got, _oracle_extend(orc, off, boxes, tau), str(hook))
 
 
-def test_extend_scratch_overflow_is_an_error(S, monkeypatch):
+def test_extend_scratch_overflow_is_an_error(S):
     """A region whose start windows alone exceed the per-workgroup scratch
     is reported as SDF_EINTERNAL, and the index stays usable."""
     rng = synth.rng_for(5)
     A = synth.random_bases(rng, 8000)
     ix = S.Index([A, A.copy()], 12, 16)
     box = [(0, 0, 1000, 5000, 1, 1000, 5000)]
-    monkeypatch.setenv("SDF_EXT_ECAP", "200")
-    with pytest.raises(S.SdfError) as e:
+    with S.tuning(ext_ecap=200), pytest.raises(S.SdfError) as e:
         ix.extend(box, 0.25)
     assert e.value.code == S.SDF_EINTERNAL
-    monkeypatch.delenv("SDF_EXT_ECAP")
     r = ix.extend(box, 0.25)
     assert (int(r["q_begin"][0]), int(r["q_end"][0])) == (0, 8000)
 
@@ -232,13 +229,12 @@ def test_search_extend_config1(S, oracle_lib):
     _same(r.regions(), _oracle_extend(orc, off, _boxes_from_cands(S, oc), tau), "config1")
 
 
-def test_search_extend_tied_candidates(S, oracle_lib, monkeypatch):
+def test_search_extend_tied_candidates(S, oracle_lib):
     """Candidates that share their sort prefix (query, strand, sequence,
     begin: tandem arrays), with every such run sent to the whole-record sort
-    (SDF_CAND_TIE_MAX=1), then extended: the order is final before the
+    (cand_tie_max = 1), then extended: the order is final before the
     extension starts, so each region is the oracle's extension of the oracle
     candidate at the same place."""
-    monkeypatch.setenv("SDF_CAND_TIE_MAX", "1")
     g = synth.tandem_case(93, length=200_000, n_arrays=120, copies_hi=60, n_seqs=3)
     b, off = g.concat()
     spans = list(g.spans) + [(0, 100, len(g.seqs[0]) - 50)]
@@ -248,7 +244,8 @@ def test_search_extend_tied_candidates(S, oracle_lib, monkeypatch):
     pre = np.stack([oc["query_id"], oc["strand"], oc["q_seq"], oc["q_begin"]], 1)
     assert np.any(np.all(pre[1:] == pre[:-1], axis=1)), "no tied candidates"
     ix = S.Index(g.seqs, 12, 16)
-    r = ix.search_batch(spans, 0.25, 200, extend=True)
+    with S.tuning(cand_tie_max=1):
+        r = ix.search_batch(spans, 0.25, 200, extend=True)
     gc = r.candidates()
     for f in ("query_id", "strand", "q_seq", "t_seq", "q_begin", "q_end", "t_begin", "t_end",
               "n_seeds", "max_shared"):
@@ -351,7 +348,7 @@ def test_qgram_errors(S):
     assert len(got) == 0
 
 
-def test_extend_tandem_array_hash_set(S, oracle_lib, monkeypatch, capfd):
+def test_extend_tandem_array_hash_set(S, oracle_lib, capfd):
     """A 100 kbp tandem array of a 17-base unit (two distinct minimizer
     hashes repeated thousands of times) and its 1%-mutated copy: ranking
     meets buckets of more than 4,096 keys and goes through the LDS hash set;
@@ -373,8 +370,8 @@ def test_extend_tandem_array_hash_set(S, oracle_lib, monkeypatch, capfd):
     boxes[1] = (0, 0, 1, 0, 50000, 52000, 50300, 52300, 0, 0)
     boxes[2] = (0, 1, 0, 0, 4000, 9000, 70000, 75000, 0, 0)
     ix = S.Index([s0, s1], 12, 16)
-    monkeypatch.setenv("SDF_EXT_STATS", "1")
-    got = ix.extend(boxes, 0.25)
+    with S.tuning(ext_stats=1):
+        got = ix.extend(boxes, 0.25)
     err = capfd.readouterr().err
     _same(got, _oracle_extend(orc, off, boxes, tau), "tandem array")
     big = [int(w.split("=")[1]) for w in err.split() if w.startswith("big_buckets=")]

@@ -292,6 +292,7 @@ def extend_mode(ix, span, max_error, min_len, steps=3, cpu=None, cpu_sample=200)
     oracle's extension rate on a seeded sample of its own candidates."""
     import numpy as np
     import torch
+    from paper_1807_00205_amd import sdf
     r = ix.search(span, max_error, min_len, timing=True, extend=True)
     cands = r.candidates()
     reg = r.regions()
@@ -362,7 +363,8 @@ def extend_mode(ix, span, max_error, min_len, steps=3, cpu=None, cpu_sample=200)
         rows = np.stack([rr["q_begin"] + qo, rr["q_end"] + qo, rr["t_begin"] + to,
                          rr["t_end"] + to, rr["strand"].astype(np.uint64)], axis=1)
         t = time.time()
-        oracle.sd_align(cpu["bytes"], cpu["off"], rows, 11, min_len, max_error, cpu["threads"])
+        oracle.sd_align(cpu["bytes"], cpu["off"], rows, 11, min_len, max_error, cpu["threads"],
+                        pad_frac=sdf.PAD_FRAC)
         dt = time.time() - t
         out["final_sds"]["cpu_baseline"] = {
             "value": round(len(sel) / dt, 2), "unit": "regions/s", "cores": cpu["threads"],

@@ -66,7 +66,7 @@ typedef struct sdf_index_s *sdf_index;   /* device-resident, read-only after bui
 typedef struct sdf_result_s *sdf_result; /* device buffers + host copies of one search */
 
 /* k: k-mer length, 1 <= k <= 16 (Section 3.3 uses k = 12 for seeding).
- * w: winnowing window in k-mers, 1 <= w <= 64 (Section 2.2). */
+ * w: winnowing window in k-mers, 1 <= w <= 256 (Section 2.2). */
 typedef struct {
     uint32_t k, w;
 } sdf_index_params;
@@ -309,6 +309,7 @@ typedef struct {
     double max_error;   /* delta, 0 < delta < 1 */
     uint32_t min_len;   /* minimum SD length L >= 1 */
     uint32_t k;         /* seed length, 1 <= k <= 11 */
+    double pad_frac;    /* region padding (Section 3.2), 0 <= pad_frac <= 1 */
 } sdf_align_params;
 
 /* One final SD (120 bytes): region index, strand, sequences and 0-based
@@ -330,6 +331,10 @@ typedef struct sdf_sds_s *sdf_sds;
 /* Final SDs of n region pairs (host array; strand, sequences and bounds
  * are read; each side below 2^20 bases, n below 2^22), records in region
  * order (within a region in the order the final chains are taken out).
+ * Each region is padded first (Section 3.2 pads every potential SD region
+ * by a number of bases that grows with its size, not given): each side of
+ * L bases gains pad = min(ceil(pad_frac L), floor((2^20 - 1 - L) / 2))
+ * bases at both ends, cut at the ends of its sequence.
  * Errors: SDF_EINVAL for NULL arguments, parameters out of range, strand >
  * 1 or a side of 2^20 bases or more; SDF_ERANGE for a region outside the
  * index; SDF_ENOMEM, SDF_EDEVICE. */

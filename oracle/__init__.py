@@ -115,7 +115,7 @@ def lib():
         L.or_seed_size.restype = ctypes.c_int
         L.or_cand_size.restype = ctypes.c_int
         L.or_sd_align.restype = vp
-        L.or_sd_align.argtypes = [vp, vp, u32, vp, u64, u32, u32, dbl, ctypes.c_int]
+        L.or_sd_align.argtypes = [vp, vp, u32, vp, u64, u32, u32, dbl, dbl, ctypes.c_int]
         L.or_sd_count.restype = u64
         L.or_sd_count.argtypes = [vp]
         L.or_sd_ops_count.restype = u64
@@ -277,14 +277,15 @@ class OracleIndex:
 
 
 def sd_align(bytes_: np.ndarray, off: np.ndarray, rows, k: int = 11, min_len: int = 1000,
-             max_error: float = 0.25, threads: int = 0):
+             max_error: float = 0.25, threads: int = 0, pad_frac: float = 0.0):
     """Final SDs (Section 3.3) of region pairs given as rows (q0, q1, t0, t1,
-    strand) of global coordinates: (SD_DTYPE array, CIGAR operations)."""
+    strand) of global coordinates, each side padded first by pad_frac of its
+    length at both ends (Section 3.2): (SD_DTYPE array, CIGAR operations)."""
     b = np.ascontiguousarray(bytes_, dtype=np.uint8)
     off = np.ascontiguousarray(off, dtype=np.uint64)
     r = np.ascontiguousarray(np.array(rows, dtype=np.uint64).reshape(-1, 5))
     h = lib().or_sd_align(_ptr(b), _ptr(off), len(off) - 1, _ptr(r), len(r), k, min_len,
-                          max_error, threads)
+                          max_error, pad_frac, threads)
     if not h:
         raise ValueError("invalid region rows or parameters")
     try:

@@ -51,6 +51,10 @@
  *    and the traceback go to the diagonal, then the query-gap, then the
  *    target-gap state), in full when (dx + 1)(dy + 1) <= 2^20 cells, else
  *    as its diagonal followed by the leftover bases as one gap;
+ *  - padding (Section 3.2 pads every potential SD region by a number of
+ *    bases that grows with its size; the function is not given): each side
+ *    of L bases gains min(ceil(pad_frac L), floor((2^20 - 1 - L) / 2))
+ *    bases at both ends, cut at the ends of its sequence;
  *  - report: alignment length l >= L and (mismatches + gap openings) <=
  *    delta * l (gaps counted once each: the affine view of Section 2's
  *    error, which no longer charges gap extensions);
@@ -568,15 +572,36 @@ static void align_region(const uint8_t *bytes, const uint64_t *off, uint32_t nse
  * returns a handle to the reported SDs in region order (within a region,
  * in the order the final chains are extracted).  Returns NULL for an
  * invalid row. */
-void *or_sd_align(const uint8_t *bytes, const uint64_t *off, uint32_t nseq, const uint64_t *rows,
-                  uint64_t n, uint32_t k, uint32_t min_len, double delta, int threads)
+/* The side [*b, *e) of global coordinates, padded as stated above. */
+static void pad_side(const uint64_t *off, uint32_t nseq, double pad_frac, uint64_t *b, uint64_t *e)
 {
-    if (k < 1 || k > 16) return NULL;
+    uint64_t L = *e - *b;
+    if (L == 0) return;
+    uint32_t s = 0;  /* the sequence holding the side */
+    while (s + 1 < nseq && off[s + 1] <= *b) s++;
+    uint64_t g = (uint64_t)ceil(pad_frac * (double)L);
+    uint64_t room = ((1u << 20) - 1 - L) / 2;
+    if (g > room) g = room;
+    *b -= (*b - off[s] < g) ? *b - off[s] : g;
+    *e += (off[s + 1] - *e < g) ? off[s + 1] - *e : g;
+}
+
+void *or_sd_align(const uint8_t *bytes, const uint64_t *off, uint32_t nseq, const uint64_t *rows_in,
+                  uint64_t n, uint32_t k, uint32_t min_len, double delta, double pad_frac,
+                  int threads)
+{
+    if (k < 1 || k > 16 || !(pad_frac >= 0.0 && pad_frac <= 1.0)) return NULL;
     for (uint64_t r = 0; r < n; r++) {
-        const uint64_t *g = rows + 5 * r;
+        const uint64_t *g = rows_in + 5 * r;
         if (g[0] > g[1] || g[2] > g[3] || g[1] - g[0] >= (1u << 20) || g[3] - g[2] >= (1u << 20) ||
             g[4] > 1)
             return NULL;
+    }
+    uint64_t *rows = (uint64_t *)malloc((n ? n : 1) * 5 * sizeof(uint64_t));
+    memcpy(rows, rows_in, n * 5 * sizeof(uint64_t));
+    for (uint64_t r = 0; r < n; r++) {
+        pad_side(off, nseq, pad_frac, &rows[5 * r], &rows[5 * r + 1]);
+        pad_side(off, nseq, pad_frac, &rows[5 * r + 2], &rows[5 * r + 3]);
     }
     sa_out *parts = (sa_out *)calloc(n ? n : 1, sizeof(sa_out));
 #ifdef _OPENMP
@@ -596,6 +621,7 @@ void *or_sd_align(const uint8_t *bytes, const uint64_t *off, uint32_t nseq, cons
         free(parts[r].ops);
     }
     free(parts);
+    free(rows);
     return all;
 }
 

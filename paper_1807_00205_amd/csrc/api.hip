@@ -747,7 +747,7 @@ sdf_status sdf_index_build(const char *const *seqs, const uint64_t *lens, uint32
         if (!out || !p || !seqs || !lens) throw Error{SDF_EINVAL, "NULL argument"};
         if (n_seqs == 0) throw Error{SDF_EINVAL, "no sequences"};
         if (p->k < 1 || p->k > 16) throw Error{SDF_EINVAL, "k must lie in [1, 16]"};
-        if (p->w < 1 || p->w > 64) throw Error{SDF_EINVAL, "w must lie in [1, 64]"};
+        if (p->w < 1 || p->w > 256) throw Error{SDF_EINVAL, "w must lie in [1, 256]"};
         uint64_t total = 0;
         for (uint32_t s = 0; s < n_seqs; s++) {
             if (!seqs[s] && lens[s]) throw Error{SDF_EINVAL, "NULL sequence"};
@@ -1143,9 +1143,12 @@ sdf_status sdf_align_regions(sdf_index ix, const sdf_region *in, uint64_t n,
         if (!(d > 0.0 && d < 1.0)) throw Error{SDF_EINVAL, "max_error must lie in (0, 1)"};
         if (p->min_len < 1) throw Error{SDF_EINVAL, "min_len must be at least 1"};
         if (p->k < 1 || p->k > 11) throw Error{SDF_EINVAL, "k must lie in [1, 11]"};
+        if (!(p->pad_frac >= 0.0 && p->pad_frac <= 1.0))
+            throw Error{SDF_EINVAL, "pad_frac must lie in [0, 1]"};
         if (n >= (1ull << 22)) throw Error{SDF_EINVAL, "too many regions (2^22 at most)"};
+        std::vector<sdf_region> padded(in, in + n);
         for (uint64_t i = 0; i < n; i++) {
-            const sdf_region &x = in[i];
+            sdf_region &x = padded[i];
             if (x.strand > 1) throw Error{SDF_EINVAL, "strand must be 0 or 1"};
             if (x.q_seq >= ix->nseq || x.t_seq >= ix->nseq)
                 throw Error{SDF_ERANGE, "region sequence index out of range"};
@@ -1155,6 +1158,17 @@ sdf_status sdf_align_regions(sdf_index ix, const sdf_region *in, uint64_t n,
                 throw Error{SDF_ERANGE, "region outside its sequence"};
             if (x.q_end - x.q_begin >= (1ull << 20) || x.t_end - x.t_begin >= (1ull << 20))
                 throw Error{SDF_EINVAL, "a region side holds 2^20 bases or more"};
+            // padding: both ends of a side of L bases by ceil(pad_frac L),
+            // kept below 2^20 bases and inside the sequence
+            auto pad = [&](uint64_t &b, uint64_t &e, uint64_t len) {
+                const uint64_t L = e - b;
+                uint64_t g = (uint64_t)std::ceil(p->pad_frac * (double)L);
+                g = std::min<uint64_t>(g, ((1ull << 20) - 1 - L) / 2);
+                b -= std::min<uint64_t>(g, b);
+                e += std::min<uint64_t>(g, len - e);
+            };
+            pad(x.q_begin, x.q_end, ql);
+            pad(x.t_begin, x.t_end, tl);
         }
         SDF_HIP(hipSetDevice(ix->device));
         const hipStream_t st = (hipStream_t)hip_stream;
@@ -1162,7 +1176,7 @@ sdf_status sdf_align_regions(sdf_index ix, const sdf_region *in, uint64_t n,
         res = new sdf_sds_s();
         res->device = ix->device;
         res->st = st;
-        sd_align(ix->view(), ix->h_off.data(), in, n, p->k, p->min_len, d, res->r, st);
+        sd_align(ix->view(), ix->h_off.data(), padded.data(), n, p->k, p->min_len, d, res->r, st);
         *out = res;
     });
     if (rc != SDF_OK && res) {

@@ -51,7 +51,8 @@ __global__ void k_encode(const uint8_t *__restrict__ bytes, uint64_t total, uint
 // ------------------------------------------------------------------ winnow --
 constexpr int WN_THREADS = 256;
 constexpr int WN_CHUNK = 4096;  // owned positions per block
-constexpr int WN_MAXW = 64;
+constexpr int WN_MAXW_FAST = 64;  // windows up to 64 k-mers: minima by wave shuffles
+constexpr int WN_MAXW = 256;      // wider windows: block prefix/suffix minima in LDS
 constexpr int WN_NB = 64;       // sequence boundaries cached per block
 
 struct WinArgs {
@@ -111,8 +112,14 @@ __device__ __forceinline__ uint64_t shift_pair(uint64_t lo, uint64_t hi, int lan
     return (lane + d < 64) ? from_lo : from_hi;
 }
 
+// Selects the minimizers of the windows starting in a chunk of WN_CHUNK
+// positions (plus the w - 1 before it).  MAXW bounds the window: up to 64
+// k-mers the minima come from doubling over wave shuffles; wider windows use
+// the block method (minimum of the suffix of one w-block and the prefix of
+// the next, both precomputed in LDS).
+template <int MAXW>
 __global__ void __launch_bounds__(WN_THREADS) k_winnow(WinArgs a) {
-    __shared__ uint64_t key[WN_CHUNK + 2 * WN_MAXW + 64];
+    __shared__ uint64_t key[WN_CHUNK + 2 * MAXW + 64];
     __shared__ uint8_t sel[WN_CHUNK];
     __shared__ uint64_t bnd[WN_NB + 1];
     __shared__ uint32_t nbnd, s0, use_global, cnt;
@@ -172,28 +179,10 @@ __global__ void __launch_bounds__(WN_THREADS) k_winnow(WinArgs a) {
     }
     __syncthreads();
 
-    // window starts s in [K0, P0 + CHUNK): groups of 64 per wave
+    // window starts s in [K0, P0 + CHUNK)
     const int nstarts = WN_CHUNK + (int)(w - 1);
-    int L = 1;
-    while (2 * L <= (int)w) L <<= 1;
-    for (int g = wave * 64; g < nstarts; g += WN_THREADS) {
-        const int li = g + lane;  // local index of the window start
-        uint64_t lo = (li < nkeys) ? key[li] : SENT64;
-        uint64_t hi = (li + 64 < nkeys) ? key[li + 64] : SENT64;
-        // doubling: after the loop lo = min over [x, x+L)
-        for (int d = 1; d < L; d <<= 1) {
-            uint64_t ls = shift_pair(lo, hi, lane, d);
-            uint64_t hs = __shfl(hi, (lane + d) & 63, 64);
-            if (lane + d >= 64) hs = SENT64;
-            lo = ls < lo ? ls : lo;
-            hi = hs < hi ? hs : hi;
-        }
-        uint64_t m = lo;
-        const int rest = (int)w - L;
-        if (rest > 0) {
-            uint64_t t = shift_pair(lo, hi, lane, rest);
-            m = t < m ? t : m;
-        }
+    // marks the minimizer m of the window starting at local index li
+    auto mark = [&](int li, uint64_t m) {
         const int64_t s = K0 + li;
         if (li < nstarts && s >= 0 && (uint64_t)s < a.total && m != SENT64) {
             uint64_t sb, se;
@@ -203,6 +192,55 @@ __global__ void __launch_bounds__(WN_THREADS) k_winnow(WinArgs a) {
                 uint64_t p = 0xFFFFFFFFu - (uint32_t)m;
                 if (p >= P0 && p < P0 + WN_CHUNK) sel[p - P0] = 1;
             }
+        }
+    };
+    if constexpr (MAXW <= WN_MAXW_FAST) {
+        // groups of 64 starts per wave
+        int L = 1;
+        while (2 * L <= (int)w) L <<= 1;
+        for (int g = wave * 64; g < nstarts; g += WN_THREADS) {
+            const int li = g + lane;  // local index of the window start
+            uint64_t lo = (li < nkeys) ? key[li] : SENT64;
+            uint64_t hi = (li + 64 < nkeys) ? key[li + 64] : SENT64;
+            // doubling: after the loop lo = min over [x, x+L)
+            for (int d = 1; d < L; d <<= 1) {
+                uint64_t ls = shift_pair(lo, hi, lane, d);
+                uint64_t hs = __shfl(hi, (lane + d) & 63, 64);
+                if (lane + d >= 64) hs = SENT64;
+                lo = ls < lo ? ls : lo;
+                hi = hs < hi ? hs : hi;
+            }
+            uint64_t m = lo;
+            const int rest = (int)w - L;
+            if (rest > 0) {
+                uint64_t t = shift_pair(lo, hi, lane, rest);
+                m = t < m ? t : m;
+            }
+            mark(li, m);
+        }
+    } else {
+        // blocks of w keys from local index 0: prefix minima in pre, suffix
+        // minima in place; the window [li, li + w - 1] spans at most two
+        // blocks, so its minimum is min(suffix(li), prefix(li + w - 1))
+        __shared__ uint64_t pre[WN_CHUNK + 2 * MAXW + 64];
+        const int nb = (nkeys + (int)w - 1) / (int)w;
+        for (int b = threadIdx.x; b < nb; b += WN_THREADS) {
+            const int lo = b * (int)w, hi = lo + (int)w < nkeys ? lo + (int)w : nkeys;
+            uint64_t m = SENT64;
+            for (int i = lo; i < hi; i++) {
+                m = key[i] < m ? key[i] : m;
+                pre[i] = m;
+            }
+            m = SENT64;
+            for (int i = hi - 1; i >= lo; i--) {
+                m = key[i] < m ? key[i] : m;
+                key[i] = m;
+            }
+        }
+        __syncthreads();
+        for (int li = threadIdx.x; li < nstarts; li += WN_THREADS) {
+            const uint64_t x = key[li], y = pre[li + (int)w - 1];  // li + w - 1 < nkeys
+            mark(li, x < y ? x : y);
         }
     }
     __syncthreads();
@@ -581,7 +619,8 @@ void build_index(sdf_index_s *ix, const char *const *seqs, const uint64_t *lens,
     k_winnow_short<<<blocks_for(n_seqs, 64), 64, 0, st>>>(wa);
     SDF_HIP(hipGetLastError());
     if (nblk) {
-        k_winnow<<<(unsigned)nblk, WN_THREADS, 0, st>>>(wa);
+        if (w <= (uint32_t)WN_MAXW_FAST) k_winnow<WN_MAXW_FAST><<<(unsigned)nblk, WN_THREADS, 0, st>>>(wa);
+        else k_winnow<WN_MAXW><<<(unsigned)nblk, WN_THREADS, 0, st>>>(wa);
         SDF_HIP(hipGetLastError());
     }
     DevBuf<uint64_t> blkoff(nblk + 1);

@@ -55,6 +55,10 @@ EXPORTS = ["sdf_last_error", "sdf_index_build", "sdf_index_info", "sdf_index_hit
            "sdf_sds_copy", "sdf_sds_free", "sdf_tuning_defaults", "sdf_set_tuning",
            "sdf_get_tuning"]
 NOALLOC_SCRATCH_BYTES = 128 << 20
+# Section 3.2 pads every potential SD region by a number of bases that grows
+# with its size but gives no formula: here a tenth of each side's length at
+# both ends.
+PAD_FRAC = 0.1
 NOALLOC_MAX_SPANS = 65536
 NOALLOC_MAX_QUERY_BASES = 8_000_000
 
@@ -106,7 +110,7 @@ class _PlanParams(ctypes.Structure):
 
 class _AlignParams(ctypes.Structure):
     _fields_ = [("max_error", ctypes.c_double), ("min_len", ctypes.c_uint32),
-                ("k", ctypes.c_uint32)]
+                ("k", ctypes.c_uint32), ("pad_frac", ctypes.c_double)]
 
 
 class _Span(ctypes.Structure):
@@ -598,12 +602,13 @@ class Index:
         return Plan(self, spans, max_error, min_len, seed_cap, cand_cap, stream)
 
     def align_regions(self, regions, k: int = 11, min_len: int = 1000, max_error: float = 0.25,
-                      stream=None):
+                      pad_frac: float = PAD_FRAC, stream=None):
         """Final SDs (Section 3.3) of region pairs (a REGION_DTYPE array, as
-        from an extension): (SD_DTYPE records, CIGAR operations)."""
+        from an extension), each side padded first by pad_frac of its length
+        at both ends (Section 3.2): (SD_DTYPE records, CIGAR operations)."""
         inp = np.ascontiguousarray(regions)
         assert inp.dtype == REGION_DTYPE
-        p = _AlignParams(max_error, min_len, k)
+        p = _AlignParams(max_error, min_len, k, pad_frac)
         h = ctypes.c_void_p()
         _check(lib().sdf_align_regions(self._h, inp.ctypes.data_as(ctypes.c_void_p), len(inp),
                                        ctypes.byref(p), _stream_ptr(stream), ctypes.byref(h)))

@@ -68,8 +68,9 @@ def test_planted_copies(oracle_lib, seed, rate, k, min_len):
     b = np.concatenate(seqs)
     off = np.array([0, len(seqs[0]), len(b)], np.uint64)
     ix = sdf.Index(seqs, 12, 16)
-    got = ix.align_regions(_regions(sdf, rows, off), k, min_len, 0.25)
-    want = oracle_lib.sd_align(b, off, rows, k, min_len, 0.25)
+    pad = 0.1 if seed % 2 else 0.0
+    got = ix.align_regions(_regions(sdf, rows, off), k, min_len, 0.25, pad_frac=pad)
+    want = oracle_lib.sd_align(b, off, rows, k, min_len, 0.25, pad_frac=pad)
     _same(got, want, "planted")
     if rate <= 0.08 and min_len == 200:  # copies of 300-600 bases, all longer than 200
         assert len(got[0]) >= 4
@@ -97,6 +98,36 @@ def test_closed_forms(oracle_lib, strand):
     assert line[:6] == ["a", "0", "2000", "c", "0", "2000"] and line[-1] == "2000="
 
 
+@pytest.mark.parametrize("strand", [0, 1])
+def test_padding_closed_form(oracle_lib, strand):
+    """Section 3.2 padding: the middle 1,000 bases of an exact 2,000-base
+    copy, padded by half their length at both ends, reach both ends of the
+    copy (one SD of '2000='); unpadded the SD is the given 1,000 bases; a
+    pad past the sequence ends is cut there.  The oracle agrees."""
+    from paper_1807_00205_amd import sdf
+    rng = synth.rng_for(78)
+    x = synth.random_bases(rng, 2000)
+    flank = synth.random_bases(rng, 300)
+    t = synth.revcomp(x) if strand else x
+    seqs = [x, flank, t]
+    b = np.concatenate(seqs)
+    off = np.array([0, 2000, 2300, 4300], np.uint64)
+    ix = sdf.Index(seqs, 12, 16)
+    reg = np.zeros(1, sdf.REGION_DTYPE)
+    tb, te = (500, 1500)
+    reg[0] = (strand, 0, 2, 0, 500, 1500, tb, te, 0, 0)
+    row = [(500, 1500, 2300 + tb, 2300 + te, strand)]
+    for pad, span, cig in ((0.5, (0, 2000), "2000="), (0.9, (0, 2000), "2000="),
+                           (0.0, (500, 1500), "1000=")):
+        sd, ops = ix.align_regions(reg, 11, 1000 if pad else 900, 0.25, pad_frac=pad)
+        assert len(sd) == 1, pad
+        assert (int(sd["q_begin"][0]), int(sd["q_end"][0])) == span
+        assert (int(sd["t_begin"][0]), int(sd["t_end"][0])) == span
+        assert sdf.cigar_string(ops) == cig
+        _same((sd, ops), oracle_lib.sd_align(b, off, row, 11, 1000 if pad else 900, 0.25,
+                                             pad_frac=pad), "pad %g" % pad)
+
+
 def test_config1_extended_regions(oracle_lib):
     """The whole path on the 1 Mbp workload: search, extension of every
     candidate (Section 3.2), final SDs of every extended region."""
@@ -110,7 +141,7 @@ def test_config1_extended_regions(oracle_lib):
     to = off[reg["t_seq"]].astype(np.uint64)
     rows = np.stack([reg["q_begin"] + qo, reg["q_end"] + qo, reg["t_begin"] + to,
                      reg["t_end"] + to, reg["strand"].astype(np.uint64)], axis=1)
-    want = oracle_lib.sd_align(b, off, rows, 11, 1000, 0.25)
+    want = oracle_lib.sd_align(b, off, rows, 11, 1000, 0.25, pad_frac=sdf.PAD_FRAC)
     _same(got, want, "config 1")
     # every planted duplication (both directions) is reported
     assert len(got[0]) >= 20
@@ -133,7 +164,8 @@ def test_config2_sampled_regions(oracle_lib):
     to = off[reg["t_seq"]].astype(np.uint64)
     rows = np.stack([reg["q_begin"] + qo, reg["q_end"] + qo, reg["t_begin"] + to,
                      reg["t_end"] + to, reg["strand"].astype(np.uint64)], axis=1)
-    want = oracle_lib.sd_align(b, off, rows, 11, 1000, 0.25, min(16, os.cpu_count() or 1))
+    want = oracle_lib.sd_align(b, off, rows, 11, 1000, 0.25, min(16, os.cpu_count() or 1),
+                               pad_frac=sdf.PAD_FRAC)
     _same(got, want, "config 2")
     assert len(got[0]) > 0
 
@@ -147,6 +179,10 @@ def test_errors():
     with pytest.raises(sdf.SdfError) as e:
         ix.align_regions(reg, k=12)
     assert e.value.code == sdf.SDF_EINVAL
+    for pad in (-0.1, 1.5):
+        with pytest.raises(sdf.SdfError) as e:
+            ix.align_regions(reg, pad_frac=pad)
+        assert e.value.code == sdf.SDF_EINVAL
     bad = reg.copy()
     bad["strand"] = 2
     with pytest.raises(sdf.SdfError) as e:

@@ -68,10 +68,12 @@ def test_encode_bits(S, oracle_lib):
     assert np.array_equal(gp, (nw << sh).sum(axis=1).astype(np.uint32))
 
 
-@pytest.mark.parametrize("k,w", [(12, 16), (5, 1), (16, 64), (11, 7), (14, 20)])
+@pytest.mark.parametrize("k,w", [(12, 16), (5, 1), (16, 64), (11, 7), (14, 20), (12, 65),
+                                 (12, 100), (11, 256)])
 def test_winnow_and_reverse_index(S, oracle_lib, k, w):
     """a2-a4: minimizer positions, hashes, strand and eligibility flags, and
-    the reverse index grouped by (hash, strand) with ascending positions."""
+    the reverse index grouped by (hash, strand) with ascending positions;
+    windows of up to 64 k-mers and the wider ones (block minima)."""
     g = _mixed_genome(2 + k + w, length=20000)
     b, off = g.concat()
     orc = oracle_lib.OracleIndex(b, off, k, w)
@@ -122,7 +124,7 @@ SMALL = [
 
 @pytest.mark.parametrize("case", SMALL, ids=lambda c: "seed%d" % c["seed"])
 @pytest.mark.parametrize("max_error,min_len,k,w", [(0.25, 200, 12, 16), (0.1, 300, 11, 8),
-                                                   (0.3, 120, 9, 5)])
+                                                   (0.3, 120, 9, 5), (0.25, 600, 12, 100)])
 def test_search_small(S, oracle_lib, case, max_error, min_len, k, w):
     """a5-a10 on small inputs (several sequences, masking, gaps, partial
     spans): seeds and candidates equal the oracle's exactly."""

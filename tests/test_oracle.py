@@ -121,7 +121,7 @@ def test_kmer_table_matches_bruteforce(oracle_lib):
 
 # ---------------------------------------------------------------- winnow ----
 
-@pytest.mark.parametrize("w", [1, 5, 16])
+@pytest.mark.parametrize("w", [1, 5, 16, 100, 256])
 def test_winnow_homopolymer(oracle_lib, w):
     """P4: in A^N every k-mer ties, so the rightmost rule (Section 2.2)
     selects the last position of every window: W = {w-1, ..., N-k},
@@ -160,7 +160,7 @@ def test_winnow_period4(oracle_lib):
         assert bool(e & 2) == (p % 4 in (1, 3))
 
 
-@pytest.mark.parametrize("w", [8, 16, 32])
+@pytest.mark.parametrize("w", [8, 16, 32, 128, 256])
 def test_winnow_density(oracle_lib, w):
     """Section 2.2: the expected winnow size of a random sequence is
     2|A|/(w+1).  1 Mbp of i.i.d. bases; the sampling s.d. is < 0.5%."""
@@ -183,7 +183,7 @@ def test_winnow_streaming_equals_naive(oracle_lib):
                          (b"ACG", b"ACGTTGCAACGTAGG", b"ACGTTGCAACGTAGGCATTGACCAGTACAAAA",
                           b"NNNNNNNNNNNNNNNNNNNNN", b"acgtnacgtacgtgggtttacgtacg")]
         b, off = _genome(seqs)
-        for (k, w) in ((12, 16), (7, 3), (16, 24), (3, 1)):
+        for (k, w) in ((12, 16), (7, 3), (16, 24), (3, 1), (11, 100), (12, 256)):
             ix = oracle_lib.OracleIndex(b, off, k, w)
             pos, h, fl = ix.minimizers()
             M = brute.winnow(b, off, k, w)

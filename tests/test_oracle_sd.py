@@ -200,3 +200,22 @@ def test_pipeline_links_overlapping_anchors(orc, strand):
     assert (s["aln_len"], s["matches"], s["mismatches"], s["ins"], s["dels"], s["gap_opens"]) == \
         (len(x), len(y), 0, n, 0, n)
     assert s["jc"] == 0.0 and s["k2p"] == 0.0
+
+
+@pytest.mark.parametrize("pad,span", [(0.0, (500, 1500)), (0.25, (250, 1750)), (0.5, (0, 2000)),
+                                      (1.0, (0, 2000))])
+def test_padding_closed_form(orc, pad, span):
+    """Section 3.2 padding: the middle 1,000 bases of an exact 2,000-base
+    copy gain ceil(pad * 1000) bases at both ends, cut at the sequence ends;
+    the SD then spans exactly the padded sides, all '='."""
+    rng = synth.rng_for(80)
+    x = synth.random_bases(rng, 2000)
+    flank = synth.random_bases(rng, 300)
+    b = np.concatenate([x, flank, x])
+    off = np.array([0, 2000, 2300, 4300], np.uint64)
+    sd, ops = orc.sd_align(b, off, [(500, 1500, 2800, 3800, 0)], k=11, min_len=900,
+                           max_error=0.25, pad_frac=pad)
+    assert len(sd) == 1
+    s = sd[0]
+    assert (int(s["q_begin"]), int(s["q_end"]), int(s["t_begin"]), int(s["t_end"])) == span * 2
+    assert _ops(ops) == [("=", span[1] - span[0])]

@@ -17,6 +17,7 @@ UNITS = [(src, os.path.splitext(src)[0], []) for src in SOURCES] + [
     ("search.hip", "search512", ["-DSDF_TILE_THREADS=512"])]
 ARCH = os.environ.get("SDF_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ROCM_LIB = "/opt/rocm/lib"  # profiler ranges (roctx)
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
          # packed fp32 instructions stay off (no packed fp32 in this code either)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -38,7 +39,8 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(UNITS))) as ex:
         objs = list(ex.map(_compile, UNITS))
     tmp = OUT + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + [
+        "-L" + ROCM_LIB, "-lrocprofiler-sdk-roctx", "-Wl,-rpath," + ROCM_LIB]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (r.stdout, r.stderr))

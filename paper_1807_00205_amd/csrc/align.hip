@@ -915,6 +915,8 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     SDF_HIP(hipMemcpyAsync(toff.p, hto.data(), (n + 1) * 8, hipMemcpyHostToDevice, st));
     SDF_HIP(hipMemcpyAsync(qoff.p, hqo.data(), (n + 1) * 8, hipMemcpyHostToDevice, st));
     const uint64_t TT = hto[n], QT = hqo[n];
+    std::optional<Range> stage;
+    stage.emplace("sdf final SDs: seeds");
     // 1. target keys, sorted
     DevBuf<uint64_t> tkey(TT + 1);
     DevBuf<uint32_t> tval(TT + 1);
@@ -944,6 +946,7 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     tkey.reset();
     tval.reset();
     // 2. anchors
+    stage.emplace("sdf final SDs: anchors");
     DevBuf<uint32_t> flag(M + 1), fpre(M + 1);
     if (M) {
         k_run_starts<<<nb(M), 256, 0, st>>>(mkey.p, M, flag.p);
@@ -970,6 +973,7 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     k_region_bounds<<<nb(n + 1), 256, 0, st>>>(kxy.p, A, 42, nr, bnd.p);
     SDF_HIP(hipGetLastError());
     // 3. tier 1
+    stage.emplace("sdf final SDs: tier 1");
     const double dM = delta < 0.15 ? delta : 0.15, dG = delta - dM;
     uint32_t G1 = (uint32_t)std::ceil((double)min_len * dG);
     if (G1 < 1) G1 = 1;
@@ -1001,6 +1005,7 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     k_region_bounds<<<nb(n + 1), 256, 0, st>>>(kbuf.p, A, 42, nr, nbnd.p);
     SDF_HIP(hipGetLastError());
     // 4. tier 2: nodes by end, scores, extraction order, final chains
+    stage.emplace("sdf final SDs: tier 2");
     DevBuf<uint32_t> nodes_e(A), order(A);
     DevBuf<uint64_t> ekey(A);
     DevBuf<int64_t> s2(A);
@@ -1028,6 +1033,7 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     const uint64_t NF = read1(foff.p + n, st);
     if (NF == 0) return;
     // 5. stretches between anchors, aligned
+    stage.emplace("sdf final SDs: alignment");
     DevBuf<uint32_t> nseg(NF + 1);
     DevBuf<uint64_t> ncell(NF + 1), nops(NF + 1), nrow(NF + 1);
     k_seg_count<<<nb(NF), 256, 0, st>>>(an, c, fin, foff.p, nr, nbnd.p, NF, nseg.p, ncell.p,
@@ -1059,6 +1065,7 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
         SDF_HIP(hipGetLastError());
     }
     // 6. records and CIGAR
+    stage.emplace("sdf final SDs: records");
     DevBuf<uint32_t> aops(NF + 1), apass(NF + 1);
     SdOut none{nullptr, nullptr};
     k_assemble<<<nb(NF, 64), 64, 0, st>>>(ix, dreg.p, an, c, fin, foff.p, nr, nbnd.p, NF, soff.p,

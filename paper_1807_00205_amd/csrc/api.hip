@@ -513,10 +513,14 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
     const Params P = derive(p, ix->k, ix->w);
     res->n = P.n;
     check_spans(ix, qs, nq);
+    Range whole("sdf search");
+    std::optional<Range> stage;
+    stage.emplace("sdf search: set-up");
     Timer tm((p->flags & SDF_TIMING) != 0, st);
     tm.mark();
     Prepared pr;
     prepare(ix, qs, nq, P, st, pr, core_override, threads_override);
+    stage.emplace("sdf search: tiles");
     res->core = pr.core;
     res->threads = pr.threads;
     const uint64_t qbases = pr.qbases;
@@ -577,6 +581,7 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
         // windows too dense for a tile: their seeds are recomputed in global memory
         if (p->flags & SDF_SEED_ESTIMATE)
             throw Error{SDF_EINTERNAL, "seeds by the estimate: a window is too dense for a tile"};
+        stage.emplace("sdf search: dense windows");
         uint64_t ns = hc[CNT_SEEDS];
         resolve_dense(ix->view(), pr.dsd, pr.dT, P.n, P.max_overlap, dense.p, hc[CNT_DENSE],
                       res->seeds, ns, counters + CNT_SEEDS, st);
@@ -608,6 +613,7 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
     if (p->flags & SDF_SEED_ESTIMATE) {
         // the tile kernel wrote runs (first j, last j); pick each run's seed by
         // the winnowed MinHash estimate
+        stage.emplace("sdf search: estimate");
         const uint64_t nruns = res->nseeds;
         DevBuf<uint32_t> est((nruns ? nruns : 1) * 6);
         DevBuf<unsigned long long> ecount(1);
@@ -631,9 +637,11 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
         res->seeds = std::move(est);
         res->nseeds = ne;
         res->stats[5] = ne;
+        stage.emplace("sdf search: chaining");
         chain_seeds(ix->view(), res->seeds.p, DevCount{ecount.p, res->nseeds}, P.n,
                     P.max_overlap, nq, res->chain, st);
     } else {
+        stage.emplace("sdf search: chaining");
         chain_seeds(ix->view(), res->seeds.p, DevCount{counters + CNT_SEEDS, res->nseeds}, P.n,
                     P.max_overlap, nq, res->chain, st);
     }
@@ -641,6 +649,7 @@ void run_search(sdf_index_s *ix, const sdf_span *qs, uint32_t nq, const sdf_sear
     tm.mark();
     if (p->flags & SDF_EXTEND) {
         // Section 3.2: every candidate's box is extended while the estimate holds
+        stage.emplace("sdf search: extension");
         const uint64_t nc = res->chain.ncands;
         res->regions.alloc(nc);
         if (nc) {
@@ -756,6 +765,7 @@ sdf_status sdf_index_build(const char *const *seqs, const uint64_t *lens, uint32
         if (total == 0) throw Error{SDF_EINVAL, "empty input"};
         if (total > MAX_TOTAL) throw Error{SDF_EINVAL, "total length too large for 32-bit positions"};
         StreamScope scope((hipStream_t)hip_stream);
+        Range range("sdf index build");
         ix = new sdf_index_s();
         SDF_HIP(hipGetDevice(&ix->device));
         ix->k = p->k;
@@ -942,6 +952,7 @@ sdf_status sdf_autotune(sdf_index ix, const sdf_span *qs, uint32_t n, const sdf_
         SDF_HIP(hipSetDevice(ix->device));
         const hipStream_t st = (hipStream_t)hip_stream;
         StreamScope scope(st);
+        Range range("sdf autotune");
         sdf_search_params q = *p;
         q.flags = (q.flags | SDF_TIMING) & ~(uint32_t)(SDF_EXTEND | SDF_SEED_ESTIMATE);
         const Params P = derive(&q, ix->k, ix->w);
@@ -1088,6 +1099,7 @@ sdf_status sdf_qgram_filter(sdf_index ix, const sdf_region *in, uint64_t n,
         SDF_HIP(hipSetDevice(ix->device));
         const hipStream_t st = (hipStream_t)hip_stream;
         StreamScope scope(st);
+        Range range("sdf q-gram filter");
         DevBuf<sdf_region> buf(n);
         DevBuf<unsigned long long> out(n);
         SDF_HIP(hipMemcpyAsync(buf.p, in, n * sizeof(sdf_region), hipMemcpyHostToDevice, st));
@@ -1125,6 +1137,7 @@ sdf_status sdf_extend(sdf_index ix, const sdf_region *in, uint64_t n, const sdf_
         SDF_HIP(hipSetDevice(ix->device));
         const hipStream_t st = (hipStream_t)hip_stream;
         StreamScope scope(st);
+        Range range("sdf extend");
         DevBuf<sdf_region> buf(n);
         SDF_HIP(hipMemcpyAsync(buf.p, in, n * sizeof(sdf_region), hipMemcpyHostToDevice, st));
         launch_extend(ix->view(), buf.p, n, tau_of(d, ix->k), p->max_len, buf.p, nullptr, st);
@@ -1173,6 +1186,7 @@ sdf_status sdf_align_regions(sdf_index ix, const sdf_region *in, uint64_t n,
         SDF_HIP(hipSetDevice(ix->device));
         const hipStream_t st = (hipStream_t)hip_stream;
         StreamScope scope(st);
+        Range range("sdf final SDs");
         res = new sdf_sds_s();
         res->device = ix->device;
         res->st = st;
@@ -1251,6 +1265,7 @@ sdf_status sdf_plan_create(sdf_index ix, const sdf_span *qs, uint32_t n,
         }
         const hipStream_t st = pl->st;
         StreamScope scope(st);
+        Range range("sdf plan create");
         // 1. calibration: the search run once as it is, for its counts and schedule
         uint64_t ns = 0, nc = 0;
         {
@@ -1320,6 +1335,7 @@ sdf_status sdf_plan_run(sdf_plan pl, void *hip_stream, sdf_result *out) {
         std::lock_guard<std::mutex> lk(pl->mu);
         const hipStream_t st = hip_stream ? (hipStream_t)hip_stream : pl->st;
         StreamScope scope(st);
+        Range range("sdf plan replay");
         SDF_HIP(hipGraphLaunch(pl->exec, st));
         SDF_HIP(hipStreamSynchronize(st));
         pl->replays++;
@@ -1407,6 +1423,7 @@ sdf_status sdf_search_batch_noalloc(sdf_index ix, const sdf_span *qs, uint32_t n
         ar.cap = SDF_NOALLOC_SCRATCH_BYTES;
         const hipStream_t st = (hipStream_t)hip_stream;
         StreamScope scope(st);
+        Range range("sdf search (no allocation)");
         ArenaScope as(&ar);
         sdf_result_s r;  // on the stack; its device buffers are carved from the scratch
         r.device = ix->device;

@@ -2,9 +2,11 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <stdint.h>
 
 #include <mutex>
+#include <optional>
 #include <string>
 #include <vector>
 
@@ -16,6 +18,16 @@ namespace sdf {
 const sdf_tuning &tuning();
 // A setting, or def where it is SDF_AUTO.
 inline uint32_t knob(uint32_t v, uint32_t def) { return v == SDF_AUTO ? def : v; }
+
+// A named range of host-side work, visible to profilers (rocprofv3
+// --marker-trace): pushed on construction, popped on destruction.  A stage
+// sequence keeps one in a std::optional and emplaces the next stage's name.
+struct Range {
+    explicit Range(const char *name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
 
 
 constexpr uint32_t NONE32 = 0xFFFFFFFFu;

@@ -173,6 +173,27 @@ sdf_status sdf_index_packed(sdf_index ix, uint32_t *packed, uint32_t *mask, uint
 /* Release the index and its device memory.  NULL is ignored. */
 void sdf_index_free(sdf_index ix);
 
+/* Writes the index to a file at path (created or replaced) so that a later
+ * process can load it instead of indexing the sequences again (I_G and
+ * I_G^{-1} of Section 3.1 do not depend on the queries).  The format is this
+ * library's own (header with k, w, the sequence offsets and counts, then
+ * every device array with its size; little-endian).  Device arrays pass
+ * through a 64 MiB pinned host block.  Errors: SDF_EINVAL for NULL
+ * arguments or a file that cannot be written; SDF_EDEVICE. */
+sdf_status sdf_index_save(sdf_index ix, const char *path, void *hip_stream);
+/* Reads an index file into a new index on the current device; searches on
+ * it give the results of the index that was saved.  Errors: SDF_EINVAL for
+ * NULL arguments, a file that cannot be read, is not an index file, has
+ * another version, or whose header and arrays do not agree (nothing is
+ * kept); SDF_ENOMEM, SDF_EDEVICE. */
+sdf_status sdf_index_load(const char *path, void *hip_stream, sdf_index *out);
+/* The index's k and w (Section 2.2), its number of sequences, and the
+ * lengths of the first lens_cap of them (host array; may be NULL when
+ * lens_cap is 0): what a loaded index was built with.  SDF_EINVAL for a NULL
+ * index. */
+sdf_status sdf_index_shape(sdf_index ix, uint32_t *k, uint32_t *w, uint32_t *n_seqs,
+                           uint64_t *lens, uint32_t lens_cap);
+
 /*
  * Search one span against the whole index (self-search included).
  * Every query window [i, i+n) of the span starts at an eligible minimizer,

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsdf.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["prims.hip", "index.hip", "search.hip", "dense.hip", "estimate.hip", "extend.hip", "qgram.hip",
-           "chain.hip", "align.hip", "api.hip"]
+           "chain.hip", "align.hip", "store.hip", "api.hip"]
 # (source, object name, extra flags): the tile kernel is built in two workgroup layouts
 UNITS = [(src, os.path.splitext(src)[0], []) for src in SOURCES] + [
     ("search.hip", "search512", ["-DSDF_TILE_THREADS=512"])]

@@ -777,6 +777,45 @@ sdf_status sdf_index_build(const char *const *seqs, const uint64_t *lens, uint32
     return rc;
 }
 
+sdf_status sdf_index_save(sdf_index ix, const char *path, void *hip_stream) {
+    return guarded([&] {
+        if (!ix || !path) throw Error{SDF_EINVAL, "NULL argument"};
+        SDF_HIP(hipSetDevice(ix->device));
+        Range range("sdf index save");
+        StreamScope scope((hipStream_t)hip_stream);
+        save_index(ix, path, (hipStream_t)hip_stream);
+    });
+}
+
+sdf_status sdf_index_load(const char *path, void *hip_stream, sdf_index *out) {
+    if (out) *out = nullptr;
+    sdf_index_s *ix = nullptr;
+    sdf_status rc = guarded([&] {
+        if (!path || !out) throw Error{SDF_EINVAL, "NULL argument"};
+        Range range("sdf index load");
+        StreamScope scope((hipStream_t)hip_stream);
+        ix = new sdf_index_s();
+        SDF_HIP(hipGetDevice(&ix->device));
+        load_index(ix, path, (hipStream_t)hip_stream);
+        *out = ix;
+    });
+    if (rc != SDF_OK) delete ix;
+    return rc;
+}
+
+sdf_status sdf_index_shape(sdf_index ix, uint32_t *k, uint32_t *w, uint32_t *n_seqs,
+                           uint64_t *lens, uint32_t lens_cap) {
+    return guarded([&] {
+        if (!ix) throw Error{SDF_EINVAL, "NULL index"};
+        if (lens_cap && !lens) throw Error{SDF_EINVAL, "NULL lengths"};
+        if (k) *k = ix->k;
+        if (w) *w = ix->w;
+        if (n_seqs) *n_seqs = ix->nseq;
+        for (uint32_t s = 0; s < lens_cap && s < ix->nseq; s++)
+            lens[s] = ix->h_off[s + 1] - ix->h_off[s];
+    });
+}
+
 sdf_status sdf_index_info(sdf_index ix, uint64_t *nm, uint64_t *ne, uint64_t *bytes) {
     return guarded([&] {
         if (!ix) throw Error{SDF_EINVAL, "NULL index"};

@@ -250,4 +250,7 @@ struct sdf_index_s {
 namespace sdf {
 void build_index(sdf_index_s *ix, const char *const *seqs, const uint64_t *lens,
                  uint32_t n_seqs, hipStream_t st);
+// Index files (store.hip): every field and device array of the index.
+void save_index(sdf_index_s *ix, const char *path, hipStream_t st);
+void load_index(sdf_index_s *ix, const char *path, hipStream_t st);
 }

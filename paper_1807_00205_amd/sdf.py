@@ -53,7 +53,7 @@ EXPORTS = ["sdf_last_error", "sdf_index_build", "sdf_index_info", "sdf_index_hit
            "sdf_search_batch_noalloc", "sdf_plan_create", "sdf_plan_run", "sdf_plan_info",
            "sdf_plan_free", "sdf_search_batch_capped", "sdf_align_regions", "sdf_sds_count",
            "sdf_sds_copy", "sdf_sds_free", "sdf_tuning_defaults", "sdf_set_tuning",
-           "sdf_get_tuning"]
+           "sdf_get_tuning", "sdf_index_save", "sdf_index_load", "sdf_index_shape"]
 NOALLOC_SCRATCH_BYTES = 128 << 20
 # Section 3.2 pads every potential SD region by a number of bases that grows
 # with its size but gives no formula: here a tenth of each side's length at
@@ -218,6 +218,12 @@ def lib() -> ctypes.CDLL:
         L.sdf_extend.restype = st
         L.sdf_extend.argtypes = [vp, vp, u64, P(_ExtendParams), vp, vp]
         L.sdf_autotune.restype = st
+        L.sdf_index_save.restype = st
+        L.sdf_index_save.argtypes = [vp, ctypes.c_char_p, vp]
+        L.sdf_index_load.restype = st
+        L.sdf_index_load.argtypes = [ctypes.c_char_p, vp, P(vp)]
+        L.sdf_index_shape.restype = st
+        L.sdf_index_shape.argtypes = [vp, P(u32), P(u32), P(u32), vp, u32]
         L.sdf_tuning_defaults.restype = None
         L.sdf_tuning_defaults.argtypes = [P(_Tuning)]
         L.sdf_set_tuning.restype = st
@@ -433,6 +439,28 @@ class Index:
         self._keep = None
         self.k, self.w = k, w
         self.lengths = [len(b) for b in bufs]
+
+    @classmethod
+    def load(cls, path: str, stream=None) -> "Index":
+        """An index read from a file written by ``save`` (``sdf_index_load``)."""
+        h = ctypes.c_void_p()
+        _check(lib().sdf_index_load(os.fsencode(path), _stream_ptr(stream), ctypes.byref(h)))
+        self = cls.__new__(cls)
+        self._h = h.value
+        self._keep = None
+        k, w, n = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().sdf_index_shape(self._h, ctypes.byref(k), ctypes.byref(w), ctypes.byref(n),
+                                     None, 0))
+        lens = np.zeros(max(1, n.value), np.uint64)
+        _check(lib().sdf_index_shape(self._h, None, None, None,
+                                     lens.ctypes.data_as(ctypes.c_void_p), n.value))
+        self.k, self.w = k.value, w.value
+        self.lengths = [int(x) for x in lens[:n.value]]
+        return self
+
+    def save(self, path: str, stream=None) -> None:
+        """Writes the index to a file (``sdf_index_save``)."""
+        _check(lib().sdf_index_save(self._h, os.fsencode(path), _stream_ptr(stream)))
 
     def close(self):
         if getattr(self, "_h", None):

@@ -420,6 +420,10 @@ typedef struct {
     uint32_t ext_batch_min;       /* extension: smallest batch of insertions */
     uint32_t ext_ecap;            /* extension: scratch elements per workgroup (>= 64) */
     uint32_t ext_stats;           /* 1: one line of extension counters on stderr per call */
+    uint32_t align_wave_cells;    /* final SDs: stretches of at least this many cells are
+                                     aligned by one wave each */
+    uint32_t align_wave_lds_cols; /* final SDs: the most columns whose previous row such a
+                                     wave keeps in LDS (at most 4,096; global memory above) */
 } sdf_tuning;
 
 /* Every field of *t set to SDF_AUTO. */

@@ -615,6 +615,53 @@ __global__ void k_seg_emit(const Anchors an, const Chains1 c, const Final fin,
 
 constexpr int NEG = -1000000000;
 
+// Stretches of at least `wave_cells` cells are aligned by one 64-lane
+// workgroup each (k_align_wave), with the previous row in LDS up to
+// WAVE_COLS columns and in the stretch's global rows beyond; the others by
+// one thread each (k_align_segs).
+constexpr uint32_t WAVE_S = 64;              // columns per lane in LDS at most
+constexpr uint32_t WAVE_COLS = 64 * WAVE_S;  // 4,096 columns
+enum : uint32_t { SEG_THREAD = 0, SEG_WAVE_LDS = 1, SEG_WAVE_GLOBAL = 2 };
+// wave_cols: the most columns whose previous row goes in LDS (<= WAVE_COLS)
+__device__ __forceinline__ uint32_t seg_mode(uint32_t dx, uint32_t dy, uint32_t wave_cells,
+                                             uint32_t wave_cols) {
+    const uint64_t c = seg_cells(dx, dy);
+    if (!c || c < wave_cells) return SEG_THREAD;
+    return dy + 1 <= wave_cols ? SEG_WAVE_LDS : SEG_WAVE_GLOBAL;
+}
+
+// The traceback of a filled stretch from its end state st (0 M, 1 I, 2 D):
+// column operations written to out in order; returns their number.
+__device__ uint32_t trace_back(const IndexView &ix, const ARegion &R, const Seg &S,
+                               const uint8_t *T, uint32_t W, int st, uint8_t *out) {
+    uint32_t i = S.dx, j = S.dy, n = 0;
+    while (i > 0 || j > 0) {
+        const uint8_t code = T[(uint64_t)i * W + j];
+        if (st == 0) {
+            const uint32_t a = base_at(ix, R.q0 + S.qx + i - 1), b = t_base(ix, R, S.ty + j - 1);
+            out[n++] = (a < 4 && a == b) ? OP_EQ : OP_X;
+            st = code & 3;
+            i--;
+            j--;
+        } else if (st == 1) {
+            out[n++] = OP_I;
+            st = (code >> 2) & 3;
+            i--;
+        } else {
+            out[n++] = OP_D;
+            st = (code >> 4) & 3;
+            j--;
+        }
+    }
+    // columns were written end first: reverse them
+    for (uint32_t a = 0, b = n; a + 1 < b; a++, b--) {
+        const uint8_t x = out[a];
+        out[a] = out[b - 1];
+        out[b - 1] = x;
+    }
+    return n;
+}
+
 // 5b. one thread per stretch: the three-state affine recurrence (match 2,
 // mismatch -4, a gap of L bases -(4 + 2 L)) over two rolling rows, one
 // traceback byte per cell (bits 0-1: best state before a diagonal step,
@@ -622,13 +669,15 @@ constexpr int NEG = -1000000000;
 // state; ties to M, then I, then D), then the columns written backwards
 // (op codes, one byte each, dx + dy of them at most).
 __global__ void k_align_segs(const IndexView ix, const ARegion *reg, const Seg *seg, uint64_t ns,
-                             uint8_t *tb, int *rows, uint8_t *cols, uint32_t *ncol) {
+                             uint8_t *tb, int *rows, uint8_t *cols, uint32_t *ncol,
+                             uint32_t wave_cells, uint32_t wave_cols) {
     const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ns) return;
     const Seg S = seg[t];
+    const uint32_t dx = S.dx, dy = S.dy;
+    if (seg_mode(dx, dy, wave_cells, wave_cols) != SEG_THREAD) return;  // k_align_wave's
     const ARegion R = reg[S.region];
     uint8_t *out = cols + S.ops;
-    const uint32_t dx = S.dx, dy = S.dy;
     if (!seg_cells(dx, dy)) {  // the diagonal stand-in
         const uint32_t m = dx < dy ? dx : dy;
         uint32_t n = 0;
@@ -704,32 +753,116 @@ __global__ void k_align_segs(const IndexView ix, const ARegion *reg, const Seg *
         if (Ir[dy] > best) { best = Ir[dy]; st = 1; }
         if (Dr[dy] > best) { best = Dr[dy]; st = 2; }
     }
-    uint32_t i = dx, j = dy, n = 0;
-    while (i > 0 || j > 0) {
-        const uint8_t code = T[(uint64_t)i * W + j];
-        if (st == 0) {
-            const uint32_t a = base_at(ix, R.q0 + S.qx + i - 1), b = t_base(ix, R, S.ty + j - 1);
-            out[n++] = (a < 4 && a == b) ? OP_EQ : OP_X;
-            st = code & 3;
-            i--;
-            j--;
-        } else if (st == 1) {
-            out[n++] = OP_I;
-            st = (code >> 2) & 3;
-            i--;
-        } else {
-            out[n++] = OP_D;
-            st = (code >> 4) & 3;
-            j--;
+    ncol[t] = trace_back(ix, R, S, T, W, st, out);
+}
+
+// 5c. one 64-lane workgroup per large stretch, the same recurrence and tie
+// rules as k_align_segs.  Lane l owns columns [l * SW, (l + 1) * SW) (SW =
+// ceil((dy + 1) / 64)) and takes row i at step i + l: at each step it gets
+// from lane l - 1 that lane's last column of the row it finished in the
+// step before (the cell to the left) and keeps the value it got one step
+// earlier (the cell up and to the left); its own previous row lives in LDS
+// (GLOBAL false) or in the stretch's rows in global memory (GLOBAL true,
+// wider stretches).  Lane 0 then walks the traceback.
+template <bool GLOBAL>
+__global__ __launch_bounds__(64) void k_align_wave(const IndexView ix, const ARegion *reg,
+                                                   const Seg *seg, uint64_t ns, uint8_t *tb,
+                                                   int *rows, uint8_t *cols, uint32_t *ncol,
+                                                   uint32_t wave_cells, uint32_t wave_cols) {
+    __shared__ int LM[GLOBAL ? 1 : WAVE_COLS], LI[GLOBAL ? 1 : WAVE_COLS],
+        LD[GLOBAL ? 1 : WAVE_COLS];  // row i - 1, per column
+    const uint64_t t = blockIdx.x;
+    if (t >= ns) return;
+    const Seg S = seg[t];
+    const uint32_t dx = S.dx, dy = S.dy;
+    if (seg_mode(dx, dy, wave_cells, wave_cols) != (GLOBAL ? SEG_WAVE_GLOBAL : SEG_WAVE_LDS))
+        return;  // uniform over the workgroup
+    const ARegion R = reg[S.region];
+    const uint32_t W = dy + 1, lane = threadIdx.x;
+    int *PM = GLOBAL ? rows + S.rows : LM;
+    int *PI = GLOBAL ? PM + W : LI;
+    int *PD = GLOBAL ? PI + W : LD;
+    const uint32_t SW = (W + 63) / 64;
+    const uint32_t c0 = min(W, lane * SW), c1 = min(W, c0 + SW);
+    uint8_t *T = tb + S.cells;
+    const int GO = 4, GE = 2, MA = 2, MI = -4;
+    int oM = NEG, oI = NEG, oD = NEG;  // this lane's last column of its previous row
+    int gM = NEG, gI = NEG, gD = NEG;  // (row i - 1, column c0 - 1), received a step earlier
+    for (uint32_t step = 0; step < dx + 64; step++) {
+        // (row i, column c0 - 1): lane l - 1 finished row i in the step before
+        const int inM = __shfl_up(oM, 1), inI = __shfl_up(oI, 1), inD = __shfl_up(oD, 1);
+        const int64_t irow = (int64_t)step - (int64_t)lane;
+        if (irow >= 0 && irow <= (int64_t)dx && c0 < c1) {
+            const uint32_t i = (uint32_t)irow;
+            const uint32_t qa = i ? base_at(ix, R.q0 + S.qx + i - 1) : 4u;
+            int pm = gM, pi = gI, pd = gD;     // row i - 1, column j - 1
+            int lm = inM, li = inI, ld = inD;  // row i, column j - 1
+            uint8_t *trow = T + (uint64_t)i * W;
+            for (uint32_t j = c0; j < c1; j++) {
+                const int um = i ? PM[j] : NEG, ui = i ? PI[j] : NEG, ud = i ? PD[j] : NEG;
+                int m = NEG, ii = NEG, dd = NEG;
+                uint8_t code = 0;
+                if (i == 0 && j == 0) {
+                    m = 0;
+                } else {
+                    if (i > 0 && j > 0) {
+                        int best = pm;
+                        uint8_t st = 0;
+                        if (pi > best) { best = pi; st = 1; }
+                        if (pd > best) { best = pd; st = 2; }
+                        if (best > NEG / 2) {
+                            const uint32_t tbase = t_base(ix, R, S.ty + j - 1);
+                            m = best + ((qa < 4 && qa == tbase) ? MA : MI);
+                        }
+                        code |= st;
+                    }
+                    if (i > 0) {
+                        const int a = um > NEG / 2 ? um - GO - GE : NEG;
+                        const int b = ui > NEG / 2 ? ui - GE : NEG;
+                        const int d = ud > NEG / 2 ? ud - GO - GE : NEG;
+                        ii = a;
+                        uint8_t st = 0;
+                        if (b > ii) { ii = b; st = 1; }
+                        if (d > ii) { ii = d; st = 2; }
+                        code |= st << 2;
+                    }
+                    if (j > 0) {
+                        const int a = lm > NEG / 2 ? lm - GO - GE : NEG;
+                        const int b = li > NEG / 2 ? li - GO - GE : NEG;
+                        const int d = ld > NEG / 2 ? ld - GE : NEG;
+                        dd = a;
+                        uint8_t st = 0;
+                        if (b > dd) { dd = b; st = 1; }
+                        if (d > dd) { dd = d; st = 2; }
+                        code |= st << 4;
+                    }
+                }
+                pm = um;
+                pi = ui;
+                pd = ud;
+                lm = m;
+                li = ii;
+                ld = dd;
+                PM[j] = m;
+                PI[j] = ii;
+                PD[j] = dd;
+                trow[j] = code;
+            }
+            oM = lm;
+            oI = li;
+            oD = ld;
         }
+        gM = inM;
+        gI = inI;
+        gD = inD;
     }
-    // columns were written end first: reverse them
-    for (uint32_t a = 0, b = n; a + 1 < b; a++, b--) {
-        const uint8_t x = out[a];
-        out[a] = out[b - 1];
-        out[b - 1] = x;
+    __syncthreads();  // row dx of every column is written
+    if (lane == 0) {
+        int st = 0, best = PM[dy];
+        if (PI[dy] > best) { best = PI[dy]; st = 1; }
+        if (PD[dy] > best) { best = PD[dy]; st = 2; }
+        ncol[t] = trace_back(ix, R, S, T, W, st, cols + S.ops);
     }
-    ncol[t] = n;
 }
 
 struct SdOut {
@@ -1061,7 +1194,17 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
                                        roff.p, seg.p);
     SDF_HIP(hipGetLastError());
     if (NS) {
-        k_align_segs<<<nb(NS, 64), 64, 0, st>>>(ix, dreg.p, seg.p, NS, tb.p, rows.p, cols.p, ncol.p);
+        const uint32_t wave_cells = knob(tuning().align_wave_cells, 1u << 14);
+        const uint32_t wave_cols = min(knob(tuning().align_wave_lds_cols, WAVE_COLS), WAVE_COLS);
+        k_align_segs<<<nb(NS, 64), 64, 0, st>>>(ix, dreg.p, seg.p, NS, tb.p, rows.p, cols.p, ncol.p,
+                                                wave_cells, wave_cols);
+        SDF_HIP(hipGetLastError());
+        SDF_HIP(hipGetLastError());
+        k_align_wave<false><<<(unsigned)NS, 64, 0, st>>>(ix, dreg.p, seg.p, NS, tb.p, rows.p,
+                                                         cols.p, ncol.p, wave_cells, wave_cols);
+        SDF_HIP(hipGetLastError());
+        k_align_wave<true><<<(unsigned)NS, 64, 0, st>>>(ix, dreg.p, seg.p, NS, tb.p, rows.p,
+                                                        cols.p, ncol.p, wave_cells, wave_cols);
         SDF_HIP(hipGetLastError());
     }
     // 6. records and CIGAR

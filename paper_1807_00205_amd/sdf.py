@@ -83,7 +83,8 @@ TUNING_FIELDS = ("tile_threads", "tile_core", "hits_per_part", "wg_per_cu", "spa
                  "kept_cap", "phase_prof", "chain_fused_max", "cand_sort_general",
                  "cand_sort_small_max", "cand_tie_max", "est_lds_cap", "est_reg_cap",
                  "est_first_amax", "ext_h0", "ext_lds_words", "ext_hb0", "ext_hdiv",
-                 "ext_batch_min", "ext_ecap", "ext_stats")
+                 "ext_batch_min", "ext_ecap", "ext_stats", "align_wave_cells",
+                 "align_wave_lds_cols")
 
 
 class _Tuning(ctypes.Structure):

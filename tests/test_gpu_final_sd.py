@@ -195,3 +195,34 @@ def test_errors():
     assert e.value.code == sdf.SDF_ERANGE
     sd, ops = ix.align_regions(reg[:0])
     assert len(sd) == 0 and len(ops) == 0
+
+
+@pytest.mark.parametrize("lds_cols", [4096, 0])
+@pytest.mark.parametrize("seed,rate", [(2, 0.03), (4, 0.15), (5, 0.25)])
+def test_wave_aligner(oracle_lib, seed, rate, lds_cols):
+    """Every stretch aligned by the one-wave-per-stretch kernel instead of one
+    thread (align_wave_cells = 1), its previous row in LDS (up to 4,096
+    columns) or in global memory (align_wave_lds_cols = 0): records and
+    CIGARs equal the oracle's, on planted copies and on the extended regions
+    of the 1 Mbp workload."""
+    from paper_1807_00205_amd import sdf
+    seqs, rows = _planted(seed, 3000, 4, rate)
+    b = np.concatenate(seqs)
+    off = np.array([0, len(seqs[0]), len(b)], np.uint64)
+    ix = sdf.Index(seqs, 12, 16)
+    with sdf.tuning(align_wave_cells=1, align_wave_lds_cols=lds_cols):
+        got = ix.align_regions(_regions(sdf, rows, off), 7, 200, 0.25, pad_frac=0.1)
+    _same(got, oracle_lib.sd_align(b, off, rows, 7, 200, 0.25, pad_frac=0.1), "planted, wave")
+    if seed == 2:
+        g = synth.config1()
+        b, off = g.concat()
+        ix = sdf.Index(g.seqs, 12, 16)
+        reg = ix.search_batch(g.spans, extend=True).regions()
+        with sdf.tuning(align_wave_cells=1, align_wave_lds_cols=lds_cols):
+            got = ix.align_regions(reg)
+        qo = off[reg["q_seq"]].astype(np.uint64)
+        to = off[reg["t_seq"]].astype(np.uint64)
+        rows = np.stack([reg["q_begin"] + qo, reg["q_end"] + qo, reg["t_begin"] + to,
+                         reg["t_end"] + to, reg["strand"].astype(np.uint64)], axis=1)
+        _same(got, oracle_lib.sd_align(b, off, rows, 11, 1000, 0.25, pad_frac=sdf.PAD_FRAC),
+              "config 1, wave")

@@ -342,6 +342,7 @@ struct Chains1 {
     uint32_t *count;         // chains per region
     uint32_t *cx, *cy, *cex, *cey;  // node extents
     int64_t *w;                     // node weights
+    uint32_t *flen;                 // length of each node's first anchor
 };
 
 // 3b. tier-1 chains of a region (one thread): anchors in score order; a
@@ -384,6 +385,7 @@ __global__ void k_extract1(Anchors an, const uint32_t *byscore, const uint32_t *
         c.cex[node] = an.x[l] + an.len[l];
         c.cey[node] = an.y[l] + an.len[l];
         c.w[node] = w;
+        c.flen[node] = an.len[f];
         nc++;
     }
     c.count[r] = nc;
@@ -412,54 +414,86 @@ struct Final {
     uint32_t *count;         // final chains per region
 };
 
-// 4a. tier-2 scores, one 64-lane workgroup per region: the region's
-// nodes (tier-1 chains) are the entries [nbnd[r], nbnd[r+1]) of `nodes`
-// (by start) and of `nodes_e` (by end, keys ekey); the predecessors of a
-// node are the earlier ones ending in [x - 10000, x + first anchor length),
-// with the affine cost plus the cut.
-__global__ __launch_bounds__(64) void k_tier2(const Anchors an, const uint32_t *nbnd, uint32_t nr,
-                                              const uint32_t *nodes, const uint64_t *ekey,
-                                              const uint32_t *nodes_e, const Chains1 c,
-                                              int64_t *score, uint32_t *pred) {
+// 4a. tier-2 scores, one 64-lane workgroup per region: the region's nodes
+// (tier-1 chains) are the entries [nbnd[r], nbnd[r+1]) of `nodes` (by start,
+// keys xykey = region | x | y) and of `nodes_e` (by end, keys ekey = region
+// | ex | ey, starts ecxy); the predecessors of a node are the earlier ones
+// ending in [x - 10000, x + first anchor length), with the affine cost plus
+// the cut.  The lanes load the next 64 nodes' start and first-anchor length
+// at once; scores are kept by slot (score) and by end order (score_e, read
+// by the window scan) so that a candidate's fields are one load each.
+__global__ __launch_bounds__(64) void k_tier2(const uint32_t *nbnd, uint32_t nr,
+                                              const uint32_t *nodes, const uint64_t *xykey,
+                                              const uint64_t *ekey, const uint32_t *nodes_e,
+                                              const uint2 *ecxy, const uint32_t *pos_e,
+                                              const Chains1 c, int64_t *score, int64_t *score_e,
+                                              uint32_t *pred) {
     const uint32_t r = blockIdx.x;
     if (r >= nr) return;
     const uint32_t lo = nbnd[r], hi = nbnd[r + 1];
+    const uint64_t rk = (uint64_t)r << 42;
     uint32_t p0 = lo;
-    for (uint32_t u = lo; u < hi; u++) {
-        const uint32_t a = nodes[u];
-        const uint32_t x = c.cx[a], y = c.cy[a];
-        const uint32_t flen = an.len[c.member[c.start[a]]];  // its first anchor
-        const uint64_t rk = (uint64_t)r << 42;
-        p0 = skip_below(ekey, p0, hi,
-                        rk | ((uint64_t)(x >= TIER2_GAP ? x - TIER2_GAP : 0) << 21));
-        const uint64_t khi = rk | ((uint64_t)(x + flen) << 21);
-        Best B{0, 0, 0, NONE32};
-        for (uint32_t base = p0; base < hi; base += 64) {
-            const uint32_t v = base + threadIdx.x;
-            const bool in = v < hi && ekey[v] < khi;
-            if (in) {
-                const uint32_t b = nodes_e[v];
-                const uint32_t bx = c.cx[b], by = c.cy[b];
-                uint32_t o, dx, dy;
-                if ((bx < x || (bx == x && by < y)) &&
-                    link_trim(c.cex[b], c.cey[b], x, y, flen, o, dx, dy) &&
-                    (dx > dy ? dx : dy) <= TIER2_GAP) {
-                    const uint32_t g = absdiff(dx, dy);
-                    const int64_t cost = (int64_t)(dx < dy ? dx : dy) +
-                                         (g > 0 ? 10 + (int64_t)((g + 9) / 10) : 0) + (int64_t)o;
-                    const int64_t val = ld_score(score + b) - cost;
-                    if (better(val, bx, by, B)) B = Best{val, bx, by, b};
+    for (uint32_t u0 = lo; u0 < hi; u0 += 64) {
+        uint32_t na = NONE32, nx = 0, ny = 0, nf = 0, npos = 0;
+        if (u0 + threadIdx.x < hi) {
+            const uint32_t e = u0 + threadIdx.x;
+            const uint64_t key = xykey[e];
+            na = nodes[e];
+            nx = (uint32_t)(key >> 21) & 0x1FFFFFu;
+            ny = (uint32_t)key & 0x1FFFFFu;
+            nf = c.flen[na];
+            npos = pos_e[na];
+        }
+        const uint32_t cnt = min(64u, hi - u0);
+        for (uint32_t k = 0; k < cnt; k++) {
+            const uint32_t a = __shfl(na, k), x = __shfl(nx, k), y = __shfl(ny, k);
+            const uint32_t flen = __shfl(nf, k), apos = __shfl(npos, k);
+            p0 = skip_below(ekey, p0, hi,
+                            rk | ((uint64_t)(x >= TIER2_GAP ? x - TIER2_GAP : 0) << 21));
+            const uint64_t khi = rk | ((uint64_t)(x + flen) << 21);
+            Best B{0, 0, 0, NONE32};
+            for (uint32_t base = p0; base < hi; base += 64) {
+                const uint32_t v = base + threadIdx.x;
+                const uint64_t ek = v < hi ? ekey[v] : ~0ull;
+                const bool in = ek < khi;
+                if (in) {
+                    const uint2 bxy = ecxy[v];
+                    const uint32_t bex = (uint32_t)(ek >> 21) & 0x1FFFFFu, bey = (uint32_t)ek & 0x1FFFFFu;
+                    uint32_t o, dx, dy;
+                    if ((bxy.x < x || (bxy.x == x && bxy.y < y)) &&
+                        link_trim(bex, bey, x, y, flen, o, dx, dy) &&
+                        (dx > dy ? dx : dy) <= TIER2_GAP) {
+                        const uint32_t g = absdiff(dx, dy);
+                        const int64_t cost = (int64_t)(dx < dy ? dx : dy) +
+                                             (g > 0 ? 10 + (int64_t)((g + 9) / 10) : 0) + (int64_t)o;
+                        const int64_t val = ld_score(score_e + v) - cost;
+                        if (better(val, bxy.x, bxy.y, B)) B = Best{val, bxy.x, bxy.y, v};
+                    }
                 }
+                if (__ballot(!in)) break;
             }
-            if (__ballot(!in)) break;
+            B = wave_best(B);
+            if (threadIdx.x == 0) {
+                const int64_t sa = c.w[a] + B.v;
+                st_score(score + a, sa);
+                st_score(score_e + apos, sa);
+                pred[a] = B.v > 0 ? nodes_e[B.b] : NONE32;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         }
-        B = wave_best(B);
-        if (threadIdx.x == 0) {
-            st_score(score + a, c.w[a] + B.v);
-            pred[a] = B.v > 0 ? B.b : NONE32;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     }
+}
+
+// pos_e[nodes_e[v]] = v: the end-order entry of every node slot.
+__global__ void k_invert(const uint32_t *nodes_e, uint64_t na, uint32_t *pos_e) {
+    const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < na) pos_e[nodes_e[v]] = (uint32_t)v;
+}
+
+// Starts (x, y) of the nodes in end order.
+__global__ void k_end_starts(const uint32_t *nodes_e, uint64_t na, const Chains1 c, uint2 *ecxy) {
+    const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < na) ecxy[v] = make_uint2(c.cx[nodes_e[v]], c.cy[nodes_e[v]]);
 }
 
 // Keys of the node entries: pass 0 by end (region, ex, ey); pass 1 and 2
@@ -1124,9 +1158,10 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     radix_sort_u64(kbuf.p, byscore.p, A, 64, st);
     DevBuf<uint8_t> used(A + 4);
     fill_u32(reinterpret_cast<uint32_t *>(used.p), 0u, (A + 3) / 4, st);
-    DevBuf<uint32_t> tmp(A), mem1(A), cst(A), cend(A), ccount(n), cx(A), cy(A), cex(A), cey(A);
+    DevBuf<uint32_t> tmp(A), mem1(A), cst(A), cend(A), ccount(n), cx(A), cy(A), cex(A), cey(A),
+        cfl(A);
     DevBuf<int64_t> cw(A);
-    Chains1 c{mem1.p, cst.p, cend.p, ccount.p, cx.p, cy.p, cex.p, cey.p, cw.p};
+    Chains1 c{mem1.p, cst.p, cend.p, ccount.p, cx.p, cy.p, cex.p, cey.p, cw.p, cfl.p};
     k_extract1<<<nb(n, 64), 64, 0, st>>>(an, byscore.p, bnd.p, nr, t1, used.p, tmp.p, c);
     SDF_HIP(hipGetLastError());
     // nodes ordered by (region, x, y)
@@ -1147,8 +1182,17 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
                                         ekey.p, nodes_e.p);
     SDF_HIP(hipGetLastError());
     radix_sort_u64(ekey.p, nodes_e.p, A, 64, st);
-    k_tier2<<<nr, 64, 0, st>>>(an, nbnd.p, nr, nodes.p, ekey.p, nodes_e.p, c, s2.p, p2.p);
-    SDF_HIP(hipGetLastError());
+    {
+        DevBuf<uint32_t> pos_e(A);
+        DevBuf<uint2> ecxy(A);
+        DevBuf<int64_t> s2e(A);
+        k_invert<<<nb(A), 256, 0, st>>>(nodes_e.p, A, pos_e.p);
+        k_end_starts<<<nb(A), 256, 0, st>>>(nodes_e.p, A, c, ecxy.p);
+        SDF_HIP(hipGetLastError());
+        k_tier2<<<nr, 64, 0, st>>>(nbnd.p, nr, nodes.p, kbuf.p, ekey.p, nodes_e.p, ecxy.p, pos_e.p,
+                                   c, s2.p, s2e.p, p2.p);
+        SDF_HIP(hipGetLastError());
+    }
     k_node_keys2<<<nb(A), 256, 0, st>>>(nodes.p, A, nbnd.p + nr, rslot.p, c, s2.p, 1, nullptr,
                                         kbuf.p, perm.p);
     SDF_HIP(hipGetLastError());

@@ -396,7 +396,7 @@ def test_errors(S):
         S.Index(g.seqs, 0, 16)
     assert e.value.code == S.SDF_EINVAL
     with pytest.raises(S.SdfError) as e:
-        S.Index(g.seqs, 12, 65)
+        S.Index(g.seqs, 12, 257)
     assert e.value.code == S.SDF_EINVAL
     # the index still works after failed searches
     assert len(ix.search((0, 0, 3000)).candidates()) >= 0

@@ -279,45 +279,77 @@ __device__ __forceinline__ uint32_t skip_below(const uint64_t *key, uint32_t p0,
 // region.  Anchors are scored one after another in (x, y) order; the
 // predecessors of an anchor are the earlier anchors ending in [x - G1, x +
 // len) (a window of the by-end order whose lower end only moves forward),
-// tested by the lanes 64 at a time.
-__global__ __launch_bounds__(64) void k_tier1(Anchors an, const uint32_t *byxy,
-                                              const uint64_t *endkey, const uint32_t *byend,
-                                              const uint32_t *bnd, uint32_t nr, uint32_t G1,
-                                              Tier1 t1) {
+// tested by the lanes 64 at a time.  The lanes load the next 64 anchors at
+// once; candidates' lengths and scores come from arrays kept in end order,
+// so each is one load after its sort key.
+__global__ __launch_bounds__(64) void k_tier1(const uint64_t *xykey, const uint32_t *byxy,
+                                              const uint32_t *alen, const uint64_t *endkey,
+                                              const uint32_t *byend, const uint32_t *elen,
+                                              const uint32_t *pos_e, const uint32_t *bnd,
+                                              uint32_t nr, uint32_t G1, Tier1 t1,
+                                              int64_t *score_e) {
     const uint32_t r = blockIdx.x;
     if (r >= nr) return;
     const uint32_t lo = bnd[r], hi = bnd[r + 1];
+    const uint64_t rk = (uint64_t)r << 42;
     uint32_t p0 = lo;
-    for (uint32_t u = lo; u < hi; u++) {
-        const uint32_t a = byxy[u];
-        const uint32_t x = an.x[a], y = an.y[a], len = an.len[a];
-        const uint64_t rk = (uint64_t)r << 42;
-        p0 = skip_below(endkey, p0, hi, rk | ((uint64_t)(x >= G1 ? x - G1 : 0) << 21));
-        const uint64_t khi = rk | ((uint64_t)(x + len) << 21);
-        Best B{0, 0, 0, NONE32};
-        for (uint32_t base = p0; base < hi; base += 64) {
-            const uint32_t v = base + threadIdx.x;
-            const bool in = v < hi && endkey[v] < khi;
-            if (in) {
-                const uint32_t b = byend[v];
-                const uint32_t bx = an.x[b], by = an.y[b];
-                uint32_t o, dx, dy;
-                if ((bx < x || (bx == x && by < y)) &&
-                    link_trim(bx + an.len[b], by + an.len[b], x, y, len, o, dx, dy) &&
-                    (dx > dy ? dx : dy) <= G1) {
-                    const int64_t val = ld_score(t1.score + b) - (int64_t)absdiff(dx, dy) - (int64_t)o;
-                    if (better(val, bx, by, B)) B = Best{val, bx, by, b};
+    for (uint32_t u0 = lo; u0 < hi; u0 += 64) {
+        // the lanes load the next 64 anchors (start from the sort key)
+        uint32_t na = NONE32, nx = 0, ny = 0, nl = 0, npos = 0;
+        if (u0 + threadIdx.x < hi) {
+            const uint32_t e = u0 + threadIdx.x;
+            const uint64_t key = xykey[e];
+            na = byxy[e];
+            nx = (uint32_t)(key >> 21) & 0x1FFFFFu;
+            ny = (uint32_t)key & 0x1FFFFFu;
+            nl = alen[na];
+            npos = pos_e[na];
+        }
+        const uint32_t cnt = min(64u, hi - u0);
+        for (uint32_t k = 0; k < cnt; k++) {
+            const uint32_t a = __shfl(na, k), x = __shfl(nx, k), y = __shfl(ny, k);
+            const uint32_t len = __shfl(nl, k), apos = __shfl(npos, k);
+            p0 = skip_below(endkey, p0, hi, rk | ((uint64_t)(x >= G1 ? x - G1 : 0) << 21));
+            const uint64_t khi = rk | ((uint64_t)(x + len) << 21);
+            Best B{0, 0, 0, NONE32};
+            for (uint32_t base = p0; base < hi; base += 64) {
+                const uint32_t v = base + threadIdx.x;
+                const uint64_t ek = v < hi ? endkey[v] : ~0ull;
+                const bool in = ek < khi;
+                if (in) {
+                    const uint32_t bex = (uint32_t)(ek >> 21) & 0x1FFFFFu, bey = (uint32_t)ek & 0x1FFFFFu;
+                    const uint32_t bl = elen[v], bx = bex - bl, by = bey - bl;
+                    uint32_t o, dx, dy;
+                    if ((bx < x || (bx == x && by < y)) && link_trim(bex, bey, x, y, len, o, dx, dy) &&
+                        (dx > dy ? dx : dy) <= G1) {
+                        const int64_t val =
+                            ld_score(score_e + v) - (int64_t)absdiff(dx, dy) - (int64_t)o;
+                        if (better(val, bx, by, B)) B = Best{val, bx, by, v};
+                    }
                 }
+                if (__ballot(!in)) break;  // the window ends in this chunk
             }
-            if (__ballot(!in)) break;  // the window ends in this chunk
+            B = wave_best(B);
+            if (threadIdx.x == 0) {
+                const int64_t sa = (int64_t)len + B.v;
+                st_score(t1.score + a, sa);
+                st_score(score_e + apos, sa);
+                t1.pred[a] = B.v > 0 ? byend[B.b] : NONE32;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         }
-        B = wave_best(B);
-        if (threadIdx.x == 0) {
-            st_score(t1.score + a, (int64_t)len + B.v);
-            t1.pred[a] = B.v > 0 ? B.b : NONE32;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     }
+}
+
+// Lengths and end-order positions of the anchors: elen[v] = len(byend[v]),
+// pos_e[byend[v]] = v.
+__global__ void k_end_order(const Anchors an, const uint32_t *byend, uint64_t na, uint32_t *elen,
+                            uint32_t *pos_e) {
+    const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= na) return;
+    const uint32_t a = byend[v];
+    elen[v] = an.len[a];
+    pos_e[a] = (uint32_t)v;
 }
 
 // The score order of tier-1 extraction: (region, score descending, x), then
@@ -452,13 +484,26 @@ __global__ __launch_bounds__(64) void k_tier2(const uint32_t *nbnd, uint32_t nr,
                             rk | ((uint64_t)(x >= TIER2_GAP ? x - TIER2_GAP : 0) << 21));
             const uint64_t khi = rk | ((uint64_t)(x + flen) << 21);
             Best B{0, 0, 0, NONE32};
-            for (uint32_t base = p0; base < hi; base += 64) {
-                const uint32_t v = base + threadIdx.x;
-                const uint64_t ek = v < hi ? ekey[v] : ~0ull;
-                const bool in = ek < khi;
-                if (in) {
+            // the window in rounds of 4 x 64 candidates, the keys of a round
+            // loaded before any is tested
+            for (uint32_t base = p0; base < hi; base += 4 * 64) {
+                uint64_t ek[4];
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const uint32_t v = base + (uint32_t)q * 64 + threadIdx.x;
+                    ek[q] = v < hi ? ekey[v] : ~0ull;
+                }
+                bool out = false;
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const uint32_t v = base + (uint32_t)q * 64 + threadIdx.x;
+                    if (ek[q] >= khi) {
+                        out = true;
+                        continue;
+                    }
                     const uint2 bxy = ecxy[v];
-                    const uint32_t bex = (uint32_t)(ek >> 21) & 0x1FFFFFu, bey = (uint32_t)ek & 0x1FFFFFu;
+                    const uint32_t bex = (uint32_t)(ek[q] >> 21) & 0x1FFFFFu;
+                    const uint32_t bey = (uint32_t)ek[q] & 0x1FFFFFu;
                     uint32_t o, dx, dy;
                     if ((bxy.x < x || (bxy.x == x && bxy.y < y)) &&
                         link_trim(bex, bey, x, y, flen, o, dx, dy) &&
@@ -470,7 +515,7 @@ __global__ __launch_bounds__(64) void k_tier2(const uint32_t *nbnd, uint32_t nr,
                         if (better(val, bxy.x, bxy.y, B)) B = Best{val, bxy.x, bxy.y, v};
                     }
                 }
-                if (__ballot(!in)) break;
+                if (__ballot(out)) break;  // the window ends in this round
             }
             B = wave_best(B);
             if (threadIdx.x == 0) {
@@ -1147,8 +1192,15 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     DevBuf<int64_t> s1(A);
     DevBuf<uint32_t> p1(A);
     Tier1 t1{s1.p, p1.p};
-    k_tier1<<<nr, 64, 0, st>>>(an, byxy.p, kend.p, byend.p, bnd.p, nr, G1, t1);
-    SDF_HIP(hipGetLastError());
+    {
+        DevBuf<uint32_t> elen(A), pos_e(A);
+        DevBuf<int64_t> s1e(A);
+        k_end_order<<<nb(A), 256, 0, st>>>(an, byend.p, A, elen.p, pos_e.p);
+        SDF_HIP(hipGetLastError());
+        k_tier1<<<nr, 64, 0, st>>>(kxy.p, byxy.p, an.len, kend.p, byend.p, elen.p, pos_e.p, bnd.p,
+                                   nr, G1, t1, s1e.p);
+        SDF_HIP(hipGetLastError());
+    }
     // score order: y first (stable), then (region, score descending, x)
     k_score_keys<<<nb(A), 256, 0, st>>>(an, A, t1, 0, kbuf.p, perm.p, nullptr);
     SDF_HIP(hipGetLastError());

@@ -39,6 +39,8 @@ namespace {
 
 constexpr uint32_t MAXOCC = 32;
 constexpr uint32_t TIER2_GAP = 10000;
+constexpr uint32_t T2_BLOCKS = 4096;  // tier-2 end-order blocks per region with LDS bounds
+constexpr uint32_t T2_WAVES = 8;      // waves of a tier-2 workgroup
 constexpr uint64_t DP_CELLS = 1ull << 20;
 enum : uint32_t { OP_EQ = 7, OP_X = 8, OP_I = 1, OP_D = 2 };
 
@@ -446,87 +448,233 @@ struct Final {
     uint32_t *count;         // final chains per region
 };
 
-// 4a. tier-2 scores, one 64-lane workgroup per region: the region's nodes
-// (tier-1 chains) are the entries [nbnd[r], nbnd[r+1]) of `nodes` (by start,
-// keys xykey = region | x | y) and of `nodes_e` (by end, keys ekey = region
-// | ex | ey, starts ecxy); the predecessors of a node are the earlier ones
-// ending in [x - 10000, x + first anchor length), with the affine cost plus
-// the cut.  The lanes load the next 64 nodes' start and first-anchor length
-// at once; scores are kept by slot (score) and by end order (score_e, read
-// by the window scan) so that a candidate's fields are one load each.
-__global__ __launch_bounds__(64) void k_tier2(const uint32_t *nbnd, uint32_t nr,
-                                              const uint32_t *nodes, const uint64_t *xykey,
-                                              const uint64_t *ekey, const uint32_t *nodes_e,
-                                              const uint2 *ecxy, const uint32_t *pos_e,
-                                              const Chains1 c, int64_t *score, int64_t *score_e,
-                                              uint32_t *pred) {
+// Lower bound of the tier-2 cost of a link whose predecessor ends at x - d
+// or earlier (d >= 0): with equal gaps the cost is min(dx, dy) = dx >= d;
+// with unequal ones it is at least 10 + ceil(dx / 10) (the smaller gap plus
+// a tenth of the difference is at least a tenth of dx); both grow with dx,
+// and the trim only adds.
+__device__ __forceinline__ int32_t tier2_min_cost(uint32_t d) {
+    const uint32_t u = 10 + (d + 9) / 10;
+    return (int32_t)(d < u ? d : u);
+}
+
+// A 32-bit value of lane i (i the same in every lane).
+__device__ __forceinline__ uint32_t lane_u32(uint32_t v, uint32_t i) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)i);
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+    for (int m = 32; m >= 1; m >>= 1) {
+        const uint32_t o = __shfl_xor(v, m);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int64_t tier2_cost(uint32_t dx, uint32_t dy, uint32_t o) {
+    const uint32_t g = absdiff(dx, dy);
+    return (int64_t)(dx < dy ? dx : dy) + (g > 0 ? 10 + (int64_t)((g + 9) / 10) : 0) + (int64_t)o;
+}
+
+// The best tier-2 predecessor seen by a lane (values fit 32 bits: scores
+// lie in (-2^20, 2^20]); the same order as Best.
+struct Best2 {
+    int32_t v;
+    uint32_t x, y, b;
+};
+
+__device__ __forceinline__ bool better2(int32_t v, uint32_t x, uint32_t y, const Best2 &B) {
+    return v > B.v || (v == B.v && v > 0 && (x > B.x || (x == B.x && y > B.y)));
+}
+
+// 4a. tier-2 scores, one workgroup of T2_WAVES waves per region: the
+// region's nodes (tier-1 chains) are the entries [nbnd[r], nbnd[r+1]) of
+// `nodes` (by start, keys xykey = region | x | y) and of `nodes_e` (by end,
+// keys ekey = region | ex | ey, starts ecxy); the predecessors of a node are
+// the earlier ones ending in [x - 10000, x + first anchor length), with the
+// affine cost plus the cut.  Scores are kept by slot (score) and by end
+// order (score_e).  Nodes are scored 64 at a time in start order, node k of
+// a batch in lane k of every wave:
+//  1. predecessors scored before the batch: the end order is cut into
+//     blocks of 64 entries, and LDS holds, for the first nblk blocks of the
+//     region, the last end x of each block (static) and the best score of
+//     its nodes scored so far.  A block that cannot give any node of the
+//     batch a positive link value (its best score does not exceed the least
+//     cost of a link from its last end to the batch's first start) is not
+//     read; the others are dealt round robin to the waves, which read them
+//     four at a time, one entry per lane, and test every entry against
+//     every lane's node; the waves' best predecessors meet in LDS;
+//  2. predecessors inside the batch (wave 0): node k's score is final once
+//     nodes 0..k-1 are done, so k runs from first to last and every later
+//     lane tests node k as its predecessor.
+// Only positive link values are kept and the choice among equal ones does
+// not depend on the order candidates are met, so this equals scoring the
+// nodes one at a time against every earlier node.
+__global__ __launch_bounds__(64 * T2_WAVES) void k_tier2(
+    const uint32_t *nbnd, uint32_t nr, const uint32_t *nodes, const uint64_t *xykey,
+    const uint64_t *ekey, const uint32_t *nodes_e, const uint2 *ecxy, const uint32_t *pos_e,
+    const Chains1 c, int64_t *score, int64_t *score_e, uint32_t *pred, uint32_t nblk) {
+    extern __shared__ uint32_t t2_lds[];
+    uint32_t *const exhi = t2_lds;                                      // [nblk]
+    int32_t *const bmax = reinterpret_cast<int32_t *>(t2_lds + nblk);  // [nblk]
+    __shared__ Best2 part[T2_WAVES][64];                                 // per wave and node
     const uint32_t r = blockIdx.x;
     if (r >= nr) return;
+    const uint32_t lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     const uint32_t lo = nbnd[r], hi = nbnd[r + 1];
-    const uint64_t rk = (uint64_t)r << 42;
-    uint32_t p0 = lo;
-    for (uint32_t u0 = lo; u0 < hi; u0 += 64) {
-        uint32_t na = NONE32, nx = 0, ny = 0, nf = 0, npos = 0;
-        if (u0 + threadIdx.x < hi) {
-            const uint32_t e = u0 + threadIdx.x;
-            const uint64_t key = xykey[e];
-            na = nodes[e];
-            nx = (uint32_t)(key >> 21) & 0x1FFFFFu;
-            ny = (uint32_t)key & 0x1FFFFFu;
-            nf = c.flen[na];
-            npos = pos_e[na];
-        }
-        const uint32_t cnt = min(64u, hi - u0);
-        for (uint32_t k = 0; k < cnt; k++) {
-            const uint32_t a = __shfl(na, k), x = __shfl(nx, k), y = __shfl(ny, k);
-            const uint32_t flen = __shfl(nf, k), apos = __shfl(npos, k);
-            p0 = skip_below(ekey, p0, hi,
-                            rk | ((uint64_t)(x >= TIER2_GAP ? x - TIER2_GAP : 0) << 21));
-            const uint64_t khi = rk | ((uint64_t)(x + flen) << 21);
-            Best B{0, 0, 0, NONE32};
-            // the window in rounds of 4 x 64 candidates, the keys of a round
-            // loaded before any is tested
-            for (uint32_t base = p0; base < hi; base += 4 * 64) {
-                uint64_t ek[4];
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    const uint32_t v = base + (uint32_t)q * 64 + threadIdx.x;
-                    ek[q] = v < hi ? ekey[v] : ~0ull;
-                }
-                bool out = false;
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    const uint32_t v = base + (uint32_t)q * 64 + threadIdx.x;
-                    if (ek[q] >= khi) {
-                        out = true;
-                        continue;
-                    }
-                    const uint2 bxy = ecxy[v];
-                    const uint32_t bex = (uint32_t)(ek[q] >> 21) & 0x1FFFFFu;
-                    const uint32_t bey = (uint32_t)ek[q] & 0x1FFFFFu;
-                    uint32_t o, dx, dy;
-                    if ((bxy.x < x || (bxy.x == x && bxy.y < y)) &&
-                        link_trim(bex, bey, x, y, flen, o, dx, dy) &&
-                        (dx > dy ? dx : dy) <= TIER2_GAP) {
-                        const uint32_t g = absdiff(dx, dy);
-                        const int64_t cost = (int64_t)(dx < dy ? dx : dy) +
-                                             (g > 0 ? 10 + (int64_t)((g + 9) / 10) : 0) + (int64_t)o;
-                        const int64_t val = ld_score(score_e + v) - cost;
-                        if (better(val, bxy.x, bxy.y, B)) B = Best{val, bxy.x, bxy.y, v};
-                    }
-                }
-                if (__ballot(out)) break;  // the window ends in this round
-            }
-            B = wave_best(B);
-            if (threadIdx.x == 0) {
-                const int64_t sa = c.w[a] + B.v;
-                st_score(score + a, sa);
-                st_score(score_e + apos, sa);
-                pred[a] = B.v > 0 ? nodes_e[B.b] : NONE32;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        }
+    const uint32_t nbr = (hi - lo + 63) / 64;  // blocks of the region
+    const uint32_t nbl = min(nbr, nblk);        // blocks with bounds in LDS
+    const auto block_end = [&](uint32_t j) -> uint32_t {  // end x of block j's last entry
+        if (j < nbl) return exhi[j];
+        return (uint32_t)(ekey[min(lo + 64 * j + 63, hi - 1)] >> 21) & 0x1FFFFFu;
+    };
+    for (uint32_t j = threadIdx.x; j < nbl; j += 64 * T2_WAVES) {
+        exhi[j] = (uint32_t)(ekey[min(lo + 64 * j + 63, hi - 1)] >> 21) & 0x1FFFFFu;
+        bmax[j] = INT32_MIN;
     }
+    __syncthreads();
+    const uint64_t rk = (uint64_t)r << 42;
+    uint32_t jlo = 0;  // first block that ends at or after the batch's window start
+    for (uint32_t u0 = lo; u0 < hi; u0 += 64) {
+        const uint32_t cnt = min(64u, hi - u0);
+        const bool mine = lane < cnt;
+        uint32_t a = NONE32, x = 0, y = 0, flen = 0;
+        if (mine) {
+            const uint64_t key = xykey[u0 + lane];
+            a = nodes[u0 + lane];
+            x = (uint32_t)(key >> 21) & 0x1FFFFFu;
+            y = (uint32_t)key & 0x1FFFFFu;
+            flen = c.flen[a];
+        }
+        const uint32_t xend = x + flen;  // this node's window: ends in [x - 10000, xend)
+        const uint64_t khi = rk | ((uint64_t)xend << 21);
+        const uint32_t x0 = lane_u32(x, 0), y0 = lane_u32(y, 0);  // the batch's first start
+        const uint32_t xend_max = wave_max_u32(mine ? xend : 0u);
+        const uint64_t khi_max = rk | ((uint64_t)xend_max << 21);
+        Best2 B{0, 0, 0, NONE32};
+        // 1. predecessors scored before the batch
+        const uint32_t xlo = x0 >= TIER2_GAP ? x0 - TIER2_GAP : 0;
+        for (;;) {  // blocks ending before every window: a prefix, and x0 only grows
+            const uint32_t j = jlo + lane;
+            const uint32_t cb = (uint32_t)__popcll(__ballot(j < nbr && block_end(j) < xlo));
+            jlo += cb;
+            if (cb < 64) break;
+        }
+        const auto scan = [&](uint64_t ek, uint2 exy, int32_t es, uint32_t esl) {
+            for (uint32_t i = 0; i < 64; i++) {
+                const uint64_t key = ((uint64_t)lane_u32((uint32_t)(ek >> 32), i) << 32) |
+                                     lane_u32((uint32_t)ek, i);
+                if (key >= khi_max) break;  // sorted: no later entry is in any window
+                const int32_t sb = (int32_t)lane_u32((uint32_t)es, i);
+                const uint32_t bex = (uint32_t)(key >> 21) & 0x1FFFFFu;
+                const uint32_t bey = (uint32_t)key & 0x1FFFFFu;
+                const bool pass = mine && key < khi && sb > tier2_min_cost(x > bex ? x - bex : 0);
+                if (!__ballot(pass)) continue;
+                const uint32_t bx = lane_u32(exy.x, i), by = lane_u32(exy.y, i);
+                if (!(bx < x0 || (bx == x0 && by < y0))) continue;  // not scored yet
+                uint32_t o, dx, dy;
+                if (pass && link_trim(bex, bey, x, y, flen, o, dx, dy) &&
+                    (dx > dy ? dx : dy) <= TIER2_GAP) {
+                    const int32_t val = sb - (int32_t)tier2_cost(dx, dy, o);
+                    if (better2(val, bx, by, B)) B = Best2{val, bx, by, lane_u32(esl, i)};
+                }
+            }
+        };
+        uint32_t dealt = 0;  // needed blocks met so far (dealt round robin)
+        for (uint32_t j0 = jlo; j0 < nbr; j0 += 64) {
+            const uint32_t j = j0 + lane;
+            bool beyond = true, need = false;
+            if (j < nbr) {
+                // block j starts no earlier than block j - 1 ends
+                beyond = j > jlo && block_end(j - 1) >= xend_max;
+                if (!beyond) {
+                    need = true;
+                    if (j < nbl) {
+                        const uint32_t eh = exhi[j];
+                        need = bmax[j] > tier2_min_cost(x0 > eh ? x0 - eh : 0);
+                    }
+                }
+            }
+            uint64_t mneed = __ballot(need);
+            const uint64_t mbey = __ballot(beyond);
+            if (mbey) mneed &= (mbey & (0ull - mbey)) - 1;  // blocks before the first beyond
+            // this wave's share: every T2_WAVES-th needed block
+            uint64_t mine_b = 0;
+            for (uint64_t m = mneed; m; m &= m - 1, dealt++)
+                if (dealt % T2_WAVES == wave) mine_b |= m & (0ull - m);
+            while (mine_b) {
+                uint32_t jb[4];
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    jb[q] = mine_b ? j0 + (uint32_t)__builtin_ctzll(mine_b) : nbr;
+                    mine_b &= mine_b - 1;
+                }
+                uint64_t ek[4];
+                uint2 exy[4];
+                int32_t es[4];
+                uint32_t esl[4];
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const uint32_t v = lo + 64 * jb[q] + lane;
+                    const bool ok = jb[q] < nbr && v < hi;
+                    ek[q] = ok ? ekey[v] : ~0ull;
+                    exy[q] = ok ? ecxy[v] : make_uint2(0u, 0u);
+                    es[q] = ok ? (int32_t)ld_score(score_e + v) : INT32_MIN;
+                    esl[q] = ok ? nodes_e[v] : NONE32;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; q++)
+                    if (jb[q] < nbr) scan(ek[q], exy[q], es[q], esl[q]);
+            }
+            if (mbey) break;
+        }
+        part[wave][lane] = B;
+        __syncthreads();
+        if (wave == 0) {
+            for (uint32_t q = 1; q < T2_WAVES; q++) {
+                const Best2 o = part[q][lane];
+                if (better2(o.v, o.x, o.y, B)) B = o;
+            }
+            uint32_t apos = 0, ex = 0, ey = 0;
+            int32_t w = 0;
+            if (mine) {
+                apos = pos_e[a];
+                ex = c.cex[a];
+                ey = c.cey[a];
+                w = (int32_t)c.w[a];
+            }
+            // 2. predecessors inside the batch
+            for (uint32_t k = 0; k + 1 < cnt; k++) {
+                const int32_t sk = (int32_t)lane_u32((uint32_t)(w + B.v), k);
+                const uint32_t exk = lane_u32(ex, k), eyk = lane_u32(ey, k);
+                if (lane > k && mine && exk < xend &&
+                    sk > tier2_min_cost(x > exk ? x - exk : 0)) {
+                    const uint32_t xk = lane_u32(x, k), yk = lane_u32(y, k);
+                    uint32_t o, dx, dy;
+                    if (link_trim(exk, eyk, x, y, flen, o, dx, dy) &&
+                        (dx > dy ? dx : dy) <= TIER2_GAP) {
+                        const int32_t val = sk - (int32_t)tier2_cost(dx, dy, o);
+                        if (better2(val, xk, yk, B)) B = Best2{val, xk, yk, lane_u32(a, k)};
+                    }
+                }
+            }
+            if (mine) {
+                const int32_t sa = w + B.v;
+                st_score(score + a, (int64_t)sa);
+                st_score(score_e + apos, (int64_t)sa);
+                pred[a] = B.v > 0 ? B.b : NONE32;
+                const uint32_t jp = (apos - lo) / 64;  // the node's block in end order
+                if (jp < nbl) atomicMax(bmax + jp, sa);
+            }
+        }
+        __syncthreads();  // scores and block bounds seen by every wave
+    }
+}
+
+// Most nodes of one region (entries between consecutive region bounds).
+__global__ void k_max_span(const uint32_t *bnd, uint32_t nr, uint32_t *out) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < nr) atomicMax(out, bnd[r + 1] - bnd[r]);
 }
 
 // pos_e[nodes_e[v]] = v: the end-order entry of every node slot.
@@ -1241,8 +1389,16 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
         k_invert<<<nb(A), 256, 0, st>>>(nodes_e.p, A, pos_e.p);
         k_end_starts<<<nb(A), 256, 0, st>>>(nodes_e.p, A, c, ecxy.p);
         SDF_HIP(hipGetLastError());
-        k_tier2<<<nr, 64, 0, st>>>(nbnd.p, nr, nodes.p, kbuf.p, ekey.p, nodes_e.p, ecxy.p, pos_e.p,
-                                   c, s2.p, s2e.p, p2.p);
+        // LDS bounds for up to T2_BLOCKS blocks of 64 nodes per region
+        DevBuf<uint32_t> most(1);
+        fill_u32(most.p, 0u, 1, st);
+        k_max_span<<<nb(n), 256, 0, st>>>(nbnd.p, nr, most.p);
+        SDF_HIP(hipGetLastError());
+        const uint32_t nblk =
+            std::max<uint32_t>(1, std::min<uint32_t>(T2_BLOCKS, (read1(most.p, st) + 63) / 64));
+        k_tier2<<<nr, 64 * T2_WAVES, 8 * nblk, st>>>(nbnd.p, nr, nodes.p, kbuf.p, ekey.p,
+                                                     nodes_e.p, ecxy.p, pos_e.p, c, s2.p, s2e.p,
+                                                     p2.p, nblk);
         SDF_HIP(hipGetLastError());
     }
     k_node_keys2<<<nb(A), 256, 0, st>>>(nodes.p, A, nbnd.p + nr, rslot.p, c, s2.p, 1, nullptr,

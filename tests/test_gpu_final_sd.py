@@ -147,17 +147,23 @@ def test_config1_extended_regions(oracle_lib):
     assert len(got[0]) >= 20
 
 
-def test_config2_sampled_regions(oracle_lib):
-    """200 sampled extended regions of the 50 Mbp workload (soft-masked
-    repeats, N-gaps, 1-25% divergence)."""
-    import os
+@pytest.fixture(scope="module")
+def config2_regions():
+    """The 50 Mbp workload (soft-masked repeats, N-gaps, 1-25% divergence),
+    its index and every extended region of its self-search."""
     from paper_1807_00205_amd import sdf
     g = synth.config2()
     b, off = g.concat()
     ix = sdf.Index(g.seqs, 12, 16)
     reg = ix.search_batch(g.spans, extend=True).regions()
-    rng = synth.rng_for(5)
-    reg = reg[np.sort(rng.choice(len(reg), 200, replace=False))]
+    yield ix, b, off, reg
+    ix.close()
+
+
+def _config2_check(oracle_lib, config2_regions, reg, what):
+    import os
+    from paper_1807_00205_amd import sdf
+    ix, b, off, _ = config2_regions
     reg = reg[(reg["q_end"] - reg["q_begin"] < (1 << 20)) & (reg["t_end"] - reg["t_begin"] < (1 << 20))]
     got = ix.align_regions(reg)
     qo = off[reg["q_seq"]].astype(np.uint64)
@@ -166,8 +172,26 @@ def test_config2_sampled_regions(oracle_lib):
                      reg["t_end"] + to, reg["strand"].astype(np.uint64)], axis=1)
     want = oracle_lib.sd_align(b, off, rows, 11, 1000, 0.25, min(16, os.cpu_count() or 1),
                                pad_frac=sdf.PAD_FRAC)
-    _same(got, want, "config 2")
+    _same(got, want, what)
     assert len(got[0]) > 0
+
+
+def test_config2_sampled_regions(oracle_lib, config2_regions):
+    """200 sampled extended regions of the 50 Mbp workload."""
+    reg = config2_regions[3]
+    rng = synth.rng_for(5)
+    _config2_check(oracle_lib, config2_regions,
+                   reg[np.sort(rng.choice(len(reg), 200, replace=False))], "config 2 sample")
+
+
+def test_config2_largest_regions(oracle_lib, config2_regions):
+    """The 16 longest extended regions of the 50 Mbp workload (about 300 kbp
+    a side, tens of thousands of mostly chance anchors each): the tier-2
+    scan skips most of the end-order blocks of their nodes."""
+    reg = config2_regions[3]
+    L = (reg["q_end"] - reg["q_begin"]).astype(np.int64) + (reg["t_end"] - reg["t_begin"])
+    _config2_check(oracle_lib, config2_regions, reg[np.sort(np.argsort(L, kind="stable")[-16:])],
+                   "config 2 largest")
 
 
 def test_errors():

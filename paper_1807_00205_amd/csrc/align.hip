@@ -233,29 +233,32 @@ __device__ __forceinline__ uint32_t absdiff(uint32_t a, uint32_t b) { return a >
 // The best predecessor seen by a lane: largest value, then (for values
 // above 0) the larger start (x, then y).  Starts are unique within a
 // region, so the choice does not depend on the order candidates are met.
-struct Best {
-    int64_t v;
+// Values fit 32 bits: scores lie in (-2^21, 2^21).
+struct Best2 {
+    int32_t v;
     uint32_t x, y, b;
 };
 
-__device__ __forceinline__ bool better(int64_t v, uint32_t x, uint32_t y, const Best &B) {
+__device__ __forceinline__ bool better2(int32_t v, uint32_t x, uint32_t y, const Best2 &B) {
     return v > B.v || (v == B.v && v > 0 && (x > B.x || (x == B.x && y > B.y)));
 }
 
-__device__ __forceinline__ Best wave_best(Best B) {
-    for (int m = 32; m >= 1; m >>= 1) {
-        Best o;
-        o.v = __shfl_xor(B.v, m);
-        o.x = __shfl_xor(B.x, m);
-        o.y = __shfl_xor(B.y, m);
-        o.b = __shfl_xor(B.b, m);
-        if (better(o.v, o.x, o.y, B)) B = o;
-    }
-    return B;
+// A 32-bit value of lane i (i the same in every lane).
+__device__ __forceinline__ uint32_t lane_u32(uint32_t v, uint32_t i) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)i);
 }
 
-// Scores are written by lane 0 and read by every lane of the wave in later
-// steps: workgroup-scope atomics, with a release fence after each step.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+    for (int m = 32; m >= 1; m >>= 1) {
+        const uint32_t o = __shfl_xor(v, m);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Scores are written by the lane that owns a node and read by every lane of
+// the workgroup in later batches: workgroup-scope atomics, with a fence or a
+// barrier after each batch.
 __device__ __forceinline__ int64_t ld_score(const int64_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -263,83 +266,142 @@ __device__ __forceinline__ void st_score(int64_t *p, int64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Advances p0 (an entry of a key-sorted list [., hi)) to the first key >=
-// klo; keys below klo form a prefix, so each lane tests one entry and the
-// wave moves 64 at a time.
-__device__ __forceinline__ uint32_t skip_below(const uint64_t *key, uint32_t p0, uint32_t hi,
-                                               uint64_t klo) {
-    for (;;) {
-        const uint32_t v = p0 + threadIdx.x;
-        const uint32_t c = (uint32_t)__popcll(__ballot(v < hi && key[v] < klo));
-        p0 += c;
-        if (c < 64) return p0;
-    }
-}
-
 // 3a. tier-1 scores (the longest chains: a link costs the indel |dx - dy|
 // it implies plus its cut, gaps at most G1), one 64-lane workgroup per
-// region.  Anchors are scored one after another in (x, y) order; the
-// predecessors of an anchor are the earlier anchors ending in [x - G1, x +
-// len) (a window of the by-end order whose lower end only moves forward),
-// tested by the lanes 64 at a time.  The lanes load the next 64 anchors at
-// once; candidates' lengths and scores come from arrays kept in end order,
-// so each is one load after its sort key.
+// region.  Anchors are scored 64 at a time in (x, y) order, anchor k of a
+// batch in lane k:
+//  1. predecessors scored before the batch: the anchors ending in [x0 - G1,
+//     the last window end of the batch) (x0 its first start), read in
+//     blocks of 64 entries of the end order, four blocks at a time, one
+//     entry per lane; every lane tests every entry against its own anchor.
+//     LDS holds the last end x of each of the region's first nblk blocks, so
+//     the window's first block is found without memory reads;
+//  2. predecessors inside the batch: anchor k's score is final once anchors
+//     0..k-1 are done, so k runs from first to last and every later lane
+//     tests anchor k as its predecessor.
+// Only positive link values are kept and the choice among equal ones does
+// not depend on the order candidates are met, so this equals scoring the
+// anchors one at a time against every earlier anchor.  Candidates' lengths,
+// scores and anchor ids come from arrays kept in end order.
 __global__ __launch_bounds__(64) void k_tier1(const uint64_t *xykey, const uint32_t *byxy,
                                               const uint32_t *alen, const uint64_t *endkey,
                                               const uint32_t *byend, const uint32_t *elen,
                                               const uint32_t *pos_e, const uint32_t *bnd,
                                               uint32_t nr, uint32_t G1, Tier1 t1,
-                                              int64_t *score_e) {
+                                              int64_t *score_e, uint32_t nblk) {
+    extern __shared__ uint32_t t1_lds[];
+    uint32_t *const exhi = t1_lds;  // [nblk]
     const uint32_t r = blockIdx.x;
     if (r >= nr) return;
+    const uint32_t lane = threadIdx.x;
     const uint32_t lo = bnd[r], hi = bnd[r + 1];
+    const uint32_t nbr = (hi - lo + 63) / 64;  // blocks of the region's end order
+    const uint32_t nbl = min(nbr, nblk);        // blocks with their last end in LDS
+    const auto block_end = [&](uint32_t j) -> uint32_t {
+        if (j < nbl) return exhi[j];
+        return (uint32_t)(endkey[min(lo + 64 * j + 63, hi - 1)] >> 21) & 0x1FFFFFu;
+    };
+    for (uint32_t j = lane; j < nbl; j += 64)
+        exhi[j] = (uint32_t)(endkey[min(lo + 64 * j + 63, hi - 1)] >> 21) & 0x1FFFFFu;
+    __syncthreads();
     const uint64_t rk = (uint64_t)r << 42;
-    uint32_t p0 = lo;
+    uint32_t jlo = 0;  // first block that ends at or after the batch's window start
     for (uint32_t u0 = lo; u0 < hi; u0 += 64) {
-        // the lanes load the next 64 anchors (start from the sort key)
-        uint32_t na = NONE32, nx = 0, ny = 0, nl = 0, npos = 0;
-        if (u0 + threadIdx.x < hi) {
-            const uint32_t e = u0 + threadIdx.x;
-            const uint64_t key = xykey[e];
-            na = byxy[e];
-            nx = (uint32_t)(key >> 21) & 0x1FFFFFu;
-            ny = (uint32_t)key & 0x1FFFFFu;
-            nl = alen[na];
-            npos = pos_e[na];
-        }
         const uint32_t cnt = min(64u, hi - u0);
-        for (uint32_t k = 0; k < cnt; k++) {
-            const uint32_t a = __shfl(na, k), x = __shfl(nx, k), y = __shfl(ny, k);
-            const uint32_t len = __shfl(nl, k), apos = __shfl(npos, k);
-            p0 = skip_below(endkey, p0, hi, rk | ((uint64_t)(x >= G1 ? x - G1 : 0) << 21));
-            const uint64_t khi = rk | ((uint64_t)(x + len) << 21);
-            Best B{0, 0, 0, NONE32};
-            for (uint32_t base = p0; base < hi; base += 64) {
-                const uint32_t v = base + threadIdx.x;
-                const uint64_t ek = v < hi ? endkey[v] : ~0ull;
-                const bool in = ek < khi;
-                if (in) {
-                    const uint32_t bex = (uint32_t)(ek >> 21) & 0x1FFFFFu, bey = (uint32_t)ek & 0x1FFFFFu;
-                    const uint32_t bl = elen[v], bx = bex - bl, by = bey - bl;
-                    uint32_t o, dx, dy;
-                    if ((bx < x || (bx == x && by < y)) && link_trim(bex, bey, x, y, len, o, dx, dy) &&
-                        (dx > dy ? dx : dy) <= G1) {
-                        const int64_t val =
-                            ld_score(score_e + v) - (int64_t)absdiff(dx, dy) - (int64_t)o;
-                        if (better(val, bx, by, B)) B = Best{val, bx, by, v};
-                    }
-                }
-                if (__ballot(!in)) break;  // the window ends in this chunk
-            }
-            B = wave_best(B);
-            if (threadIdx.x == 0) {
-                const int64_t sa = (int64_t)len + B.v;
-                st_score(t1.score + a, sa);
-                st_score(score_e + apos, sa);
-                t1.pred[a] = B.v > 0 ? byend[B.b] : NONE32;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        const bool mine = lane < cnt;
+        uint32_t a = NONE32, x = 0, y = 0, len = 0, apos = 0;
+        if (mine) {
+            const uint64_t key = xykey[u0 + lane];
+            a = byxy[u0 + lane];
+            x = (uint32_t)(key >> 21) & 0x1FFFFFu;
+            y = (uint32_t)key & 0x1FFFFFu;
+            len = alen[a];
+            apos = pos_e[a];
         }
+        const uint32_t xend = x + len;  // this anchor's window: ends in [x - G1, xend)
+        const uint64_t khi = rk | ((uint64_t)xend << 21);
+        const uint32_t x0 = lane_u32(x, 0), y0 = lane_u32(y, 0);  // the batch's first start
+        const uint32_t xend_max = wave_max_u32(mine ? xend : 0u);
+        const uint64_t khi_max = rk | ((uint64_t)xend_max << 21);
+        Best2 B{0, 0, 0, NONE32};
+        // 1. predecessors scored before the batch
+        const uint32_t xlo = x0 >= G1 ? x0 - G1 : 0;
+        for (;;) {  // blocks ending before every window: a prefix, and x0 only grows
+            const uint32_t j = jlo + lane;
+            const uint32_t cb = (uint32_t)__popcll(__ballot(j < nbr && block_end(j) < xlo));
+            jlo += cb;
+            if (cb < 64) break;
+        }
+        const auto scan = [&](uint64_t ek, uint32_t el, int32_t es, uint32_t esl) {
+            for (uint32_t i = 0; i < 64; i++) {
+                const uint64_t key = ((uint64_t)lane_u32((uint32_t)(ek >> 32), i) << 32) |
+                                     lane_u32((uint32_t)ek, i);
+                if (key >= khi_max) break;  // sorted: no later entry is in any window
+                const uint32_t bex = (uint32_t)(key >> 21) & 0x1FFFFFu;
+                const uint32_t bey = (uint32_t)key & 0x1FFFFFu;
+                const bool pass = mine && key < khi && bex + G1 >= x;
+                if (!__ballot(pass)) continue;
+                const uint32_t bl = lane_u32(el, i), bx = bex - bl, by = bey - bl;
+                if (!(bx < x0 || (bx == x0 && by < y0))) continue;  // not scored yet
+                uint32_t o, dx, dy;
+                if (pass && link_trim(bex, bey, x, y, len, o, dx, dy) && (dx > dy ? dx : dy) <= G1) {
+                    const int32_t val =
+                        (int32_t)lane_u32((uint32_t)es, i) - (int32_t)(absdiff(dx, dy) + o);
+                    if (better2(val, bx, by, B)) B = Best2{val, bx, by, lane_u32(esl, i)};
+                }
+            }
+        };
+        for (uint32_t j0 = jlo; j0 < nbr; j0 += 64) {
+            const uint32_t j = j0 + lane;
+            // block j starts no earlier than block j - 1 ends
+            const bool beyond = j >= nbr || (j > jlo && block_end(j - 1) >= xend_max);
+            const uint64_t mbey = __ballot(beyond);
+            uint64_t mneed = mbey ? (mbey & (0ull - mbey)) - 1 : ~0ull;
+            while (mneed) {
+                uint32_t jb[4];
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    jb[q] = mneed ? j0 + (uint32_t)__builtin_ctzll(mneed) : nbr;
+                    mneed &= mneed - 1;
+                }
+                uint64_t ek[4];
+                uint32_t el[4], esl[4];
+                int32_t es[4];
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const uint32_t v = lo + 64 * jb[q] + lane;
+                    const bool ok = jb[q] < nbr && v < hi;
+                    ek[q] = ok ? endkey[v] : ~0ull;
+                    el[q] = ok ? elen[v] : 0u;
+                    es[q] = ok ? (int32_t)ld_score(score_e + v) : INT32_MIN;
+                    esl[q] = ok ? byend[v] : NONE32;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; q++)
+                    if (jb[q] < nbr) scan(ek[q], el[q], es[q], esl[q]);
+            }
+            if (mbey) break;
+        }
+        // 2. predecessors inside the batch
+        for (uint32_t k = 0; k + 1 < cnt; k++) {
+            const int32_t sk = (int32_t)lane_u32((uint32_t)((int32_t)len + B.v), k);
+            const uint32_t xk = lane_u32(x, k), yk = lane_u32(y, k), lk = lane_u32(len, k);
+            const uint32_t exk = xk + lk, eyk = yk + lk;
+            if (lane > k && mine && exk < xend && exk + G1 >= x) {
+                uint32_t o, dx, dy;
+                if (link_trim(exk, eyk, x, y, len, o, dx, dy) && (dx > dy ? dx : dy) <= G1) {
+                    const int32_t val = sk - (int32_t)(absdiff(dx, dy) + o);
+                    if (better2(val, xk, yk, B)) B = Best2{val, xk, yk, lane_u32(a, k)};
+                }
+            }
+        }
+        if (mine) {
+            const int64_t sa = (int64_t)len + B.v;  // scores < 2^21
+            st_score(t1.score + a, sa);
+            st_score(score_e + apos, sa);
+            t1.pred[a] = B.v > 0 ? B.b : NONE32;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
     }
 }
 
@@ -458,33 +520,9 @@ __device__ __forceinline__ int32_t tier2_min_cost(uint32_t d) {
     return (int32_t)(d < u ? d : u);
 }
 
-// A 32-bit value of lane i (i the same in every lane).
-__device__ __forceinline__ uint32_t lane_u32(uint32_t v, uint32_t i) {
-    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)i);
-}
-
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-    for (int m = 32; m >= 1; m >>= 1) {
-        const uint32_t o = __shfl_xor(v, m);
-        v = o > v ? o : v;
-    }
-    return v;
-}
-
 __device__ __forceinline__ int64_t tier2_cost(uint32_t dx, uint32_t dy, uint32_t o) {
     const uint32_t g = absdiff(dx, dy);
     return (int64_t)(dx < dy ? dx : dy) + (g > 0 ? 10 + (int64_t)((g + 9) / 10) : 0) + (int64_t)o;
-}
-
-// The best tier-2 predecessor seen by a lane (values fit 32 bits: scores
-// lie in (-2^20, 2^20]); the same order as Best.
-struct Best2 {
-    int32_t v;
-    uint32_t x, y, b;
-};
-
-__device__ __forceinline__ bool better2(int32_t v, uint32_t x, uint32_t y, const Best2 &B) {
-    return v > B.v || (v == B.v && v > 0 && (x > B.x || (x == B.x && y > B.y)));
 }
 
 // 4a. tier-2 scores, one workgroup of T2_WAVES waves per region: the
@@ -1345,8 +1383,15 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
         DevBuf<int64_t> s1e(A);
         k_end_order<<<nb(A), 256, 0, st>>>(an, byend.p, A, elen.p, pos_e.p);
         SDF_HIP(hipGetLastError());
-        k_tier1<<<nr, 64, 0, st>>>(kxy.p, byxy.p, an.len, kend.p, byend.p, elen.p, pos_e.p, bnd.p,
-                                   nr, G1, t1, s1e.p);
+        // LDS block ends for up to T2_BLOCKS blocks of 64 anchors per region
+        DevBuf<uint32_t> most(1);
+        fill_u32(most.p, 0u, 1, st);
+        k_max_span<<<nb(n), 256, 0, st>>>(bnd.p, nr, most.p);
+        SDF_HIP(hipGetLastError());
+        const uint32_t nblk =
+            std::max<uint32_t>(1, std::min<uint32_t>(T2_BLOCKS, (read1(most.p, st) + 63) / 64));
+        k_tier1<<<nr, 64, 4 * nblk, st>>>(kxy.p, byxy.p, an.len, kend.p, byend.p, elen.p, pos_e.p,
+                                          bnd.p, nr, G1, t1, s1e.p, nblk);
         SDF_HIP(hipGetLastError());
     }
     // score order: y first (stable), then (region, score descending, x)

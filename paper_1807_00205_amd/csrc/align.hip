@@ -41,6 +41,7 @@ constexpr uint32_t MAXOCC = 32;
 constexpr uint32_t TIER2_GAP = 10000;
 constexpr uint32_t T2_BLOCKS = 4096;  // tier-2 end-order blocks per region with LDS bounds
 constexpr uint32_t T2_WAVES = 8;      // waves of a tier-2 workgroup
+constexpr uint32_t X_CAP = 1u << 19;  // ids per region with used flags in LDS (64 KiB of bits)
 constexpr uint64_t DP_CELLS = 1ull << 20;
 enum : uint32_t { OP_EQ = 7, OP_X = 8, OP_I = 1, OP_D = 2 };
 
@@ -441,14 +442,16 @@ struct Chains1 {
     uint32_t *flen;                 // length of each node's first anchor
 };
 
-// 3b. tier-1 chains of a region (one thread): anchors in score order; a
-// chain follows kept predecessors until a used one.  The region owns the
-// slots [bnd[r], bnd[r+1]) of every per-anchor array: members, nodes, tmp.
-__global__ void k_extract1(Anchors an, const uint32_t *byscore, const uint32_t *bnd, uint32_t nr,
-                           const Tier1 t1, uint8_t *used, uint32_t *tmp, Chains1 c) {
-    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nr) return;
-    const uint32_t lo = bnd[r], hi = bnd[r + 1];
+// 3b. tier-1 chains of a region: anchors in score order; an anchor not yet
+// used starts a chain that follows kept predecessors until a used one (or
+// none); the chain's anchors in x order are its members.  The region owns
+// the slots [bnd[r], bnd[r+1]) of every per-anchor array (members, nodes,
+// tmp); its anchors are the ids [bnd[r], bnd[r+1]) too (anchors are made in
+// region order).  One thread, the used flags in global memory: the
+// reference form, kept for regions with more anchors than LDS holds flags.
+__device__ void extract1_serial(const Anchors &an, const uint32_t *byscore, uint32_t r,
+                                uint32_t lo, uint32_t hi, const Tier1 &t1, uint8_t *used,
+                                uint32_t *tmp, const Chains1 &c) {
     uint32_t pos = lo, nc = 0;
     for (uint32_t u = lo; u < hi; u++) {
         uint32_t a = byscore[u];
@@ -485,6 +488,106 @@ __global__ void k_extract1(Anchors an, const uint32_t *byscore, const uint32_t *
         nc++;
     }
     c.count[r] = nc;
+}
+
+// The used flags of a region's ids [base, base + n) as bits in LDS (one
+// wave: lane 0 sets, every lane reads).
+struct UsedBits {
+    uint32_t *bits;
+    uint32_t base;
+    __device__ bool get(uint32_t a) const {
+        const uint32_t i = a - base;
+        return (__hip_atomic_load(bits + (i >> 5), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >>
+                (i & 31)) & 1u;
+    }
+    __device__ void set(uint32_t a) const {
+        const uint32_t i = a - base;
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_or(bits + (i >> 5), 1u << (i & 31), __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+};
+
+// The same chains, one 64-lane workgroup per region with the used flags in
+// LDS (regions of at most cap anchors): the lanes load the next 64 anchors
+// in score order with their predecessors and coordinates at once, and the
+// wave takes them in order; a predecessor costs one memory round trip only
+// when the chain goes on through it.  A chain's members (the walk
+// reversed) are written by the lanes together.
+__global__ __launch_bounds__(64) void k_extract1(Anchors an, const uint32_t *byscore,
+                                                 const uint32_t *bnd, uint32_t nr, const Tier1 t1,
+                                                 uint8_t *used, uint32_t *tmp, Chains1 c,
+                                                 uint32_t cap) {
+    extern __shared__ uint32_t x1_bits[];
+    const uint32_t r = blockIdx.x;
+    if (r >= nr) return;
+    const uint32_t lane = threadIdx.x;
+    const uint32_t lo = bnd[r], hi = bnd[r + 1];
+    if (hi - lo > cap) {
+        if (lane == 0) extract1_serial(an, byscore, r, lo, hi, t1, used, tmp, c);
+        return;
+    }
+    for (uint32_t j = lane; j < (hi - lo + 31) / 32; j += 64) x1_bits[j] = 0;
+    __syncthreads();
+    const UsedBits U{x1_bits, lo};
+    uint32_t pos = lo, nc = 0;
+    for (uint32_t u0 = lo; u0 < hi; u0 += 64) {
+        const uint32_t cnt = min(64u, hi - u0);
+        uint32_t ma = 0, mp = NONE32, mx = 0, my = 0, ml = 0;
+        if (lane < cnt) {
+            ma = byscore[u0 + lane];
+            mp = t1.pred[ma];
+            mx = an.x[ma];
+            my = an.y[ma];
+            ml = an.len[ma];
+        }
+        for (uint32_t i = 0; i < cnt; i++) {
+            const uint32_t a = lane_u32(ma, i);
+            if (U.get(a)) continue;
+            uint32_t cur = a, p = lane_u32(mp, i);
+            uint32_t x = lane_u32(mx, i), y = lane_u32(my, i), l = lane_u32(ml, i);
+            const uint32_t ex = x + l, ey = y + l;  // the chain's end (its last anchor)
+            int64_t w = 0;
+            uint32_t m = 0;
+            for (;;) {
+                U.set(cur);
+                if (lane == 0) tmp[lo + m] = cur;
+                m++;
+                w += l;
+                if (p == NONE32 || U.get(p)) break;
+                // the predecessor, linked to cur with its trim
+                const uint32_t px = an.x[p], py = an.y[p], pl = an.len[p], pp = t1.pred[p];
+                uint32_t o = 0, dx = 0, dy = 0;
+                link_trim(px + pl, py + pl, x, y, l, o, dx, dy);
+                w -= (int64_t)absdiff(dx, dy) + o;
+                cur = p;
+                x = px;
+                y = py;
+                l = pl;
+                p = pp;
+            }
+            if (m == 1) {
+                if (lane == 0) c.member[pos] = a;
+            } else {
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");  // tmp, written by lane 0
+                for (uint32_t t = lane; t < m; t += 64) c.member[pos + m - 1 - t] = tmp[lo + t];
+            }
+            if (lane == 0) {
+                const uint32_t node = lo + nc;
+                c.start[node] = pos;
+                c.end[node] = pos + m;
+                c.cx[node] = x;  // the first anchor: the walk's last
+                c.cy[node] = y;
+                c.cex[node] = ex;
+                c.cey[node] = ey;
+                c.w[node] = w;
+                c.flen[node] = l;
+            }
+            pos += m;
+            nc++;
+        }
+    }
+    if (lane == 0) c.count[r] = nc;
 }
 
 __global__ void k_slot_regions(const Anchors an, const uint32_t *byxy, uint64_t na,
@@ -753,14 +856,15 @@ __global__ void k_node_keys2(const uint32_t *nodes, uint64_t na, const uint32_t 
     }
 }
 
-// 4b. final chains of a region (one thread): nodes in extraction order, each
-// following kept predecessors until a used one.  Final chains of the region
-// use entries from nbnd[r] on.
-__global__ void k_extract2(const uint32_t *nbnd, uint32_t nr, const uint32_t *order,
-                           const uint32_t *pred, uint8_t *used, uint32_t *tmp, Final fin) {
-    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nr) return;
-    const uint32_t lo = nbnd[r], hi = nbnd[r + 1];
+// 4b. final chains of a region: nodes in extraction order, each not yet
+// used starting a chain that follows kept predecessors until a used one.
+// Final chains of the region use entries from nbnd[r] on; its nodes are
+// the slots [bnd[r], bnd[r] + live nodes).  One thread, the used flags in
+// global memory: the reference form, kept for regions with more slots than
+// LDS holds flags.
+__device__ void extract2_serial(uint32_t r, uint32_t lo, uint32_t hi, const uint32_t *order,
+                                const uint32_t *pred, uint8_t *used, uint32_t *tmp,
+                                const Final &fin) {
     uint32_t pos = lo, nf = 0;
     for (uint32_t u = lo; u < hi; u++) {
         uint32_t a = order[u];
@@ -777,6 +881,61 @@ __global__ void k_extract2(const uint32_t *nbnd, uint32_t nr, const uint32_t *or
         nf++;
     }
     fin.count[r] = nf;
+}
+
+// The same chains, one 64-lane workgroup per region with the used flags in
+// LDS (regions of at most cap slots), as for the tier-1 chains.
+__global__ __launch_bounds__(64) void k_extract2(const uint32_t *nbnd, const uint32_t *bnd,
+                                                 uint32_t nr, const uint32_t *order,
+                                                 const uint32_t *pred, uint8_t *used,
+                                                 uint32_t *tmp, Final fin, uint32_t cap) {
+    extern __shared__ uint32_t x2_bits[];
+    const uint32_t r = blockIdx.x;
+    if (r >= nr) return;
+    const uint32_t lane = threadIdx.x;
+    const uint32_t lo = nbnd[r], hi = nbnd[r + 1], base = bnd[r], ns = bnd[r + 1] - base;
+    if (ns > cap) {
+        if (lane == 0) extract2_serial(r, lo, hi, order, pred, used, tmp, fin);
+        return;
+    }
+    for (uint32_t j = lane; j < (ns + 31) / 32; j += 64) x2_bits[j] = 0;
+    __syncthreads();
+    const UsedBits U{x2_bits, base};
+    uint32_t pos = lo, nf = 0;
+    for (uint32_t u0 = lo; u0 < hi; u0 += 64) {
+        const uint32_t cnt = min(64u, hi - u0);
+        uint32_t ma = 0, mp = NONE32;
+        if (lane < cnt) {
+            ma = order[u0 + lane];
+            mp = pred[ma];
+        }
+        for (uint32_t i = 0; i < cnt; i++) {
+            const uint32_t a = lane_u32(ma, i);
+            if (U.get(a)) continue;
+            uint32_t cur = a, p = lane_u32(mp, i), m = 0;
+            for (;;) {
+                U.set(cur);
+                if (lane == 0) tmp[lo + m] = cur;
+                m++;
+                if (p == NONE32 || U.get(p)) break;
+                cur = p;
+                p = pred[p];
+            }
+            if (m == 1) {
+                if (lane == 0) fin.member[pos] = a;
+            } else {
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");  // tmp, written by lane 0
+                for (uint32_t t = lane; t < m; t += 64) fin.member[pos + m - 1 - t] = tmp[lo + t];
+            }
+            if (lane == 0) {
+                fin.start[lo + nf] = pos;
+                fin.end[lo + nf] = pos + m;
+            }
+            pos += m;
+            nf++;
+        }
+    }
+    if (lane == 0) fin.count[r] = nf;
 }
 
 // Final chain g (global, in region order) as (region, entry).
@@ -1378,6 +1537,7 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     DevBuf<int64_t> s1(A);
     DevBuf<uint32_t> p1(A);
     Tier1 t1{s1.p, p1.p};
+    uint32_t most_anchors = 0;  // anchors of the largest region
     {
         DevBuf<uint32_t> elen(A), pos_e(A);
         DevBuf<int64_t> s1e(A);
@@ -1388,8 +1548,9 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
         fill_u32(most.p, 0u, 1, st);
         k_max_span<<<nb(n), 256, 0, st>>>(bnd.p, nr, most.p);
         SDF_HIP(hipGetLastError());
+        most_anchors = read1(most.p, st);
         const uint32_t nblk =
-            std::max<uint32_t>(1, std::min<uint32_t>(T2_BLOCKS, (read1(most.p, st) + 63) / 64));
+            std::max<uint32_t>(1, std::min<uint32_t>(T2_BLOCKS, (most_anchors + 63) / 64));
         k_tier1<<<nr, 64, 4 * nblk, st>>>(kxy.p, byxy.p, an.len, kend.p, byend.p, elen.p, pos_e.p,
                                           bnd.p, nr, G1, t1, s1e.p, nblk);
         SDF_HIP(hipGetLastError());
@@ -1407,7 +1568,10 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
         cfl(A);
     DevBuf<int64_t> cw(A);
     Chains1 c{mem1.p, cst.p, cend.p, ccount.p, cx.p, cy.p, cex.p, cey.p, cw.p, cfl.p};
-    k_extract1<<<nb(n, 64), 64, 0, st>>>(an, byscore.p, bnd.p, nr, t1, used.p, tmp.p, c);
+    // used flags of up to X_CAP ids per region as LDS bits
+    const uint32_t xcap = (uint32_t)std::min<uint64_t>(X_CAP, (most_anchors + 31) / 32 * 32);
+    k_extract1<<<nr, 64, std::max<uint32_t>(4, xcap / 8), st>>>(an, byscore.p, bnd.p, nr, t1,
+                                                                used.p, tmp.p, c, xcap);
     SDF_HIP(hipGetLastError());
     // nodes ordered by (region, x, y)
     DevBuf<uint32_t> rslot(A), nodes(A), nbnd(n + 1);
@@ -1456,7 +1620,8 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     radix_sort_u64(kbuf.p, order.p, A, 64, st);
     fill_u32(reinterpret_cast<uint32_t *>(used.p), 0u, (A + 3) / 4, st);
     Final fin{fmem.p, fst.p, fend.p, fcount.p};
-    k_extract2<<<nb(n, 64), 64, 0, st>>>(nbnd.p, nr, order.p, p2.p, used.p, tmp.p, fin);
+    k_extract2<<<nr, 64, std::max<uint32_t>(4, xcap / 8), st>>>(nbnd.p, bnd.p, nr, order.p, p2.p,
+                                                                used.p, tmp.p, fin, xcap);
     SDF_HIP(hipGetLastError());
     DevBuf<uint64_t> foff(n + 1);
     scan_u32_to_u64(fcount.p, foff.p, n, st);

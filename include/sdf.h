@@ -424,6 +424,13 @@ typedef struct {
                                      aligned by one wave each */
     uint32_t align_wave_lds_cols; /* final SDs: the most columns whose previous row such a
                                      wave keeps in LDS (at most 4,096; global memory above) */
+    uint32_t align_lds_blocks;    /* final SDs: end-order blocks of 64 anchors or nodes per
+                                     region whose bounds the chaining tiers keep in LDS
+                                     (at most 4,096; later blocks are read from memory and
+                                     never skipped) */
+    uint32_t align_lds_ids;       /* final SDs: the most anchors of a region whose used flags
+                                     chain extraction keeps in LDS (at most 2^19; larger
+                                     regions are extracted by one thread from memory) */
 } sdf_tuning;
 
 /* Every field of *t set to SDF_AUTO. */

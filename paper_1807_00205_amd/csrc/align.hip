@@ -1543,14 +1543,15 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
         DevBuf<int64_t> s1e(A);
         k_end_order<<<nb(A), 256, 0, st>>>(an, byend.p, A, elen.p, pos_e.p);
         SDF_HIP(hipGetLastError());
-        // LDS block ends for up to T2_BLOCKS blocks of 64 anchors per region
+        // LDS block ends for up to T2_BLOCKS blocks of 64 anchors a region (align_lds_blocks)
         DevBuf<uint32_t> most(1);
         fill_u32(most.p, 0u, 1, st);
         k_max_span<<<nb(n), 256, 0, st>>>(bnd.p, nr, most.p);
         SDF_HIP(hipGetLastError());
         most_anchors = read1(most.p, st);
         const uint32_t nblk =
-            std::max<uint32_t>(1, std::min<uint32_t>(T2_BLOCKS, (most_anchors + 63) / 64));
+            std::min<uint32_t>(std::min(knob(tuning().align_lds_blocks, T2_BLOCKS), T2_BLOCKS),
+                               (most_anchors + 63) / 64);
         k_tier1<<<nr, 64, 4 * nblk, st>>>(kxy.p, byxy.p, an.len, kend.p, byend.p, elen.p, pos_e.p,
                                           bnd.p, nr, G1, t1, s1e.p, nblk);
         SDF_HIP(hipGetLastError());
@@ -1568,8 +1569,10 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
         cfl(A);
     DevBuf<int64_t> cw(A);
     Chains1 c{mem1.p, cst.p, cend.p, ccount.p, cx.p, cy.p, cex.p, cey.p, cw.p, cfl.p};
-    // used flags of up to X_CAP ids per region as LDS bits
-    const uint32_t xcap = (uint32_t)std::min<uint64_t>(X_CAP, (most_anchors + 31) / 32 * 32);
+    // used flags of up to X_CAP ids per region as LDS bits (align_lds_ids)
+    const uint32_t xcap =
+        (uint32_t)std::min<uint64_t>(std::min(knob(tuning().align_lds_ids, X_CAP), X_CAP) / 32 * 32,
+                                     (most_anchors + 31) / 32 * 32);
     k_extract1<<<nr, 64, std::max<uint32_t>(4, xcap / 8), st>>>(an, byscore.p, bnd.p, nr, t1,
                                                                 used.p, tmp.p, c, xcap);
     SDF_HIP(hipGetLastError());
@@ -1598,13 +1601,14 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
         k_invert<<<nb(A), 256, 0, st>>>(nodes_e.p, A, pos_e.p);
         k_end_starts<<<nb(A), 256, 0, st>>>(nodes_e.p, A, c, ecxy.p);
         SDF_HIP(hipGetLastError());
-        // LDS bounds for up to T2_BLOCKS blocks of 64 nodes per region
+        // LDS bounds for up to T2_BLOCKS blocks of 64 nodes per region (align_lds_blocks)
         DevBuf<uint32_t> most(1);
         fill_u32(most.p, 0u, 1, st);
         k_max_span<<<nb(n), 256, 0, st>>>(nbnd.p, nr, most.p);
         SDF_HIP(hipGetLastError());
-        const uint32_t nblk =
-            std::max<uint32_t>(1, std::min<uint32_t>(T2_BLOCKS, (read1(most.p, st) + 63) / 64));
+        const uint32_t nblk = std::min<uint32_t>(
+            std::min(knob(tuning().align_lds_blocks, T2_BLOCKS), T2_BLOCKS),
+            (read1(most.p, st) + 63) / 64);
         k_tier2<<<nr, 64 * T2_WAVES, 8 * nblk, st>>>(nbnd.p, nr, nodes.p, kbuf.p, ekey.p,
                                                      nodes_e.p, ecxy.p, pos_e.p, c, s2.p, s2e.p,
                                                      p2.p, nblk);

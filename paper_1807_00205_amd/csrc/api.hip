@@ -19,8 +19,8 @@ static thread_local sdf_tuning g_tuning = {SDF_AUTO, SDF_AUTO, SDF_AUTO, SDF_AUT
                                            SDF_AUTO, SDF_AUTO, SDF_AUTO, SDF_AUTO, SDF_AUTO,
                                            SDF_AUTO, SDF_AUTO, SDF_AUTO, SDF_AUTO, SDF_AUTO,
                                            SDF_AUTO, SDF_AUTO, SDF_AUTO, SDF_AUTO, SDF_AUTO,
-                                           SDF_AUTO, SDF_AUTO, SDF_AUTO};
-static_assert(sizeof(sdf_tuning) == 23 * sizeof(uint32_t), "every setting listed");
+                                           SDF_AUTO, SDF_AUTO, SDF_AUTO, SDF_AUTO, SDF_AUTO};
+static_assert(sizeof(sdf_tuning) == 25 * sizeof(uint32_t), "every setting listed");
 
 const sdf_tuning &tuning() { return g_tuning; }
 }  // namespace sdf

@@ -84,7 +84,7 @@ TUNING_FIELDS = ("tile_threads", "tile_core", "hits_per_part", "wg_per_cu", "spa
                  "cand_sort_small_max", "cand_tie_max", "est_lds_cap", "est_reg_cap",
                  "est_first_amax", "ext_h0", "ext_lds_words", "ext_hb0", "ext_hdiv",
                  "ext_batch_min", "ext_ecap", "ext_stats", "align_wave_cells",
-                 "align_wave_lds_cols")
+                 "align_wave_lds_cols", "align_lds_blocks", "align_lds_ids")
 
 
 class _Tuning(ctypes.Structure):

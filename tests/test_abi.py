@@ -34,7 +34,7 @@ def test_binding_layouts_match_header():
     assert sdf.SEED_DTYPE.itemsize == 24
     assert ctypes.sizeof(sdf._Span) == 24
     assert ctypes.sizeof(sdf._SearchParams) == 16
-    assert ctypes.sizeof(sdf._Tuning) == 4 * len(sdf.TUNING_FIELDS) == 92
+    assert ctypes.sizeof(sdf._Tuning) == 4 * len(sdf.TUNING_FIELDS) == 100
 
 
 def test_tuning_is_per_thread():

@@ -160,20 +160,22 @@ def config2_regions():
     ix.close()
 
 
-def _config2_check(oracle_lib, config2_regions, reg, what):
+def _config2_check(oracle_lib, config2_regions, reg, what, tunings=({},)):
     import os
     from paper_1807_00205_amd import sdf
     ix, b, off, _ = config2_regions
     reg = reg[(reg["q_end"] - reg["q_begin"] < (1 << 20)) & (reg["t_end"] - reg["t_begin"] < (1 << 20))]
-    got = ix.align_regions(reg)
     qo = off[reg["q_seq"]].astype(np.uint64)
     to = off[reg["t_seq"]].astype(np.uint64)
     rows = np.stack([reg["q_begin"] + qo, reg["q_end"] + qo, reg["t_begin"] + to,
                      reg["t_end"] + to, reg["strand"].astype(np.uint64)], axis=1)
     want = oracle_lib.sd_align(b, off, rows, 11, 1000, 0.25, min(16, os.cpu_count() or 1),
                                pad_frac=sdf.PAD_FRAC)
-    _same(got, want, what)
-    assert len(got[0]) > 0
+    assert len(want[0]) > 0
+    for tu in tunings:
+        with sdf.tuning(**tu):
+            got = ix.align_regions(reg)
+        _same(got, want, "%s %s" % (what, tu))
 
 
 def test_config2_sampled_regions(oracle_lib, config2_regions):
@@ -186,12 +188,16 @@ def test_config2_sampled_regions(oracle_lib, config2_regions):
 
 def test_config2_largest_regions(oracle_lib, config2_regions):
     """The 16 longest extended regions of the 50 Mbp workload (about 300 kbp
-    a side, tens of thousands of mostly chance anchors each): the tier-2
-    scan skips most of the end-order blocks of their nodes."""
+    a side, tens of thousands of mostly chance anchors each), with the
+    chaining tiers' block bounds and the extraction's used flags in LDS (the
+    default), for a few blocks or anchors only (the rest from memory), and
+    for none (every block read from memory, one-thread extraction)."""
     reg = config2_regions[3]
     L = (reg["q_end"] - reg["q_begin"]).astype(np.int64) + (reg["t_end"] - reg["t_begin"])
     _config2_check(oracle_lib, config2_regions, reg[np.sort(np.argsort(L, kind="stable")[-16:])],
-                   "config 2 largest")
+                   "config 2 largest",
+                   ({}, {"align_lds_blocks": 3, "align_lds_ids": 20000},
+                    {"align_lds_blocks": 0, "align_lds_ids": 0}))
 
 
 def test_errors():

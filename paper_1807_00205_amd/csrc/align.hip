@@ -1316,16 +1316,18 @@ __global__ void k_assemble(const IndexView ix, const ARegion *reg, const Anchors
     const ARegion R = reg[r];
     if (pass == 1 && !pass_out[g]) return;
     ChainStats st = {};
-    uint32_t last = 0xFFu;   // last op written
+    uint32_t last = 0xFFu;   // op of the open run
+    uint32_t run = 0;        // its length (written once it ends)
     uint64_t wop = pass == 1 ? op_off[g] : 0;
     auto emit = [&](uint32_t op, uint32_t len) {
         if (!len) return;
         if (op == last) {
-            if (pass == 1) out.cigar[wop - 1] += len << 4;
+            run += len;
         } else {
-            if (pass == 1) out.cigar[wop++] = (len << 4) | op;
+            if (pass == 1 && run) out.cigar[wop++] = (run << 4) | last;
             st.nops++;
             last = op;
+            run = len;
         }
     };
     uint64_t s = soff[g];
@@ -1336,20 +1338,19 @@ __global__ void k_assemble(const IndexView ix, const ARegion *reg, const Anchors
         if (!first) {
             uint32_t dx = 0, dy = 0;
             link_trim(qi, ti, an.x[a], an.y[a], an.len[a], o, dx, dy);
-            const Seg &S = seg[s];
-            const uint8_t *col = cols + S.ops;
-            for (uint32_t u = 0; u < ncol[s]; u++) {
-                const uint32_t op = col[u];
+            const uint8_t *col = cols + seg[s].ops;
+            const uint32_t n = ncol[s];
+            const auto column = [&](uint32_t op) {
                 st.aln++;
-                if (op == OP_EQ || op == OP_X) {
+                if (op == OP_EQ) {  // the aligners write it for equal bases only
+                    st.match++;
+                    qi++;
+                    ti++;
+                } else if (op == OP_X) {  // unequal bases, or an N on either side
                     const uint32_t x = base_at(ix, R.q0 + qi), y = t_base(ix, R, ti);
-                    if (x < 4 && x == y) {
-                        st.match++;
-                    } else {
-                        st.mism++;
-                        if (x < 4 && y < 4) {
-                            if ((x ^ y) == 2) st.ts++; else st.tv++;
-                        }
+                    st.mism++;
+                    if (x < 4 && y < 4) {
+                        if ((x ^ y) == 2) st.ts++; else st.tv++;
                     }
                     qi++;
                     ti++;
@@ -1363,6 +1364,15 @@ __global__ void k_assemble(const IndexView ix, const ARegion *reg, const Anchors
                     ti++;
                 }
                 emit(op, 1);
+            };
+            // 16 column ops at a time, all loaded before any is used
+            for (uint32_t u0 = 0; u0 < n; u0 += 16) {
+                uint8_t cb[16];
+#pragma unroll
+                for (uint32_t q = 0; q < 16; q++) cb[q] = u0 + q < n ? col[u0 + q] : 0;
+#pragma unroll
+                for (uint32_t q = 0; q < 16; q++)
+                    if (u0 + q < n) column(cb[q]);
             }
             s++;
         } else {
@@ -1381,6 +1391,7 @@ __global__ void k_assemble(const IndexView ix, const ARegion *reg, const Anchors
         st.ex = qi;
         st.ey = ti;
     });
+    if (pass == 1 && run) out.cigar[wop++] = (run << 4) | last;  // the last run
     const bool ok = st.aln >= min_len && (double)(st.mism + st.opens) <= delta * (double)st.aln;
     if (pass == 0) {
         pass_out[g] = ok ? 1u : 0u;

@@ -1054,16 +1054,21 @@ __device__ __forceinline__ uint32_t seg_mode(uint32_t dx, uint32_t dy, uint32_t 
     return dy + 1 <= wave_cols ? SEG_WAVE_LDS : SEG_WAVE_GLOBAL;
 }
 
+// Traceback byte of a cell (i, j): bits 0-1 the best state before a
+// diagonal step, 2-3 the source of the query-gap state, 4-5 of the
+// target-gap state, and TB_EQ when query base i - 1 equals target base j - 1
+// (neither an N), so that the traceback reads no bases.
+constexpr uint8_t TB_EQ = 64;
+
 // The traceback of a filled stretch from its end state st (0 M, 1 I, 2 D):
 // column operations written to out in order; returns their number.
-__device__ uint32_t trace_back(const IndexView &ix, const ARegion &R, const Seg &S,
-                               const uint8_t *T, uint32_t W, int st, uint8_t *out) {
+__device__ uint32_t trace_back(const Seg &S, const uint8_t *T, uint32_t W, int st,
+                               uint8_t *out) {
     uint32_t i = S.dx, j = S.dy, n = 0;
     while (i > 0 || j > 0) {
         const uint8_t code = T[(uint64_t)i * W + j];
         if (st == 0) {
-            const uint32_t a = base_at(ix, R.q0 + S.qx + i - 1), b = t_base(ix, R, S.ty + j - 1);
-            out[n++] = (a < 4 && a == b) ? OP_EQ : OP_X;
+            out[n++] = (code & TB_EQ) ? OP_EQ : OP_X;
             st = code & 3;
             i--;
             j--;
@@ -1105,9 +1110,18 @@ __global__ void k_align_segs(const IndexView ix, const ARegion *reg, const Seg *
     if (!seg_cells(dx, dy)) {  // the diagonal stand-in
         const uint32_t m = dx < dy ? dx : dy;
         uint32_t n = 0;
-        for (uint32_t i = 0; i < m; i++) {
-            const uint32_t a = base_at(ix, R.q0 + S.qx + i), b = t_base(ix, R, S.ty + i);
-            out[n++] = (a < 4 && a == b) ? OP_EQ : OP_X;
+        for (uint32_t i0 = 0; i0 < m; i0 += 16) {  // 16 base pairs read before any op is written
+            uint8_t v[16];
+#pragma unroll
+            for (uint32_t q = 0; q < 16; q++) {
+                const uint32_t i = i0 + q;
+                const uint32_t a = i < m ? base_at(ix, R.q0 + S.qx + i) : 4u;
+                const uint32_t b = i < m ? t_base(ix, R, S.ty + i) : 4u;
+                v[q] = (a < 4 && a == b) ? OP_EQ : OP_X;
+            }
+#pragma unroll
+            for (uint32_t q = 0; q < 16; q++)
+                if (i0 + q < m) out[n++] = v[q];
         }
         for (uint32_t i = m; i < dx; i++) out[n++] = OP_I;
         for (uint32_t j = m; j < dy; j++) out[n++] = OP_D;
@@ -1118,56 +1132,73 @@ __global__ void k_align_segs(const IndexView ix, const ARegion *reg, const Seg *
     uint8_t *T = tb + S.cells;
     int *Mr = rows + S.rows, *Ir = Mr + W, *Dr = Ir + W;  // row i - 1, then row i in place
     const int GO = 4, GE = 2, MA = 2, MI = -4;
+    constexpr uint32_t CH = 8;  // cells whose loads are issued before any of them is written
     for (uint32_t i = 0; i <= dx; i++) {
         const uint32_t qa = i ? base_at(ix, R.q0 + S.qx + i - 1) : 4u;
         int pm = NEG, pi = NEG, pd = NEG;  // row i - 1, column j - 1
-        for (uint32_t j = 0; j <= dy; j++) {
-            const int um = Mr[j], ui = Ir[j], ud = Dr[j];  // row i - 1, column j (i > 0)
-            int m = NEG, ii = NEG, dd = NEG;
-            uint8_t code = 0;
-            if (i == 0 && j == 0) {
-                m = 0;
-            } else {
-                if (i > 0 && j > 0) {
-                    int best = pm;
-                    uint8_t st = 0;
-                    if (pi > best) { best = pi; st = 1; }
-                    if (pd > best) { best = pd; st = 2; }
-                    if (best > NEG / 2) {
-                        const uint32_t tbase = t_base(ix, R, S.ty + j - 1);
-                        m = best + ((qa < 4 && qa == tbase) ? MA : MI);
-                    }
-                    code |= st;
-                }
-                if (i > 0) {
-                    const int a = um > NEG / 2 ? um - GO - GE : NEG;
-                    const int b = ui > NEG / 2 ? ui - GE : NEG;
-                    const int d = ud > NEG / 2 ? ud - GO - GE : NEG;
-                    ii = a;
-                    uint8_t st = 0;
-                    if (b > ii) { ii = b; st = 1; }
-                    if (d > ii) { ii = d; st = 2; }
-                    code |= st << 2;
-                }
-                if (j > 0) {
-                    const int lm = Mr[j - 1], li = Ir[j - 1], ld = Dr[j - 1];  // row i, column j - 1
-                    const int a = lm > NEG / 2 ? lm - GO - GE : NEG;
-                    const int b = li > NEG / 2 ? li - GO - GE : NEG;
-                    const int d = ld > NEG / 2 ? ld - GE : NEG;
-                    dd = a;
-                    uint8_t st = 0;
-                    if (b > dd) { dd = b; st = 1; }
-                    if (d > dd) { dd = d; st = 2; }
-                    code |= st << 4;
-                }
+        int lm = NEG, li = NEG, ld = NEG;  // row i, column j - 1
+        for (uint32_t j0 = 0; j0 <= dy; j0 += CH) {
+            int um[CH], ui[CH], ud[CH];  // row i - 1, column j (i > 0)
+            uint32_t tbv[CH];            // target base j - 1 (j > 0)
+#pragma unroll
+            for (uint32_t q = 0; q < CH; q++) {
+                const uint32_t j = j0 + q;
+                const bool in = j <= dy;
+                um[q] = in && i ? Mr[j] : NEG;
+                ui[q] = in && i ? Ir[j] : NEG;
+                ud[q] = in && i ? Dr[j] : NEG;
+                tbv[q] = in && i && j ? t_base(ix, R, S.ty + j - 1) : 4u;
             }
-            pm = um;
-            pi = ui;
-            pd = ud;
-            Mr[j] = m;
-            Ir[j] = ii;
-            Dr[j] = dd;
-            T[(uint64_t)i * W + j] = code;
+#pragma unroll
+            for (uint32_t q = 0; q < CH; q++) {
+                const uint32_t j = j0 + q;
+                if (j > dy) break;
+                int m = NEG, ii = NEG, dd = NEG;
+                uint8_t code = 0;
+                if (i == 0 && j == 0) {
+                    m = 0;
+                } else {
+                    if (i > 0 && j > 0) {
+                        int best = pm;
+                        uint8_t st = 0;
+                        if (pi > best) { best = pi; st = 1; }
+                        if (pd > best) { best = pd; st = 2; }
+                        const bool eq = qa < 4 && qa == tbv[q];
+                        if (best > NEG / 2) m = best + (eq ? MA : MI);
+                        code |= st | (eq ? TB_EQ : 0);
+                    }
+                    if (i > 0) {
+                        const int a = um[q] > NEG / 2 ? um[q] - GO - GE : NEG;
+                        const int b = ui[q] > NEG / 2 ? ui[q] - GE : NEG;
+                        const int d = ud[q] > NEG / 2 ? ud[q] - GO - GE : NEG;
+                        ii = a;
+                        uint8_t st = 0;
+                        if (b > ii) { ii = b; st = 1; }
+                        if (d > ii) { ii = d; st = 2; }
+                        code |= st << 2;
+                    }
+                    if (j > 0) {
+                        const int a = lm > NEG / 2 ? lm - GO - GE : NEG;
+                        const int b = li > NEG / 2 ? li - GO - GE : NEG;
+                        const int d = ld > NEG / 2 ? ld - GE : NEG;
+                        dd = a;
+                        uint8_t st = 0;
+                        if (b > dd) { dd = b; st = 1; }
+                        if (d > dd) { dd = d; st = 2; }
+                        code |= st << 4;
+                    }
+                }
+                pm = um[q];
+                pi = ui[q];
+                pd = ud[q];
+                lm = m;
+                li = ii;
+                ld = dd;
+                Mr[j] = m;
+                Ir[j] = ii;
+                Dr[j] = dd;
+                T[(uint64_t)i * W + j] = code;
+            }
         }
     }
     // end state: ties M, then I, then D
@@ -1177,7 +1208,7 @@ __global__ void k_align_segs(const IndexView ix, const ARegion *reg, const Seg *
         if (Ir[dy] > best) { best = Ir[dy]; st = 1; }
         if (Dr[dy] > best) { best = Dr[dy]; st = 2; }
     }
-    ncol[t] = trace_back(ix, R, S, T, W, st, out);
+    ncol[t] = trace_back(S, T, W, st, out);
 }
 
 // 5c. one 64-lane workgroup per large stretch, the same recurrence and tie
@@ -1194,7 +1225,8 @@ __global__ __launch_bounds__(64) void k_align_wave(const IndexView ix, const ARe
                                                    int *rows, uint8_t *cols, uint32_t *ncol,
                                                    uint32_t wave_cells, uint32_t wave_cols) {
     __shared__ int LM[GLOBAL ? 1 : WAVE_COLS], LI[GLOBAL ? 1 : WAVE_COLS],
-        LD[GLOBAL ? 1 : WAVE_COLS];  // row i - 1, per column
+        LD[GLOBAL ? 1 : WAVE_COLS];     // row i - 1, per column
+    __shared__ uint8_t TBc[WAVE_COLS];  // target base j - 1 of the first WAVE_COLS columns
     const uint64_t t = blockIdx.x;
     if (t >= ns) return;
     const Seg S = seg[t];
@@ -1210,6 +1242,9 @@ __global__ __launch_bounds__(64) void k_align_wave(const IndexView ix, const ARe
     const uint32_t c0 = min(W, lane * SW), c1 = min(W, c0 + SW);
     uint8_t *T = tb + S.cells;
     const int GO = 4, GE = 2, MA = 2, MI = -4;
+    for (uint32_t j = lane; j < W && j < WAVE_COLS; j += 64)
+        TBc[j] = j ? (uint8_t)t_base(ix, R, S.ty + j - 1) : (uint8_t)4;
+    __syncthreads();
     int oM = NEG, oI = NEG, oD = NEG;  // this lane's last column of its previous row
     int gM = NEG, gI = NEG, gD = NEG;  // (row i - 1, column c0 - 1), received a step earlier
     for (uint32_t step = 0; step < dx + 64; step++) {
@@ -1234,11 +1269,11 @@ __global__ __launch_bounds__(64) void k_align_wave(const IndexView ix, const ARe
                         uint8_t st = 0;
                         if (pi > best) { best = pi; st = 1; }
                         if (pd > best) { best = pd; st = 2; }
-                        if (best > NEG / 2) {
-                            const uint32_t tbase = t_base(ix, R, S.ty + j - 1);
-                            m = best + ((qa < 4 && qa == tbase) ? MA : MI);
-                        }
-                        code |= st;
+                        const uint32_t tbase =
+                            j < WAVE_COLS ? (uint32_t)TBc[j] : t_base(ix, R, S.ty + j - 1);
+                        const bool eq = qa < 4 && qa == tbase;
+                        if (best > NEG / 2) m = best + (eq ? MA : MI);
+                        code |= st | (eq ? TB_EQ : 0);
                     }
                     if (i > 0) {
                         const int a = um > NEG / 2 ? um - GO - GE : NEG;
@@ -1285,7 +1320,7 @@ __global__ __launch_bounds__(64) void k_align_wave(const IndexView ix, const ARe
         int st = 0, best = PM[dy];
         if (PI[dy] > best) { best = PI[dy]; st = 1; }
         if (PD[dy] > best) { best = PD[dy]; st = 2; }
-        ncol[t] = trace_back(ix, R, S, T, W, st, cols + S.ops);
+        ncol[t] = trace_back(S, T, W, st, cols + S.ops);
     }
 }
 

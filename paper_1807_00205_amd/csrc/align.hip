@@ -105,6 +105,34 @@ __device__ __forceinline__ uint64_t first_at_least(const uint64_t *key, uint64_t
     return lo;
 }
 
+// Every TS-th target key (smp[i] = tkey[TS i]): a search first finds its
+// block of TS keys among the samples (a small array that stays in cache)
+// and then its key inside the block, so that it reads few lines of the
+// large key array.
+constexpr uint64_t TS = 32;
+
+__global__ void k_key_samples(const uint64_t *key, uint64_t n, uint64_t *smp) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i * TS < n) smp[i] = key[i * TS];
+}
+
+// first_at_least(key, n, x) through the samples smp[0, (n + TS - 1) / TS).
+__device__ __forceinline__ uint64_t first_at_least_s(const uint64_t *key, uint64_t n,
+                                                     const uint64_t *smp, uint64_t x) {
+    uint64_t lo = 0, hi = (n + TS - 1) / TS;  // first sample >= x
+    while (lo < hi) {
+        const uint64_t m = (lo + hi) >> 1;
+        if (smp[m] < x) lo = m + 1; else hi = m;
+    }
+    // keys before sample lo - 1's are below x; sample lo's (if any) is >= x
+    uint64_t a = lo ? (lo - 1) * TS + 1 : 0, b = min(n, lo * TS);
+    while (a < b) {
+        const uint64_t m = (a + b) >> 1;
+        if (key[m] < x) a = m + 1; else b = m;
+    }
+    return a;
+}
+
 // The query k-mer at x of region R (false when it holds a gap base or ends
 // past the side).
 __device__ __forceinline__ bool q_kmer(const IndexView &ix, const ARegion &R, uint64_t x,
@@ -122,7 +150,7 @@ __device__ __forceinline__ bool q_kmer(const IndexView &ix, const ARegion &R, ui
 // 1b. seed matches per query position (0 for seeds above MAXOCC)
 __global__ void k_q_count(const IndexView ix, const ARegion *reg, uint32_t nr,
                           const uint64_t *qoff, uint64_t total, uint32_t k, const uint64_t *tkey,
-                          uint64_t ntk, uint32_t *cnt) {
+                          uint64_t ntk, const uint64_t *smp, uint32_t *cnt) {
     for (uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; f < total;
          f += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t r = region_of(qoff, nr, f);
@@ -131,8 +159,10 @@ __global__ void k_q_count(const IndexView ix, const ARegion *reg, uint32_t nr,
         uint32_t c = 0;
         if (q_kmer(ix, R, f - qoff[r], k, code)) {
             const uint64_t base = ((uint64_t)r << 42) | (code << 20);
-            const uint64_t a = first_at_least(tkey, ntk, base);
-            const uint64_t b = first_at_least(tkey, ntk, base + (1ull << 20));
+            const uint64_t a = first_at_least_s(tkey, ntk, smp, base);
+            // the occurrences end among the next MAXOCC + 1 keys, or there are too many
+            const uint64_t e = min(ntk, a + MAXOCC + 1);
+            const uint64_t b = a + first_at_least(tkey + a, e - a, base + (1ull << 20));
             c = (b - a <= MAXOCC) ? (uint32_t)(b - a) : 0u;
         }
         cnt[f] = c;
@@ -142,7 +172,8 @@ __global__ void k_q_count(const IndexView ix, const ARegion *reg, uint32_t nr,
 // 2a. match keys: region << 41 | (y - x + 2^20) << 20 | x
 __global__ void k_q_emit(const IndexView ix, const ARegion *reg, uint32_t nr, const uint64_t *qoff,
                          uint64_t total, uint32_t k, const uint64_t *tkey, uint64_t ntk,
-                         const uint32_t *cnt, const uint64_t *moff, uint64_t *mkey, uint32_t *mval) {
+                         const uint64_t *smp, const uint32_t *cnt, const uint64_t *moff,
+                         uint64_t *mkey, uint32_t *mval) {
     for (uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; f < total;
          f += (uint64_t)gridDim.x * blockDim.x) {
         if (!cnt[f]) continue;
@@ -152,7 +183,7 @@ __global__ void k_q_emit(const IndexView ix, const ARegion *reg, uint32_t nr, co
         uint64_t code;
         q_kmer(ix, R, x, k, code);
         const uint64_t base = ((uint64_t)r << 42) | (code << 20);
-        const uint64_t a = first_at_least(tkey, ntk, base);
+        const uint64_t a = first_at_least_s(tkey, ntk, smp, base);
         for (uint32_t t = 0; t < cnt[f]; t++) {
             const uint64_t y = tkey[a + t] & 0xFFFFF;
             const uint64_t d = y + (1ull << 20) - x;
@@ -1528,12 +1559,18 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
         SDF_HIP(hipGetLastError());
         radix_sort_u64(tkey.p, tval.p, TT, 64, st);
     }
-    // matches per query position, their offsets, the matches sorted
+    // samples of the target keys, matches per query position, their
+    // offsets, the matches sorted
+    DevBuf<uint64_t> smp((TT + TS - 1) / TS + 1);
+    if (TT) {
+        k_key_samples<<<nb((TT + TS - 1) / TS), 256, 0, st>>>(tkey.p, TT, smp.p);
+        SDF_HIP(hipGetLastError());
+    }
     DevBuf<uint32_t> qcnt(QT + 1);
     DevBuf<uint64_t> moff(QT + 1);
     if (QT) {
         k_q_count<<<grid_stride(QT), 256, 0, st>>>(ix, dreg.p, nr, qoff.p, QT, k, tkey.p, TT,
-                                                   qcnt.p);
+                                                   smp.p, qcnt.p);
         SDF_HIP(hipGetLastError());
     }
     scan_u32_to_u64(qcnt.p, moff.p, QT, st);
@@ -1541,13 +1578,14 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     DevBuf<uint64_t> mkey(M + 1);
     DevBuf<uint32_t> mval(M + 1);
     if (M) {
-        k_q_emit<<<grid_stride(QT), 256, 0, st>>>(ix, dreg.p, nr, qoff.p, QT, k, tkey.p, TT, qcnt.p,
-                                                  moff.p, mkey.p, mval.p);
+        k_q_emit<<<grid_stride(QT), 256, 0, st>>>(ix, dreg.p, nr, qoff.p, QT, k, tkey.p, TT, smp.p,
+                                                  qcnt.p, moff.p, mkey.p, mval.p);
         SDF_HIP(hipGetLastError());
         radix_sort_u64(mkey.p, mval.p, M, 64, st);
     }
     tkey.reset();
     tval.reset();
+    smp.reset();
     // 2. anchors
     stage.emplace("sdf final SDs: anchors");
     DevBuf<uint32_t> flag(M + 1), fpre(M + 1);

@@ -992,6 +992,8 @@ struct Seg {
     uint32_t region;
     uint32_t qx, ty;  // start of the stretch on Q and T'
     uint32_t dx, dy;
+    uint32_t keep;    // bases of the anchor after it, past the anchor's cut
+    uint32_t _pad;
     uint64_t cells;   // offset of its traceback bytes
     uint64_t ops;     // offset of its column operations
     uint64_t rows;    // offset of its rolling score rows
@@ -1036,12 +1038,13 @@ __global__ void k_seg_count(const Anchors an, const Chains1 c, const Final fin,
 __global__ void k_seg_emit(const Anchors an, const Chains1 c, const Final fin,
                            const uint64_t *foff, uint32_t nr, const uint32_t *nbnd, uint64_t nf,
                            const uint64_t *soff, const uint64_t *coff, const uint64_t *ooff,
-                           const uint64_t *roff, Seg *seg) {
+                           const uint64_t *roff, Seg *seg, uint32_t *fanchor) {
     const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= nf) return;
     uint32_t r, e;
     final_of(foff, nr, g, nbnd, r, e);
     uint64_t s = soff[g], cells = coff[g], ops = ooff[g], rows = roff[g];
+    uint32_t *const first3 = fanchor + 3 * g;  // the chain's first anchor: x, y, length
     uint32_t px = 0, py = 0;
     bool first = true;
     walk_anchors(c, fin, e, [&](uint32_t a) {
@@ -1053,6 +1056,8 @@ __global__ void k_seg_emit(const Anchors an, const Chains1 c, const Final fin,
             x.qx = px;
             x.ty = py;
             link_trim(px, py, an.x[a], an.y[a], an.len[a], o, x.dx, x.dy);
+            x.keep = an.len[a] - o;
+            x._pad = 0;
             x.cells = cells;
             x.ops = ops;
             x.rows = rows;
@@ -1061,6 +1066,10 @@ __global__ void k_seg_emit(const Anchors an, const Chains1 c, const Final fin,
             cells += cc;
             ops += (uint64_t)x.dx + x.dy;
             rows += cc ? 3ull * (x.dy + 1) : 0;
+        } else {  // the chain's first anchor, kept whole
+            first3[0] = an.x[a];
+            first3[1] = an.y[a];
+            first3[2] = an.len[a];
         }
         first = false;
         px = an.x[a] + an.len[a];
@@ -1367,97 +1376,190 @@ struct ChainStats {
     uint32_t x0, y0, ex, ey;
 };
 
-// 6. one thread per final chain: merged operations, counts, report rule;
-// pass 0 counts (ops, passing), pass 1 writes record and CIGAR.
-__global__ void k_assemble(const IndexView ix, const ARegion *reg, const Anchors an,
-                           const Chains1 c, const Final fin, const uint64_t *foff, uint32_t nr,
-                           const uint32_t *nbnd, uint64_t nf, const uint64_t *soff, const Seg *seg,
-                           const uint8_t *cols, const uint32_t *ncol, uint32_t min_len,
-                           double delta, int pass, uint32_t *nops_out, uint32_t *pass_out,
-                           const uint64_t *wr_off, const uint64_t *op_off, SdOut out) {
-    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= nf) return;
-    uint32_t r, e;
-    final_of(foff, nr, g, nbnd, r, e);
-    const ARegion R = reg[r];
-    if (pass == 1 && !pass_out[g]) return;
-    ChainStats st = {};
-    uint32_t last = 0xFFu;   // op of the open run
-    uint32_t run = 0;        // its length (written once it ends)
-    uint64_t wop = pass == 1 ? op_off[g] : 0;
-    auto emit = [&](uint32_t op, uint32_t len) {
-        if (!len) return;
-        if (op == last) {
-            run += len;
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
+// One lane's share of a final chain: the stretch before its anchor (n
+// column ops at col, starting at (qi, ti); none for the chain's first
+// anchor) and then the anchor's '=' run of `keep` bases.  Calls run(op, len)
+// for its runs in order (equal ops next to each other merged) and, when
+// `counts`, adds its columns to the counts (I and D runs that start in the
+// share are counted as opened).
+template <class F>
+__device__ __forceinline__ void walk_share(const IndexView &ix, const ARegion &R, const uint8_t *col,
+                                           uint32_t n, uint32_t qi, uint32_t ti, uint32_t keep,
+                                           bool counts, ChainStats &st, F &&run) {
+    uint32_t cur = 0xFFu, len = 0;
+    const auto op1 = [&](uint32_t op) {
+        if (counts) {
+            st.aln++;
+            if (op == OP_EQ) {  // the aligners write it for equal bases only
+                st.match++;
+                qi++;
+                ti++;
+            } else if (op == OP_X) {  // unequal bases, or an N on either side
+                const uint32_t x = base_at(ix, R.q0 + qi), y = t_base(ix, R, ti);
+                st.mism++;
+                if (x < 4 && y < 4) {
+                    if ((x ^ y) == 2) st.ts++; else st.tv++;
+                }
+                qi++;
+                ti++;
+            } else if (op == OP_I) {
+                st.ins++;
+                if (cur != OP_I) st.opens++;
+                qi++;
+            } else {
+                st.del++;
+                if (cur != OP_D) st.opens++;
+                ti++;
+            }
+        }
+        if (op == cur) {
+            len++;
         } else {
-            if (pass == 1 && run) out.cigar[wop++] = (run << 4) | last;
-            st.nops++;
-            last = op;
-            run = len;
+            if (len) run(cur, len);
+            cur = op;
+            len = 1;
         }
     };
-    uint64_t s = soff[g];
-    bool first = true;
-    uint32_t qi = 0, ti = 0;
-    walk_anchors(c, fin, e, [&](uint32_t a) {
-        uint32_t o = 0;  // bases cut from the anchor's start by its link
-        if (!first) {
-            uint32_t dx = 0, dy = 0;
-            link_trim(qi, ti, an.x[a], an.y[a], an.len[a], o, dx, dy);
-            const uint8_t *col = cols + seg[s].ops;
-            const uint32_t n = ncol[s];
-            const auto column = [&](uint32_t op) {
-                st.aln++;
-                if (op == OP_EQ) {  // the aligners write it for equal bases only
-                    st.match++;
-                    qi++;
-                    ti++;
-                } else if (op == OP_X) {  // unequal bases, or an N on either side
-                    const uint32_t x = base_at(ix, R.q0 + qi), y = t_base(ix, R, ti);
-                    st.mism++;
-                    if (x < 4 && y < 4) {
-                        if ((x ^ y) == 2) st.ts++; else st.tv++;
-                    }
-                    qi++;
-                    ti++;
-                } else if (op == OP_I) {
-                    st.ins++;
-                    if (last != OP_I) st.opens++;
-                    qi++;
-                } else {
-                    st.del++;
-                    if (last != OP_D) st.opens++;
-                    ti++;
-                }
-                emit(op, 1);
-            };
-            // 16 column ops at a time, all loaded before any is used
-            for (uint32_t u0 = 0; u0 < n; u0 += 16) {
-                uint8_t cb[16];
+    // 16 column ops at a time, all loaded before any is used
+    for (uint32_t u0 = 0; u0 < n; u0 += 16) {
+        uint8_t cb[16];
 #pragma unroll
-                for (uint32_t q = 0; q < 16; q++) cb[q] = u0 + q < n ? col[u0 + q] : 0;
+        for (uint32_t q = 0; q < 16; q++) cb[q] = u0 + q < n ? col[u0 + q] : 0;
 #pragma unroll
-                for (uint32_t q = 0; q < 16; q++)
-                    if (u0 + q < n) column(cb[q]);
-            }
-            s++;
-        } else {
-            st.x0 = an.x[a];
-            st.y0 = an.y[a];
-            qi = an.x[a];
-            ti = an.y[a];
+        for (uint32_t q = 0; q < 16; q++)
+            if (u0 + q < n) op1(cb[q]);
+    }
+    if (keep) {
+        if (counts) {
+            st.aln += keep;
+            st.match += keep;
         }
-        first = false;
-        const uint32_t keep = an.len[a] - o;
-        emit(OP_EQ, keep);
-        st.aln += keep;
-        st.match += keep;
-        qi += keep;
-        ti += keep;
-        st.ex = qi;
-        st.ey = ti;
-    });
-    if (pass == 1 && run) out.cigar[wop++] = (run << 4) | last;  // the last run
+        if (cur == OP_EQ) {
+            len += keep;
+        } else {
+            if (len) run(cur, len);
+            cur = OP_EQ;
+            len = keep;
+        }
+    }
+    if (len) run(cur, len);
+}
+
+// 6. records and CIGARs, one 64-lane workgroup per final chain: the chain
+// is its first anchor's '=' run and then its stretches in order (soff[g] ..
+// soff[g + 1]), each followed by its anchor's '=' run after the cut; the
+// lanes take 64 consecutive stretches at a time.  Each lane counts its
+// columns and runs; then, lane after lane in order, the runs at the lanes'
+// borders are merged with the run still open and placed in the CIGAR (the
+// runs inside a lane's share are placed by that lane).  Pass 0 counts (ops,
+// passing), pass 1 writes record and CIGAR.
+__global__ __launch_bounds__(64) void k_assemble(const IndexView ix, const ARegion *reg,
+                                                 const uint64_t *foff, uint32_t nr, uint64_t nf,
+                                                 const uint64_t *soff, const Seg *seg,
+                                                 const uint8_t *cols, const uint32_t *ncol,
+                                                 const uint32_t *fanchor, uint32_t min_len,
+                                                 double delta, int pass, uint32_t *nops_out,
+                                                 uint32_t *pass_out, const uint64_t *wr_off,
+                                                 const uint64_t *op_off, SdOut out) {
+    const uint64_t g = blockIdx.x;
+    if (g >= nf) return;
+    const uint32_t lane = threadIdx.x;
+    if (pass == 1 && !pass_out[g]) return;
+    const uint32_t r = region_of(foff, nr, g);
+    const ARegion R = reg[r];
+    const uint64_t s0 = soff[g], ns = soff[g + 1] - s0;
+    uint32_t *const cig = pass == 1 ? out.cigar + op_off[g] : nullptr;
+    ChainStats st = {};  // the chain's counts (the same in every lane)
+    st.x0 = fanchor[3 * g];
+    st.y0 = fanchor[3 * g + 1];
+    const uint32_t l0 = fanchor[3 * g + 2];
+    st.aln = st.match = l0;
+    st.ex = st.x0 + l0;
+    st.ey = st.y0 + l0;
+    uint32_t open_op = OP_EQ, open_len = l0;  // the run still open
+    uint32_t placed = 0;                      // CIGAR runs placed so far
+    int32_t opens_adj = 0;
+    const auto place = [&](uint32_t op, uint32_t len) {  // a complete run (uniform)
+        if (!len) return;
+        if (cig && lane == 0) cig[placed] = (len << 4) | op;
+        placed++;
+    };
+    for (uint64_t j0 = 0; j0 < ns; j0 += 64) {
+        const uint32_t cnt = (uint32_t)min<uint64_t>(64, ns - j0);
+        const bool mine = lane < cnt;
+        Seg S{};
+        uint32_t n = 0;
+        if (mine) {
+            S = seg[s0 + j0 + lane];
+            n = ncol[s0 + j0 + lane];
+        }
+        const uint8_t *col = cols + S.ops;
+        const uint32_t keep = mine ? S.keep : 0u;
+        // the lane's runs: how many, the first and the last
+        ChainStats ls = {};
+        uint32_t nruns = 0, fo = 0, fl = 0, lo = 0, ll = 0;
+        walk_share(ix, R, col, n, S.qx, S.ty, keep, true, ls, [&](uint32_t op, uint32_t len) {
+            if (!nruns) {
+                fo = op;
+                fl = len;
+            }
+            lo = op;
+            ll = len;
+            nruns++;
+        });
+        // lane by lane: merge at the borders, place the complete runs
+        uint32_t mid = 0;  // where this lane's inner runs go
+        for (uint32_t t = 0; t < cnt; t++) {
+            const uint32_t nt = lane_u32(nruns, t), fot = lane_u32(fo, t), flt = lane_u32(fl, t);
+            const uint32_t lot = lane_u32(lo, t), llt = lane_u32(ll, t);
+            if (!nt) continue;
+            const bool merged = fot == open_op;
+            if (merged && (fot == OP_I || fot == OP_D)) opens_adj--;  // not a new gap
+            if (merged) {
+                open_len += flt;
+            } else {
+                place(open_op, open_len);
+                open_op = fot;
+                open_len = flt;
+            }
+            if (nt >= 2) {
+                place(open_op, open_len);  // the lane's first run is complete
+                if (lane == t) mid = placed;
+                placed += nt - 2;
+                open_op = lot;
+                open_len = llt;
+            }
+        }
+        if (cig && nruns > 2) {  // this lane's inner runs
+            uint32_t j = 0;
+            ChainStats unused;
+            walk_share(ix, R, col, n, S.qx, S.ty, keep, false, unused,
+                       [&](uint32_t op, uint32_t len) {
+                           if (j > 0 && j + 1 < nruns) cig[mid + j - 1] = (len << 4) | op;
+                           j++;
+                       });
+        }
+        st.aln += wave_sum_u32(ls.aln);
+        st.match += wave_sum_u32(ls.match);
+        st.mism += wave_sum_u32(ls.mism);
+        st.ins += wave_sum_u32(ls.ins);
+        st.del += wave_sum_u32(ls.del);
+        st.opens += wave_sum_u32(ls.opens);
+        st.ts += wave_sum_u32(ls.ts);
+        st.tv += wave_sum_u32(ls.tv);
+        // the end of the last stretch's anchor
+        st.ex = lane_u32(S.qx + S.dx + keep, cnt - 1);
+        st.ey = lane_u32(S.ty + S.dy + keep, cnt - 1);
+    }
+    place(open_op, open_len);  // the last run
+    st.opens = (uint32_t)((int32_t)st.opens + opens_adj);
+    st.nops = placed;
+    if (lane != 0) return;
     const bool ok = st.aln >= min_len && (double)(st.mism + st.opens) <= delta * (double)st.aln;
     if (pass == 0) {
         pass_out[g] = ok ? 1u : 0u;
@@ -1740,8 +1842,9 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     DevBuf<uint8_t> tb(NC + 1), cols(NO + 1);
     DevBuf<int> rows(NRW + 1);
     DevBuf<uint32_t> ncol(NS + 1);
+    DevBuf<uint32_t> fanchor(3 * NF);
     k_seg_emit<<<nb(NF), 256, 0, st>>>(an, c, fin, foff.p, nr, nbnd.p, NF, soff.p, coff.p, ooff.p,
-                                       roff.p, seg.p);
+                                       roff.p, seg.p, fanchor.p);
     SDF_HIP(hipGetLastError());
     if (NS) {
         const uint32_t wave_cells = knob(tuning().align_wave_cells, 1u << 14);
@@ -1761,9 +1864,9 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     stage.emplace("sdf final SDs: records");
     DevBuf<uint32_t> aops(NF + 1), apass(NF + 1);
     SdOut none{nullptr, nullptr};
-    k_assemble<<<nb(NF, 64), 64, 0, st>>>(ix, dreg.p, an, c, fin, foff.p, nr, nbnd.p, NF, soff.p,
-                                          seg.p, cols.p, ncol.p, min_len, delta, 0, aops.p,
-                                          apass.p, nullptr, nullptr, none);
+    k_assemble<<<(unsigned)NF, 64, 0, st>>>(ix, dreg.p, foff.p, nr, NF, soff.p, seg.p, cols.p,
+                                            ncol.p, fanchor.p, min_len, delta, 0, aops.p, apass.p,
+                                            nullptr, nullptr, none);
     SDF_HIP(hipGetLastError());
     DevBuf<uint64_t> woff(NF + 1), opoff(NF + 1);
     scan_u32_to_u64(apass.p, woff.p, NF, st);
@@ -1778,10 +1881,10 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     res.sd.alloc(NSD + 1);
     res.cigar.alloc(NOPS + 1);
     if (NSD) {
-        k_assemble<<<nb(NF, 64), 64, 0, st>>>(ix, dreg.p, an, c, fin, foff.p, nr, nbnd.p, NF,
-                                              soff.p, seg.p, cols.p, ncol.p, min_len, delta, 1,
-                                              aops.p, apass.p, woff.p, opoff.p,
-                                              SdOut{res.sd.p, res.cigar.p});
+        k_assemble<<<(unsigned)NF, 64, 0, st>>>(ix, dreg.p, foff.p, nr, NF, soff.p, seg.p,
+                                                cols.p, ncol.p, fanchor.p, min_len, delta, 1,
+                                                aops.p, apass.p, woff.p, opoff.p,
+                                                SdOut{res.sd.p, res.cigar.p});
         SDF_HIP(hipGetLastError());
     }
     SDF_HIP(hipStreamSynchronize(st));

@@ -1651,6 +1651,10 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     SDF_HIP(hipMemcpyAsync(toff.p, hto.data(), (n + 1) * 8, hipMemcpyHostToDevice, st));
     SDF_HIP(hipMemcpyAsync(qoff.p, hqo.data(), (n + 1) * 8, hipMemcpyHostToDevice, st));
     const uint64_t TT = hto[n], QT = hqo[n];
+    // key bits of a region number: every region number stays below 2^rbits - 1, so
+    // no key of a region has all of its bits set like the sentinel ~0
+    int rbits = 1;
+    while ((1ull << rbits) <= (uint64_t)n) rbits++;
     std::optional<Range> stage;
     stage.emplace("sdf final SDs: seeds");
     // 1. target keys, sorted
@@ -1659,7 +1663,8 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     if (TT) {
         k_t_keys<<<grid_stride(TT), 256, 0, st>>>(ix, dreg.p, nr, toff.p, TT, k, tkey.p, tval.p);
         SDF_HIP(hipGetLastError());
-        radix_sort_u64(tkey.p, tval.p, TT, 64, st);
+        // (region, k-mer): the keys are made in position order, so equal ones keep y ascending
+        radix_sort_u64_bits(tkey.p, tval.p, TT, 20, 42 + rbits, st);
     }
     // samples of the target keys, matches per query position, their
     // offsets, the matches sorted
@@ -1683,7 +1688,8 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
         k_q_emit<<<grid_stride(QT), 256, 0, st>>>(ix, dreg.p, nr, qoff.p, QT, k, tkey.p, TT, smp.p,
                                                   qcnt.p, moff.p, mkey.p, mval.p);
         SDF_HIP(hipGetLastError());
-        radix_sort_u64(mkey.p, mval.p, M, 64, st);
+        // (region, diagonal): the matches are made in x order within a region
+        radix_sort_u64_bits(mkey.p, mval.p, M, 20, 41 + rbits, st);
     }
     tkey.reset();
     tval.reset();
@@ -1710,8 +1716,8 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     k_order_keys<<<nb(A), 256, 0, st>>>(an, A, 0, kxy.p, byxy.p);
     k_order_keys<<<nb(A), 256, 0, st>>>(an, A, 1, kend.p, byend.p);
     SDF_HIP(hipGetLastError());
-    radix_sort_u64(kxy.p, byxy.p, A, 64, st);
-    radix_sort_u64(kend.p, byend.p, A, 64, st);
+    radix_sort_u64(kxy.p, byxy.p, A, 42 + rbits, st);
+    radix_sort_u64(kend.p, byend.p, A, 42 + rbits, st);
     DevBuf<uint32_t> bnd(n + 1);
     k_region_bounds<<<nb(n + 1), 256, 0, st>>>(kxy.p, A, 42, nr, bnd.p);
     SDF_HIP(hipGetLastError());
@@ -1748,7 +1754,7 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     radix_sort_u64(kbuf.p, perm.p, A, 20, st);
     k_score_keys<<<nb(A), 256, 0, st>>>(an, A, t1, 1, kbuf.p, byscore.p, perm.p);
     SDF_HIP(hipGetLastError());
-    radix_sort_u64(kbuf.p, byscore.p, A, 64, st);
+    radix_sort_u64(kbuf.p, byscore.p, A, 41 + rbits, st);
     DevBuf<uint8_t> used(A + 4);
     fill_u32(reinterpret_cast<uint32_t *>(used.p), 0u, (A + 3) / 4, st);
     DevBuf<uint32_t> tmp(A), mem1(A), cst(A), cend(A), ccount(n), cx(A), cy(A), cex(A), cey(A),
@@ -1767,7 +1773,7 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     k_slot_regions<<<nb(A), 256, 0, st>>>(an, byxy.p, A, rslot.p);
     k_node_keys<<<nb(A), 256, 0, st>>>(bnd.p, rslot.p, A, c, kbuf.p, nodes.p);
     SDF_HIP(hipGetLastError());
-    radix_sort_u64(kbuf.p, nodes.p, A, 64, st);
+    radix_sort_u64(kbuf.p, nodes.p, A, 42 + rbits, st);
     k_region_bounds<<<nb(n + 1), 256, 0, st>>>(kbuf.p, A, 42, nr, nbnd.p);
     SDF_HIP(hipGetLastError());
     // 4. tier 2: nodes by end, scores, extraction order, final chains
@@ -1779,7 +1785,7 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     k_node_keys2<<<nb(A), 256, 0, st>>>(nodes.p, A, nbnd.p + nr, rslot.p, c, s2.p, 0, nullptr,
                                         ekey.p, nodes_e.p);
     SDF_HIP(hipGetLastError());
-    radix_sort_u64(ekey.p, nodes_e.p, A, 64, st);
+    radix_sort_u64(ekey.p, nodes_e.p, A, 42 + rbits, st);
     {
         DevBuf<uint32_t> pos_e(A);
         DevBuf<uint2> ecxy(A);
@@ -1807,7 +1813,7 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     k_node_keys2<<<nb(A), 256, 0, st>>>(nodes.p, A, nbnd.p + nr, rslot.p, c, s2.p, 2, perm.p,
                                         kbuf.p, order.p);
     SDF_HIP(hipGetLastError());
-    radix_sort_u64(kbuf.p, order.p, A, 64, st);
+    radix_sort_u64(kbuf.p, order.p, A, 42 + rbits, st);
     fill_u32(reinterpret_cast<uint32_t *>(used.p), 0u, (A + 3) / 4, st);
     Final fin{fmem.p, fst.p, fend.p, fcount.p};
     k_extract2<<<nr, 64, std::max<uint32_t>(4, xcap / 8), st>>>(nbnd.p, bnd.p, nr, order.p, p2.p,

@@ -574,7 +574,8 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const K *kin, const u
 }
 
 template <class K>
-static void radix_impl(K *keys, uint32_t *vals, DevCount cnt, int bits, hipStream_t st) {
+static void radix_impl(K *keys, uint32_t *vals, DevCount cnt, int bits, hipStream_t st,
+                       int lo = 0) {
     const uint64_t n = cnt.bound;  // grid and buffer sizes; the kernels stop at cnt.get()
     if (n <= 1 || bits <= 0) return;
     uint64_t nb64 = (n + RS_TILE - 1) / RS_TILE;
@@ -588,7 +589,7 @@ static void radix_impl(K *keys, uint32_t *vals, DevCount cnt, int bits, hipStrea
     uint32_t *va = vals, *vb = v2.p;
     int passes = (bits + 7) / 8;
     for (int p = 0; p < passes; p++) {
-        int shift = 8 * p;
+        int shift = lo + 8 * p;
         k_rs_hist<K><<<nb, RS_THREADS, 0, st>>>(ka, cnt, shift, hist.p, nb);
         SDF_HIP(hipGetLastError());
         scan_u32_to_u64(hist.p, hoff.p, (uint64_t)RS_BINS * nb, st);
@@ -614,6 +615,10 @@ void radix_sort_u32(uint32_t *keys, uint32_t *vals, uint64_t n, int bits, hipStr
 }
 void radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t n, int bits, hipStream_t st) {
     radix_impl<uint64_t>(keys, vals, DevCount{nullptr, n}, bits, st);
+}
+void radix_sort_u64_bits(uint64_t *keys, uint32_t *vals, uint64_t n, int lo, int hi,
+                         hipStream_t st) {
+    radix_impl<uint64_t>(keys, vals, DevCount{nullptr, n}, hi - lo, st, lo);
 }
 
 }  // namespace sdf

@@ -198,6 +198,9 @@ void scan_u64(const uint64_t *in, uint64_t *out, uint64_t n, hipStream_t st);
 // Stable LSD radix sort of (key, value) pairs on key bits [0, bits).
 void radix_sort_u32(uint32_t *keys, uint32_t *vals, uint64_t n, int bits, hipStream_t st);
 void radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t n, int bits, hipStream_t st);
+// The same on key bits [lo, hi) only (lower bits keep their input order).
+void radix_sort_u64_bits(uint64_t *keys, uint32_t *vals, uint64_t n, int lo, int hi,
+                         hipStream_t st);
 // The same for a device count: grids and buffers by n.bound, keys [0, n.get())
 // sorted (entries past it are moved about but not ordered).
 void radix_sort_u32(uint32_t *keys, uint32_t *vals, DevCount n, int bits, hipStream_t st);

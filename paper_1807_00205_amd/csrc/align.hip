@@ -1004,6 +1004,14 @@ __device__ __forceinline__ uint64_t seg_cells(uint32_t dx, uint32_t dy) {
     return c <= DP_CELLS ? c : 0;  // 0: the diagonal stand-in, no table
 }
 
+// Traceback tables hold one byte per cell, row by row, each row padded to a
+// multiple of 8 bytes (tables start at multiples of 8 too), so that the
+// thread aligner writes eight cells of a row with one 8-byte store.
+__device__ __forceinline__ uint32_t tb_pitch(uint32_t dy) { return (dy + 1 + 7) & ~7u; }
+__device__ __forceinline__ uint64_t seg_tb_bytes(uint32_t dx, uint32_t dy) {
+    return seg_cells(dx, dy) ? (uint64_t)(dx + 1) * tb_pitch(dy) : 0;
+}
+
 // 5a. per final chain: stretches, traceback bytes, column operations
 __global__ void k_seg_count(const Anchors an, const Chains1 c, const Final fin,
                             const uint64_t *foff, uint32_t nr, const uint32_t *nbnd, uint64_t nf,
@@ -1021,7 +1029,7 @@ __global__ void k_seg_count(const Anchors an, const Chains1 c, const Final fin,
             link_trim(px, py, an.x[a], an.y[a], an.len[a], o, dx, dy);
             ns++;
             const uint64_t cc = seg_cells(dx, dy);
-            cells += cc;
+            cells += seg_tb_bytes(dx, dy);
             ops += (uint64_t)dx + dy;
             rows += cc ? 3ull * (dy + 1) : 0;
         }
@@ -1063,7 +1071,7 @@ __global__ void k_seg_emit(const Anchors an, const Chains1 c, const Final fin,
             x.rows = rows;
             seg[s++] = x;
             const uint64_t cc = seg_cells(x.dx, x.dy);
-            cells += cc;
+            cells += seg_tb_bytes(x.dx, x.dy);
             ops += (uint64_t)x.dx + x.dy;
             rows += cc ? 3ull * (x.dy + 1) : 0;
         } else {  // the chain's first anchor, kept whole
@@ -1100,13 +1108,42 @@ __device__ __forceinline__ uint32_t seg_mode(uint32_t dx, uint32_t dy, uint32_t 
 // (neither an N), so that the traceback reads no bases.
 constexpr uint8_t TB_EQ = 64;
 
-// The traceback of a filled stretch from its end state st (0 M, 1 I, 2 D):
-// column operations written to out in order; returns their number.
-__device__ uint32_t trace_back(const Seg &S, const uint8_t *T, uint32_t W, int st,
+// One cell of the three-state recurrence (match 2, mismatch -4, a gap of L
+// bases -(4 + 2 L); ties to M, then I, then D) from its diagonal (p*), upper
+// (u*) and left (l*) neighbours: M, I, D and the traceback byte.  Cells
+// outside the table, and states that cannot be reached, hold values near
+// NEG: they stay far below every reachable score (a step lowers them by 6
+// at most, a stretch has fewer than 2^21 steps), so they never win against
+// a reachable state and need no test of their own; the traceback never
+// enters them.
+__device__ __forceinline__ uint8_t cell(int pm, int pi, int pd, int um, int ui, int ud, int lm,
+                                        int li, int ld, bool eq, int &m, int &ii, int &dd) {
+    constexpr int GO = 4, GE = 2, MA = 2, MI = -4;
+    int best = pm;
+    uint32_t sm = 0;
+    if (pi > best) { best = pi; sm = 1; }
+    if (pd > best) { best = pd; sm = 2; }
+    m = best + (eq ? MA : MI);
+    ii = um - GO - GE;
+    uint32_t si = 0;
+    if (ui - GE > ii) { ii = ui - GE; si = 1; }
+    if (ud - GO - GE > ii) { ii = ud - GO - GE; si = 2; }
+    dd = lm - GO - GE;
+    uint32_t sd = 0;
+    if (li - GO - GE > dd) { dd = li - GO - GE; sd = 1; }
+    if (ld - GE > dd) { dd = ld - GE; sd = 2; }
+    return (uint8_t)(sm | (si << 2) | (sd << 4) | (eq ? TB_EQ : 0));
+}
+
+
+// The traceback of a filled stretch (table rows P bytes apart) from its end
+// state st (0 M, 1 I, 2 D): column operations written to out in order;
+// returns their number.
+__device__ uint32_t trace_back(const Seg &S, const uint8_t *T, uint32_t P, int st,
                                uint8_t *out) {
     uint32_t i = S.dx, j = S.dy, n = 0;
     while (i > 0 || j > 0) {
-        const uint8_t code = T[(uint64_t)i * W + j];
+        const uint8_t code = T[(uint64_t)i * P + j];
         if (st == 0) {
             out[n++] = (code & TB_EQ) ? OP_EQ : OP_X;
             st = code & 3;
@@ -1131,20 +1168,43 @@ __device__ uint32_t trace_back(const Seg &S, const uint8_t *T, uint32_t W, int s
     return n;
 }
 
+// The stretches by the aligner that takes them (a stable sort on the mode:
+// the thread aligner's first, in chain order, whose neighbours share cache
+// lines; then the wave aligner's, LDS rows before global ones), so that
+// each aligner is launched on its own stretches only.  counts[m]: stretches
+// of mode m.  (Ordering the thread aligner's stretches by size, for alike
+// work per wave, was slower: it scatters the lanes' memory.)
+__global__ void k_seg_order(const Seg *seg, uint64_t ns, uint32_t wave_cells, uint32_t wave_cols,
+                            uint32_t *key, uint32_t *val, unsigned long long *counts) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t mode = 3;
+    if (t < ns) {
+        const Seg S = seg[t];
+        mode = seg_mode(S.dx, S.dy, wave_cells, wave_cols);
+        key[t] = mode;
+        val[t] = (uint32_t)t;
+    }
+    for (uint32_t m = 0; m < 3; m++) {  // one atomic per wave and mode
+        const uint64_t b = __ballot(mode == m);
+        if (b && (threadIdx.x % 64) == (uint32_t)__builtin_ctzll(b))
+            atomicAdd(counts + m, (unsigned long long)__popcll(b));
+    }
+}
+
 // 5b. one thread per stretch: the three-state affine recurrence (match 2,
 // mismatch -4, a gap of L bases -(4 + 2 L)) over two rolling rows, one
 // traceback byte per cell (bits 0-1: best state before a diagonal step,
 // bits 2-3: source of the query-gap state, bits 4-5: of the target-gap
 // state; ties to M, then I, then D), then the columns written backwards
 // (op codes, one byte each, dx + dy of them at most).
-__global__ void k_align_segs(const IndexView ix, const ARegion *reg, const Seg *seg, uint64_t ns,
-                             uint8_t *tb, int *rows, uint8_t *cols, uint32_t *ncol,
-                             uint32_t wave_cells, uint32_t wave_cols) {
-    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ns) return;
+__global__ void k_align_segs(const IndexView ix, const ARegion *reg, const Seg *seg,
+                             const uint32_t *order, uint64_t ns, uint8_t *tb, int *rows,
+                             uint8_t *cols, uint32_t *ncol) {
+    const uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= ns) return;
+    const uint32_t t = order[u];  // the stretch (k_seg_order's thread-aligner part)
     const Seg S = seg[t];
     const uint32_t dx = S.dx, dy = S.dy;
-    if (seg_mode(dx, dy, wave_cells, wave_cols) != SEG_THREAD) return;  // k_align_wave's
     const ARegion R = reg[S.region];
     uint8_t *out = cols + S.ops;
     if (!seg_cells(dx, dy)) {  // the diagonal stand-in
@@ -1168,11 +1228,11 @@ __global__ void k_align_segs(const IndexView ix, const ARegion *reg, const Seg *
         ncol[t] = n;
         return;
     }
-    const uint32_t W = dy + 1;
+    const uint32_t W = dy + 1, P = tb_pitch(dy);
     uint8_t *T = tb + S.cells;
     int *Mr = rows + S.rows, *Ir = Mr + W, *Dr = Ir + W;  // row i - 1, then row i in place
-    const int GO = 4, GE = 2, MA = 2, MI = -4;
-    constexpr uint32_t CH = 8;  // cells whose loads are issued before any of them is written
+    constexpr uint32_t CH = 8;  // cells whose loads are issued before any of them is written,
+                                // and whose traceback bytes go out in one 8-byte store
     for (uint32_t i = 0; i <= dx; i++) {
         const uint32_t qa = i ? base_at(ix, R.q0 + S.qx + i - 1) : 4u;
         int pm = NEG, pi = NEG, pd = NEG;  // row i - 1, column j - 1
@@ -1189,45 +1249,15 @@ __global__ void k_align_segs(const IndexView ix, const ARegion *reg, const Seg *
                 ud[q] = in && i ? Dr[j] : NEG;
                 tbv[q] = in && i && j ? t_base(ix, R, S.ty + j - 1) : 4u;
             }
+            uint64_t codes = 0;  // the chunk's traceback bytes (0 past the row)
 #pragma unroll
             for (uint32_t q = 0; q < CH; q++) {
                 const uint32_t j = j0 + q;
                 if (j > dy) break;
-                int m = NEG, ii = NEG, dd = NEG;
-                uint8_t code = 0;
-                if (i == 0 && j == 0) {
-                    m = 0;
-                } else {
-                    if (i > 0 && j > 0) {
-                        int best = pm;
-                        uint8_t st = 0;
-                        if (pi > best) { best = pi; st = 1; }
-                        if (pd > best) { best = pd; st = 2; }
-                        const bool eq = qa < 4 && qa == tbv[q];
-                        if (best > NEG / 2) m = best + (eq ? MA : MI);
-                        code |= st | (eq ? TB_EQ : 0);
-                    }
-                    if (i > 0) {
-                        const int a = um[q] > NEG / 2 ? um[q] - GO - GE : NEG;
-                        const int b = ui[q] > NEG / 2 ? ui[q] - GE : NEG;
-                        const int d = ud[q] > NEG / 2 ? ud[q] - GO - GE : NEG;
-                        ii = a;
-                        uint8_t st = 0;
-                        if (b > ii) { ii = b; st = 1; }
-                        if (d > ii) { ii = d; st = 2; }
-                        code |= st << 2;
-                    }
-                    if (j > 0) {
-                        const int a = lm > NEG / 2 ? lm - GO - GE : NEG;
-                        const int b = li > NEG / 2 ? li - GO - GE : NEG;
-                        const int d = ld > NEG / 2 ? ld - GE : NEG;
-                        dd = a;
-                        uint8_t st = 0;
-                        if (b > dd) { dd = b; st = 1; }
-                        if (d > dd) { dd = d; st = 2; }
-                        code |= st << 4;
-                    }
-                }
+                int m, ii, dd;
+                const uint8_t code = cell(pm, pi, pd, um[q], ui[q], ud[q], lm, li, ld,
+                                          qa < 4 && qa == tbv[q], m, ii, dd);
+                if (i == 0 && j == 0) m = 0;
                 pm = um[q];
                 pi = ui[q];
                 pd = ud[q];
@@ -1237,8 +1267,9 @@ __global__ void k_align_segs(const IndexView ix, const ARegion *reg, const Seg *
                 Mr[j] = m;
                 Ir[j] = ii;
                 Dr[j] = dd;
-                T[(uint64_t)i * W + j] = code;
+                codes |= (uint64_t)code << (8 * q);
             }
+            *reinterpret_cast<uint64_t *>(T + (uint64_t)i * P + j0) = codes;
         }
     }
     // end state: ties M, then I, then D
@@ -1248,7 +1279,7 @@ __global__ void k_align_segs(const IndexView ix, const ARegion *reg, const Seg *
         if (Ir[dy] > best) { best = Ir[dy]; st = 1; }
         if (Dr[dy] > best) { best = Dr[dy]; st = 2; }
     }
-    ncol[t] = trace_back(S, T, W, st, out);
+    ncol[t] = trace_back(S, T, P, st, out);
 }
 
 // 5c. one 64-lane workgroup per large stretch, the same recurrence and tie
@@ -1261,18 +1292,16 @@ __global__ void k_align_segs(const IndexView ix, const ARegion *reg, const Seg *
 // wider stretches).  Lane 0 then walks the traceback.
 template <bool GLOBAL>
 __global__ __launch_bounds__(64) void k_align_wave(const IndexView ix, const ARegion *reg,
-                                                   const Seg *seg, uint64_t ns, uint8_t *tb,
-                                                   int *rows, uint8_t *cols, uint32_t *ncol,
-                                                   uint32_t wave_cells, uint32_t wave_cols) {
+                                                   const Seg *seg, const uint32_t *order,
+                                                   uint64_t ns, uint8_t *tb, int *rows,
+                                                   uint8_t *cols, uint32_t *ncol) {
     __shared__ int LM[GLOBAL ? 1 : WAVE_COLS], LI[GLOBAL ? 1 : WAVE_COLS],
         LD[GLOBAL ? 1 : WAVE_COLS];     // row i - 1, per column
     __shared__ uint8_t TBc[WAVE_COLS];  // target base j - 1 of the first WAVE_COLS columns
-    const uint64_t t = blockIdx.x;
-    if (t >= ns) return;
+    if (blockIdx.x >= ns) return;
+    const uint32_t t = order[blockIdx.x];  // the stretch (k_seg_order's part for this mode)
     const Seg S = seg[t];
     const uint32_t dx = S.dx, dy = S.dy;
-    if (seg_mode(dx, dy, wave_cells, wave_cols) != (GLOBAL ? SEG_WAVE_GLOBAL : SEG_WAVE_LDS))
-        return;  // uniform over the workgroup
     const ARegion R = reg[S.region];
     const uint32_t W = dy + 1, lane = threadIdx.x;
     int *PM = GLOBAL ? rows + S.rows : LM;
@@ -1281,7 +1310,7 @@ __global__ __launch_bounds__(64) void k_align_wave(const IndexView ix, const ARe
     const uint32_t SW = (W + 63) / 64;
     const uint32_t c0 = min(W, lane * SW), c1 = min(W, c0 + SW);
     uint8_t *T = tb + S.cells;
-    const int GO = 4, GE = 2, MA = 2, MI = -4;
+    const uint32_t P = tb_pitch(dy);
     for (uint32_t j = lane; j < W && j < WAVE_COLS; j += 64)
         TBc[j] = j ? (uint8_t)t_base(ix, R, S.ty + j - 1) : (uint8_t)4;
     __syncthreads();
@@ -1289,53 +1318,24 @@ __global__ __launch_bounds__(64) void k_align_wave(const IndexView ix, const ARe
     int gM = NEG, gI = NEG, gD = NEG;  // (row i - 1, column c0 - 1), received a step earlier
     for (uint32_t step = 0; step < dx + 64; step++) {
         // (row i, column c0 - 1): lane l - 1 finished row i in the step before
-        const int inM = __shfl_up(oM, 1), inI = __shfl_up(oI, 1), inD = __shfl_up(oD, 1);
+        // (column -1 does not exist: lane 0 takes the unreachable value)
+        int inM = __shfl_up(oM, 1), inI = __shfl_up(oI, 1), inD = __shfl_up(oD, 1);
+        if (lane == 0) inM = inI = inD = NEG;
         const int64_t irow = (int64_t)step - (int64_t)lane;
         if (irow >= 0 && irow <= (int64_t)dx && c0 < c1) {
             const uint32_t i = (uint32_t)irow;
             const uint32_t qa = i ? base_at(ix, R.q0 + S.qx + i - 1) : 4u;
             int pm = gM, pi = gI, pd = gD;     // row i - 1, column j - 1
             int lm = inM, li = inI, ld = inD;  // row i, column j - 1
-            uint8_t *trow = T + (uint64_t)i * W;
+            uint8_t *trow = T + (uint64_t)i * P;
             for (uint32_t j = c0; j < c1; j++) {
                 const int um = i ? PM[j] : NEG, ui = i ? PI[j] : NEG, ud = i ? PD[j] : NEG;
-                int m = NEG, ii = NEG, dd = NEG;
-                uint8_t code = 0;
-                if (i == 0 && j == 0) {
-                    m = 0;
-                } else {
-                    if (i > 0 && j > 0) {
-                        int best = pm;
-                        uint8_t st = 0;
-                        if (pi > best) { best = pi; st = 1; }
-                        if (pd > best) { best = pd; st = 2; }
-                        const uint32_t tbase =
-                            j < WAVE_COLS ? (uint32_t)TBc[j] : t_base(ix, R, S.ty + j - 1);
-                        const bool eq = qa < 4 && qa == tbase;
-                        if (best > NEG / 2) m = best + (eq ? MA : MI);
-                        code |= st | (eq ? TB_EQ : 0);
-                    }
-                    if (i > 0) {
-                        const int a = um > NEG / 2 ? um - GO - GE : NEG;
-                        const int b = ui > NEG / 2 ? ui - GE : NEG;
-                        const int d = ud > NEG / 2 ? ud - GO - GE : NEG;
-                        ii = a;
-                        uint8_t st = 0;
-                        if (b > ii) { ii = b; st = 1; }
-                        if (d > ii) { ii = d; st = 2; }
-                        code |= st << 2;
-                    }
-                    if (j > 0) {
-                        const int a = lm > NEG / 2 ? lm - GO - GE : NEG;
-                        const int b = li > NEG / 2 ? li - GO - GE : NEG;
-                        const int d = ld > NEG / 2 ? ld - GE : NEG;
-                        dd = a;
-                        uint8_t st = 0;
-                        if (b > dd) { dd = b; st = 1; }
-                        if (d > dd) { dd = d; st = 2; }
-                        code |= st << 4;
-                    }
-                }
+                int m, ii, dd;
+                const uint32_t tbase =
+                    j < WAVE_COLS ? (uint32_t)TBc[j] : t_base(ix, R, S.ty + j - 1);
+                const uint8_t code = cell(pm, pi, pd, um, ui, ud, lm, li, ld,
+                                          i > 0 && j > 0 && qa < 4 && qa == tbase, m, ii, dd);
+                if (i == 0 && j == 0) m = 0;
                 pm = um;
                 pi = ui;
                 pd = ud;
@@ -1360,7 +1360,7 @@ __global__ __launch_bounds__(64) void k_align_wave(const IndexView ix, const ARe
         int st = 0, best = PM[dy];
         if (PI[dy] > best) { best = PI[dy]; st = 1; }
         if (PD[dy] > best) { best = PD[dy]; st = 2; }
-        ncol[t] = trace_back(S, T, W, st, cols + S.ops);
+        ncol[t] = trace_back(S, T, P, st, cols + S.ops);
     }
 }
 
@@ -1855,15 +1855,33 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     if (NS) {
         const uint32_t wave_cells = knob(tuning().align_wave_cells, 1u << 14);
         const uint32_t wave_cols = min(knob(tuning().align_wave_lds_cols, WAVE_COLS), WAVE_COLS);
-        k_align_segs<<<nb(NS, 64), 64, 0, st>>>(ix, dreg.p, seg.p, NS, tb.p, rows.p, cols.p, ncol.p,
-                                                wave_cells, wave_cols);
+        DevBuf<uint32_t> okey(NS), order(NS);
+        DevBuf<unsigned long long> mcount(3);
+        fill_u32(reinterpret_cast<uint32_t *>(mcount.p), 0u, 6, st);
+        k_seg_order<<<nb(NS, 256), 256, 0, st>>>(seg.p, NS, wave_cells, wave_cols, okey.p, order.p,
+                                                 mcount.p);
         SDF_HIP(hipGetLastError());
+        radix_sort_u32(okey.p, order.p, NS, 2, st);
+        unsigned long long mc[3] = {0, 0, 0};
+        {
+            Readback rb(st);
+            rb.add(mc, mcount.p, sizeof(mc));
+            rb.wait();
+        }
+        if (mc[SEG_THREAD])
+            k_align_segs<<<nb(mc[SEG_THREAD], 64), 64, 0, st>>>(ix, dreg.p, seg.p, order.p,
+                                                               mc[SEG_THREAD], tb.p, rows.p,
+                                                               cols.p, ncol.p);
         SDF_HIP(hipGetLastError());
-        k_align_wave<false><<<(unsigned)NS, 64, 0, st>>>(ix, dreg.p, seg.p, NS, tb.p, rows.p,
-                                                         cols.p, ncol.p, wave_cells, wave_cols);
+        if (mc[SEG_WAVE_LDS])
+            k_align_wave<false><<<(unsigned)mc[SEG_WAVE_LDS], 64, 0, st>>>(
+                ix, dreg.p, seg.p, order.p + mc[SEG_THREAD], mc[SEG_WAVE_LDS], tb.p, rows.p, cols.p,
+                ncol.p);
         SDF_HIP(hipGetLastError());
-        k_align_wave<true><<<(unsigned)NS, 64, 0, st>>>(ix, dreg.p, seg.p, NS, tb.p, rows.p,
-                                                        cols.p, ncol.p, wave_cells, wave_cols);
+        if (mc[SEG_WAVE_GLOBAL])
+            k_align_wave<true><<<(unsigned)mc[SEG_WAVE_GLOBAL], 64, 0, st>>>(
+                ix, dreg.p, seg.p, order.p + mc[SEG_THREAD] + mc[SEG_WAVE_LDS],
+                mc[SEG_WAVE_GLOBAL], tb.p, rows.p, cols.p, ncol.p);
         SDF_HIP(hipGetLastError());
     }
     // 6. records and CIGAR

@@ -1112,10 +1112,11 @@ constexpr uint8_t TB_EQ = 64;
 // bases -(4 + 2 L); ties to M, then I, then D) from its diagonal (p*), upper
 // (u*) and left (l*) neighbours: M, I, D and the traceback byte.  Cells
 // outside the table, and states that cannot be reached, hold values near
-// NEG: they stay far below every reachable score (a step lowers them by 6
-// at most, a stretch has fewer than 2^21 steps), so they never win against
-// a reachable state and need no test of their own; the traceback never
-// enters them.
+// NEG: they stay far below every reachable score (a step moves a value by 6
+// at most and a stretch has fewer than 2^21 steps, so they stay within
+// 1.3e7 of NEG = -1e9, and reachable scores above -1.3e7), so they never win
+// against a reachable state and need no test of their own; the traceback
+// never enters them.
 __device__ __forceinline__ uint8_t cell(int pm, int pi, int pd, int um, int ui, int ud, int lm,
                                         int li, int ld, bool eq, int &m, int &ii, int &dd) {
     constexpr int GO = 4, GE = 2, MA = 2, MI = -4;

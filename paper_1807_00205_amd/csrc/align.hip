@@ -41,6 +41,7 @@ constexpr uint32_t MAXOCC = 32;
 constexpr uint32_t TIER2_GAP = 10000;
 constexpr uint32_t T2_BLOCKS = 4096;  // tier-2 end-order blocks per region with LDS bounds
 constexpr uint32_t T2_WAVES = 8;      // waves of a tier-2 workgroup
+constexpr uint32_t T1_WAVES = 4;      // waves of a tier-1 workgroup
 constexpr uint32_t X_CAP = 1u << 19;  // ids per region with used flags in LDS (64 KiB of bits)
 constexpr uint64_t DP_CELLS = 1ull << 20;
 enum : uint32_t { OP_EQ = 7, OP_X = 8, OP_I = 1, OP_D = 2 };
@@ -299,23 +300,25 @@ __device__ __forceinline__ void st_score(int64_t *p, int64_t v) {
 }
 
 // 3a. tier-1 scores (the longest chains: a link costs the indel |dx - dy|
-// it implies plus its cut, gaps at most G1), one 64-lane workgroup per
-// region.  Anchors are scored 64 at a time in (x, y) order, anchor k of a
-// batch in lane k:
+// it implies plus its cut, gaps at most G1), one workgroup of T1_WAVES waves
+// per region.  Anchors are scored 64 at a time in (x, y) order, anchor k of
+// a batch in lane k of every wave:
 //  1. predecessors scored before the batch: the anchors ending in [x0 - G1,
 //     the last window end of the batch) (x0 its first start), read in
-//     blocks of 64 entries of the end order, four blocks at a time, one
-//     entry per lane; every lane tests every entry against its own anchor.
+//     blocks of 64 entries of the end order, dealt round robin to the waves
+//     and read four at a time, one entry per lane; every lane tests every
+//     entry against its own anchor, and the waves' best predecessors meet in
+//     LDS.
 //     LDS holds the last end x of each of the region's first nblk blocks, so
 //     the window's first block is found without memory reads;
-//  2. predecessors inside the batch: anchor k's score is final once anchors
-//     0..k-1 are done, so k runs from first to last and every later lane
-//     tests anchor k as its predecessor.
+//  2. predecessors inside the batch (wave 0): anchor k's score is final once
+//     anchors 0..k-1 are done, so k runs from first to last and every later
+//     lane tests anchor k as its predecessor.
 // Only positive link values are kept and the choice among equal ones does
 // not depend on the order candidates are met, so this equals scoring the
 // anchors one at a time against every earlier anchor.  Candidates' lengths,
 // scores and anchor ids come from arrays kept in end order.
-__global__ __launch_bounds__(64) void k_tier1(const uint64_t *xykey, const uint32_t *byxy,
+__global__ __launch_bounds__(64 * T1_WAVES) void k_tier1(const uint64_t *xykey, const uint32_t *byxy,
                                               const uint32_t *alen, const uint64_t *endkey,
                                               const uint32_t *byend, const uint32_t *elen,
                                               const uint32_t *pos_e, const uint32_t *bnd,
@@ -323,9 +326,10 @@ __global__ __launch_bounds__(64) void k_tier1(const uint64_t *xykey, const uint3
                                               int64_t *score_e, uint32_t nblk) {
     extern __shared__ uint32_t t1_lds[];
     uint32_t *const exhi = t1_lds;  // [nblk]
+    __shared__ Best2 part[T1_WAVES][64];  // per wave and anchor
     const uint32_t r = blockIdx.x;
     if (r >= nr) return;
-    const uint32_t lane = threadIdx.x;
+    const uint32_t lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     const uint32_t lo = bnd[r], hi = bnd[r + 1];
     const uint32_t nbr = (hi - lo + 63) / 64;  // blocks of the region's end order
     const uint32_t nbl = min(nbr, nblk);        // blocks with their last end in LDS
@@ -333,7 +337,7 @@ __global__ __launch_bounds__(64) void k_tier1(const uint64_t *xykey, const uint3
         if (j < nbl) return exhi[j];
         return (uint32_t)(endkey[min(lo + 64 * j + 63, hi - 1)] >> 21) & 0x1FFFFFu;
     };
-    for (uint32_t j = lane; j < nbl; j += 64)
+    for (uint32_t j = threadIdx.x; j < nbl; j += 64 * T1_WAVES)
         exhi[j] = (uint32_t)(endkey[min(lo + 64 * j + 63, hi - 1)] >> 21) & 0x1FFFFFu;
     __syncthreads();
     const uint64_t rk = (uint64_t)r << 42;
@@ -383,12 +387,16 @@ __global__ __launch_bounds__(64) void k_tier1(const uint64_t *xykey, const uint3
                 }
             }
         };
+        uint32_t dealt = 0;  // blocks met so far (dealt round robin to the waves)
         for (uint32_t j0 = jlo; j0 < nbr; j0 += 64) {
             const uint32_t j = j0 + lane;
             // block j starts no earlier than block j - 1 ends
             const bool beyond = j >= nbr || (j > jlo && block_end(j - 1) >= xend_max);
             const uint64_t mbey = __ballot(beyond);
-            uint64_t mneed = mbey ? (mbey & (0ull - mbey)) - 1 : ~0ull;
+            const uint64_t mall = mbey ? (mbey & (0ull - mbey)) - 1 : ~0ull;
+            uint64_t mneed = 0;  // this wave's share
+            for (uint64_t m = mall; m; m &= m - 1, dealt++)
+                if (dealt % T1_WAVES == wave) mneed |= m & (0ull - m);
             while (mneed) {
                 uint32_t jb[4];
 #pragma unroll
@@ -414,26 +422,34 @@ __global__ __launch_bounds__(64) void k_tier1(const uint64_t *xykey, const uint3
             }
             if (mbey) break;
         }
-        // 2. predecessors inside the batch
-        for (uint32_t k = 0; k + 1 < cnt; k++) {
-            const int32_t sk = (int32_t)lane_u32((uint32_t)((int32_t)len + B.v), k);
-            const uint32_t xk = lane_u32(x, k), yk = lane_u32(y, k), lk = lane_u32(len, k);
-            const uint32_t exk = xk + lk, eyk = yk + lk;
-            if (lane > k && mine && exk < xend && exk + G1 >= x) {
-                uint32_t o, dx, dy;
-                if (link_trim(exk, eyk, x, y, len, o, dx, dy) && (dx > dy ? dx : dy) <= G1) {
-                    const int32_t val = sk - (int32_t)(absdiff(dx, dy) + o);
-                    if (better2(val, xk, yk, B)) B = Best2{val, xk, yk, lane_u32(a, k)};
+        part[wave][lane] = B;
+        __syncthreads();
+        if (wave == 0) {
+            for (uint32_t q = 1; q < T1_WAVES; q++) {
+                const Best2 o = part[q][lane];
+                if (better2(o.v, o.x, o.y, B)) B = o;
+            }
+            // 2. predecessors inside the batch
+            for (uint32_t k = 0; k + 1 < cnt; k++) {
+                const int32_t sk = (int32_t)lane_u32((uint32_t)((int32_t)len + B.v), k);
+                const uint32_t xk = lane_u32(x, k), yk = lane_u32(y, k), lk = lane_u32(len, k);
+                const uint32_t exk = xk + lk, eyk = yk + lk;
+                if (lane > k && mine && exk < xend && exk + G1 >= x) {
+                    uint32_t o, dx, dy;
+                    if (link_trim(exk, eyk, x, y, len, o, dx, dy) && (dx > dy ? dx : dy) <= G1) {
+                        const int32_t val = sk - (int32_t)(absdiff(dx, dy) + o);
+                        if (better2(val, xk, yk, B)) B = Best2{val, xk, yk, lane_u32(a, k)};
+                    }
                 }
             }
+            if (mine) {
+                const int64_t sa = (int64_t)len + B.v;  // scores < 2^21
+                st_score(t1.score + a, sa);
+                st_score(score_e + apos, sa);
+                t1.pred[a] = B.v > 0 ? B.b : NONE32;
+            }
         }
-        if (mine) {
-            const int64_t sa = (int64_t)len + B.v;  // scores < 2^21
-            st_score(t1.score + a, sa);
-            st_score(score_e + apos, sa);
-            t1.pred[a] = B.v > 0 ? B.b : NONE32;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __syncthreads();  // scores seen by every wave
     }
 }
 
@@ -1745,8 +1761,9 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
         const uint32_t nblk =
             std::min<uint32_t>(std::min(knob(tuning().align_lds_blocks, T2_BLOCKS), T2_BLOCKS),
                                (most_anchors + 63) / 64);
-        k_tier1<<<nr, 64, 4 * nblk, st>>>(kxy.p, byxy.p, an.len, kend.p, byend.p, elen.p, pos_e.p,
-                                          bnd.p, nr, G1, t1, s1e.p, nblk);
+        k_tier1<<<nr, 64 * T1_WAVES, 4 * nblk, st>>>(kxy.p, byxy.p, an.len, kend.p, byend.p,
+                                                     elen.p, pos_e.p, bnd.p, nr, G1, t1, s1e.p,
+                                                     nblk);
         SDF_HIP(hipGetLastError());
     }
     // score order: y first (stable), then (region, score descending, x)

@@ -148,10 +148,11 @@ __device__ __forceinline__ bool q_kmer(const IndexView &ix, const ARegion &R, ui
     return true;
 }
 
-// 1b. seed matches per query position (0 for seeds above MAXOCC)
+// 1b. seed matches per query position (0 for seeds above MAXOCC), and where
+// their target keys start (qa, read by k_q_emit)
 __global__ void k_q_count(const IndexView ix, const ARegion *reg, uint32_t nr,
                           const uint64_t *qoff, uint64_t total, uint32_t k, const uint64_t *tkey,
-                          uint64_t ntk, const uint64_t *smp, uint32_t *cnt) {
+                          uint64_t ntk, const uint64_t *smp, uint32_t *cnt, uint64_t *qa) {
     for (uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; f < total;
          f += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t r = region_of(qoff, nr, f);
@@ -165,26 +166,21 @@ __global__ void k_q_count(const IndexView ix, const ARegion *reg, uint32_t nr,
             const uint64_t e = min(ntk, a + MAXOCC + 1);
             const uint64_t b = a + first_at_least(tkey + a, e - a, base + (1ull << 20));
             c = (b - a <= MAXOCC) ? (uint32_t)(b - a) : 0u;
+            if (c) qa[f] = a;
         }
         cnt[f] = c;
     }
 }
 
 // 2a. match keys: region << 41 | (y - x + 2^20) << 20 | x
-__global__ void k_q_emit(const IndexView ix, const ARegion *reg, uint32_t nr, const uint64_t *qoff,
-                         uint64_t total, uint32_t k, const uint64_t *tkey, uint64_t ntk,
-                         const uint64_t *smp, const uint32_t *cnt, const uint64_t *moff,
+__global__ void k_q_emit(uint32_t nr, const uint64_t *qoff, uint64_t total, const uint64_t *tkey,
+                         const uint32_t *cnt, const uint64_t *qa, const uint64_t *moff,
                          uint64_t *mkey, uint32_t *mval) {
     for (uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; f < total;
          f += (uint64_t)gridDim.x * blockDim.x) {
         if (!cnt[f]) continue;
         const uint32_t r = region_of(qoff, nr, f);
-        const ARegion R = reg[r];
-        const uint64_t x = f - qoff[r];
-        uint64_t code;
-        q_kmer(ix, R, x, k, code);
-        const uint64_t base = ((uint64_t)r << 42) | (code << 20);
-        const uint64_t a = first_at_least_s(tkey, ntk, smp, base);
+        const uint64_t x = f - qoff[r], a = qa[f];
         for (uint32_t t = 0; t < cnt[f]; t++) {
             const uint64_t y = tkey[a + t] & 0xFFFFF;
             const uint64_t d = y + (1ull << 20) - x;
@@ -1691,10 +1687,10 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
         SDF_HIP(hipGetLastError());
     }
     DevBuf<uint32_t> qcnt(QT + 1);
-    DevBuf<uint64_t> moff(QT + 1);
+    DevBuf<uint64_t> moff(QT + 1), qa(QT + 1);
     if (QT) {
         k_q_count<<<grid_stride(QT), 256, 0, st>>>(ix, dreg.p, nr, qoff.p, QT, k, tkey.p, TT,
-                                                   smp.p, qcnt.p);
+                                                   smp.p, qcnt.p, qa.p);
         SDF_HIP(hipGetLastError());
     }
     scan_u32_to_u64(qcnt.p, moff.p, QT, st);
@@ -1702,8 +1698,8 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     DevBuf<uint64_t> mkey(M + 1);
     DevBuf<uint32_t> mval(M + 1);
     if (M) {
-        k_q_emit<<<grid_stride(QT), 256, 0, st>>>(ix, dreg.p, nr, qoff.p, QT, k, tkey.p, TT, smp.p,
-                                                  qcnt.p, moff.p, mkey.p, mval.p);
+        k_q_emit<<<grid_stride(QT), 256, 0, st>>>(nr, qoff.p, QT, tkey.p, qcnt.p, qa.p, moff.p,
+                                                  mkey.p, mval.p);
         SDF_HIP(hipGetLastError());
         // (region, diagonal): the matches are made in x order within a region
         radix_sort_u64_bits(mkey.p, mval.p, M, 20, 41 + rbits, st);
@@ -1711,6 +1707,7 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     tkey.reset();
     tval.reset();
     smp.reset();
+    qa.reset();
     // 2. anchors
     stage.emplace("sdf final SDs: anchors");
     DevBuf<uint32_t> flag(M + 1), fpre(M + 1);

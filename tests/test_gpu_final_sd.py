@@ -256,3 +256,29 @@ def test_wave_aligner(oracle_lib, seed, rate, lds_cols):
                          reg["t_end"] + to, reg["strand"].astype(np.uint64)], axis=1)
         _same(got, oracle_lib.sd_align(b, off, rows, 11, 1000, 0.25, pad_frac=sdf.PAD_FRAC),
               "config 1, wave")
+
+
+def test_largest_side_paths_agree():
+    """One region of the largest sides the aligner takes (2^20 - 1 bases
+    each: random sequences with a 20 kbp copy at 10% divergence, about 250k
+    chance anchors): the chaining tiers with the most LDS block bounds and the
+    extraction with its LDS flags give the same records and CIGARs as with
+    every block read from memory and one-thread extraction.  (The oracle's
+    quadratic chaining is too slow at this size; the smaller cases above pin
+    both forms to it.)"""
+    from paper_1807_00205_amd import sdf
+    rng = synth.rng_for(77)
+    L = (1 << 20) - 1
+    q = synth.random_bases(rng, L)
+    t = synth.random_bases(rng, L)
+    cp = synth.mutate(rng, q[500000:520000], 0.10)
+    t[300000:300000 + min(len(cp), 20000)] = cp[:20000]
+    ix = sdf.Index([q, t], 12, 16)
+    reg = np.zeros(1, sdf.REGION_DTYPE)
+    reg[0] = (0, 0, 1, 0, 0, L, 0, L, 0, 0)
+    fast = ix.align_regions(reg, pad_frac=0.0)
+    with sdf.tuning(align_lds_blocks=0, align_lds_ids=0):
+        slow = ix.align_regions(reg, pad_frac=0.0)
+    _same(fast, slow, "largest sides")
+    assert len(fast[0]) >= 1
+    ix.close()

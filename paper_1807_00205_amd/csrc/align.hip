@@ -485,6 +485,16 @@ struct Chains1 {
     uint32_t *flen;                 // length of each node's first anchor
 };
 
+// has_child[p] = 1 for every p that is the kept predecessor of an entry:
+// ids[u] for u < *n (or u itself without ids), the array zeroed beforehand.
+__global__ void k_child_flags(const uint32_t *pred, const uint32_t *ids, uint64_t cap,
+                              const uint32_t *n, uint8_t *has_child) {
+    const uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= cap || (n && u >= *n)) return;
+    const uint32_t p = pred[ids ? ids[u] : (uint32_t)u];
+    if (p != NONE32) has_child[p] = 1;
+}
+
 // 3b. tier-1 chains of a region: anchors in score order; an anchor not yet
 // used starts a chain that follows kept predecessors until a used one (or
 // none); the chain's anchors in x order are its members.  The region owns
@@ -559,8 +569,8 @@ struct UsedBits {
 // reversed) are written by the lanes together.
 __global__ __launch_bounds__(64) void k_extract1(Anchors an, const uint32_t *byscore,
                                                  const uint32_t *bnd, uint32_t nr, const Tier1 t1,
-                                                 uint8_t *used, uint32_t *tmp, Chains1 c,
-                                                 uint32_t cap) {
+                                                 const uint8_t *has_child, uint8_t *used,
+                                                 uint32_t *tmp, Chains1 c, uint32_t cap) {
     extern __shared__ uint32_t x1_bits[];
     const uint32_t r = blockIdx.x;
     if (r >= nr) return;
@@ -577,14 +587,27 @@ __global__ __launch_bounds__(64) void k_extract1(Anchors an, const uint32_t *bys
     for (uint32_t u0 = lo; u0 < hi; u0 += 64) {
         const uint32_t cnt = min(64u, hi - u0);
         uint32_t ma = 0, mp = NONE32, mx = 0, my = 0, ml = 0;
+        bool lone = false;  // no predecessor and no successor: a chain of its own
         if (lane < cnt) {
             ma = byscore[u0 + lane];
             mp = t1.pred[ma];
             mx = an.x[ma];
             my = an.y[ma];
             ml = an.len[ma];
+            lone = mp == NONE32 && !has_child[ma];
         }
+        const uint64_t mlone = __ballot(lone);
+        uint32_t lone_node = 0, lone_pos = 0;  // this lane's, when lone
         for (uint32_t i = 0; i < cnt; i++) {
+            if ((mlone >> i) & 1) {  // no walk reaches it and it reaches none: no flag needed
+                if (lane == i) {
+                    lone_node = nc;
+                    lone_pos = pos;
+                }
+                pos++;
+                nc++;
+                continue;
+            }
             const uint32_t a = lane_u32(ma, i);
             if (U.get(a)) continue;
             uint32_t cur = a, p = lane_u32(mp, i);
@@ -628,6 +651,18 @@ __global__ __launch_bounds__(64) void k_extract1(Anchors an, const uint32_t *bys
             }
             pos += m;
             nc++;
+        }
+        if (lone) {  // the batch's lone anchors, written by their lanes
+            const uint32_t node = lo + lone_node;
+            c.member[lone_pos] = ma;
+            c.start[node] = lone_pos;
+            c.end[node] = lone_pos + 1;
+            c.cx[node] = mx;
+            c.cy[node] = my;
+            c.cex[node] = mx + ml;
+            c.cey[node] = my + ml;
+            c.w[node] = ml;
+            c.flen[node] = ml;
         }
     }
     if (lane == 0) c.count[r] = nc;
@@ -930,8 +965,9 @@ __device__ void extract2_serial(uint32_t r, uint32_t lo, uint32_t hi, const uint
 // LDS (regions of at most cap slots), as for the tier-1 chains.
 __global__ __launch_bounds__(64) void k_extract2(const uint32_t *nbnd, const uint32_t *bnd,
                                                  uint32_t nr, const uint32_t *order,
-                                                 const uint32_t *pred, uint8_t *used,
-                                                 uint32_t *tmp, Final fin, uint32_t cap) {
+                                                 const uint32_t *pred, const uint8_t *has_child,
+                                                 uint8_t *used, uint32_t *tmp, Final fin,
+                                                 uint32_t cap) {
     extern __shared__ uint32_t x2_bits[];
     const uint32_t r = blockIdx.x;
     if (r >= nr) return;
@@ -948,11 +984,24 @@ __global__ __launch_bounds__(64) void k_extract2(const uint32_t *nbnd, const uin
     for (uint32_t u0 = lo; u0 < hi; u0 += 64) {
         const uint32_t cnt = min(64u, hi - u0);
         uint32_t ma = 0, mp = NONE32;
+        bool lone = false;  // no predecessor and no successor: a chain of its own
         if (lane < cnt) {
             ma = order[u0 + lane];
             mp = pred[ma];
+            lone = mp == NONE32 && !has_child[ma];
         }
+        const uint64_t mlone = __ballot(lone);
+        uint32_t lone_f = 0, lone_pos = 0;  // this lane's, when lone
         for (uint32_t i = 0; i < cnt; i++) {
+            if ((mlone >> i) & 1) {
+                if (lane == i) {
+                    lone_f = nf;
+                    lone_pos = pos;
+                }
+                pos++;
+                nf++;
+                continue;
+            }
             const uint32_t a = lane_u32(ma, i);
             if (U.get(a)) continue;
             uint32_t cur = a, p = lane_u32(mp, i), m = 0;
@@ -976,6 +1025,11 @@ __global__ __launch_bounds__(64) void k_extract2(const uint32_t *nbnd, const uin
             }
             pos += m;
             nf++;
+        }
+        if (lone) {  // the batch's lone nodes, written by their lanes
+            fin.member[lone_pos] = ma;
+            fin.start[lo + lone_f] = lone_pos;
+            fin.end[lo + lone_f] = lone_pos + 1;
         }
     }
     if (lane == 0) fin.count[r] = nf;
@@ -1780,8 +1834,11 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     const uint32_t xcap =
         (uint32_t)std::min<uint64_t>(std::min(knob(tuning().align_lds_ids, X_CAP), X_CAP) / 32 * 32,
                                      (most_anchors + 31) / 32 * 32);
+    DevBuf<uint8_t> child(A + 4);  // anchors (then node slots) that are some entry's predecessor
+    fill_u32(reinterpret_cast<uint32_t *>(child.p), 0u, (A + 3) / 4, st);
+    k_child_flags<<<nb(A), 256, 0, st>>>(t1.pred, nullptr, A, nullptr, child.p);
     k_extract1<<<nr, 64, std::max<uint32_t>(4, xcap / 8), st>>>(an, byscore.p, bnd.p, nr, t1,
-                                                                used.p, tmp.p, c, xcap);
+                                                                child.p, used.p, tmp.p, c, xcap);
     SDF_HIP(hipGetLastError());
     // nodes ordered by (region, x, y)
     DevBuf<uint32_t> rslot(A), nodes(A), nbnd(n + 1);
@@ -1831,8 +1888,10 @@ void sd_align(const IndexView &ix, const uint64_t *h_off, const sdf_region *regi
     radix_sort_u64(kbuf.p, order.p, A, 42 + rbits, st);
     fill_u32(reinterpret_cast<uint32_t *>(used.p), 0u, (A + 3) / 4, st);
     Final fin{fmem.p, fst.p, fend.p, fcount.p};
+    fill_u32(reinterpret_cast<uint32_t *>(child.p), 0u, (A + 3) / 4, st);
+    k_child_flags<<<nb(A), 256, 0, st>>>(p2.p, order.p, A, nbnd.p + nr, child.p);
     k_extract2<<<nr, 64, std::max<uint32_t>(4, xcap / 8), st>>>(nbnd.p, bnd.p, nr, order.p, p2.p,
-                                                                used.p, tmp.p, fin, xcap);
+                                                                child.p, used.p, tmp.p, fin, xcap);
     SDF_HIP(hipGetLastError());
     DevBuf<uint64_t> foff(n + 1);
     scan_u32_to_u64(fcount.p, foff.p, n, st);

@@ -8,24 +8,27 @@
 // Device pipeline, all regions of a call at once:
 //   1. every k-mer of every target side T' (the target read reverse-
 //      complemented on strand 1) as a key (region, k-mer, position), radix
-//      sorted; every query k-mer finds its target occurrences by binary
-//      search; seeds occurring more than 32 times are skipped;
+//      sorted on its region and k-mer bits, every 32nd key sampled; every
+//      query k-mer finds its target occurrences through the samples; seeds
+//      occurring more than 32 times are skipped;
 //   2. matches as keys (region, diagonal, query position), radix sorted;
 //      maximal runs of consecutive positions on a diagonal are the anchors;
-//   3. tier 1: one 64-lane workgroup per region scores its anchors in
-//      (x, y) order, its lanes testing the predecessors that end within the
-//      gap limit or inside the anchor itself (a link then cuts the overlap
-//      from the later anchor's start), a window of a second order, by end;
-//      the anchors are then ordered by (region, score descending, x, y) and
-//      one thread per region takes the chains out; the chains become nodes,
-//      ordered by (region, x, y) and by (region, end);
+//   3. tier 1: one workgroup per region scores its anchors 64 at a time in
+//      (x, y) order, testing the predecessors that end within the gap limit
+//      or inside the anchor itself (a link then cuts the overlap from the
+//      later anchor's start), a window of a second order, by end, and then
+//      the links inside the batch; the anchors are then ordered by (region,
+//      score descending, x, y) and one wave per region takes the chains
+//      out; the chains become nodes, ordered by (region, x, y) and by
+//      (region, end);
 //   4. tier 2: the same scoring over the nodes (affine cost, gaps up to
-//      10 kbp), the same ordering and one thread per region taking the
-//      final chains out;
+//      10 kbp, blocks of candidates that cannot give a positive link
+//      skipped), the same ordering and extraction of the final chains;
 //   5. the stretches between consecutive anchors of every final chain are
 //      aligned by one thread each (three-state affine recurrence over two
-//      rolling rows, one byte of traceback per cell);
-//   6. one thread per final chain joins anchors and stretches into merged
+//      rolling rows, one byte of traceback per cell), the large ones by one
+//      wave each;
+//   6. one wave per final chain joins anchors and stretches into merged
 //      operations, counts matches, transitions and gaps, applies the report
 //      rule and writes the record and its CIGAR.
 #include <vector>

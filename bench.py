@@ -661,6 +661,23 @@ def chromosome_section(args, steps):
         r.close()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # the same search captured once as a HIP graph and replayed: no launch
+    # gaps or count read-backs between its kernels
+    stream = torch.cuda.Stream()
+    plan = ix.plan([span], args.max_error, args.min_len, stream=stream)
+    r = plan.run(stream)
+    r.candidates()
+    r.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = plan.run(stream)
+        ncand_g = len(r.candidates())
+        r.close()
+    torch.cuda.synchronize()
+    tg = (time.perf_counter() - t0) / steps
+    ginfo = plan.info()
+    plan.close()
     sdf.set_tuning()
     mean_k = float(np.mean(kernel_ms))
     alg = qbases * alg_bytes_per_query_base(nm, ne, g.total, hbar)
@@ -670,6 +687,10 @@ def chromosome_section(args, steps):
            "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                           "p99": round(float(np.percentile(lat, 99)), 4)},
            "roofline": roofline(alg, mean_k, measured_traffic("chromosome50")),
+           "graph": {"path": "the same search captured once as a HIP graph (sdf_plan_create) "
+                             "and replayed (sdf_plan_run), candidates copied out each step",
+                     "mbp_per_s": round(qbases / tg / 1e6, 3), "ms_per_search": round(tg * 1e3, 4),
+                     "candidates": ncand_g, **ginfo},
            "detail": {"autotuned_core": tuned_core, "autotuned_threads": tuned_threads,
                       "tile_kernel_ms_per_schedule": {"%d threads, %d starts" % k: round(v, 3)
                                                       for k, v in tuned_ms.items()},
